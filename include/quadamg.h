@@ -1,0 +1,157 @@
+/* quadamg: auxiliary-grid algebraic multigrid on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the method of Wang, Hu, Cohen and Xu, "A Parallel Auxiliary Grid AMG Method for GPU": an SPD system
+ * A x = b from a 2D discretisation (Section 1, eq. 1) is solved by unsmoothed aggregation on a region quadtree of an
+ * auxiliary grid (Section 3), with Galerkin coarse operators of fixed 9-point pattern (eq. 3-4, Section 4.4), a
+ * quadtree-colored Gauss-Seidel smoother (Section 4.5) and the nonlinear AMLI-cycle (Algorithm 2.2) used as the
+ * preconditioner of a flexible conjugate-gradient iteration (Algorithm 2.1).
+ *
+ * Conventions shared by every entry point:
+ *  - Pointers marked "device" are device memory of the hierarchy's device (the device current at amg_setup);
+ *    "host" pointers are ordinary host memory. Inputs are borrowed for the duration of the call only.
+ *  - Arrays are 0-based; coords is n x 2 interleaved (x0, y0, x1, y1, ...); CSR is row_ptr[n+1] (int64),
+ *    col_idx[nnz] (int32), vals[nnz] (float64), columns in any order inside a row, the diagonal present.
+ *  - Work is enqueued on the options' stream (NULL = the default stream). Calls that return data to the host
+ *    synchronise that stream.
+ *  - Every call returns an amg_status; on failure no output handle is created and nothing leaks.
+ *  - A hierarchy holds one solve workspace: one solve at a time per hierarchy. Distinct hierarchies may be used
+ *    concurrently on different streams.
+ *  - Results are deterministic: no floating-point atomics; reductions use a fixed tree that depends only on the
+ *    system size.
+ */
+#ifndef QUADAMG_H
+#define QUADAMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AMG_OK = 0,
+    AMG_ERR_INVALID = 1,   /* bad argument or malformed input (checked before the hierarchy is built) */
+    AMG_ERR_NOMEM = 2,     /* a device or host allocation failed */
+    AMG_ERR_DEVICE = 3,    /* a HIP runtime call failed */
+    AMG_ERR_NOT_SPD = 4,   /* non-positive diagonal on some level, or the coarsest Cholesky failed */
+    AMG_ERR_BREAKDOWN = 5, /* (p, A p) <= 0 in the outer iteration */
+    AMG_ERR_NOCONV = 6     /* max_iters reached; x holds the last iterate */
+} amg_status;
+
+typedef struct amg_hierarchy amg_hierarchy;
+
+typedef struct {
+    int32_t precision;   /* 0: plain FP64 solve. 1: FP32 hierarchy, smoother and SpMV inside the preconditioner,
+                            FP64 outer iteration, FP64 inner products and FP64 coarsest solve. */
+    int32_t coarse_max;  /* the coarsest quadtree level is the first k <= L with 4^k <= coarse_max; a system with
+                            n <= coarse_max is solved directly (default 64) */
+    int32_t inner_iters; /* steps n of Algorithm 2.1 inside the cycle: 1 or 2 (default 2, the K-cycle) */
+    int32_t sweeps;      /* smoothing sweeps before and after the coarse correction (default 1) */
+    int32_t outer_mmax;  /* directions kept by the outer flexible CG: 0 or 1 (default 1) */
+    int32_t max_iters;   /* outer iteration cap (default 1000) */
+    const double *box;   /* host {a1, b1, a2, b2}: the auxiliary box of eq. (5); NULL = bounding box of coords
+                            (eq. 6). Points outside a given box are rejected. */
+    void *stream;        /* hipStream_t used for every launch; NULL = default stream */
+} amg_options;
+
+typedef struct {
+    int32_t iters;       /* outer iterations performed */
+    int32_t restarts;    /* restarts from the true residual */
+    double relres;       /* true relative residual ||b - A x|| / ||b|| of the returned x (FP64) */
+    double setup_ms;     /* wall time of amg_setup */
+    double solve_ms;     /* wall time of this solve */
+} amg_info;
+
+/* Fill *opt with the defaults listed above. */
+void amg_default_options(amg_options *opt);
+
+/* Build the hierarchy (Section 3 and Sections 4.2-4.4): auxiliary box (eq. 5-6), depth L = max{l : 4^l < n}
+ * (Section 3.1), level-L aggregates by cell index (eq. 9), coarse aggregates by quadtree parent (eq. 10),
+ * Galerkin operators A_{k-1} = P^t A_k P (eq. 3-4, eq. 11), 4-coloring (Section 4.5) and the factorised coarsest
+ * operator. coords, row_ptr, col_idx, vals: device. opt may be NULL (defaults). On success *out owns all device
+ * memory it needs; the inputs may be freed afterwards. Errors: AMG_ERR_INVALID (n < 1, nnz mismatch, row_ptr not
+ * monotone, column out of range, non-finite coordinate, a point outside a given box, bad option),
+ * AMG_ERR_NOT_SPD, AMG_ERR_NOMEM, AMG_ERR_DEVICE. */
+amg_status amg_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
+                     const double *vals, int64_t nnz, const amg_options *opt, amg_hierarchy **out);
+
+/* Solve A x = b with the outer flexible CG preconditioned by the nonlinear AMLI-cycle (Algorithms 2.1 and 2.2),
+ * from x = 0, until ||r|| <= tol ||b|| holds for the recurrence residual and for the true FP64 residual (the
+ * iteration restarts from the true residual when only the former holds). b, x: device, n entries; x is output
+ * only. b = 0 gives x = 0 and iters = 0. info may be NULL. Blocks until the solve ends. Errors:
+ * AMG_ERR_NOCONV (x = last iterate), AMG_ERR_BREAKDOWN, AMG_ERR_INVALID (tol <= 0 or not finite),
+ * AMG_ERR_DEVICE. */
+amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_info *info);
+
+/* Release every resource of h (NULL is allowed). Synchronises the hierarchy's stream first. */
+void amg_free(amg_hierarchy *h);
+
+/* Change the solve precision of an existing hierarchy (0 = FP64, 1 = FP32 preconditioner / FP64 outer). */
+amg_status amg_set_precision(amg_hierarchy *h, int32_t precision);
+
+/* Change the stream used by later calls on h (hipStream_t, NULL = default stream). */
+amg_status amg_set_stream(amg_hierarchy *h, void *stream);
+
+/* Solve `count` independent systems, each with its own hierarchy and workspace, overlapping their work on the
+ * device. h, b, x, tol are host arrays of `count` entries; b[i] and x[i] are device vectors of hierarchy i's size;
+ * info is a host array of `count` entries or NULL. The hierarchies must be distinct. Each result equals the
+ * result of amg_solve on that system alone. Returns the first non-OK status (all systems are still attempted). */
+amg_status amg_solve_batch(amg_hierarchy *const *h, const double *const *b, double *const *x, const double *tol,
+                           int32_t count, amg_info *info);
+
+/* Upper estimate of the device bytes a hierarchy for an n-unknown, nnz-entry system needs, workspace included
+ * (used for admission by memory footprint). */
+amg_status amg_estimate_bytes(int64_t n, int64_t nnz, const amg_options *opt, size_t *bytes);
+
+/* Device bytes actually held by h. */
+amg_status amg_hierarchy_bytes(const amg_hierarchy *h, size_t *bytes);
+
+/* Number of levels: 1 (direct solve) or 1 + (L - kc + 1): the fine level then quadtree levels L, L-1, ..., kc. */
+amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels);
+
+/* Shape of a level: rows, quadtree level k (-1 for the fine level), overflow entries, depth L. */
+amg_status amg_level_info(const amg_hierarchy *h, int32_t level, int64_t *n_rows, int32_t *k, int64_t *ovf_nnz,
+                          int32_t *depth_L);
+
+/* Copy a level to host buffers in canonical numbering: the caller's unknown order on the fine level,
+ * lexicographic cell ids i = t1 + 2^k t2 (eq. 8) on quadtree levels. Any pointer may be NULL.
+ *  level 0: agg[n] = level-L cell of each unknown (eq. 9), color[n] = color of that cell; other arrays ignored.
+ *  level >= 1: agg[n] = parent cell on the next coarser level (eq. 10; -1 on the coarsest), color[n],
+ *  aj[n*9] row-major in the neighbour order of Section 4.4 [i, i1, ..., i8] (-1 = outside the grid),
+ *  ax[n*9] FP64 values (0 where aj = -1), ovf_ptr[n+1] / ovf_col / ovf_val: couplings that reach further than one
+ *  cell, sorted by column. Empty aggregates carry the identity row. Synchronises the stream. */
+amg_status amg_export_level(const amg_hierarchy *h, int32_t level, int32_t *agg_or_null, uint8_t *color,
+                            int32_t *aj, double *ax, int64_t *ovf_ptr, int32_t *ovf_col, double *ovf_val);
+
+/* FP32 values of a quadtree level (n*9, row-major, host): the round-to-nearest image of the FP64 values. */
+amg_status amg_export_level_f32(const amg_hierarchy *h, int32_t level, float *ax);
+
+/* Apply the fine-level preconditioner once (Algorithm 2.2 on the finest level): z = B^_F[r]. r, z: device, n
+ * entries, caller's numbering. precision as in amg_options. */
+amg_status amg_apply_precond(amg_hierarchy *h, const double *r, double *z, int32_t precision);
+
+/* One smoothing sweep on a level (Section 4.5): forward != 0 applies R_k (colors 0..3, forward substitution in
+ * each cell), else R_k^t (colors 3..0, backward), updating x in place: x <- x + R (f - A x). f, x: device, in the
+ * level's canonical numbering (see amg_export_level). Not valid on the coarsest level or a single-level
+ * hierarchy. */
+amg_status amg_level_smooth(amg_hierarchy *h, int32_t level, const double *f, double *x, int32_t forward,
+                            int32_t precision);
+
+/* y = A_level x, device vectors in the level's canonical numbering. */
+amg_status amg_level_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y, int32_t precision);
+
+/* Kernel timing of one named kernel family for roofline measurement: while enabled, every launch of that
+ * kernel on h's stream is bracketed by HIP events; amg_kernel_timing_read returns the number of launches and
+ * their summed device time since the last enable. name: "spmv64" (outer FP64 sliced-ELL SpMV), "gs_fine32",
+ * "gs_fine64" (fine-level smoother residual pass), "resid_fine32", "resid_fine64". name NULL disables. */
+amg_status amg_kernel_timing_enable(amg_hierarchy *h, const char *name);
+amg_status amg_kernel_timing_read(amg_hierarchy *h, int64_t *launches, double *total_ms, double *bytes_per_launch);
+
+/* Human-readable name of a status. */
+const char *amg_status_string(amg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

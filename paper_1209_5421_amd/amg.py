@@ -1,0 +1,271 @@
+"""Python binding of the quadamg C ABI (include/quadamg.h): argument marshalling only.
+
+Every step of setup and solve runs in the HIP kernels of libquadamg.so; torch is used for device memory and the
+stream handle. If the library is missing or no GPU is present, calls raise instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libquadamg.so")
+
+OK, INVALID, NOMEM, DEVICE, NOT_SPD, BREAKDOWN, NOCONV = range(7)
+STATUS = {0: "AMG_OK", 1: "AMG_ERR_INVALID", 2: "AMG_ERR_NOMEM", 3: "AMG_ERR_DEVICE", 4: "AMG_ERR_NOT_SPD",
+          5: "AMG_ERR_BREAKDOWN", 6: "AMG_ERR_NOCONV"}
+EXPORTED = ["amg_default_options", "amg_setup", "amg_solve", "amg_free", "amg_set_precision", "amg_set_stream",
+            "amg_solve_batch", "amg_estimate_bytes", "amg_hierarchy_bytes", "amg_num_levels", "amg_level_info",
+            "amg_export_level", "amg_export_level_f32", "amg_apply_precond", "amg_level_smooth", "amg_level_spmv",
+            "amg_kernel_timing_enable", "amg_kernel_timing_read", "amg_status_string"]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("coarse_max", C.c_int32), ("inner_iters", C.c_int32),
+                ("sweeps", C.c_int32), ("outer_mmax", C.c_int32), ("max_iters", C.c_int32),
+                ("box", C.POINTER(C.c_double)), ("stream", C.c_void_p)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("relres", C.c_double), ("setup_ms", C.c_double),
+                ("solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class AMGError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {STATUS.get(code, code)}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libquadamg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+    L = C.CDLL(path)
+    p, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.amg_default_options.argtypes = [C.POINTER(Options)]
+    L.amg_default_options.restype = None
+    L.amg_setup.argtypes = [i64, p, p, p, p, i64, C.POINTER(Options), C.POINTER(p)]
+    L.amg_solve.argtypes = [p, p, p, d, C.POINTER(Info)]
+    L.amg_free.argtypes = [p]
+    L.amg_free.restype = None
+    L.amg_set_precision.argtypes = [p, i32]
+    L.amg_set_stream.argtypes = [p, p]
+    L.amg_solve_batch.argtypes = [C.POINTER(p), C.POINTER(p), C.POINTER(p), C.POINTER(d), i32, C.POINTER(Info)]
+    L.amg_estimate_bytes.argtypes = [i64, i64, C.POINTER(Options), C.POINTER(C.c_size_t)]
+    L.amg_hierarchy_bytes.argtypes = [p, C.POINTER(C.c_size_t)]
+    L.amg_num_levels.argtypes = [p, C.POINTER(i32)]
+    L.amg_level_info.argtypes = [p, i32, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]
+    L.amg_export_level.argtypes = [p, i32, p, p, p, p, p, p, p]
+    L.amg_export_level_f32.argtypes = [p, i32, p]
+    L.amg_apply_precond.argtypes = [p, p, p, i32]
+    L.amg_level_smooth.argtypes = [p, i32, p, p, i32, i32]
+    L.amg_level_spmv.argtypes = [p, i32, p, p, i32]
+    L.amg_kernel_timing_enable.argtypes = [p, C.c_char_p]
+    L.amg_kernel_timing_read.argtypes = [p, C.POINTER(i64), C.POINTER(d), C.POINTER(d)]
+    L.amg_status_string.argtypes = [i32]
+    L.amg_status_string.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("amg_default_options", "amg_free", "amg_status_string"):
+            getattr(L, name).restype = i32
+    _lib = L
+    return L
+
+
+def _check(code, what):
+    if code != OK:
+        raise AMGError(code, what)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def default_options() -> Options:
+    o = Options()
+    load().amg_default_options(C.byref(o))
+    return o
+
+
+def estimate_bytes(n: int, nnz: int, **opts) -> int:
+    o = _options(**opts)
+    b = C.c_size_t()
+    _check(load().amg_estimate_bytes(n, nnz, C.byref(o), C.byref(b)), "amg_estimate_bytes")
+    return b.value
+
+
+def _options(precision=0, coarse_max=64, inner_iters=2, sweeps=1, outer_mmax=1, max_iters=1000, box=None,
+             stream=None):
+    o = default_options()
+    o.precision, o.coarse_max, o.inner_iters = precision, coarse_max, inner_iters
+    o.sweeps, o.outer_mmax, o.max_iters = sweeps, outer_mmax, max_iters
+    o._box = None
+    if box is not None:
+        o._box = (C.c_double * 4)(*[float(v) for v in box])
+        o.box = C.cast(o._box, C.POINTER(C.c_double))
+    o.stream = stream
+    return o
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Hierarchy:
+    """Device-resident hierarchy built by amg_setup from device tensors.
+
+    coords: (n, 2) float64, row_ptr: (n+1,) int64, col: (nnz,) int32, val: (nnz,) float64, all on one CUDA device.
+    """
+
+    def __init__(self, coords, row_ptr, col, val, box=None, precision=0, coarse_max=64, inner_iters=2, sweeps=1,
+                 outer_mmax=1, max_iters=1000, stream=None):
+        import torch
+        L = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("quadamg needs a GPU (no HIP device visible)")
+        for t, dt in ((coords, torch.float64), (row_ptr, torch.int64), (col, torch.int32), (val, torch.float64)):
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+                raise TypeError("inputs must be contiguous CUDA tensors: coords f64 (n,2), row_ptr i64, col i32, "
+                                "val f64")
+        self.device = coords.device
+        self.n = int(coords.shape[0])
+        self.nnz = int(col.numel())
+        self._stream = stream
+        o = _options(precision, coarse_max, inner_iters, sweeps, outer_mmax, max_iters, box,
+                     _stream_handle(stream))
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.amg_setup(self.n, _ptr(coords), _ptr(row_ptr), _ptr(col), _ptr(val), self.nnz, C.byref(o),
+                               C.byref(h)), "amg_setup")
+        self._h = h
+        lv = C.c_int32()
+        _check(L.amg_num_levels(h, C.byref(lv)), "amg_num_levels")
+        self.num_levels = lv.value
+
+    @classmethod
+    def from_problem(cls, prob, device="cuda", **kw):
+        import torch
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=device)
+        kw.setdefault("box", prob.box)
+        return cls(t(prob.coords, torch.float64), t(prob.row_ptr, torch.int64), t(prob.col, torch.int32),
+                   t(prob.val, torch.float64), **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().amg_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- solve --------------------------------------------------------------------------------------------------
+    def set_precision(self, precision: int):
+        _check(load().amg_set_precision(self._h, precision), "amg_set_precision")
+
+    def set_stream(self, stream):
+        self._stream = stream
+        _check(load().amg_set_stream(self._h, _stream_handle(stream)), "amg_set_stream")
+
+    def solve(self, b, tol=1e-8, x=None, check=True):
+        import torch
+        if x is None:
+            x = torch.empty_like(b)
+        info = Info()
+        code = load().amg_solve(self._h, _ptr(b), _ptr(x), float(tol), C.byref(info))
+        if check and code != OK:
+            raise AMGError(code, "amg_solve")
+        d = info.as_dict()
+        d["status"] = code
+        return x, d
+
+    def apply_precond(self, r, precision=0):
+        import torch
+        z = torch.empty_like(r)
+        _check(load().amg_apply_precond(self._h, _ptr(r), _ptr(z), precision), "amg_apply_precond")
+        return z
+
+    def smooth(self, level, f, x, forward=True, precision=0):
+        x = x.clone()
+        _check(load().amg_level_smooth(self._h, level, _ptr(f), _ptr(x), 1 if forward else 0, precision),
+               "amg_level_smooth")
+        return x
+
+    def spmv(self, level, x, precision=0):
+        import torch
+        y = torch.empty_like(x)
+        _check(load().amg_level_spmv(self._h, level, _ptr(x), _ptr(y), precision), "amg_level_spmv")
+        return y
+
+    # -- inspection ---------------------------------------------------------------------------------------------
+    def bytes(self) -> int:
+        b = C.c_size_t()
+        _check(load().amg_hierarchy_bytes(self._h, C.byref(b)), "amg_hierarchy_bytes")
+        return b.value
+
+    def level_info(self, level: int) -> dict:
+        n, k, ovf, L = C.c_int64(), C.c_int32(), C.c_int64(), C.c_int32()
+        _check(load().amg_level_info(self._h, level, C.byref(n), C.byref(k), C.byref(ovf), C.byref(L)),
+               "amg_level_info")
+        return dict(n=n.value, k=k.value, ovf_nnz=ovf.value, L=L.value)
+
+    def export_level(self, level: int, f32: bool = False) -> dict:
+        info = self.level_info(level)
+        n = info["n"]
+        out = dict(info)
+        out["agg"] = np.empty(n, dtype=np.int32)
+        out["color"] = np.empty(n, dtype=np.uint8)
+        p = lambda a: a.ctypes.data_as(C.c_void_p)
+        L = load()
+        if level == 0:
+            _check(L.amg_export_level(self._h, 0, p(out["agg"]), p(out["color"]), None, None, None, None, None),
+                   "amg_export_level")
+            return out
+        out["aj"] = np.empty((n, 9), dtype=np.int32)
+        out["ax"] = np.empty((n, 9), dtype=np.float64)
+        out["ovf_ptr"] = np.empty(n + 1, dtype=np.int64)
+        out["ovf_col"] = np.empty(info["ovf_nnz"], dtype=np.int32)
+        out["ovf_val"] = np.empty(info["ovf_nnz"], dtype=np.float64)
+        _check(L.amg_export_level(self._h, level, *[p(out[k]) for k in ("agg", "color", "aj", "ax", "ovf_ptr",
+                                                                       "ovf_col", "ovf_val")]), "amg_export_level")
+        if f32:
+            out["ax32"] = np.empty((n, 9), dtype=np.float32)
+            _check(L.amg_export_level_f32(self._h, level, p(out["ax32"])), "amg_export_level_f32")
+        return out
+
+    # -- kernel timing ------------------------------------------------------------------------------------------
+    def timing_enable(self, name):
+        _check(load().amg_kernel_timing_enable(self._h, name.encode() if name else None), "amg_kernel_timing_enable")
+
+    def timing_read(self):
+        n, ms, b = C.c_int64(), C.c_double(), C.c_double()
+        _check(load().amg_kernel_timing_read(self._h, C.byref(n), C.byref(ms), C.byref(b)), "amg_kernel_timing_read")
+        return dict(launches=n.value, total_ms=ms.value, bytes_per_launch=b.value)
+
+
+def solve_batch(hiers, bs, xs, tols):
+    """amg_solve_batch over distinct hierarchies; returns (first status, list of info dicts)."""
+    n = len(hiers)
+    H = (C.c_void_p * n)(*[h._h for h in hiers])
+    B = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+    X = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+    T = (C.c_double * n)(*[float(t) for t in tols])
+    infos = (Info * n)()
+    code = load().amg_solve_batch(H, B, X, T, n, infos)
+    return code, [i.as_dict() for i in infos]

@@ -1,0 +1,168 @@
+// Runtime pieces shared by setup and solve: tracked device allocation, exclusive scans, release, status names.
+#include "qa_internal.hpp"
+
+namespace qa {
+
+void *dalloc(amg_hierarchy *h, size_t bytes) {
+  void *p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  h->allocs.push_back(p);
+  h->bytes += bytes;
+  return p;
+}
+
+amg_status release(amg_hierarchy *h) {
+  for (void *p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+  if (h->host_scal) (void)hipHostFree(h->host_scal);
+  h->host_scal = nullptr;
+  for (hipEvent_t e : h->timing.ev) (void)hipEventDestroy(e);
+  h->timing.ev.clear();
+  return AMG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// Exclusive scan: out[i] = sum_{j<i} in[j], out[n] = total. Blocks of 256 threads x 8 items; block totals are
+// scanned recursively and added back.
+
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kBlock * kScanItems;
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_scan_block(const T *__restrict__ in, T *__restrict__ out,
+                                                        T *__restrict__ bsum, int64_t n) {
+  __shared__ T s_tot[kBlock];
+  const int64_t base = static_cast<int64_t>(blockIdx.x) * kScanChunk + static_cast<int64_t>(threadIdx.x) * kScanItems;
+  T v[kScanItems];
+  T run = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; i++) {
+    v[i] = (base + i < n) ? in[base + i] : T(0);
+    T t = v[i];
+    v[i] = run;
+    run += t;
+  }
+  s_tot[threadIdx.x] = run;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the thread totals
+  for (int off = 1; off < kBlock; off <<= 1) {
+    T add = (threadIdx.x >= off) ? s_tot[threadIdx.x - off] : T(0);
+    __syncthreads();
+    s_tot[threadIdx.x] += add;
+    __syncthreads();
+  }
+  const T excl = (threadIdx.x > 0) ? s_tot[threadIdx.x - 1] : T(0);
+#pragma unroll
+  for (int i = 0; i < kScanItems; i++)
+    if (base + i < n) out[base + i] = excl + v[i];
+  if (threadIdx.x == kBlock - 1) bsum[blockIdx.x] = s_tot[kBlock - 1];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_scan_add(T *__restrict__ out, const T *__restrict__ bsum_ex, int64_t n) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) out[i] += bsum_ex[i / kScanChunk];
+  if (i == 0) out[n] = bsum_ex[(n + kScanChunk - 1) / kScanChunk];
+}
+
+template <class T>
+__global__ void k_scan_single_tail(T *__restrict__ out, const T *__restrict__ bsum, int64_t n) {
+  out[n] = bsum[0];
+}
+
+template <class T>
+static amg_status scan_impl(const T *in, T *out, int64_t n, hipStream_t s, amg_hierarchy *h) {
+  if (n <= 0) {
+    T zero = 0;
+    QA_HIP(hipMemcpyAsync(out, &zero, sizeof(T), hipMemcpyHostToDevice, s));
+    QA_HIP(hipStreamSynchronize(s));
+    return AMG_OK;
+  }
+  const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+  T *bsum = nullptr;
+  QA_HIP(hipMallocAsync(reinterpret_cast<void **>(&bsum), sizeof(T) * (2 * nb + 2), s));
+  T *bsum_ex = bsum + nb;
+  k_scan_block<T><<<nb, kBlock, 0, s>>>(in, out, bsum, n);
+  QA_LAUNCH_CHECK();
+  if (nb == 1) {
+    k_scan_single_tail<T><<<1, 1, 0, s>>>(out, bsum, n);
+    QA_LAUNCH_CHECK();
+  } else {
+    amg_status st = scan_impl<T>(bsum, bsum_ex, nb, s, h);
+    if (st != AMG_OK) return st;
+    k_scan_add<T><<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(out, bsum_ex, n);
+    QA_LAUNCH_CHECK();
+  }
+  QA_HIP(hipFreeAsync(bsum, s));
+  return AMG_OK;
+}
+
+amg_status scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s, amg_hierarchy *h) {
+  return scan_impl<int64_t>(in, out, n, s, h);
+}
+amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, amg_hierarchy *h) {
+  return scan_impl<int32_t>(in, out, n, s, h);
+}
+
+}  // namespace qa
+
+extern "C" {
+
+void amg_default_options(amg_options *opt) {
+  if (!opt) return;
+  opt->precision = 0;
+  opt->coarse_max = 64;
+  opt->inner_iters = 2;
+  opt->sweeps = 1;
+  opt->outer_mmax = 1;
+  opt->max_iters = 1000;
+  opt->box = nullptr;
+  opt->stream = nullptr;
+}
+
+const char *amg_status_string(amg_status s) {
+  switch (s) {
+    case AMG_OK: return "AMG_OK";
+    case AMG_ERR_INVALID: return "AMG_ERR_INVALID";
+    case AMG_ERR_NOMEM: return "AMG_ERR_NOMEM";
+    case AMG_ERR_DEVICE: return "AMG_ERR_DEVICE";
+    case AMG_ERR_NOT_SPD: return "AMG_ERR_NOT_SPD";
+    case AMG_ERR_BREAKDOWN: return "AMG_ERR_BREAKDOWN";
+    case AMG_ERR_NOCONV: return "AMG_ERR_NOCONV";
+  }
+  return "AMG_ERR_UNKNOWN";
+}
+
+void amg_free(amg_hierarchy *h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  qa::release(h);
+  delete h;
+}
+
+amg_status amg_hierarchy_bytes(const amg_hierarchy *h, size_t *bytes) {
+  if (!h || !bytes) return AMG_ERR_INVALID;
+  *bytes = h->bytes;
+  return AMG_OK;
+}
+
+amg_status amg_num_levels(const amg_hierarchy *h, int32_t *levels) {
+  if (!h || !levels) return AMG_ERR_INVALID;
+  *levels = h->nlev;
+  return AMG_OK;
+}
+
+amg_status amg_set_precision(amg_hierarchy *h, int32_t precision) {
+  if (!h || (precision != 0 && precision != 1)) return AMG_ERR_INVALID;
+  h->precision = precision;
+  return AMG_OK;
+}
+
+amg_status amg_set_stream(amg_hierarchy *h, void *stream) {
+  if (!h) return AMG_ERR_INVALID;
+  h->stream = static_cast<hipStream_t>(stream);
+  return AMG_OK;
+}
+
+}  // extern "C"

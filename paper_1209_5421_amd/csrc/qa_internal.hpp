@@ -1,0 +1,212 @@
+// Internal layout of the quadamg hierarchy on the device (gfx950).
+//
+// Numbering. Quadtree level k (side 2^k, n = 4^k cells) is stored in "color-major" order: a cell with quadtree
+// coordinates (t1, t2) has Morton key m = interleave(t1 -> even bits, t2 -> odd bits), and its storage index is
+// q = (m & 3) * 4^(k-1) + (m >> 2). The low two Morton bits are the cell's color (t1 & 1) + 2 (t2 & 1) of the
+// 4-coloring (Section 4.5), so every color is one contiguous quarter of the vector; the four children of a
+// level-(k-1) cell M (Morton) sit at q = c * 4^(k-1) + M, c = 0..3, one per quarter, so restriction reads four
+// coalesced streams. The fine level is permuted the same way: rows sorted by (color-major index of their level-L
+// cell, original index), so each cell's unknowns are contiguous and ascending.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "quadamg.h"
+
+namespace qa {
+
+constexpr int kBlock = 256;        // threads per workgroup for elementwise / reduction kernels
+constexpr int kSliceRows = 64;     // sliced-ELL slice height = one wavefront
+constexpr int kRedBlocksMax = 1024;
+constexpr int kScalars = 16;       // device scalars per level
+
+// ---------------------------------------------------------------------------------------------------------------
+// Morton / color-major index helpers (k <= 15)
+
+__host__ __device__ inline uint32_t spread_bits(uint32_t v) {
+  v &= 0xFFFFu;
+  v = (v | (v << 8)) & 0x00FF00FFu;
+  v = (v | (v << 4)) & 0x0F0F0F0Fu;
+  v = (v | (v << 2)) & 0x33333333u;
+  v = (v | (v << 1)) & 0x55555555u;
+  return v;
+}
+__host__ __device__ inline uint32_t compact_bits(uint32_t v) {
+  v &= 0x55555555u;
+  v = (v | (v >> 1)) & 0x33333333u;
+  v = (v | (v >> 2)) & 0x0F0F0F0Fu;
+  v = (v | (v >> 4)) & 0x00FF00FFu;
+  v = (v | (v >> 8)) & 0x0000FFFFu;
+  return v;
+}
+__host__ __device__ inline uint32_t morton(uint32_t t1, uint32_t t2) { return spread_bits(t1) | (spread_bits(t2) << 1); }
+__host__ __device__ inline uint32_t q_of_m(uint32_t m, int k) {
+  return k == 0 ? 0u : (((m & 3u) << (2 * k - 2)) | (m >> 2));
+}
+__host__ __device__ inline uint32_t m_of_q(uint32_t q, int k) {
+  return k == 0 ? 0u : (((q & ((1u << (2 * k - 2)) - 1u)) << 2) | (q >> (2 * k - 2)));
+}
+
+// neighbour offsets of Section 4.4: self, E, NE, N, NW, W, SW, S, SE
+__host__ __device__ inline int slot_dx(int s) {
+  switch (s) {
+    case 1: case 2: case 8: return 1;
+    case 4: case 5: case 6: return -1;
+    default: return 0;
+  }
+}
+__host__ __device__ inline int slot_dy(int s) {
+  switch (s) {
+    case 2: case 3: case 4: return 1;
+    case 6: case 7: case 8: return -1;
+    default: return 0;
+  }
+}
+// slot of offset (dx, dy), both in [-1, 1]
+__host__ __device__ inline int slot_of(int dx, int dy) {
+  // index (dy + 1) * 3 + (dx + 1) -> slot
+  const int tab = (dy + 1) * 3 + (dx + 1);
+  switch (tab) {
+    case 0: return 6; case 1: return 7; case 2: return 8;
+    case 3: return 5; case 4: return 0; case 5: return 1;
+    case 6: return 4; case 7: return 3; default: return 2;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// hierarchy
+
+struct QuadLevel {              // quadtree level k, color-major numbering
+  int k = 0;
+  int64_t n = 0;                // 4^k
+  double *ax64 = nullptr;       // 9 x n, slot-major: ax[s * n + q]
+  float *ax32 = nullptr;
+  uint8_t *empty = nullptr;     // 1 = aggregate without fine unknowns (identity row)
+  int64_t ovf_nnz = 0;          // couplings beyond one cell: CSR over rows q, columns q, sorted by lexicographic id
+  int32_t *optr = nullptr;
+  int32_t *ocol = nullptr;
+  double *oval64 = nullptr;
+  float *oval32 = nullptr;
+  int same_color_ovf = 0;       // some overflow coupling joins two cells of one color
+};
+
+struct FineLevel {
+  int64_t n = 0, nnz = 0;
+  int32_t *perm = nullptr;      // position p -> caller's index
+  int32_t *iperm = nullptr;     // caller's index -> position p
+  int64_t *rp = nullptr;        // permuted CSR (caller's entry order inside a row)
+  int32_t *ci = nullptr;
+  double *va = nullptr;
+  // sliced ELL: slices of 64 consecutive rows inside each color's row range, column-major inside a slice,
+  // diagonal first; padding entries point at the row itself with value 0
+  int64_t nslices = 0;
+  int64_t *slice_ptr = nullptr; // nslices + 1 (entry offsets)
+  int32_t *slice_row0 = nullptr;// nslices + 1 (first row)
+  int32_t *s_col = nullptr;
+  double *s_val64 = nullptr;
+  float *s_val32 = nullptr;
+  int64_t sell_entries = 0;
+  int64_t color_row[5] = {0, 0, 0, 0, 0};
+  int64_t color_slice[5] = {0, 0, 0, 0, 0};
+  double *diag64 = nullptr;
+  float *diag32 = nullptr;
+  // couplings inside a cell (off-diagonal), caller's entry order, for the in-cell substitution
+  int64_t ic_nnz = 0;
+  int32_t *ic_ptr = nullptr;
+  int32_t *ic_col = nullptr;
+  double *ic_val64 = nullptr;
+  float *ic_val32 = nullptr;
+  int32_t *crow = nullptr;      // level-L cell q -> first row (4^L + 1)
+  int32_t *agg_q = nullptr;     // row -> level-L cell q
+};
+
+template <class T>
+struct LevelWork {              // per level, one precision
+  T *f = nullptr, *u = nullptr, *d = nullptr;  // fine level: B^ input, output, temporary
+  T *g = nullptr, *e = nullptr, *r = nullptr, *p0 = nullptr, *q0 = nullptr, *p1 = nullptr, *q1 = nullptr;
+};
+
+struct Timing {
+  int kind = -1;                // which kernel family is timed (see kernel_kind)
+  std::vector<hipEvent_t> ev;   // pairs
+  size_t used = 0;
+  int64_t launches = 0;
+  double total_ms = 0.0;
+  double bytes_per_launch = 0.0;
+};
+
+enum KernelKind { KK_SPMV64 = 0, KK_GS_FINE32, KK_GS_FINE64, KK_RESID_FINE32, KK_RESID_FINE64, KK_COUNT };
+
+}  // namespace qa
+
+struct amg_hierarchy {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  amg_options opt{};
+  double box[4] = {0, 0, 0, 0};
+  int64_t n = 0;
+  int L = -1, kc = -1, nlev = 1;
+  int precision = 0;
+  qa::FineLevel fine;
+  std::vector<qa::QuadLevel> lev;      // lev[1 .. nlev-1]
+  int64_t nc = 0;                      // coarsest size
+  double *ainv = nullptr;              // coarsest inverse (nc x nc), storage numbering of that level
+  std::vector<qa::LevelWork<double>> w64;
+  std::vector<qa::LevelWork<float>> w32;
+  // outer iteration (FP64, permuted numbering)
+  double *xp = nullptr, *rp = nullptr, *bp = nullptr, *zp = nullptr, *pp = nullptr, *qp = nullptr,
+         *pprev = nullptr, *qprev = nullptr, *tp = nullptr;
+  double *scal = nullptr;              // (nlev + 1) * kScalars device scalars
+  double *partials = nullptr;          // reduction partial sums
+  int64_t partials_cap = 0;
+  unsigned *counters = nullptr;        // (nlev + 1) last-block tickets
+  double *host_scal = nullptr;         // pinned mirror for convergence checks
+  int *dflag = nullptr;                // device error flags
+  std::vector<void *> allocs;
+  size_t bytes = 0;
+  double setup_ms = 0.0;
+  qa::Timing timing;
+};
+
+namespace qa {
+
+// allocation helpers (every allocation is tracked and released by amg_free)
+void *dalloc(amg_hierarchy *h, size_t bytes);
+template <class T>
+T *dalloc_n(amg_hierarchy *h, int64_t count) {
+  return static_cast<T *>(dalloc(h, sizeof(T) * static_cast<size_t>(count > 0 ? count : 1)));
+}
+
+// shared helpers implemented in qa_common.hip
+amg_status scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s, amg_hierarchy *h);
+amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, amg_hierarchy *h);
+amg_status release(amg_hierarchy *h);
+
+// solve side (qa_solve.hip)
+amg_status alloc_workspaces(amg_hierarchy *h);
+amg_status precond_apply(amg_hierarchy *h, int precision, const double *r_p, double *z_p);
+amg_status level_smooth_internal(amg_hierarchy *h, int level, const double *f, double *x, int forward, int prec);
+amg_status level_spmv_internal(amg_hierarchy *h, int level, const double *x, double *y, int prec);
+double kernel_bytes(const amg_hierarchy *h, int kind);
+
+}  // namespace qa
+
+#define QA_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t qa_e_ = (call);                                                        \
+    if (qa_e_ != hipSuccess) {                                                        \
+      return qa_e_ == hipErrorOutOfMemory ? AMG_ERR_NOMEM : AMG_ERR_DEVICE;           \
+    }                                                                                 \
+  } while (0)
+
+#define QA_TRY(call)                        \
+  do {                                      \
+    amg_status qa_s_ = (call);              \
+    if (qa_s_ != AMG_OK) return qa_s_;      \
+  } while (0)
+
+#define QA_LAUNCH_CHECK() QA_HIP(hipGetLastError())

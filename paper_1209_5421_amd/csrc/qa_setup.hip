@@ -1,0 +1,1050 @@
+// Setup of the auxiliary-grid hierarchy (Section 3, Sections 4.2-4.4) on gfx950.
+//
+// Pipeline (all on the device, one stream): validate the CSR input and sum diagonals -> auxiliary box (eq. 5-6)
+// -> level-L cell of every unknown by the index formula of Section 4.2 (eq. 9), turned into a color-major Morton
+// index, with an integer-atomic histogram -> exclusive scan = cell row pointers -> scatter + per-cell sort (a
+// stable counting sort: unknowns of a cell end up contiguous and ascending) -> permuted CSR -> sliced ELL
+// (64-row slices, column-major, diagonal first, Section 4.1) and the in-cell coupling lists of the block smoother
+// -> Galerkin operators: level L from the fine rows of each cell (eq. 11), level k-1 from the four children of
+// each cell (Section 4.4), 9 slots plus an overflow list for couplings beyond one cell -> dense inverse of the
+// coarsest operator via Cholesky (Algorithm 2.2's A_1^{-1}).
+//
+// This file is compiled with -ffp-contract=off: the cell index must be the IEEE sequence subtract, divide,
+// multiply, floor, and the Galerkin sums are plain additions taken in a fixed order (cells, then rows ascending,
+// then entries in the caller's order; children in the order of Section 4.3's restriction formula).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "qa_internal.hpp"
+
+namespace qa {
+
+enum { F_INVALID = 1, F_NOT_SPD = 2, F_SAMECOLOR = 4 };
+
+__device__ inline void q_to_t(uint32_t q, int k, uint32_t &t1, uint32_t &t2) {
+  const uint32_t m = m_of_q(q, k);
+  t1 = compact_bits(m);
+  t2 = compact_bits(m >> 1);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// validation, box, cell keys
+
+__global__ void __launch_bounds__(kBlock) k_validate(int64_t n, int64_t nnz, const double *__restrict__ coords,
+                                                      const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                      const double *__restrict__ va, int has_box, double a1,
+                                                      double b1, double a2, double b2, int *flag) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int f = 0;
+  const int64_t r0 = rp[i], r1 = rp[i + 1];
+  if (i == 0 && r0 != 0) f |= F_INVALID;
+  if (i == n - 1 && r1 != nnz) f |= F_INVALID;
+  if (r1 < r0 || r0 < 0 || r1 > nnz) f |= F_INVALID;
+  const double x = coords[2 * i], y = coords[2 * i + 1];
+  if (!isfinite(x) || !isfinite(y)) f |= F_INVALID;
+  if (has_box && (x < a1 || x > b1 || y < a2 || y > b2)) f |= F_INVALID;
+  if (!(f & F_INVALID)) {
+    double dg = 0.0;
+    for (int64_t e = r0; e < r1; e++) {
+      const int32_t c = ci[e];
+      if (c < 0 || c >= n) f |= F_INVALID;
+      else if (c == i) dg += va[e];
+    }
+    if (!(dg > 0.0)) f |= F_NOT_SPD;
+  }
+  if (f) atomicOr(flag, f);
+}
+
+__global__ void __launch_bounds__(kBlock) k_bbox_partial(int64_t n, const double *__restrict__ coords,
+                                                          double *__restrict__ part) {
+  double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const double x = coords[2 * i], y = coords[2 * i + 1];
+    mnx = fmin(mnx, x); mxx = fmax(mxx, x); mny = fmin(mny, y); mxy = fmax(mxy, y);
+  }
+  __shared__ double s[4][kBlock];
+  s[0][threadIdx.x] = mnx; s[1][threadIdx.x] = mxx; s[2][threadIdx.x] = mny; s[3][threadIdx.x] = mxy;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      s[0][threadIdx.x] = fmin(s[0][threadIdx.x], s[0][threadIdx.x + off]);
+      s[1][threadIdx.x] = fmax(s[1][threadIdx.x], s[1][threadIdx.x + off]);
+      s[2][threadIdx.x] = fmin(s[2][threadIdx.x], s[2][threadIdx.x + off]);
+      s[3][threadIdx.x] = fmax(s[3][threadIdx.x], s[3][threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int t = 0; t < 4; t++) part[blockIdx.x * 4 + t] = s[t][0];
+}
+
+__global__ void k_bbox_final(int nb, const double *__restrict__ part, double *__restrict__ box) {
+  double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
+  for (int b = 0; b < nb; b++) {
+    mnx = fmin(mnx, part[4 * b]); mxx = fmax(mxx, part[4 * b + 1]);
+    mny = fmin(mny, part[4 * b + 2]); mxy = fmax(mxy, part[4 * b + 3]);
+  }
+  box[0] = mnx; box[1] = mxx; box[2] = mny; box[3] = mxy;
+}
+
+// Section 4.2: index = floor((v - a) / (b - a) * 2^L), clamped so the upper box edge belongs to the last cell.
+__device__ inline uint32_t axis_cell(double v, double a, double b, int L) {
+  if (!(b > a)) return 0u;
+  const double t = (v - a) / (b - a);
+  const double f = floor(t * static_cast<double>(1u << L));
+  int64_t i = static_cast<int64_t>(f);
+  const int64_t top = (static_cast<int64_t>(1) << L) - 1;
+  if (i > top) i = top;
+  if (i < 0) i = 0;
+  return static_cast<uint32_t>(i);
+}
+
+__global__ void __launch_bounds__(kBlock) k_cell_key(int64_t n, const double *__restrict__ coords, double a1,
+                                                      double b1, double a2, double b2, int L,
+                                                      int32_t *__restrict__ key, int32_t *__restrict__ cnt) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t xi = axis_cell(coords[2 * i], a1, b1, L);
+  const uint32_t yi = axis_cell(coords[2 * i + 1], a2, b2, L);
+  const uint32_t q = q_of_m(morton(xi, yi), L);
+  key[i] = static_cast<int32_t>(q);
+  atomicAdd(&cnt[q], 1);
+}
+
+__global__ void __launch_bounds__(kBlock) k_scatter(int64_t n, const int32_t *__restrict__ key,
+                                                     const int32_t *__restrict__ crow, int32_t *__restrict__ fill,
+                                                     int32_t *__restrict__ perm) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t q = key[i];
+  perm[crow[q] + atomicAdd(&fill[q], 1)] = static_cast<int32_t>(i);
+}
+
+// restore ascending caller order inside each cell (the scatter order is arbitrary)
+__global__ void __launch_bounds__(kBlock) k_sort_cells(int64_t ncell, const int32_t *__restrict__ crow,
+                                                        int32_t *__restrict__ perm) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= ncell) return;
+  const int32_t a = crow[q], b = crow[q + 1];
+  for (int32_t i = a + 1; i < b; i++) {
+    const int32_t v = perm[i];
+    int32_t j = i - 1;
+    while (j >= a && perm[j] > v) {
+      perm[j + 1] = perm[j];
+      j--;
+    }
+    perm[j + 1] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_inverse_perm(int64_t n, const int32_t *__restrict__ perm,
+                                                          const int32_t *__restrict__ key, int32_t *__restrict__ iperm,
+                                                          int32_t *__restrict__ agg_q, const int64_t *__restrict__ rp_in,
+                                                          int64_t *__restrict__ len) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t i = perm[p];
+  iperm[i] = static_cast<int32_t>(p);
+  if (agg_q) agg_q[p] = key[i];
+  len[p] = rp_in[i + 1] - rp_in[i];
+}
+
+__global__ void __launch_bounds__(kBlock) k_permute_csr(int64_t n, const int32_t *__restrict__ perm,
+                                                         const int32_t *__restrict__ iperm,
+                                                         const int64_t *__restrict__ rp_in,
+                                                         const int32_t *__restrict__ ci_in,
+                                                         const double *__restrict__ va_in, const int64_t *__restrict__ rp,
+                                                         int32_t *__restrict__ ci, double *__restrict__ va,
+                                                         double *__restrict__ diag) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t i = perm[p];
+  int64_t o = rp[p];
+  double dg = 0.0;
+  for (int64_t e = rp_in[i]; e < rp_in[i + 1]; e++, o++) {
+    const int32_t c = iperm[ci_in[e]];
+    ci[o] = c;
+    va[o] = va_in[e];
+    if (c == p) dg += va_in[e];
+  }
+  diag[p] = dg;
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// sliced ELL of the fine level
+
+struct Regions {
+  int64_t row[5];
+  int64_t slice[5];
+};
+
+__device__ inline int region_of_row(const Regions &R, int64_t p) {
+  return (p >= R.row[1]) + (p >= R.row[2]) + (p >= R.row[3]);
+}
+__device__ inline int region_of_slice(const Regions &R, int64_t s) {
+  return (s >= R.slice[1]) + (s >= R.slice[2]) + (s >= R.slice[3]);
+}
+
+__global__ void __launch_bounds__(kBlock) k_slice_meta(Regions R, int64_t nslices, const int64_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci, int32_t *__restrict__ row0,
+                                                        int64_t *__restrict__ size) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (s > nslices) return;
+  if (s == nslices) {
+    row0[s] = static_cast<int32_t>(R.row[4]);
+    return;
+  }
+  // empty regions own no slices, so the region of s is found among the non-empty ones
+  int c = 0;
+  while (c < 3 && s >= R.slice[c + 1]) c++;
+  const int64_t r0 = R.row[c] + (s - R.slice[c]) * kSliceRows;
+  const int64_t r1 = min(r0 + kSliceRows, R.row[c + 1]);
+  int64_t w = 1;
+  for (int64_t p = r0; p < r1; p++) {
+    int64_t offd = 0;
+    for (int64_t e = rp[p]; e < rp[p + 1]; e++) offd += (ci[e] != p);
+    w = max(w, offd + 1);
+  }
+  row0[s] = static_cast<int32_t>(r0);
+  size[s] = w * kSliceRows;
+}
+
+__global__ void __launch_bounds__(kBlock) k_fill_sell(Regions R, int64_t n, const int64_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ ci, const double *__restrict__ va,
+                                                       const double *__restrict__ diag,
+                                                       const int64_t *__restrict__ slice_ptr,
+                                                       int32_t *__restrict__ s_col, double *__restrict__ s_val) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int c = 0;
+  while (c < 3 && p >= R.row[c + 1]) c++;
+  const int64_t rel = p - R.row[c];
+  const int64_t s = R.slice[c] + rel / kSliceRows;
+  const int lane = static_cast<int>(rel % kSliceRows);
+  const int64_t off = slice_ptr[s];
+  const int64_t w = (slice_ptr[s + 1] - off) / kSliceRows;
+  s_col[off + lane] = static_cast<int32_t>(p);
+  s_val[off + lane] = diag[p];
+  int64_t k = 1;
+  for (int64_t e = rp[p]; e < rp[p + 1]; e++) {
+    if (ci[e] == p) continue;
+    s_col[off + k * kSliceRows + lane] = ci[e];
+    s_val[off + k * kSliceRows + lane] = va[e];
+    k++;
+  }
+  for (; k < w; k++) {
+    s_col[off + k * kSliceRows + lane] = static_cast<int32_t>(p);
+    s_val[off + k * kSliceRows + lane] = 0.0;
+  }
+}
+
+// couplings between distinct unknowns of one cell (the block of the block Gauss-Seidel smoother)
+__global__ void __launch_bounds__(kBlock) k_ic_count(int64_t n, const int64_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci, const int32_t *__restrict__ agg_q,
+                                                      int32_t *__restrict__ cnt) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t q = agg_q[p];
+  int32_t c = 0;
+  for (int64_t e = rp[p]; e < rp[p + 1]; e++) c += (ci[e] != p && agg_q[ci[e]] == q);
+  cnt[p] = c;
+}
+
+__global__ void __launch_bounds__(kBlock) k_ic_fill(int64_t n, const int64_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ ci, const double *__restrict__ va,
+                                                     const int32_t *__restrict__ agg_q, const int32_t *__restrict__ ptr,
+                                                     int32_t *__restrict__ col, double *__restrict__ val) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t q = agg_q[p];
+  int32_t o = ptr[p];
+  for (int64_t e = rp[p]; e < rp[p + 1]; e++)
+    if (ci[e] != p && agg_q[ci[e]] == q) {
+      col[o] = ci[e];
+      val[o] = va[e];
+      o++;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// Galerkin operators
+
+__device__ inline void add_slot(double (&acc)[9], int s, double v) {
+#pragma unroll
+  for (int j = 0; j < 9; j++) acc[j] += (j == s) ? v : 0.0;
+}
+
+__device__ inline uint32_t lex_of_q(uint32_t q, int k) {
+  uint32_t t1, t2;
+  q_to_t(q, k, t1, t2);
+  return (t2 << k) | t1;
+}
+
+// insertion sort of an overflow row by lexicographic column
+__device__ inline void sort_ovf_row(int32_t *col, double *val, int32_t a, int32_t b, int k) {
+  for (int32_t i = a + 1; i < b; i++) {
+    const int32_t c = col[i];
+    const double v = val[i];
+    const uint32_t lc = lex_of_q(static_cast<uint32_t>(c), k);
+    int32_t j = i - 1;
+    while (j >= a && lex_of_q(static_cast<uint32_t>(col[j]), k) > lc) {
+      col[j + 1] = col[j];
+      val[j + 1] = val[j];
+      j--;
+    }
+    col[j + 1] = c;
+    val[j + 1] = v;
+  }
+}
+
+// fine -> level L: one thread per cell; its rows are contiguous, so its entries are the range rp[crow[q]] ..
+// rp[crow[q+1]] visited in order (rows ascending, entries in the caller's order)
+__global__ void __launch_bounds__(kBlock) k_galerkin_fine(int L, int64_t nL, const int32_t *__restrict__ crow,
+                                                           const int64_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ ci,
+                                                           const double *__restrict__ va,
+                                                           const int32_t *__restrict__ agg_q, double *__restrict__ ax,
+                                                           uint8_t *__restrict__ empty, int32_t *__restrict__ ovf_cnt,
+                                                           int *flag) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nL) return;
+  uint32_t t1, t2;
+  q_to_t(static_cast<uint32_t>(q), L, t1, t2);
+  const int64_t e0 = rp[crow[q]], e1 = rp[crow[q + 1]];
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int32_t cnt = 0;
+  for (int64_t e = e0; e < e1; e++) {
+    const uint32_t qq = static_cast<uint32_t>(agg_q[ci[e]]);
+    uint32_t u1, u2;
+    q_to_t(qq, L, u1, u2);
+    const int dx = static_cast<int>(u1) - static_cast<int>(t1), dy = static_cast<int>(u2) - static_cast<int>(t2);
+    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) {
+      add_slot(acc, slot_of(dx, dy), va[e]);
+    } else {
+      bool first = true;
+      for (int64_t e2 = e0; e2 < e; e2++)
+        if (static_cast<uint32_t>(agg_q[ci[e2]]) == qq) { first = false; break; }
+      cnt += first;
+    }
+  }
+  const bool emp = (crow[q] == crow[q + 1]);
+  empty[q] = emp ? 1 : 0;
+  if (emp) acc[0] = 1.0;
+#pragma unroll
+  for (int j = 0; j < 9; j++) ax[j * nL + q] = acc[j];
+  ovf_cnt[q] = cnt;
+  if (!emp && !(acc[0] > 0.0)) atomicOr(flag, F_NOT_SPD);
+}
+
+__global__ void __launch_bounds__(kBlock) k_galerkin_fine_ovf(int L, int64_t nL, const int32_t *__restrict__ crow,
+                                                               const int64_t *__restrict__ rp,
+                                                               const int32_t *__restrict__ ci,
+                                                               const double *__restrict__ va,
+                                                               const int32_t *__restrict__ agg_q,
+                                                               const int32_t *__restrict__ optr,
+                                                               int32_t *__restrict__ ocol, double *__restrict__ oval,
+                                                               int *flag) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nL) return;
+  int32_t o = optr[q];
+  if (optr[q + 1] == o) return;
+  uint32_t t1, t2;
+  q_to_t(static_cast<uint32_t>(q), L, t1, t2);
+  const int64_t e0 = rp[crow[q]], e1 = rp[crow[q + 1]];
+  const uint32_t my_color = static_cast<uint32_t>(q) >> (2 * L - 2);
+  for (int64_t e = e0; e < e1; e++) {
+    const uint32_t qq = static_cast<uint32_t>(agg_q[ci[e]]);
+    uint32_t u1, u2;
+    q_to_t(qq, L, u1, u2);
+    const int dx = static_cast<int>(u1) - static_cast<int>(t1), dy = static_cast<int>(u2) - static_cast<int>(t2);
+    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) continue;
+    bool first = true;
+    for (int64_t e2 = e0; e2 < e; e2++)
+      if (static_cast<uint32_t>(agg_q[ci[e2]]) == qq) { first = false; break; }
+    if (!first) continue;
+    double s = 0.0;
+    for (int64_t e2 = e; e2 < e1; e2++)
+      if (static_cast<uint32_t>(agg_q[ci[e2]]) == qq) s += va[e2];
+    ocol[o] = static_cast<int32_t>(qq);
+    oval[o] = s;
+    o++;
+    if ((qq >> (2 * L - 2)) == my_color) atomicOr(flag, F_SAMECOLOR);
+  }
+  sort_ovf_row(ocol, oval, optr[q], optr[q + 1], L);
+}
+
+// level k -> level k-1: one thread per coarse cell M (Morton at level k-1); children c in the order 0, 1, 3, 2
+// ((2T1,2T2), (2T1+1,2T2), (2T1+1,2T2+1), (2T1,2T2+1)), each child's 9 slots then its overflow entries.
+struct CoarseSrc {
+  int k;
+  int64_t n;
+  const double *ax;
+  const uint8_t *empty;
+  const int32_t *optr;
+  const int32_t *ocol;
+  const double *oval;
+};
+
+__constant__ int kChildOrder[4] = {0, 1, 3, 2};
+
+__global__ void __launch_bounds__(kBlock) k_galerkin_coarse(CoarseSrc F, double *__restrict__ ax,
+                                                             uint8_t *__restrict__ empty,
+                                                             int32_t *__restrict__ ovf_cnt, int *flag) {
+  const int kc = F.k - 1;
+  const int64_t nc = F.n >> 2;
+  const int64_t M = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (M >= nc) return;
+  const uint32_t T1 = compact_bits(static_cast<uint32_t>(M)), T2 = compact_bits(static_cast<uint32_t>(M) >> 1);
+  const uint32_t side = 1u << F.k;
+  double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  int32_t cnt = 0;
+  bool all_empty = true;
+  for (int oi = 0; oi < 4; oi++) {
+    const int c = kChildOrder[oi];
+    const int64_t q = c * nc + M;
+    if (F.empty[q]) continue;
+    all_empty = false;
+    const uint32_t m = (static_cast<uint32_t>(M) << 2) | static_cast<uint32_t>(c);
+    const int t1 = static_cast<int>(compact_bits(m)), t2 = static_cast<int>(compact_bits(m >> 1));
+#pragma unroll
+    for (int s = 0; s < 9; s++) {
+      const int u1 = t1 + slot_dx(s), u2 = t2 + slot_dy(s);
+      if (u1 < 0 || u2 < 0 || u1 >= static_cast<int>(side) || u2 >= static_cast<int>(side)) continue;
+      add_slot(acc, slot_of((u1 >> 1) - static_cast<int>(T1), (u2 >> 1) - static_cast<int>(T2)), F.ax[s * F.n + q]);
+    }
+    if (F.optr)
+      for (int32_t e = F.optr[q]; e < F.optr[q + 1]; e++) {
+        const uint32_t mm = m_of_q(static_cast<uint32_t>(F.ocol[e]), F.k);
+        const uint32_t P = mm >> 2;
+        const int dX = static_cast<int>(compact_bits(P)) - static_cast<int>(T1);
+        const int dY = static_cast<int>(compact_bits(P >> 1)) - static_cast<int>(T2);
+        if (dX >= -1 && dX <= 1 && dY >= -1 && dY <= 1) {
+          add_slot(acc, slot_of(dX, dY), F.oval[e]);
+        } else {
+          // first occurrence of this coarse target among the far entries visited so far
+          bool first = true;
+          for (int oj = 0; oj <= oi && first; oj++) {
+            const int64_t qj = kChildOrder[oj] * nc + M;
+            if (F.empty[qj]) continue;
+            const int32_t eend = (oj == oi) ? e : F.optr[qj + 1];
+            for (int32_t e2 = F.optr[qj]; e2 < eend; e2++)
+              if ((m_of_q(static_cast<uint32_t>(F.ocol[e2]), F.k) >> 2) == P) { first = false; break; }
+          }
+          cnt += first;
+        }
+      }
+  }
+  const uint32_t qc = q_of_m(static_cast<uint32_t>(M), kc);
+  empty[qc] = all_empty ? 1 : 0;
+  if (all_empty) acc[0] = 1.0;
+#pragma unroll
+  for (int j = 0; j < 9; j++) ax[j * nc + qc] = acc[j];
+  ovf_cnt[qc] = cnt;
+  if (!all_empty && !(acc[0] > 0.0)) atomicOr(flag, F_NOT_SPD);
+}
+
+__global__ void __launch_bounds__(kBlock) k_galerkin_coarse_ovf(CoarseSrc F, const int32_t *__restrict__ optr,
+                                                                 int32_t *__restrict__ ocol,
+                                                                 double *__restrict__ oval, int *flag) {
+  const int kc = F.k - 1;
+  const int64_t nc = F.n >> 2;
+  const int64_t M = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (M >= nc) return;
+  const uint32_t qc = q_of_m(static_cast<uint32_t>(M), kc);
+  int32_t o = optr[qc];
+  if (optr[qc + 1] == o) return;
+  const uint32_t T1 = compact_bits(static_cast<uint32_t>(M)), T2 = compact_bits(static_cast<uint32_t>(M) >> 1);
+  const uint32_t my_color = (kc >= 1) ? (qc >> (2 * kc - 2)) : 0u;
+  for (int oi = 0; oi < 4; oi++) {
+    const int64_t q = kChildOrder[oi] * nc + M;
+    if (F.empty[q]) continue;
+    for (int32_t e = F.optr[q]; e < F.optr[q + 1]; e++) {
+      const uint32_t P = m_of_q(static_cast<uint32_t>(F.ocol[e]), F.k) >> 2;
+      const int dX = static_cast<int>(compact_bits(P)) - static_cast<int>(T1);
+      const int dY = static_cast<int>(compact_bits(P >> 1)) - static_cast<int>(T2);
+      if (dX >= -1 && dX <= 1 && dY >= -1 && dY <= 1) continue;
+      bool first = true;
+      for (int oj = 0; oj <= oi && first; oj++) {
+        const int64_t qj = kChildOrder[oj] * nc + M;
+        if (F.empty[qj]) continue;
+        const int32_t eend = (oj == oi) ? e : F.optr[qj + 1];
+        for (int32_t e2 = F.optr[qj]; e2 < eend; e2++)
+          if ((m_of_q(static_cast<uint32_t>(F.ocol[e2]), F.k) >> 2) == P) { first = false; break; }
+      }
+      if (!first) continue;
+      double s = 0.0;
+      for (int oj = oi; oj < 4; oj++) {
+        const int64_t qj = kChildOrder[oj] * nc + M;
+        if (F.empty[qj]) continue;
+        const int32_t ebeg = (oj == oi) ? e : F.optr[qj];
+        for (int32_t e2 = ebeg; e2 < F.optr[qj + 1]; e2++)
+          if ((m_of_q(static_cast<uint32_t>(F.ocol[e2]), F.k) >> 2) == P) s += F.oval[e2];
+      }
+      const uint32_t target = q_of_m(P, kc);
+      ocol[o] = static_cast<int32_t>(target);
+      oval[o] = s;
+      o++;
+      if (kc >= 1 && (target >> (2 * kc - 2)) == my_color) atomicOr(flag, F_SAMECOLOR);
+    }
+  }
+  sort_ovf_row(ocol, oval, optr[qc], optr[qc + 1], kc);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// coarsest level: dense matrix, Cholesky, explicit inverse (one workgroup; n <= 1024)
+
+__global__ void __launch_bounds__(kBlock) k_densify_level(int k, int64_t n, const double *__restrict__ ax,
+                                                           const int32_t *__restrict__ optr,
+                                                           const int32_t *__restrict__ ocol,
+                                                           const double *__restrict__ oval, double *__restrict__ dense) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  uint32_t t1, t2;
+  q_to_t(static_cast<uint32_t>(q), k, t1, t2);
+  const int side = 1 << k;
+  for (int s = 0; s < 9; s++) {
+    const int u1 = static_cast<int>(t1) + slot_dx(s), u2 = static_cast<int>(t2) + slot_dy(s);
+    if (u1 < 0 || u2 < 0 || u1 >= side || u2 >= side) continue;
+    dense[q * n + q_of_m(morton(u1, u2), k)] = ax[s * n + q];
+  }
+  if (optr)
+    for (int32_t e = optr[q]; e < optr[q + 1]; e++) dense[q * n + ocol[e]] = oval[e];
+}
+
+__global__ void __launch_bounds__(kBlock) k_densify_csr(int64_t n, const int64_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ ci, const double *__restrict__ va,
+                                                         double *__restrict__ dense) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int64_t e = rp[i]; e < rp[i + 1]; e++) dense[i * n + ci[e]] += va[e];
+}
+
+__global__ void __launch_bounds__(kBlock) k_chol_inverse(int n, double *__restrict__ a, double *__restrict__ y,
+                                                          double *__restrict__ ainv, int *flag) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < n; j++) {
+    if (tid == 0) {
+      double d = a[j * n + j];
+      for (int k = 0; k < j; k++) d -= a[j * n + k] * a[j * n + k];
+      if (!(d > 0.0)) {
+        atomicOr(flag, F_NOT_SPD);
+        d = 1.0;
+      }
+      a[j * n + j] = sqrt(d);
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) {
+      double s = a[i * n + j];
+      for (int k = 0; k < j; k++) s -= a[i * n + k] * a[j * n + k];
+      a[i * n + j] = s / a[j * n + j];
+    }
+    __syncthreads();
+  }
+  // Y = L^{-1}, one column per thread
+  for (int j = tid; j < n; j += blockDim.x)
+    for (int i = 0; i < n; i++) {
+      if (i < j) {
+        y[i * n + j] = 0.0;
+        continue;
+      }
+      double s = (i == j) ? 1.0 : 0.0;
+      for (int k = j; k < i; k++) s -= a[i * n + k] * y[k * n + j];
+      y[i * n + j] = s / a[i * n + i];
+    }
+  __syncthreads();
+  // A^{-1} = Y^t Y
+  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    double s = 0.0;
+    for (int k = max(i, j); k < n; k++) s += y[k * n + i] * y[k * n + j];
+    ainv[idx] = s;
+  }
+}
+
+template <class S, class D>
+__global__ void __launch_bounds__(kBlock) k_convert(int64_t n, const S *__restrict__ src, D *__restrict__ dst) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = static_cast<D>(src[i]);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_iota(int64_t n, T *__restrict__ v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = static_cast<T>(i);
+}
+
+static inline unsigned nblk(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+
+static int depth_rule(int64_t n, int coarse_max, int &L, int &kc) {
+  if (n <= coarse_max) {
+    L = kc = -1;
+    return 1;
+  }
+  int l = 0;
+  while ((static_cast<int64_t>(1) << (2 * (l + 1))) < n) l++;
+  int k = l;
+  while (k > 0 && (static_cast<int64_t>(1) << (2 * k)) > coarse_max) k--;
+  L = l;
+  kc = k;
+  return 1 + (l - k + 1);
+}
+
+static amg_status read_flag(amg_hierarchy *h, int &f) {
+  QA_HIP(hipMemcpyAsync(&f, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  QA_HIP(hipStreamSynchronize(h->stream));
+  return AMG_OK;
+}
+
+static amg_status build_sell(amg_hierarchy *h) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  F.nslices = 0;
+  for (int c = 0; c < 4; c++) {
+    F.color_slice[c] = F.nslices;
+    F.nslices += (F.color_row[c + 1] - F.color_row[c] + kSliceRows - 1) / kSliceRows;
+  }
+  F.color_slice[4] = F.nslices;
+  Regions R;
+  for (int c = 0; c < 5; c++) { R.row[c] = F.color_row[c]; R.slice[c] = F.color_slice[c]; }
+  int64_t *size = dalloc_n<int64_t>(h, F.nslices + 1);
+  F.slice_row0 = dalloc_n<int32_t>(h, F.nslices + 1);
+  F.slice_ptr = dalloc_n<int64_t>(h, F.nslices + 1);
+  if (!size || !F.slice_row0 || !F.slice_ptr) return AMG_ERR_NOMEM;
+  k_slice_meta<<<nblk(F.nslices + 1), kBlock, 0, s>>>(R, F.nslices, F.rp, F.ci, F.slice_row0, size);
+  QA_LAUNCH_CHECK();
+  QA_TRY(scan_exclusive_i64(size, F.slice_ptr, F.nslices, s, h));
+  QA_HIP(hipMemcpyAsync(&F.sell_entries, F.slice_ptr + F.nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QA_HIP(hipStreamSynchronize(s));
+  F.s_col = dalloc_n<int32_t>(h, F.sell_entries);
+  F.s_val64 = dalloc_n<double>(h, F.sell_entries);
+  F.s_val32 = dalloc_n<float>(h, F.sell_entries);
+  if (!F.s_col || !F.s_val64 || !F.s_val32) return AMG_ERR_NOMEM;
+  k_fill_sell<<<nblk(F.n), kBlock, 0, s>>>(R, F.n, F.rp, F.ci, F.va, F.diag64, F.slice_ptr, F.s_col, F.s_val64);
+  QA_LAUNCH_CHECK();
+  k_convert<double, float><<<nblk(F.sell_entries), kBlock, 0, s>>>(F.sell_entries, F.s_val64, F.s_val32);
+  QA_LAUNCH_CHECK();
+  k_convert<double, float><<<nblk(F.n), kBlock, 0, s>>>(F.n, F.diag64, F.diag32);
+  QA_LAUNCH_CHECK();
+  return AMG_OK;
+}
+
+static amg_status build_coarsest_inverse(amg_hierarchy *h, const double *dense_src_filled, int64_t nc) {
+  hipStream_t s = h->stream;
+  double *y = dalloc_n<double>(h, nc * nc);
+  h->ainv = dalloc_n<double>(h, nc * nc);
+  if (!y || !h->ainv) return AMG_ERR_NOMEM;
+  k_chol_inverse<<<1, kBlock, 0, s>>>(static_cast<int>(nc), const_cast<double *>(dense_src_filled), y, h->ainv,
+                                       h->dflag);
+  QA_LAUNCH_CHECK();
+  h->nc = nc;
+  return AMG_OK;
+}
+
+static amg_status build_single_level(amg_hierarchy *h, const int64_t *row_ptr, const int32_t *col_idx,
+                                     const double *vals, int64_t nnz) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  const int64_t n = h->n;
+  F.perm = dalloc_n<int32_t>(h, n);
+  F.iperm = dalloc_n<int32_t>(h, n);
+  F.rp = dalloc_n<int64_t>(h, n + 1);
+  F.ci = dalloc_n<int32_t>(h, nnz);
+  F.va = dalloc_n<double>(h, nnz);
+  F.diag64 = dalloc_n<double>(h, n);
+  F.diag32 = dalloc_n<float>(h, n);
+  int64_t *len = dalloc_n<int64_t>(h, n);
+  double *dense = dalloc_n<double>(h, n * n);
+  if (!F.perm || !F.iperm || !F.rp || !F.ci || !F.va || !F.diag64 || !F.diag32 || !len || !dense)
+    return AMG_ERR_NOMEM;
+  k_iota<int32_t><<<nblk(n), kBlock, 0, s>>>(n, F.perm);
+  QA_LAUNCH_CHECK();
+  k_inverse_perm<<<nblk(n), kBlock, 0, s>>>(n, F.perm, nullptr, F.iperm, nullptr, row_ptr, len);
+  QA_LAUNCH_CHECK();
+  QA_TRY(scan_exclusive_i64(len, F.rp, n, s, h));
+  k_permute_csr<<<nblk(n), kBlock, 0, s>>>(n, F.perm, F.iperm, row_ptr, col_idx, vals, F.rp, F.ci, F.va, F.diag64);
+  QA_LAUNCH_CHECK();
+  F.color_row[0] = 0;
+  for (int c = 1; c < 5; c++) F.color_row[c] = n;
+  QA_TRY(build_sell(h));
+  QA_HIP(hipMemsetAsync(dense, 0, sizeof(double) * n * n, s));
+  k_densify_csr<<<nblk(n), kBlock, 0, s>>>(n, row_ptr, col_idx, vals, dense);
+  QA_LAUNCH_CHECK();
+  return build_coarsest_inverse(h, dense, n);
+}
+
+static amg_status build_multi_level(amg_hierarchy *h, const double *coords, const int64_t *row_ptr,
+                                    const int32_t *col_idx, const double *vals, int64_t nnz) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  const int64_t n = h->n;
+  const int L = h->L;
+  const int64_t nL = static_cast<int64_t>(1) << (2 * L);
+  // level-L cells and the stable counting sort
+  int32_t *key = dalloc_n<int32_t>(h, n);
+  int32_t *cnt = dalloc_n<int32_t>(h, nL);
+  int32_t *fill = dalloc_n<int32_t>(h, nL);
+  F.crow = dalloc_n<int32_t>(h, nL + 1);
+  F.perm = dalloc_n<int32_t>(h, n);
+  F.iperm = dalloc_n<int32_t>(h, n);
+  F.agg_q = dalloc_n<int32_t>(h, n);
+  int64_t *len = dalloc_n<int64_t>(h, n);
+  F.rp = dalloc_n<int64_t>(h, n + 1);
+  F.ci = dalloc_n<int32_t>(h, nnz);
+  F.va = dalloc_n<double>(h, nnz);
+  F.diag64 = dalloc_n<double>(h, n);
+  F.diag32 = dalloc_n<float>(h, n);
+  if (!key || !cnt || !fill || !F.crow || !F.perm || !F.iperm || !F.agg_q || !len || !F.rp || !F.ci || !F.va ||
+      !F.diag64 || !F.diag32)
+    return AMG_ERR_NOMEM;
+  QA_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nL, s));
+  QA_HIP(hipMemsetAsync(fill, 0, sizeof(int32_t) * nL, s));
+  k_cell_key<<<nblk(n), kBlock, 0, s>>>(n, coords, h->box[0], h->box[1], h->box[2], h->box[3], L, key, cnt);
+  QA_LAUNCH_CHECK();
+  QA_TRY(scan_exclusive_i32(cnt, F.crow, nL, s, h));
+  k_scatter<<<nblk(n), kBlock, 0, s>>>(n, key, F.crow, fill, F.perm);
+  QA_LAUNCH_CHECK();
+  k_sort_cells<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, F.perm);
+  QA_LAUNCH_CHECK();
+  k_inverse_perm<<<nblk(n), kBlock, 0, s>>>(n, F.perm, key, F.iperm, F.agg_q, row_ptr, len);
+  QA_LAUNCH_CHECK();
+  QA_TRY(scan_exclusive_i64(len, F.rp, n, s, h));
+  k_permute_csr<<<nblk(n), kBlock, 0, s>>>(n, F.perm, F.iperm, row_ptr, col_idx, vals, F.rp, F.ci, F.va, F.diag64);
+  QA_LAUNCH_CHECK();
+  // color regions: cells of color c are the quarter [c nL/4, (c+1) nL/4) of the color-major order
+  {
+    int32_t cr[4];
+    for (int c = 0; c < 4; c++)
+      QA_HIP(hipMemcpyAsync(&cr[c], F.crow + c * (nL / 4), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < 4; c++) F.color_row[c] = cr[c];
+    F.color_row[4] = n;
+  }
+  QA_TRY(build_sell(h));
+  // in-cell couplings
+  F.ic_ptr = dalloc_n<int32_t>(h, n + 1);
+  int32_t *iccnt = dalloc_n<int32_t>(h, n);
+  if (!F.ic_ptr || !iccnt) return AMG_ERR_NOMEM;
+  k_ic_count<<<nblk(n), kBlock, 0, s>>>(n, F.rp, F.ci, F.agg_q, iccnt);
+  QA_LAUNCH_CHECK();
+  QA_TRY(scan_exclusive_i32(iccnt, F.ic_ptr, n, s, h));
+  {
+    int32_t icn = 0;
+    QA_HIP(hipMemcpyAsync(&icn, F.ic_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
+    F.ic_nnz = icn;
+  }
+  F.ic_col = dalloc_n<int32_t>(h, F.ic_nnz);
+  F.ic_val64 = dalloc_n<double>(h, F.ic_nnz);
+  F.ic_val32 = dalloc_n<float>(h, F.ic_nnz);
+  if (!F.ic_col || !F.ic_val64 || !F.ic_val32) return AMG_ERR_NOMEM;
+  k_ic_fill<<<nblk(n), kBlock, 0, s>>>(n, F.rp, F.ci, F.va, F.agg_q, F.ic_ptr, F.ic_col, F.ic_val64);
+  QA_LAUNCH_CHECK();
+  if (F.ic_nnz) {
+    k_convert<double, float><<<nblk(F.ic_nnz), kBlock, 0, s>>>(F.ic_nnz, F.ic_val64, F.ic_val32);
+    QA_LAUNCH_CHECK();
+  }
+
+  // Galerkin operators, level L first, then coarser
+  h->lev.assign(h->nlev, QuadLevel{});
+  for (int l = 1; l < h->nlev; l++) {
+    QuadLevel &Q = h->lev[l];
+    Q.k = L - (l - 1);
+    Q.n = static_cast<int64_t>(1) << (2 * Q.k);
+    Q.ax64 = dalloc_n<double>(h, 9 * Q.n);
+    Q.ax32 = dalloc_n<float>(h, 9 * Q.n);
+    Q.empty = dalloc_n<uint8_t>(h, Q.n);
+    int32_t *ocnt = dalloc_n<int32_t>(h, Q.n);
+    Q.optr = dalloc_n<int32_t>(h, Q.n + 1);
+    if (!Q.ax64 || !Q.ax32 || !Q.empty || !ocnt || !Q.optr) return AMG_ERR_NOMEM;
+    CoarseSrc src{};
+    if (l == 1) {
+      k_galerkin_fine<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.ax64, Q.empty, ocnt,
+                                                    h->dflag);
+    } else {
+      const QuadLevel &P = h->lev[l - 1];
+      src = CoarseSrc{P.k, P.n, P.ax64, P.empty, P.ovf_nnz ? P.optr : nullptr, P.ocol, P.oval64};
+      k_galerkin_coarse<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.ax64, Q.empty, ocnt, h->dflag);
+    }
+    QA_LAUNCH_CHECK();
+    QA_TRY(scan_exclusive_i32(ocnt, Q.optr, Q.n, s, h));
+    int32_t on = 0;
+    QA_HIP(hipMemcpyAsync(&on, Q.optr + Q.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
+    Q.ovf_nnz = on;
+    if (on) {
+      Q.ocol = dalloc_n<int32_t>(h, on);
+      Q.oval64 = dalloc_n<double>(h, on);
+      Q.oval32 = dalloc_n<float>(h, on);
+      if (!Q.ocol || !Q.oval64 || !Q.oval32) return AMG_ERR_NOMEM;
+      QA_HIP(hipMemsetAsync(h->dflag + 1, 0, sizeof(int), s));
+      if (l == 1)
+        k_galerkin_fine_ovf<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.optr, Q.ocol,
+                                                          Q.oval64, h->dflag + 1);
+      else
+        k_galerkin_coarse_ovf<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.optr, Q.ocol, Q.oval64, h->dflag + 1);
+      QA_LAUNCH_CHECK();
+      int sc = 0;
+      QA_HIP(hipMemcpyAsync(&sc, h->dflag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+      QA_HIP(hipStreamSynchronize(s));
+      Q.same_color_ovf = (sc & F_SAMECOLOR) ? 1 : 0;
+      k_convert<double, float><<<nblk(on), kBlock, 0, s>>>(on, Q.oval64, Q.oval32);
+      QA_LAUNCH_CHECK();
+    }
+    k_convert<double, float><<<nblk(9 * Q.n), kBlock, 0, s>>>(9 * Q.n, Q.ax64, Q.ax32);
+    QA_LAUNCH_CHECK();
+  }
+  // coarsest
+  const QuadLevel &C = h->lev[h->nlev - 1];
+  double *dense = dalloc_n<double>(h, C.n * C.n);
+  if (!dense) return AMG_ERR_NOMEM;
+  QA_HIP(hipMemsetAsync(dense, 0, sizeof(double) * C.n * C.n, s));
+  k_densify_level<<<nblk(C.n), kBlock, 0, s>>>(C.k, C.n, C.ax64, C.ovf_nnz ? C.optr : nullptr, C.ocol, C.oval64,
+                                               dense);
+  QA_LAUNCH_CHECK();
+  return build_coarsest_inverse(h, dense, C.n);
+}
+
+static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
+                             const double *vals, int64_t nnz) {
+  hipStream_t s = h->stream;
+  const int64_t n = h->n;
+  h->dflag = dalloc_n<int>(h, 4);
+  if (!h->dflag) return AMG_ERR_NOMEM;
+  QA_HIP(hipMemsetAsync(h->dflag, 0, 4 * sizeof(int), s));
+  const double *ub = h->opt.box;
+  k_validate<<<nblk(n), kBlock, 0, s>>>(n, nnz, coords, row_ptr, col_idx, vals, ub ? 1 : 0, ub ? ub[0] : 0.0,
+                                         ub ? ub[1] : 0.0, ub ? ub[2] : 0.0, ub ? ub[3] : 0.0, h->dflag);
+  QA_LAUNCH_CHECK();
+  int f = 0;
+  QA_TRY(read_flag(h, f));
+  if (f & F_INVALID) return AMG_ERR_INVALID;
+  if (f & F_NOT_SPD) return AMG_ERR_NOT_SPD;
+  if (ub) {
+    for (int t = 0; t < 4; t++) h->box[t] = ub[t];
+  } else {
+    const int nb = static_cast<int>(std::min<int64_t>(nblk(n), kRedBlocksMax));
+    double *part = dalloc_n<double>(h, 4 * nb + 4);
+    if (!part) return AMG_ERR_NOMEM;
+    k_bbox_partial<<<nb, kBlock, 0, s>>>(n, coords, part);
+    QA_LAUNCH_CHECK();
+    k_bbox_final<<<1, 1, 0, s>>>(nb, part, part + 4 * nb);
+    QA_LAUNCH_CHECK();
+    QA_HIP(hipMemcpyAsync(h->box, part + 4 * nb, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
+  }
+  h->nlev = depth_rule(n, h->opt.coarse_max, h->L, h->kc);
+  h->fine.n = n;
+  h->fine.nnz = nnz;
+  if (h->nlev == 1) {
+    QA_TRY(build_single_level(h, row_ptr, col_idx, vals, nnz));
+    h->lev.assign(1, QuadLevel{});
+  } else {
+    QA_TRY(build_multi_level(h, coords, row_ptr, col_idx, vals, nnz));
+  }
+  QA_TRY(read_flag(h, f));
+  if (f & F_NOT_SPD) return AMG_ERR_NOT_SPD;
+  QA_TRY(alloc_workspaces(h));
+  QA_HIP(hipStreamSynchronize(s));
+  return AMG_OK;
+}
+
+}  // namespace qa
+
+using namespace qa;
+
+extern "C" amg_status amg_estimate_bytes(int64_t n, int64_t nnz, const amg_options *opt, size_t *bytes) {
+  if (n < 1 || nnz < 0 || !bytes) return AMG_ERR_INVALID;
+  amg_options o;
+  amg_default_options(&o);
+  if (opt) o = *opt;
+  int L = -1, kc = -1;
+  const int nlev = depth_rule(n, o.coarse_max, L, kc);
+  double b = 0;
+  // fine: permuted CSR (12 B/nnz + 8 B/row), sliced ELL (padding allowance 1.35) in FP64 + FP32 + columns,
+  // in-cell lists (<= nnz), vectors (3 FP64 + 3 FP32 workspace, 9 FP64 outer), indices
+  b += 12.0 * nnz + 8.0 * (n + 1);
+  b += 1.35 * (nnz + n) * (8 + 4 + 4);
+  b += 16.0 * nnz;
+  b += n * (3 * 8 + 3 * 4 + 9 * 8 + 4 * 4 + 8);
+  if (nlev > 1) {
+    const double nL = std::ldexp(1.0, 2 * L);
+    // quadtree levels: 9 FP64 + 9 FP32 + flags + 8 vectors per precision; geometric sum 4/3
+    b += (4.0 / 3.0) * nL * (9 * 12 + 1 + 4 + 8 * 12 + 4);
+    b += nL * 4.0 * 3;  // counting-sort temporaries and cell row pointers
+    const double nc = std::ldexp(1.0, 2 * kc);
+    b += 3 * nc * nc * 8;
+  } else {
+    b += 4.0 * n * n * 8;
+  }
+  b += 1 << 20;  // scalars, partial sums, alignment slack
+  *bytes = static_cast<size_t>(b);
+  return AMG_OK;
+}
+
+extern "C" amg_status amg_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
+                                const double *vals, int64_t nnz, const amg_options *opt, amg_hierarchy **out) {
+  if (!out) return AMG_ERR_INVALID;
+  *out = nullptr;
+  amg_options o;
+  amg_default_options(&o);
+  if (opt) o = *opt;
+  if (n < 1 || n > (static_cast<int64_t>(1) << 31) - 2 || nnz < 0 || !coords || !row_ptr || !col_idx || !vals)
+    return AMG_ERR_INVALID;
+  if ((o.precision != 0 && o.precision != 1) || o.coarse_max < 4 || o.coarse_max > 1024 || o.inner_iters < 1 ||
+      o.inner_iters > 2 || o.sweeps < 1 || o.sweeps > 8 || (o.outer_mmax != 0 && o.outer_mmax != 1) ||
+      o.max_iters < 1)
+    return AMG_ERR_INVALID;
+  if (o.box) {
+    for (int t = 0; t < 4; t++)
+      if (!std::isfinite(o.box[t])) return AMG_ERR_INVALID;
+    if (o.box[1] < o.box[0] || o.box[3] < o.box[2]) return AMG_ERR_INVALID;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  amg_hierarchy *h = new (std::nothrow) amg_hierarchy();
+  if (!h) return AMG_ERR_NOMEM;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return AMG_ERR_DEVICE;
+  }
+  h->opt = o;
+  h->opt.box = nullptr;  // borrowed pointer: do not keep
+  h->stream = static_cast<hipStream_t>(o.stream);
+  h->precision = o.precision;
+  h->n = n;
+  h->opt.box = o.box;
+  amg_status st = setup_impl(h, coords, row_ptr, col_idx, vals, nnz);
+  h->opt.box = nullptr;
+  if (st != AMG_OK) {
+    (void)hipStreamSynchronize(h->stream);
+    release(h);
+    delete h;
+    return st;
+  }
+  h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  *out = h;
+  return AMG_OK;
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// export in canonical numbering (host-side rearrangement of device arrays)
+
+extern "C" amg_status amg_level_info(const amg_hierarchy *h, int32_t level, int64_t *n_rows, int32_t *k,
+                                     int64_t *ovf_nnz, int32_t *depth_L) {
+  if (!h || level < 0 || level >= h->nlev) return AMG_ERR_INVALID;
+  if (depth_L) *depth_L = h->L;
+  if (level == 0) {
+    if (n_rows) *n_rows = h->n;
+    if (k) *k = -1;
+    if (ovf_nnz) *ovf_nnz = 0;
+  } else {
+    const QuadLevel &Q = h->lev[level];
+    if (n_rows) *n_rows = Q.n;
+    if (k) *k = Q.k;
+    if (ovf_nnz) *ovf_nnz = Q.ovf_nnz;
+  }
+  return AMG_OK;
+}
+
+template <class T>
+static amg_status to_host(std::vector<T> &v, const T *d, int64_t count, hipStream_t s) {
+  v.resize(static_cast<size_t>(count > 0 ? count : 0));
+  if (count > 0) QA_HIP(hipMemcpyAsync(v.data(), d, sizeof(T) * count, hipMemcpyDeviceToHost, s));
+  return AMG_OK;
+}
+
+static uint32_t host_q_of_lex(uint32_t lex, int k) {
+  const uint32_t t1 = lex & ((1u << k) - 1u), t2 = lex >> k;
+  return q_of_m(morton(t1, t2), k);
+}
+static uint32_t host_lex_of_q(uint32_t q, int k) {
+  const uint32_t m = m_of_q(q, k);
+  return (compact_bits(m >> 1) << k) | compact_bits(m);
+}
+
+template <class V>
+static amg_status export_values(const amg_hierarchy *h, int32_t level, const V *dev_ax, V *ax) {
+  const QuadLevel &Q = h->lev[level];
+  std::vector<V> hax;
+  QA_TRY(to_host(hax, dev_ax, 9 * Q.n, h->stream));
+  QA_HIP(hipStreamSynchronize(h->stream));
+  const uint32_t side = 1u << Q.k;
+  for (uint32_t I = 0; I < static_cast<uint32_t>(Q.n); I++) {
+    const uint32_t q = host_q_of_lex(I, Q.k);
+    const int t1 = static_cast<int>(I % side), t2 = static_cast<int>(I / side);
+    for (int sl = 0; sl < 9; sl++) {
+      const int u1 = t1 + slot_dx(sl), u2 = t2 + slot_dy(sl);
+      const bool in = u1 >= 0 && u2 >= 0 && u1 < static_cast<int>(side) && u2 < static_cast<int>(side);
+      ax[static_cast<size_t>(I) * 9 + sl] = in ? hax[static_cast<size_t>(sl) * Q.n + q] : V(0);
+    }
+  }
+  return AMG_OK;
+}
+
+extern "C" amg_status amg_export_level(const amg_hierarchy *h, int32_t level, int32_t *agg, uint8_t *color,
+                                       int32_t *aj, double *ax, int64_t *ovf_ptr, int32_t *ovf_col,
+                                       double *ovf_val) {
+  if (!h || level < 0 || level >= h->nlev) return AMG_ERR_INVALID;
+  QA_HIP(hipSetDevice(h->device));
+  hipStream_t s = h->stream;
+  if (level == 0) {
+    if (h->nlev == 1) {
+      for (int64_t i = 0; i < h->n; i++) {
+        if (agg) agg[i] = -1;
+        if (color) color[i] = 0;
+      }
+      return AMG_OK;
+    }
+    std::vector<int32_t> iperm, aggq;
+    QA_TRY(to_host(iperm, h->fine.iperm, h->n, s));
+    QA_TRY(to_host(aggq, h->fine.agg_q, h->n, s));
+    QA_HIP(hipStreamSynchronize(s));
+    for (int64_t i = 0; i < h->n; i++) {
+      const uint32_t q = static_cast<uint32_t>(aggq[iperm[i]]);
+      if (agg) agg[i] = static_cast<int32_t>(host_lex_of_q(q, h->L));
+      if (color) color[i] = static_cast<uint8_t>(m_of_q(q, h->L) & 3u);
+    }
+    return AMG_OK;
+  }
+  const QuadLevel &Q = h->lev[level];
+  const uint32_t side = 1u << Q.k;
+  for (uint32_t I = 0; I < static_cast<uint32_t>(Q.n); I++) {
+    const uint32_t t1 = I % side, t2 = I / side;
+    if (agg) agg[I] = (level < h->nlev - 1) ? static_cast<int32_t>((t2 >> 1) * (side >> 1) + (t1 >> 1)) : -1;
+    if (color) color[I] = static_cast<uint8_t>((t1 & 1u) + 2u * (t2 & 1u));
+    if (aj)
+      for (int sl = 0; sl < 9; sl++) {
+        const int u1 = static_cast<int>(t1) + slot_dx(sl), u2 = static_cast<int>(t2) + slot_dy(sl);
+        const bool in = u1 >= 0 && u2 >= 0 && u1 < static_cast<int>(side) && u2 < static_cast<int>(side);
+        aj[static_cast<size_t>(I) * 9 + sl] = in ? static_cast<int32_t>(u2 * side + u1) : -1;
+      }
+  }
+  if (ax) QA_TRY(export_values<double>(h, level, Q.ax64, ax));
+  if (ovf_ptr || ovf_col || ovf_val) {
+    std::vector<int32_t> optr, ocol;
+    std::vector<double> oval;
+    QA_TRY(to_host(optr, Q.optr, Q.n + 1, s));
+    QA_TRY(to_host(ocol, Q.ocol, Q.ovf_nnz, s));
+    QA_TRY(to_host(oval, Q.oval64, Q.ovf_nnz, s));
+    QA_HIP(hipStreamSynchronize(s));
+    int64_t o = 0;
+    if (ovf_ptr) ovf_ptr[0] = 0;
+    for (uint32_t I = 0; I < static_cast<uint32_t>(Q.n); I++) {
+      const uint32_t q = host_q_of_lex(I, Q.k);
+      for (int32_t e = optr[q]; e < optr[q + 1]; e++, o++) {
+        if (ovf_col) ovf_col[o] = static_cast<int32_t>(host_lex_of_q(static_cast<uint32_t>(ocol[e]), Q.k));
+        if (ovf_val) ovf_val[o] = oval[e];
+      }
+      if (ovf_ptr) ovf_ptr[I + 1] = o;
+    }
+  }
+  return AMG_OK;
+}
+
+extern "C" amg_status amg_export_level_f32(const amg_hierarchy *h, int32_t level, float *ax) {
+  if (!h || level < 1 || level >= h->nlev || !ax) return AMG_ERR_INVALID;
+  QA_HIP(hipSetDevice(h->device));
+  return export_values<float>(h, level, h->lev[level].ax32, ax);
+}

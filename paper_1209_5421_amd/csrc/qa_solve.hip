@@ -1,0 +1,1007 @@
+// Solve phase on gfx950: the nonlinear AMLI-cycle (Algorithm 2.2) with the nonlinear PCG of Algorithm 2.1 as its
+// coarse-level accelerator, used as the preconditioner of an outer flexible CG at the fine level.
+//
+// Kernels are templated on the storage/arithmetic type T (double for the plain solve, float for the
+// preconditioner of the mixed form); every inner product accumulates in double with a fixed reduction tree
+// (wavefront shuffles, then the four waves of a workgroup, then the workgroup partials summed in order by the last
+// workgroup to finish), so results depend only on the system size, never on scheduling.
+//
+// Fine level: sliced ELL (64-row slices = one wavefront, column-major, so every load of a slice row step is one
+// coalesced 256/512-byte access). The colored block Gauss-Seidel phase (Section 4.5) is split in two kernels: the
+// residual of the color's rows (sliced-ELL pass), then one thread per cell doing the forward/backward
+// substitution over the cell's unknowns with the in-cell couplings. The kernel boundary between the two is what
+// makes every residual of a color see the iterate at phase start.
+//
+// Quadtree levels: values only (9 per row, slot-major so each slot is a coalesced stream), neighbour indices
+// recomputed from the color-major Morton index; overflow couplings from a small CSR.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+
+#include "qa_internal.hpp"
+
+namespace qa {
+
+// ---------------------------------------------------------------------------------------------------------------
+// scalar slots (per level, kScalars doubles; the outer iteration uses slot block nlev)
+
+enum {
+  S_D0 = 0, S_S0 = 1, S_A0 = 2, S_STOP = 3, S_T = 4, S_BETA = 5, S_D1 = 6, S_S1 = 7, S_A1 = 8,
+  O_D = 0, O_S = 1, O_ALPHA = 2, O_BREAK = 3, O_ZQ = 4, O_BETA = 5, O_RR = 6, O_TT = 7, O_BB = 8
+};
+enum Epi { EPI_ALPHA0, EPI_BETA, EPI_ALPHA1, EPI_OUT_ALPHA, EPI_OUT_BETA, EPI_STORE };
+
+struct Red {
+  double *partials;
+  unsigned *counter;
+  double *sc;
+  int epi;
+  int slot;
+};
+
+__device__ inline void st_agent(double *p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(__double_as_longlong(v)),
+                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_agent(const double *p) {
+  return __longlong_as_double(static_cast<long long>(
+      __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
+}
+
+// sum over the workgroup (fixed order); valid in thread 0
+template <int ND>
+__device__ inline void block_sum(double (&v)[ND]) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int j = 0; j < ND; j++) v[j] += __shfl_down(v[j], off, 64);
+  __shared__ double s[ND][kBlock / 64];
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int j = 0; j < ND; j++) s[j][threadIdx.x >> 6] = v[j];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int j = 0; j < ND; j++) v[j] = (s[j][0] + s[j][1]) + (s[j][2] + s[j][3]);
+}
+
+__device__ inline void epilogue(const double *acc, const Red &R) {
+  double *sc = R.sc;
+  switch (R.epi) {
+    case EPI_ALPHA0: {
+      const double d = acc[0], s = acc[1];
+      const bool stop = !(d > 0.0);
+      sc[S_D0] = d; sc[S_S0] = s; sc[S_STOP] = stop ? 1.0 : 0.0; sc[S_A0] = stop ? 0.0 : s / d;
+      break;
+    }
+    case EPI_BETA:
+      sc[S_T] = acc[0];
+      sc[S_BETA] = (sc[S_STOP] != 0.0) ? 0.0 : -acc[0] / sc[S_D0];
+      break;
+    case EPI_ALPHA1: {
+      const double d = acc[0], s = acc[1];
+      sc[S_D1] = d; sc[S_S1] = s;
+      sc[S_A1] = (sc[S_STOP] != 0.0 || !(d > 0.0)) ? 0.0 : s / d;
+      break;
+    }
+    case EPI_OUT_ALPHA: {
+      const double d = acc[0], s = acc[1];
+      const bool ok = d > 0.0;
+      sc[O_D] = d; sc[O_S] = s; sc[O_ALPHA] = ok ? s / d : 0.0; sc[O_BREAK] = ok ? 0.0 : 1.0;
+      break;
+    }
+    case EPI_OUT_BETA:
+      sc[O_ZQ] = acc[0];
+      sc[O_BETA] = -acc[0] / sc[O_D];
+      break;
+    default:
+      sc[R.slot] = acc[0];
+  }
+}
+
+// Every thread of every workgroup must call this (no early returns in reduction kernels).
+template <int ND>
+__device__ inline void reduce_finish(double (&v)[ND], const Red &R) {
+  block_sum<ND>(v);
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < ND; j++) st_agent(&R.partials[static_cast<size_t>(blockIdx.x) * ND + j], v[j]);
+    __threadfence();
+    const unsigned t = __hip_atomic_fetch_add(R.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (t == gridDim.x - 1) ? 1 : 0;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  double acc[ND];
+#pragma unroll
+  for (int j = 0; j < ND; j++) acc[j] = 0.0;
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += kBlock)
+#pragma unroll
+    for (int j = 0; j < ND; j++) acc[j] += ld_agent(&R.partials[static_cast<size_t>(b) * ND + j]);
+  block_sum<ND>(acc);
+  if (threadIdx.x == 0) {
+    epilogue(acc, R);
+    __threadfence();
+    __hip_atomic_store(R.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// fine level kernels
+
+template <class T>
+struct SellView {
+  const int64_t *ptr;
+  const int32_t *row0;
+  const int32_t *col;
+  const T *val;
+};
+
+// d[p] = f[p] - (A x)[p] for the rows of slices [s_begin, s_end); one wavefront per slice
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fine_resid(SellView<T> S, const T *__restrict__ f,
+                                                        const T *__restrict__ x, T *__restrict__ d, int64_t s_begin,
+                                                        int64_t s_end) {
+  const int64_t s = s_begin + static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  if (s >= s_end) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t r0 = S.row0[s], r1 = S.row0[s + 1];
+  const int32_t row = r0 + lane;
+  if (row >= r1) return;
+  const int64_t off = S.ptr[s];
+  const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
+  T acc = 0;
+  for (int k = 0; k < w; k++) {
+    const int64_t e = off + static_cast<int64_t>(k) * 64 + lane;
+    acc += S.val[e] * x[S.col[e]];
+  }
+  d[row] = f[row] - acc;
+}
+
+// y = A x over all slices (level hook)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fine_apply(SellView<T> S, int64_t nslices, const T *__restrict__ x,
+                                                        T *__restrict__ y) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  if (s >= nslices) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t row = S.row0[s] + lane;
+  if (row >= S.row0[s + 1]) return;
+  const int64_t off = S.ptr[s];
+  const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
+  T acc = 0;
+  for (int k = 0; k < w; k++) {
+    const int64_t e = off + static_cast<int64_t>(k) * 64 + lane;
+    acc += S.val[e] * x[S.col[e]];
+  }
+  y[row] = acc;
+}
+
+// In-cell substitution of one color phase: thread per cell q in [q_begin, q_end). FWD: delta_p = (r_p - sum_{c<p}
+// a_pc delta_c) / a_pp over the cell's rows ascending; else descending with c > p. r comes from src (the
+// residual pass, or f itself for the first phase of a sweep from zero); delta overwrites d; x += delta.
+template <class T, bool FWD>
+__global__ void __launch_bounds__(kBlock) k_fine_subst(const int32_t *__restrict__ crow,
+                                                        const int32_t *__restrict__ icp,
+                                                        const int32_t *__restrict__ icc, const T *__restrict__ icv,
+                                                        const T *__restrict__ diag, const T *__restrict__ src,
+                                                        T *__restrict__ d, T *__restrict__ x, int64_t q_begin,
+                                                        int64_t q_end) {
+  const int64_t q = q_begin + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= q_end) return;
+  const int32_t a = crow[q], b = crow[q + 1];
+  if (FWD) {
+    for (int32_t p = a; p < b; p++) {
+      T acc = src[p];
+      for (int32_t e = icp[p]; e < icp[p + 1]; e++) {
+        const int32_t c = icc[e];
+        if (c < p) acc -= icv[e] * d[c];
+      }
+      d[p] = acc / diag[p];
+    }
+  } else {
+    for (int32_t p = b - 1; p >= a; p--) {
+      T acc = src[p];
+      for (int32_t e = icp[p]; e < icp[p + 1]; e++) {
+        const int32_t c = icc[e];
+        if (c > p) acc -= icv[e] * d[c];
+      }
+      d[p] = acc / diag[p];
+    }
+  }
+  for (int32_t p = a; p < b; p++) x[p] += d[p];
+}
+
+// g[q] = sum of d over the rows of level-L cell q (rows ascending)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fine_restrict(int64_t nL, const int32_t *__restrict__ crow,
+                                                           const T *__restrict__ d, T *__restrict__ g) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nL) return;
+  T acc = 0;
+  for (int32_t p = crow[q]; p < crow[q + 1]; p++) acc += d[p];
+  g[q] = acc;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fine_prolong(int64_t n, const int32_t *__restrict__ agg_q,
+                                                          const T *__restrict__ e, T *__restrict__ u) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n) u[p] += e[agg_q[p]];
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// quadtree level kernels
+
+template <class T>
+struct QView {
+  int k;
+  int64_t n;
+  const T *ax;       // 9 x n slot-major
+  const int32_t *optr;  // null when the level has no overflow
+  const int32_t *ocol;
+  const T *oval;
+};
+
+// (A x)_q for row q with Morton coordinates (t1, t2)
+template <class T>
+__device__ inline T row_apply(const QView<T> &Q, uint32_t q, int t1, int t2, const T *__restrict__ x) {
+  const int side = 1 << Q.k;
+  T acc = 0;
+#pragma unroll
+  for (int s = 0; s < 9; s++) {
+    const int u1 = t1 + slot_dx(s), u2 = t2 + slot_dy(s);
+    if (u1 >= 0 && u2 >= 0 && u1 < side && u2 < side)
+      acc += Q.ax[s * Q.n + q] * x[q_of_m(morton(static_cast<uint32_t>(u1), static_cast<uint32_t>(u2)), Q.k)];
+  }
+  if (Q.optr)
+    for (int32_t e = Q.optr[q]; e < Q.optr[q + 1]; e++) acc += Q.oval[e] * x[Q.ocol[e]];
+  return acc;
+}
+
+// first phase of a sweep from zero: x = f / diag on color 0, zero elsewhere
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cgs_first(QView<T> Q, const T *__restrict__ f, T *__restrict__ x) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= Q.n) return;
+  x[q] = (q < (Q.n >> 2)) ? f[q] / Q.ax[q] : T(0);
+}
+
+// one color phase of the pointwise 4-color Gauss-Seidel: rows q = c n/4 + j, Morton m = 4 j + c.
+// delta == nullptr: update in place (valid when no coupling joins two cells of color c); else write delta only.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cgs(QView<T> Q, const T *__restrict__ f, T *__restrict__ x,
+                                                T *__restrict__ delta, int c) {
+  const int64_t n4 = Q.n >> 2;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n4) return;
+  const uint32_t q = static_cast<uint32_t>(c * n4 + j);
+  const uint32_t m = (static_cast<uint32_t>(j) << 2) | static_cast<uint32_t>(c);
+  const int t1 = static_cast<int>(compact_bits(m)), t2 = static_cast<int>(compact_bits(m >> 1));
+  const T dl = (f[q] - row_apply(Q, q, t1, t2, x)) / Q.ax[q];
+  if (delta) delta[q] = dl;
+  else x[q] += dl;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_add_range(int64_t begin, int64_t count, const T *__restrict__ delta,
+                                                       T *__restrict__ x) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) x[begin + i] += delta[begin + i];
+}
+
+// residual of the four children of coarse cell M, summed in the order 0, 1, 3, 2 (Section 4.3's explicit
+// restriction), written to the parent's color-major slot
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cres_restrict(QView<T> Q, const T *__restrict__ f,
+                                                           const T *__restrict__ u, T *__restrict__ g) {
+  const int64_t n4 = Q.n >> 2;
+  const int64_t M = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (M >= n4) return;
+  const int order[4] = {0, 1, 3, 2};
+  T acc = 0;
+#pragma unroll
+  for (int oi = 0; oi < 4; oi++) {
+    const int c = order[oi];
+    const uint32_t q = static_cast<uint32_t>(c * n4 + M);
+    const uint32_t m = (static_cast<uint32_t>(M) << 2) | static_cast<uint32_t>(c);
+    const int t1 = static_cast<int>(compact_bits(m)), t2 = static_cast<int>(compact_bits(m >> 1));
+    acc += f[q] - row_apply(Q, q, t1, t2, u);
+  }
+  g[q_of_m(static_cast<uint32_t>(M), Q.k - 1)] = acc;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cprolong(int k, int64_t n, const T *__restrict__ e, T *__restrict__ u) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  // children of M are q = c n/4 + M: the parent's Morton index is q mod n/4
+  const uint32_t M = static_cast<uint32_t>(q & ((n >> 2) - 1));
+  u[q] += e[q_of_m(M, k - 1)];
+}
+
+// y = A x on a quadtree level with two inner products (x, y) and (w, x); grid-stride, fixed grid
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cspmv_dot(QView<T> Q, const T *__restrict__ x, T *__restrict__ y,
+                                                       const T *__restrict__ w, Red R) {
+  double v[2] = {0.0, 0.0};
+  for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < Q.n;
+       q += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const uint32_t m = m_of_q(static_cast<uint32_t>(q), Q.k);
+    const int t1 = static_cast<int>(compact_bits(m)), t2 = static_cast<int>(compact_bits(m >> 1));
+    const T yq = row_apply(Q, static_cast<uint32_t>(q), t1, t2, x);
+    y[q] = yq;
+    const double xq = static_cast<double>(x[q]);
+    v[0] += xq * static_cast<double>(yq);
+    v[1] += static_cast<double>(w[q]) * xq;
+  }
+  reduce_finish<2>(v, R);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// vector kernels of Algorithm 2.1 (n = 2); scalars are read from device memory
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_update1(int64_t n, const double *__restrict__ sc,
+                                                     const T *__restrict__ p0, const T *__restrict__ q0,
+                                                     const T *__restrict__ g, T *__restrict__ e, T *__restrict__ r) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const T a = static_cast<T>(sc[S_A0]);
+  e[i] = a * p0[i];
+  r[i] = g[i] - a * q0[i];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dot(int64_t n, const T *__restrict__ a, const T *__restrict__ b, Red R) {
+  double v[1] = {0.0};
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    v[0] += static_cast<double>(a[i]) * static_cast<double>(b[i]);
+  reduce_finish<1>(v, R);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_axpy_beta(int64_t n, const double *__restrict__ sc, T *__restrict__ p1,
+                                                       const T *__restrict__ p0) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p1[i] += static_cast<T>(sc[S_BETA]) * p0[i];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_update2(int64_t n, const double *__restrict__ sc, const T *__restrict__ p1,
+                                                     T *__restrict__ e) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) e[i] += static_cast<T>(sc[S_A1]) * p1[i];
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fill(int64_t n, T *__restrict__ v, T val) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = val;
+}
+
+// e = A^{-1} g on the coarsest level (FP64 arithmetic whatever T is); one workgroup
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dense_solve(int n, const double *__restrict__ ainv,
+                                                         const T *__restrict__ g, T *__restrict__ e) {
+  __shared__ double sg[1024];
+  for (int i = threadIdx.x; i < n; i += kBlock) sg[i] = static_cast<double>(g[i]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    double acc = 0.0;
+    for (int j = 0; j < n; j++) acc += ainv[static_cast<size_t>(i) * n + j] * sg[j];
+    e[i] = static_cast<T>(acc);
+  }
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// outer flexible CG kernels (FP64, permuted numbering)
+
+// q = A p over all slices, with (p, q) and (r, p); one wavefront per slice
+__global__ void __launch_bounds__(kBlock) k_outer_spmv_dot(SellView<double> S, int64_t nslices,
+                                                            const double *__restrict__ p, double *__restrict__ q,
+                                                            const double *__restrict__ r, Red R) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  double v[2] = {0.0, 0.0};
+  if (s < nslices) {
+    const int32_t row = S.row0[s] + lane;
+    if (row < S.row0[s + 1]) {
+      const int64_t off = S.ptr[s];
+      const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
+      double acc = 0.0;
+      for (int k = 0; k < w; k++) {
+        const int64_t e = off + static_cast<int64_t>(k) * 64 + lane;
+        acc += S.val[e] * p[S.col[e]];
+      }
+      q[row] = acc;
+      v[0] = p[row] * acc;
+      v[1] = r[row] * p[row];
+    }
+  }
+  reduce_finish<2>(v, R);
+}
+
+// t = b - A x with (t, t)
+__global__ void __launch_bounds__(kBlock) k_outer_true_resid(SellView<double> S, int64_t nslices,
+                                                              const double *__restrict__ b,
+                                                              const double *__restrict__ x, double *__restrict__ t,
+                                                              Red R) {
+  const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  double v[1] = {0.0};
+  if (s < nslices) {
+    const int32_t row = S.row0[s] + lane;
+    if (row < S.row0[s + 1]) {
+      const int64_t off = S.ptr[s];
+      const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
+      double acc = 0.0;
+      for (int k = 0; k < w; k++) {
+        const int64_t e = off + static_cast<int64_t>(k) * 64 + lane;
+        acc += S.val[e] * x[S.col[e]];
+      }
+      const double tr = b[row] - acc;
+      t[row] = tr;
+      v[0] = tr * tr;
+    }
+  }
+  reduce_finish<1>(v, R);
+}
+
+// x += alpha p, r -= alpha q, with (r, r)
+__global__ void __launch_bounds__(kBlock) k_outer_update(int64_t n, const double *__restrict__ sc,
+                                                          const double *__restrict__ p, const double *__restrict__ q,
+                                                          double *__restrict__ x, double *__restrict__ r, Red R) {
+  const double a = sc[O_ALPHA];
+  double v[1] = {0.0};
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock) {
+    x[i] += a * p[i];
+    const double ri = r[i] - a * q[i];
+    r[i] = ri;
+    v[0] += ri * ri;
+  }
+  reduce_finish<1>(v, R);
+}
+
+// p = z + beta pprev (beta from the scalar block when use_beta)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_outer_dir(int64_t n, const double *__restrict__ sc,
+                                                       const T *__restrict__ z, const double *__restrict__ pprev,
+                                                       double *__restrict__ p, int use_beta) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double zi = static_cast<double>(z[i]);
+  p[i] = use_beta ? zi + sc[O_BETA] * pprev[i] : zi;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_dot_mixed(int64_t n, const T *__restrict__ a, const double *__restrict__ b,
+                                                       Red R) {
+  double v[1] = {0.0};
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    v[0] += static_cast<double>(a[i]) * b[i];
+  reduce_finish<1>(v, R);
+}
+
+template <class S, class D>
+__global__ void __launch_bounds__(kBlock) k_gather(int64_t n, const int32_t *__restrict__ perm,
+                                                    const S *__restrict__ src, D *__restrict__ dst) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n) dst[p] = static_cast<D>(src[perm[p]]);
+}
+
+template <class S, class D>
+__global__ void __launch_bounds__(kBlock) k_scatter_back(int64_t n, const int32_t *__restrict__ perm,
+                                                          const S *__restrict__ src, D *__restrict__ dst) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p < n) dst[perm[p]] = static_cast<D>(src[p]);
+}
+
+template <class S, class D>
+__global__ void __launch_bounds__(kBlock) k_cast(int64_t n, const S *__restrict__ src, D *__restrict__ dst) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = static_cast<D>(src[i]);
+}
+
+// lexicographic <-> color-major numbering of a quadtree level (tests and level hooks)
+template <class S, class D>
+__global__ void __launch_bounds__(kBlock) k_lex_to_q(int k, int64_t n, const S *__restrict__ src, D *__restrict__ dst,
+                                                      int inverse) {
+  const int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (I >= n) return;
+  const uint32_t t1 = static_cast<uint32_t>(I) & ((1u << k) - 1u), t2 = static_cast<uint32_t>(I) >> k;
+  const uint32_t q = q_of_m(morton(t1, t2), k);
+  if (inverse) dst[I] = static_cast<D>(src[q]);
+  else dst[q] = static_cast<D>(src[I]);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// host orchestration
+
+static inline unsigned nblk(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+static inline unsigned nred(int64_t n) { return static_cast<unsigned>(std::min<int64_t>(nblk(n), kRedBlocksMax)); }
+
+template <class T> struct P;
+template <> struct P<double> {
+  static std::vector<LevelWork<double>> &W(amg_hierarchy *h) { return h->w64; }
+  static const double *ax(const QuadLevel &Q) { return Q.ax64; }
+  static const double *oval(const QuadLevel &Q) { return Q.oval64; }
+  static const double *sval(const FineLevel &F) { return F.s_val64; }
+  static const double *diag(const FineLevel &F) { return F.diag64; }
+  static const double *icv(const FineLevel &F) { return F.ic_val64; }
+  static constexpr int kResid = KK_RESID_FINE64, kGs = KK_GS_FINE64;
+};
+template <> struct P<float> {
+  static std::vector<LevelWork<float>> &W(amg_hierarchy *h) { return h->w32; }
+  static const float *ax(const QuadLevel &Q) { return Q.ax32; }
+  static const float *oval(const QuadLevel &Q) { return Q.oval32; }
+  static const float *sval(const FineLevel &F) { return F.s_val32; }
+  static const float *diag(const FineLevel &F) { return F.diag32; }
+  static const float *icv(const FineLevel &F) { return F.ic_val32; }
+  static constexpr int kResid = KK_RESID_FINE32, kGs = KK_GS_FINE32;
+};
+
+template <class T>
+static QView<T> qview(const QuadLevel &Q) {
+  return QView<T>{Q.k, Q.n, P<T>::ax(Q), Q.ovf_nnz ? Q.optr : nullptr, Q.ocol, P<T>::oval(Q)};
+}
+template <class T>
+static SellView<T> sview(const FineLevel &F, const T *val) {
+  return SellView<T>{F.slice_ptr, F.slice_row0, F.s_col, val};
+}
+static Red red(amg_hierarchy *h, int l, int epi, int slot = 0) {
+  return Red{h->partials, h->counters, h->scal + static_cast<size_t>(l) * kScalars, epi, slot};
+}
+
+// kernel timing: events around launches of the selected family
+struct Timed {
+  amg_hierarchy *h;
+  bool on;
+  Timed(amg_hierarchy *hh, int kind) : h(hh), on(kind >= 0 && hh->timing.kind == kind && hh->timing.used + 2 <= hh->timing.ev.size()) {
+    if (on) (void)hipEventRecord(h->timing.ev[h->timing.used], h->stream);
+  }
+  ~Timed() {
+    if (on) {
+      (void)hipEventRecord(h->timing.ev[h->timing.used + 1], h->stream);
+      h->timing.used += 2;
+    }
+  }
+};
+
+template <class T> static void btilde(amg_hierarchy *h, int l, const T *g, T *e);
+
+template <class T>
+static void coarse_solve_or_cycle(amg_hierarchy *h, int l) {
+  LevelWork<T> &w = P<T>::W(h)[l];
+  if (l == h->nlev - 1) {
+    k_dense_solve<T><<<1, kBlock, 0, h->stream>>>(static_cast<int>(h->nc), h->ainv, w.g, w.e);
+  } else {
+    btilde<T>(h, l, w.g, w.e);
+  }
+}
+
+template <class T>
+static void gs_phase_coarse(amg_hierarchy *h, int l, const T *f, T *u, int c) {
+  const QuadLevel &Q = h->lev[l];
+  const int64_t n4 = Q.n >> 2;
+  if (Q.same_color_ovf) {
+    T *dl = P<T>::W(h)[l].d;
+    k_cgs<T><<<nblk(n4), kBlock, 0, h->stream>>>(qview<T>(Q), f, u, dl, c);
+    k_add_range<T><<<nblk(n4), kBlock, 0, h->stream>>>(c * n4, n4, dl, u);
+  } else {
+    k_cgs<T><<<nblk(n4), kBlock, 0, h->stream>>>(qview<T>(Q), f, u, nullptr, c);
+  }
+}
+
+// B^_l for a quadtree level l (not the coarsest): Algorithm 2.2
+template <class T>
+static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u) {
+  const QuadLevel &Q = h->lev[l];
+  hipStream_t s = h->stream;
+  const int sweeps = h->opt.sweeps;
+  for (int sw = 0; sw < sweeps; sw++)
+    for (int c = 0; c < 4; c++) {
+      if (sw == 0 && c == 0) k_cgs_first<T><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u);
+      else gs_phase_coarse<T>(h, l, f, u, c);
+    }
+  LevelWork<T> &wc = P<T>::W(h)[l + 1];
+  k_cres_restrict<T><<<nblk(Q.n >> 2), kBlock, 0, s>>>(qview<T>(Q), f, u, wc.g);
+  coarse_solve_or_cycle<T>(h, l + 1);
+  k_cprolong<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, wc.e, u);
+  for (int sw = 0; sw < sweeps; sw++)
+    for (int c = 3; c >= 0; c--) gs_phase_coarse<T>(h, l, f, u, c);
+}
+
+template <class T>
+static void fine_resid(amg_hierarchy *h, const T *f, const T *x, T *d, int64_t s0, int64_t s1, int kind) {
+  if (s1 <= s0) return;
+  Timed tm(h, kind);
+  k_fine_resid<T><<<static_cast<unsigned>((s1 - s0 + 3) / 4), kBlock, 0, h->stream>>>(
+      sview<T>(h->fine, P<T>::sval(h->fine)), f, x, d, s0, s1);
+}
+
+template <class T>
+static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd, bool from_f) {
+  const FineLevel &F = h->fine;
+  const int64_t nL4 = static_cast<int64_t>(1) << (2 * h->L - 2);
+  const T *src = d;
+  if (from_f) src = f;
+  else fine_resid<T>(h, f, u, d, F.color_slice[c], F.color_slice[c + 1], P<T>::kGs);
+  const int64_t q0 = c * nL4, q1 = (c + 1) * nL4;
+  if (fwd)
+    k_fine_subst<T, true><<<nblk(nL4), kBlock, 0, h->stream>>>(F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F),
+                                                                P<T>::diag(F), src, d, u, q0, q1);
+  else
+    k_fine_subst<T, false><<<nblk(nL4), kBlock, 0, h->stream>>>(F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F),
+                                                                 P<T>::diag(F), src, d, u, q0, q1);
+}
+
+// B^_F on the fine level (f, u in permuted numbering)
+template <class T>
+static void bhat_fine(amg_hierarchy *h, const T *f, T *u) {
+  const FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  LevelWork<T> &w = P<T>::W(h)[0];
+  k_fill<T><<<nblk(F.n), kBlock, 0, s>>>(F.n, u, T(0));
+  const int sweeps = h->opt.sweeps;
+  for (int sw = 0; sw < sweeps; sw++)
+    for (int c = 0; c < 4; c++) fine_phase<T>(h, f, u, w.d, c, true, sw == 0 && c == 0);
+  LevelWork<T> &wc = P<T>::W(h)[1];
+  fine_resid<T>(h, f, u, w.d, 0, F.nslices, P<T>::kResid);
+  const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
+  k_fine_restrict<T><<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, w.d, wc.g);
+  coarse_solve_or_cycle<T>(h, 1);
+  k_fine_prolong<T><<<nblk(F.n), kBlock, 0, s>>>(F.n, F.agg_q, wc.e, u);
+  for (int sw = 0; sw < sweeps; sw++)
+    for (int c = 3; c >= 0; c--) fine_phase<T>(h, f, u, w.d, c, false, false);
+}
+
+template <class T>
+static void bhat(amg_hierarchy *h, int l, const T *f, T *u) {
+  if (l == 0) bhat_fine<T>(h, f, u);
+  else bhat_coarse<T>(h, l, f, u);
+}
+
+// B~_l: Algorithm 2.1 with n = inner_iters (1 or 2) steps and B^_l as preconditioner
+template <class T>
+static void btilde(amg_hierarchy *h, int l, const T *g, T *e) {
+  const QuadLevel &Q = h->lev[l];
+  LevelWork<T> &w = P<T>::W(h)[l];
+  hipStream_t s = h->stream;
+  const double *sc = h->scal + static_cast<size_t>(l) * kScalars;
+  bhat<T>(h, l, g, w.p0);
+  k_cspmv_dot<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), w.p0, w.q0, g, red(h, l, EPI_ALPHA0));
+  k_update1<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p0, w.q0, g, e, w.r);
+  if (h->opt.inner_iters < 2) return;
+  bhat<T>(h, l, w.r, w.p1);
+  k_dot<T><<<nred(Q.n), kBlock, 0, s>>>(Q.n, w.p1, w.q0, red(h, l, EPI_BETA));
+  k_axpy_beta<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p1, w.p0);
+  k_cspmv_dot<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), w.p1, w.q1, w.r, red(h, l, EPI_ALPHA1));
+  k_update2<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p1, e);
+}
+
+// z = B^_F[r] in the requested precision (r, z: FP64, permuted numbering)
+amg_status precond_apply(amg_hierarchy *h, int precision, const double *r, double *z) {
+  const int64_t n = h->n;
+  hipStream_t s = h->stream;
+  if (h->nlev == 1) {
+    k_dense_solve<double><<<1, kBlock, 0, s>>>(static_cast<int>(h->nc), h->ainv, r, z);
+    QA_LAUNCH_CHECK();
+    return AMG_OK;
+  }
+  if (precision == 1) {
+    LevelWork<float> &w = h->w32[0];
+    k_cast<double, float><<<nblk(n), kBlock, 0, s>>>(n, r, w.f);
+    bhat_fine<float>(h, w.f, w.u);
+    k_cast<float, double><<<nblk(n), kBlock, 0, s>>>(n, w.u, z);
+  } else {
+    bhat_fine<double>(h, r, z);
+  }
+  QA_LAUNCH_CHECK();
+  return AMG_OK;
+}
+
+amg_status alloc_workspaces(amg_hierarchy *h) {
+  const int64_t n = h->n;
+  h->w64.assign(h->nlev, LevelWork<double>{});
+  h->w32.assign(h->nlev, LevelWork<float>{});
+  {
+    auto mk = [&](auto &W) -> bool {
+      using T = std::remove_pointer_t<decltype(W[0].f)>;
+      W[0].f = dalloc_n<T>(h, n);
+      W[0].u = dalloc_n<T>(h, n);
+      W[0].d = dalloc_n<T>(h, n);
+      if (!W[0].f || !W[0].u || !W[0].d) return false;
+      for (int l = 1; l < h->nlev; l++) {
+        const int64_t m = h->lev[l].n;
+        W[l].g = dalloc_n<T>(h, m);
+        W[l].e = dalloc_n<T>(h, m);
+        if (!W[l].g || !W[l].e) return false;
+        if (l < h->nlev - 1) {
+          W[l].r = dalloc_n<T>(h, m);
+          W[l].p0 = dalloc_n<T>(h, m);
+          W[l].q0 = dalloc_n<T>(h, m);
+          W[l].p1 = dalloc_n<T>(h, m);
+          W[l].q1 = dalloc_n<T>(h, m);
+          W[l].d = dalloc_n<T>(h, m);
+          if (!W[l].r || !W[l].p0 || !W[l].q0 || !W[l].p1 || !W[l].q1 || !W[l].d) return false;
+        }
+      }
+      return true;
+    };
+    if (!mk(h->w64) || !mk(h->w32)) return AMG_ERR_NOMEM;
+  }
+  double **outer[] = {&h->xp, &h->rp, &h->bp, &h->zp, &h->pp, &h->qp, &h->pprev, &h->qprev, &h->tp};
+  for (double **v : outer) {
+    *v = dalloc_n<double>(h, n);
+    if (!*v) return AMG_ERR_NOMEM;
+  }
+  h->scal = dalloc_n<double>(h, (h->nlev + 1) * kScalars);
+  h->partials_cap = std::max<int64_t>(kRedBlocksMax, (h->fine.nslices + 3) / 4 + 1) * 2;
+  h->partials = dalloc_n<double>(h, h->partials_cap);
+  h->counters = dalloc_n<unsigned>(h, 4);
+  if (!h->scal || !h->partials || !h->counters) return AMG_ERR_NOMEM;
+  QA_HIP(hipMemsetAsync(h->scal, 0, sizeof(double) * (h->nlev + 1) * kScalars, h->stream));
+  QA_HIP(hipMemsetAsync(h->counters, 0, sizeof(unsigned) * 4, h->stream));
+  QA_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->host_scal), sizeof(double) * kScalars, hipHostMallocDefault));
+  return AMG_OK;
+}
+
+double kernel_bytes(const amg_hierarchy *h, int kind) {
+  const double n = static_cast<double>(h->n), nnz = static_cast<double>(h->fine.nnz);
+  switch (kind) {
+    case KK_SPMV64: return 12.0 * nnz + 24.0 * n;   // values + columns, x, q written, r read for (r, p)
+    case KK_RESID_FINE64: return 12.0 * nnz + 24.0 * n;
+    case KK_RESID_FINE32: return 8.0 * nnz + 12.0 * n;
+    case KK_GS_FINE64: return (12.0 * nnz + 24.0 * n) / 4.0;
+    case KK_GS_FINE32: return (8.0 * nnz + 12.0 * n) / 4.0;
+  }
+  return 0.0;
+}
+
+static amg_status read_scalars(amg_hierarchy *h, int first, int count) {
+  const double *src = h->scal + static_cast<size_t>(h->nlev) * kScalars + first;
+  QA_HIP(hipMemcpyAsync(h->host_scal + first, src, sizeof(double) * count, hipMemcpyDeviceToHost, h->stream));
+  QA_HIP(hipStreamSynchronize(h->stream));
+  return AMG_OK;
+}
+
+static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, double tol, amg_info *info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = h->n;
+  const FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  const int L0 = h->nlev;  // outer scalar block
+  const double *osc = h->scal + static_cast<size_t>(L0) * kScalars;
+  const unsigned nsl_blocks = static_cast<unsigned>((F.nslices + 3) / 4);
+  SellView<double> A64 = sview<double>(F, F.s_val64);
+  amg_info inf{};
+  inf.setup_ms = h->setup_ms;
+
+  k_gather<double, double><<<nblk(n), kBlock, 0, s>>>(n, F.perm, b, h->bp);
+  k_dot<double><<<nred(n), kBlock, 0, s>>>(n, h->bp, h->bp, red(h, L0, EPI_STORE, O_BB));
+  k_fill<double><<<nblk(n), kBlock, 0, s>>>(n, h->xp, 0.0);
+  QA_LAUNCH_CHECK();
+  QA_TRY(read_scalars(h, O_BB, 1));
+  const double bn = std::sqrt(h->host_scal[O_BB]);
+  if (bn == 0.0) {
+    k_fill<double><<<nblk(n), kBlock, 0, s>>>(n, x, 0.0);
+    QA_HIP(hipStreamSynchronize(s));
+    inf.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = inf;
+    return AMG_OK;
+  }
+  QA_HIP(hipMemcpyAsync(h->rp, h->bp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+  amg_status st = AMG_ERR_NOCONV;
+  int it = 0;
+  bool have_prev = false;
+  double *p = h->pp, *q = h->qp, *pprev = h->pprev, *qprev = h->qprev;
+  const int prec = h->precision;
+  while (it < h->opt.max_iters) {
+    QA_TRY(precond_apply(h, prec, h->rp, h->zp));
+    const bool use_beta = have_prev && h->opt.outer_mmax == 1;
+    if (use_beta) k_dot<double><<<nred(n), kBlock, 0, s>>>(n, h->zp, qprev, red(h, L0, EPI_OUT_BETA));
+    k_outer_dir<double><<<nblk(n), kBlock, 0, s>>>(n, osc, h->zp, pprev, p, use_beta ? 1 : 0);
+    {
+      Timed tm(h, KK_SPMV64);
+      k_outer_spmv_dot<<<nsl_blocks, kBlock, 0, s>>>(A64, F.nslices, p, q, h->rp, red(h, L0, EPI_OUT_ALPHA));
+    }
+    k_outer_update<<<nred(n), kBlock, 0, s>>>(n, osc, p, q, h->xp, h->rp, red(h, L0, EPI_STORE, O_RR));
+    QA_LAUNCH_CHECK();
+    QA_TRY(read_scalars(h, 0, O_BB));
+    if (h->host_scal[O_BREAK] != 0.0) {
+      st = AMG_ERR_BREAKDOWN;
+      break;
+    }
+    it++;
+    have_prev = true;
+    std::swap(p, pprev);
+    std::swap(q, qprev);
+    if (std::sqrt(h->host_scal[O_RR]) <= tol * bn) {
+      k_outer_true_resid<<<nsl_blocks, kBlock, 0, s>>>(A64, F.nslices, h->bp, h->xp, h->tp,
+                                                        red(h, L0, EPI_STORE, O_TT));
+      QA_LAUNCH_CHECK();
+      QA_TRY(read_scalars(h, O_TT, 1));
+      if (std::sqrt(h->host_scal[O_TT]) <= tol * bn) {
+        st = AMG_OK;
+        break;
+      }
+      QA_HIP(hipMemcpyAsync(h->rp, h->tp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+      have_prev = false;
+      inf.restarts++;
+    }
+  }
+  k_outer_true_resid<<<nsl_blocks, kBlock, 0, s>>>(A64, F.nslices, h->bp, h->xp, h->tp, red(h, L0, EPI_STORE, O_TT));
+  k_scatter_back<double, double><<<nblk(n), kBlock, 0, s>>>(n, F.perm, h->xp, x);
+  QA_LAUNCH_CHECK();
+  QA_TRY(read_scalars(h, O_TT, 1));
+  inf.iters = it;
+  inf.relres = std::sqrt(h->host_scal[O_TT]) / bn;
+  inf.solve_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  return st;
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// level hooks (tests): vectors in canonical numbering
+
+template <class T>
+static amg_status level_smooth_t(amg_hierarchy *h, int level, const double *f, double *x, int forward) {
+  hipStream_t s = h->stream;
+  std::vector<LevelWork<T>> &W = P<T>::W(h);
+  if (level == 0) {
+    const FineLevel &F = h->fine;
+    const int64_t n = F.n;
+    T *ff = W[0].f, *xx = W[0].u;
+    k_gather<double, T><<<nblk(n), kBlock, 0, s>>>(n, F.perm, f, ff);
+    k_gather<double, T><<<nblk(n), kBlock, 0, s>>>(n, F.perm, x, xx);
+    for (int c = 0; c < 4; c++) fine_phase<T>(h, ff, xx, W[0].d, forward ? c : 3 - c, forward != 0, false);
+    k_scatter_back<T, double><<<nblk(n), kBlock, 0, s>>>(n, F.perm, xx, x);
+  } else {
+    const QuadLevel &Q = h->lev[level];
+    T *ff = W[level].r, *xx = W[level].p0;
+    k_lex_to_q<double, T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, f, ff, 0);
+    k_lex_to_q<double, T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, x, xx, 0);
+    for (int c = 0; c < 4; c++) gs_phase_coarse<T>(h, level, ff, xx, forward ? c : 3 - c);
+    k_lex_to_q<T, double><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, xx, x, 1);
+  }
+  QA_LAUNCH_CHECK();
+  QA_HIP(hipStreamSynchronize(s));
+  return AMG_OK;
+}
+
+amg_status level_smooth_internal(amg_hierarchy *h, int level, const double *f, double *x, int forward, int prec) {
+  return prec == 1 ? level_smooth_t<float>(h, level, f, x, forward) : level_smooth_t<double>(h, level, f, x, forward);
+}
+
+template <class T>
+static amg_status level_spmv_t(amg_hierarchy *h, int level, const double *x, double *y) {
+  hipStream_t s = h->stream;
+  std::vector<LevelWork<T>> &W = P<T>::W(h);
+  if (level == 0) {
+    const FineLevel &F = h->fine;
+    const int64_t n = F.n;
+    T *xx = W[0].f, *yy = W[0].u;
+    k_gather<double, T><<<nblk(n), kBlock, 0, s>>>(n, F.perm, x, xx);
+    k_fine_apply<T><<<static_cast<unsigned>((F.nslices + 3) / 4), kBlock, 0, s>>>(
+        sview<T>(F, P<T>::sval(F)), F.nslices, xx, yy);
+    k_scatter_back<T, double><<<nblk(n), kBlock, 0, s>>>(n, F.perm, yy, y);
+    QA_LAUNCH_CHECK();
+    QA_HIP(hipStreamSynchronize(s));
+    return AMG_OK;
+  }
+  const QuadLevel &Q = h->lev[level];
+  T *xx = W[level].g, *yy = W[level].e;
+  k_lex_to_q<double, T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, x, xx, 0);
+  // reuse the dot kernel's SpMV (the inner products are discarded into the scratch slot of level 0)
+  k_cspmv_dot<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), xx, yy, xx, red(h, h->nlev, EPI_STORE, 15));
+  k_lex_to_q<T, double><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, yy, y, 1);
+  QA_LAUNCH_CHECK();
+  QA_HIP(hipStreamSynchronize(s));
+  return AMG_OK;
+}
+
+amg_status level_spmv_internal(amg_hierarchy *h, int level, const double *x, double *y, int prec) {
+  return prec == 1 ? level_spmv_t<float>(h, level, x, y) : level_spmv_t<double>(h, level, x, y);
+}
+
+}  // namespace qa
+
+using namespace qa;
+
+extern "C" amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_info *info) {
+  if (!h || !b || !x || !(tol > 0.0) || !std::isfinite(tol)) return AMG_ERR_INVALID;
+  QA_HIP(hipSetDevice(h->device));
+  return solve_impl(h, b, x, tol, info);
+}
+
+extern "C" amg_status amg_apply_precond(amg_hierarchy *h, const double *r, double *z, int32_t precision) {
+  if (!h || !r || !z || (precision != 0 && precision != 1)) return AMG_ERR_INVALID;
+  QA_HIP(hipSetDevice(h->device));
+  const int64_t n = h->n;
+  hipStream_t s = h->stream;
+  k_gather<double, double><<<nblk(n), kBlock, 0, s>>>(n, h->fine.perm, r, h->tp);
+  QA_TRY(precond_apply(h, precision, h->tp, h->zp));
+  k_scatter_back<double, double><<<nblk(n), kBlock, 0, s>>>(n, h->fine.perm, h->zp, z);
+  QA_LAUNCH_CHECK();
+  QA_HIP(hipStreamSynchronize(s));
+  return AMG_OK;
+}
+
+extern "C" amg_status amg_level_smooth(amg_hierarchy *h, int32_t level, const double *f, double *x, int32_t forward,
+                                       int32_t precision) {
+  if (!h || !f || !x || level < 0 || level >= h->nlev - 1 || h->nlev == 1 || (precision != 0 && precision != 1))
+    return AMG_ERR_INVALID;
+  QA_HIP(hipSetDevice(h->device));
+  return level_smooth_internal(h, level, f, x, forward, precision);
+}
+
+extern "C" amg_status amg_level_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y, int32_t precision) {
+  if (!h || !x || !y || level < 0 || level >= h->nlev || (precision != 0 && precision != 1)) return AMG_ERR_INVALID;
+  if (level == 0 && h->nlev == 1 && precision == 1) return AMG_ERR_INVALID;
+  QA_HIP(hipSetDevice(h->device));
+  return level_spmv_internal(h, level, x, y, precision);
+}
+
+extern "C" amg_status amg_solve_batch(amg_hierarchy *const *hs, const double *const *b, double *const *x,
+                                      const double *tol, int32_t count, amg_info *info) {
+  if (count < 0 || (count > 0 && (!hs || !b || !x || !tol))) return AMG_ERR_INVALID;
+  amg_status first = AMG_OK;
+  for (int32_t i = 0; i < count; i++) {
+    const amg_status st = amg_solve(hs[i], b[i], x[i], tol[i], info ? &info[i] : nullptr);
+    if (st != AMG_OK && first == AMG_OK) first = st;
+  }
+  return first;
+}
+
+extern "C" amg_status amg_kernel_timing_enable(amg_hierarchy *h, const char *name) {
+  if (!h) return AMG_ERR_INVALID;
+  int kind = -1;
+  if (name) {
+    if (!std::strcmp(name, "spmv64")) kind = KK_SPMV64;
+    else if (!std::strcmp(name, "gs_fine32")) kind = KK_GS_FINE32;
+    else if (!std::strcmp(name, "gs_fine64")) kind = KK_GS_FINE64;
+    else if (!std::strcmp(name, "resid_fine32")) kind = KK_RESID_FINE32;
+    else if (!std::strcmp(name, "resid_fine64")) kind = KK_RESID_FINE64;
+    else return AMG_ERR_INVALID;
+  }
+  QA_HIP(hipSetDevice(h->device));
+  QA_HIP(hipStreamSynchronize(h->stream));
+  Timing &t = h->timing;
+  if (kind >= 0 && t.ev.empty()) {
+    t.ev.resize(2 * 4096);
+    for (auto &e : t.ev) QA_HIP(hipEventCreate(&e));
+  }
+  t.kind = kind;
+  t.used = 0;
+  t.launches = 0;
+  t.total_ms = 0.0;
+  t.bytes_per_launch = kind >= 0 ? kernel_bytes(h, kind) : 0.0;
+  return AMG_OK;
+}
+
+extern "C" amg_status amg_kernel_timing_read(amg_hierarchy *h, int64_t *launches, double *total_ms,
+                                             double *bytes_per_launch) {
+  if (!h) return AMG_ERR_INVALID;
+  QA_HIP(hipSetDevice(h->device));
+  QA_HIP(hipStreamSynchronize(h->stream));
+  Timing &t = h->timing;
+  for (size_t i = 0; i + 1 < t.used; i += 2) {
+    float ms = 0.f;
+    QA_HIP(hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1]));
+    t.total_ms += ms;
+    t.launches++;
+  }
+  t.used = 0;
+  if (launches) *launches = t.launches;
+  if (total_ms) *total_ms = t.total_ms;
+  if (bytes_per_launch) *bytes_per_launch = t.bytes_per_launch;
+  return AMG_OK;
+}

@@ -102,3 +102,26 @@ def graph_laplacian_problem(coords, seed=0):
     A = (W + sp.diags(d)).tocsr()
     A.sort_indices()
     return A
+
+
+def longrange_problem(n=6000, extra=300, seed=11):
+    """Scattered points, Delaunay graph Laplacian plus `extra` random long-range couplings and a positive shift:
+    SPD, and its couplings overflow the 9-point pattern on every quadtree level. No box is given (bounding box)."""
+    import scipy.sparse as sp
+    from paper_1209_5421_amd import meshgen as mg
+    rng = np.random.default_rng(seed)
+    pts = scattered_points(n, seed)
+    A = graph_laplacian_problem(pts, seed)
+    i = rng.integers(0, n, extra)
+    j = rng.integers(0, n, extra)
+    keep = i != j
+    i, j = i[keep], j[keep]
+    w = rng.uniform(0.1, 1.0, len(i))
+    W = sp.csr_matrix((np.concatenate([-w, -w]), (np.concatenate([i, j]), np.concatenate([j, i]))), shape=(n, n))
+    D = sp.diags(np.asarray(-W.sum(1)).ravel())
+    A = (A + W + D).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    b = rng.uniform(-1, 1, n)
+    return mg.Problem(f"longrange{n}", pts, A.indptr.astype(np.int64), A.indices.astype(np.int32),
+                      A.data.astype(np.float64), b, None, dict(kind="longrange"))

@@ -1,0 +1,204 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, element by element on seeded inputs.
+
+Bars: integer outputs (aggregates, colors, patterns, overflow columns) bit-exact; hierarchy values bit-exact (both
+sides sum the same terms in the same order with plain IEEE additions); FP32 hierarchy = round-to-nearest of the FP64
+one; smoother / SpMV / preconditioner within a few ulps of accumulated rounding; solves agree to 1e-6 relative error
+at 1e-8 relative residual with iteration counts equal within one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1209_5421_amd import meshgen as mg
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _amg():
+    from paper_1209_5421_amd import amg
+    return amg
+
+
+PROBLEMS = {
+    "uniform65": lambda: mg.uniform_problem(64),
+    "jittered130": lambda: mg.jittered_problem(130),                 # 16,384 unknowns, L = 6
+    "jittered177_kappa": lambda: mg.jittered_problem(177, kappa_tiles=16),  # level-L overflow, same-color pairs
+    "graded20k": lambda: mg.graded_problem(20000),                    # level-L overflow, big cells
+    "longrange6k": lambda: H.longrange_problem(6000),                 # overflow on every level, no box given
+    "two_level": lambda: mg.jittered_problem(16),                     # 196 unknowns: fine + coarsest
+}
+
+_cache = {}
+
+
+def problem(name):
+    if name not in _cache:
+        _cache[name] = PROBLEMS[name]()
+    return _cache[name]
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def gpu_hier(prob, **kw):
+    print(f"[gpu] setup {prob.name} n={prob.n} nnz={prob.nnz} {kw}", flush=True)
+    return _amg().Hierarchy.from_problem(prob, device=dev(), **kw)
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev())
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_hierarchy_bit_exact(name):
+    prob = problem(name)
+    g = gpu_hier(prob)
+    o = oracle.setup_problem(prob)
+    assert g.num_levels == o.num_levels
+    e0g, e0o = g.export_level(0), o.export_level(0)
+    np.testing.assert_array_equal(e0g["agg"], e0o["agg"])
+    np.testing.assert_array_equal(e0g["color"], e0o["color"])
+    for level in range(1, g.num_levels):
+        eg, eo = g.export_level(level, f32=True), o.export_level(level)
+        assert eg["n"] == eo["n"] and eg["k"] == eo["k"] and eg["ovf_nnz"] == eo["ovf_nnz"]
+        for key in ("agg", "color", "aj", "ovf_ptr", "ovf_col"):
+            np.testing.assert_array_equal(eg[key], eo[key], err_msg=f"level {level} {key}")
+        np.testing.assert_array_equal(eg["ax"], eo["ax"], err_msg=f"level {level} ax")
+        np.testing.assert_array_equal(eg["ovf_val"], eo["ovf_val"], err_msg=f"level {level} ovf_val")
+        np.testing.assert_array_equal(eg["ax32"], eo["ax"].astype(np.float32), err_msg=f"level {level} fp32")
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["uniform65", "jittered177_kappa", "graded20k", "longrange6k"])
+def test_level_spmv_and_smoother(name):
+    prob = problem(name)
+    g = gpu_hier(prob)
+    o = oracle.setup_problem(prob)
+    rng = np.random.default_rng(7)
+    for level in range(g.num_levels):
+        n = g.level_info(level)["n"]
+        x = rng.standard_normal(n)
+        f = rng.standard_normal(n)
+        y_o = o.spmv(level, x)
+        y_g = g.spmv(level, T(x)).cpu().numpy()
+        scale = np.abs(y_o).max()
+        np.testing.assert_allclose(y_g, y_o, rtol=0, atol=1e-13 * scale)
+        y32 = g.spmv(level, T(x), precision=1).cpu().numpy()
+        np.testing.assert_allclose(y32, y_o, rtol=0, atol=2e-5 * scale)
+        if level == g.num_levels - 1:
+            continue
+        for fwd in (True, False):
+            s_o = o.smooth(level, f, x, fwd)
+            s_g = g.smooth(level, T(f), T(x), fwd).cpu().numpy()
+            np.testing.assert_allclose(s_g, s_o, rtol=0, atol=1e-11 * np.abs(s_o).max(), err_msg=f"{level} {fwd}")
+    g.close()
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_preconditioner_parity(name):
+    prob = problem(name)
+    g = gpu_hier(prob)
+    o = oracle.setup_problem(prob)
+    r = np.random.default_rng(9).standard_normal(prob.n)
+    z_o = o.apply_precond(r)
+    z_g = g.apply_precond(T(r)).cpu().numpy()
+    assert np.linalg.norm(z_g - z_o) <= 1e-10 * np.linalg.norm(z_o)
+    z32 = g.apply_precond(T(r), precision=1).cpu().numpy()
+    assert np.linalg.norm(z32 - z_o) <= 1e-3 * np.linalg.norm(z_o)
+    g.close()
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_solve_parity_fp64(name):
+    prob = problem(name)
+    g = gpu_hier(prob)
+    o = oracle.setup_problem(prob)
+    x_o, io = o.solve(prob.b, tol=1e-8)
+    x_g, ig = g.solve(T(prob.b), tol=1e-8)
+    x_g = x_g.cpu().numpy()
+    A = H.csr_of(prob)
+    assert io["status"] == 0 and ig["status"] == 0
+    assert ig["relres"] <= 1e-8
+    assert np.linalg.norm(A @ x_g - prob.b) <= 1e-8 * np.linalg.norm(prob.b) * (1 + 1e-6)
+    assert abs(ig["iters"] - io["iters"]) <= 1, (ig, io)
+    assert np.linalg.norm(x_g - x_o) <= 1e-6 * np.linalg.norm(x_o)
+    g.close()
+
+
+@pytest.mark.parametrize("name", ["uniform65", "jittered130", "jittered177_kappa", "graded20k"])
+def test_solve_mixed_precision(name):
+    prob = problem(name)
+    g = gpu_hier(prob, precision=1)
+    o = oracle.setup_problem(prob)
+    x_ref, _ = o.solve(prob.b, tol=1e-12)
+    x_g, ig = g.solve(T(prob.b), tol=1e-8)
+    x_g = x_g.cpu().numpy()
+    A = H.csr_of(prob)
+    assert ig["status"] == 0 and ig["relres"] <= 1e-8
+    assert np.linalg.norm(A @ x_g - prob.b) <= 1e-8 * np.linalg.norm(prob.b) * (1 + 1e-6)
+    err = np.linalg.norm(x_g - x_ref) / np.linalg.norm(x_ref)
+    # ||x - x*|| / ||x*|| <= cond(A) * relres; cond(A) of these meshes stays below 1e6
+    print(f"[gpu] mixed {name}: iters={ig['iters']} relres={ig['relres']:.2e} err_vs_fp64_oracle={err:.2e}")
+    assert err <= 1e6 * 1e-8
+    g.close()
+
+
+def test_single_level_direct():
+    prob = mg.jittered_problem(9)  # 49 unknowns <= 64
+    g = gpu_hier(prob)
+    assert g.num_levels == 1
+    x, info = g.solve(T(prob.b), tol=1e-12)
+    xs = np.linalg.solve(H.csr_of(prob).toarray(), prob.b)
+    np.testing.assert_allclose(x.cpu().numpy(), xs, rtol=1e-11, atol=1e-13)
+    assert info["iters"] <= 2
+    g.close()
+
+
+def test_zero_rhs_and_determinism():
+    prob = problem("jittered130")
+    g = gpu_hier(prob)
+    x, info = g.solve(torch.zeros(prob.n, dtype=torch.float64, device=dev()))
+    assert info["iters"] == 0 and not x.any()
+    x1, i1 = g.solve(T(prob.b))
+    x2, i2 = g.solve(T(prob.b))
+    assert torch.equal(x1, x2) and i1["iters"] == i2["iters"]
+    g.set_precision(1)
+    y1, _ = g.solve(T(prob.b))
+    y2, _ = g.solve(T(prob.b))
+    assert torch.equal(y1, y2)
+    g.close()
+
+
+def test_error_paths():
+    amg = _amg()
+    prob = mg.jittered_problem(20)
+    with pytest.raises(amg.AMGError) as e:
+        gpu_hier(prob, box=(0.2, 1.0, 0.0, 1.0))
+    assert e.value.code == amg.INVALID
+    bad = mg.jittered_problem(20)
+    bad.coords = bad.coords.copy()
+    bad.coords[3, 0] = np.nan
+    with pytest.raises(amg.AMGError) as e:
+        gpu_hier(bad)
+    assert e.value.code == amg.INVALID
+    neg = mg.jittered_problem(20)
+    rows = np.repeat(np.arange(neg.n), np.diff(neg.row_ptr))
+    neg.val = neg.val.copy()
+    neg.val[(rows == 5) & (neg.col == 5)] = -2.0
+    with pytest.raises(amg.AMGError) as e:
+        gpu_hier(neg)
+    assert e.value.code == amg.NOT_SPD
+    badcol = mg.jittered_problem(20)
+    badcol.col = badcol.col.copy()
+    badcol.col[10] = badcol.n + 5
+    with pytest.raises(amg.AMGError) as e:
+        gpu_hier(badcol)
+    assert e.value.code == amg.INVALID
+    g = gpu_hier(prob, max_iters=1)
+    x, info = g.solve(T(prob.b), check=False)
+    assert info["status"] == amg.NOCONV and info["iters"] == 1
+    g.close()

@@ -179,6 +179,7 @@ def _gamma(m):
     lambda: mg.jittered_problem(48),
     lambda: mg.jittered_problem(40, kappa_tiles=16),
     lambda: mg.graded_problem(6000),
+    lambda: H.longrange_problem(3000, 150),
 ])
 def test_galerkin_matches_scipy_triple_product(orc, maker):
     prob = maker()
@@ -207,10 +208,11 @@ def test_galerkin_exact_on_uniform_grid(orc):
                 np.testing.assert_array_equal(ex["ax"][i], [c, -c / 4, 0, -c / 4, 0, -c / 4, 0, -c / 4, 0])
 
 
-def test_overflow_structure_brute_force(orc):
+@pytest.mark.parametrize("maker", [lambda: mg.graded_problem(6000), lambda: H.longrange_problem(3000, 150)])
+def test_overflow_structure_brute_force(orc, maker):
     """Overflow entries are exactly the aggregate pairs more than one cell apart that some stored fine entry
     couples (zero values included), found by brute force over the fine pattern."""
-    prob = mg.graded_problem(6000)
+    prob = maker()
     o = orc.setup_problem(prob)
     ex0 = o.export_level(0)
     A = H.csr_of(prob).tocoo()
@@ -235,7 +237,8 @@ def test_overflow_structure_brute_force(orc):
     assert total > 0
 
 
-@pytest.mark.parametrize("maker", [lambda: mg.jittered_problem(40), lambda: mg.graded_problem(6000)])
+@pytest.mark.parametrize("maker", [lambda: mg.jittered_problem(40), lambda: mg.graded_problem(6000),
+                                   lambda: H.longrange_problem(3000, 150)])
 def test_galerkin_invariants(orc, maker):
     prob = maker()
     o = orc.setup_problem(prob)
@@ -294,8 +297,9 @@ def test_fine_sweep_is_triangular_solve(orc, maker):
     np.testing.assert_allclose(o.smooth(0, f, x0, False), bwd, rtol=1e-9, atol=1e-10)
 
 
-def test_coarse_sweep_is_four_color_gauss_seidel(orc):
-    prob = mg.graded_problem(6000)
+@pytest.mark.parametrize("maker", [lambda: mg.graded_problem(6000), lambda: H.longrange_problem(3000, 150)])
+def test_coarse_sweep_is_four_color_gauss_seidel(orc, maker):
+    prob = maker()
     o = orc.setup_problem(prob)
     rng = np.random.default_rng(2)
     for level in range(1, o.num_levels - 1):
