@@ -1,0 +1,208 @@
+"""Benchmark: auxiliary-grid AMG on one MI355X.
+
+A step is one pass of the whole hot path over the workload: amg_setup (box, cell keys, counting sort, sliced ELL,
+Galerkin hierarchy, coarsest factor) followed by one amg_solve to a 1e-8 relative residual with the FP32
+preconditioner / FP64 outer iteration. The default workload is the quasi-uniform 2D P1 Poisson system: a 1024 x 1024
+lattice jittered by U[-0.3h, 0.3h], Delaunay-triangulated, Dirichlet boundary eliminated (1,044,484 unknowns),
+right-hand side U[-1, 1]. Inputs are resident in HBM before the timed region starts.
+
+Printed: one JSON line. value = unknowns x steps / wall time of the K timed steps (DOF/s of setup + solve). Extra
+fields give solve-only rates on a resident hierarchy for both forms (solves/s, DOF/s, p50/p99 latency), the
+roofline of the dominant kernel (HIP-event timing of its launches inside the timed steps) and the oracle timed on
+the host (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF/s + solves/s to 1e-8 rel residual (FP32-precond vs FP64); p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "c1": ("uniform 65x65 vertices P1 Poisson (3,969 DOF)", lambda mg: mg.uniform_problem(64)),
+    "c2": ("quasi-uniform jittered Delaunay 1024x1024 P1 Poisson (1,044,484 DOF)", lambda mg: mg.jittered_problem(1024)),
+    "c3": ("graded Delaunay ~4.0M points, density (r+0.01)^-1.5, P1 Poisson", lambda mg: mg.graded_problem(4_000_000)),
+    "c4": ("jittered Delaunay 1416x1416, kappa 10^U[-3,3] 16x16 checkerboard (1,999,396 DOF)",
+           lambda mg: mg.jittered_problem(1416, kappa_tiles=16)),
+}
+ROOFLINE_KERNELS = {"spmv64": "k_outer_spmv_dot", "resid_fine32": "k_fine_resid<float>",
+                    "gs_fine32": "k_fine_resid<float> (color phase)"}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1209_5421_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1209_5421_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel, workload):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, tol):
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    t0 = time.perf_counter()
+    o = oracle.setup_problem(prob)
+    t1 = time.perf_counter()
+    x, info = o.solve(prob.b, tol=tol)
+    t2 = time.perf_counter()
+    o.close()
+    total = t2 - t0
+    return {"value": prob.n / total, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full oracle setup + FP64 solve of the same {prob.n}-unknown system to {tol:g} "
+                      f"(setup {t1 - t0:.2f} s, solve {t2 - t1:.2f} s, {info['iters']} iterations); "
+                      f"single-threaded, 1 of {cores} host cores ({model})",
+            "setup_s": t1 - t0, "solve_s": t2 - t1, "iters": info["iters"]}, x
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--repeats", type=int, default=20, help="resident-hierarchy solves per form for latency")
+    ap.add_argument("--roofline-kernel", default="resid_fine32", choices=sorted(ROOFLINE_KERNELS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU: multi-GPU sharding is not implemented "
+                                   "(see the design notes); run with --gpus 1"}))
+        sys.exit(2)
+
+    from paper_1209_5421_amd import amg, meshgen
+    import torch
+
+    desc, make = WORKLOADS[args.workload]
+    t = time.time()
+    prob = make(meshgen)
+    log(f"workload {args.workload}: n={prob.n} nnz={prob.nnz} generated in {time.time() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    amg.load()
+    tt = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    coords, rp, ci, va = tt(prob.coords, torch.float64), tt(prob.row_ptr, torch.int64), tt(prob.col, torch.int32), \
+        tt(prob.val, torch.float64)
+    b = tt(prob.b, torch.float64)
+    x = torch.empty_like(b)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def step(timing_kernel=None):
+        h = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=1, stream=stream)
+        if timing_kernel:
+            h.timing_enable(timing_kernel)
+        _, info = h.solve(b, tol=args.tol, x=x)
+        tm = h.timing_read() if timing_kernel else None
+        h.close()
+        return info, tm
+
+    for w in range(args.warmup):
+        info, _ = step()
+        log(f"warmup {w}: setup {info['setup_ms']:.2f} ms solve {info['solve_ms']:.2f} ms iters {info['iters']}")
+
+    launches, kern_ms, bytes_per_launch = 0, 0.0, 0.0
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        info, tm = step(args.roofline_kernel)
+        infos.append(info)
+        launches += tm["launches"]
+        kern_ms += tm["total_ms"]
+        bytes_per_launch = tm["bytes_per_launch"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    for k, info in enumerate(infos):
+        log(f"step {k}: setup {info['setup_ms']:.2f} ms solve {info['solve_ms']:.2f} ms iters {info['iters']} "
+            f"relres {info['relres']:.2e}")
+
+    # resident-hierarchy solves: both forms
+    forms = {}
+    h = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=0, stream=stream)
+    for name, prec in (("fp64", 0), ("fp32_precond", 1)):
+        h.set_precision(prec)
+        h.solve(b, tol=args.tol, x=x)
+        lat = []
+        for _ in range(args.repeats):
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            _, info = h.solve(b, tol=args.tol, x=x)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - s0) * 1e3)
+        lat = np.array(lat)
+        forms[name] = {"iters": info["iters"], "relres": info["relres"], "p50_ms": float(np.percentile(lat, 50)),
+                       "p99_ms": float(np.percentile(lat, 99)), "solves_per_s": float(1e3 / np.median(lat)),
+                       "dof_per_s": float(prob.n * 1e3 / np.median(lat))}
+        log(f"resident {name}: {forms[name]}")
+    x_gpu = x.cpu().numpy()
+    h.close()
+
+    avg_ms = kern_ms / max(launches, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
+    roofline = {"bound": "hbm", "kernel": ROOFLINE_KERNELS[args.roofline_kernel], "achieved": achieved,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                "traffic": traffic_from_profiles(args.roofline_kernel, args.workload),
+                "launches": launches, "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    cpu = None
+    err_vs_oracle = None
+    if not args.no_cpu_baseline:
+        log("oracle (CPU baseline) ...")
+        cpu, x_orc = cpu_baseline(prob, args.tol)
+        err_vs_oracle = float(np.linalg.norm(x_gpu - x_orc) / np.linalg.norm(x_orc))
+        log(f"oracle: {cpu['sample']}; fp32-precond solution vs oracle rel err {err_vs_oracle:.2e}")
+
+    out = {
+        "metric": METRIC, "value": prob.n * 1e3 / ms_per_step, "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {desc}", "n": prob.n, "nnz": prob.nnz, "tol": args.tol,
+                   "step": "amg_setup + amg_solve (FP32 preconditioner, FP64 outer)",
+                   "setup_ms_median": float(np.median([i["setup_ms"] for i in infos])),
+                   "solve_ms_median": float(np.median([i["solve_ms"] for i in infos])),
+                   "iters": infos[-1]["iters"], "relres": infos[-1]["relres"]},
+        "solve_resident": forms,
+        "err_vs_oracle": err_vs_oracle,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

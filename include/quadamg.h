@@ -50,6 +50,8 @@ typedef struct {
     int32_t sweeps;      /* smoothing sweeps before and after the coarse correction (default 1) */
     int32_t outer_mmax;  /* directions kept by the outer flexible CG: 0 or 1 (default 1) */
     int32_t max_iters;   /* outer iteration cap (default 1000) */
+    int32_t engine;      /* 1 (default): the small coarse levels of the cycle run inside one persistent workgroup
+                            with LDS-resident operators; 0: one kernel launch per step on every level */
     const double *box;   /* host {a1, b1, a2, b2}: the auxiliary box of eq. (5); NULL = bounding box of coords
                             (eq. 6). Points outside a given box are rejected. */
     void *stream;        /* hipStream_t used for every launch; NULL = default stream */

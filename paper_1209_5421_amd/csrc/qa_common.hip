@@ -116,6 +116,7 @@ void amg_default_options(amg_options *opt) {
   opt->sweeps = 1;
   opt->outer_mmax = 1;
   opt->max_iters = 1000;
+  opt->engine = 1;
   opt->box = nullptr;
   opt->stream = nullptr;
 }

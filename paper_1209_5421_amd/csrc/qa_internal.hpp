@@ -163,13 +163,22 @@ struct amg_hierarchy {
   double *scal = nullptr;              // (nlev + 1) * kScalars device scalars
   double *partials = nullptr;          // reduction partial sums
   int64_t partials_cap = 0;
-  unsigned *counters = nullptr;        // (nlev + 1) last-block tickets
   double *host_scal = nullptr;         // pinned mirror for convergence checks
   int *dflag = nullptr;                // device error flags
   std::vector<void *> allocs;
   size_t bytes = 0;
   double setup_ms = 0.0;
   qa::Timing timing;
+  // persistent small-level engine: top level index per precision (0 = FP64, 1 = FP32), -1 = not used
+  int engine_top[2] = {-1, -1};
+  int engine_lds_top[2] = {-1, -1};  // first level index whose operators and vectors live in LDS
+  int engine_ainv_lds[2] = {0, 0};
+  void *engine_ops[2] = {nullptr, nullptr};
+  int engine_nops[2] = {0, 0};
+  int64_t engine_global_rows = 4096;  // a top level this small may run from global memory
+  size_t engine_lds[2] = {0, 0};
+  size_t lds_max = 0;
+  int use_engine = 1;
 };
 
 namespace qa {
@@ -188,6 +197,7 @@ amg_status release(amg_hierarchy *h);
 
 // solve side (qa_solve.hip)
 amg_status alloc_workspaces(amg_hierarchy *h);
+amg_status plan_engine(amg_hierarchy *h);
 amg_status precond_apply(amg_hierarchy *h, int precision, const double *r_p, double *z_p);
 amg_status level_smooth_internal(amg_hierarchy *h, int level, const double *f, double *x, int forward, int prec);
 amg_status level_spmv_internal(amg_hierarchy *h, int level, const double *x, double *y, int prec);

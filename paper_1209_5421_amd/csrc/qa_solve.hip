@@ -34,20 +34,10 @@ enum Epi { EPI_ALPHA0, EPI_BETA, EPI_ALPHA1, EPI_OUT_ALPHA, EPI_OUT_BETA, EPI_ST
 
 struct Red {
   double *partials;
-  unsigned *counter;
   double *sc;
   int epi;
   int slot;
 };
-
-__device__ inline void st_agent(double *p, double v) {
-  __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), static_cast<unsigned long long>(__double_as_longlong(v)),
-                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline double ld_agent(const double *p) {
-  return __longlong_as_double(static_cast<long long>(
-      __hip_atomic_load(reinterpret_cast<const unsigned long long *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)));
-}
 
 // sum over the workgroup (fixed order); valid in thread 0
 template <int ND>
@@ -101,33 +91,33 @@ __device__ inline void epilogue(const double *acc, const Red &R) {
   }
 }
 
-// Every thread of every workgroup must call this (no early returns in reduction kernels).
+// Every thread of every workgroup must call this (no early returns in reduction kernels). A single-workgroup
+// launch applies the epilogue directly; otherwise each workgroup stores its partial sums and a one-workgroup
+// k_finish launched right after sums them in workgroup order. The kernel boundary orders the two, so no
+// device-scope fence is needed (on this multi-XCD part such a fence writes back the L2 of every workgroup).
 template <int ND>
 __device__ inline void reduce_finish(double (&v)[ND], const Red &R) {
   block_sum<ND>(v);
-  __shared__ int s_last;
   if (threadIdx.x == 0) {
+    if (gridDim.x == 1) {
+      epilogue(v, R);
+    } else {
 #pragma unroll
-    for (int j = 0; j < ND; j++) st_agent(&R.partials[static_cast<size_t>(blockIdx.x) * ND + j], v[j]);
-    __threadfence();
-    const unsigned t = __hip_atomic_fetch_add(R.counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (t == gridDim.x - 1) ? 1 : 0;
+      for (int j = 0; j < ND; j++) R.partials[static_cast<size_t>(blockIdx.x) * ND + j] = v[j];
+    }
   }
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+}
+
+template <int ND>
+__global__ void __launch_bounds__(kBlock) k_finish(unsigned nb, Red R) {
   double acc[ND];
 #pragma unroll
   for (int j = 0; j < ND; j++) acc[j] = 0.0;
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += kBlock)
+  for (unsigned b = threadIdx.x; b < nb; b += kBlock)
 #pragma unroll
-    for (int j = 0; j < ND; j++) acc[j] += ld_agent(&R.partials[static_cast<size_t>(b) * ND + j]);
+    for (int j = 0; j < ND; j++) acc[j] += R.partials[static_cast<size_t>(b) * ND + j];
   block_sum<ND>(acc);
-  if (threadIdx.x == 0) {
-    epilogue(acc, R);
-    __threadfence();
-    __hip_atomic_store(R.counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
+  if (threadIdx.x == 0) epilogue(acc, R);
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -557,7 +547,13 @@ static SellView<T> sview(const FineLevel &F, const T *val) {
   return SellView<T>{F.slice_ptr, F.slice_row0, F.s_col, val};
 }
 static Red red(amg_hierarchy *h, int l, int epi, int slot = 0) {
-  return Red{h->partials, h->counters, h->scal + static_cast<size_t>(l) * kScalars, epi, slot};
+  return Red{h->partials, h->scal + static_cast<size_t>(l) * kScalars, epi, slot};
+}
+
+// second stage of a multi-workgroup reduction (no-op for a single-workgroup launch)
+template <int ND>
+static void finish(amg_hierarchy *h, unsigned nb, const Red &R) {
+  if (nb > 1) k_finish<ND><<<1, kBlock, 0, h->stream>>>(nb, R);
 }
 
 // kernel timing: events around launches of the selected family
@@ -575,13 +571,380 @@ struct Timed {
   }
 };
 
+
+// ---------------------------------------------------------------------------------------------------------------
+// Persistent small-level engine. Below a size threshold the cycle is latency-bound: level k - j is visited 2^(j+1)
+// times per outer iteration, each visit a chain of ~10 dependent steps on a few thousand rows. One workgroup runs
+// B~ of the engine's top level and everything below it (B^, restriction, prolongation, the inner nonlinear PCG,
+// the coarsest solve) in a single launch. The host emits the step list of that recursion once per hierarchy; the
+// workgroup interprets it with a barrier after every step. Levels below the top keep operators and vectors in
+// LDS; the top level stays in global memory when it does not fit. Inner products are workgroup reductions in
+// double with a fixed tree.
+
+constexpr int kEngThreads = 512;
+constexpr int kEngWaves = kEngThreads / 64;
+constexpr int kEngMaxLevels = 8;
+
+enum EngOpType : int32_t {
+  EO_GS_FIRST = 0, EO_GS, EO_RES_RESTRICT, EO_DENSE, EO_PROLONG, EO_SPMV_DOT0, EO_UPDATE1, EO_DOT_BETA,
+  EO_AXPY_BETA, EO_SPMV_DOT1, EO_UPDATE2
+};
+enum EngVec : int32_t { EV_G = 0, EV_E, EV_R, EV_P0, EV_Q0, EV_P1, EV_Q1, EV_D, EV_COUNT };
+
+struct EngOp {
+  int32_t type, lvl, color, f, u;  // f, u: vector slots of level lvl
+};
+
+template <class T>
+struct EngLevel {
+  int k, n;
+  int in_lds;
+  const T *ax;                 // global 9 x n
+  const int32_t *optr, *ocol;  // overflow in global (null when none)
+  const T *oval;
+  int same_color;
+  int ax_off, vec_off;         // LDS offsets (T units) of the 9 x n operator and of the vectors when in_lds
+  T *vec[EV_COUNT];            // global vectors when not in LDS
+};
+
+template <class T>
+struct EngPlan {
+  int nlev, nops, nc, ainv_in_lds;
+  int t_base;                  // byte offset of the T arrays in dynamic LDS
+  const EngOp *ops;
+  const double *ainv;
+  const T *g_in;
+  T *e_out;
+  EngLevel<T> lv[kEngMaxLevels];
+};
+
+template <int ND>
+__device__ inline void eng_reduce(double (&v)[ND], double *red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int j = 0; j < ND; j++) v[j] += __shfl_down(v[j], off, 64);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int j = 0; j < ND; j++) red[j * kEngWaves + (threadIdx.x >> 6)] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < ND; j++) {
+    double acc = 0.0;
+#pragma unroll
+    for (int w = 0; w < kEngWaves; w++) acc += red[j * kEngWaves + w];
+    v[j] = acc;  // every thread sums the same values in the same order
+  }
+}
+
+template <class T>
+__device__ inline T eng_row(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
+                            uint32_t q, int t1, int t2, const T *x) {
+  const int side = 1 << k;
+  T acc = 0;
+#pragma unroll
+  for (int s = 0; s < 9; s++) {
+    const int u1 = t1 + slot_dx(s), u2 = t2 + slot_dy(s);
+    if (u1 >= 0 && u2 >= 0 && u1 < side && u2 < side)
+      acc += ax[s * n + q] * x[q_of_m(morton(static_cast<uint32_t>(u1), static_cast<uint32_t>(u2)), k)];
+  }
+  if (optr)
+    for (int32_t e = optr[q]; e < optr[q + 1]; e++) acc += oval[e] * x[ocol[e]];
+  return acc;
+}
+
+template <class T>
+__global__ void __launch_bounds__(kEngThreads) k_engine(EngPlan<T> P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ T *vp[kEngMaxLevels][EV_COUNT];
+  __shared__ const T *axp[kEngMaxLevels];
+  __shared__ double sc[kEngMaxLevels][8];
+  __shared__ double red[2 * kEngWaves];
+  const int tid = threadIdx.x;
+  T *S = reinterpret_cast<T *>(smem + P.t_base);
+  double *ainv_lds = reinterpret_cast<double *>(smem);
+  if (tid < P.nlev) {
+    const EngLevel<T> &L = P.lv[tid];
+    if (L.in_lds) {
+      axp[tid] = S + L.ax_off;
+      for (int v = 0; v < EV_COUNT; v++) vp[tid][v] = S + L.vec_off + v * L.n;
+    } else {
+      axp[tid] = L.ax;
+      for (int v = 0; v < EV_COUNT; v++) vp[tid][v] = L.vec[v];
+    }
+  }
+  if (P.ainv_in_lds)
+    for (int i = tid; i < P.nc * P.nc; i += kEngThreads) ainv_lds[i] = P.ainv[i];
+  for (int l = 0; l < P.nlev; l++) {
+    const EngLevel<T> &L = P.lv[l];
+    if (L.in_lds && l + 1 < P.nlev)
+      for (int i = tid; i < 9 * L.n; i += kEngThreads) S[L.ax_off + i] = L.ax[i];
+  }
+  __syncthreads();
+  if (P.lv[0].in_lds)
+    for (int i = tid; i < P.lv[0].n; i += kEngThreads) vp[0][EV_G][i] = P.g_in[i];
+  __syncthreads();
+  const double *Ainv = P.ainv_in_lds ? ainv_lds : P.ainv;
+
+  for (int oi = 0; oi < P.nops; oi++) {
+    const EngOp op = P.ops[oi];
+    const int l = op.lvl;
+    const EngLevel<T> &L = P.lv[l];
+    const int k = L.k, n = L.n, n4 = n >> 2;
+    const T *ax = axp[l];
+    T *const *V = vp[l];
+    switch (op.type) {
+      case EO_GS_FIRST: {
+        const T *f = V[op.f];
+        T *u = V[op.u];
+        for (int q = tid; q < n; q += kEngThreads) u[q] = (q < n4) ? f[q] / ax[q] : T(0);
+        break;
+      }
+      case EO_GS: {
+        const T *f = V[op.f];
+        T *u = V[op.u];
+        T *d = V[EV_D];
+        const int c = op.color;
+        for (int j = tid; j < n4; j += kEngThreads) {
+          const uint32_t q = static_cast<uint32_t>(c * n4 + j);
+          const uint32_t m = (static_cast<uint32_t>(j) << 2) | static_cast<uint32_t>(c);
+          const T dl = (f[q] - eng_row(k, n, ax, L.optr, L.ocol, L.oval, q, static_cast<int>(compact_bits(m)),
+                                       static_cast<int>(compact_bits(m >> 1)), u)) / ax[q];
+          if (L.same_color) d[q] = dl;
+          else u[q] += dl;
+        }
+        if (L.same_color) {
+          __syncthreads();
+          for (int j = tid; j < n4; j += kEngThreads) u[c * n4 + j] += d[c * n4 + j];
+        }
+        break;
+      }
+      case EO_RES_RESTRICT: {
+        const T *f = V[op.f];
+        const T *u = V[op.u];
+        T *gc = vp[l + 1][EV_G];
+        const int order[4] = {0, 1, 3, 2};
+        for (int M = tid; M < n4; M += kEngThreads) {
+          T acc = 0;
+#pragma unroll
+          for (int o = 0; o < 4; o++) {
+            const uint32_t q = static_cast<uint32_t>(order[o] * n4 + M);
+            const uint32_t m = (static_cast<uint32_t>(M) << 2) | static_cast<uint32_t>(order[o]);
+            acc += f[q] - eng_row(k, n, ax, L.optr, L.ocol, L.oval, q, static_cast<int>(compact_bits(m)),
+                                  static_cast<int>(compact_bits(m >> 1)), u);
+          }
+          gc[q_of_m(static_cast<uint32_t>(M), k - 1)] = acc;
+        }
+        break;
+      }
+      case EO_DENSE: {
+        const T *g = V[EV_G];
+        T *e = V[EV_E];
+        for (int i = tid; i < P.nc; i += kEngThreads) {
+          double acc = 0.0;
+          for (int j = 0; j < P.nc; j++) acc += Ainv[i * P.nc + j] * static_cast<double>(g[j]);
+          e[i] = static_cast<T>(acc);
+        }
+        break;
+      }
+      case EO_PROLONG: {
+        T *u = V[op.u];
+        const T *ec = vp[l + 1][EV_E];
+        for (int q = tid; q < n; q += kEngThreads)
+          u[q] += ec[q_of_m(static_cast<uint32_t>(q & (n4 - 1)), k - 1)];
+        break;
+      }
+      case EO_SPMV_DOT0:
+      case EO_SPMV_DOT1: {
+        const bool first = op.type == EO_SPMV_DOT0;
+        const T *x = V[first ? EV_P0 : EV_P1];
+        T *y = V[first ? EV_Q0 : EV_Q1];
+        const T *w = V[first ? EV_G : EV_R];
+        double v[2] = {0.0, 0.0};
+        for (int q = tid; q < n; q += kEngThreads) {
+          const uint32_t m = m_of_q(static_cast<uint32_t>(q), k);
+          const T yq = eng_row(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q),
+                               static_cast<int>(compact_bits(m)), static_cast<int>(compact_bits(m >> 1)), x);
+          y[q] = yq;
+          v[0] += static_cast<double>(x[q]) * static_cast<double>(yq);
+          v[1] += static_cast<double>(w[q]) * static_cast<double>(x[q]);
+        }
+        eng_reduce<2>(v, red);
+        if (tid == 0) {
+          if (first) {
+            const bool stop = !(v[0] > 0.0);
+            sc[l][S_D0] = v[0];
+            sc[l][S_STOP] = stop ? 1.0 : 0.0;
+            sc[l][S_A0] = stop ? 0.0 : v[1] / v[0];
+          } else {
+            sc[l][S_A1 - 3] = (sc[l][S_STOP] != 0.0 || !(v[0] > 0.0)) ? 0.0 : v[1] / v[0];
+          }
+        }
+        break;
+      }
+      case EO_UPDATE1: {
+        const T a0 = static_cast<T>(sc[l][S_A0]);
+        const T *p0 = V[EV_P0], *q0 = V[EV_Q0], *g = V[EV_G];
+        T *e = V[EV_E], *r = V[EV_R];
+        for (int i = tid; i < n; i += kEngThreads) {
+          e[i] = a0 * p0[i];
+          r[i] = g[i] - a0 * q0[i];
+        }
+        break;
+      }
+      case EO_DOT_BETA: {
+        const T *p1 = V[EV_P1], *q0 = V[EV_Q0];
+        double t[1] = {0.0};
+        for (int i = tid; i < n; i += kEngThreads) t[0] += static_cast<double>(p1[i]) * static_cast<double>(q0[i]);
+        eng_reduce<1>(t, red);
+        if (tid == 0) sc[l][S_BETA] = (sc[l][S_STOP] != 0.0) ? 0.0 : -t[0] / sc[l][S_D0];
+        break;
+      }
+      case EO_AXPY_BETA: {
+        const T beta = static_cast<T>(sc[l][S_BETA]);
+        T *p1 = V[EV_P1];
+        const T *p0 = V[EV_P0];
+        for (int i = tid; i < n; i += kEngThreads) p1[i] += beta * p0[i];
+        break;
+      }
+      case EO_UPDATE2: {
+        const T a1 = static_cast<T>(sc[l][S_A1 - 3]);
+        const T *p1 = V[EV_P1];
+        T *e = V[EV_E];
+        for (int i = tid; i < n; i += kEngThreads) e[i] += a1 * p1[i];
+        break;
+      }
+      default:
+        break;
+    }
+    __syncthreads();
+  }
+  if (P.lv[0].in_lds)
+    for (int i = tid; i < P.lv[0].n; i += kEngThreads) P.e_out[i] = vp[0][EV_E][i];
+}
+
+// step list of B~ at engine level l (mirrors btilde / bhat_coarse below)
+static void emit_bhat(std::vector<EngOp> &ops, int l, int nl, int sweeps, int inner, int f, int u);
+static void emit_btilde(std::vector<EngOp> &ops, int l, int nl, int sweeps, int inner) {
+  emit_bhat(ops, l, nl, sweeps, inner, EV_G, EV_P0);
+  ops.push_back({EO_SPMV_DOT0, l, 0, 0, 0});
+  ops.push_back({EO_UPDATE1, l, 0, 0, 0});
+  if (inner < 2) return;
+  emit_bhat(ops, l, nl, sweeps, inner, EV_R, EV_P1);
+  ops.push_back({EO_DOT_BETA, l, 0, 0, 0});
+  ops.push_back({EO_AXPY_BETA, l, 0, 0, 0});
+  ops.push_back({EO_SPMV_DOT1, l, 0, 0, 0});
+  ops.push_back({EO_UPDATE2, l, 0, 0, 0});
+}
+static void emit_bhat(std::vector<EngOp> &ops, int l, int nl, int sweeps, int inner, int f, int u) {
+  for (int sw = 0; sw < sweeps; sw++)
+    for (int c = 0; c < 4; c++)
+      ops.push_back({(sw == 0 && c == 0) ? EO_GS_FIRST : EO_GS, l, c, f, u});
+  ops.push_back({EO_RES_RESTRICT, l, 0, f, u});
+  if (l + 1 == nl - 1) ops.push_back({EO_DENSE, l + 1, 0, 0, 0});
+  else emit_btilde(ops, l + 1, nl, sweeps, inner);
+  ops.push_back({EO_PROLONG, l, 0, f, u});
+  for (int sw = 0; sw < sweeps; sw++)
+    for (int c = 3; c >= 0; c--) ops.push_back({EO_GS, l, c, f, u});
+}
+
+amg_status plan_engine(amg_hierarchy *h) {
+  h->engine_top[0] = h->engine_top[1] = -1;
+  if (h->nlev < 3) return AMG_OK;  // nothing between the fine level and the coarsest
+  int lds = 0;
+  QA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+  h->lds_max = static_cast<size_t>(lds);
+  const size_t budget = h->lds_max > 8192 ? h->lds_max - 8192 : 0;  // room for the static shared arrays
+  for (int pi = 0; pi < 2; pi++) {
+    const size_t ts = pi == 0 ? sizeof(double) : sizeof(float);
+    // deepest levels first: find the largest set of LDS-resident levels (coarsest included)
+    size_t bytes = static_cast<size_t>(h->nc) * 2 * ts;
+    int lds_top = h->nlev - 1;
+    while (lds_top - 1 >= 1 && bytes + static_cast<size_t>(h->lev[lds_top - 1].n) * 17 * ts <= budget) {
+      lds_top--;
+      bytes += static_cast<size_t>(h->lev[lds_top].n) * 17 * ts;
+    }
+    int top = lds_top;
+    // one more level above may run from global memory (L2-resident) when it is small enough
+    if (top - 1 >= 1 && h->lev[top - 1].n <= h->engine_global_rows) top--;
+    if (top >= h->nlev - 1 || h->nlev - top > kEngMaxLevels) continue;
+    const bool ainv = bytes + static_cast<size_t>(h->nc * h->nc) * 8 <= budget;
+    h->engine_top[pi] = top;
+    h->engine_lds_top[pi] = lds_top;
+    h->engine_ainv_lds[pi] = ainv ? 1 : 0;
+    h->engine_lds[pi] = bytes + (ainv ? static_cast<size_t>(h->nc * h->nc) * 8 : 0);
+    std::vector<EngOp> ops;
+    emit_btilde(ops, 0, h->nlev - top, h->opt.sweeps, h->opt.inner_iters);
+    EngOp *d = static_cast<EngOp *>(dalloc(h, sizeof(EngOp) * ops.size()));
+    if (!d) return AMG_ERR_NOMEM;
+    QA_HIP(hipMemcpy(d, ops.data(), sizeof(EngOp) * ops.size(), hipMemcpyHostToDevice));
+    h->engine_ops[pi] = d;
+    h->engine_nops[pi] = static_cast<int>(ops.size());
+  }
+  if (h->engine_lds[0] > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_engine<double>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(h->engine_lds[0]));
+  if (h->engine_lds[1] > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_engine<float>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(h->engine_lds[1]));
+  return AMG_OK;
+}
+
+template <class T>
+static void launch_engine(amg_hierarchy *h, int top) {
+  const int pi = std::is_same<T, float>::value ? 1 : 0;
+  EngPlan<T> E{};
+  E.nlev = h->nlev - top;
+  E.nops = h->engine_nops[pi];
+  E.ops = static_cast<const EngOp *>(h->engine_ops[pi]);
+  E.nc = static_cast<int>(h->nc);
+  E.ainv_in_lds = h->engine_ainv_lds[pi];
+  E.ainv = h->ainv;
+  E.t_base = E.ainv_in_lds ? static_cast<int>(h->nc * h->nc * 8) : 0;
+  int off = 0;
+  std::vector<LevelWork<T>> &W = P<T>::W(h);
+  for (int i = 0; i < E.nlev; i++) {
+    const int l = top + i;
+    const QuadLevel &Q = h->lev[l];
+    EngLevel<T> &L = E.lv[i];
+    L.k = Q.k;
+    L.n = static_cast<int>(Q.n);
+    L.ax = P<T>::ax(Q);
+    L.optr = Q.ovf_nnz ? Q.optr : nullptr;
+    L.ocol = Q.ocol;
+    L.oval = P<T>::oval(Q);
+    L.same_color = Q.same_color_ovf;
+    L.in_lds = l >= h->engine_lds_top[pi] ? 1 : 0;
+    if (L.in_lds) {
+      if (i + 1 < E.nlev) {  // operator and the eight vectors
+        L.ax_off = off;
+        L.vec_off = off + 9 * L.n;
+        off += 17 * L.n;
+      } else {               // coarsest: g and e only (slot pointers beyond EV_E are never used there)
+        L.ax_off = off;
+        L.vec_off = off;
+        off += 2 * L.n;
+      }
+    } else {
+      L.vec[EV_G] = W[l].g; L.vec[EV_E] = W[l].e; L.vec[EV_R] = W[l].r; L.vec[EV_P0] = W[l].p0;
+      L.vec[EV_Q0] = W[l].q0; L.vec[EV_P1] = W[l].p1; L.vec[EV_Q1] = W[l].q1; L.vec[EV_D] = W[l].d;
+    }
+  }
+  E.g_in = W[top].g;
+  E.e_out = W[top].e;
+  k_engine<T><<<1, kEngThreads, h->engine_lds[pi], h->stream>>>(E);
+}
+
 template <class T> static void btilde(amg_hierarchy *h, int l, const T *g, T *e);
 
 template <class T>
 static void coarse_solve_or_cycle(amg_hierarchy *h, int l) {
   LevelWork<T> &w = P<T>::W(h)[l];
+  const int pi = std::is_same<T, float>::value ? 1 : 0;
   if (l == h->nlev - 1) {
     k_dense_solve<T><<<1, kBlock, 0, h->stream>>>(static_cast<int>(h->nc), h->ainv, w.g, w.e);
+  } else if (h->use_engine && l == h->engine_top[pi]) {
+    launch_engine<T>(h, l);
   } else {
     btilde<T>(h, l, w.g, w.e);
   }
@@ -678,12 +1041,15 @@ static void btilde(amg_hierarchy *h, int l, const T *g, T *e) {
   const double *sc = h->scal + static_cast<size_t>(l) * kScalars;
   bhat<T>(h, l, g, w.p0);
   k_cspmv_dot<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), w.p0, w.q0, g, red(h, l, EPI_ALPHA0));
+  finish<2>(h, nred(Q.n), red(h, l, EPI_ALPHA0));
   k_update1<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p0, w.q0, g, e, w.r);
   if (h->opt.inner_iters < 2) return;
   bhat<T>(h, l, w.r, w.p1);
   k_dot<T><<<nred(Q.n), kBlock, 0, s>>>(Q.n, w.p1, w.q0, red(h, l, EPI_BETA));
+  finish<1>(h, nred(Q.n), red(h, l, EPI_BETA));
   k_axpy_beta<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p1, w.p0);
   k_cspmv_dot<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), w.p1, w.q1, w.r, red(h, l, EPI_ALPHA1));
+  finish<2>(h, nred(Q.n), red(h, l, EPI_ALPHA1));
   k_update2<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p1, e);
 }
 
@@ -746,10 +1112,8 @@ amg_status alloc_workspaces(amg_hierarchy *h) {
   h->scal = dalloc_n<double>(h, (h->nlev + 1) * kScalars);
   h->partials_cap = std::max<int64_t>(kRedBlocksMax, (h->fine.nslices + 3) / 4 + 1) * 2;
   h->partials = dalloc_n<double>(h, h->partials_cap);
-  h->counters = dalloc_n<unsigned>(h, 4);
-  if (!h->scal || !h->partials || !h->counters) return AMG_ERR_NOMEM;
+  if (!h->scal || !h->partials) return AMG_ERR_NOMEM;
   QA_HIP(hipMemsetAsync(h->scal, 0, sizeof(double) * (h->nlev + 1) * kScalars, h->stream));
-  QA_HIP(hipMemsetAsync(h->counters, 0, sizeof(unsigned) * 4, h->stream));
   QA_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->host_scal), sizeof(double) * kScalars, hipHostMallocDefault));
   return AMG_OK;
 }
@@ -787,6 +1151,7 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
 
   k_gather<double, double><<<nblk(n), kBlock, 0, s>>>(n, F.perm, b, h->bp);
   k_dot<double><<<nred(n), kBlock, 0, s>>>(n, h->bp, h->bp, red(h, L0, EPI_STORE, O_BB));
+  finish<1>(h, nred(n), red(h, L0, EPI_STORE, O_BB));
   k_fill<double><<<nblk(n), kBlock, 0, s>>>(n, h->xp, 0.0);
   QA_LAUNCH_CHECK();
   QA_TRY(read_scalars(h, O_BB, 1));
@@ -807,13 +1172,18 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
   while (it < h->opt.max_iters) {
     QA_TRY(precond_apply(h, prec, h->rp, h->zp));
     const bool use_beta = have_prev && h->opt.outer_mmax == 1;
-    if (use_beta) k_dot<double><<<nred(n), kBlock, 0, s>>>(n, h->zp, qprev, red(h, L0, EPI_OUT_BETA));
+    if (use_beta) {
+      k_dot<double><<<nred(n), kBlock, 0, s>>>(n, h->zp, qprev, red(h, L0, EPI_OUT_BETA));
+      finish<1>(h, nred(n), red(h, L0, EPI_OUT_BETA));
+    }
     k_outer_dir<double><<<nblk(n), kBlock, 0, s>>>(n, osc, h->zp, pprev, p, use_beta ? 1 : 0);
     {
       Timed tm(h, KK_SPMV64);
       k_outer_spmv_dot<<<nsl_blocks, kBlock, 0, s>>>(A64, F.nslices, p, q, h->rp, red(h, L0, EPI_OUT_ALPHA));
     }
+    finish<2>(h, nsl_blocks, red(h, L0, EPI_OUT_ALPHA));
     k_outer_update<<<nred(n), kBlock, 0, s>>>(n, osc, p, q, h->xp, h->rp, red(h, L0, EPI_STORE, O_RR));
+    finish<1>(h, nred(n), red(h, L0, EPI_STORE, O_RR));
     QA_LAUNCH_CHECK();
     QA_TRY(read_scalars(h, 0, O_BB));
     if (h->host_scal[O_BREAK] != 0.0) {
@@ -827,6 +1197,7 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
     if (std::sqrt(h->host_scal[O_RR]) <= tol * bn) {
       k_outer_true_resid<<<nsl_blocks, kBlock, 0, s>>>(A64, F.nslices, h->bp, h->xp, h->tp,
                                                         red(h, L0, EPI_STORE, O_TT));
+      finish<1>(h, nsl_blocks, red(h, L0, EPI_STORE, O_TT));
       QA_LAUNCH_CHECK();
       QA_TRY(read_scalars(h, O_TT, 1));
       if (std::sqrt(h->host_scal[O_TT]) <= tol * bn) {
@@ -839,6 +1210,7 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
     }
   }
   k_outer_true_resid<<<nsl_blocks, kBlock, 0, s>>>(A64, F.nslices, h->bp, h->xp, h->tp, red(h, L0, EPI_STORE, O_TT));
+  finish<1>(h, nsl_blocks, red(h, L0, EPI_STORE, O_TT));
   k_scatter_back<double, double><<<nblk(n), kBlock, 0, s>>>(n, F.perm, h->xp, x);
   QA_LAUNCH_CHECK();
   QA_TRY(read_scalars(h, O_TT, 1));
@@ -902,6 +1274,7 @@ static amg_status level_spmv_t(amg_hierarchy *h, int level, const double *x, dou
   k_lex_to_q<double, T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, x, xx, 0);
   // reuse the dot kernel's SpMV (the inner products are discarded into the scratch slot of level 0)
   k_cspmv_dot<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), xx, yy, xx, red(h, h->nlev, EPI_STORE, 15));
+  finish<2>(h, nred(Q.n), red(h, h->nlev, EPI_STORE, 15));
   k_lex_to_q<T, double><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, yy, y, 1);
   QA_LAUNCH_CHECK();
   QA_HIP(hipStreamSynchronize(s));

@@ -147,6 +147,29 @@ def test_solve_mixed_precision(name):
     g.close()
 
 
+@pytest.mark.parametrize("name", ["uniform65", "jittered130", "longrange6k"])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_engine_matches_per_step_launches(name, precision):
+    """The persistent small-level workgroup and the launch-per-step path compute the same preconditioner (their
+    inner products use different reduction trees, so agreement is to rounding)."""
+    prob = problem(name)
+    ga = gpu_hier(prob, engine=1)
+    gb = gpu_hier(prob, engine=0)
+    r = T(np.random.default_rng(3).standard_normal(prob.n))
+    za = ga.apply_precond(r, precision=precision).cpu().numpy()
+    zb = gb.apply_precond(r, precision=precision).cpu().numpy()
+    tol = 1e-11 if precision == 0 else 1e-4
+    assert np.linalg.norm(za - zb) <= tol * np.linalg.norm(zb)
+    ga.set_precision(precision)
+    gb.set_precision(precision)
+    xa, ia = ga.solve(T(prob.b))
+    xb, ib = gb.solve(T(prob.b))
+    assert abs(ia["iters"] - ib["iters"]) <= 1
+    assert torch.linalg.norm(xa - xb) <= 1e-6 * torch.linalg.norm(xb)
+    ga.close()
+    gb.close()
+
+
 def test_single_level_direct():
     prob = mg.jittered_problem(9)  # 49 unknowns <= 64
     g = gpu_hier(prob)
