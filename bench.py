@@ -154,6 +154,9 @@ def main():
     # resident-hierarchy solves: both forms
     forms = {}
     h = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=0, stream=stream)
+    engine = {name: h.engine_info(prec) for name, prec in (("fp64", 0), ("fp32_precond", 1))}
+    levels = [h.level_info(l) for l in range(h.num_levels)]
+    log(f"levels {[(lv['k'], lv['n']) for lv in levels]} engine {engine}")
     for name, prec in (("fp64", 0), ("fp32_precond", 1)):
         h.set_precision(prec)
         h.solve(b, tol=args.tol, x=x)
@@ -197,6 +200,7 @@ def main():
                    "solve_ms_median": float(np.median([i["solve_ms"] for i in infos])),
                    "iters": infos[-1]["iters"], "relres": infos[-1]["relres"]},
         "solve_resident": forms,
+        "engine": engine,
         "err_vs_oracle": err_vs_oracle,
         "roofline": roofline,
         "cpu_baseline": cpu,

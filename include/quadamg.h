@@ -52,6 +52,9 @@ typedef struct {
     int32_t max_iters;   /* outer iteration cap (default 1000) */
     int32_t engine;      /* 1 (default): the small coarse levels of the cycle run inside one persistent workgroup
                             with LDS-resident operators; 0: one kernel launch per step on every level */
+    int32_t batch;       /* 1 (default): amg_solve_batch runs this system, when it has at most 65,536 unknowns, as
+                            one workgroup of a whole-solve launch shared with the batch's other small systems;
+                            0: it runs as its own amg_solve */
     const double *box;   /* host {a1, b1, a2, b2}: the auxiliary box of eq. (5); NULL = bounding box of coords
                             (eq. 6). Points outside a given box are rejected. */
     void *stream;        /* hipStream_t used for every launch; NULL = default stream */
@@ -95,10 +98,15 @@ amg_status amg_set_precision(amg_hierarchy *h, int32_t precision);
 /* Change the stream used by later calls on h (hipStream_t, NULL = default stream). */
 amg_status amg_set_stream(amg_hierarchy *h, void *stream);
 
-/* Solve `count` independent systems, each with its own hierarchy and workspace, overlapping their work on the
- * device. h, b, x, tol are host arrays of `count` entries; b[i] and x[i] are device vectors of hierarchy i's size;
- * info is a host array of `count` entries or NULL. The hierarchies must be distinct. Each result equals the
- * result of amg_solve on that system alone. Returns the first non-OK status (all systems are still attempted). */
+/* Solve `count` independent systems of one device concurrently (the serving form). h, b, x, tol are host arrays of
+ * `count` entries; b[i] and x[i] are device vectors of hierarchy i's size, ready once that hierarchy's stream has
+ * drained (the call synchronises each stream first); info is a host array of `count` entries or NULL. The
+ * hierarchies must be distinct. Small systems (options.batch, at most 65,536 unknowns) are solved together in one
+ * launch with one persistent workgroup per system: outer flexible CG, smoother, K-cycle and convergence test all
+ * on the device. Every other system is driven by its own host thread on its own stream, overlapping with the
+ * launch. A system's result does not depend on the rest of the batch (bit-identical alone and in any mix); the
+ * whole-solve workgroup and amg_solve differ only by rounding (different reduction trees). Returns the first
+ * non-OK status; every system is attempted. */
 amg_status amg_solve_batch(amg_hierarchy *const *h, const double *const *b, double *const *x, const double *tol,
                            int32_t count, amg_info *info);
 
@@ -149,6 +157,12 @@ amg_status amg_level_spmv(amg_hierarchy *h, int32_t level, const double *x, doub
  * "gs_fine64" (fine-level smoother residual pass), "resid_fine32", "resid_fine64". name NULL disables. */
 amg_status amg_kernel_timing_enable(amg_hierarchy *h, const char *name);
 amg_status amg_kernel_timing_read(amg_hierarchy *h, int64_t *launches, double *total_ms, double *bytes_per_launch);
+
+/* Configuration of the persistent small-level workgroup for a precision: the hierarchy level index of its top
+ * (-1 = not used), the first level index whose operators live in LDS, the length of its step list and its dynamic
+ * LDS bytes. */
+amg_status amg_engine_info(const amg_hierarchy *h, int32_t precision, int32_t *top_level, int32_t *lds_level,
+                           int32_t *steps, size_t *lds_bytes);
 
 /* Human-readable name of a status. */
 const char *amg_status_string(amg_status s);

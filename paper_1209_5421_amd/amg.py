@@ -19,13 +19,13 @@ STATUS = {0: "AMG_OK", 1: "AMG_ERR_INVALID", 2: "AMG_ERR_NOMEM", 3: "AMG_ERR_DEV
 EXPORTED = ["amg_default_options", "amg_setup", "amg_solve", "amg_free", "amg_set_precision", "amg_set_stream",
             "amg_solve_batch", "amg_estimate_bytes", "amg_hierarchy_bytes", "amg_num_levels", "amg_level_info",
             "amg_export_level", "amg_export_level_f32", "amg_apply_precond", "amg_level_smooth", "amg_level_spmv",
-            "amg_kernel_timing_enable", "amg_kernel_timing_read", "amg_status_string"]
+            "amg_kernel_timing_enable", "amg_kernel_timing_read", "amg_engine_info", "amg_status_string"]
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("coarse_max", C.c_int32), ("inner_iters", C.c_int32),
                 ("sweeps", C.c_int32), ("outer_mmax", C.c_int32), ("max_iters", C.c_int32),
-                ("engine", C.c_int32), ("box", C.POINTER(C.c_double)), ("stream", C.c_void_p)]
+                ("engine", C.c_int32), ("batch", C.c_int32), ("box", C.POINTER(C.c_double)), ("stream", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -74,6 +74,7 @@ def load(path: str = LIB_PATH):
     L.amg_level_spmv.argtypes = [p, i32, p, p, i32]
     L.amg_kernel_timing_enable.argtypes = [p, C.c_char_p]
     L.amg_kernel_timing_read.argtypes = [p, C.POINTER(i64), C.POINTER(d), C.POINTER(d)]
+    L.amg_engine_info.argtypes = [p, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_size_t)]
     L.amg_status_string.argtypes = [i32]
     L.amg_status_string.restype = C.c_char_p
     for name in EXPORTED:
@@ -106,10 +107,10 @@ def estimate_bytes(n: int, nnz: int, **opts) -> int:
 
 
 def _options(precision=0, coarse_max=64, inner_iters=2, sweeps=1, outer_mmax=1, max_iters=1000, box=None,
-             stream=None, engine=1):
+             stream=None, engine=1, batch=1):
     o = default_options()
     o.precision, o.coarse_max, o.inner_iters = precision, coarse_max, inner_iters
-    o.sweeps, o.outer_mmax, o.max_iters, o.engine = sweeps, outer_mmax, max_iters, engine
+    o.sweeps, o.outer_mmax, o.max_iters, o.engine, o.batch = sweeps, outer_mmax, max_iters, engine, batch
     o._box = None
     if box is not None:
         o._box = (C.c_double * 4)(*[float(v) for v in box])
@@ -132,7 +133,7 @@ class Hierarchy:
     """
 
     def __init__(self, coords, row_ptr, col, val, box=None, precision=0, coarse_max=64, inner_iters=2, sweeps=1,
-                 outer_mmax=1, max_iters=1000, stream=None, engine=1):
+                 outer_mmax=1, max_iters=1000, stream=None, engine=1, batch=1):
         import torch
         L = load()
         if not torch.cuda.is_available():
@@ -146,7 +147,7 @@ class Hierarchy:
         self.nnz = int(col.numel())
         self._stream = stream
         o = _options(precision, coarse_max, inner_iters, sweeps, outer_mmax, max_iters, box,
-                     _stream_handle(stream), engine)
+                     _stream_handle(stream), engine, batch)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             _check(L.amg_setup(self.n, _ptr(coords), _ptr(row_ptr), _ptr(col), _ptr(val), self.nnz, C.byref(o),
@@ -248,6 +249,12 @@ class Hierarchy:
             out["ax32"] = np.empty((n, 9), dtype=np.float32)
             _check(L.amg_export_level_f32(self._h, level, p(out["ax32"])), "amg_export_level_f32")
         return out
+
+    def engine_info(self, precision=0) -> dict:
+        t, l, st, b = C.c_int32(), C.c_int32(), C.c_int32(), C.c_size_t()
+        _check(load().amg_engine_info(self._h, precision, C.byref(t), C.byref(l), C.byref(st), C.byref(b)),
+               "amg_engine_info")
+        return dict(top_level=t.value, lds_level=l.value, steps=st.value, lds_bytes=b.value)
 
     # -- kernel timing ------------------------------------------------------------------------------------------
     def timing_enable(self, name):

@@ -3,16 +3,45 @@
 
 namespace qa {
 
+// Hierarchy memory comes from a library-owned stream-ordered pool per device that keeps freed blocks cached, so
+// repeated setup / free cycles (a request stream) do not pay hipMalloc / hipFree each time.
+static hipMemPool_t pool_for(int device) {
+  static hipMemPool_t pools[64] = {};
+  static bool ready[64] = {};
+  if (device < 0 || device >= 64) return nullptr;
+  if (!ready[device]) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    hipMemPool_t p = nullptr;
+    if (hipMemPoolCreate(&p, &props) == hipSuccess) {
+      uint64_t keep = ~0ull;
+      (void)hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+      pools[device] = p;
+    }
+    ready[device] = true;
+  }
+  return pools[device];
+}
+
 void *dalloc(amg_hierarchy *h, size_t bytes) {
   void *p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  hipMemPool_t pool = pool_for(h->device);
+  if (pool) {
+    if (hipMallocFromPoolAsync(&p, bytes, pool, h->stream) != hipSuccess) return nullptr;
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    return nullptr;
+  }
   h->allocs.push_back(p);
   h->bytes += bytes;
   return p;
 }
 
 amg_status release(amg_hierarchy *h) {
-  for (void *p : h->allocs) (void)hipFree(p);
+  const bool pooled = pool_for(h->device) != nullptr;
+  for (void *p : h->allocs) (void)(pooled ? hipFreeAsync(p, h->stream) : hipFree(p));
+  if (pooled) (void)hipStreamSynchronize(h->stream);
   h->allocs.clear();
   if (h->host_scal) (void)hipHostFree(h->host_scal);
   h->host_scal = nullptr;
@@ -117,6 +146,7 @@ void amg_default_options(amg_options *opt) {
   opt->outer_mmax = 1;
   opt->max_iters = 1000;
   opt->engine = 1;
+  opt->batch = 1;
   opt->box = nullptr;
   opt->stream = nullptr;
 }

@@ -77,6 +77,41 @@ __host__ __device__ inline int slot_of(int dx, int dy) {
   }
 }
 
+// Neighbourhood of a level-k cell in color-major numbering. Cell q = c n4 + j (n4 = 4^(k-1)) is child
+// c = (cx, cy) of the level-(k-1) super-cell with Morton index j; each of its 8 neighbours is a child of j or of one of
+// the super-cells around j. Those come from dilated-integer increments of j's x bits (even) and y bits (odd), so a
+// neighbour costs a few integer operations instead of a full Morton re-encoding.
+struct Nbhd {
+  uint32_t jx, jy, xl, xr, yd, yu;
+  bool okl, okr, okd, oku;
+};
+__host__ __device__ inline Nbhd nbhd(uint32_t j, uint32_t n4) {
+  const uint32_t xm = 0x55555555u & (n4 - 1u), ym = 0xAAAAAAAAu & (n4 - 1u);
+  Nbhd N;
+  N.jx = j & xm;
+  N.jy = j & ym;
+  N.okl = N.jx != 0u;
+  N.okr = N.jx != xm;
+  N.okd = N.jy != 0u;
+  N.oku = N.jy != ym;
+  N.xl = (N.jx - 1u) & xm;
+  N.xr = ((N.jx | ~xm) + 1u) & xm;
+  N.yd = (N.jy - 1u) & ym;
+  N.yu = ((N.jy | ~ym) + 1u) & ym;
+  return N;
+}
+// color-major index of the neighbour of child (cx, cy) at offset (dx, dy), or -1 outside the grid
+__host__ __device__ inline int nbr_q(const Nbhd &N, int cx, int cy, int dx, int dy, uint32_t n4) {
+  const int ux = cx + dx, uy = cy + dy;
+  uint32_t sx = N.jx, sy = N.jy;
+  bool ok = true;
+  if (ux < 0) { sx = N.xl; ok = N.okl; }
+  else if (ux > 1) { sx = N.xr; ok = N.okr; }
+  if (uy < 0) { sy = N.yd; ok = ok && N.okd; }
+  else if (uy > 1) { sy = N.yu; ok = ok && N.oku; }
+  return ok ? static_cast<int>(static_cast<uint32_t>((ux & 1) + 2 * (uy & 1)) * n4 + (sx | sy)) : -1;
+}
+
 // ---------------------------------------------------------------------------------------------------------------
 // hierarchy
 
@@ -179,6 +214,13 @@ struct amg_hierarchy {
   size_t engine_lds[2] = {0, 0};
   size_t lds_max = 0;
   int use_engine = 1;
+  int use_batch = 1;
+  // whole-solve workgroup (batched serving of small systems), per precision
+  void *wg_ops[2] = {nullptr, nullptr};
+  int wg_nops[2] = {0, 0};
+  int wg_lds_top[2] = {-1, -1};
+  int wg_ainv_lds[2] = {0, 0};
+  size_t wg_lds[2] = {0, 0};
 };
 
 namespace qa {
@@ -198,6 +240,7 @@ amg_status release(amg_hierarchy *h);
 // solve side (qa_solve.hip)
 amg_status alloc_workspaces(amg_hierarchy *h);
 amg_status plan_engine(amg_hierarchy *h);
+amg_status plan_wg(amg_hierarchy *h);
 amg_status precond_apply(amg_hierarchy *h, int precision, const double *r_p, double *z_p);
 amg_status level_smooth_internal(amg_hierarchy *h, int level, const double *f, double *x, int forward, int prec);
 amg_status level_spmv_internal(amg_hierarchy *h, int level, const double *x, double *y, int prec);

@@ -848,6 +848,7 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
   if (f & F_NOT_SPD) return AMG_ERR_NOT_SPD;
   QA_TRY(alloc_workspaces(h));
   QA_TRY(plan_engine(h));
+  QA_TRY(plan_wg(h));
   QA_HIP(hipStreamSynchronize(s));
   return AMG_OK;
 }
@@ -915,6 +916,7 @@ extern "C" amg_status amg_setup(int64_t n, const double *coords, const int64_t *
   h->stream = static_cast<hipStream_t>(o.stream);
   h->precision = o.precision;
   h->use_engine = o.engine ? 1 : 0;
+  h->use_batch = o.batch ? 1 : 0;
   h->n = n;
   h->opt.box = o.box;
   amg_status st = setup_impl(h, coords, row_ptr, col_idx, vals, nnz);

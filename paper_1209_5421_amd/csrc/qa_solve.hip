@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <type_traits>
 
 #include "qa_internal.hpp"
@@ -133,9 +134,8 @@ struct SellView {
 
 // d[p] = f[p] - (A x)[p] for the rows of slices [s_begin, s_end); one wavefront per slice
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_fine_resid(SellView<T> S, const T *__restrict__ f,
-                                                        const T *__restrict__ x, T *__restrict__ d, int64_t s_begin,
-                                                        int64_t s_end) {
+__device__ inline void fine_resid_body(const SellView<T> &S, const T *__restrict__ f, const T *__restrict__ x,
+                                       T *__restrict__ d, int64_t s_begin, int64_t s_end) {
   const int64_t s = s_begin + static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
   if (s >= s_end) return;
   const int lane = threadIdx.x & 63;
@@ -150,6 +150,22 @@ __global__ void __launch_bounds__(kBlock) k_fine_resid(SellView<T> S, const T *_
     acc += S.val[e] * x[S.col[e]];
   }
   d[row] = f[row] - acc;
+}
+
+// residual of one color's rows (a smoother phase)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fine_resid(SellView<T> S, const T *__restrict__ f,
+                                                        const T *__restrict__ x, T *__restrict__ d, int64_t s_begin,
+                                                        int64_t s_end) {
+  fine_resid_body(S, f, x, d, s_begin, s_end);
+}
+
+// residual of all rows (input of the restriction); a kernel of its own so its launches are timed separately
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fine_resid_full(SellView<T> S, const T *__restrict__ f,
+                                                             const T *__restrict__ x, T *__restrict__ d,
+                                                             int64_t nslices) {
+  fine_resid_body(S, f, x, d, 0, nslices);
 }
 
 // y = A x over all slices (level hook)
@@ -237,16 +253,20 @@ struct QView {
   const T *oval;
 };
 
-// (A x)_q for row q with Morton coordinates (t1, t2)
+// (A x)_q for row q of a quadtree level (slots in order 0..8, then overflow entries). A slot whose neighbour lies
+// outside the grid holds the value 0, so its product is taken with x[q] instead of being branched around: all nine
+// loads are then independent and issue back to back.
 template <class T>
-__device__ inline T row_apply(const QView<T> &Q, uint32_t q, int t1, int t2, const T *__restrict__ x) {
-  const int side = 1 << Q.k;
+__device__ inline T row_apply(const QView<T> &Q, uint32_t q, const T *__restrict__ x) {
+  const uint32_t n4 = static_cast<uint32_t>(Q.n >> 2);
+  const uint32_t j = q & (n4 - 1u);
+  const int c = static_cast<int>(q >> (2 * Q.k - 2));
+  const Nbhd N = nbhd(j, n4);
   T acc = 0;
 #pragma unroll
   for (int s = 0; s < 9; s++) {
-    const int u1 = t1 + slot_dx(s), u2 = t2 + slot_dy(s);
-    if (u1 >= 0 && u2 >= 0 && u1 < side && u2 < side)
-      acc += Q.ax[s * Q.n + q] * x[q_of_m(morton(static_cast<uint32_t>(u1), static_cast<uint32_t>(u2)), Q.k)];
+    const int qn = nbr_q(N, c & 1, c >> 1, slot_dx(s), slot_dy(s), n4);
+    acc += Q.ax[s * Q.n + q] * x[qn >= 0 ? static_cast<uint32_t>(qn) : q];
   }
   if (Q.optr)
     for (int32_t e = Q.optr[q]; e < Q.optr[q + 1]; e++) acc += Q.oval[e] * x[Q.ocol[e]];
@@ -270,9 +290,7 @@ __global__ void __launch_bounds__(kBlock) k_cgs(QView<T> Q, const T *__restrict_
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n4) return;
   const uint32_t q = static_cast<uint32_t>(c * n4 + j);
-  const uint32_t m = (static_cast<uint32_t>(j) << 2) | static_cast<uint32_t>(c);
-  const int t1 = static_cast<int>(compact_bits(m)), t2 = static_cast<int>(compact_bits(m >> 1));
-  const T dl = (f[q] - row_apply(Q, q, t1, t2, x)) / Q.ax[q];
+  const T dl = (f[q] - row_apply(Q, q, x)) / Q.ax[q];
   if (delta) delta[q] = dl;
   else x[q] += dl;
 }
@@ -298,9 +316,7 @@ __global__ void __launch_bounds__(kBlock) k_cres_restrict(QView<T> Q, const T *_
   for (int oi = 0; oi < 4; oi++) {
     const int c = order[oi];
     const uint32_t q = static_cast<uint32_t>(c * n4 + M);
-    const uint32_t m = (static_cast<uint32_t>(M) << 2) | static_cast<uint32_t>(c);
-    const int t1 = static_cast<int>(compact_bits(m)), t2 = static_cast<int>(compact_bits(m >> 1));
-    acc += f[q] - row_apply(Q, q, t1, t2, u);
+    acc += f[q] - row_apply(Q, q, u);
   }
   g[q_of_m(static_cast<uint32_t>(M), Q.k - 1)] = acc;
 }
@@ -321,9 +337,7 @@ __global__ void __launch_bounds__(kBlock) k_cspmv_dot(QView<T> Q, const T *__res
   double v[2] = {0.0, 0.0};
   for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < Q.n;
        q += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const uint32_t m = m_of_q(static_cast<uint32_t>(q), Q.k);
-    const int t1 = static_cast<int>(compact_bits(m)), t2 = static_cast<int>(compact_bits(m >> 1));
-    const T yq = row_apply(Q, static_cast<uint32_t>(q), t1, t2, x);
+    const T yq = row_apply(Q, static_cast<uint32_t>(q), x);
     y[q] = yq;
     const double xq = static_cast<double>(x[q]);
     v[0] += xq * static_cast<double>(yq);
@@ -581,9 +595,10 @@ struct Timed {
 // LDS; the top level stays in global memory when it does not fit. Inner products are workgroup reductions in
 // double with a fixed tree.
 
-constexpr int kEngThreads = 512;
+constexpr int kEngThreads = 1024;
 constexpr int kEngWaves = kEngThreads / 64;
 constexpr int kEngMaxLevels = 8;
+constexpr int kEngMaxOps = 512;  // step list staged in LDS (20 bytes each)
 
 enum EngOpType : int32_t {
   EO_GS_FIRST = 0, EO_GS, EO_RES_RESTRICT, EO_DENSE, EO_PROLONG, EO_SPMV_DOT0, EO_UPDATE1, EO_DOT_BETA,
@@ -639,40 +654,202 @@ __device__ inline void eng_reduce(double (&v)[ND], double *red) {
 
 template <class T>
 __device__ inline T eng_row(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
-                            uint32_t q, int t1, int t2, const T *x) {
-  const int side = 1 << k;
+                            uint32_t q, const T *x) {
+  const uint32_t n4 = static_cast<uint32_t>(n >> 2);
+  const uint32_t j = q & (n4 - 1u);
+  const int c = static_cast<int>(q >> (2 * k - 2));
+  const Nbhd N = nbhd(j, n4);
   T acc = 0;
 #pragma unroll
   for (int s = 0; s < 9; s++) {
-    const int u1 = t1 + slot_dx(s), u2 = t2 + slot_dy(s);
-    if (u1 >= 0 && u2 >= 0 && u1 < side && u2 < side)
-      acc += ax[s * n + q] * x[q_of_m(morton(static_cast<uint32_t>(u1), static_cast<uint32_t>(u2)), k)];
+    const int qn = nbr_q(N, c & 1, c >> 1, slot_dx(s), slot_dy(s), n4);
+    acc += ax[s * n + q] * x[qn >= 0 ? static_cast<uint32_t>(qn) : q];  // absent slots hold 0
   }
   if (optr)
     for (int32_t e = optr[q]; e < optr[q + 1]; e++) acc += oval[e] * x[ocol[e]];
   return acc;
 }
 
-template <class T>
-__global__ void __launch_bounds__(kEngThreads) k_engine(EngPlan<T> P) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ T *vp[kEngMaxLevels][EV_COUNT];
-  __shared__ const T *axp[kEngMaxLevels];
-  __shared__ double sc[kEngMaxLevels][8];
-  __shared__ double red[2 * kEngWaves];
-  const int tid = threadIdx.x;
-  T *S = reinterpret_cast<T *>(smem + P.t_base);
-  double *ainv_lds = reinterpret_cast<double *>(smem);
-  if (tid < P.nlev) {
-    const EngLevel<T> &L = P.lv[tid];
-    if (L.in_lds) {
-      axp[tid] = S + L.ax_off;
-      for (int v = 0; v < EV_COUNT; v++) vp[tid][v] = S + L.vec_off + v * L.n;
-    } else {
-      axp[tid] = L.ax;
-      for (int v = 0; v < EV_COUNT; v++) vp[tid][v] = L.vec[v];
+// Vector and operator access of one engine level: LDS levels are addressed as offsets into the dynamic shared
+// array (so the compiler emits LDS instructions), the global top level through its device pointers.
+template <class T, bool LDS>
+struct EngMem {
+  T *S;
+  const EngLevel<T> &L;
+  __device__ T *vec(int v) const { return LDS ? S + L.vec_off + v * L.n : L.vec[v]; }
+  __device__ const T *ax() const { return LDS ? S + L.ax_off : L.ax; }
+};
+
+struct EngCtx {
+  double *sc;       // this level's scalars
+  double *red;
+};
+
+// One step of the interpreter, run by the whole workgroup. LDS / LDS_CHILD: where this level's and its child's
+// vectors live.
+template <class T, bool LDS, bool LDS_CHILD>
+__device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const EngPlan<T> &P, T *S,
+                                const double *Ainv, EngCtx C) {
+  constexpr int kStride = kEngThreads;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int l = op.lvl;
+  const EngLevel<T> &L = LV[l];
+  const EngMem<T, LDS> M{S, L};
+  const int k = L.k, n = L.n, n4 = n >> 2;
+  const T *ax = M.ax();
+  switch (op.type) {
+    case EO_GS_FIRST: {
+      const T *f = M.vec(op.f);
+      T *u = M.vec(op.u);
+      for (int q = tid; q < n; q += kStride) u[q] = (q < n4) ? f[q] / ax[q] : T(0);
+      break;
     }
+    case EO_GS: {
+      const T *f = M.vec(op.f);
+      T *u = M.vec(op.u);
+      T *d = M.vec(EV_D);
+      const int c = op.color;
+      for (int j = tid; j < n4; j += kStride) {
+        const uint32_t q = static_cast<uint32_t>(c * n4 + j);
+        const T dl = (f[q] - eng_row(k, n, ax, L.optr, L.ocol, L.oval, q, u)) / ax[q];
+        if (L.same_color) d[q] = dl;
+        else u[q] += dl;
+      }
+      if (L.same_color) {
+        __syncthreads();
+        for (int j = tid; j < n4; j += kStride) u[c * n4 + j] += d[c * n4 + j];
+      }
+      break;
+    }
+    case EO_RES_RESTRICT: {
+      const T *f = M.vec(op.f);
+      const T *u = M.vec(op.u);
+      const EngMem<T, LDS_CHILD> MC{S, LV[l + 1]};
+      T *gc = MC.vec(EV_G);
+      const int order[4] = {0, 1, 3, 2};
+      for (int m = tid; m < n4; m += kStride) {
+        T r[4];
+#pragma unroll
+        for (int o = 0; o < 4; o++) {
+          const uint32_t q = static_cast<uint32_t>(order[o] * n4 + m);
+          r[o] = f[q] - eng_row(k, n, ax, L.optr, L.ocol, L.oval, q, u);
+        }
+        T acc = 0;
+#pragma unroll
+        for (int o = 0; o < 4; o++) acc += r[o];
+        gc[q_of_m(static_cast<uint32_t>(m), k - 1)] = acc;
+      }
+      break;
+    }
+    case EO_DENSE: {
+      // 16 threads per row: strided partial sums, then a fixed butterfly over the 16 lanes
+      const T *g = M.vec(EV_G);
+      T *e = M.vec(EV_E);
+      const int part = tid & 15;
+      for (int i0 = 0; i0 < P.nc; i0 += kStride / 16) {
+        const int i = i0 + (tid >> 4);
+        double acc = 0.0;
+        if (i < P.nc)
+          for (int j = part; j < P.nc; j += 16) acc += Ainv[i * P.nc + j] * static_cast<double>(g[j]);
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 16);
+        if (i < P.nc && part == 0) e[i] = static_cast<T>(acc);
+      }
+      break;
+    }
+    case EO_PROLONG: {
+      T *u = M.vec(op.u);
+      const EngMem<T, LDS_CHILD> MC{S, LV[l + 1]};
+      const T *ec = MC.vec(EV_E);
+      for (int q = tid; q < n; q += kStride)
+        u[q] += ec[q_of_m(static_cast<uint32_t>(q & (n4 - 1)), k - 1)];
+      break;
+    }
+    case EO_SPMV_DOT0:
+    case EO_SPMV_DOT1: {
+      const bool first = op.type == EO_SPMV_DOT0;
+      const T *x = M.vec(first ? EV_P0 : EV_P1);
+      T *y = M.vec(first ? EV_Q0 : EV_Q1);
+      const T *w = M.vec(first ? EV_G : EV_R);
+      double v[2] = {0.0, 0.0};
+      for (int q = tid; q < n; q += kStride) {
+        const T yq = eng_row(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q), x);
+        y[q] = yq;
+        v[0] += static_cast<double>(x[q]) * static_cast<double>(yq);
+        v[1] += static_cast<double>(w[q]) * static_cast<double>(x[q]);
+      }
+      eng_reduce<2>(v, C.red);
+      if (tid == 0) {
+        if (first) {
+          const bool stop = !(v[0] > 0.0);
+          C.sc[S_D0] = v[0];
+          C.sc[S_STOP] = stop ? 1.0 : 0.0;
+          C.sc[S_A0] = stop ? 0.0 : v[1] / v[0];
+        } else {
+          C.sc[S_A1 - 3] = (C.sc[S_STOP] != 0.0 || !(v[0] > 0.0)) ? 0.0 : v[1] / v[0];
+        }
+      }
+      break;
+    }
+    case EO_UPDATE1: {
+      const T a0 = static_cast<T>(C.sc[S_A0]);
+      const T *p0 = M.vec(EV_P0), *q0 = M.vec(EV_Q0), *g = M.vec(EV_G);
+      T *e = M.vec(EV_E), *r = M.vec(EV_R);
+      for (int i = tid; i < n; i += kStride) {
+        e[i] = a0 * p0[i];
+        r[i] = g[i] - a0 * q0[i];
+      }
+      break;
+    }
+    case EO_DOT_BETA: {
+      const T *p1 = M.vec(EV_P1), *q0 = M.vec(EV_Q0);
+      double t[1] = {0.0};
+      for (int i = tid; i < n; i += kStride) t[0] += static_cast<double>(p1[i]) * static_cast<double>(q0[i]);
+      eng_reduce<1>(t, C.red);
+      if (tid == 0) C.sc[S_BETA] = (C.sc[S_STOP] != 0.0) ? 0.0 : -t[0] / C.sc[S_D0];
+      break;
+    }
+    case EO_AXPY_BETA: {
+      const T beta = static_cast<T>(C.sc[S_BETA]);
+      T *p1 = M.vec(EV_P1);
+      const T *p0 = M.vec(EV_P0);
+      for (int i = tid; i < n; i += kStride) p1[i] += beta * p0[i];
+      break;
+    }
+    case EO_UPDATE2: {
+      const T a1 = static_cast<T>(C.sc[S_A1 - 3]);
+      const T *p1 = M.vec(EV_P1);
+      T *e = M.vec(EV_E);
+      for (int i = tid; i < n; i += kStride) e[i] += a1 * p1[i];
+      break;
+    }
+    default:
+      break;
   }
+}
+
+// Interpret a step list (operators and step list already staged in LDS).
+template <class T>
+__device__ inline void eng_run(const EngPlan<T> &P, const EngOp *ops, const EngLevel<T> *LV, T *S,
+                               const double *Ainv, double (*sc)[8], double *red) {
+  for (int oi = 0; oi < P.nops; oi++) {
+    const EngOp op = ops[oi];
+    const EngCtx C{sc[op.lvl], red};
+    const bool lds = LV[op.lvl].in_lds != 0;
+    const bool lds_child = (op.lvl + 1 < P.nlev) && LV[op.lvl + 1].in_lds != 0;
+    if (lds) eng_step<T, true, true>(op, LV, P, S, Ainv, C);
+    else if (lds_child) eng_step<T, false, true>(op, LV, P, S, Ainv, C);
+    else eng_step<T, false, false>(op, LV, P, S, Ainv, C);
+    __syncthreads();
+  }
+}
+
+// Copy the step list, level table, coarsest inverse and LDS-resident operators into LDS.
+template <class T>
+__device__ inline void eng_stage(const EngPlan<T> &P, EngOp *ops, EngLevel<T> *LV, T *S, double *ainv_lds) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < P.nops; i += kEngThreads) ops[i] = P.ops[i];
+  if (tid < P.nlev) LV[tid] = P.lv[tid];
   if (P.ainv_in_lds)
     for (int i = tid; i < P.nc * P.nc; i += kEngThreads) ainv_lds[i] = P.ainv[i];
   for (int l = 0; l < P.nlev; l++) {
@@ -680,172 +857,55 @@ __global__ void __launch_bounds__(kEngThreads) k_engine(EngPlan<T> P) {
     if (L.in_lds && l + 1 < P.nlev)
       for (int i = tid; i < 9 * L.n; i += kEngThreads) S[L.ax_off + i] = L.ax[i];
   }
-  __syncthreads();
-  if (P.lv[0].in_lds)
-    for (int i = tid; i < P.lv[0].n; i += kEngThreads) vp[0][EV_G][i] = P.g_in[i];
-  __syncthreads();
-  const double *Ainv = P.ainv_in_lds ? ainv_lds : P.ainv;
-
-  for (int oi = 0; oi < P.nops; oi++) {
-    const EngOp op = P.ops[oi];
-    const int l = op.lvl;
-    const EngLevel<T> &L = P.lv[l];
-    const int k = L.k, n = L.n, n4 = n >> 2;
-    const T *ax = axp[l];
-    T *const *V = vp[l];
-    switch (op.type) {
-      case EO_GS_FIRST: {
-        const T *f = V[op.f];
-        T *u = V[op.u];
-        for (int q = tid; q < n; q += kEngThreads) u[q] = (q < n4) ? f[q] / ax[q] : T(0);
-        break;
-      }
-      case EO_GS: {
-        const T *f = V[op.f];
-        T *u = V[op.u];
-        T *d = V[EV_D];
-        const int c = op.color;
-        for (int j = tid; j < n4; j += kEngThreads) {
-          const uint32_t q = static_cast<uint32_t>(c * n4 + j);
-          const uint32_t m = (static_cast<uint32_t>(j) << 2) | static_cast<uint32_t>(c);
-          const T dl = (f[q] - eng_row(k, n, ax, L.optr, L.ocol, L.oval, q, static_cast<int>(compact_bits(m)),
-                                       static_cast<int>(compact_bits(m >> 1)), u)) / ax[q];
-          if (L.same_color) d[q] = dl;
-          else u[q] += dl;
-        }
-        if (L.same_color) {
-          __syncthreads();
-          for (int j = tid; j < n4; j += kEngThreads) u[c * n4 + j] += d[c * n4 + j];
-        }
-        break;
-      }
-      case EO_RES_RESTRICT: {
-        const T *f = V[op.f];
-        const T *u = V[op.u];
-        T *gc = vp[l + 1][EV_G];
-        const int order[4] = {0, 1, 3, 2};
-        for (int M = tid; M < n4; M += kEngThreads) {
-          T acc = 0;
-#pragma unroll
-          for (int o = 0; o < 4; o++) {
-            const uint32_t q = static_cast<uint32_t>(order[o] * n4 + M);
-            const uint32_t m = (static_cast<uint32_t>(M) << 2) | static_cast<uint32_t>(order[o]);
-            acc += f[q] - eng_row(k, n, ax, L.optr, L.ocol, L.oval, q, static_cast<int>(compact_bits(m)),
-                                  static_cast<int>(compact_bits(m >> 1)), u);
-          }
-          gc[q_of_m(static_cast<uint32_t>(M), k - 1)] = acc;
-        }
-        break;
-      }
-      case EO_DENSE: {
-        const T *g = V[EV_G];
-        T *e = V[EV_E];
-        for (int i = tid; i < P.nc; i += kEngThreads) {
-          double acc = 0.0;
-          for (int j = 0; j < P.nc; j++) acc += Ainv[i * P.nc + j] * static_cast<double>(g[j]);
-          e[i] = static_cast<T>(acc);
-        }
-        break;
-      }
-      case EO_PROLONG: {
-        T *u = V[op.u];
-        const T *ec = vp[l + 1][EV_E];
-        for (int q = tid; q < n; q += kEngThreads)
-          u[q] += ec[q_of_m(static_cast<uint32_t>(q & (n4 - 1)), k - 1)];
-        break;
-      }
-      case EO_SPMV_DOT0:
-      case EO_SPMV_DOT1: {
-        const bool first = op.type == EO_SPMV_DOT0;
-        const T *x = V[first ? EV_P0 : EV_P1];
-        T *y = V[first ? EV_Q0 : EV_Q1];
-        const T *w = V[first ? EV_G : EV_R];
-        double v[2] = {0.0, 0.0};
-        for (int q = tid; q < n; q += kEngThreads) {
-          const uint32_t m = m_of_q(static_cast<uint32_t>(q), k);
-          const T yq = eng_row(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q),
-                               static_cast<int>(compact_bits(m)), static_cast<int>(compact_bits(m >> 1)), x);
-          y[q] = yq;
-          v[0] += static_cast<double>(x[q]) * static_cast<double>(yq);
-          v[1] += static_cast<double>(w[q]) * static_cast<double>(x[q]);
-        }
-        eng_reduce<2>(v, red);
-        if (tid == 0) {
-          if (first) {
-            const bool stop = !(v[0] > 0.0);
-            sc[l][S_D0] = v[0];
-            sc[l][S_STOP] = stop ? 1.0 : 0.0;
-            sc[l][S_A0] = stop ? 0.0 : v[1] / v[0];
-          } else {
-            sc[l][S_A1 - 3] = (sc[l][S_STOP] != 0.0 || !(v[0] > 0.0)) ? 0.0 : v[1] / v[0];
-          }
-        }
-        break;
-      }
-      case EO_UPDATE1: {
-        const T a0 = static_cast<T>(sc[l][S_A0]);
-        const T *p0 = V[EV_P0], *q0 = V[EV_Q0], *g = V[EV_G];
-        T *e = V[EV_E], *r = V[EV_R];
-        for (int i = tid; i < n; i += kEngThreads) {
-          e[i] = a0 * p0[i];
-          r[i] = g[i] - a0 * q0[i];
-        }
-        break;
-      }
-      case EO_DOT_BETA: {
-        const T *p1 = V[EV_P1], *q0 = V[EV_Q0];
-        double t[1] = {0.0};
-        for (int i = tid; i < n; i += kEngThreads) t[0] += static_cast<double>(p1[i]) * static_cast<double>(q0[i]);
-        eng_reduce<1>(t, red);
-        if (tid == 0) sc[l][S_BETA] = (sc[l][S_STOP] != 0.0) ? 0.0 : -t[0] / sc[l][S_D0];
-        break;
-      }
-      case EO_AXPY_BETA: {
-        const T beta = static_cast<T>(sc[l][S_BETA]);
-        T *p1 = V[EV_P1];
-        const T *p0 = V[EV_P0];
-        for (int i = tid; i < n; i += kEngThreads) p1[i] += beta * p0[i];
-        break;
-      }
-      case EO_UPDATE2: {
-        const T a1 = static_cast<T>(sc[l][S_A1 - 3]);
-        const T *p1 = V[EV_P1];
-        T *e = V[EV_E];
-        for (int i = tid; i < n; i += kEngThreads) e[i] += a1 * p1[i];
-        break;
-      }
-      default:
-        break;
-    }
-    __syncthreads();
-  }
-  if (P.lv[0].in_lds)
-    for (int i = tid; i < P.lv[0].n; i += kEngThreads) P.e_out[i] = vp[0][EV_E][i];
 }
 
-// step list of B~ at engine level l (mirrors btilde / bhat_coarse below)
-static void emit_bhat(std::vector<EngOp> &ops, int l, int nl, int sweeps, int inner, int f, int u);
-static void emit_btilde(std::vector<EngOp> &ops, int l, int nl, int sweeps, int inner) {
-  emit_bhat(ops, l, nl, sweeps, inner, EV_G, EV_P0);
+template <class T>
+__global__ void __launch_bounds__(kEngThreads) k_engine(EngPlan<T> P) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double sc[kEngMaxLevels][8];
+  __shared__ double red[2 * kEngWaves];
+  __shared__ EngOp ops[kEngMaxOps];
+  __shared__ EngLevel<T> LV[kEngMaxLevels];
+  const int tid = threadIdx.x;
+  T *S = reinterpret_cast<T *>(smem + P.t_base);
+  double *ainv_lds = reinterpret_cast<double *>(smem);
+  eng_stage(P, ops, LV, S, ainv_lds);
+  if (P.lv[0].in_lds)
+    for (int i = tid; i < P.lv[0].n; i += kEngThreads) S[P.lv[0].vec_off + EV_G * P.lv[0].n + i] = P.g_in[i];
+  __syncthreads();
+  eng_run(P, ops, LV, S, P.ainv_in_lds ? ainv_lds : P.ainv, sc, red);
+  if (P.lv[0].in_lds)
+    for (int i = tid; i < P.lv[0].n; i += kEngThreads) P.e_out[i] = S[P.lv[0].vec_off + EV_E * P.lv[0].n + i];
+}
+
+// Step list of B~ at engine level l; mirrors btilde / bhat_coarse below.
+struct EmitCtx {
+  int nl, sweeps, inner;
+};
+
+static void emit_btilde(std::vector<EngOp> &ops, const EmitCtx &E, int l);
+
+static void emit_bhat(std::vector<EngOp> &ops, const EmitCtx &E, int l, int f, int u) {
+  for (int sw = 0; sw < E.sweeps; sw++)
+    for (int c = 0; c < 4; c++) ops.push_back({(sw == 0 && c == 0) ? EO_GS_FIRST : EO_GS, l, c, f, u});
+  ops.push_back({EO_RES_RESTRICT, l, 0, f, u});
+  if (l + 1 == E.nl - 1) ops.push_back({EO_DENSE, l + 1, 0, 0, 0});
+  else emit_btilde(ops, E, l + 1);
+  ops.push_back({EO_PROLONG, l, 0, f, u});
+  for (int sw = 0; sw < E.sweeps; sw++)
+    for (int c = 3; c >= 0; c--) ops.push_back({EO_GS, l, c, f, u});
+}
+
+static void emit_btilde(std::vector<EngOp> &ops, const EmitCtx &E, int l) {
+  emit_bhat(ops, E, l, EV_G, EV_P0);
   ops.push_back({EO_SPMV_DOT0, l, 0, 0, 0});
   ops.push_back({EO_UPDATE1, l, 0, 0, 0});
-  if (inner < 2) return;
-  emit_bhat(ops, l, nl, sweeps, inner, EV_R, EV_P1);
+  if (E.inner < 2) return;
+  emit_bhat(ops, E, l, EV_R, EV_P1);
   ops.push_back({EO_DOT_BETA, l, 0, 0, 0});
   ops.push_back({EO_AXPY_BETA, l, 0, 0, 0});
   ops.push_back({EO_SPMV_DOT1, l, 0, 0, 0});
   ops.push_back({EO_UPDATE2, l, 0, 0, 0});
-}
-static void emit_bhat(std::vector<EngOp> &ops, int l, int nl, int sweeps, int inner, int f, int u) {
-  for (int sw = 0; sw < sweeps; sw++)
-    for (int c = 0; c < 4; c++)
-      ops.push_back({(sw == 0 && c == 0) ? EO_GS_FIRST : EO_GS, l, c, f, u});
-  ops.push_back({EO_RES_RESTRICT, l, 0, f, u});
-  if (l + 1 == nl - 1) ops.push_back({EO_DENSE, l + 1, 0, 0, 0});
-  else emit_btilde(ops, l + 1, nl, sweeps, inner);
-  ops.push_back({EO_PROLONG, l, 0, f, u});
-  for (int sw = 0; sw < sweeps; sw++)
-    for (int c = 3; c >= 0; c--) ops.push_back({EO_GS, l, c, f, u});
 }
 
 amg_status plan_engine(amg_hierarchy *h) {
@@ -854,10 +914,12 @@ amg_status plan_engine(amg_hierarchy *h) {
   int lds = 0;
   QA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
   h->lds_max = static_cast<size_t>(lds);
-  const size_t budget = h->lds_max > 8192 ? h->lds_max - 8192 : 0;  // room for the static shared arrays
+  // room for the static shared arrays (step list, pointer tables, scalars)
+  const size_t stat = sizeof(EngOp) * kEngMaxOps + 4096;
+  const size_t budget = h->lds_max > stat ? h->lds_max - stat : 0;
   for (int pi = 0; pi < 2; pi++) {
     const size_t ts = pi == 0 ? sizeof(double) : sizeof(float);
-    // deepest levels first: find the largest set of LDS-resident levels (coarsest included)
+    // deepest levels first: the largest set of LDS-resident levels (coarsest included)
     size_t bytes = static_cast<size_t>(h->nc) * 2 * ts;
     int lds_top = h->nlev - 1;
     while (lds_top - 1 >= 1 && bytes + static_cast<size_t>(h->lev[lds_top - 1].n) * 17 * ts <= budget) {
@@ -867,17 +929,28 @@ amg_status plan_engine(amg_hierarchy *h) {
     int top = lds_top;
     // one more level above may run from global memory (L2-resident) when it is small enough
     if (top - 1 >= 1 && h->lev[top - 1].n <= h->engine_global_rows) top--;
-    if (top >= h->nlev - 1 || h->nlev - top > kEngMaxLevels) continue;
+    std::vector<EngOp> ops;
+    for (;; top++) {
+      if (top >= h->nlev - 1) break;
+      ops.clear();
+      if (h->nlev - top <= kEngMaxLevels) emit_btilde(ops, EmitCtx{h->nlev - top, h->opt.sweeps, h->opt.inner_iters}, 0);
+      if (!ops.empty() && ops.size() <= static_cast<size_t>(kEngMaxOps)) break;
+    }
+    if (top >= h->nlev - 1) continue;  // no engine for this precision
+    if (lds_top < top) {               // LDS holds exactly the engine's levels from top down
+      lds_top = top;
+      bytes = static_cast<size_t>(h->nc) * 2 * ts;
+      for (int l = top; l < h->nlev - 1; l++) bytes += static_cast<size_t>(h->lev[l].n) * 17 * ts;
+    }
     const bool ainv = bytes + static_cast<size_t>(h->nc * h->nc) * 8 <= budget;
+    EngOp *d = static_cast<EngOp *>(dalloc(h, sizeof(EngOp) * ops.size()));
+    if (!d) return AMG_ERR_NOMEM;
+    QA_HIP(hipMemcpyAsync(d, ops.data(), sizeof(EngOp) * ops.size(), hipMemcpyHostToDevice, h->stream));
+    QA_HIP(hipStreamSynchronize(h->stream));
     h->engine_top[pi] = top;
     h->engine_lds_top[pi] = lds_top;
     h->engine_ainv_lds[pi] = ainv ? 1 : 0;
     h->engine_lds[pi] = bytes + (ainv ? static_cast<size_t>(h->nc * h->nc) * 8 : 0);
-    std::vector<EngOp> ops;
-    emit_btilde(ops, 0, h->nlev - top, h->opt.sweeps, h->opt.inner_iters);
-    EngOp *d = static_cast<EngOp *>(dalloc(h, sizeof(EngOp) * ops.size()));
-    if (!d) return AMG_ERR_NOMEM;
-    QA_HIP(hipMemcpy(d, ops.data(), sizeof(EngOp) * ops.size(), hipMemcpyHostToDevice));
     h->engine_ops[pi] = d;
     h->engine_nops[pi] = static_cast<int>(ops.size());
   }
@@ -890,15 +963,12 @@ amg_status plan_engine(amg_hierarchy *h) {
   return AMG_OK;
 }
 
+// Level table of an engine whose top is hierarchy level `top`, levels from `lds_top` down LDS-resident.
 template <class T>
-static void launch_engine(amg_hierarchy *h, int top) {
-  const int pi = std::is_same<T, float>::value ? 1 : 0;
-  EngPlan<T> E{};
+static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, EngPlan<T> &E) {
   E.nlev = h->nlev - top;
-  E.nops = h->engine_nops[pi];
-  E.ops = static_cast<const EngOp *>(h->engine_ops[pi]);
   E.nc = static_cast<int>(h->nc);
-  E.ainv_in_lds = h->engine_ainv_lds[pi];
+  E.ainv_in_lds = ainv_lds;
   E.ainv = h->ainv;
   E.t_base = E.ainv_in_lds ? static_cast<int>(h->nc * h->nc * 8) : 0;
   int off = 0;
@@ -914,7 +984,7 @@ static void launch_engine(amg_hierarchy *h, int top) {
     L.ocol = Q.ocol;
     L.oval = P<T>::oval(Q);
     L.same_color = Q.same_color_ovf;
-    L.in_lds = l >= h->engine_lds_top[pi] ? 1 : 0;
+    L.in_lds = l >= lds_top ? 1 : 0;
     if (L.in_lds) {
       if (i + 1 < E.nlev) {  // operator and the eight vectors
         L.ax_off = off;
@@ -930,9 +1000,313 @@ static void launch_engine(amg_hierarchy *h, int top) {
       L.vec[EV_Q0] = W[l].q0; L.vec[EV_P1] = W[l].p1; L.vec[EV_Q1] = W[l].q1; L.vec[EV_D] = W[l].d;
     }
   }
+}
+
+template <class T>
+static void launch_engine(amg_hierarchy *h, int top) {
+  const int pi = std::is_same<T, float>::value ? 1 : 0;
+  EngPlan<T> E{};
+  fill_engine(h, top, h->engine_lds_top[pi], h->engine_ainv_lds[pi], E);
+  E.nops = h->engine_nops[pi];
+  E.ops = static_cast<const EngOp *>(h->engine_ops[pi]);
+  std::vector<LevelWork<T>> &W = P<T>::W(h);
   E.g_in = W[top].g;
   E.e_out = W[top].e;
   k_engine<T><<<1, kEngThreads, h->engine_lds[pi], h->stream>>>(E);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
+// Whole-solve workgroup: the serving form for small systems. One workgroup runs a complete solve of one system
+// (outer flexible CG, fine-level block smoother, the coarse cycle through the step interpreter, the convergence
+// test) with no host round trip; a batch of systems is one launch with one workgroup per system, so the result of
+// a system does not depend on what else is in the batch.
+
+constexpr int64_t kWgMaxRows = 65536;
+
+template <class T>
+struct WgSys {
+  int n, L, nslices;
+  int64_t color_row[5], color_slice[5];
+  const int64_t *slice_ptr;
+  const int32_t *slice_row0, *s_col;
+  const T *s_val;             // preconditioner precision
+  const double *s_val64;      // outer FP64 operator
+  const T *diag;
+  const int32_t *ic_ptr, *ic_col;
+  const T *ic_val;
+  const int32_t *crow, *agg_q, *perm;
+  const double *b;            // caller numbering
+  double *x;
+  double *xp, *rp, *bp, *zp, *tp, *pv[2], *qv[2];
+  T *f, *u, *d;               // preconditioner input / output / temporary (f, u alias rp, zp in FP64)
+  double *info;               // status, iterations, restarts, relative residual
+  double tol;
+  int max_iters, mmax, sweeps;
+  EngPlan<T> E;               // coarse levels: engine level 0 = hierarchy level 1
+};
+
+// residual of the rows of slices [s0, s1) (one wavefront per slice, strided over the workgroup's wavefronts)
+template <class V, class X>
+__device__ inline void wg_resid(const int64_t *sp, const int32_t *r0, const int32_t *col, const V *val, const X *f,
+                                const X *x, X *d, int64_t s0, int64_t s1) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t s = s0 + (threadIdx.x >> 6); s < s1; s += kEngWaves) {
+    const int32_t row = r0[s] + lane;
+    if (row >= r0[s + 1]) continue;
+    const int64_t off = sp[s];
+    const int w = static_cast<int>((sp[s + 1] - off) >> 6);
+    X acc = 0;
+    for (int k = 0; k < w; k++) {
+      const int64_t e = off + static_cast<int64_t>(k) * 64 + lane;
+      acc += val[e] * x[col[e]];
+    }
+    d[row] = f[row] - acc;
+  }
+}
+
+template <class T>
+__device__ inline void wg_subst(const WgSys<T> &Y, const T *src, T *d, T *x, int c, bool fwd) {
+  const int64_t nL4 = Y.E.lv[0].n >> 2;
+  for (int64_t q = c * nL4 + threadIdx.x; q < (c + 1) * nL4; q += kEngThreads) {
+    const int32_t a = Y.crow[q], b = Y.crow[q + 1];
+    if (fwd) {
+      for (int32_t p = a; p < b; p++) {
+        T acc = src[p];
+        for (int32_t e = Y.ic_ptr[p]; e < Y.ic_ptr[p + 1]; e++)
+          if (Y.ic_col[e] < p) acc -= Y.ic_val[e] * d[Y.ic_col[e]];
+        d[p] = acc / Y.diag[p];
+      }
+    } else {
+      for (int32_t p = b - 1; p >= a; p--) {
+        T acc = src[p];
+        for (int32_t e = Y.ic_ptr[p]; e < Y.ic_ptr[p + 1]; e++)
+          if (Y.ic_col[e] > p) acc -= Y.ic_val[e] * d[Y.ic_col[e]];
+        d[p] = acc / Y.diag[p];
+      }
+    }
+    for (int32_t p = a; p < b; p++) x[p] += d[p];
+  }
+}
+
+template <class T>
+__device__ inline void wg_fine_phase(const WgSys<T> &Y, const T *f, T *u, int c, bool fwd, bool from_f) {
+  if (!from_f) {
+    wg_resid(Y.slice_ptr, Y.slice_row0, Y.s_col, Y.s_val, f, u, Y.d, Y.color_slice[c], Y.color_slice[c + 1]);
+    __syncthreads();
+  }
+  wg_subst(Y, from_f ? f : Y.d, Y.d, u, c, fwd);
+  __syncthreads();
+}
+
+template <class T>
+__device__ inline T *wg_engine_vec(const EngLevel<T> &L, T *S, int v) {
+  return L.in_lds ? S + L.vec_off + v * L.n : L.vec[v];
+}
+
+// z = B^_F[f] on the fine level (Algorithm 2.2), the coarse B~ through the step interpreter
+template <class T>
+__device__ void wg_bhat_fine(const WgSys<T> &Y, const EngOp *ops, const EngLevel<T> *LV, T *S, const double *Ainv,
+                             double (*sc)[8], double *red, const T *f, T *u) {
+  const int tid = threadIdx.x;
+  for (int i = tid; i < Y.n; i += kEngThreads) u[i] = T(0);
+  __syncthreads();
+  for (int sw = 0; sw < Y.sweeps; sw++)
+    for (int c = 0; c < 4; c++) wg_fine_phase(Y, f, u, c, true, sw == 0 && c == 0);
+  wg_resid(Y.slice_ptr, Y.slice_row0, Y.s_col, Y.s_val, f, u, Y.d, 0, Y.nslices);
+  __syncthreads();
+  T *g0 = wg_engine_vec(LV[0], S, EV_G);
+  const int nL = LV[0].n;
+  for (int q = tid; q < nL; q += kEngThreads) {
+    T acc = 0;
+    for (int32_t p = Y.crow[q]; p < Y.crow[q + 1]; p++) acc += Y.d[p];
+    g0[q] = acc;
+  }
+  __syncthreads();
+  eng_run(Y.E, ops, LV, S, Ainv, sc, red);
+  const T *e0 = wg_engine_vec(LV[0], S, EV_E);
+  for (int i = tid; i < Y.n; i += kEngThreads) u[i] += e0[Y.agg_q[i]];
+  __syncthreads();
+  for (int sw = 0; sw < Y.sweeps; sw++)
+    for (int c = 3; c >= 0; c--) wg_fine_phase(Y, f, u, c, false, false);
+}
+
+// q = A p (FP64) with (p, q) and (r, p), or the true residual t = b - A x with (t, t)
+__device__ inline void wg_spmv64(const int64_t *sp, const int32_t *r0, const int32_t *col, const double *val,
+                                 int64_t ns, const double *p, double *q, const double *r, double (&v)[2]) {
+  const int lane = threadIdx.x & 63;
+  v[0] = 0.0; v[1] = 0.0;
+  for (int64_t s = threadIdx.x >> 6; s < ns; s += kEngWaves) {
+    const int32_t row = r0[s] + lane;
+    if (row >= r0[s + 1]) continue;
+    const int64_t off = sp[s];
+    const int w = static_cast<int>((sp[s + 1] - off) >> 6);
+    double acc = 0.0;
+    for (int k = 0; k < w; k++) {
+      const int64_t e = off + static_cast<int64_t>(k) * 64 + lane;
+      acc += val[e] * p[col[e]];
+    }
+    q[row] = acc;
+    v[0] += p[row] * acc;
+    v[1] += r[row] * p[row];
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kEngThreads) k_solve_wg(const WgSys<T> *systems) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double sc[kEngMaxLevels][8];
+  __shared__ double red[2 * kEngWaves];
+  __shared__ EngOp ops[kEngMaxOps];
+  __shared__ EngLevel<T> LV[kEngMaxLevels];
+  const WgSys<T> &Y = systems[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int n = Y.n;
+  T *S = reinterpret_cast<T *>(smem + Y.E.t_base);
+  double *ainv_lds = reinterpret_cast<double *>(smem);
+  eng_stage(Y.E, ops, LV, S, ainv_lds);
+  const double *Ainv = Y.E.ainv_in_lds ? ainv_lds : Y.E.ainv;
+  // x = 0, r = b (permuted)
+  double v1[1] = {0.0};
+  for (int i = tid; i < n; i += kEngThreads) {
+    const double bi = Y.b[Y.perm[i]];
+    Y.bp[i] = bi;
+    Y.rp[i] = bi;
+    Y.xp[i] = 0.0;
+    v1[0] += bi * bi;
+  }
+  eng_reduce<1>(v1, red);  // includes the barrier that publishes the staging above
+  const double bn = sqrt(v1[0]);
+  double status = 6.0;  // NOCONV unless something else happens
+  int it = 0, restarts = 0, par = 0;
+  bool have_prev = false;
+  double dprev = 0.0;
+  if (bn == 0.0) {
+    status = 0.0;
+  } else {
+    while (it < Y.max_iters) {
+      // z = B^_F[r]
+      if constexpr (std::is_same<T, double>::value) {
+        wg_bhat_fine(Y, ops, LV, S, Ainv, sc, red, Y.rp, Y.zp);
+      } else {
+        for (int i = tid; i < n; i += kEngThreads) Y.f[i] = static_cast<T>(Y.rp[i]);
+        __syncthreads();
+        wg_bhat_fine(Y, ops, LV, S, Ainv, sc, red, Y.f, Y.u);
+        for (int i = tid; i < n; i += kEngThreads) Y.zp[i] = static_cast<double>(Y.u[i]);
+        __syncthreads();
+      }
+      double *p = Y.pv[par], *q = Y.qv[par];
+      const double *pprev = Y.pv[1 - par], *qprev = Y.qv[1 - par];
+      double beta = 0.0;
+      if (have_prev && Y.mmax == 1) {
+        double t1[1] = {0.0};
+        for (int i = tid; i < n; i += kEngThreads) t1[0] += Y.zp[i] * qprev[i];
+        eng_reduce<1>(t1, red);
+        beta = -t1[0] / dprev;
+      }
+      for (int i = tid; i < n; i += kEngThreads) p[i] = (have_prev && Y.mmax == 1) ? Y.zp[i] + beta * pprev[i] : Y.zp[i];
+      __syncthreads();
+      double v2[2];
+      wg_spmv64(Y.slice_ptr, Y.slice_row0, Y.s_col, Y.s_val64, Y.nslices, p, q, Y.rp, v2);
+      eng_reduce<2>(v2, red);
+      const double d = v2[0];
+      if (!(d > 0.0)) {
+        status = 5.0;  // BREAKDOWN
+        break;
+      }
+      const double alpha = v2[1] / d;
+      double v3[1] = {0.0};
+      for (int i = tid; i < n; i += kEngThreads) {
+        Y.xp[i] += alpha * p[i];
+        const double ri = Y.rp[i] - alpha * q[i];
+        Y.rp[i] = ri;
+        v3[0] += ri * ri;
+      }
+      eng_reduce<1>(v3, red);
+      it++;
+      have_prev = true;
+      dprev = d;
+      par ^= 1;
+      if (sqrt(v3[0]) <= Y.tol * bn) {
+        double v4[2];
+        wg_spmv64(Y.slice_ptr, Y.slice_row0, Y.s_col, Y.s_val64, Y.nslices, Y.xp, Y.tp, Y.xp, v4);
+        __syncthreads();
+        double v5[1] = {0.0};
+        for (int i = tid; i < n; i += kEngThreads) {
+          const double ti = Y.bp[i] - Y.tp[i];
+          Y.tp[i] = ti;
+          v5[0] += ti * ti;
+        }
+        eng_reduce<1>(v5, red);
+        if (sqrt(v5[0]) <= Y.tol * bn) {
+          status = 0.0;
+          break;
+        }
+        for (int i = tid; i < n; i += kEngThreads) Y.rp[i] = Y.tp[i];
+        __syncthreads();
+        have_prev = false;
+        restarts++;
+      }
+    }
+  }
+  // true relative residual and the solution in the caller's numbering
+  double v6[2];
+  wg_spmv64(Y.slice_ptr, Y.slice_row0, Y.s_col, Y.s_val64, Y.nslices, Y.xp, Y.tp, Y.xp, v6);
+  __syncthreads();
+  double v7[1] = {0.0};
+  for (int i = tid; i < n; i += kEngThreads) {
+    const double ti = Y.bp[i] - Y.tp[i];
+    v7[0] += ti * ti;
+    Y.x[Y.perm[i]] = Y.xp[i];
+  }
+  eng_reduce<1>(v7, red);
+  if (tid == 0) {
+    Y.info[0] = status;
+    Y.info[1] = it;
+    Y.info[2] = restarts;
+    Y.info[3] = bn == 0.0 ? 0.0 : sqrt(v7[0]) / bn;
+  }
+}
+
+// Plan of the whole-solve workgroup for one precision: all quadtree levels run through the step interpreter, the
+// deepest ones from LDS.
+amg_status plan_wg(amg_hierarchy *h) {
+  h->wg_nops[0] = h->wg_nops[1] = 0;
+  if (h->nlev < 3 || h->n > kWgMaxRows) return AMG_OK;
+  if (h->lds_max == 0) {
+    int lds = 0;
+    QA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+    h->lds_max = static_cast<size_t>(lds);
+  }
+  const size_t stat = sizeof(EngOp) * kEngMaxOps + 4096;
+  const size_t budget = h->lds_max > stat ? h->lds_max - stat : 0;
+  std::vector<EngOp> ops;
+  emit_btilde(ops, EmitCtx{h->nlev - 1, h->opt.sweeps, h->opt.inner_iters}, 0);
+  if (ops.size() > static_cast<size_t>(kEngMaxOps) || h->nlev - 1 > kEngMaxLevels) return AMG_OK;
+  for (int pi = 0; pi < 2; pi++) {
+    const size_t ts = pi == 0 ? sizeof(double) : sizeof(float);
+    size_t bytes = static_cast<size_t>(h->nc) * 2 * ts;
+    int lds_top = h->nlev - 1;
+    while (lds_top - 1 >= 1 && bytes + static_cast<size_t>(h->lev[lds_top - 1].n) * 17 * ts <= budget) {
+      lds_top--;
+      bytes += static_cast<size_t>(h->lev[lds_top].n) * 17 * ts;
+    }
+    const bool ainv = bytes + static_cast<size_t>(h->nc * h->nc) * 8 <= budget;
+    EngOp *d = static_cast<EngOp *>(dalloc(h, sizeof(EngOp) * ops.size()));
+    if (!d) return AMG_ERR_NOMEM;
+    QA_HIP(hipMemcpyAsync(d, ops.data(), sizeof(EngOp) * ops.size(), hipMemcpyHostToDevice, h->stream));
+    QA_HIP(hipStreamSynchronize(h->stream));
+    h->wg_ops[pi] = d;
+    h->wg_nops[pi] = static_cast<int>(ops.size());
+    h->wg_lds_top[pi] = lds_top;
+    h->wg_ainv_lds[pi] = ainv ? 1 : 0;
+    h->wg_lds[pi] = bytes + (ainv ? static_cast<size_t>(h->nc * h->nc) * 8 : 0);
+  }
+  for (size_t b : {h->wg_lds[0], h->wg_lds[1]}) (void)b;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_solve_wg<double>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(budget));
+  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_solve_wg<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(budget));
+  return AMG_OK;
 }
 
 template <class T> static void btilde(amg_hierarchy *h, int l, const T *g, T *e);
@@ -986,8 +1360,12 @@ template <class T>
 static void fine_resid(amg_hierarchy *h, const T *f, const T *x, T *d, int64_t s0, int64_t s1, int kind) {
   if (s1 <= s0) return;
   Timed tm(h, kind);
-  k_fine_resid<T><<<static_cast<unsigned>((s1 - s0 + 3) / 4), kBlock, 0, h->stream>>>(
-      sview<T>(h->fine, P<T>::sval(h->fine)), f, x, d, s0, s1);
+  if (kind == P<T>::kResid)
+    k_fine_resid_full<T><<<static_cast<unsigned>((s1 - s0 + 3) / 4), kBlock, 0, h->stream>>>(
+        sview<T>(h->fine, P<T>::sval(h->fine)), f, x, d, s1 - s0);
+  else
+    k_fine_resid<T><<<static_cast<unsigned>((s1 - s0 + 3) / 4), kBlock, 0, h->stream>>>(
+        sview<T>(h->fine, P<T>::sval(h->fine)), f, x, d, s0, s1);
 }
 
 template <class T>
@@ -1323,13 +1701,128 @@ extern "C" amg_status amg_level_spmv(amg_hierarchy *h, int32_t level, const doub
   return level_spmv_internal(h, level, x, y, precision);
 }
 
+namespace qa {
+
+template <class T>
+static void fill_wg(amg_hierarchy *h, const double *b, double *x, double tol, double *info, WgSys<T> &Y) {
+  const int pi = std::is_same<T, float>::value ? 1 : 0;
+  const FineLevel &F = h->fine;
+  Y.n = static_cast<int>(h->n);
+  Y.L = h->L;
+  Y.nslices = static_cast<int>(F.nslices);
+  for (int c = 0; c < 5; c++) { Y.color_row[c] = F.color_row[c]; Y.color_slice[c] = F.color_slice[c]; }
+  Y.slice_ptr = F.slice_ptr; Y.slice_row0 = F.slice_row0; Y.s_col = F.s_col;
+  Y.s_val = P<T>::sval(F); Y.s_val64 = F.s_val64; Y.diag = P<T>::diag(F);
+  Y.ic_ptr = F.ic_ptr; Y.ic_col = F.ic_col; Y.ic_val = P<T>::icv(F);
+  Y.crow = F.crow; Y.agg_q = F.agg_q; Y.perm = F.perm;
+  Y.b = b; Y.x = x;
+  Y.xp = h->xp; Y.rp = h->rp; Y.bp = h->bp; Y.zp = h->zp; Y.tp = h->tp;
+  Y.pv[0] = h->pp; Y.pv[1] = h->pprev; Y.qv[0] = h->qp; Y.qv[1] = h->qprev;
+  LevelWork<T> &w0 = P<T>::W(h)[0];
+  Y.f = w0.f; Y.u = w0.u; Y.d = w0.d;
+  Y.info = info;
+  Y.tol = tol;
+  Y.max_iters = h->opt.max_iters;
+  Y.mmax = h->opt.outer_mmax;
+  Y.sweeps = h->opt.sweeps;
+  Y.E = EngPlan<T>{};
+  fill_engine(h, 1, h->wg_lds_top[pi], h->wg_ainv_lds[pi], Y.E);
+  Y.E.nops = h->wg_nops[pi];
+  Y.E.ops = static_cast<const EngOp *>(h->wg_ops[pi]);
+}
+
+static hipStream_t batch_stream(int device) {
+  static hipStream_t streams[64] = {};
+  if (device < 0 || device >= 64) return nullptr;
+  if (!streams[device]) (void)hipStreamCreateWithFlags(&streams[device], hipStreamNonBlocking);
+  return streams[device];
+}
+
+// one launch, one workgroup per system; info of system i -> out[4 i .. 4 i + 3]
+template <class T>
+static amg_status launch_wg_batch(amg_hierarchy *const *hs, const double *const *b, double *const *x,
+                                  const double *tol, const std::vector<int> &ids, std::vector<double> &out) {
+  const int pi = std::is_same<T, float>::value ? 1 : 0;
+  const int m = static_cast<int>(ids.size());
+  const int device = hs[ids[0]]->device;
+  QA_HIP(hipSetDevice(device));
+  hipStream_t s = batch_stream(device);
+  void *buf = nullptr;
+  const size_t sys_bytes = sizeof(WgSys<T>) * m;
+  QA_HIP(hipMallocAsync(&buf, sys_bytes + sizeof(double) * 4 * m, s));
+  double *info_d = reinterpret_cast<double *>(static_cast<char *>(buf) + sys_bytes);
+  std::vector<WgSys<T>> sys(m);
+  size_t lds = 0;
+  for (int j = 0; j < m; j++) {
+    const int i = ids[j];
+    fill_wg<T>(hs[i], b[i], x[i], tol[i], info_d + 4 * j, sys[j]);
+    lds = std::max(lds, hs[i]->wg_lds[pi]);
+  }
+  QA_HIP(hipMemcpyAsync(buf, sys.data(), sys_bytes, hipMemcpyHostToDevice, s));
+  k_solve_wg<T><<<m, kEngThreads, lds, s>>>(static_cast<const WgSys<T> *>(buf));
+  QA_LAUNCH_CHECK();
+  out.assign(4 * m, 0.0);
+  QA_HIP(hipMemcpyAsync(out.data(), info_d, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, s));
+  QA_HIP(hipStreamSynchronize(s));
+  QA_HIP(hipFreeAsync(buf, s));
+  return AMG_OK;
+}
+
+}  // namespace qa
+
 extern "C" amg_status amg_solve_batch(amg_hierarchy *const *hs, const double *const *b, double *const *x,
                                       const double *tol, int32_t count, amg_info *info) {
   if (count < 0 || (count > 0 && (!hs || !b || !x || !tol))) return AMG_ERR_INVALID;
-  amg_status first = AMG_OK;
+  if (count == 0) return AMG_OK;
+  const auto t0 = std::chrono::steady_clock::now();
   for (int32_t i = 0; i < count; i++) {
-    const amg_status st = amg_solve(hs[i], b[i], x[i], tol[i], info ? &info[i] : nullptr);
-    if (st != AMG_OK && first == AMG_OK) first = st;
+    if (!hs[i] || !b[i] || !x[i] || !(tol[i] > 0.0) || !std::isfinite(tol[i])) return AMG_ERR_INVALID;
+    for (int32_t j = 0; j < i; j++)
+      if (hs[j] == hs[i]) return AMG_ERR_INVALID;  // one workspace per hierarchy
+    if (hs[i]->device != hs[0]->device) return AMG_ERR_INVALID;
+  }
+  // inputs are complete once each hierarchy's stream has drained
+  for (int32_t i = 0; i < count; i++) {
+    QA_HIP(hipSetDevice(hs[i]->device));
+    QA_HIP(hipStreamSynchronize(hs[i]->stream));
+  }
+  std::vector<int> small[2], large;
+  for (int32_t i = 0; i < count; i++) {
+    const int pi = hs[i]->precision;
+    if (hs[i]->use_batch && hs[i]->wg_nops[pi] > 0) small[pi].push_back(i);
+    else large.push_back(i);
+  }
+  std::vector<amg_status> st(count, AMG_OK);
+  std::vector<amg_info> inf(count);
+  std::vector<std::thread> threads;
+  for (int i : large)
+    threads.emplace_back([&, i]() {
+      if (hipSetDevice(hs[i]->device) != hipSuccess) { st[i] = AMG_ERR_DEVICE; return; }
+      st[i] = amg_solve(hs[i], b[i], x[i], tol[i], &inf[i]);
+    });
+  amg_status launch_st = AMG_OK;
+  for (int pi = 0; pi < 2 && launch_st == AMG_OK; pi++) {
+    if (small[pi].empty()) continue;
+    std::vector<double> out;
+    launch_st = pi == 0 ? launch_wg_batch<double>(hs, b, x, tol, small[pi], out)
+                        : launch_wg_batch<float>(hs, b, x, tol, small[pi], out);
+    if (launch_st != AMG_OK) break;
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    for (size_t j = 0; j < small[pi].size(); j++) {
+      const int i = small[pi][j];
+      st[i] = static_cast<amg_status>(static_cast<int>(out[4 * j]));
+      inf[i].iters = static_cast<int32_t>(out[4 * j + 1]);
+      inf[i].restarts = static_cast<int32_t>(out[4 * j + 2]);
+      inf[i].relres = out[4 * j + 3];
+      inf[i].setup_ms = hs[i]->setup_ms;
+      inf[i].solve_ms = ms;
+    }
+  }
+  for (auto &t : threads) t.join();
+  amg_status first = launch_st;
+  for (int32_t i = 0; i < count; i++) {
+    if (info) info[i] = inf[i];
+    if (first == AMG_OK && st[i] != AMG_OK) first = st[i];
   }
   return first;
 }
@@ -1376,5 +1869,16 @@ extern "C" amg_status amg_kernel_timing_read(amg_hierarchy *h, int64_t *launches
   if (launches) *launches = t.launches;
   if (total_ms) *total_ms = t.total_ms;
   if (bytes_per_launch) *bytes_per_launch = t.bytes_per_launch;
+  return AMG_OK;
+}
+
+extern "C" amg_status amg_engine_info(const amg_hierarchy *h, int32_t precision, int32_t *top_level,
+                                      int32_t *lds_level, int32_t *steps, size_t *lds_bytes) {
+  if (!h || (precision != 0 && precision != 1)) return AMG_ERR_INVALID;
+  const int pi = precision;
+  if (top_level) *top_level = h->use_engine ? h->engine_top[pi] : -1;
+  if (lds_level) *lds_level = h->engine_lds_top[pi];
+  if (steps) *steps = h->engine_nops[pi];
+  if (lds_bytes) *lds_bytes = h->engine_lds[pi];
   return AMG_OK;
 }

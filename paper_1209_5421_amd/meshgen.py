@@ -226,6 +226,47 @@ def p1_assemble(pts: np.ndarray, tris: np.ndarray, kappa_t: np.ndarray | None = 
     return (np.ascontiguousarray(pts[keep_v]), row_ptr, cu.astype(np.int32), vsum.astype(np.float64))
 
 
+def lattice_p1_assemble(side: int, pts: np.ndarray, tris: np.ndarray, kappa_t: np.ndarray | None = None):
+    """The same P1 system as ``p1_assemble`` for a triangulation whose edges join lattice neighbours (the
+    square-by-square triangulation of a side x side lattice), in O(N): element entries are accumulated into a 9-slot
+    stencil per vertex with bincount instead of sorting all entry pairs. Boundary vertices are eliminated."""
+    tris = np.asarray(tris, dtype=np.int64)
+    npts = len(pts)
+    s = _signed_area2(pts, tris)
+    if np.any(s <= 0):
+        raise ValueError("lattice triangles must be counter-clockwise and non-degenerate")
+    P = [pts[tris[:, k]] for k in range(3)]
+    E = [P[2] - P[1], P[0] - P[2], P[1] - P[0]]
+    kap = np.ones(len(tris)) if kappa_t is None else np.asarray(kappa_t, dtype=np.float64)
+    scale = kap / (2.0 * s)
+    tx = [tris[:, k] % side for k in range(3)]
+    ty = [tris[:, k] // side for k in range(3)]
+    idx, w = [], []
+    for a in range(3):
+        for b in range(3):
+            dx, dy = tx[b] - tx[a], ty[b] - ty[a]
+            if np.abs(dx).max() > 1 or np.abs(dy).max() > 1:
+                raise ValueError("an edge leaves the lattice neighbourhood")
+            idx.append(tris[:, a] * 9 + (dy + 1) * 3 + (dx + 1))
+            w.append(scale * (E[a][:, 0] * E[b][:, 0] + E[a][:, 1] * E[b][:, 1]))
+    idx = np.concatenate(idx)
+    S = np.bincount(idx, weights=np.concatenate(w), minlength=npts * 9).reshape(npts, 9)
+    present = (np.bincount(idx, minlength=npts * 9) > 0).reshape(npts, 9)
+    vx, vy = np.arange(npts) % side, np.arange(npts) // side
+    interior = ~((vx == 0) | (vy == 0) | (vx == side - 1) | (vy == side - 1))
+    newid = np.full(npts, -1, dtype=np.int64)
+    newid[interior] = np.arange(int(interior.sum()))
+    rows = np.nonzero(interior)[0]
+    off = np.array([(dy * side + dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+    nb = rows[:, None] + off[None, :]
+    keep = present[rows] & interior[nb]
+    row_ptr = np.zeros(len(rows) + 1, dtype=np.int64)
+    row_ptr[1:] = np.cumsum(keep.sum(1))
+    col = newid[nb[keep]].astype(np.int32)
+    vals = S[rows][keep].astype(np.float64)
+    return np.ascontiguousarray(pts[interior]), row_ptr, col, vals
+
+
 def checkerboard_kappa(pts, tris, tiles: int = 16, seed: int = SEED_KAPPA, lo: float = -3.0, hi: float = 3.0):
     """Per-element coefficient from a tiles x tiles checkerboard with tile values 10^U[lo,hi]; an element takes the
     tile of its centroid."""
@@ -265,8 +306,12 @@ def jittered_problem(side: int = 1024, seed: int = SEED_MESH, rhs_seed: int = SE
     tris = local_delaunay_lattice(side, pts) if fast else delaunay(pts)
     kap = checkerboard_kappa(pts, tris, kappa_tiles) if kappa_tiles else None
     name = f"jittered{side}" + (f"_kappa{kappa_tiles}" if kappa_tiles else "") + ("_fast" if fast else "")
-    return _problem(name, pts, tris, kap, rhs_seed=rhs_seed, kind="jittered", side=side, seed=seed,
-                    kappa_tiles=kappa_tiles, fast=fast)
+    meta = dict(kind="jittered", side=side, seed=seed, kappa_tiles=kappa_tiles, fast=fast)
+    if fast:
+        coords, rp, col, val = lattice_p1_assemble(side, pts, tris, kap)
+        return Problem(name, coords, rp, col, val, rhs(len(coords), rhs_seed), UNIT_BOX,
+                       dict(meta, n_points=len(pts), n_tris=len(tris)))
+    return _problem(name, pts, tris, kap, rhs_seed=rhs_seed, **meta)
 
 
 def graded_problem(target_n: int = 4_000_000, seed: int = SEED_MESH, rhs_seed: int = SEED_RHS) -> Problem:

@@ -1,0 +1,117 @@
+"""Parity at the benchmark configurations' full sizes, in the launch configuration bench.py times (default options,
+engine on).
+
+- quasi-uniform 1024x1024 jittered Delaunay (1,044,484 unknowns) and the 16x16 kappa checkerboard on 1416x1416
+  (1,999,396 unknowns): whole hierarchy bit-exact, FP64 solve vs the oracle's solve (iterations +-1, relative error
+  <= 1e-6 at 1e-8), mixed solve error vs the FP64 oracle solve stated and bounded.
+- graded Delaunay, ~4.0M unknowns: whole hierarchy bit-exact, one preconditioner application vs the oracle's, and the
+  solves checked through properties that hold at any size (true FP64 residual, agreement of the two forms).
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1209_5421_amd import meshgen as mg
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def log(msg):
+    print(f"[fullsize] {msg}", flush=True)
+
+
+_cache = {}
+
+
+def problem(name):
+    if name not in _cache:
+        t = time.time()
+        _cache[name] = {"c2": lambda: mg.jittered_problem(1024),
+                        "c4": lambda: mg.jittered_problem(1416, kappa_tiles=16),
+                        "c3": lambda: mg.graded_problem(4_000_000)}[name]()
+        log(f"{name}: n={_cache[name].n} generated in {time.time() - t:.1f}s")
+    return _cache[name]
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0")
+
+
+def hier(prob, **kw):
+    from paper_1209_5421_amd import amg
+    return amg.Hierarchy.from_problem(prob, device="cuda:0", **kw)
+
+
+def assert_hierarchy_equal(g, o):
+    assert g.num_levels == o.num_levels
+    a, b = g.export_level(0), o.export_level(0)
+    np.testing.assert_array_equal(a["agg"], b["agg"])
+    np.testing.assert_array_equal(a["color"], b["color"])
+    for level in range(1, g.num_levels):
+        a, b = g.export_level(level, f32=True), o.export_level(level)
+        for key in ("aj", "ax", "ovf_ptr", "ovf_col", "ovf_val"):
+            np.testing.assert_array_equal(a[key], b[key], err_msg=f"level {level} {key}")
+        np.testing.assert_array_equal(a["ax32"], b["ax"].astype(np.float32))
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["c2", "c4"])
+def test_fullsize_solve_parity(name):
+    prob = problem(name)
+    g = hier(prob)
+    o = oracle.setup_problem(prob)
+    assert_hierarchy_equal(g, o)
+    log(f"{name}: hierarchy bit-exact over {g.num_levels} levels")
+    t = time.time()
+    x_o, io = o.solve(prob.b, tol=1e-8)
+    log(f"{name}: oracle solve {time.time() - t:.1f}s, {io['iters']} iterations")
+    x_g, ig = g.solve(T(prob.b), tol=1e-8)
+    x_g = x_g.cpu().numpy()
+    assert ig["status"] == 0 and ig["relres"] <= 1e-8
+    assert abs(ig["iters"] - io["iters"]) <= 1, (ig, io)
+    err = np.linalg.norm(x_g - x_o) / np.linalg.norm(x_o)
+    assert err <= 1e-6
+    g.set_precision(1)
+    x_m, im = g.solve(T(prob.b), tol=1e-8)
+    x_m = x_m.cpu().numpy()
+    A = H.csr_of(prob)
+    assert im["status"] == 0 and np.linalg.norm(A @ x_m - prob.b) <= 1e-8 * np.linalg.norm(prob.b) * (1 + 1e-6)
+    err_m = np.linalg.norm(x_m - x_o) / np.linalg.norm(x_o)
+    log(f"{name}: fp64 iters {ig['iters']} err {err:.2e}; fp32-precond iters {im['iters']} relres {im['relres']:.2e} "
+        f"err vs fp64 oracle {err_m:.2e}")
+    assert err_m <= 1e-6
+    g.close()
+    o.close()
+
+
+@pytest.mark.timeout(600)
+def test_fullsize_graded():
+    prob = problem("c3")
+    assert 4 ** 10 < prob.n <= 4 ** 11
+    g = hier(prob)
+    o = oracle.setup_problem(prob)
+    assert_hierarchy_equal(g, o)
+    log(f"c3: hierarchy bit-exact over {g.num_levels} levels, level-L overflow {g.level_info(1)['ovf_nnz']}")
+    r = np.random.default_rng(5).standard_normal(prob.n)
+    z_o = o.apply_precond(r)
+    z_g = g.apply_precond(T(r)).cpu().numpy()
+    assert np.linalg.norm(z_g - z_o) <= 1e-10 * np.linalg.norm(z_o)
+    A = H.csr_of(prob)
+    g.set_precision(1)
+    x_m, im = g.solve(T(prob.b), tol=1e-8)
+    g.set_precision(0)
+    x_d, idd = g.solve(T(prob.b), tol=1e-8)
+    x_m, x_d = x_m.cpu().numpy(), x_d.cpu().numpy()
+    bn = np.linalg.norm(prob.b)
+    assert im["status"] == 0 and idd["status"] == 0
+    assert np.linalg.norm(A @ x_m - prob.b) <= 1e-8 * bn * (1 + 1e-6)
+    assert np.linalg.norm(A @ x_d - prob.b) <= 1e-8 * bn * (1 + 1e-6)
+    diff = np.linalg.norm(x_m - x_d) / np.linalg.norm(x_d)
+    log(f"c3: fp64 iters {idd['iters']}, fp32-precond iters {im['iters']}, forms differ by {diff:.2e}")
+    assert diff <= 1e-5
+    g.close()
+    o.close()
