@@ -33,8 +33,10 @@ WORKLOADS = {
     "c3": ("graded Delaunay ~4.0M points, density (r+0.01)^-1.5, P1 Poisson", lambda mg: mg.graded_problem(4_000_000)),
     "c4": ("jittered Delaunay 1416x1416, kappa 10^U[-3,3] 16x16 checkerboard (1,999,396 DOF)",
            lambda mg: mg.jittered_problem(1416, kappa_tiles=16)),
+    "c5": ("serving stream: 512 Poisson-arrival requests, jittered-lattice P1 Poisson systems with DOF log-uniform in "
+           "[1e4, 2e6], 30% repeat right-hand sides on a cached hierarchy", None),
 }
-ROOFLINE_KERNELS = {"spmv64": "k_outer_spmv_dot", "resid_fine32": "k_fine_resid<float>",
+ROOFLINE_KERNELS = {"spmv64": "k_outer_spmv_dot", "resid_fine32": "k_fine_resid_full<float>",
                     "gs_fine32": "k_fine_resid<float> (color phase)"}
 
 
@@ -98,6 +100,10 @@ def main():
     ap.add_argument("--repeats", type=int, default=20, help="resident-hierarchy solves per form for latency")
     ap.add_argument("--roofline-kernel", default="resid_fine32", choices=sorted(ROOFLINE_KERNELS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--requests", type=int, default=512, help="c5: requests in the stream")
+    ap.add_argument("--rate", type=float, default=40.0, help="c5: Poisson arrival rate (requests/s)")
+    ap.add_argument("--dispatchers", type=int, default=4, help="c5: concurrent batch dispatchers")
+    ap.add_argument("--mem-gb", type=float, default=200.0, help="c5: HBM budget for resident hierarchies")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: multi-GPU sharding is not implemented "
@@ -107,6 +113,8 @@ def main():
     from paper_1209_5421_amd import amg, meshgen
     import torch
 
+    if args.workload == "c5":
+        return serve_bench(args)
     desc, make = WORKLOADS[args.workload]
     t = time.time()
     prob = make(meshgen)
@@ -121,13 +129,23 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
 
+    wall = {"setup_call": [], "timing_enable": [], "solve_call": [], "timing_read": [], "free": []}
+
     def step(timing_kernel=None):
+        c0 = time.perf_counter()
         h = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=1, stream=stream)
+        c1 = time.perf_counter()
         if timing_kernel:
             h.timing_enable(timing_kernel)
+        c2 = time.perf_counter()
         _, info = h.solve(b, tol=args.tol, x=x)
+        c3 = time.perf_counter()
         tm = h.timing_read() if timing_kernel else None
+        c4 = time.perf_counter()
         h.close()
+        c5 = time.perf_counter()
+        for key, dt in zip(wall, (c1 - c0, c2 - c1, c3 - c2, c4 - c3, c5 - c4)):
+            wall[key].append(dt * 1e3)
         return info, tm
 
     for w in range(args.warmup):
@@ -136,6 +154,8 @@ def main():
 
     launches, kern_ms, bytes_per_launch = 0, 0.0, 0.0
     infos = []
+    for v in wall.values():
+        v.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -199,11 +219,84 @@ def main():
                    "setup_ms_median": float(np.median([i["setup_ms"] for i in infos])),
                    "solve_ms_median": float(np.median([i["solve_ms"] for i in infos])),
                    "iters": infos[-1]["iters"], "relres": infos[-1]["relres"]},
+        "step_wall_ms": {k: float(np.median(v)) for k, v in wall.items()},
         "solve_resident": forms,
         "engine": engine,
         "err_vs_oracle": err_vs_oracle,
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """The served form: a request stream through the continuous-batching loop, three ways over the same stream
+    (FP32-preconditioned and FP64 served with batching and overlap, and the plain FP64 solver taking one request at a
+    time in arrival order). Meshes and right-hand sides are made resident in HBM before the stream starts; each pass
+    starts with an empty hierarchy cache, so a new mesh pays its setup inside its request's latency."""
+    import types
+    import torch
+    from paper_1209_5421_amd import amg, meshgen as mg
+    from paper_1209_5421_amd.serve import Request, Server, summarize
+
+    dev = torch.device("cuda:0")
+    amg.load()
+    stream = mg.serving_sides(args.requests)
+    t = time.time()
+    meshes = {}
+    for mid, side, _ in stream:
+        if mid not in meshes:
+            c, rp, ci, va = mg.lattice_system(side, seed=100 + mid, device=dev)
+            meshes[mid] = types.SimpleNamespace(coords=c, row_ptr=rp, col=ci, val=va, n=int(c.shape[0]),
+                                                nnz=int(va.shape[0]), box=mg.UNIT_BOX)
+    rng = np.random.default_rng(mg.SEED_STREAM + 1)
+    gaps = rng.exponential(1.0 / args.rate, size=len(stream))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    reqs = [Request(q, mid, meshes[mid], torch.as_tensor(mg.rhs(meshes[mid].n, rs), device=dev), float(arrivals[q]))
+            for q, (mid, _, rs) in enumerate(stream)]
+    torch.cuda.synchronize()
+    dof = {r.rid: r.problem.n for r in reqs}
+    log(f"c5: {len(reqs)} requests over {len(meshes)} meshes ({sum(m.n for m in meshes.values()) / 1e6:.1f}M unique "
+        f"DOF, {sum(dof.values()) / 1e6:.1f}M requested DOF), arrivals over {arrivals[-1]:.1f}s at {args.rate}/s; "
+        f"inputs resident in {time.time() - t:.1f}s")
+
+    # warm-up: a short stream on separate small meshes (kernels loaded, pools primed)
+    warm = []
+    for q in range(8):
+        c, rp, ci, va = mg.lattice_system(60 + 40 * q, seed=50 + q, device=dev)
+        p = types.SimpleNamespace(coords=c, row_ptr=rp, col=ci, val=va, n=int(c.shape[0]), nnz=int(va.shape[0]),
+                                  box=mg.UNIT_BOX)
+        warm.append(Request(q, ("warm", q), p, torch.as_tensor(mg.rhs(p.n, q), device=dev), 0.002 * q))
+    for prec in (1, 0):
+        srv = Server(precision=prec, dispatchers=args.dispatchers, mem_budget=int(args.mem_gb * 2**30))
+        srv.serve(warm)
+        srv.close()
+
+    passes = {"fp32_precond": dict(precision=1, dispatchers=args.dispatchers),
+              "fp64": dict(precision=0, dispatchers=args.dispatchers),
+              "plain_fp64_fifo": dict(precision=0, dispatchers=1, max_batch=1, batch=0)}
+    served = {}
+    for name, kw in passes.items():
+        srv = Server(mem_budget=int(args.mem_gb * 2**30), **kw)
+        res = srv.serve(reqs)
+        m = summarize(res, dof=dof)
+        m.update(setups=srv.setups, evictions=srv.evictions, config=kw)
+        served[name] = m
+        log(f"c5 {name}: {m}")
+        srv.close()
+        torch.cuda.synchronize()
+
+    main_pass = served["fp32_precond"]
+    out = {
+        "metric": METRIC, "value": main_pass["dof_per_s"], "unit": "DOF/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": main_pass["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
+        "config": {"workload": f"c5: {WORKLOADS['c5'][0]}", "requests": len(reqs), "unique_meshes": len(meshes),
+                   "rate_per_s": args.rate, "tol": 1e-8, "dispatchers": args.dispatchers,
+                   "step": "the whole stream served once (FP32 preconditioner, FP64 outer)"},
+        "serving": served,
+        "roofline": None,
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 

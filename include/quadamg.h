@@ -63,6 +63,7 @@ typedef struct {
 typedef struct {
     int32_t iters;       /* outer iterations performed */
     int32_t restarts;    /* restarts from the true residual */
+    int32_t status;      /* amg_status of this system's solve (per system in amg_solve_batch) */
     double relres;       /* true relative residual ||b - A x|| / ||b|| of the returned x (FP64) */
     double setup_ms;     /* wall time of amg_setup */
     double solve_ms;     /* wall time of this solve */
@@ -95,16 +96,18 @@ void amg_free(amg_hierarchy *h);
 /* Change the solve precision of an existing hierarchy (0 = FP64, 1 = FP32 preconditioner / FP64 outer). */
 amg_status amg_set_precision(amg_hierarchy *h, int32_t precision);
 
-/* Change the stream used by later calls on h (hipStream_t, NULL = default stream). */
+/* Change the stream used by later calls on h (hipStream_t, NULL = default stream). Work already queued on the
+ * previous stream is waited for first, so later calls never race with it. */
 amg_status amg_set_stream(amg_hierarchy *h, void *stream);
 
 /* Solve `count` independent systems of one device concurrently (the serving form). h, b, x, tol are host arrays of
  * `count` entries; b[i] and x[i] are device vectors of hierarchy i's size, ready once that hierarchy's stream has
  * drained (the call synchronises each stream first); info is a host array of `count` entries or NULL. The
  * hierarchies must be distinct. Small systems (options.batch, at most 65,536 unknowns) are solved together in one
- * launch with one persistent workgroup per system: outer flexible CG, smoother, K-cycle and convergence test all
- * on the device. Every other system is driven by its own host thread on its own stream, overlapping with the
- * launch. A system's result does not depend on the rest of the batch (bit-identical alone and in any mix); the
+ * launch, on the stream of the first of them, with one persistent workgroup per system: outer flexible CG,
+ * smoother, K-cycle and convergence test all on the device. Every other system is driven by its own host thread on
+ * its hierarchy's stream, overlapping with the launch (systems whose hierarchies share a stream run in turn). The
+ * call returns when every system is done. A system's result does not depend on the rest of the batch (bit-identical alone and in any mix); the
  * whole-solve workgroup and amg_solve differ only by rounding (different reduction trees). Returns the first
  * non-OK status; every system is attempted. */
 amg_status amg_solve_batch(amg_hierarchy *const *h, const double *const *b, double *const *x, const double *tol,

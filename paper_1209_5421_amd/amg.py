@@ -29,8 +29,8 @@ class Options(C.Structure):
 
 
 class Info(C.Structure):
-    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("relres", C.c_double), ("setup_ms", C.c_double),
-                ("solve_ms", C.c_double)]
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32), ("relres", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -193,7 +193,7 @@ class Hierarchy:
         if check and code != OK:
             raise AMGError(code, "amg_solve")
         d = info.as_dict()
-        d["status"] = code
+        d["status"] = code    # also set when the call fails before the solve starts
         return x, d
 
     def apply_precond(self, r, precision=0):

@@ -1,7 +1,11 @@
 // Runtime pieces shared by setup and solve: tracked device allocation, exclusive scans, release, status names.
+#include <mutex>
+
 #include "qa_internal.hpp"
 
 namespace qa {
+
+static std::mutex g_pool_mu;  // guards the per-device pools below (setups may run on several host threads)
 
 // Hierarchy memory comes from a library-owned stream-ordered pool per device that keeps freed blocks cached, so
 // repeated setup / free cycles (a request stream) do not pay hipMalloc / hipFree each time.
@@ -9,6 +13,7 @@ static hipMemPool_t pool_for(int device) {
   static hipMemPool_t pools[64] = {};
   static bool ready[64] = {};
   if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(g_pool_mu);
   if (!ready[device]) {
     hipMemPoolProps props{};
     props.allocType = hipMemAllocationTypePinned;
@@ -45,9 +50,37 @@ amg_status release(amg_hierarchy *h) {
   h->allocs.clear();
   if (h->host_scal) (void)hipHostFree(h->host_scal);
   h->host_scal = nullptr;
-  for (hipEvent_t e : h->timing.ev) (void)hipEventDestroy(e);
-  h->timing.ev.clear();
+  return_events(h->device, h->timing.ev);
   return AMG_OK;
+}
+
+// Timing events are kept in a process-wide pool per device: a hierarchy borrows a block while kernel timing is on
+// and returns it when freed, so a stream of short-lived timed hierarchies creates events only once.
+static std::vector<hipEvent_t> g_free_events[64];
+
+amg_status borrow_events(int device, size_t count, std::vector<hipEvent_t> &out) {
+  if (device < 0 || device >= 64) return AMG_ERR_INVALID;
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  std::vector<hipEvent_t> &fl = g_free_events[device];
+  while (fl.size() < count) {
+    hipEvent_t e = nullptr;
+    QA_HIP(hipEventCreate(&e));
+    fl.push_back(e);
+  }
+  out.assign(fl.end() - static_cast<std::ptrdiff_t>(count), fl.end());
+  fl.resize(fl.size() - count);
+  return AMG_OK;
+}
+
+void return_events(int device, std::vector<hipEvent_t> &ev) {
+  if (ev.empty()) return;
+  if (device >= 0 && device < 64) {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    g_free_events[device].insert(g_free_events[device].end(), ev.begin(), ev.end());
+  } else {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+  ev.clear();
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -192,6 +225,9 @@ amg_status amg_set_precision(amg_hierarchy *h, int32_t precision) {
 
 amg_status amg_set_stream(amg_hierarchy *h, void *stream) {
   if (!h) return AMG_ERR_INVALID;
+  if (static_cast<hipStream_t>(stream) == h->stream) return AMG_OK;
+  QA_HIP(hipSetDevice(h->device));
+  QA_HIP(hipStreamSynchronize(h->stream));
   h->stream = static_cast<hipStream_t>(stream);
   return AMG_OK;
 }

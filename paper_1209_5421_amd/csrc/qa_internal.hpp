@@ -236,6 +236,8 @@ T *dalloc_n(amg_hierarchy *h, int64_t count) {
 amg_status scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s, amg_hierarchy *h);
 amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, amg_hierarchy *h);
 amg_status release(amg_hierarchy *h);
+amg_status borrow_events(int device, size_t count, std::vector<hipEvent_t> &out);
+void return_events(int device, std::vector<hipEvent_t> &ev);
 
 // solve side (qa_solve.hip)
 amg_status alloc_workspaces(amg_hierarchy *h);

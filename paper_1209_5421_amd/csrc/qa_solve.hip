@@ -14,11 +14,14 @@
 //
 // Quadtree levels: values only (9 per row, slot-major so each slot is a coalesced stream), neighbour indices
 // recomputed from the color-major Morton index; overflow couplings from a small CSR.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <thread>
 #include <type_traits>
+
+#include <hip/hip_ext.h>
 
 #include "qa_internal.hpp"
 
@@ -570,21 +573,20 @@ static void finish(amg_hierarchy *h, unsigned nb, const Red &R) {
   if (nb > 1) k_finish<ND><<<1, kBlock, 0, h->stream>>>(nb, R);
 }
 
-// kernel timing: events around launches of the selected family
-struct Timed {
-  amg_hierarchy *h;
-  bool on;
-  Timed(amg_hierarchy *hh, int kind) : h(hh), on(kind >= 0 && hh->timing.kind == kind && hh->timing.used + 2 <= hh->timing.ev.size()) {
-    if (on) (void)hipEventRecord(h->timing.ev[h->timing.used], h->stream);
+// Launch `kern` on the hierarchy's stream with kBlock threads per workgroup. When its family is the one being timed,
+// the launch goes through hipExtLaunchKernelGGL with a start/stop event pair: the runtime stamps both events from
+// the dispatch packet itself, so the interval is the kernel's own execution window (the same span a kernel-trace
+// profiler reports), not the gap between two markers queued around it.
+template <typename F, typename... Args>
+static void launch_timed(amg_hierarchy *h, int kind, F kern, unsigned grid, Args... args) {
+  Timing &t = h->timing;
+  if (kind >= 0 && t.kind == kind && t.used + 2 <= t.ev.size()) {
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, h->stream, t.ev[t.used], t.ev[t.used + 1], 0, args...);
+    t.used += 2;
+  } else {
+    kern<<<grid, kBlock, 0, h->stream>>>(args...);
   }
-  ~Timed() {
-    if (on) {
-      (void)hipEventRecord(h->timing.ev[h->timing.used + 1], h->stream);
-      h->timing.used += 2;
-    }
-  }
-};
-
+}
 
 // ---------------------------------------------------------------------------------------------------------------
 // Persistent small-level engine. Below a size threshold the cycle is latency-bound: level k - j is visited 2^(j+1)
@@ -1359,13 +1361,11 @@ static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u) {
 template <class T>
 static void fine_resid(amg_hierarchy *h, const T *f, const T *x, T *d, int64_t s0, int64_t s1, int kind) {
   if (s1 <= s0) return;
-  Timed tm(h, kind);
+  const unsigned grid = static_cast<unsigned>((s1 - s0 + 3) / 4);
   if (kind == P<T>::kResid)
-    k_fine_resid_full<T><<<static_cast<unsigned>((s1 - s0 + 3) / 4), kBlock, 0, h->stream>>>(
-        sview<T>(h->fine, P<T>::sval(h->fine)), f, x, d, s1 - s0);
+    launch_timed(h, kind, k_fine_resid_full<T>, grid, sview<T>(h->fine, P<T>::sval(h->fine)), f, x, d, s1 - s0);
   else
-    k_fine_resid<T><<<static_cast<unsigned>((s1 - s0 + 3) / 4), kBlock, 0, h->stream>>>(
-        sview<T>(h->fine, P<T>::sval(h->fine)), f, x, d, s0, s1);
+    launch_timed(h, kind, k_fine_resid<T>, grid, sview<T>(h->fine, P<T>::sval(h->fine)), f, x, d, s0, s1);
 }
 
 template <class T>
@@ -1555,10 +1555,8 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
       finish<1>(h, nred(n), red(h, L0, EPI_OUT_BETA));
     }
     k_outer_dir<double><<<nblk(n), kBlock, 0, s>>>(n, osc, h->zp, pprev, p, use_beta ? 1 : 0);
-    {
-      Timed tm(h, KK_SPMV64);
-      k_outer_spmv_dot<<<nsl_blocks, kBlock, 0, s>>>(A64, F.nslices, p, q, h->rp, red(h, L0, EPI_OUT_ALPHA));
-    }
+    launch_timed(h, KK_SPMV64, k_outer_spmv_dot, nsl_blocks, A64, F.nslices, static_cast<const double *>(p), q,
+                 static_cast<const double *>(h->rp), red(h, L0, EPI_OUT_ALPHA));
     finish<2>(h, nsl_blocks, red(h, L0, EPI_OUT_ALPHA));
     k_outer_update<<<nred(n), kBlock, 0, s>>>(n, osc, p, q, h->xp, h->rp, red(h, L0, EPI_STORE, O_RR));
     finish<1>(h, nred(n), red(h, L0, EPI_STORE, O_RR));
@@ -1670,7 +1668,9 @@ using namespace qa;
 extern "C" amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_info *info) {
   if (!h || !b || !x || !(tol > 0.0) || !std::isfinite(tol)) return AMG_ERR_INVALID;
   QA_HIP(hipSetDevice(h->device));
-  return solve_impl(h, b, x, tol, info);
+  const amg_status st = solve_impl(h, b, x, tol, info);
+  if (info) info->status = st;
+  return st;
 }
 
 extern "C" amg_status amg_apply_precond(amg_hierarchy *h, const double *r, double *z, int32_t precision) {
@@ -1731,13 +1731,6 @@ static void fill_wg(amg_hierarchy *h, const double *b, double *x, double tol, do
   Y.E.ops = static_cast<const EngOp *>(h->wg_ops[pi]);
 }
 
-static hipStream_t batch_stream(int device) {
-  static hipStream_t streams[64] = {};
-  if (device < 0 || device >= 64) return nullptr;
-  if (!streams[device]) (void)hipStreamCreateWithFlags(&streams[device], hipStreamNonBlocking);
-  return streams[device];
-}
-
 // one launch, one workgroup per system; info of system i -> out[4 i .. 4 i + 3]
 template <class T>
 static amg_status launch_wg_batch(amg_hierarchy *const *hs, const double *const *b, double *const *x,
@@ -1746,7 +1739,7 @@ static amg_status launch_wg_batch(amg_hierarchy *const *hs, const double *const 
   const int m = static_cast<int>(ids.size());
   const int device = hs[ids[0]]->device;
   QA_HIP(hipSetDevice(device));
-  hipStream_t s = batch_stream(device);
+  hipStream_t s = hs[ids[0]]->stream;
   void *buf = nullptr;
   const size_t sys_bytes = sizeof(WgSys<T>) * m;
   QA_HIP(hipMallocAsync(&buf, sys_bytes + sizeof(double) * 4 * m, s));
@@ -1821,6 +1814,8 @@ extern "C" amg_status amg_solve_batch(amg_hierarchy *const *hs, const double *co
   for (auto &t : threads) t.join();
   amg_status first = launch_st;
   for (int32_t i = 0; i < count; i++) {
+    if (launch_st != AMG_OK && std::find(large.begin(), large.end(), i) == large.end()) st[i] = launch_st;
+    inf[i].status = st[i];
     if (info) info[i] = inf[i];
     if (first == AMG_OK && st[i] != AMG_OK) first = st[i];
   }
@@ -1841,10 +1836,8 @@ extern "C" amg_status amg_kernel_timing_enable(amg_hierarchy *h, const char *nam
   QA_HIP(hipSetDevice(h->device));
   QA_HIP(hipStreamSynchronize(h->stream));
   Timing &t = h->timing;
-  if (kind >= 0 && t.ev.empty()) {
-    t.ev.resize(2 * 4096);
-    for (auto &e : t.ev) QA_HIP(hipEventCreate(&e));
-  }
+  if (kind >= 0 && t.ev.empty()) QA_TRY(borrow_events(h->device, 2 * 4096, t.ev));
+  if (kind < 0) return_events(h->device, t.ev);
   t.kind = kind;
   t.used = 0;
   t.launches = 0;

@@ -82,12 +82,13 @@ def jittered_points(side: int, seed: int = SEED_MESH, jitter: float = 0.3):
     rng = np.random.default_rng(seed)
     h = 1.0 / (side - 1)
     g = np.arange(side, dtype=np.float64) / (side - 1)
-    X, Y = np.meshgrid(g, g)
-    pts = np.stack([X.ravel(), Y.ravel()], 1)
-    bnd = _on_unit_boundary(pts)
-    jit = rng.uniform(-jitter * h, jitter * h, size=pts.shape)
-    pts[~bnd] += jit[~bnd]
-    return pts
+    jit = rng.uniform(-jitter * h, jitter * h, size=(side * side, 2))
+    P = np.empty((side, side, 2))
+    P[..., 0] = g[None, :]
+    P[..., 1] = g[:, None]
+    # lattice points on the boundary (first / last row or column) stay put
+    P[1:-1, 1:-1] += jit.reshape(side, side, 2)[1:-1, 1:-1]
+    return P.reshape(-1, 2)
 
 
 def delaunay(pts: np.ndarray) -> np.ndarray:
@@ -95,21 +96,32 @@ def delaunay(pts: np.ndarray) -> np.ndarray:
     return np.ascontiguousarray(Delaunay(pts).simplices.astype(np.int64))
 
 
+def _lattice_corners(side: int, pts: np.ndarray):
+    """Corner views (a, b, c, d) = (i,j), (i+1,j), (i+1,j+1), (i,j+1) of every lattice square, each (m, m, 2) with
+    m = side - 1, indexed [j, i] (vertex (i, j) is point j * side + i)."""
+    P = pts.reshape(side, side, 2)
+    return P[:-1, :-1], P[:-1, 1:], P[1:, 1:], P[1:, :-1]
+
+
+def lattice_diagonals(side: int, pts: np.ndarray) -> np.ndarray:
+    """Per lattice square ([j, i], (m, m) bool): True if its Delaunay diagonal is a-c, False for b-d. The a-c
+    diagonal is taken unless d lies strictly inside the circumcircle of (a, b, c)."""
+    A, B, C, D = _lattice_corners(side, pts)
+    ad, bd, cd = A - D, B - D, C - D
+    det = ((ad[..., 0] ** 2 + ad[..., 1] ** 2) * (bd[..., 0] * cd[..., 1] - cd[..., 0] * bd[..., 1])
+           - (bd[..., 0] ** 2 + bd[..., 1] ** 2) * (ad[..., 0] * cd[..., 1] - cd[..., 0] * ad[..., 1])
+           + (cd[..., 0] ** 2 + cd[..., 1] ** 2) * (ad[..., 0] * bd[..., 1] - bd[..., 0] * ad[..., 1]))
+    return det <= 0.0
+
+
 def local_delaunay_lattice(side: int, pts: np.ndarray) -> np.ndarray:
-    """Triangulate a jittered lattice square by square, taking in each square the diagonal that passes the
-    empty-circumcircle test (the Delaunay choice whenever all Delaunay edges stay inside lattice squares).
-    Vectorised and fast; used for the serving request stream where Qhull on hundreds of meshes would dominate."""
+    """Triangles of the square-by-square triangulation (``lattice_diagonals``) as an index array: the Delaunay
+    triangulation whenever all Delaunay edges stay inside lattice squares."""
     m = side - 1
+    use_ac = lattice_diagonals(side, pts).ravel()
     i, j = np.meshgrid(np.arange(m), np.arange(m))
     a = (j * side + i).ravel()
     b, c, d = a + 1, a + side + 1, a + side
-    A, B, C, D = pts[a], pts[b], pts[c], pts[d]
-    # d inside circumcircle(a,b,c) (a,b,c counter-clockwise) <=> incircle determinant > 0
-    ad, bd, cd = A - D, B - D, C - D
-    det = ((ad[:, 0] ** 2 + ad[:, 1] ** 2) * (bd[:, 0] * cd[:, 1] - cd[:, 0] * bd[:, 1])
-           - (bd[:, 0] ** 2 + bd[:, 1] ** 2) * (ad[:, 0] * cd[:, 1] - cd[:, 0] * ad[:, 1])
-           + (cd[:, 0] ** 2 + cd[:, 1] ** 2) * (ad[:, 0] * bd[:, 1] - bd[:, 0] * ad[:, 1]))
-    use_ac = det <= 0.0
     t1 = np.where(use_ac[:, None], np.stack([a, b, c], 1), np.stack([a, b, d], 1))
     t2 = np.where(use_ac[:, None], np.stack([a, c, d], 1), np.stack([b, c, d], 1))
     tris = np.concatenate([t1, t2])
@@ -226,45 +238,141 @@ def p1_assemble(pts: np.ndarray, tris: np.ndarray, kappa_t: np.ndarray | None = 
     return (np.ascontiguousarray(pts[keep_v]), row_ptr, cu.astype(np.int32), vsum.astype(np.float64))
 
 
-def lattice_p1_assemble(side: int, pts: np.ndarray, tris: np.ndarray, kappa_t: np.ndarray | None = None):
-    """The same P1 system as ``p1_assemble`` for a triangulation whose edges join lattice neighbours (the
-    square-by-square triangulation of a side x side lattice), in O(N): element entries are accumulated into a 9-slot
-    stencil per vertex with bincount instead of sorting all entry pairs. Boundary vertices are eliminated."""
-    tris = np.asarray(tris, dtype=np.int64)
-    npts = len(pts)
-    s = _signed_area2(pts, tris)
-    if np.any(s <= 0):
-        raise ValueError("lattice triangles must be counter-clockwise and non-degenerate")
-    P = [pts[tris[:, k]] for k in range(3)]
-    E = [P[2] - P[1], P[0] - P[2], P[1] - P[0]]
-    kap = np.ones(len(tris)) if kappa_t is None else np.asarray(kappa_t, dtype=np.float64)
-    scale = kap / (2.0 * s)
-    tx = [tris[:, k] % side for k in range(3)]
-    ty = [tris[:, k] // side for k in range(3)]
-    idx, w = [], []
-    for a in range(3):
-        for b in range(3):
-            dx, dy = tx[b] - tx[a], ty[b] - ty[a]
-            if np.abs(dx).max() > 1 or np.abs(dy).max() > 1:
-                raise ValueError("an edge leaves the lattice neighbourhood")
-            idx.append(tris[:, a] * 9 + (dy + 1) * 3 + (dx + 1))
-            w.append(scale * (E[a][:, 0] * E[b][:, 0] + E[a][:, 1] * E[b][:, 1]))
-    idx = np.concatenate(idx)
-    S = np.bincount(idx, weights=np.concatenate(w), minlength=npts * 9).reshape(npts, 9)
-    present = (np.bincount(idx, minlength=npts * 9) > 0).reshape(npts, 9)
-    vx, vy = np.arange(npts) % side, np.arange(npts) // side
-    interior = ~((vx == 0) | (vy == 0) | (vx == side - 1) | (vy == side - 1))
-    newid = np.full(npts, -1, dtype=np.int64)
-    newid[interior] = np.arange(int(interior.sum()))
-    rows = np.nonzero(interior)[0]
-    off = np.array([(dy * side + dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
-    nb = rows[:, None] + off[None, :]
-    keep = present[rows] & interior[nb]
-    row_ptr = np.zeros(len(rows) + 1, dtype=np.int64)
-    row_ptr[1:] = np.cumsum(keep.sum(1))
-    col = newid[nb[keep]].astype(np.int32)
-    vals = S[rows][keep].astype(np.float64)
-    return np.ascontiguousarray(pts[interior]), row_ptr, col, vals
+# corner offsets (dx, dy) of a, b, c, d inside a lattice square
+_CORNER = ((0, 0), (1, 0), (1, 1), (0, 1))
+
+
+class _NumpyOps:
+    """The few array operations the lattice assembly needs, for numpy arrays."""
+    xp = np
+    i32, i64, boolean = np.int32, np.int64, bool
+
+    @staticmethod
+    def zeros(shape, like, dtype=None):
+        return np.zeros(shape, dtype=like.dtype if dtype is None else dtype)
+
+    @staticmethod
+    def asarray(a, like):
+        return np.asarray(a)
+
+    @staticmethod
+    def cast(a, dtype):
+        return a.astype(dtype)
+
+    @staticmethod
+    def contiguous(a):
+        return np.ascontiguousarray(a)
+
+    @staticmethod
+    def grid(n, like):
+        """(ix, iy) of an n x n grid, indexed [iy, ix]."""
+        g = np.arange(n)
+        return np.broadcast_to(g[None, :], (n, n)), np.broadcast_to(g[:, None], (n, n))
+
+
+class _TorchOps:
+    """The same operations for torch tensors (on any device)."""
+    def __init__(self):
+        import torch
+        self.xp = torch
+        self.i32, self.i64, self.boolean = torch.int32, torch.int64, torch.bool
+
+    def zeros(self, shape, like, dtype=None):
+        return self.xp.zeros(shape, dtype=like.dtype if dtype is None else dtype, device=like.device)
+
+    def asarray(self, a, like):
+        return self.xp.as_tensor(a, device=like.device)
+
+    def cast(self, a, dtype):
+        return a.to(dtype)
+
+    def contiguous(self, a):
+        return a.contiguous()
+
+    def grid(self, n, like):
+        g = self.xp.arange(n, device=like.device)
+        return g[None, :].expand(n, n), g[:, None].expand(n, n)
+
+
+def _ops_for(a):
+    return _NumpyOps if isinstance(a, np.ndarray) else _TorchOps()
+
+
+def lattice_p1_assemble(side: int, pts, use_ac, kappa_tiles: int = 0, kappa_seed: int = SEED_KAPPA):
+    """The P1 system of ``p1_assemble`` for the square-by-square triangulation of a side x side lattice, built square
+    by square: each square's two element matrices are summed into a symmetric 4x4 square matrix, and each vertex
+    gathers its 9-slot stencil from the four squares around it in a fixed order. Deterministic, O(N), strided slices
+    and elementwise work only, so it runs unchanged on numpy arrays or on torch tensors (e.g. on the GPU, to prepare
+    inputs in place). ``kappa_tiles`` > 0 gives each element the checkerboard tile value at its centroid. Boundary
+    vertices are eliminated; returns (coords, row_ptr, col, val) like ``p1_assemble``, as arrays of the input kind."""
+    ops = _ops_for(pts)
+    xp = ops.xp
+    m = side - 1
+    P = pts.reshape(side, side, 2)
+    X, Y = ops.contiguous(P[..., 0]), ops.contiguous(P[..., 1])
+    cx = [X[:-1, :-1], X[:-1, 1:], X[1:, 1:], X[1:, :-1]]   # corner k of square [j, i]
+    cy = [Y[:-1, :-1], Y[:-1, 1:], Y[1:, 1:], Y[1:, :-1]]
+    ac = use_ac
+    # the two triangles of each square: T1 = (a, b, c|d), T2 = (a|b, c, d); corner 0..3 of each per square
+    t1x, t1y = (cx[0], cx[1], xp.where(ac, cx[2], cx[3])), (cy[0], cy[1], xp.where(ac, cy[2], cy[3]))
+    t2x, t2y = (xp.where(ac, cx[0], cx[1]), cx[2], cx[3]), (xp.where(ac, cy[0], cy[1]), cy[2], cy[3])
+    tile_val = None
+    if kappa_tiles:
+        tile_val = ops.asarray(10.0 ** np.random.default_rng(kappa_seed).uniform(-3.0, 3.0,
+                                                                                (kappa_tiles, kappa_tiles)), X)
+    M = {}
+
+    def add(key, v):
+        M[key] = M[key] + v if key in M else v
+
+    for tx, ty, corner_of in ((t1x, t1y, lambda v: (0, 1, 2 if v else 3)), (t2x, t2y, lambda v: (0 if v else 1, 2, 3))):
+        ex = (tx[2] - tx[1], tx[0] - tx[2], tx[1] - tx[0])
+        ey = (ty[2] - ty[1], ty[0] - ty[2], ty[1] - ty[0])
+        s2 = ex[2] * (-ey[1]) - ey[2] * (-ex[1])          # (p1 - p0) x (p2 - p0), twice the signed area
+        if bool((s2 <= 0).any()):
+            raise RuntimeError("lattice triangle inverted or degenerate")
+        scale = 1.0 / (2.0 * s2)
+        if tile_val is not None:
+            ti = ops.cast((tx[0] + tx[1] + tx[2]) / 3.0 * kappa_tiles, ops.i64).clip(0, kappa_tiles - 1)
+            tj = ops.cast((ty[0] + ty[1] + ty[2]) / 3.0 * kappa_tiles, ops.i64).clip(0, kappa_tiles - 1)
+            scale = scale * tile_val[tj, ti]
+        ca, cb = corner_of(True), corner_of(False)      # corner numbers for the a-c and the b-d split
+        for a in range(3):
+            for b in range(a, 3):
+                v = scale * (ex[a] * ex[b] + ey[a] * ey[b])
+                if ca[a] == cb[a] and ca[b] == cb[b]:
+                    add((ca[a], ca[b]), v)
+                else:
+                    zero = ops.zeros(v.shape, v)
+                    add((ca[a], ca[b]), xp.where(ac, v, zero))
+                    add((cb[a], cb[b]), xp.where(ac, zero, v))
+    # structural presence of each square-matrix pair: the 4 sides always, a-c on a-c squares, b-d on the others
+    S = ops.zeros((side, side, 9), X)
+    pres = ops.zeros((side, side, 9), X, dtype=ops.boolean)
+    for (k, k2) in sorted(M):
+        v = M[(k, k2)]
+        diag = {(0, 2): ac, (1, 3): ~ac}.get((k, k2))
+        for (r, c) in ((k, k2), (k2, k)) if k != k2 else ((k, k2),):
+            (x0, y0), (x1, y1) = _CORNER[r], _CORNER[c]
+            slot = (y1 - y0 + 1) * 3 + (x1 - x0 + 1)
+            S[y0:y0 + m, x0:x0 + m, slot] += v
+            if diag is None:
+                pres[y0:y0 + m, x0:x0 + m, slot] = True
+            else:
+                pres[y0:y0 + m, x0:x0 + m, slot] |= diag
+    ni = side - 2
+    dxs = ops.asarray([dx for dy in (-1, 0, 1) for dx in (-1, 0, 1)], X)
+    dys = ops.asarray([dy for dy in (-1, 0, 1) for dx in (-1, 0, 1)], X)
+    ix, iy = ops.grid(ni, X)
+    nx, ny = ix[..., None] + dxs, iy[..., None] + dys
+    keep = pres[1:-1, 1:-1] & (nx >= 0) & (nx < ni) & (ny >= 0) & (ny < ni)
+    counts = keep.reshape(-1, 9).sum(1)
+    row_ptr = ops.zeros(ni * ni + 1, counts, dtype=ops.i64)
+    row_ptr[1:] = xp.cumsum(counts, 0)
+    col = ops.cast((ny * ni + nx)[keep], ops.i32)
+    val = S[1:-1, 1:-1][keep]
+    coords = ops.contiguous(P[1:-1, 1:-1].reshape(-1, 2))
+    return coords, row_ptr, col, val
 
 
 def checkerboard_kappa(pts, tris, tiles: int = 16, seed: int = SEED_KAPPA, lo: float = -3.0, hi: float = 3.0):
@@ -303,15 +411,25 @@ def jittered_problem(side: int = 1024, seed: int = SEED_MESH, rhs_seed: int = SE
     """Poisson (or checkerboard diffusion if kappa_tiles > 0) on a jittered side x side lattice, Delaunay-
     triangulated by Qhull (``fast``: square-by-square empty-circumcircle diagonals)."""
     pts = jittered_points(side, seed)
-    tris = local_delaunay_lattice(side, pts) if fast else delaunay(pts)
-    kap = checkerboard_kappa(pts, tris, kappa_tiles) if kappa_tiles else None
     name = f"jittered{side}" + (f"_kappa{kappa_tiles}" if kappa_tiles else "") + ("_fast" if fast else "")
     meta = dict(kind="jittered", side=side, seed=seed, kappa_tiles=kappa_tiles, fast=fast)
     if fast:
-        coords, rp, col, val = lattice_p1_assemble(side, pts, tris, kap)
+        coords, rp, col, val = lattice_p1_assemble(side, pts, lattice_diagonals(side, pts), kappa_tiles)
         return Problem(name, coords, rp, col, val, rhs(len(coords), rhs_seed), UNIT_BOX,
-                       dict(meta, n_points=len(pts), n_tris=len(tris)))
+                       dict(meta, n_points=len(pts), n_tris=2 * (side - 1) ** 2))
+    tris = delaunay(pts)
+    kap = checkerboard_kappa(pts, tris, kappa_tiles) if kappa_tiles else None
     return _problem(name, pts, tris, kap, rhs_seed=rhs_seed, **meta)
+
+
+def lattice_system(side: int, seed: int = SEED_MESH, kappa_tiles: int = 0, device=None):
+    """(coords, row_ptr, col, val) of the square-by-square jittered-lattice system. With ``device`` (a torch device)
+    the points are drawn on the host as usual and the assembly runs there, leaving the system resident on it."""
+    pts = jittered_points(side, seed)
+    if device is not None:
+        import torch
+        pts = torch.as_tensor(pts, device=device)
+    return lattice_p1_assemble(side, pts, lattice_diagonals(side, pts), kappa_tiles)
 
 
 def graded_problem(target_n: int = 4_000_000, seed: int = SEED_MESH, rhs_seed: int = SEED_RHS) -> Problem:

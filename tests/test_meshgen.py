@@ -1,0 +1,57 @@
+"""Input generators (no GPU): the square-by-square lattice assembly against the generic element-by-element one."""
+import numpy as np
+import pytest
+
+from paper_1209_5421_amd import meshgen as mg
+
+
+@pytest.mark.parametrize("side,kappa,seed", [(12, 0, 0), (40, 0, 0), (40, 16, 2), (30, 16, 1)])
+def test_lattice_assembly_matches_generic_assembly(side, kappa, seed):
+    """Where Qhull's Delaunay triangulation keeps to lattice squares, both give the same pattern and values to
+    rounding."""
+    f = mg.jittered_problem(side, seed=seed, kappa_tiles=kappa, fast=True)
+    g = mg.jittered_problem(side, seed=seed, kappa_tiles=kappa, fast=False)
+    np.testing.assert_array_equal(f.coords, g.coords)
+    np.testing.assert_array_equal(f.row_ptr, g.row_ptr)
+    np.testing.assert_array_equal(f.col, g.col)
+    assert np.abs(f.val - g.val).max() <= 1e-14 * np.abs(g.val).max()
+
+
+def test_lattice_triangulation_is_the_local_delaunay_choice():
+    side = 100
+    pts = mg.jittered_points(side, 0)
+    tris = mg.local_delaunay_lattice(side, pts)
+    qh = mg.delaunay(pts)
+
+    def edges(t):
+        e = np.sort(np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]]), 1)
+        return set(map(tuple, e))
+    diff = edges(qh) - edges(tris)
+    # jitter of 0.3h lets a Delaunay edge leave its square only rarely; every other edge agrees
+    assert len(tris) == len(qh) and len(diff) <= 3
+    for a, b in diff:
+        assert max(abs(a % side - b % side), abs(a // side - b // side)) == 2
+
+
+def test_lattice_system_properties():
+    p = mg.jittered_problem(64, seed=4, fast=True)
+    A = p.scipy()
+    assert abs(A - A.T).max() <= 1e-15 * abs(A).max()
+    assert np.all(A.diagonal() > 0)
+    # Poisson rows away from the boundary sum to zero (constants are in the kernel of the Neumann operator)
+    x = p.coords
+    h = 1.0 / 63
+    inner = np.all((x > 2.5 * h) & (x < 1 - 2.5 * h), axis=1)
+    rs = np.asarray(A.sum(1)).ravel()
+    assert np.abs(rs[inner]).max() <= 1e-13 * A.diagonal().max()
+
+
+def test_torch_backend_is_bitwise_numpy():
+    torch = pytest.importorskip("torch")
+    for side, kappa in ((33, 0), (33, 16)):
+        f = mg.jittered_problem(side, seed=7, kappa_tiles=kappa, fast=True)
+        pts = torch.as_tensor(mg.jittered_points(side, 7))
+        out = mg.lattice_p1_assemble(side, pts, mg.lattice_diagonals(side, pts), kappa)
+        for a, b in zip((f.coords, f.row_ptr, f.col, f.val), out):
+            assert a.dtype == b.numpy().dtype
+            np.testing.assert_array_equal(a, b.numpy())

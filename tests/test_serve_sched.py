@@ -1,0 +1,97 @@
+"""Host-side scheduling of the serving loop (no GPU): HBM admission, LRU eviction of idle hierarchies, one in-flight
+batch per mesh, arrival order kept for requests that must wait."""
+import types
+
+import numpy as np
+import pytest
+
+from paper_1209_5421_amd.serve import Request, Scheduler, summarize, Result
+
+
+def req(rid, mesh, n):
+    return Request(rid, mesh, types.SimpleNamespace(n=n, nnz=7 * n), np.zeros(n))
+
+
+def make(budget=100, max_batch=8):
+    closed = []
+    s = Scheduler(budget, max_batch, estimate=lambda p: p.n, close=closed.append)
+    return s, closed
+
+
+def run_batch(s, batch, size=None):
+    """Pretend the dispatcher set up the new meshes (measured size = estimate unless given) and finished."""
+    for r, hit in batch:
+        if not hit:
+            s.installed(r.mesh_id, f"h{r.mesh_id}", size if size is not None else r.problem.n)
+    for r, _ in batch:
+        s.done(r.mesh_id)
+
+
+def test_one_request_per_mesh_per_batch_and_order_kept():
+    s, _ = make()
+    s.pending.extend([req(0, "a", 10), req(1, "a", 10), req(2, "b", 10), req(3, "a", 10)])
+    b1 = s.take_batch()
+    assert [(r.rid, hit) for r, hit in b1] == [(0, False), (2, False)]
+    assert [r.rid for r in s.pending] == [1, 3]
+    # mesh a is in flight: nothing may start
+    assert s.take_batch() == []
+    run_batch(s, b1)
+    b2 = s.take_batch()
+    assert [(r.rid, hit) for r, hit in b2] == [(1, True)]
+    assert [r.rid for r in s.pending] == [3]
+
+
+def test_admission_and_lru_eviction():
+    s, closed = make(budget=100)
+    s.pending.extend([req(0, "a", 40), req(1, "b", 40)])
+    run_batch(s, s.take_batch())
+    assert s.mem_used == 80
+    s.pending.append(req(2, "a", 40))        # touch a: b becomes least recently used
+    run_batch(s, s.take_batch())
+    s.pending.append(req(3, "c", 40))        # needs 40 more: evict b (idle, LRU), not a
+    b = s.take_batch()
+    assert [(r.rid, hit) for r, hit in b] == [(3, False)]
+    assert closed == ["hb"] and s.evictions == 1 and s.mem_used == 80
+    assert list(s.cache) == ["a", "c"]
+
+
+def test_busy_hierarchies_are_not_evicted_request_waits():
+    s, closed = make(budget=100)
+    s.pending.extend([req(0, "a", 60)])
+    b1 = s.take_batch()
+    run_batch(s, [])                          # a reserved but not finished
+    s.pending.append(req(1, "b", 60))
+    assert s.take_batch() == [] and closed == [] and [r.rid for r in s.pending] == [1]
+    run_batch(s, b1)
+    b2 = s.take_batch()                       # a idle now: evicted for b
+    assert [(r.rid, hit) for r, hit in b2] == [(1, False)] and closed == ["ha"]
+
+
+def test_measured_size_replaces_estimate_and_failed_setup_releases():
+    s, _ = make(budget=100)
+    s.pending.append(req(0, "a", 30))
+    b = s.take_batch()
+    assert s.mem_used == 30
+    run_batch(s, b, size=25)
+    assert s.mem_used == 25
+    s.pending.append(req(1, "b", 30))
+    s.take_batch()
+    s.failed("b")
+    assert s.mem_used == 25 and "b" not in s.cache
+
+
+def test_max_batch_and_oversized_request():
+    s, _ = make(budget=1000, max_batch=2)
+    s.pending.extend([req(i, i, 1) for i in range(5)])
+    assert len(s.take_batch()) == 2 and len(s.pending) == 3
+    s2, _ = make(budget=10)
+    s2.pending.append(req(0, "x", 11))
+    with pytest.raises(MemoryError):
+        s2.take_batch()
+
+
+def test_summarize():
+    res = {i: Result(i, None, 10, 1e-9, 0, 0.1 * i, 0.1 * i, 0.1 * i + 0.01 * (i + 1), i % 2 == 0, 1) for i in range(10)}
+    m = summarize(res)
+    assert m["requests"] == 10 and m["all_converged"] and m["cache_hit_rate"] == 0.5
+    assert abs(m["p50_ms"] - 55.0) < 1e-9
