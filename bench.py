@@ -45,10 +45,18 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the sources the fine-level kernels depend on: their section of qa_solve.hip, the sliced-ELL layout
+    built in qa_setup.hip and the shared header. A counter record taken on other sources is not used."""
+    csrc = os.path.join(ROOT, "paper_1209_5421_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1209_5421_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1209_5421_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    with open(os.path.join(csrc, "qa_solve.hip")) as f:
+        text = f.read()
+    start = text.index("\n// fine level kernels\n")
+    end = text.index("\n// -----", start + 1)
+    h.update(text[start:end].encode())
+    for name in ("qa_setup.hip", "qa_internal.hpp"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -62,6 +70,64 @@ def traffic_from_profiles(kernel, workload):
     if rec.get("source_hash") != kernel_source_hash():
         return None
     return rec.get("bytes_per_launch")
+
+
+COPY_ELEMS = 1 << 28           # calibration copy: 1 GiB of float32 read, 1 GiB written
+COPY_KERNEL_TAG = "neg_kernel"
+
+
+def copy_calibration():
+    """A plain streaming kernel of known size for scaling the FETCH_SIZE / WRITE_SIZE counters: y = -x over 1 GiB."""
+    import torch
+    x = torch.ones(COPY_ELEMS, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+
+
+def _counter_rows(d):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    rows = []
+    for fn in files:
+        with open(fn) as f:
+            rows += list(csv.DictReader(f))
+    return rows
+
+
+def _per_dispatch(rows, counter, tag):
+    vals = {}
+    for r in rows:
+        if r.get("Counter_Name") == counter and tag in r.get("Kernel_Name", ""):
+            key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+            vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    if not vals:
+        raise SystemExit(f"no {counter} rows for kernels matching {tag!r}")
+    return float(np.mean(list(vals.values()))), len(vals)
+
+
+def traffic_record(fetch_dir, write_dir, kernel, workload, commands):
+    """Combine a FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch) into HBM bytes per launch of `kernel`,
+    each counter scaled by what it reads for the calibration copy (expected / measured)."""
+    tag = ROOFLINE_KERNELS[kernel].split(" ")[0]
+    fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
+    f_k, nf = _per_dispatch(fr, "FETCH_SIZE", tag)
+    w_k, nw = _per_dispatch(wr, "WRITE_SIZE", tag)
+    f_c, _ = _per_dispatch(fr, "FETCH_SIZE", COPY_KERNEL_TAG)
+    w_c, _ = _per_dispatch(wr, "WRITE_SIZE", COPY_KERNEL_TAG)
+    expect_kib = COPY_ELEMS * 4 / 1024.0
+    sf, sw = expect_kib / f_c, expect_kib / w_c
+    return {"kernel": kernel, "kernel_name": ROOFLINE_KERNELS[kernel], "workload": workload,
+            "source_hash": kernel_source_hash(),
+            "fetch_kib_per_launch": f_k, "write_kib_per_launch": w_k, "dispatches": [nf, nw],
+            "copy_calibration": {"bytes_read": COPY_ELEMS * 4, "bytes_written": COPY_ELEMS * 4,
+                                 "fetch_kib": f_c, "write_kib": w_c, "fetch_scale": sf, "write_scale": sw},
+            "bytes_per_launch": (f_k * sf + w_k * sw) * 1024.0, "commands": commands}
 
 
 def cpu_baseline(prob, tol):
@@ -104,7 +170,19 @@ def main():
     ap.add_argument("--rate", type=float, default=40.0, help="c5: Poisson arrival rate (requests/s)")
     ap.add_argument("--dispatchers", type=int, default=4, help="c5: concurrent batch dispatchers")
     ap.add_argument("--mem-gb", type=float, default=200.0, help="c5: HBM budget for resident hierarchies")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run the 1 GiB streaming kernel that scales the HBM counters")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/traffic_<kernel>_<workload>.json from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--traffic-commands", nargs="*", default=[], help="commands that produced the counter runs")
     args = ap.parse_args()
+    if args.traffic_from:
+        rec = traffic_record(*args.traffic_from, args.roofline_kernel, args.workload, args.traffic_commands)
+        out = os.path.join(ROOT, "profiles", f"traffic_{args.roofline_kernel}_{args.workload}.json")
+        with open(out, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU: multi-GPU sharding is not implemented "
                                    "(see the design notes); run with --gpus 1"}))
@@ -201,6 +279,9 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                 "traffic": traffic_from_profiles(args.roofline_kernel, args.workload),
                 "launches": launches, "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch}
+
+    if args.copy_calibration:
+        copy_calibration()
 
     cpu = None
     err_vs_oracle = None

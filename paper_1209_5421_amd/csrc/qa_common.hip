@@ -48,7 +48,7 @@ amg_status release(amg_hierarchy *h) {
   for (void *p : h->allocs) (void)(pooled ? hipFreeAsync(p, h->stream) : hipFree(p));
   if (pooled) (void)hipStreamSynchronize(h->stream);
   h->allocs.clear();
-  if (h->host_scal) (void)hipHostFree(h->host_scal);
+  if (h->host_scal) return_pinned_scalars(h->host_scal);
   h->host_scal = nullptr;
   return_events(h->device, h->timing.ev);
   return AMG_OK;
@@ -70,6 +70,30 @@ amg_status borrow_events(int device, size_t count, std::vector<hipEvent_t> &out)
   out.assign(fl.end() - static_cast<std::ptrdiff_t>(count), fl.end());
   fl.resize(fl.size() - count);
   return AMG_OK;
+}
+
+// Pinned host mirrors of the convergence scalars (kScalars doubles each) come from a process-wide free list filled
+// in chunks that are never freed: pinning and unpinning host memory costs milliseconds, far more than a solve's
+// bookkeeping, and a request stream creates and frees hierarchies continually.
+static std::vector<double *> g_free_pinned;
+
+amg_status borrow_pinned_scalars(double **out) {
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  if (g_free_pinned.empty()) {
+    constexpr int kPerChunk = 64;
+    double *chunk = nullptr;
+    QA_HIP(hipHostMalloc(reinterpret_cast<void **>(&chunk), sizeof(double) * kScalars * kPerChunk,
+                         hipHostMallocDefault));
+    for (int i = kPerChunk - 1; i >= 0; i--) g_free_pinned.push_back(chunk + static_cast<size_t>(i) * kScalars);
+  }
+  *out = g_free_pinned.back();
+  g_free_pinned.pop_back();
+  return AMG_OK;
+}
+
+void return_pinned_scalars(double *p) {
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  g_free_pinned.push_back(p);
 }
 
 void return_events(int device, std::vector<hipEvent_t> &ev) {

@@ -77,39 +77,29 @@ __host__ __device__ inline int slot_of(int dx, int dy) {
   }
 }
 
-// Neighbourhood of a level-k cell in color-major numbering. Cell q = c n4 + j (n4 = 4^(k-1)) is child
-// c = (cx, cy) of the level-(k-1) super-cell with Morton index j; each of its 8 neighbours is a child of j or of one of
-// the super-cells around j. Those come from dilated-integer increments of j's x bits (even) and y bits (odd), so a
-// neighbour costs a few integer operations instead of a full Morton re-encoding.
-struct Nbhd {
-  uint32_t jx, jy, xl, xr, yd, yu;
-  bool okl, okr, okd, oku;
-};
-__host__ __device__ inline Nbhd nbhd(uint32_t j, uint32_t n4) {
+// The nine stencil cells of a level-k cell in color-major numbering. Cell q = c n4 + j (n4 = 4^(k-1) = 2^sh) is child
+// c = (cx, cy) of the level-(k-1) super-cell with Morton index j; each neighbour is a child of j or of one of the
+// super-cells around j, found by dilated-integer +-1 on j's x bits (even) and y bits (odd). Only selects, no
+// branches: when the caller passes a color that is uniform over the wavefront (one color phase, or 64 consecutive
+// rows of one color) every condition below is uniform too. A neighbour outside the grid is replaced by q itself
+// (its slot value is 0), so every slot can be loaded unconditionally.
+__host__ __device__ inline void stencil_q(uint32_t q, uint32_t j, int c, int sh, uint32_t (&out)[9]) {
+  const uint32_t n4 = 1u << sh;
   const uint32_t xm = 0x55555555u & (n4 - 1u), ym = 0xAAAAAAAAu & (n4 - 1u);
-  Nbhd N;
-  N.jx = j & xm;
-  N.jy = j & ym;
-  N.okl = N.jx != 0u;
-  N.okr = N.jx != xm;
-  N.okd = N.jy != 0u;
-  N.oku = N.jy != ym;
-  N.xl = (N.jx - 1u) & xm;
-  N.xr = ((N.jx | ~xm) + 1u) & xm;
-  N.yd = (N.jy - 1u) & ym;
-  N.yu = ((N.jy | ~ym) + 1u) & ym;
-  return N;
-}
-// color-major index of the neighbour of child (cx, cy) at offset (dx, dy), or -1 outside the grid
-__host__ __device__ inline int nbr_q(const Nbhd &N, int cx, int cy, int dx, int dy, uint32_t n4) {
-  const int ux = cx + dx, uy = cy + dy;
-  uint32_t sx = N.jx, sy = N.jy;
-  bool ok = true;
-  if (ux < 0) { sx = N.xl; ok = N.okl; }
-  else if (ux > 1) { sx = N.xr; ok = N.okr; }
-  if (uy < 0) { sy = N.yd; ok = ok && N.okd; }
-  else if (uy > 1) { sy = N.yu; ok = ok && N.oku; }
-  return ok ? static_cast<int>(static_cast<uint32_t>((ux & 1) + 2 * (uy & 1)) * n4 + (sx | sy)) : -1;
+  const uint32_t jx = j & xm, jy = j & ym;
+  const uint32_t xl = (jx - 1u) & xm, xr = ((jx | ~xm) + 1u) & xm;
+  const uint32_t yd = (jy - 1u) & ym, yu = ((jy | ~ym) + 1u) & ym;
+  const bool okl = jx != 0u, okr = jx != xm, okd = jy != 0u, oku = jy != ym;
+  const int cx = c & 1, cy = c >> 1;
+#pragma unroll
+  for (int s = 0; s < 9; s++) {
+    const int ux = cx + slot_dx(s), uy = cy + slot_dy(s);
+    const uint32_t sx = ux < 0 ? xl : (ux > 1 ? xr : jx);
+    const uint32_t sy = uy < 0 ? yd : (uy > 1 ? yu : jy);
+    const bool ok = (ux < 0 ? okl : (ux > 1 ? okr : true)) && (uy < 0 ? okd : (uy > 1 ? oku : true));
+    const uint32_t qn = (static_cast<uint32_t>((ux & 1) | ((uy & 1) << 1)) << sh) | sx | sy;
+    out[s] = ok ? qn : q;
+  }
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -221,6 +211,10 @@ struct amg_hierarchy {
   int wg_lds_top[2] = {-1, -1};
   int wg_ainv_lds[2] = {0, 0};
   size_t wg_lds[2] = {0, 0};
+  // B^ of the level above the coarsest as an explicit matrix (column-major, FP64 and FP32), or none
+  int mhat_level = -1;
+  int64_t mhat_n = 0;
+  void *mhat[2] = {nullptr, nullptr};
 };
 
 namespace qa {
@@ -238,9 +232,12 @@ amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStr
 amg_status release(amg_hierarchy *h);
 amg_status borrow_events(int device, size_t count, std::vector<hipEvent_t> &out);
 void return_events(int device, std::vector<hipEvent_t> &ev);
+amg_status borrow_pinned_scalars(double **out);
+void return_pinned_scalars(double *p);
 
 // solve side (qa_solve.hip)
 amg_status alloc_workspaces(amg_hierarchy *h);
+amg_status build_mhat(amg_hierarchy *h);
 amg_status plan_engine(amg_hierarchy *h);
 amg_status plan_wg(amg_hierarchy *h);
 amg_status precond_apply(amg_hierarchy *h, int precision, const double *r_p, double *z_p);

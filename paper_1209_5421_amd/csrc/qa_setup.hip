@@ -847,6 +847,7 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
   QA_TRY(read_flag(h, f));
   if (f & F_NOT_SPD) return AMG_ERR_NOT_SPD;
   QA_TRY(alloc_workspaces(h));
+  QA_TRY(build_mhat(h));
   QA_TRY(plan_engine(h));
   QA_TRY(plan_wg(h));
   QA_HIP(hipStreamSynchronize(s));

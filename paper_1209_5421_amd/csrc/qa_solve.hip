@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <thread>
 #include <type_traits>
 
@@ -135,12 +136,42 @@ struct SellView {
   const T *val;
 };
 
-// d[p] = f[p] - (A x)[p] for the rows of slices [s_begin, s_end); one wavefront per slice
+// Which slices a launch over the colors [c0, c1) gives to which workgroup. Workgroups are dispatched to the eight
+// XCDs round-robin (workgroup b runs on XCD b mod 8) and every XCD has an L2 of its own. In the XCD-aware order,
+// workgroup b takes its slices from chunk b mod 8 of every color in [c0, c1), the same eighth of the Morton range in
+// each color. A row's couplings reach the other colors at nearby Morton positions, so each XCD gathers mostly its
+// own eighth of x instead of all of it. Small passes keep the plain order (one grid-ordered run of slices, which also
+// keeps single-workgroup reductions in one launch).
+struct SliceSched {
+  int64_t cs[5];  // first slice of each color; cs[4] = number of slices
+  int c0, c1;
+  int xcd;        // 1: XCD-aware order (grid = 8 x the largest per-XCD share), 0: slices in grid order
+};
+
+// slice of this thread's wavefront (4 per workgroup), or -1
+__device__ inline int64_t sched_slice(const SliceSched &S) {
+  const int w = static_cast<int>(threadIdx.x >> 6);
+  if (!S.xcd) {
+    const int64_t s = S.cs[S.c0] + static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + w;
+    return s < S.cs[S.c1] ? s : -1;
+  }
+  const int64_t x = blockIdx.x & 7u;
+  int64_t p = static_cast<int64_t>(blockIdx.x >> 3) * (kBlock / 64) + w;
+  for (int c = S.c0; c < S.c1; c++) {
+    const int64_t len = S.cs[c + 1] - S.cs[c];
+    const int64_t b0 = len * x / 8, b1 = len * (x + 1) / 8;
+    if (p < b1 - b0) return S.cs[c] + b0 + p;
+    p -= b1 - b0;
+  }
+  return -1;
+}
+
+// d[p] = f[p] - (A x)[p] for the rows of the scheduled slices; one wavefront per slice
 template <class T>
-__device__ inline void fine_resid_body(const SellView<T> &S, const T *__restrict__ f, const T *__restrict__ x,
-                                       T *__restrict__ d, int64_t s_begin, int64_t s_end) {
-  const int64_t s = s_begin + static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
-  if (s >= s_end) return;
+__device__ inline void fine_resid_body(const SellView<T> &S, const SliceSched &Z, const T *__restrict__ f,
+                                       const T *__restrict__ x, T *__restrict__ d) {
+  const int64_t s = sched_slice(Z);
+  if (s < 0) return;
   const int lane = threadIdx.x & 63;
   const int32_t r0 = S.row0[s], r1 = S.row0[s + 1];
   const int32_t row = r0 + lane;
@@ -157,26 +188,24 @@ __device__ inline void fine_resid_body(const SellView<T> &S, const T *__restrict
 
 // residual of one color's rows (a smoother phase)
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_fine_resid(SellView<T> S, const T *__restrict__ f,
-                                                        const T *__restrict__ x, T *__restrict__ d, int64_t s_begin,
-                                                        int64_t s_end) {
-  fine_resid_body(S, f, x, d, s_begin, s_end);
+__global__ void __launch_bounds__(kBlock) k_fine_resid(SellView<T> S, SliceSched Z, const T *__restrict__ f,
+                                                        const T *__restrict__ x, T *__restrict__ d) {
+  fine_resid_body(S, Z, f, x, d);
 }
 
 // residual of all rows (input of the restriction); a kernel of its own so its launches are timed separately
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_fine_resid_full(SellView<T> S, const T *__restrict__ f,
-                                                             const T *__restrict__ x, T *__restrict__ d,
-                                                             int64_t nslices) {
-  fine_resid_body(S, f, x, d, 0, nslices);
+__global__ void __launch_bounds__(kBlock) k_fine_resid_full(SellView<T> S, SliceSched Z, const T *__restrict__ f,
+                                                             const T *__restrict__ x, T *__restrict__ d) {
+  fine_resid_body(S, Z, f, x, d);
 }
 
-// y = A x over all slices (level hook)
+// y = A x over the scheduled slices (level hook)
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_fine_apply(SellView<T> S, int64_t nslices, const T *__restrict__ x,
+__global__ void __launch_bounds__(kBlock) k_fine_apply(SellView<T> S, SliceSched Z, const T *__restrict__ x,
                                                         T *__restrict__ y) {
-  const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
-  if (s >= nslices) return;
+  const int64_t s = sched_slice(Z);
+  if (s < 0) return;
   const int lane = threadIdx.x & 63;
   const int32_t row = S.row0[s] + lane;
   if (row >= S.row0[s + 1]) return;
@@ -256,24 +285,26 @@ struct QView {
   const T *oval;
 };
 
-// (A x)_q for row q of a quadtree level (slots in order 0..8, then overflow entries). A slot whose neighbour lies
-// outside the grid holds the value 0, so its product is taken with x[q] instead of being branched around: all nine
-// loads are then independent and issue back to back.
+// (A x)_q for row q = c n/4 + j of a quadtree level (slots in order 0..8, then overflow entries). A slot whose
+// neighbour lies outside the grid holds the value 0, so its product is taken with x[q] instead of being branched
+// around: all nine loads are independent and issue back to back.
 template <class T>
-__device__ inline T row_apply(const QView<T> &Q, uint32_t q, const T *__restrict__ x) {
-  const uint32_t n4 = static_cast<uint32_t>(Q.n >> 2);
-  const uint32_t j = q & (n4 - 1u);
-  const int c = static_cast<int>(q >> (2 * Q.k - 2));
-  const Nbhd N = nbhd(j, n4);
+__device__ inline T row_apply(const QView<T> &Q, uint32_t q, int c, const T *__restrict__ x) {
+  const int sh = 2 * Q.k - 2;
+  uint32_t nb[9];
+  stencil_q(q, q & ((1u << sh) - 1u), c, sh, nb);
   T acc = 0;
 #pragma unroll
-  for (int s = 0; s < 9; s++) {
-    const int qn = nbr_q(N, c & 1, c >> 1, slot_dx(s), slot_dy(s), n4);
-    acc += Q.ax[s * Q.n + q] * x[qn >= 0 ? static_cast<uint32_t>(qn) : q];
-  }
+  for (int s = 0; s < 9; s++) acc += Q.ax[s * Q.n + q] * x[nb[s]];
   if (Q.optr)
     for (int32_t e = Q.optr[q]; e < Q.optr[q + 1]; e++) acc += Q.oval[e] * x[Q.ocol[e]];
   return acc;
+}
+
+// color of row q (sh = 2k - 2); uniform over a wavefront of consecutive rows when a color block holds >= 64 rows
+__device__ inline int row_color(uint32_t q, int sh) {
+  const int c = static_cast<int>(q >> sh);
+  return sh >= 6 ? __builtin_amdgcn_readfirstlane(c) : c;
 }
 
 // first phase of a sweep from zero: x = f / diag on color 0, zero elsewhere
@@ -293,7 +324,7 @@ __global__ void __launch_bounds__(kBlock) k_cgs(QView<T> Q, const T *__restrict_
   const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n4) return;
   const uint32_t q = static_cast<uint32_t>(c * n4 + j);
-  const T dl = (f[q] - row_apply(Q, q, x)) / Q.ax[q];
+  const T dl = (f[q] - row_apply(Q, q, c, x)) / Q.ax[q];
   if (delta) delta[q] = dl;
   else x[q] += dl;
 }
@@ -319,7 +350,7 @@ __global__ void __launch_bounds__(kBlock) k_cres_restrict(QView<T> Q, const T *_
   for (int oi = 0; oi < 4; oi++) {
     const int c = order[oi];
     const uint32_t q = static_cast<uint32_t>(c * n4 + M);
-    acc += f[q] - row_apply(Q, q, u);
+    acc += f[q] - row_apply(Q, q, c, u);
   }
   g[q_of_m(static_cast<uint32_t>(M), Q.k - 1)] = acc;
 }
@@ -340,7 +371,7 @@ __global__ void __launch_bounds__(kBlock) k_cspmv_dot(QView<T> Q, const T *__res
   double v[2] = {0.0, 0.0};
   for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < Q.n;
        q += static_cast<int64_t>(gridDim.x) * kBlock) {
-    const T yq = row_apply(Q, static_cast<uint32_t>(q), x);
+    const T yq = row_apply(Q, static_cast<uint32_t>(q), row_color(static_cast<uint32_t>(q), 2 * Q.k - 2), x);
     y[q] = yq;
     const double xq = static_cast<double>(x[q]);
     v[0] += xq * static_cast<double>(yq);
@@ -410,13 +441,13 @@ __global__ void __launch_bounds__(kBlock) k_dense_solve(int n, const double *__r
 // outer flexible CG kernels (FP64, permuted numbering)
 
 // q = A p over all slices, with (p, q) and (r, p); one wavefront per slice
-__global__ void __launch_bounds__(kBlock) k_outer_spmv_dot(SellView<double> S, int64_t nslices,
+__global__ void __launch_bounds__(kBlock) k_outer_spmv_dot(SellView<double> S, SliceSched Z,
                                                             const double *__restrict__ p, double *__restrict__ q,
                                                             const double *__restrict__ r, Red R) {
-  const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t s = sched_slice(Z);
   const int lane = threadIdx.x & 63;
   double v[2] = {0.0, 0.0};
-  if (s < nslices) {
+  if (s >= 0) {
     const int32_t row = S.row0[s] + lane;
     if (row < S.row0[s + 1]) {
       const int64_t off = S.ptr[s];
@@ -435,14 +466,14 @@ __global__ void __launch_bounds__(kBlock) k_outer_spmv_dot(SellView<double> S, i
 }
 
 // t = b - A x with (t, t)
-__global__ void __launch_bounds__(kBlock) k_outer_true_resid(SellView<double> S, int64_t nslices,
+__global__ void __launch_bounds__(kBlock) k_outer_true_resid(SellView<double> S, SliceSched Z,
                                                               const double *__restrict__ b,
                                                               const double *__restrict__ x, double *__restrict__ t,
                                                               Red R) {
-  const int64_t s = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t s = sched_slice(Z);
   const int lane = threadIdx.x & 63;
   double v[1] = {0.0};
-  if (s < nslices) {
+  if (s >= 0) {
     const int32_t row = S.row0[s] + lane;
     if (row < S.row0[s + 1]) {
       const int64_t off = S.ptr[s];
@@ -573,6 +604,31 @@ static void finish(amg_hierarchy *h, unsigned nb, const Red &R) {
   if (nb > 1) k_finish<ND><<<1, kBlock, 0, h->stream>>>(nb, R);
 }
 
+// Schedule of a fine-level pass over colors [c0, c1); the XCD-aware order from 256 slices (16,384 rows) up.
+static SliceSched slice_sched(const FineLevel &F, int c0, int c1) {
+  SliceSched Z{};
+  for (int c = 0; c < 5; c++) Z.cs[c] = F.color_slice[c];
+  Z.c0 = c0;
+  Z.c1 = c1;
+  Z.xcd = (Z.cs[c1] - Z.cs[c0]) >= 256 ? 1 : 0;
+  return Z;
+}
+
+// workgroups of a scheduled pass (4 slices each)
+static unsigned sched_grid(const SliceSched &Z) {
+  if (!Z.xcd) return static_cast<unsigned>((Z.cs[Z.c1] - Z.cs[Z.c0] + 3) / 4);
+  int64_t most = 0;
+  for (int64_t x = 0; x < 8; x++) {
+    int64_t mine = 0;
+    for (int c = Z.c0; c < Z.c1; c++) {
+      const int64_t len = Z.cs[c + 1] - Z.cs[c];
+      mine += len * (x + 1) / 8 - len * x / 8;
+    }
+    most = std::max(most, mine);
+  }
+  return static_cast<unsigned>(8 * ((most + 3) / 4));
+}
+
 // Launch `kern` on the hierarchy's stream with kBlock threads per workgroup. When its family is the one being timed,
 // the launch goes through hipExtLaunchKernelGGL with a start/stop event pair: the runtime stamps both events from
 // the dispatch packet itself, so the interval is the kernel's own execution window (the same span a kernel-trace
@@ -604,8 +660,10 @@ constexpr int kEngMaxOps = 512;  // step list staged in LDS (20 bytes each)
 
 enum EngOpType : int32_t {
   EO_GS_FIRST = 0, EO_GS, EO_RES_RESTRICT, EO_DENSE, EO_PROLONG, EO_SPMV_DOT0, EO_UPDATE1, EO_DOT_BETA,
-  EO_AXPY_BETA, EO_SPMV_DOT1, EO_UPDATE2
+  EO_AXPY_BETA, EO_SPMV_DOT1, EO_UPDATE2, EO_BHAT_M
 };
+constexpr int kMhatMaxRows = 256;   // B^ kept as a matrix when the level above the coarsest has at most this many rows
+constexpr int kMhatPart = 1024;     // LDS partial sums of the matrix-vector product (T units)
 enum EngVec : int32_t { EV_G = 0, EV_E, EV_R, EV_P0, EV_Q0, EV_P1, EV_Q1, EV_D, EV_COUNT };
 
 struct EngOp {
@@ -632,6 +690,10 @@ struct EngPlan {
   const double *ainv;
   const T *g_in;
   T *e_out;
+  int64_t batch_stride;        // workgroup b reads g_in + b * stride, writes e_out + b * stride (0: one system)
+  const T *mhat;               // B^ of the level above the coarsest, column-major (EO_BHAT_M), or null
+  int mhat_parts;              // threads per row of its product
+  int mpart_off;               // LDS offset (T units) of the partial sums
   EngLevel<T> lv[kEngMaxLevels];
 };
 
@@ -656,17 +718,13 @@ __device__ inline void eng_reduce(double (&v)[ND], double *red) {
 
 template <class T>
 __device__ inline T eng_row(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
-                            uint32_t q, const T *x) {
-  const uint32_t n4 = static_cast<uint32_t>(n >> 2);
-  const uint32_t j = q & (n4 - 1u);
-  const int c = static_cast<int>(q >> (2 * k - 2));
-  const Nbhd N = nbhd(j, n4);
+                            uint32_t q, int c, const T *x) {
+  const int sh = 2 * k - 2;
+  uint32_t nb[9];
+  stencil_q(q, q & ((1u << sh) - 1u), c, sh, nb);
   T acc = 0;
 #pragma unroll
-  for (int s = 0; s < 9; s++) {
-    const int qn = nbr_q(N, c & 1, c >> 1, slot_dx(s), slot_dy(s), n4);
-    acc += ax[s * n + q] * x[qn >= 0 ? static_cast<uint32_t>(qn) : q];  // absent slots hold 0
-  }
+  for (int s = 0; s < 9; s++) acc += ax[s * n + q] * x[nb[s]];  // absent slots hold 0
   if (optr)
     for (int32_t e = optr[q]; e < optr[q + 1]; e++) acc += oval[e] * x[ocol[e]];
   return acc;
@@ -710,10 +768,10 @@ __device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const En
       const T *f = M.vec(op.f);
       T *u = M.vec(op.u);
       T *d = M.vec(EV_D);
-      const int c = op.color;
+      const int c = __builtin_amdgcn_readfirstlane(op.color);
       for (int j = tid; j < n4; j += kStride) {
         const uint32_t q = static_cast<uint32_t>(c * n4 + j);
-        const T dl = (f[q] - eng_row(k, n, ax, L.optr, L.ocol, L.oval, q, u)) / ax[q];
+        const T dl = (f[q] - eng_row(k, n, ax, L.optr, L.ocol, L.oval, q, c, u)) / ax[q];
         if (L.same_color) d[q] = dl;
         else u[q] += dl;
       }
@@ -734,7 +792,7 @@ __device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const En
 #pragma unroll
         for (int o = 0; o < 4; o++) {
           const uint32_t q = static_cast<uint32_t>(order[o] * n4 + m);
-          r[o] = f[q] - eng_row(k, n, ax, L.optr, L.ocol, L.oval, q, u);
+          r[o] = f[q] - eng_row(k, n, ax, L.optr, L.ocol, L.oval, q, order[o], u);
         }
         T acc = 0;
 #pragma unroll
@@ -759,6 +817,31 @@ __device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const En
       }
       break;
     }
+    case EO_BHAT_M: {
+      // u = B^ f with B^ precomputed as a matrix (column-major, global memory): mhat_parts threads per row, each
+      // summing a contiguous run of columns; the partial sums are added in a fixed order
+      const T *f = M.vec(op.f);
+      T *u = M.vec(op.u);
+      T *part = S + P.mpart_off;
+      const int parts = P.mhat_parts;
+      const int cols = n / parts;
+      if (tid < n * parts) {
+        const int r = tid & (n - 1);
+        const int b = tid / n;
+        const T *mc = P.mhat + static_cast<size_t>(b) * cols * n + r;
+        const T *fb = f + b * cols;
+        T acc = 0;
+        for (int i = 0; i < cols; i++) acc += mc[static_cast<size_t>(i) * n] * fb[i];
+        part[b * n + r] = acc;
+      }
+      __syncthreads();
+      for (int r = tid; r < n; r += kStride) {
+        T acc = part[r];
+        for (int b = 1; b < parts; b++) acc += part[b * n + r];
+        u[r] = acc;
+      }
+      break;
+    }
     case EO_PROLONG: {
       T *u = M.vec(op.u);
       const EngMem<T, LDS_CHILD> MC{S, LV[l + 1]};
@@ -775,7 +858,8 @@ __device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const En
       const T *w = M.vec(first ? EV_G : EV_R);
       double v[2] = {0.0, 0.0};
       for (int q = tid; q < n; q += kStride) {
-        const T yq = eng_row(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q), x);
+        const T yq = eng_row(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q),
+                             row_color(static_cast<uint32_t>(q), 2 * k - 2), x);
         y[q] = yq;
         v[0] += static_cast<double>(x[q]) * static_cast<double>(yq);
         v[1] += static_cast<double>(w[q]) * static_cast<double>(x[q]);
@@ -871,23 +955,30 @@ __global__ void __launch_bounds__(kEngThreads) k_engine(EngPlan<T> P) {
   const int tid = threadIdx.x;
   T *S = reinterpret_cast<T *>(smem + P.t_base);
   double *ainv_lds = reinterpret_cast<double *>(smem);
+  const T *g_in = P.g_in + blockIdx.x * P.batch_stride;
+  T *e_out = P.e_out + blockIdx.x * P.batch_stride;
   eng_stage(P, ops, LV, S, ainv_lds);
   if (P.lv[0].in_lds)
-    for (int i = tid; i < P.lv[0].n; i += kEngThreads) S[P.lv[0].vec_off + EV_G * P.lv[0].n + i] = P.g_in[i];
+    for (int i = tid; i < P.lv[0].n; i += kEngThreads) S[P.lv[0].vec_off + EV_G * P.lv[0].n + i] = g_in[i];
   __syncthreads();
   eng_run(P, ops, LV, S, P.ainv_in_lds ? ainv_lds : P.ainv, sc, red);
   if (P.lv[0].in_lds)
-    for (int i = tid; i < P.lv[0].n; i += kEngThreads) P.e_out[i] = S[P.lv[0].vec_off + EV_E * P.lv[0].n + i];
+    for (int i = tid; i < P.lv[0].n; i += kEngThreads) e_out[i] = S[P.lv[0].vec_off + EV_E * P.lv[0].n + i];
 }
 
 // Step list of B~ at engine level l; mirrors btilde / bhat_coarse below.
 struct EmitCtx {
   int nl, sweeps, inner;
+  int mhat;  // B^ of the level above the coarsest is one EO_BHAT_M step
 };
 
 static void emit_btilde(std::vector<EngOp> &ops, const EmitCtx &E, int l);
 
 static void emit_bhat(std::vector<EngOp> &ops, const EmitCtx &E, int l, int f, int u) {
+  if (E.mhat && l + 1 == E.nl - 1) {
+    ops.push_back({EO_BHAT_M, l, 0, f, u});
+    return;
+  }
   for (int sw = 0; sw < E.sweeps; sw++)
     for (int c = 0; c < 4; c++) ops.push_back({(sw == 0 && c == 0) ? EO_GS_FIRST : EO_GS, l, c, f, u});
   ops.push_back({EO_RES_RESTRICT, l, 0, f, u});
@@ -910,6 +1001,32 @@ static void emit_btilde(std::vector<EngOp> &ops, const EmitCtx &E, int l) {
   ops.push_back({EO_UPDATE2, l, 0, 0, 0});
 }
 
+template <class T> struct WgSys;
+template <class T> __global__ void k_solve_wg(const WgSys<T> *systems);
+
+// Dynamic LDS limit of the persistent kernels: set once per device, to all the device allows beside their static
+// arrays, so that hierarchies set up concurrently on several host threads never lower it under one another's launch.
+static amg_status engine_lds_limits(amg_hierarchy *h) {
+  static std::once_flag once[64];
+  if (h->device < 0 || h->device >= 64) return AMG_ERR_DEVICE;
+  amg_status st = AMG_OK;
+  std::call_once(once[h->device], [&]() {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device) != hipSuccess) {
+      st = AMG_ERR_DEVICE;
+      return;
+    }
+    const int dyn = lds - static_cast<int>(sizeof(EngOp) * kEngMaxOps + 4096);
+    const void *kernels[4] = {reinterpret_cast<const void *>(k_engine<double>),
+                              reinterpret_cast<const void *>(k_engine<float>),
+                              reinterpret_cast<const void *>(k_solve_wg<double>),
+                              reinterpret_cast<const void *>(k_solve_wg<float>)};
+    for (const void *k : kernels)
+      if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, dyn) != hipSuccess) st = AMG_ERR_DEVICE;
+  });
+  return st;
+}
+
 amg_status plan_engine(amg_hierarchy *h) {
   h->engine_top[0] = h->engine_top[1] = -1;
   if (h->nlev < 3) return AMG_OK;  // nothing between the fine level and the coarsest
@@ -919,10 +1036,12 @@ amg_status plan_engine(amg_hierarchy *h) {
   // room for the static shared arrays (step list, pointer tables, scalars)
   const size_t stat = sizeof(EngOp) * kEngMaxOps + 4096;
   const size_t budget = h->lds_max > stat ? h->lds_max - stat : 0;
+  const int mhat = h->mhat_level >= 0 ? 1 : 0;
   for (int pi = 0; pi < 2; pi++) {
     const size_t ts = pi == 0 ? sizeof(double) : sizeof(float);
+    const size_t extra = mhat ? static_cast<size_t>(kMhatPart) * ts : 0;  // partial sums of EO_BHAT_M
     // deepest levels first: the largest set of LDS-resident levels (coarsest included)
-    size_t bytes = static_cast<size_t>(h->nc) * 2 * ts;
+    size_t bytes = static_cast<size_t>(h->nc) * 2 * ts + extra;
     int lds_top = h->nlev - 1;
     while (lds_top - 1 >= 1 && bytes + static_cast<size_t>(h->lev[lds_top - 1].n) * 17 * ts <= budget) {
       lds_top--;
@@ -935,16 +1054,18 @@ amg_status plan_engine(amg_hierarchy *h) {
     for (;; top++) {
       if (top >= h->nlev - 1) break;
       ops.clear();
-      if (h->nlev - top <= kEngMaxLevels) emit_btilde(ops, EmitCtx{h->nlev - top, h->opt.sweeps, h->opt.inner_iters}, 0);
+      if (h->nlev - top <= kEngMaxLevels)
+        emit_btilde(ops, EmitCtx{h->nlev - top, h->opt.sweeps, h->opt.inner_iters, mhat}, 0);
       if (!ops.empty() && ops.size() <= static_cast<size_t>(kEngMaxOps)) break;
     }
     if (top >= h->nlev - 1) continue;  // no engine for this precision
     if (lds_top < top) {               // LDS holds exactly the engine's levels from top down
       lds_top = top;
-      bytes = static_cast<size_t>(h->nc) * 2 * ts;
+      bytes = static_cast<size_t>(h->nc) * 2 * ts + extra;
       for (int l = top; l < h->nlev - 1; l++) bytes += static_cast<size_t>(h->lev[l].n) * 17 * ts;
     }
-    const bool ainv = bytes + static_cast<size_t>(h->nc * h->nc) * 8 <= budget;
+    // the coarsest inverse is staged into LDS only when the step list uses it (no B^ matrix)
+    const bool ainv = !mhat && bytes + static_cast<size_t>(h->nc * h->nc) * 8 <= budget;
     EngOp *d = static_cast<EngOp *>(dalloc(h, sizeof(EngOp) * ops.size()));
     if (!d) return AMG_ERR_NOMEM;
     QA_HIP(hipMemcpyAsync(d, ops.data(), sizeof(EngOp) * ops.size(), hipMemcpyHostToDevice, h->stream));
@@ -956,18 +1077,75 @@ amg_status plan_engine(amg_hierarchy *h) {
     h->engine_ops[pi] = d;
     h->engine_nops[pi] = static_cast<int>(ops.size());
   }
-  if (h->engine_lds[0] > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_engine<double>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(h->engine_lds[0]));
-  if (h->engine_lds[1] > 65536)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_engine<float>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(h->engine_lds[1]));
+  return engine_lds_limits(h);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_identity(int64_t n, T *__restrict__ a) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n * n) a[i] = (i / n == i % n) ? T(1) : T(0);
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_round(int64_t n, const double *__restrict__ a, T *__restrict__ b) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = static_cast<T>(a[i]);
+}
+
+template <class T>
+static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, EngPlan<T> &E);
+
+// B^ on the level just above the coarsest is linear (smoothing, restriction, the exact coarsest solve, prolongation,
+// smoothing: Algorithm 2.2 with no nonlinear inner iteration below it). When that level is small it is evaluated
+// once here, column by column, by running its own step list on the unit vectors (one workgroup per column, FP64),
+// and kept as an n x n matrix; the cycle then applies it as one matrix-vector product instead of ten dependent
+// steps. The FP32 copy is the rounded FP64 matrix.
+amg_status build_mhat(amg_hierarchy *h) {
+  h->mhat_level = -1;
+  if (h->nlev < 3) return AMG_OK;
+  const int l = h->nlev - 2;
+  const int64_t n = h->lev[l].n;
+  if (n > kMhatMaxRows) return AMG_OK;
+  hipStream_t s = h->stream;
+  int lds = 0;
+  QA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+  const size_t bytes = static_cast<size_t>(n) * 17 * sizeof(double) + static_cast<size_t>(h->nc) * 2 * sizeof(double) +
+                       static_cast<size_t>(h->nc * h->nc) * 8;
+  const size_t stat = sizeof(EngOp) * kEngMaxOps + 4096;
+  if (bytes + stat > static_cast<size_t>(lds)) return AMG_OK;
+  std::vector<EngOp> ops;
+  emit_bhat(ops, EmitCtx{2, h->opt.sweeps, h->opt.inner_iters, 0}, 0, EV_G, EV_E);
+  if (ops.size() > static_cast<size_t>(kEngMaxOps)) return AMG_OK;
+  double *ident = dalloc_n<double>(h, n * n);
+  double *m64 = dalloc_n<double>(h, n * n);
+  float *m32 = dalloc_n<float>(h, n * n);
+  EngOp *d = static_cast<EngOp *>(dalloc(h, sizeof(EngOp) * ops.size()));
+  if (!ident || !m64 || !m32 || !d) return AMG_ERR_NOMEM;
+  QA_HIP(hipMemcpyAsync(d, ops.data(), sizeof(EngOp) * ops.size(), hipMemcpyHostToDevice, s));
+  k_identity<double><<<nblk(n * n), kBlock, 0, s>>>(n, ident);
+  EngPlan<double> E{};
+  fill_engine(h, l, l, 1, E);  // both levels and the coarsest inverse in LDS
+  E.nops = static_cast<int>(ops.size());
+  E.ops = d;
+  E.g_in = ident;
+  E.e_out = m64;
+  E.batch_stride = n;
+  QA_TRY(engine_lds_limits(h));
+  k_engine<double><<<static_cast<unsigned>(n), kEngThreads, bytes, s>>>(E);
+  k_round<float><<<nblk(n * n), kBlock, 0, s>>>(n * n, m64, m32);
+  QA_LAUNCH_CHECK();
+  QA_HIP(hipStreamSynchronize(s));
+  h->mhat_level = l;
+  h->mhat_n = n;
+  h->mhat[0] = m64;
+  h->mhat[1] = m32;
   return AMG_OK;
 }
 
 // Level table of an engine whose top is hierarchy level `top`, levels from `lds_top` down LDS-resident.
 template <class T>
 static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, EngPlan<T> &E) {
+  const int pi = std::is_same<T, float>::value ? 1 : 0;
   E.nlev = h->nlev - top;
   E.nc = static_cast<int>(h->nc);
   E.ainv_in_lds = ainv_lds;
@@ -1001,6 +1179,14 @@ static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, En
       L.vec[EV_G] = W[l].g; L.vec[EV_E] = W[l].e; L.vec[EV_R] = W[l].r; L.vec[EV_P0] = W[l].p0;
       L.vec[EV_Q0] = W[l].q0; L.vec[EV_P1] = W[l].p1; L.vec[EV_Q1] = W[l].q1; L.vec[EV_D] = W[l].d;
     }
+  }
+  E.batch_stride = 0;
+  E.mhat = nullptr;
+  if (h->mhat_level >= top) {
+    const int n = static_cast<int>(h->mhat_n);
+    E.mhat = static_cast<const T *>(h->mhat[pi]);
+    E.mhat_parts = std::min(std::min(kEngThreads / n, 16), n);
+    E.mpart_off = off;
   }
 }
 
@@ -1282,17 +1468,19 @@ amg_status plan_wg(amg_hierarchy *h) {
   const size_t stat = sizeof(EngOp) * kEngMaxOps + 4096;
   const size_t budget = h->lds_max > stat ? h->lds_max - stat : 0;
   std::vector<EngOp> ops;
-  emit_btilde(ops, EmitCtx{h->nlev - 1, h->opt.sweeps, h->opt.inner_iters}, 0);
+  const int mhat = h->mhat_level >= 0 ? 1 : 0;
+  emit_btilde(ops, EmitCtx{h->nlev - 1, h->opt.sweeps, h->opt.inner_iters, mhat}, 0);
   if (ops.size() > static_cast<size_t>(kEngMaxOps) || h->nlev - 1 > kEngMaxLevels) return AMG_OK;
   for (int pi = 0; pi < 2; pi++) {
     const size_t ts = pi == 0 ? sizeof(double) : sizeof(float);
-    size_t bytes = static_cast<size_t>(h->nc) * 2 * ts;
+    const size_t extra = mhat ? static_cast<size_t>(kMhatPart) * ts : 0;
+    size_t bytes = static_cast<size_t>(h->nc) * 2 * ts + extra;
     int lds_top = h->nlev - 1;
     while (lds_top - 1 >= 1 && bytes + static_cast<size_t>(h->lev[lds_top - 1].n) * 17 * ts <= budget) {
       lds_top--;
       bytes += static_cast<size_t>(h->lev[lds_top].n) * 17 * ts;
     }
-    const bool ainv = bytes + static_cast<size_t>(h->nc * h->nc) * 8 <= budget;
+    const bool ainv = !mhat && bytes + static_cast<size_t>(h->nc * h->nc) * 8 <= budget;
     EngOp *d = static_cast<EngOp *>(dalloc(h, sizeof(EngOp) * ops.size()));
     if (!d) return AMG_ERR_NOMEM;
     QA_HIP(hipMemcpyAsync(d, ops.data(), sizeof(EngOp) * ops.size(), hipMemcpyHostToDevice, h->stream));
@@ -1303,12 +1491,7 @@ amg_status plan_wg(amg_hierarchy *h) {
     h->wg_ainv_lds[pi] = ainv ? 1 : 0;
     h->wg_lds[pi] = bytes + (ainv ? static_cast<size_t>(h->nc * h->nc) * 8 : 0);
   }
-  for (size_t b : {h->wg_lds[0], h->wg_lds[1]}) (void)b;
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_solve_wg<double>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(budget));
-  (void)hipFuncSetAttribute(reinterpret_cast<const void *>(k_solve_wg<float>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(budget));
-  return AMG_OK;
+  return engine_lds_limits(h);
 }
 
 template <class T> static void btilde(amg_hierarchy *h, int l, const T *g, T *e);
@@ -1359,13 +1542,14 @@ static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u) {
 }
 
 template <class T>
-static void fine_resid(amg_hierarchy *h, const T *f, const T *x, T *d, int64_t s0, int64_t s1, int kind) {
-  if (s1 <= s0) return;
-  const unsigned grid = static_cast<unsigned>((s1 - s0 + 3) / 4);
+static void fine_resid(amg_hierarchy *h, const T *f, const T *x, T *d, int c0, int c1, int kind) {
+  const SliceSched Z = slice_sched(h->fine, c0, c1);
+  const unsigned grid = sched_grid(Z);
+  if (grid == 0) return;
   if (kind == P<T>::kResid)
-    launch_timed(h, kind, k_fine_resid_full<T>, grid, sview<T>(h->fine, P<T>::sval(h->fine)), f, x, d, s1 - s0);
+    launch_timed(h, kind, k_fine_resid_full<T>, grid, sview<T>(h->fine, P<T>::sval(h->fine)), Z, f, x, d);
   else
-    launch_timed(h, kind, k_fine_resid<T>, grid, sview<T>(h->fine, P<T>::sval(h->fine)), f, x, d, s0, s1);
+    launch_timed(h, kind, k_fine_resid<T>, grid, sview<T>(h->fine, P<T>::sval(h->fine)), Z, f, x, d);
 }
 
 template <class T>
@@ -1374,7 +1558,7 @@ static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd
   const int64_t nL4 = static_cast<int64_t>(1) << (2 * h->L - 2);
   const T *src = d;
   if (from_f) src = f;
-  else fine_resid<T>(h, f, u, d, F.color_slice[c], F.color_slice[c + 1], P<T>::kGs);
+  else fine_resid<T>(h, f, u, d, c, c + 1, P<T>::kGs);
   const int64_t q0 = c * nL4, q1 = (c + 1) * nL4;
   if (fwd)
     k_fine_subst<T, true><<<nblk(nL4), kBlock, 0, h->stream>>>(F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F),
@@ -1395,7 +1579,7 @@ static void bhat_fine(amg_hierarchy *h, const T *f, T *u) {
   for (int sw = 0; sw < sweeps; sw++)
     for (int c = 0; c < 4; c++) fine_phase<T>(h, f, u, w.d, c, true, sw == 0 && c == 0);
   LevelWork<T> &wc = P<T>::W(h)[1];
-  fine_resid<T>(h, f, u, w.d, 0, F.nslices, P<T>::kResid);
+  fine_resid<T>(h, f, u, w.d, 0, 4, P<T>::kResid);
   const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
   k_fine_restrict<T><<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, w.d, wc.g);
   coarse_solve_or_cycle<T>(h, 1);
@@ -1488,11 +1672,12 @@ amg_status alloc_workspaces(amg_hierarchy *h) {
     if (!*v) return AMG_ERR_NOMEM;
   }
   h->scal = dalloc_n<double>(h, (h->nlev + 1) * kScalars);
-  h->partials_cap = std::max<int64_t>(kRedBlocksMax, (h->fine.nslices + 3) / 4 + 1) * 2;
+  // two values per workgroup of the largest reduction launch (a scheduled pass over all slices)
+  h->partials_cap = std::max<int64_t>(kRedBlocksMax, sched_grid(slice_sched(h->fine, 0, 4)) + 1) * 2;
   h->partials = dalloc_n<double>(h, h->partials_cap);
   if (!h->scal || !h->partials) return AMG_ERR_NOMEM;
   QA_HIP(hipMemsetAsync(h->scal, 0, sizeof(double) * (h->nlev + 1) * kScalars, h->stream));
-  QA_HIP(hipHostMalloc(reinterpret_cast<void **>(&h->host_scal), sizeof(double) * kScalars, hipHostMallocDefault));
+  QA_TRY(borrow_pinned_scalars(&h->host_scal));
   return AMG_OK;
 }
 
@@ -1522,7 +1707,8 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
   hipStream_t s = h->stream;
   const int L0 = h->nlev;  // outer scalar block
   const double *osc = h->scal + static_cast<size_t>(L0) * kScalars;
-  const unsigned nsl_blocks = static_cast<unsigned>((F.nslices + 3) / 4);
+  const SliceSched Zall = slice_sched(F, 0, 4);
+  const unsigned nsl_blocks = sched_grid(Zall);
   SellView<double> A64 = sview<double>(F, F.s_val64);
   amg_info inf{};
   inf.setup_ms = h->setup_ms;
@@ -1555,7 +1741,7 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
       finish<1>(h, nred(n), red(h, L0, EPI_OUT_BETA));
     }
     k_outer_dir<double><<<nblk(n), kBlock, 0, s>>>(n, osc, h->zp, pprev, p, use_beta ? 1 : 0);
-    launch_timed(h, KK_SPMV64, k_outer_spmv_dot, nsl_blocks, A64, F.nslices, static_cast<const double *>(p), q,
+    launch_timed(h, KK_SPMV64, k_outer_spmv_dot, nsl_blocks, A64, Zall, static_cast<const double *>(p), q,
                  static_cast<const double *>(h->rp), red(h, L0, EPI_OUT_ALPHA));
     finish<2>(h, nsl_blocks, red(h, L0, EPI_OUT_ALPHA));
     k_outer_update<<<nred(n), kBlock, 0, s>>>(n, osc, p, q, h->xp, h->rp, red(h, L0, EPI_STORE, O_RR));
@@ -1571,7 +1757,7 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
     std::swap(p, pprev);
     std::swap(q, qprev);
     if (std::sqrt(h->host_scal[O_RR]) <= tol * bn) {
-      k_outer_true_resid<<<nsl_blocks, kBlock, 0, s>>>(A64, F.nslices, h->bp, h->xp, h->tp,
+      k_outer_true_resid<<<nsl_blocks, kBlock, 0, s>>>(A64, Zall, h->bp, h->xp, h->tp,
                                                         red(h, L0, EPI_STORE, O_TT));
       finish<1>(h, nsl_blocks, red(h, L0, EPI_STORE, O_TT));
       QA_LAUNCH_CHECK();
@@ -1585,7 +1771,7 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
       inf.restarts++;
     }
   }
-  k_outer_true_resid<<<nsl_blocks, kBlock, 0, s>>>(A64, F.nslices, h->bp, h->xp, h->tp, red(h, L0, EPI_STORE, O_TT));
+  k_outer_true_resid<<<nsl_blocks, kBlock, 0, s>>>(A64, Zall, h->bp, h->xp, h->tp, red(h, L0, EPI_STORE, O_TT));
   finish<1>(h, nsl_blocks, red(h, L0, EPI_STORE, O_TT));
   k_scatter_back<double, double><<<nblk(n), kBlock, 0, s>>>(n, F.perm, h->xp, x);
   QA_LAUNCH_CHECK();
@@ -1638,8 +1824,8 @@ static amg_status level_spmv_t(amg_hierarchy *h, int level, const double *x, dou
     const int64_t n = F.n;
     T *xx = W[0].f, *yy = W[0].u;
     k_gather<double, T><<<nblk(n), kBlock, 0, s>>>(n, F.perm, x, xx);
-    k_fine_apply<T><<<static_cast<unsigned>((F.nslices + 3) / 4), kBlock, 0, s>>>(
-        sview<T>(F, P<T>::sval(F)), F.nslices, xx, yy);
+    const SliceSched Z = slice_sched(F, 0, 4);
+    k_fine_apply<T><<<sched_grid(Z), kBlock, 0, s>>>(sview<T>(F, P<T>::sval(F)), Z, xx, yy);
     k_scatter_back<T, double><<<nblk(n), kBlock, 0, s>>>(n, F.perm, yy, y);
     QA_LAUNCH_CHECK();
     QA_HIP(hipStreamSynchronize(s));
