@@ -1,4 +1,5 @@
 // Runtime pieces shared by setup and solve: tracked device allocation, exclusive scans, release, status names.
+#include <algorithm>
 #include <mutex>
 
 #include "qa_internal.hpp"
@@ -30,7 +31,7 @@ static hipMemPool_t pool_for(int device) {
   return pools[device];
 }
 
-void *dalloc(amg_hierarchy *h, size_t bytes) {
+static void *raw_alloc(amg_hierarchy *h, size_t bytes) {
   void *p = nullptr;
   hipMemPool_t pool = pool_for(h->device);
   if (pool) {
@@ -43,11 +44,31 @@ void *dalloc(amg_hierarchy *h, size_t bytes) {
   return p;
 }
 
+// A hierarchy holds a few hundred device arrays; one pool allocation and one free for each would cost more than the
+// setup's kernels. Arrays up to half a chunk are therefore carved (256-byte aligned, first fit) from shared chunks
+// of chunk_unit bytes, about an eighth of the hierarchy's estimated size; larger arrays get an allocation of their
+// own. A hierarchy then makes a few dozen allocations.
+void *dalloc(amg_hierarchy *h, size_t bytes) {
+  bytes = (bytes + 255) & ~static_cast<size_t>(255);
+  if (bytes > h->chunk_unit / 2) return raw_alloc(h, bytes);
+  for (Chunk &c : h->chunks)
+    if (c.used + bytes <= c.size) {
+      void *p = c.base + c.used;
+      c.used += bytes;
+      return p;
+    }
+  char *base = static_cast<char *>(raw_alloc(h, h->chunk_unit));
+  if (!base) return nullptr;
+  h->chunks.push_back(Chunk{base, h->chunk_unit, bytes});
+  return base;
+}
+
 amg_status release(amg_hierarchy *h) {
   const bool pooled = pool_for(h->device) != nullptr;
   for (void *p : h->allocs) (void)(pooled ? hipFreeAsync(p, h->stream) : hipFree(p));
   if (pooled) (void)hipStreamSynchronize(h->stream);
   h->allocs.clear();
+  h->chunks.clear();
   if (h->host_scal) return_pinned_scalars(h->host_scal);
   h->host_scal = nullptr;
   return_events(h->device, h->timing.ev);

@@ -166,6 +166,11 @@ struct Timing {
 
 enum KernelKind { KK_SPMV64 = 0, KK_GS_FINE32, KK_GS_FINE64, KK_RESID_FINE32, KK_RESID_FINE64, KK_COUNT };
 
+struct Chunk {                  // a device allocation that several arrays are carved from
+  char *base = nullptr;
+  size_t size = 0, used = 0;
+};
+
 }  // namespace qa
 
 struct amg_hierarchy {
@@ -190,8 +195,10 @@ struct amg_hierarchy {
   int64_t partials_cap = 0;
   double *host_scal = nullptr;         // pinned mirror for convergence checks
   int *dflag = nullptr;                // device error flags
-  std::vector<void *> allocs;
-  size_t bytes = 0;
+  std::vector<void *> allocs;           // device chunks (freed by amg_free)
+  size_t bytes = 0;                     // device bytes held (chunks, including unused tails)
+  std::vector<qa::Chunk> chunks;        // shared chunks that small arrays are carved from
+  size_t chunk_unit = 8u << 20;         // size of a shared chunk (set from the size estimate at setup)
   double setup_ms = 0.0;
   qa::Timing timing;
   // persistent small-level engine: top level index per precision (0 = FP64, 1 = FP32), -1 = not used

@@ -858,6 +858,13 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
 
 using namespace qa;
 
+// shared-chunk size for a hierarchy of about `estimate` bytes: an eighth of it, 4 MB to 256 MB, whole megabytes
+static size_t chunk_unit_for(size_t estimate) {
+  const size_t mb = static_cast<size_t>(1) << 20;
+  const size_t u = std::min(std::max(estimate / 8, 4 * mb), 256 * mb);
+  return (u + mb - 1) / mb * mb;
+}
+
 extern "C" amg_status amg_estimate_bytes(int64_t n, int64_t nnz, const amg_options *opt, size_t *bytes) {
   if (n < 1 || nnz < 0 || !bytes) return AMG_ERR_INVALID;
   amg_options o;
@@ -883,6 +890,8 @@ extern "C" amg_status amg_estimate_bytes(int64_t n, int64_t nnz, const amg_optio
     b += 4.0 * n * n * 8;
   }
   b += 1 << 20;  // scalars, partial sums, alignment slack
+  // arrays are carved from shared chunks of about b / 8 bytes (see chunk_unit_for): allow a chunk and a half unused
+  b += 1.5 * static_cast<double>(chunk_unit_for(static_cast<size_t>(b)));
   *bytes = static_cast<size_t>(b);
   return AMG_OK;
 }
@@ -919,6 +928,12 @@ extern "C" amg_status amg_setup(int64_t n, const double *coords, const int64_t *
   h->use_engine = o.engine ? 1 : 0;
   h->use_batch = o.batch ? 1 : 0;
   h->n = n;
+  {
+    size_t est = 0;
+    amg_options eo = o;
+    eo.box = nullptr;
+    if (amg_estimate_bytes(n, nnz, &eo, &est) == AMG_OK) h->chunk_unit = chunk_unit_for(est);
+  }
   h->opt.box = o.box;
   amg_status st = setup_impl(h, coords, row_ptr, col_idx, vals, nnz);
   h->opt.box = nullptr;

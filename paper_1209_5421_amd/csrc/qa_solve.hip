@@ -136,6 +136,33 @@ struct SellView {
   const T *val;
 };
 
+// (A x)_row for the row of `lane` in a slice of width w starting at entry `off`: the loop is unrolled by four with the
+// column and value loads of a group issued before its gathers, so each wavefront keeps several gathers in flight
+template <class T, class XT>
+__device__ inline XT sell_row(const SellView<T> &S, int64_t off, int w, int lane, const XT *__restrict__ x) {
+  const T *vp = S.val + off + lane;
+  const int32_t *cp = S.col + off + lane;
+  XT acc = 0;
+  int k = 0;
+  for (; k + 4 <= w; k += 4) {
+    const int32_t c0 = cp[0], c1 = cp[64], c2 = cp[128], c3 = cp[192];
+    const T v0 = vp[0], v1 = vp[64], v2 = vp[128], v3 = vp[192];
+    const XT x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
+    acc += v0 * x0;
+    acc += v1 * x1;
+    acc += v2 * x2;
+    acc += v3 * x3;
+    vp += 256;
+    cp += 256;
+  }
+  for (; k < w; k++) {
+    acc += vp[0] * x[cp[0]];
+    vp += 64;
+    cp += 64;
+  }
+  return acc;
+}
+
 // Which slices a launch over the colors [c0, c1) gives to which workgroup. Workgroups are dispatched to the eight
 // XCDs round-robin (workgroup b runs on XCD b mod 8) and every XCD has an L2 of its own. In the XCD-aware order,
 // workgroup b takes its slices from chunk b mod 8 of every color in [c0, c1), the same eighth of the Morton range in
@@ -178,11 +205,7 @@ __device__ inline void fine_resid_body(const SellView<T> &S, const SliceSched &Z
   if (row >= r1) return;
   const int64_t off = S.ptr[s];
   const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
-  T acc = 0;
-  for (int k = 0; k < w; k++) {
-    const int64_t e = off + static_cast<int64_t>(k) * 64 + lane;
-    acc += S.val[e] * x[S.col[e]];
-  }
+  const T acc = sell_row<T, T>(S, off, w, lane, x);
   d[row] = f[row] - acc;
 }
 
@@ -211,11 +234,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_apply(SellView<T> S, SliceSched
   if (row >= S.row0[s + 1]) return;
   const int64_t off = S.ptr[s];
   const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
-  T acc = 0;
-  for (int k = 0; k < w; k++) {
-    const int64_t e = off + static_cast<int64_t>(k) * 64 + lane;
-    acc += S.val[e] * x[S.col[e]];
-  }
+  const T acc = sell_row<T, T>(S, off, w, lane, x);
   y[row] = acc;
 }
 
@@ -452,11 +471,7 @@ __global__ void __launch_bounds__(kBlock) k_outer_spmv_dot(SellView<double> S, S
     if (row < S.row0[s + 1]) {
       const int64_t off = S.ptr[s];
       const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
-      double acc = 0.0;
-      for (int k = 0; k < w; k++) {
-        const int64_t e = off + static_cast<int64_t>(k) * 64 + lane;
-        acc += S.val[e] * p[S.col[e]];
-      }
+      const double acc = sell_row<double, double>(S, off, w, lane, p);
       q[row] = acc;
       v[0] = p[row] * acc;
       v[1] = r[row] * p[row];
@@ -478,11 +493,7 @@ __global__ void __launch_bounds__(kBlock) k_outer_true_resid(SellView<double> S,
     if (row < S.row0[s + 1]) {
       const int64_t off = S.ptr[s];
       const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
-      double acc = 0.0;
-      for (int k = 0; k < w; k++) {
-        const int64_t e = off + static_cast<int64_t>(k) * 64 + lane;
-        acc += S.val[e] * x[S.col[e]];
-      }
+      const double acc = sell_row<double, double>(S, off, w, lane, x);
       const double tr = b[row] - acc;
       t[row] = tr;
       v[0] = tr * tr;
@@ -660,10 +671,12 @@ constexpr int kEngMaxOps = 512;  // step list staged in LDS (20 bytes each)
 
 enum EngOpType : int32_t {
   EO_GS_FIRST = 0, EO_GS, EO_RES_RESTRICT, EO_DENSE, EO_PROLONG, EO_SPMV_DOT0, EO_UPDATE1, EO_DOT_BETA,
-  EO_AXPY_BETA, EO_SPMV_DOT1, EO_UPDATE2, EO_BHAT_M
+  EO_AXPY_BETA, EO_SPMV_DOT1, EO_UPDATE2, EO_BHAT_M, EO_GS_FIRST2
 };
+// engine scalars of a level (8 per level)
+enum EngScalar : int { ES_D0 = 0, ES_A0 = 2, ES_STOP = 3, ES_BETA = 5, ES_A1 = 6 };
 constexpr int kMhatMaxRows = 256;   // B^ kept as a matrix when the level above the coarsest has at most this many rows
-constexpr int kMhatPart = 1024;     // LDS partial sums of the matrix-vector product (T units)
+constexpr int kMhatPart = 4096;     // LDS partial sums of the matrix-vector product (T units)
 enum EngVec : int32_t { EV_G = 0, EV_E, EV_R, EV_P0, EV_Q0, EV_P1, EV_Q1, EV_D, EV_COUNT };
 
 struct EngOp {
@@ -716,18 +729,25 @@ __device__ inline void eng_reduce(double (&v)[ND], double *red) {
   }
 }
 
-template <class T>
-__device__ inline T eng_row(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
-                            uint32_t q, int c, const T *x) {
+// (A x)_q on an engine level, x given by a function of the index (a stored vector, or values formed on the fly)
+template <class T, class XV>
+__device__ inline T eng_row_f(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
+                              uint32_t q, int c, XV xv) {
   const int sh = 2 * k - 2;
   uint32_t nb[9];
   stencil_q(q, q & ((1u << sh) - 1u), c, sh, nb);
   T acc = 0;
 #pragma unroll
-  for (int s = 0; s < 9; s++) acc += ax[s * n + q] * x[nb[s]];  // absent slots hold 0
+  for (int s = 0; s < 9; s++) acc += ax[s * n + q] * xv(nb[s]);  // absent slots hold 0
   if (optr)
-    for (int32_t e = optr[q]; e < optr[q + 1]; e++) acc += oval[e] * x[ocol[e]];
+    for (int32_t e = optr[q]; e < optr[q + 1]; e++) acc += oval[e] * xv(static_cast<uint32_t>(ocol[e]));
   return acc;
+}
+
+template <class T>
+__device__ inline T eng_row(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
+                            uint32_t q, int c, const T *x) {
+  return eng_row_f<T>(k, n, ax, optr, ocol, oval, q, c, [x](uint32_t i) { return x[i]; });
 }
 
 // Vector and operator access of one engine level: LDS levels are addressed as offsets into the dynamic shared
@@ -742,6 +762,7 @@ struct EngMem {
 
 struct EngCtx {
   double *sc;       // this level's scalars
+  double *sc_child; // the next coarser level's scalars
   double *red;
 };
 
@@ -762,6 +783,24 @@ __device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const En
       const T *f = M.vec(op.f);
       T *u = M.vec(op.u);
       for (int q = tid; q < n; q += kStride) u[q] = (q < n4) ? f[q] / ax[q] : T(0);
+      break;
+    }
+    case EO_GS_FIRST2: {
+      // the first two phases of a sweep from zero in one step (levels without same-color couplings): color 0 takes
+      // u = f / diag, and the color-1 rows read those values formed on the fly (colors 2 and 3 are still 0); no
+      // thread reads u here, so the writes of colors 0, 2 and 3 can go alongside
+      const T *f = M.vec(op.f);
+      T *u = M.vec(op.u);
+      const uint32_t n4u = static_cast<uint32_t>(n4);
+      auto first = [f, ax, n4u](uint32_t i) { return i < n4u ? f[i] / ax[i] : T(0); };
+      for (int j = tid; j < n4; j += kStride) {
+        const uint32_t q = static_cast<uint32_t>(n4 + j);
+        u[q] = T(0) + (f[q] - eng_row_f<T>(k, n, ax, L.optr, L.ocol, L.oval, q, 1, first)) / ax[q];
+      }
+      for (int q = tid; q < n; q += kStride) {
+        if (q < n4) u[q] = f[q] / ax[q];
+        else if (q >= 2 * n4) u[q] = T(0);
+      }
       break;
     }
     case EO_GS: {
@@ -818,21 +857,35 @@ __device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const En
       break;
     }
     case EO_BHAT_M: {
-      // u = B^ f with B^ precomputed as a matrix (column-major, global memory): mhat_parts threads per row, each
-      // summing a contiguous run of columns; the partial sums are added in a fixed order
+      // u = B^ f with B^ precomputed as a matrix (column-major, global memory). A thread owns four consecutive rows
+      // (one 16-byte load per column in FP32, two in FP64) for a run of columns; the workgroup splits the columns
+      // into mhat_parts runs, and the partial sums of a row are added in a fixed order.
       const T *f = M.vec(op.f);
       T *u = M.vec(op.u);
       T *part = S + P.mpart_off;
+      const int groups = n >> 2;
       const int parts = P.mhat_parts;
       const int cols = n / parts;
-      if (tid < n * parts) {
-        const int r = tid & (n - 1);
-        const int b = tid / n;
-        const T *mc = P.mhat + static_cast<size_t>(b) * cols * n + r;
+      if (tid < groups * parts) {
+        const int g = tid % groups;
+        const int b = tid / groups;
+        const T *mc = P.mhat + static_cast<size_t>(b) * cols * n + 4 * g;
         const T *fb = f + b * cols;
-        T acc = 0;
-        for (int i = 0; i < cols; i++) acc += mc[static_cast<size_t>(i) * n] * fb[i];
-        part[b * n + r] = acc;
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+        for (int i = 0; i < cols; i++) {
+          const T *col = mc + static_cast<size_t>(i) * n;
+          const T fi = fb[i];
+          if constexpr (std::is_same<T, float>::value) {
+            const float4 v = *reinterpret_cast<const float4 *>(col);
+            a0 += v.x * fi; a1 += v.y * fi; a2 += v.z * fi; a3 += v.w * fi;
+          } else {
+            const double2 v0 = *reinterpret_cast<const double2 *>(col);
+            const double2 v1 = *reinterpret_cast<const double2 *>(col + 2);
+            a0 += v0.x * fi; a1 += v0.y * fi; a2 += v1.x * fi; a3 += v1.y * fi;
+          }
+        }
+        T *pb = part + b * n + 4 * g;
+        pb[0] = a0; pb[1] = a1; pb[2] = a2; pb[3] = a3;
       }
       __syncthreads();
       for (int r = tid; r < n; r += kStride) {
@@ -843,19 +896,28 @@ __device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const En
       break;
     }
     case EO_PROLONG: {
+      // u += P e_c; with op.color = 1 the child's last update e_c += a1 (p1 + beta p0) (UPDATE2, deferred) is
+      // formed here, value for value as that step would have stored it
       T *u = M.vec(op.u);
       const EngMem<T, LDS_CHILD> MC{S, LV[l + 1]};
       const T *ec = MC.vec(EV_E);
-      for (int q = tid; q < n; q += kStride)
-        u[q] += ec[q_of_m(static_cast<uint32_t>(q & (n4 - 1)), k - 1)];
+      if (op.color) {
+        const T a1 = static_cast<T>(C.sc_child[ES_A1]), beta = static_cast<T>(C.sc_child[ES_BETA]);
+        const T *p1c = MC.vec(EV_P1), *p0c = MC.vec(EV_P0);
+        for (int q = tid; q < n; q += kStride) {
+          const uint32_t m = q_of_m(static_cast<uint32_t>(q & (n4 - 1)), k - 1);
+          const T ecm = ec[m] + a1 * (p1c[m] + beta * p0c[m]);
+          u[q] += ecm;
+        }
+      } else {
+        for (int q = tid; q < n; q += kStride) u[q] += ec[q_of_m(static_cast<uint32_t>(q & (n4 - 1)), k - 1)];
+      }
       break;
     }
-    case EO_SPMV_DOT0:
-    case EO_SPMV_DOT1: {
-      const bool first = op.type == EO_SPMV_DOT0;
-      const T *x = M.vec(first ? EV_P0 : EV_P1);
-      T *y = M.vec(first ? EV_Q0 : EV_Q1);
-      const T *w = M.vec(first ? EV_G : EV_R);
+    case EO_SPMV_DOT0: {
+      const T *x = M.vec(EV_P0);
+      T *y = M.vec(EV_Q0);
+      const T *w = M.vec(EV_G);
       double v[2] = {0.0, 0.0};
       for (int q = tid; q < n; q += kStride) {
         const T yq = eng_row(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q),
@@ -866,19 +928,34 @@ __device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const En
       }
       eng_reduce<2>(v, C.red);
       if (tid == 0) {
-        if (first) {
-          const bool stop = !(v[0] > 0.0);
-          C.sc[S_D0] = v[0];
-          C.sc[S_STOP] = stop ? 1.0 : 0.0;
-          C.sc[S_A0] = stop ? 0.0 : v[1] / v[0];
-        } else {
-          C.sc[S_A1 - 3] = (C.sc[S_STOP] != 0.0 || !(v[0] > 0.0)) ? 0.0 : v[1] / v[0];
-        }
+        const bool stop = !(v[0] > 0.0);
+        C.sc[ES_D0] = v[0];
+        C.sc[ES_STOP] = stop ? 1.0 : 0.0;
+        C.sc[ES_A0] = stop ? 0.0 : v[1] / v[0];
       }
       break;
     }
+    case EO_SPMV_DOT1: {
+      // A p1 with the direction update p1 + beta p0 formed on the fly (it is never stored: UPDATE2 forms it too);
+      // only the two inner products are kept
+      const T beta = static_cast<T>(C.sc[ES_BETA]);
+      const T *p1 = M.vec(EV_P1), *p0 = M.vec(EV_P0);
+      const T *w = M.vec(EV_R);
+      auto dir = [p1, p0, beta](uint32_t i) { return p1[i] + beta * p0[i]; };
+      double v[2] = {0.0, 0.0};
+      for (int q = tid; q < n; q += kStride) {
+        const T yq = eng_row_f<T>(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q),
+                                  row_color(static_cast<uint32_t>(q), 2 * k - 2), dir);
+        const T xq = dir(static_cast<uint32_t>(q));
+        v[0] += static_cast<double>(xq) * static_cast<double>(yq);
+        v[1] += static_cast<double>(w[q]) * static_cast<double>(xq);
+      }
+      eng_reduce<2>(v, C.red);
+      if (tid == 0) C.sc[ES_A1] = (C.sc[ES_STOP] != 0.0 || !(v[0] > 0.0)) ? 0.0 : v[1] / v[0];
+      break;
+    }
     case EO_UPDATE1: {
-      const T a0 = static_cast<T>(C.sc[S_A0]);
+      const T a0 = static_cast<T>(C.sc[ES_A0]);
       const T *p0 = M.vec(EV_P0), *q0 = M.vec(EV_Q0), *g = M.vec(EV_G);
       T *e = M.vec(EV_E), *r = M.vec(EV_R);
       for (int i = tid; i < n; i += kStride) {
@@ -892,21 +969,14 @@ __device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const En
       double t[1] = {0.0};
       for (int i = tid; i < n; i += kStride) t[0] += static_cast<double>(p1[i]) * static_cast<double>(q0[i]);
       eng_reduce<1>(t, C.red);
-      if (tid == 0) C.sc[S_BETA] = (C.sc[S_STOP] != 0.0) ? 0.0 : -t[0] / C.sc[S_D0];
-      break;
-    }
-    case EO_AXPY_BETA: {
-      const T beta = static_cast<T>(C.sc[S_BETA]);
-      T *p1 = M.vec(EV_P1);
-      const T *p0 = M.vec(EV_P0);
-      for (int i = tid; i < n; i += kStride) p1[i] += beta * p0[i];
+      if (tid == 0) C.sc[ES_BETA] = (C.sc[ES_STOP] != 0.0) ? 0.0 : -t[0] / C.sc[ES_D0];
       break;
     }
     case EO_UPDATE2: {
-      const T a1 = static_cast<T>(C.sc[S_A1 - 3]);
-      const T *p1 = M.vec(EV_P1);
+      const T a1 = static_cast<T>(C.sc[ES_A1]), beta = static_cast<T>(C.sc[ES_BETA]);
+      const T *p1 = M.vec(EV_P1), *p0 = M.vec(EV_P0);
       T *e = M.vec(EV_E);
-      for (int i = tid; i < n; i += kStride) e[i] += a1 * p1[i];
+      for (int i = tid; i < n; i += kStride) e[i] += a1 * (p1[i] + beta * p0[i]);
       break;
     }
     default:
@@ -920,7 +990,7 @@ __device__ inline void eng_run(const EngPlan<T> &P, const EngOp *ops, const EngL
                                const double *Ainv, double (*sc)[8], double *red) {
   for (int oi = 0; oi < P.nops; oi++) {
     const EngOp op = ops[oi];
-    const EngCtx C{sc[op.lvl], red};
+    const EngCtx C{sc[op.lvl], sc[op.lvl + 1 < kEngMaxLevels ? op.lvl + 1 : op.lvl], red};
     const bool lds = LV[op.lvl].in_lds != 0;
     const bool lds_child = (op.lvl + 1 < P.nlev) && LV[op.lvl + 1].in_lds != 0;
     if (lds) eng_step<T, true, true>(op, LV, P, S, Ainv, C);
@@ -969,36 +1039,55 @@ __global__ void __launch_bounds__(kEngThreads) k_engine(EngPlan<T> P) {
 // Step list of B~ at engine level l; mirrors btilde / bhat_coarse below.
 struct EmitCtx {
   int nl, sweeps, inner;
-  int mhat;  // B^ of the level above the coarsest is one EO_BHAT_M step
+  int mhat;               // B^ of the level above the coarsest is one EO_BHAT_M step
+  const int *same_color;  // per engine level: some coupling joins two cells of one color
 };
 
-static void emit_btilde(std::vector<EngOp> &ops, const EmitCtx &E, int l);
+static void emit_btilde(std::vector<EngOp> &ops, const EmitCtx &E, int l, bool defer_update2);
 
+// B^ of Algorithm 2.2 on engine level l (f, u: vector slots). The first two phases of the first sweep are one step
+// where no coupling joins cells of one color; with a second inner iteration below, the child's last update is
+// folded into this level's prolongation.
 static void emit_bhat(std::vector<EngOp> &ops, const EmitCtx &E, int l, int f, int u) {
   if (E.mhat && l + 1 == E.nl - 1) {
     ops.push_back({EO_BHAT_M, l, 0, f, u});
     return;
   }
   for (int sw = 0; sw < E.sweeps; sw++)
-    for (int c = 0; c < 4; c++) ops.push_back({(sw == 0 && c == 0) ? EO_GS_FIRST : EO_GS, l, c, f, u});
+    for (int c = 0; c < 4; c++) {
+      if (sw == 0 && c == 0 && !E.same_color[l]) {
+        ops.push_back({EO_GS_FIRST2, l, 1, f, u});
+        c = 1;
+      } else {
+        ops.push_back({(sw == 0 && c == 0) ? EO_GS_FIRST : EO_GS, l, c, f, u});
+      }
+    }
   ops.push_back({EO_RES_RESTRICT, l, 0, f, u});
+  const bool defer = l + 1 < E.nl - 1 && E.inner >= 2;
   if (l + 1 == E.nl - 1) ops.push_back({EO_DENSE, l + 1, 0, 0, 0});
-  else emit_btilde(ops, E, l + 1);
-  ops.push_back({EO_PROLONG, l, 0, f, u});
+  else emit_btilde(ops, E, l + 1, defer);
+  ops.push_back({EO_PROLONG, l, defer ? 1 : 0, f, u});
   for (int sw = 0; sw < E.sweeps; sw++)
     for (int c = 3; c >= 0; c--) ops.push_back({EO_GS, l, c, f, u});
 }
 
-static void emit_btilde(std::vector<EngOp> &ops, const EmitCtx &E, int l) {
+// B~ of Algorithm 2.1 with n = inner iterations on engine level l
+static void emit_btilde(std::vector<EngOp> &ops, const EmitCtx &E, int l, bool defer_update2) {
   emit_bhat(ops, E, l, EV_G, EV_P0);
   ops.push_back({EO_SPMV_DOT0, l, 0, 0, 0});
   ops.push_back({EO_UPDATE1, l, 0, 0, 0});
   if (E.inner < 2) return;
   emit_bhat(ops, E, l, EV_R, EV_P1);
   ops.push_back({EO_DOT_BETA, l, 0, 0, 0});
-  ops.push_back({EO_AXPY_BETA, l, 0, 0, 0});
   ops.push_back({EO_SPMV_DOT1, l, 0, 0, 0});
-  ops.push_back({EO_UPDATE2, l, 0, 0, 0});
+  if (!defer_update2) ops.push_back({EO_UPDATE2, l, 0, 0, 0});
+}
+
+// same-color flags of the levels from `top` down, indexed from 0
+static std::vector<int> same_color_from(const amg_hierarchy *h, int top) {
+  std::vector<int> v;
+  for (int l = top; l < h->nlev; l++) v.push_back(l >= 1 ? h->lev[l].same_color_ovf : 0);
+  return v;
 }
 
 template <class T> struct WgSys;
@@ -1051,11 +1140,13 @@ amg_status plan_engine(amg_hierarchy *h) {
     // one more level above may run from global memory (L2-resident) when it is small enough
     if (top - 1 >= 1 && h->lev[top - 1].n <= h->engine_global_rows) top--;
     std::vector<EngOp> ops;
+    std::vector<int> same_top;
     for (;; top++) {
+      same_top = same_color_from(h, top);
       if (top >= h->nlev - 1) break;
       ops.clear();
       if (h->nlev - top <= kEngMaxLevels)
-        emit_btilde(ops, EmitCtx{h->nlev - top, h->opt.sweeps, h->opt.inner_iters, mhat}, 0);
+        emit_btilde(ops, EmitCtx{h->nlev - top, h->opt.sweeps, h->opt.inner_iters, mhat, same_top.data()}, 0, false);
       if (!ops.empty() && ops.size() <= static_cast<size_t>(kEngMaxOps)) break;
     }
     if (top >= h->nlev - 1) continue;  // no engine for this precision
@@ -1114,7 +1205,8 @@ amg_status build_mhat(amg_hierarchy *h) {
   const size_t stat = sizeof(EngOp) * kEngMaxOps + 4096;
   if (bytes + stat > static_cast<size_t>(lds)) return AMG_OK;
   std::vector<EngOp> ops;
-  emit_bhat(ops, EmitCtx{2, h->opt.sweeps, h->opt.inner_iters, 0}, 0, EV_G, EV_E);
+  const std::vector<int> same_l = same_color_from(h, l);
+  emit_bhat(ops, EmitCtx{2, h->opt.sweeps, h->opt.inner_iters, 0, same_l.data()}, 0, EV_G, EV_E);
   if (ops.size() > static_cast<size_t>(kEngMaxOps)) return AMG_OK;
   double *ident = dalloc_n<double>(h, n * n);
   double *m64 = dalloc_n<double>(h, n * n);
@@ -1185,7 +1277,8 @@ static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, En
   if (h->mhat_level >= top) {
     const int n = static_cast<int>(h->mhat_n);
     E.mhat = static_cast<const T *>(h->mhat[pi]);
-    E.mhat_parts = std::min(std::min(kEngThreads / n, 16), n);
+    // four rows per thread: n / 4 row groups, the columns split over the rest of the workgroup (at most n runs)
+    E.mhat_parts = std::max(1, std::min(kEngThreads / std::max(n / 4, 1), std::min(n, kMhatPart / n)));
     E.mpart_off = off;
   }
 }
@@ -1469,7 +1562,8 @@ amg_status plan_wg(amg_hierarchy *h) {
   const size_t budget = h->lds_max > stat ? h->lds_max - stat : 0;
   std::vector<EngOp> ops;
   const int mhat = h->mhat_level >= 0 ? 1 : 0;
-  emit_btilde(ops, EmitCtx{h->nlev - 1, h->opt.sweeps, h->opt.inner_iters, mhat}, 0);
+  const std::vector<int> same1 = same_color_from(h, 1);
+  emit_btilde(ops, EmitCtx{h->nlev - 1, h->opt.sweeps, h->opt.inner_iters, mhat, same1.data()}, 0, false);
   if (ops.size() > static_cast<size_t>(kEngMaxOps) || h->nlev - 1 > kEngMaxLevels) return AMG_OK;
   for (int pi = 0; pi < 2; pi++) {
     const size_t ts = pi == 0 ? sizeof(double) : sizeof(float);

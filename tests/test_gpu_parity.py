@@ -225,3 +225,24 @@ def test_error_paths():
     x, info = g.solve(T(prob.b), check=False)
     assert info["status"] == amg.NOCONV and info["iters"] == 1
     g.close()
+
+
+@pytest.mark.parametrize("name", list(PROBLEMS))
+def test_footprint_within_estimate(name):
+    """amg_estimate_bytes (used for admission by HBM footprint) bounds what a hierarchy actually holds."""
+    prob = problem(name)
+    g = gpu_hier(prob)
+    est = _amg().estimate_bytes(prob.n, prob.nnz)
+    print(f"[gpu] {name}: {g.bytes()} bytes held, estimate {est}", flush=True)
+    assert 0 < g.bytes() <= est
+    g.close()
+
+
+def test_footprint_within_estimate_large():
+    prob = mg.jittered_problem(700, fast=True)
+    g = gpu_hier(prob)
+    est = _amg().estimate_bytes(prob.n, prob.nnz)
+    print(f"[gpu] jittered700: {g.bytes()} bytes held ({g.bytes() / prob.n:.0f} per unknown), estimate {est}",
+          flush=True)
+    assert 0 < g.bytes() <= est
+    g.close()
