@@ -125,6 +125,19 @@ __global__ void __launch_bounds__(kBlock) k_finish(unsigned nb, Red R) {
   if (threadIdx.x == 0) epilogue(acc, R);
 }
 
+// the child's pending last update e_c + a1 (p1 + beta p0) of Algorithm 2.1, formed where the prolongation reads e_c
+// (null sc: nothing pending)
+template <class T>
+struct Pending {
+  const double *sc;
+  const T *p1, *p0;
+  __device__ T apply(const T *e, uint32_t m) const {
+    if (!sc) return e[m];
+    const T a1 = static_cast<T>(sc[S_A1]), beta = static_cast<T>(sc[S_BETA]);
+    return e[m] + a1 * (p1[m] + beta * p0[m]);
+  }
+};
+
 // ---------------------------------------------------------------------------------------------------------------
 // fine level kernels
 
@@ -286,9 +299,12 @@ __global__ void __launch_bounds__(kBlock) k_fine_restrict(int64_t nL, const int3
 
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_fine_prolong(int64_t n, const int32_t *__restrict__ agg_q,
-                                                          const T *__restrict__ e, T *__restrict__ u) {
+                                                          const T *__restrict__ e, Pending<T> pend,
+                                                          T *__restrict__ u) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p < n) u[p] += e[agg_q[p]];
+  if (p >= n) return;
+  const T em = pend.apply(e, static_cast<uint32_t>(agg_q[p]));
+  u[p] += em;
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -307,17 +323,22 @@ struct QView {
 // (A x)_q for row q = c n/4 + j of a quadtree level (slots in order 0..8, then overflow entries). A slot whose
 // neighbour lies outside the grid holds the value 0, so its product is taken with x[q] instead of being branched
 // around: all nine loads are independent and issue back to back.
-template <class T>
-__device__ inline T row_apply(const QView<T> &Q, uint32_t q, int c, const T *__restrict__ x) {
+template <class T, class XV>
+__device__ inline T row_apply_f(const QView<T> &Q, uint32_t q, int c, XV xv) {
   const int sh = 2 * Q.k - 2;
   uint32_t nb[9];
   stencil_q(q, q & ((1u << sh) - 1u), c, sh, nb);
   T acc = 0;
 #pragma unroll
-  for (int s = 0; s < 9; s++) acc += Q.ax[s * Q.n + q] * x[nb[s]];
+  for (int s = 0; s < 9; s++) acc += Q.ax[s * Q.n + q] * xv(nb[s]);
   if (Q.optr)
-    for (int32_t e = Q.optr[q]; e < Q.optr[q + 1]; e++) acc += Q.oval[e] * x[Q.ocol[e]];
+    for (int32_t e = Q.optr[q]; e < Q.optr[q + 1]; e++) acc += Q.oval[e] * xv(static_cast<uint32_t>(Q.ocol[e]));
   return acc;
+}
+
+template <class T>
+__device__ inline T row_apply(const QView<T> &Q, uint32_t q, int c, const T *__restrict__ x) {
+  return row_apply_f<T>(Q, q, c, [x](uint32_t i) { return x[i]; });
 }
 
 // color of row q (sh = 2k - 2); uniform over a wavefront of consecutive rows when a color block holds >= 64 rows
@@ -332,6 +353,25 @@ __global__ void __launch_bounds__(kBlock) k_cgs_first(QView<T> Q, const T *__res
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= Q.n) return;
   x[q] = (q < (Q.n >> 2)) ? f[q] / Q.ax[q] : T(0);
+}
+
+// the first two phases of a sweep from zero (levels without same-color couplings): x = f / diag on color 0, zero on
+// colors 2 and 3, and the color-1 rows relaxed against the color-0 values formed on the fly (nothing reads x here)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cgs_first2(QView<T> Q, const T *__restrict__ f, T *__restrict__ x) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= Q.n) return;
+  const int64_t n4 = Q.n >> 2;
+  if (q < n4) {
+    x[q] = f[q] / Q.ax[q];
+  } else if (q < 2 * n4) {
+    const uint32_t n4u = static_cast<uint32_t>(n4);
+    const T *ax = Q.ax;
+    auto first = [f, ax, n4u](uint32_t i) { return i < n4u ? f[i] / ax[i] : T(0); };
+    x[q] = T(0) + (f[q] - row_apply_f<T>(Q, static_cast<uint32_t>(q), 1, first)) / Q.ax[q];
+  } else {
+    x[q] = T(0);
+  }
 }
 
 // one color phase of the pointwise 4-color Gauss-Seidel: rows q = c n/4 + j, Morton m = 4 j + c.
@@ -375,12 +415,14 @@ __global__ void __launch_bounds__(kBlock) k_cres_restrict(QView<T> Q, const T *_
 }
 
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_cprolong(int k, int64_t n, const T *__restrict__ e, T *__restrict__ u) {
+__global__ void __launch_bounds__(kBlock) k_cprolong(int k, int64_t n, const T *__restrict__ e, Pending<T> pend,
+                                                      T *__restrict__ u) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= n) return;
   // children of M are q = c n/4 + M: the parent's Morton index is q mod n/4
   const uint32_t M = static_cast<uint32_t>(q & ((n >> 2) - 1));
-  u[q] += e[q_of_m(M, k - 1)];
+  const T em = pend.apply(e, q_of_m(M, k - 1));
+  u[q] += em;
 }
 
 // y = A x on a quadtree level with two inner products (x, y) and (w, x); grid-stride, fixed grid
@@ -395,6 +437,26 @@ __global__ void __launch_bounds__(kBlock) k_cspmv_dot(QView<T> Q, const T *__res
     const double xq = static_cast<double>(x[q]);
     v[0] += xq * static_cast<double>(yq);
     v[1] += static_cast<double>(w[q]) * xq;
+  }
+  reduce_finish<2>(v, R);
+}
+
+// the second inner step of Algorithm 2.1: A d with the direction d = p1 + beta p0 formed on the fly (never stored),
+// inner products (d, A d) and (r, d)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cspmv_dir(QView<T> Q, const double *__restrict__ sc,
+                                                       const T *__restrict__ p1, const T *__restrict__ p0,
+                                                       const T *__restrict__ r, Red R) {
+  const T beta = static_cast<T>(sc[S_BETA]);
+  auto dir = [p1, p0, beta](uint32_t i) { return p1[i] + beta * p0[i]; };
+  double v[2] = {0.0, 0.0};
+  for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < Q.n;
+       q += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const uint32_t qu = static_cast<uint32_t>(q);
+    const T yq = row_apply_f<T>(Q, qu, row_color(qu, 2 * Q.k - 2), dir);
+    const double dq = static_cast<double>(dir(qu));
+    v[0] += dq * static_cast<double>(yq);
+    v[1] += static_cast<double>(r[q]) * dq;
   }
   reduce_finish<2>(v, R);
 }
@@ -422,18 +484,14 @@ __global__ void __launch_bounds__(kBlock) k_dot(int64_t n, const T *__restrict__
   reduce_finish<1>(v, R);
 }
 
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_axpy_beta(int64_t n, const double *__restrict__ sc, T *__restrict__ p1,
-                                                       const T *__restrict__ p0) {
-  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) p1[i] += static_cast<T>(sc[S_BETA]) * p0[i];
-}
-
+// e += a1 (p1 + beta p0): the last update of Algorithm 2.1 with the direction formed on the fly
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_update2(int64_t n, const double *__restrict__ sc, const T *__restrict__ p1,
-                                                     T *__restrict__ e) {
+                                                     const T *__restrict__ p0, T *__restrict__ e) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < n) e[i] += static_cast<T>(sc[S_A1]) * p1[i];
+  if (i >= n) return;
+  const T a1 = static_cast<T>(sc[S_A1]), beta = static_cast<T>(sc[S_BETA]);
+  e[i] += a1 * (p1[i] + beta * p0[i]);
 }
 
 template <class T>
@@ -1588,10 +1646,12 @@ amg_status plan_wg(amg_hierarchy *h) {
   return engine_lds_limits(h);
 }
 
-template <class T> static void btilde(amg_hierarchy *h, int l, const T *g, T *e);
+template <class T> static void btilde(amg_hierarchy *h, int l, const T *g, T *e, bool defer_update2);
 
+// Solve or cycle on level l for the correction of level l - 1. Returns the pending last update of B~ on level l when
+// it was left for the parent's prolongation (only levels that run per step, with two inner iterations).
 template <class T>
-static void coarse_solve_or_cycle(amg_hierarchy *h, int l) {
+static Pending<T> coarse_solve_or_cycle(amg_hierarchy *h, int l) {
   LevelWork<T> &w = P<T>::W(h)[l];
   const int pi = std::is_same<T, float>::value ? 1 : 0;
   if (l == h->nlev - 1) {
@@ -1599,8 +1659,11 @@ static void coarse_solve_or_cycle(amg_hierarchy *h, int l) {
   } else if (h->use_engine && l == h->engine_top[pi]) {
     launch_engine<T>(h, l);
   } else {
-    btilde<T>(h, l, w.g, w.e);
+    const bool defer = h->opt.inner_iters >= 2;
+    btilde<T>(h, l, w.g, w.e, defer);
+    if (defer) return Pending<T>{h->scal + static_cast<size_t>(l) * kScalars, w.p1, w.p0};
   }
+  return Pending<T>{nullptr, nullptr, nullptr};
 }
 
 template <class T>
@@ -1624,13 +1687,19 @@ static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u) {
   const int sweeps = h->opt.sweeps;
   for (int sw = 0; sw < sweeps; sw++)
     for (int c = 0; c < 4; c++) {
-      if (sw == 0 && c == 0) k_cgs_first<T><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u);
-      else gs_phase_coarse<T>(h, l, f, u, c);
+      if (sw == 0 && c == 0 && !Q.same_color_ovf) {
+        k_cgs_first2<T><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u);
+        c = 1;
+      } else if (sw == 0 && c == 0) {
+        k_cgs_first<T><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u);
+      } else {
+        gs_phase_coarse<T>(h, l, f, u, c);
+      }
     }
   LevelWork<T> &wc = P<T>::W(h)[l + 1];
   k_cres_restrict<T><<<nblk(Q.n >> 2), kBlock, 0, s>>>(qview<T>(Q), f, u, wc.g);
-  coarse_solve_or_cycle<T>(h, l + 1);
-  k_cprolong<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, wc.e, u);
+  const Pending<T> pend = coarse_solve_or_cycle<T>(h, l + 1);
+  k_cprolong<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, wc.e, pend, u);
   for (int sw = 0; sw < sweeps; sw++)
     for (int c = 3; c >= 0; c--) gs_phase_coarse<T>(h, l, f, u, c);
 }
@@ -1676,8 +1745,8 @@ static void bhat_fine(amg_hierarchy *h, const T *f, T *u) {
   fine_resid<T>(h, f, u, w.d, 0, 4, P<T>::kResid);
   const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
   k_fine_restrict<T><<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, w.d, wc.g);
-  coarse_solve_or_cycle<T>(h, 1);
-  k_fine_prolong<T><<<nblk(F.n), kBlock, 0, s>>>(F.n, F.agg_q, wc.e, u);
+  const Pending<T> pend = coarse_solve_or_cycle<T>(h, 1);
+  k_fine_prolong<T><<<nblk(F.n), kBlock, 0, s>>>(F.n, F.agg_q, wc.e, pend, u);
   for (int sw = 0; sw < sweeps; sw++)
     for (int c = 3; c >= 0; c--) fine_phase<T>(h, f, u, w.d, c, false, false);
 }
@@ -1690,7 +1759,7 @@ static void bhat(amg_hierarchy *h, int l, const T *f, T *u) {
 
 // B~_l: Algorithm 2.1 with n = inner_iters (1 or 2) steps and B^_l as preconditioner
 template <class T>
-static void btilde(amg_hierarchy *h, int l, const T *g, T *e) {
+static void btilde(amg_hierarchy *h, int l, const T *g, T *e, bool defer_update2) {
   const QuadLevel &Q = h->lev[l];
   LevelWork<T> &w = P<T>::W(h)[l];
   hipStream_t s = h->stream;
@@ -1703,10 +1772,9 @@ static void btilde(amg_hierarchy *h, int l, const T *g, T *e) {
   bhat<T>(h, l, w.r, w.p1);
   k_dot<T><<<nred(Q.n), kBlock, 0, s>>>(Q.n, w.p1, w.q0, red(h, l, EPI_BETA));
   finish<1>(h, nred(Q.n), red(h, l, EPI_BETA));
-  k_axpy_beta<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p1, w.p0);
-  k_cspmv_dot<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), w.p1, w.q1, w.r, red(h, l, EPI_ALPHA1));
+  k_cspmv_dir<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), sc, w.p1, w.p0, w.r, red(h, l, EPI_ALPHA1));
   finish<2>(h, nred(Q.n), red(h, l, EPI_ALPHA1));
-  k_update2<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p1, e);
+  if (!defer_update2) k_update2<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p1, w.p0, e);
 }
 
 // z = B^_F[r] in the requested precision (r, z: FP64, permuted numbering)
