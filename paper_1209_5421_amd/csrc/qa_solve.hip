@@ -789,7 +789,7 @@ __device__ inline void eng_reduce(double (&v)[ND], double *red) {
 
 // (A x)_q on an engine level, x given by a function of the index (a stored vector, or values formed on the fly)
 template <class T, class XV>
-__device__ inline T eng_row_f(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
+__device__ __forceinline__ T eng_row_f(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
                               uint32_t q, int c, XV xv) {
   const int sh = 2 * k - 2;
   uint32_t nb[9];
@@ -803,7 +803,7 @@ __device__ inline T eng_row_f(int k, int n, const T *ax, const int32_t *optr, co
 }
 
 template <class T>
-__device__ inline T eng_row(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
+__device__ __forceinline__ T eng_row(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
                             uint32_t q, int c, const T *x) {
   return eng_row_f<T>(k, n, ax, optr, ocol, oval, q, c, [x](uint32_t i) { return x[i]; });
 }
@@ -827,7 +827,7 @@ struct EngCtx {
 // One step of the interpreter, run by the whole workgroup. LDS / LDS_CHILD: where this level's and its child's
 // vectors live.
 template <class T, bool LDS, bool LDS_CHILD>
-__device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const EngPlan<T> &P, T *S,
+__device__ __forceinline__ void eng_step(const EngOp &op, const EngLevel<T> *LV, const EngPlan<T> &P, T *S,
                                 const double *Ainv, EngCtx C) {
   constexpr int kStride = kEngThreads;
   const int tid = static_cast<int>(threadIdx.x);
@@ -1044,7 +1044,7 @@ __device__ inline void eng_step(const EngOp &op, const EngLevel<T> *LV, const En
 
 // Interpret a step list (operators and step list already staged in LDS).
 template <class T>
-__device__ inline void eng_run(const EngPlan<T> &P, const EngOp *ops, const EngLevel<T> *LV, T *S,
+__device__ __forceinline__ void eng_run(const EngPlan<T> &P, const EngOp *ops, const EngLevel<T> *LV, T *S,
                                const double *Ainv, double (*sc)[8], double *red) {
   for (int oi = 0; oi < P.nops; oi++) {
     const EngOp op = ops[oi];
