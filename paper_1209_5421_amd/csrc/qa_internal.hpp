@@ -22,6 +22,7 @@ namespace qa {
 constexpr int kBlock = 256;        // threads per workgroup for elementwise / reduction kernels
 constexpr int kSliceRows = 64;     // sliced-ELL slice height = one wavefront
 constexpr int kRedBlocksMax = 1024;
+constexpr int kBigCell = 24;        // cells with more unknowns get a level-scheduled in-cell substitution
 constexpr int kScalars = 16;       // device scalars per level
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -147,6 +148,14 @@ struct FineLevel {
   float *ic_val32 = nullptr;
   int32_t *crow = nullptr;      // level-L cell q -> first row (4^L + 1)
   int32_t *agg_q = nullptr;     // row -> level-L cell q
+  // cells of more than kBigCell unknowns: their in-cell substitution runs level by level (rows on one level of the
+  // substitution's dependency graph are independent), one workgroup per cell; [0] forward, [1] backward
+  int64_t nbig = 0;
+  int64_t big_color[5] = {0, 0, 0, 0, 0};       // first big cell of each color (big cells ascend by cell id)
+  int32_t *big_cells = nullptr;                 // cell ids
+  int32_t *big_lofs[2] = {nullptr, nullptr};    // per big cell, its first entry in big_lptr (nbig + 1)
+  int32_t *big_lptr[2] = {nullptr, nullptr};    // level starts as row positions, then the cell's end
+  int32_t *big_sched[2] = {nullptr, nullptr};   // the big cells' rows ordered by level (indexed by row position)
 };
 
 template <class T>

@@ -269,6 +269,65 @@ __global__ void __launch_bounds__(kBlock) k_ic_fill(int64_t n, const int64_t *__
     }
 }
 
+// Level schedule of the in-cell substitution of big cells (more than kBigCell unknowns). The forward substitution
+// of a cell takes its rows in ascending order and row p uses the new values of the coupled rows c < p; its
+// dependency level is 1 + the largest level among those rows (0 if none), and rows of one level are independent.
+// Backward: descending order, c > p. One thread per big cell (sequential over the cell, once at setup).
+__global__ void __launch_bounds__(kBlock) k_big_flag(int64_t nL, const int32_t *__restrict__ crow,
+                                                      int32_t *__restrict__ flag) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q < nL) flag[q] = (crow[q + 1] - crow[q]) > kBigCell ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(kBlock) k_big_list(int64_t nL, const int32_t *__restrict__ flag,
+                                                      const int32_t *__restrict__ pos, int32_t *__restrict__ cells) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q < nL && flag[q]) cells[pos[q]] = static_cast<int32_t>(q);
+}
+
+template <bool FWD>
+__global__ void __launch_bounds__(kBlock) k_big_levels(int64_t nbig, const int32_t *__restrict__ cells,
+                                                        const int32_t *__restrict__ crow,
+                                                        const int32_t *__restrict__ icp,
+                                                        const int32_t *__restrict__ icc, int32_t *__restrict__ lv,
+                                                        int32_t *__restrict__ nptr) {
+  const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= nbig) return;
+  const int32_t q = cells[b], a = crow[q], e = crow[q + 1];
+  int32_t depth = 0;
+  for (int32_t i = 0; i < e - a; i++) {
+    const int32_t p = FWD ? a + i : e - 1 - i;
+    int32_t m = 0;
+    for (int32_t k = icp[p]; k < icp[p + 1]; k++) {
+      const int32_t c = icc[k];
+      if (FWD ? c < p : c > p) m = max(m, lv[c] + 1);
+    }
+    lv[p] = m;
+    depth = max(depth, m + 1);
+  }
+  nptr[b] = depth + 1;  // level starts plus the end
+}
+
+// rows of each big cell sorted by level (stable: ascending row within a level); lptr gets the level starts
+__global__ void __launch_bounds__(kBlock) k_big_sched(int64_t nbig, const int32_t *__restrict__ cells,
+                                                       const int32_t *__restrict__ crow, const int32_t *__restrict__ lv,
+                                                       const int32_t *__restrict__ lofs, int32_t *__restrict__ lptr,
+                                                       int32_t *__restrict__ sched) {
+  const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b >= nbig) return;
+  const int32_t q = cells[b], a = crow[q], e = crow[q + 1];
+  int32_t *ptr = lptr + lofs[b];
+  const int32_t depth = lofs[b + 1] - lofs[b] - 1;
+  for (int32_t l = 0; l <= depth; l++) ptr[l] = 0;
+  for (int32_t p = a; p < e; p++) ptr[lv[p] + 1]++;
+  ptr[0] = a;
+  for (int32_t l = 1; l <= depth; l++) ptr[l] += ptr[l - 1];
+  // place rows, using ptr[l] as the cursor of level l (it ends at the start of level l + 1), then shift back
+  for (int32_t p = a; p < e; p++) sched[ptr[lv[p]]++] = p;
+  for (int32_t l = depth; l >= 1; l--) ptr[l] = ptr[l - 1];
+  ptr[0] = a;
+}
+
 // ---------------------------------------------------------------------------------------------------------------
 // Galerkin operators
 
@@ -675,6 +734,50 @@ static amg_status build_single_level(amg_hierarchy *h, const int64_t *row_ptr, c
   return build_coarsest_inverse(h, dense, n);
 }
 
+static amg_status build_big_cells(amg_hierarchy *h) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  const int64_t n = h->n;
+  const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
+  int32_t *flag = dalloc_n<int32_t>(h, nL);
+  int32_t *pos = dalloc_n<int32_t>(h, nL + 1);
+  if (!flag || !pos) return AMG_ERR_NOMEM;
+  k_big_flag<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, flag);
+  QA_LAUNCH_CHECK();
+  QA_TRY(scan_exclusive_i32(flag, pos, nL, s, h));
+  int32_t bc[5];
+  for (int c = 0; c < 5; c++)
+    QA_HIP(hipMemcpyAsync(&bc[c], pos + c * (nL / 4), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  QA_HIP(hipStreamSynchronize(s));
+  for (int c = 0; c < 5; c++) F.big_color[c] = bc[c];
+  F.nbig = bc[4];
+  if (F.nbig == 0) return AMG_OK;
+  F.big_cells = dalloc_n<int32_t>(h, F.nbig);
+  int32_t *lv = dalloc_n<int32_t>(h, n);
+  int32_t *cnt = dalloc_n<int32_t>(h, F.nbig);
+  if (!F.big_cells || !lv || !cnt) return AMG_ERR_NOMEM;
+  k_big_list<<<nblk(nL), kBlock, 0, s>>>(nL, flag, pos, F.big_cells);
+  for (int dir = 0; dir < 2; dir++) {
+    if (dir == 0)
+      k_big_levels<true><<<nblk(F.nbig), kBlock, 0, s>>>(F.nbig, F.big_cells, F.crow, F.ic_ptr, F.ic_col, lv, cnt);
+    else
+      k_big_levels<false><<<nblk(F.nbig), kBlock, 0, s>>>(F.nbig, F.big_cells, F.crow, F.ic_ptr, F.ic_col, lv, cnt);
+    F.big_lofs[dir] = dalloc_n<int32_t>(h, F.nbig + 1);
+    if (!F.big_lofs[dir]) return AMG_ERR_NOMEM;
+    QA_TRY(scan_exclusive_i32(cnt, F.big_lofs[dir], F.nbig, s, h));
+    int32_t total = 0;
+    QA_HIP(hipMemcpyAsync(&total, F.big_lofs[dir] + F.nbig, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
+    F.big_lptr[dir] = dalloc_n<int32_t>(h, total);
+    F.big_sched[dir] = dalloc_n<int32_t>(h, n);
+    if (!F.big_lptr[dir] || !F.big_sched[dir]) return AMG_ERR_NOMEM;
+    k_big_sched<<<nblk(F.nbig), kBlock, 0, s>>>(F.nbig, F.big_cells, F.crow, lv, F.big_lofs[dir], F.big_lptr[dir],
+                                                F.big_sched[dir]);
+    QA_LAUNCH_CHECK();
+  }
+  return AMG_OK;
+}
+
 static amg_status build_multi_level(amg_hierarchy *h, const double *coords, const int64_t *row_ptr,
                                     const int32_t *col_idx, const double *vals, int64_t nnz) {
   FineLevel &F = h->fine;
@@ -746,6 +849,7 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
     k_convert<double, float><<<nblk(F.ic_nnz), kBlock, 0, s>>>(F.ic_nnz, F.ic_val64, F.ic_val32);
     QA_LAUNCH_CHECK();
   }
+  QA_TRY(build_big_cells(h));
 
   // Galerkin operators, level L first, then coarser
   h->lev.assign(h->nlev, QuadLevel{});

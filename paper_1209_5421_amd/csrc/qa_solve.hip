@@ -264,6 +264,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_subst(const int32_t *__restrict
   const int64_t q = q_begin + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= q_end) return;
   const int32_t a = crow[q], b = crow[q + 1];
+  if (b - a > kBigCell) return;  // k_fine_subst_big
   if (FWD) {
     for (int32_t p = a; p < b; p++) {
       T acc = src[p];
@@ -284,6 +285,39 @@ __global__ void __launch_bounds__(kBlock) k_fine_subst(const int32_t *__restrict
     }
   }
   for (int32_t p = a; p < b; p++) x[p] += d[p];
+}
+
+// The same substitution for the big cells of one color, one workgroup per cell: rows are taken level by level of the
+// cell's dependency schedule (the rows of a level use only values of earlier levels), with a barrier between levels;
+// each row's arithmetic is the thread-per-cell kernel's, so the results are identical. Global memory is coherent
+// within a workgroup at the barrier (all its wavefronts share one CU).
+template <class T, bool FWD>
+__global__ void __launch_bounds__(kBlock) k_fine_subst_big(const int32_t *__restrict__ crow,
+                                                            const int32_t *__restrict__ icp,
+                                                            const int32_t *__restrict__ icc,
+                                                            const T *__restrict__ icv, const T *__restrict__ diag,
+                                                            const T *src, T *d, T *__restrict__ x,
+                                                            const int32_t *__restrict__ cells, int64_t b_begin,
+                                                            const int32_t *__restrict__ lofs,
+                                                            const int32_t *__restrict__ lptr,
+                                                            const int32_t *__restrict__ sched) {
+  const int64_t b = b_begin + blockIdx.x;
+  const int32_t q = cells[b];
+  const int32_t a = crow[q], e = crow[q + 1];
+  const int32_t l0 = lofs[b], l1 = lofs[b + 1];
+  for (int32_t lv = l0; lv + 1 < l1; lv++) {
+    for (int32_t i = lptr[lv] + static_cast<int32_t>(threadIdx.x); i < lptr[lv + 1]; i += kBlock) {
+      const int32_t p = sched[i];
+      T acc = src[p];
+      for (int32_t k = icp[p]; k < icp[p + 1]; k++) {
+        const int32_t c = icc[k];
+        if (FWD ? c < p : c > p) acc -= icv[k] * d[c];
+      }
+      d[p] = acc / diag[p];
+    }
+    __syncthreads();
+  }
+  for (int32_t p = a + static_cast<int32_t>(threadIdx.x); p < e; p += kBlock) x[p] += d[p];
 }
 
 // g[q] = sum of d over the rows of level-L cell q (rows ascending)
@@ -1729,6 +1763,18 @@ static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd
   else
     k_fine_subst<T, false><<<nblk(nL4), kBlock, 0, h->stream>>>(F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F),
                                                                  P<T>::diag(F), src, d, u, q0, q1);
+  const int64_t b0 = F.big_color[c], nb = F.big_color[c + 1] - b0;
+  if (nb > 0) {
+    const int dir = fwd ? 0 : 1;
+    if (fwd)
+      k_fine_subst_big<T, true><<<static_cast<unsigned>(nb), kBlock, 0, h->stream>>>(
+          F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F), P<T>::diag(F), src, d, u, F.big_cells, b0, F.big_lofs[dir],
+          F.big_lptr[dir], F.big_sched[dir]);
+    else
+      k_fine_subst_big<T, false><<<static_cast<unsigned>(nb), kBlock, 0, h->stream>>>(
+          F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F), P<T>::diag(F), src, d, u, F.big_cells, b0, F.big_lofs[dir],
+          F.big_lptr[dir], F.big_sched[dir]);
+  }
 }
 
 // B^_F on the fine level (f, u in permuted numbering)
