@@ -22,7 +22,7 @@ namespace qa {
 constexpr int kBlock = 256;        // threads per workgroup for elementwise / reduction kernels
 constexpr int kSliceRows = 64;     // sliced-ELL slice height = one wavefront
 constexpr int kRedBlocksMax = 1024;
-constexpr int kBigCell = 24;        // cells with more unknowns get a level-scheduled in-cell substitution
+constexpr int kBigCell = 10;        // cells with more unknowns get a level-scheduled in-cell substitution
 constexpr int kScalars = 16;       // device scalars per level
 
 // ---------------------------------------------------------------------------------------------------------------

@@ -123,12 +123,16 @@ __global__ void __launch_bounds__(kBlock) k_scatter(int64_t n, const int32_t *__
   perm[crow[q] + atomicAdd(&fill[q], 1)] = static_cast<int32_t>(i);
 }
 
-// restore ascending caller order inside each cell (the scatter order is arbitrary)
+// restore ascending caller order inside each cell (the scatter order is arbitrary): insertion sort, one thread per
+// cell of at most kSortCell unknowns (larger cells: k_rank_sort_cells)
+constexpr int kSortCell = 32;
+
 __global__ void __launch_bounds__(kBlock) k_sort_cells(int64_t ncell, const int32_t *__restrict__ crow,
                                                         int32_t *__restrict__ perm) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= ncell) return;
   const int32_t a = crow[q], b = crow[q + 1];
+  if (b - a > kSortCell) return;
   for (int32_t i = a + 1; i < b; i++) {
     const int32_t v = perm[i];
     int32_t j = i - 1;
@@ -137,6 +141,28 @@ __global__ void __launch_bounds__(kBlock) k_sort_cells(int64_t ncell, const int3
       j--;
     }
     perm[j + 1] = v;
+  }
+}
+
+// the same for one large cell per workgroup: each entry's place is the number of smaller entries in the cell (the
+// entries are distinct unknown indices), read from a copy staged in LDS when the cell fits
+constexpr int kRankLds = 8192;
+
+__global__ void __launch_bounds__(kBlock) k_rank_sort_cells(const int32_t *__restrict__ cells,
+                                                             const int32_t *__restrict__ crow,
+                                                             const int32_t *__restrict__ in, int32_t *__restrict__ out) {
+  __shared__ int32_t v[kRankLds];
+  const int32_t q = cells[blockIdx.x];
+  const int32_t a = crow[q], m = crow[q + 1] - a;
+  const bool lds = m <= kRankLds;
+  if (lds)
+    for (int32_t i = threadIdx.x; i < m; i += kBlock) v[i] = in[a + i];
+  __syncthreads();
+  for (int32_t i = threadIdx.x; i < m; i += kBlock) {
+    const int32_t x = in[a + i];
+    int32_t r = 0;
+    for (int32_t j = 0; j < m; j++) r += ((lds ? v[j] : in[a + j]) < x) ? 1 : 0;
+    out[a + r] = x;
   }
 }
 
@@ -273,10 +299,10 @@ __global__ void __launch_bounds__(kBlock) k_ic_fill(int64_t n, const int64_t *__
 // of a cell takes its rows in ascending order and row p uses the new values of the coupled rows c < p; its
 // dependency level is 1 + the largest level among those rows (0 if none), and rows of one level are independent.
 // Backward: descending order, c > p. One thread per big cell (sequential over the cell, once at setup).
-__global__ void __launch_bounds__(kBlock) k_big_flag(int64_t nL, const int32_t *__restrict__ crow,
+__global__ void __launch_bounds__(kBlock) k_big_flag(int64_t nL, const int32_t *__restrict__ crow, int32_t threshold,
                                                       int32_t *__restrict__ flag) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q < nL) flag[q] = (crow[q + 1] - crow[q]) > kBigCell ? 1 : 0;
+  if (q < nL) flag[q] = (crow[q + 1] - crow[q]) > threshold ? 1 : 0;
 }
 
 __global__ void __launch_bounds__(kBlock) k_big_list(int64_t nL, const int32_t *__restrict__ flag,
@@ -734,29 +760,42 @@ static amg_status build_single_level(amg_hierarchy *h, const int64_t *row_ptr, c
   return build_coarsest_inverse(h, dense, n);
 }
 
-static amg_status build_big_cells(amg_hierarchy *h) {
+// cells of more than `threshold` unknowns, ascending: *cells (device), *count, and the first of each color in
+// first[0..4] (first[4] = count)
+static amg_status cell_list(amg_hierarchy *h, int32_t threshold, int32_t **cells, int64_t *count, int64_t first[5]) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
-  const int64_t n = h->n;
   const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
   int32_t *flag = dalloc_n<int32_t>(h, nL);
   int32_t *pos = dalloc_n<int32_t>(h, nL + 1);
   if (!flag || !pos) return AMG_ERR_NOMEM;
-  k_big_flag<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, flag);
+  k_big_flag<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, threshold, flag);
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i32(flag, pos, nL, s, h));
   int32_t bc[5];
   for (int c = 0; c < 5; c++)
     QA_HIP(hipMemcpyAsync(&bc[c], pos + c * (nL / 4), sizeof(int32_t), hipMemcpyDeviceToHost, s));
   QA_HIP(hipStreamSynchronize(s));
-  for (int c = 0; c < 5; c++) F.big_color[c] = bc[c];
-  F.nbig = bc[4];
+  for (int c = 0; c < 5; c++) first[c] = bc[c];
+  *count = bc[4];
+  *cells = nullptr;
+  if (*count == 0) return AMG_OK;
+  *cells = dalloc_n<int32_t>(h, *count);
+  if (!*cells) return AMG_ERR_NOMEM;
+  k_big_list<<<nblk(nL), kBlock, 0, s>>>(nL, flag, pos, *cells);
+  QA_LAUNCH_CHECK();
+  return AMG_OK;
+}
+
+static amg_status build_big_cells(amg_hierarchy *h) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  const int64_t n = h->n;
+  QA_TRY(cell_list(h, kBigCell, &F.big_cells, &F.nbig, F.big_color));
   if (F.nbig == 0) return AMG_OK;
-  F.big_cells = dalloc_n<int32_t>(h, F.nbig);
   int32_t *lv = dalloc_n<int32_t>(h, n);
   int32_t *cnt = dalloc_n<int32_t>(h, F.nbig);
-  if (!F.big_cells || !lv || !cnt) return AMG_ERR_NOMEM;
-  k_big_list<<<nblk(nL), kBlock, 0, s>>>(nL, flag, pos, F.big_cells);
+  if (!lv || !cnt) return AMG_ERR_NOMEM;
   for (int dir = 0; dir < 2; dir++) {
     if (dir == 0)
       k_big_levels<true><<<nblk(F.nbig), kBlock, 0, s>>>(F.nbig, F.big_cells, F.crow, F.ic_ptr, F.ic_col, lv, cnt);
@@ -811,6 +850,19 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
   QA_LAUNCH_CHECK();
   k_sort_cells<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, F.perm);
   QA_LAUNCH_CHECK();
+  {
+    int32_t *large = nullptr;
+    int64_t nlarge = 0, first[5];
+    QA_TRY(cell_list(h, kSortCell, &large, &nlarge, first));
+    if (nlarge > 0) {
+      int32_t *sorted = dalloc_n<int32_t>(h, n);
+      if (!sorted) return AMG_ERR_NOMEM;
+      QA_HIP(hipMemcpyAsync(sorted, F.perm, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+      k_rank_sort_cells<<<static_cast<unsigned>(nlarge), kBlock, 0, s>>>(large, F.crow, F.perm, sorted);
+      QA_LAUNCH_CHECK();
+      F.perm = sorted;
+    }
+  }
   k_inverse_perm<<<nblk(n), kBlock, 0, s>>>(n, F.perm, key, F.iperm, F.agg_q, row_ptr, len);
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i64(len, F.rp, n, s, h));

@@ -287,12 +287,15 @@ __global__ void __launch_bounds__(kBlock) k_fine_subst(const int32_t *__restrict
   for (int32_t p = a; p < b; p++) x[p] += d[p];
 }
 
-// The same substitution for the big cells of one color, one workgroup per cell: rows are taken level by level of the
-// cell's dependency schedule (the rows of a level use only values of earlier levels), with a barrier between levels;
+// The same substitution for the big cells of one color, one wavefront-sized workgroup per cell (barriers between
+// levels are then nearly free): rows are taken level by level of the cell's dependency schedule (the rows of a level
+// use only values of earlier levels), with a barrier between levels;
 // each row's arithmetic is the thread-per-cell kernel's, so the results are identical. Global memory is coherent
 // within a workgroup at the barrier (all its wavefronts share one CU).
+constexpr int kSubstLanes = 64;
+
 template <class T, bool FWD>
-__global__ void __launch_bounds__(kBlock) k_fine_subst_big(const int32_t *__restrict__ crow,
+__global__ void __launch_bounds__(kSubstLanes) k_fine_subst_big(const int32_t *__restrict__ crow,
                                                             const int32_t *__restrict__ icp,
                                                             const int32_t *__restrict__ icc,
                                                             const T *__restrict__ icv, const T *__restrict__ diag,
@@ -306,7 +309,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_subst_big(const int32_t *__rest
   const int32_t a = crow[q], e = crow[q + 1];
   const int32_t l0 = lofs[b], l1 = lofs[b + 1];
   for (int32_t lv = l0; lv + 1 < l1; lv++) {
-    for (int32_t i = lptr[lv] + static_cast<int32_t>(threadIdx.x); i < lptr[lv + 1]; i += kBlock) {
+    for (int32_t i = lptr[lv] + static_cast<int32_t>(threadIdx.x); i < lptr[lv + 1]; i += kSubstLanes) {
       const int32_t p = sched[i];
       T acc = src[p];
       for (int32_t k = icp[p]; k < icp[p + 1]; k++) {
@@ -317,7 +320,7 @@ __global__ void __launch_bounds__(kBlock) k_fine_subst_big(const int32_t *__rest
     }
     __syncthreads();
   }
-  for (int32_t p = a + static_cast<int32_t>(threadIdx.x); p < e; p += kBlock) x[p] += d[p];
+  for (int32_t p = a + static_cast<int32_t>(threadIdx.x); p < e; p += kSubstLanes) x[p] += d[p];
 }
 
 // g[q] = sum of d over the rows of level-L cell q (rows ascending)
@@ -1767,11 +1770,11 @@ static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd
   if (nb > 0) {
     const int dir = fwd ? 0 : 1;
     if (fwd)
-      k_fine_subst_big<T, true><<<static_cast<unsigned>(nb), kBlock, 0, h->stream>>>(
+      k_fine_subst_big<T, true><<<static_cast<unsigned>(nb), kSubstLanes, 0, h->stream>>>(
           F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F), P<T>::diag(F), src, d, u, F.big_cells, b0, F.big_lofs[dir],
           F.big_lptr[dir], F.big_sched[dir]);
     else
-      k_fine_subst_big<T, false><<<static_cast<unsigned>(nb), kBlock, 0, h->stream>>>(
+      k_fine_subst_big<T, false><<<static_cast<unsigned>(nb), kSubstLanes, 0, h->stream>>>(
           F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F), P<T>::diag(F), src, d, u, F.big_cells, b0, F.big_lofs[dir],
           F.big_lptr[dir], F.big_sched[dir]);
   }
