@@ -20,7 +20,8 @@
 namespace qa {
 
 constexpr int kBlock = 256;        // threads per workgroup for elementwise / reduction kernels
-constexpr int kSliceRows = 64;     // sliced-ELL slice height = one wavefront
+constexpr int kSliceRows = 64;
+constexpr int kSellWindow = 256;    // rows are sorted by length inside windows of this many positions (4 slices)     // sliced-ELL slice height = one wavefront
 constexpr int kRedBlocksMax = 1024;
 constexpr int kBigCell = 10;        // cells with more unknowns get a level-scheduled in-cell substitution
 constexpr int kScalars = 16;       // device scalars per level
@@ -133,6 +134,7 @@ struct FineLevel {
   int64_t *slice_ptr = nullptr; // nslices + 1 (entry offsets)
   int32_t *slice_row0 = nullptr;// nslices + 1 (first row)
   int32_t *s_col = nullptr;
+  int32_t *s_row = nullptr;     // SELL position -> row: rows sorted by length within windows of kSellWindow
   double *s_val64 = nullptr;
   float *s_val32 = nullptr;
   int64_t sell_entries = 0;

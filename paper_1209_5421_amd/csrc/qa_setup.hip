@@ -214,9 +214,29 @@ __device__ inline int region_of_slice(const Regions &R, int64_t s) {
   return (s >= R.slice[1]) + (s >= R.slice[2]) + (s >= R.slice[3]);
 }
 
+// Rows of each window of kSellWindow positions inside a color region, sorted by length (longest first, ascending
+// row among equal lengths), so that the four 64-row slices of a window hold rows of similar length and the padding
+// of sliced ELL stays small (sliced ELL with sorting windows, "SELL-C-sigma"). One thread per window.
+__global__ void __launch_bounds__(kBlock) k_sell_sort(int64_t begin, int64_t end, const int64_t *__restrict__ rp,
+                                                       int32_t *__restrict__ s_row) {
+  const int64_t w0 = begin + (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * kSellWindow;
+  if (w0 >= end) return;
+  const int64_t w1 = min(w0 + static_cast<int64_t>(kSellWindow), end);
+  int64_t lo = INT64_MAX, hi = 0;
+  for (int64_t p = w0; p < w1; p++) {
+    const int64_t len = rp[p + 1] - rp[p];
+    lo = min(lo, len);
+    hi = max(hi, len);
+  }
+  int64_t pos = w0;
+  for (int64_t len = hi; len >= lo; len--)
+    for (int64_t p = w0; p < w1; p++)
+      if (rp[p + 1] - rp[p] == len) s_row[pos++] = static_cast<int32_t>(p);
+}
+
 __global__ void __launch_bounds__(kBlock) k_slice_meta(Regions R, int64_t nslices, const int64_t *__restrict__ rp,
-                                                        const int32_t *__restrict__ ci, int32_t *__restrict__ row0,
-                                                        int64_t *__restrict__ size) {
+                                                        const int32_t *__restrict__ ci, const int32_t *__restrict__ s_row,
+                                                        int32_t *__restrict__ row0, int64_t *__restrict__ size) {
   const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (s > nslices) return;
   if (s == nslices) {
@@ -229,7 +249,8 @@ __global__ void __launch_bounds__(kBlock) k_slice_meta(Regions R, int64_t nslice
   const int64_t r0 = R.row[c] + (s - R.slice[c]) * kSliceRows;
   const int64_t r1 = min(r0 + kSliceRows, R.row[c + 1]);
   int64_t w = 1;
-  for (int64_t p = r0; p < r1; p++) {
+  for (int64_t pos = r0; pos < r1; pos++) {
+    const int64_t p = s_row[pos];
     int64_t offd = 0;
     for (int64_t e = rp[p]; e < rp[p + 1]; e++) offd += (ci[e] != p);
     w = max(w, offd + 1);
@@ -242,12 +263,14 @@ __global__ void __launch_bounds__(kBlock) k_fill_sell(Regions R, int64_t n, cons
                                                        const int32_t *__restrict__ ci, const double *__restrict__ va,
                                                        const double *__restrict__ diag,
                                                        const int64_t *__restrict__ slice_ptr,
+                                                       const int32_t *__restrict__ s_row,
                                                        int32_t *__restrict__ s_col, double *__restrict__ s_val) {
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+  const int64_t pos = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (pos >= n) return;
+  const int64_t p = s_row[pos];  // the row at this position
   int c = 0;
-  while (c < 3 && p >= R.row[c + 1]) c++;
-  const int64_t rel = p - R.row[c];
+  while (c < 3 && pos >= R.row[c + 1]) c++;
+  const int64_t rel = pos - R.row[c];
   const int64_t s = R.slice[c] + rel / kSliceRows;
   const int lane = static_cast<int>(rel % kSliceRows);
   const int64_t off = slice_ptr[s];
@@ -697,8 +720,14 @@ static amg_status build_sell(amg_hierarchy *h) {
   int64_t *size = dalloc_n<int64_t>(h, F.nslices + 1);
   F.slice_row0 = dalloc_n<int32_t>(h, F.nslices + 1);
   F.slice_ptr = dalloc_n<int64_t>(h, F.nslices + 1);
-  if (!size || !F.slice_row0 || !F.slice_ptr) return AMG_ERR_NOMEM;
-  k_slice_meta<<<nblk(F.nslices + 1), kBlock, 0, s>>>(R, F.nslices, F.rp, F.ci, F.slice_row0, size);
+  F.s_row = dalloc_n<int32_t>(h, F.n);
+  if (!size || !F.slice_row0 || !F.slice_ptr || !F.s_row) return AMG_ERR_NOMEM;
+  for (int c = 0; c < 4; c++) {
+    const int64_t windows = (F.color_row[c + 1] - F.color_row[c] + kSellWindow - 1) / kSellWindow;
+    if (windows > 0)
+      k_sell_sort<<<nblk(windows), kBlock, 0, s>>>(F.color_row[c], F.color_row[c + 1], F.rp, F.s_row);
+  }
+  k_slice_meta<<<nblk(F.nslices + 1), kBlock, 0, s>>>(R, F.nslices, F.rp, F.ci, F.s_row, F.slice_row0, size);
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i64(size, F.slice_ptr, F.nslices, s, h));
   QA_HIP(hipMemcpyAsync(&F.sell_entries, F.slice_ptr + F.nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -707,7 +736,8 @@ static amg_status build_sell(amg_hierarchy *h) {
   F.s_val64 = dalloc_n<double>(h, F.sell_entries);
   F.s_val32 = dalloc_n<float>(h, F.sell_entries);
   if (!F.s_col || !F.s_val64 || !F.s_val32) return AMG_ERR_NOMEM;
-  k_fill_sell<<<nblk(F.n), kBlock, 0, s>>>(R, F.n, F.rp, F.ci, F.va, F.diag64, F.slice_ptr, F.s_col, F.s_val64);
+  k_fill_sell<<<nblk(F.n), kBlock, 0, s>>>(R, F.n, F.rp, F.ci, F.va, F.diag64, F.slice_ptr, F.s_row, F.s_col,
+                                            F.s_val64);
   QA_LAUNCH_CHECK();
   k_convert<double, float><<<nblk(F.sell_entries), kBlock, 0, s>>>(F.sell_entries, F.s_val64, F.s_val32);
   QA_LAUNCH_CHECK();

@@ -144,7 +144,8 @@ struct Pending {
 template <class T>
 struct SellView {
   const int64_t *ptr;
-  const int32_t *row0;
+  const int32_t *row0;    // first position of each slice
+  const int32_t *srow;    // position -> row
   const int32_t *col;
   const T *val;
 };
@@ -214,8 +215,8 @@ __device__ inline void fine_resid_body(const SellView<T> &S, const SliceSched &Z
   if (s < 0) return;
   const int lane = threadIdx.x & 63;
   const int32_t r0 = S.row0[s], r1 = S.row0[s + 1];
-  const int32_t row = r0 + lane;
-  if (row >= r1) return;
+  if (r0 + lane >= r1) return;
+  const int32_t row = S.srow[r0 + lane];
   const int64_t off = S.ptr[s];
   const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
   const T acc = sell_row<T, T>(S, off, w, lane, x);
@@ -243,8 +244,8 @@ __global__ void __launch_bounds__(kBlock) k_fine_apply(SellView<T> S, SliceSched
   const int64_t s = sched_slice(Z);
   if (s < 0) return;
   const int lane = threadIdx.x & 63;
-  const int32_t row = S.row0[s] + lane;
-  if (row >= S.row0[s + 1]) return;
+  if (S.row0[s] + lane >= S.row0[s + 1]) return;
+  const int32_t row = S.srow[S.row0[s] + lane];
   const int64_t off = S.ptr[s];
   const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
   const T acc = sell_row<T, T>(S, off, w, lane, x);
@@ -562,8 +563,8 @@ __global__ void __launch_bounds__(kBlock) k_outer_spmv_dot(SellView<double> S, S
   const int lane = threadIdx.x & 63;
   double v[2] = {0.0, 0.0};
   if (s >= 0) {
-    const int32_t row = S.row0[s] + lane;
-    if (row < S.row0[s + 1]) {
+    if (S.row0[s] + lane < S.row0[s + 1]) {
+      const int32_t row = S.srow[S.row0[s] + lane];
       const int64_t off = S.ptr[s];
       const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
       const double acc = sell_row<double, double>(S, off, w, lane, p);
@@ -584,8 +585,8 @@ __global__ void __launch_bounds__(kBlock) k_outer_true_resid(SellView<double> S,
   const int lane = threadIdx.x & 63;
   double v[1] = {0.0};
   if (s >= 0) {
-    const int32_t row = S.row0[s] + lane;
-    if (row < S.row0[s + 1]) {
+    if (S.row0[s] + lane < S.row0[s + 1]) {
+      const int32_t row = S.srow[S.row0[s] + lane];
       const int64_t off = S.ptr[s];
       const int w = static_cast<int>((S.ptr[s + 1] - off) >> 6);
       const double acc = sell_row<double, double>(S, off, w, lane, x);
@@ -698,7 +699,7 @@ static QView<T> qview(const QuadLevel &Q) {
 }
 template <class T>
 static SellView<T> sview(const FineLevel &F, const T *val) {
-  return SellView<T>{F.slice_ptr, F.slice_row0, F.s_col, val};
+  return SellView<T>{F.slice_ptr, F.slice_row0, F.s_row, F.s_col, val};
 }
 static Red red(amg_hierarchy *h, int l, int epi, int slot = 0) {
   return Red{h->partials, h->scal + static_cast<size_t>(l) * kScalars, epi, slot};
@@ -1404,7 +1405,7 @@ struct WgSys {
   int n, L, nslices;
   int64_t color_row[5], color_slice[5];
   const int64_t *slice_ptr;
-  const int32_t *slice_row0, *s_col;
+  const int32_t *slice_row0, *s_row, *s_col;
   const T *s_val;             // preconditioner precision
   const double *s_val64;      // outer FP64 operator
   const T *diag;
@@ -1423,12 +1424,12 @@ struct WgSys {
 
 // residual of the rows of slices [s0, s1) (one wavefront per slice, strided over the workgroup's wavefronts)
 template <class V, class X>
-__device__ inline void wg_resid(const int64_t *sp, const int32_t *r0, const int32_t *col, const V *val, const X *f,
-                                const X *x, X *d, int64_t s0, int64_t s1) {
+__device__ inline void wg_resid(const int64_t *sp, const int32_t *r0, const int32_t *srow, const int32_t *col,
+                                const V *val, const X *f, const X *x, X *d, int64_t s0, int64_t s1) {
   const int lane = threadIdx.x & 63;
   for (int64_t s = s0 + (threadIdx.x >> 6); s < s1; s += kEngWaves) {
-    const int32_t row = r0[s] + lane;
-    if (row >= r0[s + 1]) continue;
+    if (r0[s] + lane >= r0[s + 1]) continue;
+    const int32_t row = srow[r0[s] + lane];
     const int64_t off = sp[s];
     const int w = static_cast<int>((sp[s + 1] - off) >> 6);
     X acc = 0;
@@ -1467,7 +1468,7 @@ __device__ inline void wg_subst(const WgSys<T> &Y, const T *src, T *d, T *x, int
 template <class T>
 __device__ inline void wg_fine_phase(const WgSys<T> &Y, const T *f, T *u, int c, bool fwd, bool from_f) {
   if (!from_f) {
-    wg_resid(Y.slice_ptr, Y.slice_row0, Y.s_col, Y.s_val, f, u, Y.d, Y.color_slice[c], Y.color_slice[c + 1]);
+    wg_resid(Y.slice_ptr, Y.slice_row0, Y.s_row, Y.s_col, Y.s_val, f, u, Y.d, Y.color_slice[c], Y.color_slice[c + 1]);
     __syncthreads();
   }
   wg_subst(Y, from_f ? f : Y.d, Y.d, u, c, fwd);
@@ -1488,7 +1489,7 @@ __device__ void wg_bhat_fine(const WgSys<T> &Y, const EngOp *ops, const EngLevel
   __syncthreads();
   for (int sw = 0; sw < Y.sweeps; sw++)
     for (int c = 0; c < 4; c++) wg_fine_phase(Y, f, u, c, true, sw == 0 && c == 0);
-  wg_resid(Y.slice_ptr, Y.slice_row0, Y.s_col, Y.s_val, f, u, Y.d, 0, Y.nslices);
+  wg_resid(Y.slice_ptr, Y.slice_row0, Y.s_row, Y.s_col, Y.s_val, f, u, Y.d, 0, Y.nslices);
   __syncthreads();
   T *g0 = wg_engine_vec(LV[0], S, EV_G);
   const int nL = LV[0].n;
@@ -1507,13 +1508,14 @@ __device__ void wg_bhat_fine(const WgSys<T> &Y, const EngOp *ops, const EngLevel
 }
 
 // q = A p (FP64) with (p, q) and (r, p), or the true residual t = b - A x with (t, t)
-__device__ inline void wg_spmv64(const int64_t *sp, const int32_t *r0, const int32_t *col, const double *val,
-                                 int64_t ns, const double *p, double *q, const double *r, double (&v)[2]) {
+__device__ inline void wg_spmv64(const int64_t *sp, const int32_t *r0, const int32_t *srow, const int32_t *col,
+                                 const double *val, int64_t ns, const double *p, double *q, const double *r,
+                                 double (&v)[2]) {
   const int lane = threadIdx.x & 63;
   v[0] = 0.0; v[1] = 0.0;
   for (int64_t s = threadIdx.x >> 6; s < ns; s += kEngWaves) {
-    const int32_t row = r0[s] + lane;
-    if (row >= r0[s + 1]) continue;
+    if (r0[s] + lane >= r0[s + 1]) continue;
+    const int32_t row = srow[r0[s] + lane];
     const int64_t off = sp[s];
     const int w = static_cast<int>((sp[s + 1] - off) >> 6);
     double acc = 0.0;
@@ -1582,7 +1584,7 @@ __global__ void __launch_bounds__(kEngThreads) k_solve_wg(const WgSys<T> *system
       for (int i = tid; i < n; i += kEngThreads) p[i] = (have_prev && Y.mmax == 1) ? Y.zp[i] + beta * pprev[i] : Y.zp[i];
       __syncthreads();
       double v2[2];
-      wg_spmv64(Y.slice_ptr, Y.slice_row0, Y.s_col, Y.s_val64, Y.nslices, p, q, Y.rp, v2);
+      wg_spmv64(Y.slice_ptr, Y.slice_row0, Y.s_row, Y.s_col, Y.s_val64, Y.nslices, p, q, Y.rp, v2);
       eng_reduce<2>(v2, red);
       const double d = v2[0];
       if (!(d > 0.0)) {
@@ -1604,7 +1606,7 @@ __global__ void __launch_bounds__(kEngThreads) k_solve_wg(const WgSys<T> *system
       par ^= 1;
       if (sqrt(v3[0]) <= Y.tol * bn) {
         double v4[2];
-        wg_spmv64(Y.slice_ptr, Y.slice_row0, Y.s_col, Y.s_val64, Y.nslices, Y.xp, Y.tp, Y.xp, v4);
+        wg_spmv64(Y.slice_ptr, Y.slice_row0, Y.s_row, Y.s_col, Y.s_val64, Y.nslices, Y.xp, Y.tp, Y.xp, v4);
         __syncthreads();
         double v5[1] = {0.0};
         for (int i = tid; i < n; i += kEngThreads) {
@@ -1626,7 +1628,7 @@ __global__ void __launch_bounds__(kEngThreads) k_solve_wg(const WgSys<T> *system
   }
   // true relative residual and the solution in the caller's numbering
   double v6[2];
-  wg_spmv64(Y.slice_ptr, Y.slice_row0, Y.s_col, Y.s_val64, Y.nslices, Y.xp, Y.tp, Y.xp, v6);
+  wg_spmv64(Y.slice_ptr, Y.slice_row0, Y.s_row, Y.s_col, Y.s_val64, Y.nslices, Y.xp, Y.tp, Y.xp, v6);
   __syncthreads();
   double v7[1] = {0.0};
   for (int i = tid; i < n; i += kEngThreads) {
@@ -2108,7 +2110,7 @@ static void fill_wg(amg_hierarchy *h, const double *b, double *x, double tol, do
   Y.L = h->L;
   Y.nslices = static_cast<int>(F.nslices);
   for (int c = 0; c < 5; c++) { Y.color_row[c] = F.color_row[c]; Y.color_slice[c] = F.color_slice[c]; }
-  Y.slice_ptr = F.slice_ptr; Y.slice_row0 = F.slice_row0; Y.s_col = F.s_col;
+  Y.slice_ptr = F.slice_ptr; Y.slice_row0 = F.slice_row0; Y.s_row = F.s_row; Y.s_col = F.s_col;
   Y.s_val = P<T>::sval(F); Y.s_val64 = F.s_val64; Y.diag = P<T>::diag(F);
   Y.ic_ptr = F.ic_ptr; Y.ic_col = F.ic_col; Y.ic_val = P<T>::icv(F);
   Y.crow = F.crow; Y.agg_q = F.agg_q; Y.perm = F.perm;
