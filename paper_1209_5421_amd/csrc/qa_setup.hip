@@ -185,17 +185,29 @@ __global__ void __launch_bounds__(kBlock) k_permute_csr(int64_t n, const int32_t
                                                          const double *__restrict__ va_in, const int64_t *__restrict__ rp,
                                                          int32_t *__restrict__ ci, double *__restrict__ va,
                                                          double *__restrict__ diag) {
-  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  // eight lanes per row copy its entries (the rows arrive in permuted order, so a row's entries are the unit of
+  // contiguous access); the diagonal is summed afterwards by k_row_diag
+  const int64_t t = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t p = t >> 3;
   if (p >= n) return;
   const int32_t i = perm[p];
-  int64_t o = rp[p];
-  double dg = 0.0;
-  for (int64_t e = rp_in[i]; e < rp_in[i + 1]; e++, o++) {
-    const int32_t c = iperm[ci_in[e]];
-    ci[o] = c;
-    va[o] = va_in[e];
-    if (c == p) dg += va_in[e];
+  const int64_t e0 = rp_in[i], o0 = rp[p];
+  for (int64_t e = e0 + (t & 7); e < rp_in[i + 1]; e += 8) {
+    ci[o0 + (e - e0)] = iperm[ci_in[e]];
+    va[o0 + (e - e0)] = va_in[e];
   }
+  (void)diag;
+}
+
+// diagonal of each permuted row: its diagonal entries summed in entry order
+__global__ void __launch_bounds__(kBlock) k_row_diag(int64_t n, const int64_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci, const double *__restrict__ va,
+                                                      double *__restrict__ diag) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double dg = 0.0;
+  for (int64_t e = rp[p]; e < rp[p + 1]; e++)
+    if (ci[e] == p) dg += va[e];
   diag[p] = dg;
 }
 
@@ -217,30 +229,33 @@ __device__ inline int region_of_slice(const Regions &R, int64_t s) {
 // Rows of each window of kSellWindow positions inside a color region, sorted by length (longest first, ascending
 // row among equal lengths), so that the four 64-row slices of a window hold rows of similar length and the padding
 // of sliced ELL stays small (sliced ELL with sorting windows, "SELL-C-sigma"). One thread per window.
-__global__ void __launch_bounds__(kBlock) k_sell_sort(int64_t begin, int64_t end, const int64_t *__restrict__ rp,
-                                                       int32_t *__restrict__ s_row) {
-  const int64_t w0 = begin + (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * kSellWindow;
-  if (w0 >= end) return;
+__global__ void __launch_bounds__(kSellWindow) k_sell_sort(int64_t begin, int64_t end,
+                                                             const int64_t *__restrict__ rp,
+                                                             int32_t *__restrict__ s_row) {
+  __shared__ int32_t len[kSellWindow];
+  const int64_t w0 = begin + static_cast<int64_t>(blockIdx.x) * kSellWindow;
   const int64_t w1 = min(w0 + static_cast<int64_t>(kSellWindow), end);
-  int64_t lo = INT64_MAX, hi = 0;
-  for (int64_t p = w0; p < w1; p++) {
-    const int64_t len = rp[p + 1] - rp[p];
-    lo = min(lo, len);
-    hi = max(hi, len);
-  }
-  int64_t pos = w0;
-  for (int64_t len = hi; len >= lo; len--)
-    for (int64_t p = w0; p < w1; p++)
-      if (rp[p + 1] - rp[p] == len) s_row[pos++] = static_cast<int32_t>(p);
+  const int m = static_cast<int>(w1 - w0);
+  const int i = threadIdx.x;
+  if (i < m) len[i] = static_cast<int32_t>(rp[w0 + i + 1] - rp[w0 + i]);
+  __syncthreads();
+  if (i >= m) return;
+  // place of row i: rows that are longer, or as long and earlier, come first
+  const int32_t li = len[i];
+  int rank = 0;
+  for (int j = 0; j < m; j++) rank += (len[j] > li || (len[j] == li && j < i)) ? 1 : 0;
+  s_row[w0 + rank] = static_cast<int32_t>(w0 + i);
 }
 
 __global__ void __launch_bounds__(kBlock) k_slice_meta(Regions R, int64_t nslices, const int64_t *__restrict__ rp,
                                                         const int32_t *__restrict__ ci, const int32_t *__restrict__ s_row,
                                                         int32_t *__restrict__ row0, int64_t *__restrict__ size) {
-  const int64_t s = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  // one wavefront per slice: each lane counts the off-diagonal entries of one row, the width is their maximum + 1
+  const int64_t s = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
   if (s > nslices) return;
   if (s == nslices) {
-    row0[s] = static_cast<int32_t>(R.row[4]);
+    if (lane == 0) row0[s] = static_cast<int32_t>(R.row[4]);
     return;
   }
   // empty regions own no slices, so the region of s is found among the non-empty ones
@@ -248,15 +263,18 @@ __global__ void __launch_bounds__(kBlock) k_slice_meta(Regions R, int64_t nslice
   while (c < 3 && s >= R.slice[c + 1]) c++;
   const int64_t r0 = R.row[c] + (s - R.slice[c]) * kSliceRows;
   const int64_t r1 = min(r0 + kSliceRows, R.row[c + 1]);
-  int64_t w = 1;
-  for (int64_t pos = r0; pos < r1; pos++) {
-    const int64_t p = s_row[pos];
-    int64_t offd = 0;
+  int w = 1;
+  if (r0 + lane < r1) {
+    const int64_t p = s_row[r0 + lane];
+    int offd = 0;
     for (int64_t e = rp[p]; e < rp[p + 1]; e++) offd += (ci[e] != p);
-    w = max(w, offd + 1);
+    w = offd + 1;
   }
-  row0[s] = static_cast<int32_t>(r0);
-  size[s] = w * kSliceRows;
+  for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, 64));
+  if (lane == 0) {
+    row0[s] = static_cast<int32_t>(r0);
+    size[s] = static_cast<int64_t>(w) * kSliceRows;
+  }
 }
 
 __global__ void __launch_bounds__(kBlock) k_fill_sell(Regions R, int64_t n, const int64_t *__restrict__ rp,
@@ -424,18 +442,37 @@ __global__ void __launch_bounds__(kBlock) k_galerkin_fine(int L, int64_t nL, con
   const int64_t e0 = rp[crow[q]], e1 = rp[crow[q + 1]];
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   int32_t cnt = 0;
-  for (int64_t e = e0; e < e1; e++) {
-    const uint32_t qq = static_cast<uint32_t>(agg_q[ci[e]]);
-    uint32_t u1, u2;
-    q_to_t(qq, L, u1, u2);
-    const int dx = static_cast<int>(u1) - static_cast<int>(t1), dy = static_cast<int>(u2) - static_cast<int>(t2);
-    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) {
-      add_slot(acc, slot_of(dx, dy), va[e]);
-    } else {
-      bool first = true;
-      for (int64_t e2 = e0; e2 < e; e2++)
-        if (static_cast<uint32_t>(agg_q[ci[e2]]) == qq) { first = false; break; }
-      cnt += first;
+  // the entries are gathered kGalBatch at a time so that their loads overlap; they are still summed one by one in
+  // entry order
+  constexpr int kGalBatch = 8;
+  for (int64_t eb = e0; eb < e1; eb += kGalBatch) {
+    int32_t col[kGalBatch];
+    double val[kGalBatch];
+    uint32_t agq[kGalBatch];
+#pragma unroll
+    for (int u = 0; u < kGalBatch; u++) {
+      const bool in = eb + u < e1;
+      col[u] = in ? ci[eb + u] : 0;
+      val[u] = in ? va[eb + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kGalBatch; u++) agq[u] = (eb + u < e1) ? static_cast<uint32_t>(agg_q[col[u]]) : 0u;
+#pragma unroll
+    for (int u = 0; u < kGalBatch; u++) {
+      const int64_t e = eb + u;
+      if (e >= e1) break;
+      const uint32_t qq = agq[u];
+      uint32_t u1, u2;
+      q_to_t(qq, L, u1, u2);
+      const int dx = static_cast<int>(u1) - static_cast<int>(t1), dy = static_cast<int>(u2) - static_cast<int>(t2);
+      if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) {
+        add_slot(acc, slot_of(dx, dy), val[u]);
+      } else {
+        bool first = true;
+        for (int64_t e2 = e0; e2 < e; e2++)
+          if (static_cast<uint32_t>(agg_q[ci[e2]]) == qq) { first = false; break; }
+        cnt += first;
+      }
     }
   }
   const bool emp = (crow[q] == crow[q + 1]);
@@ -630,13 +667,31 @@ __global__ void __launch_bounds__(kBlock) k_densify_csr(int64_t n, const int64_t
   for (int64_t e = rp[i]; e < rp[i + 1]; e++) dense[i * n + ci[e]] += va[e];
 }
 
-__global__ void __launch_bounds__(kBlock) k_chol_inverse(int n, double *__restrict__ a, double *__restrict__ y,
-                                                          double *__restrict__ ainv, int *flag) {
-  const int tid = threadIdx.x;
+constexpr int kCholLds = 64;
+constexpr int kCholThreads = 1024;
+
+// Dense inverse of the coarsest matrix through its Cholesky factor: A = L L^t, Y = L^{-1}, A^{-1} = Y^t Y. One
+// workgroup; every phase is spread over all its threads, and each entry receives its updates in the same order as
+// the textbook inner-product forms (increasing summation index), so the result does not depend on the thread count.
+__global__ void __launch_bounds__(kCholThreads) k_chol_inverse(int n, double *__restrict__ ag,
+                                                                double *__restrict__ yg, double *__restrict__ ainv,
+                                                                int *flag) {
+  // the factor and L^{-1} live in LDS when they fit (n <= 64: 2 x 32 KB), else in the global scratch given
+  __shared__ double al[kCholLds * kCholLds], yl[kCholLds * kCholLds];
+  const bool lds = n <= kCholLds;
+  double *a = lds ? al : ag;
+  double *y = lds ? yl : yg;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int t = tid; t < n * n; t += nt) {
+    if (lds) a[t] = ag[t];
+    y[t] = (t / n == t % n) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  // right-looking factorisation: once column j is final, entry (i, k) of the trailing lower triangle subtracts
+  // l_ij l_kj, so entry (i, j) sees the subtractions for k = 0, 1, ..., j-1 in order
   for (int j = 0; j < n; j++) {
     if (tid == 0) {
       double d = a[j * n + j];
-      for (int k = 0; k < j; k++) d -= a[j * n + k] * a[j * n + k];
       if (!(d > 0.0)) {
         atomicOr(flag, F_NOT_SPD);
         d = 1.0;
@@ -644,27 +699,29 @@ __global__ void __launch_bounds__(kBlock) k_chol_inverse(int n, double *__restri
       a[j * n + j] = sqrt(d);
     }
     __syncthreads();
-    for (int i = j + 1 + tid; i < n; i += blockDim.x) {
-      double s = a[i * n + j];
-      for (int k = 0; k < j; k++) s -= a[i * n + k] * a[j * n + k];
-      a[i * n + j] = s / a[j * n + j];
+    for (int i = j + 1 + tid; i < n; i += nt) a[i * n + j] = a[i * n + j] / a[j * n + j];
+    __syncthreads();
+    const int m = n - j - 1;
+    for (int t = tid; t < m * m; t += nt) {
+      const int i = j + 1 + t / m, k = j + 1 + t % m;
+      if (k <= i) a[i * n + k] -= a[i * n + j] * a[k * n + j];
     }
     __syncthreads();
   }
-  // Y = L^{-1}, one column per thread
-  for (int j = tid; j < n; j += blockDim.x)
-    for (int i = 0; i < n; i++) {
-      if (i < j) {
-        y[i * n + j] = 0.0;
-        continue;
-      }
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int k = j; k < i; k++) s -= a[i * n + k] * y[k * n + j];
-      y[i * n + j] = s / a[i * n + i];
+  // Y = L^{-1} by forward substitution on the identity, row by row: row i is final once divided by l_ii, and then
+  // every later row r subtracts l_ri times it (entry (r, c) sees the rows c, c+1, ..., r-1 in order)
+  for (int i = 0; i < n; i++) {
+    for (int c = tid; c <= i; c += nt) y[i * n + c] = y[i * n + c] / a[i * n + i];
+    __syncthreads();
+    const int rows = n - i - 1, cols = i + 1;
+    for (int t = tid; t < rows * cols; t += nt) {
+      const int r = i + 1 + t / cols, c = t % cols;
+      y[r * n + c] -= a[r * n + i] * y[i * n + c];
     }
-  __syncthreads();
+    __syncthreads();
+  }
   // A^{-1} = Y^t Y
-  for (int idx = tid; idx < n * n; idx += blockDim.x) {
+  for (int idx = tid; idx < n * n; idx += nt) {
     const int i = idx / n, j = idx % n;
     double s = 0.0;
     for (int k = max(i, j); k < n; k++) s += y[k * n + i] * y[k * n + j];
@@ -725,9 +782,10 @@ static amg_status build_sell(amg_hierarchy *h) {
   for (int c = 0; c < 4; c++) {
     const int64_t windows = (F.color_row[c + 1] - F.color_row[c] + kSellWindow - 1) / kSellWindow;
     if (windows > 0)
-      k_sell_sort<<<nblk(windows), kBlock, 0, s>>>(F.color_row[c], F.color_row[c + 1], F.rp, F.s_row);
+      k_sell_sort<<<static_cast<unsigned>(windows), kSellWindow, 0, s>>>(F.color_row[c], F.color_row[c + 1], F.rp,
+                                                                          F.s_row);
   }
-  k_slice_meta<<<nblk(F.nslices + 1), kBlock, 0, s>>>(R, F.nslices, F.rp, F.ci, F.s_row, F.slice_row0, size);
+  k_slice_meta<<<nblk(64 * (F.nslices + 1)), kBlock, 0, s>>>(R, F.nslices, F.rp, F.ci, F.s_row, F.slice_row0, size);
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i64(size, F.slice_ptr, F.nslices, s, h));
   QA_HIP(hipMemcpyAsync(&F.sell_entries, F.slice_ptr + F.nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -751,7 +809,7 @@ static amg_status build_coarsest_inverse(amg_hierarchy *h, const double *dense_s
   double *y = dalloc_n<double>(h, nc * nc);
   h->ainv = dalloc_n<double>(h, nc * nc);
   if (!y || !h->ainv) return AMG_ERR_NOMEM;
-  k_chol_inverse<<<1, kBlock, 0, s>>>(static_cast<int>(nc), const_cast<double *>(dense_src_filled), y, h->ainv,
+  k_chol_inverse<<<1, kCholThreads, 0, s>>>(static_cast<int>(nc), const_cast<double *>(dense_src_filled), y, h->ainv,
                                        h->dflag);
   QA_LAUNCH_CHECK();
   h->nc = nc;
@@ -779,7 +837,9 @@ static amg_status build_single_level(amg_hierarchy *h, const int64_t *row_ptr, c
   k_inverse_perm<<<nblk(n), kBlock, 0, s>>>(n, F.perm, nullptr, F.iperm, nullptr, row_ptr, len);
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i64(len, F.rp, n, s, h));
-  k_permute_csr<<<nblk(n), kBlock, 0, s>>>(n, F.perm, F.iperm, row_ptr, col_idx, vals, F.rp, F.ci, F.va, F.diag64);
+  k_permute_csr<<<nblk(8 * n), kBlock, 0, s>>>(n, F.perm, F.iperm, row_ptr, col_idx, vals, F.rp, F.ci, F.va,
+                                               F.diag64);
+  k_row_diag<<<nblk(n), kBlock, 0, s>>>(n, F.rp, F.ci, F.va, F.diag64);
   QA_LAUNCH_CHECK();
   F.color_row[0] = 0;
   for (int c = 1; c < 5; c++) F.color_row[c] = n;
@@ -896,7 +956,9 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
   k_inverse_perm<<<nblk(n), kBlock, 0, s>>>(n, F.perm, key, F.iperm, F.agg_q, row_ptr, len);
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i64(len, F.rp, n, s, h));
-  k_permute_csr<<<nblk(n), kBlock, 0, s>>>(n, F.perm, F.iperm, row_ptr, col_idx, vals, F.rp, F.ci, F.va, F.diag64);
+  k_permute_csr<<<nblk(8 * n), kBlock, 0, s>>>(n, F.perm, F.iperm, row_ptr, col_idx, vals, F.rp, F.ci, F.va,
+                                               F.diag64);
+  k_row_diag<<<nblk(n), kBlock, 0, s>>>(n, F.rp, F.ci, F.va, F.diag64);
   QA_LAUNCH_CHECK();
   // color regions: cells of color c are the quarter [c nL/4, (c+1) nL/4) of the color-major order
   {
