@@ -777,7 +777,13 @@ enum EngVec : int32_t { EV_G = 0, EV_E, EV_R, EV_P0, EV_Q0, EV_P1, EV_Q1, EV_D, 
 
 struct EngOp {
   int32_t type, lvl, color, f, u;  // f, u: vector slots of level lvl
+  int32_t fuse;                    // EngFuse bits
 };
+// Steps folded into their neighbours in the step list of B~ (each value equal to what the separate step stores):
+// FUSE_UPD1 on the first step of the second B^: the update e = a0 p0, r = g - a0 q0 is written there, and that
+// step reads its right-hand side r as g - a0 q0 formed on the fly; FUSE_BETA on the last step of that B^: the inner
+// product (p1, q0) and beta are formed after a barrier at its end.
+enum EngFuse : int32_t { FUSE_UPD1 = 1, FUSE_BETA = 2 };
 
 template <class T>
 struct EngLevel {
@@ -862,6 +868,98 @@ struct EngCtx {
   double *red;
 };
 
+// r = g - a0 q0 of the first inner update (one expression, so the separate and the folded forms round alike)
+template <class T>
+__device__ __forceinline__ T upd1_r(T g, T a0, T q0) {
+  return g - a0 * q0;
+}
+
+// the first inner update of Algorithm 2.1 on an engine level, as a value source (r) and a store of e and r
+template <class T, bool LDS>
+struct EngUpd1 {
+  T a0;
+  const T *g, *q0, *p0;
+  T *e, *r;
+  __device__ EngUpd1(const EngMem<T, LDS> &M, const EngCtx &C)
+      : a0(static_cast<T>(C.sc[ES_A0])), g(M.vec(EV_G)), q0(M.vec(EV_Q0)), p0(M.vec(EV_P0)), e(M.vec(EV_E)),
+        r(M.vec(EV_R)) {}
+  __device__ T rv(uint32_t i) const { return upd1_r(g[i], a0, q0[i]); }
+  __device__ void store(int i) const {
+    e[i] = a0 * p0[i];
+    r[i] = upd1_r(g[i], a0, q0[i]);
+  }
+};
+
+// beta = -(p1, q0) / d0 of Algorithm 2.1 (every thread calls it; the reduction tree is fixed)
+template <class T, bool LDS>
+__device__ __forceinline__ void eng_dot_beta(const EngMem<T, LDS> &M, int n, const EngCtx &C) {
+  const T *p1 = M.vec(EV_P1), *q0 = M.vec(EV_Q0);
+  double t[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += kEngThreads) t[0] += static_cast<double>(p1[i]) * static_cast<double>(q0[i]);
+  eng_reduce<1>(t, C.red);
+  if (threadIdx.x == 0) C.sc[ES_BETA] = (C.sc[ES_STOP] != 0.0) ? 0.0 : -t[0] / C.sc[ES_D0];
+}
+
+// the first two phases of a sweep from zero (levels without same-color couplings): color 0 takes u = f / diag, and
+// the color-1 rows read those values formed on the fly (colors 2 and 3 are still 0); no thread reads u here, so
+// the writes of colors 0, 2 and 3 go alongside. `each` runs once per row (the folded first inner update).
+template <class T, class FV, class EACH>
+__device__ __forceinline__ void eng_gs_first2(const EngLevel<T> &L, int k, int n, const T *ax, T *u, FV fv,
+                                              EACH each) {
+  const int tid = static_cast<int>(threadIdx.x);
+  const int n4 = n >> 2;
+  const uint32_t n4u = static_cast<uint32_t>(n4);
+  auto first = [fv, ax, n4u](uint32_t i) { return i < n4u ? fv(i) / ax[i] : T(0); };
+  for (int j = tid; j < n4; j += kEngThreads) {
+    const uint32_t q = static_cast<uint32_t>(n4 + j);
+    u[q] = T(0) + (fv(q) - eng_row_f<T>(k, n, ax, L.optr, L.ocol, L.oval, q, 1, first)) / ax[q];
+  }
+  for (int q = tid; q < n; q += kEngThreads) {
+    if (q < n4) u[q] = fv(static_cast<uint32_t>(q)) / ax[q];
+    else if (q >= 2 * n4) u[q] = T(0);
+    each(q);
+  }
+}
+
+// u = B^ f with B^ precomputed as a matrix (column-major, global memory). A thread owns four consecutive rows
+// (one 16-byte load per column in FP32, two in FP64) for a run of columns; the workgroup splits the columns into
+// mhat_parts runs, and the partial sums of a row are added in a fixed order.
+template <class T, class FV, class EACH>
+__device__ __forceinline__ void eng_bhat_m(const EngPlan<T> &P, int n, T *S, T *u, FV fv, EACH each) {
+  const int tid = static_cast<int>(threadIdx.x);
+  T *part = S + P.mpart_off;
+  const int groups = n >> 2;
+  const int parts = P.mhat_parts;
+  const int cols = n / parts;
+  if (tid < groups * parts) {
+    const int g = tid % groups;
+    const int b = tid / groups;
+    const T *mc = P.mhat + static_cast<size_t>(b) * cols * n + 4 * g;
+    T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (int i = 0; i < cols; i++) {
+      const T *col = mc + static_cast<size_t>(i) * n;
+      const T fi = fv(static_cast<uint32_t>(b * cols + i));
+      if constexpr (std::is_same<T, float>::value) {
+        const float4 v = *reinterpret_cast<const float4 *>(col);
+        a0 += v.x * fi; a1 += v.y * fi; a2 += v.z * fi; a3 += v.w * fi;
+      } else {
+        const double2 v0 = *reinterpret_cast<const double2 *>(col);
+        const double2 v1 = *reinterpret_cast<const double2 *>(col + 2);
+        a0 += v0.x * fi; a1 += v0.y * fi; a2 += v1.x * fi; a3 += v1.y * fi;
+      }
+    }
+    T *pb = part + b * n + 4 * g;
+    pb[0] = a0; pb[1] = a1; pb[2] = a2; pb[3] = a3;
+  }
+  __syncthreads();
+  for (int r = tid; r < n; r += kEngThreads) {
+    T acc = part[r];
+    for (int b = 1; b < parts; b++) acc += part[b * n + r];
+    u[r] = acc;
+    each(r);
+  }
+}
+
 // One step of the interpreter, run by the whole workgroup. LDS / LDS_CHILD: where this level's and its child's
 // vectors live.
 template <class T, bool LDS, bool LDS_CHILD>
@@ -876,26 +974,27 @@ __device__ __forceinline__ void eng_step(const EngOp &op, const EngLevel<T> *LV,
   const T *ax = M.ax();
   switch (op.type) {
     case EO_GS_FIRST: {
-      const T *f = M.vec(op.f);
       T *u = M.vec(op.u);
-      for (int q = tid; q < n; q += kStride) u[q] = (q < n4) ? f[q] / ax[q] : T(0);
+      if (op.fuse & FUSE_UPD1) {
+        const EngUpd1<T, LDS> U(M, C);
+        for (int q = tid; q < n; q += kStride) {
+          u[q] = (q < n4) ? U.rv(static_cast<uint32_t>(q)) / ax[q] : T(0);
+          U.store(q);
+        }
+      } else {
+        const T *f = M.vec(op.f);
+        for (int q = tid; q < n; q += kStride) u[q] = (q < n4) ? f[q] / ax[q] : T(0);
+      }
       break;
     }
     case EO_GS_FIRST2: {
-      // the first two phases of a sweep from zero in one step (levels without same-color couplings): color 0 takes
-      // u = f / diag, and the color-1 rows read those values formed on the fly (colors 2 and 3 are still 0); no
-      // thread reads u here, so the writes of colors 0, 2 and 3 can go alongside
-      const T *f = M.vec(op.f);
       T *u = M.vec(op.u);
-      const uint32_t n4u = static_cast<uint32_t>(n4);
-      auto first = [f, ax, n4u](uint32_t i) { return i < n4u ? f[i] / ax[i] : T(0); };
-      for (int j = tid; j < n4; j += kStride) {
-        const uint32_t q = static_cast<uint32_t>(n4 + j);
-        u[q] = T(0) + (f[q] - eng_row_f<T>(k, n, ax, L.optr, L.ocol, L.oval, q, 1, first)) / ax[q];
-      }
-      for (int q = tid; q < n; q += kStride) {
-        if (q < n4) u[q] = f[q] / ax[q];
-        else if (q >= 2 * n4) u[q] = T(0);
+      if (op.fuse & FUSE_UPD1) {
+        const EngUpd1<T, LDS> U(M, C);
+        eng_gs_first2<T>(L, k, n, ax, u, [U](uint32_t i) { return U.rv(i); }, [U](int i) { U.store(i); });
+      } else {
+        const T *f = M.vec(op.f);
+        eng_gs_first2<T>(L, k, n, ax, u, [f](uint32_t i) { return f[i]; }, [](int) {});
       }
       break;
     }
@@ -913,6 +1012,10 @@ __device__ __forceinline__ void eng_step(const EngOp &op, const EngLevel<T> *LV,
       if (L.same_color) {
         __syncthreads();
         for (int j = tid; j < n4; j += kStride) u[c * n4 + j] += d[c * n4 + j];
+      }
+      if (op.fuse & FUSE_BETA) {
+        __syncthreads();
+        eng_dot_beta<T, LDS>(M, n, C);
       }
       break;
     }
@@ -953,41 +1056,17 @@ __device__ __forceinline__ void eng_step(const EngOp &op, const EngLevel<T> *LV,
       break;
     }
     case EO_BHAT_M: {
-      // u = B^ f with B^ precomputed as a matrix (column-major, global memory). A thread owns four consecutive rows
-      // (one 16-byte load per column in FP32, two in FP64) for a run of columns; the workgroup splits the columns
-      // into mhat_parts runs, and the partial sums of a row are added in a fixed order.
-      const T *f = M.vec(op.f);
       T *u = M.vec(op.u);
-      T *part = S + P.mpart_off;
-      const int groups = n >> 2;
-      const int parts = P.mhat_parts;
-      const int cols = n / parts;
-      if (tid < groups * parts) {
-        const int g = tid % groups;
-        const int b = tid / groups;
-        const T *mc = P.mhat + static_cast<size_t>(b) * cols * n + 4 * g;
-        const T *fb = f + b * cols;
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-        for (int i = 0; i < cols; i++) {
-          const T *col = mc + static_cast<size_t>(i) * n;
-          const T fi = fb[i];
-          if constexpr (std::is_same<T, float>::value) {
-            const float4 v = *reinterpret_cast<const float4 *>(col);
-            a0 += v.x * fi; a1 += v.y * fi; a2 += v.z * fi; a3 += v.w * fi;
-          } else {
-            const double2 v0 = *reinterpret_cast<const double2 *>(col);
-            const double2 v1 = *reinterpret_cast<const double2 *>(col + 2);
-            a0 += v0.x * fi; a1 += v0.y * fi; a2 += v1.x * fi; a3 += v1.y * fi;
-          }
-        }
-        T *pb = part + b * n + 4 * g;
-        pb[0] = a0; pb[1] = a1; pb[2] = a2; pb[3] = a3;
+      if (op.fuse & FUSE_UPD1) {
+        const EngUpd1<T, LDS> U(M, C);
+        eng_bhat_m<T>(P, n, S, u, [U](uint32_t i) { return U.rv(i); }, [U](int i) { U.store(i); });
+      } else {
+        const T *f = M.vec(op.f);
+        eng_bhat_m<T>(P, n, S, u, [f](uint32_t i) { return f[i]; }, [](int) {});
       }
-      __syncthreads();
-      for (int r = tid; r < n; r += kStride) {
-        T acc = part[r];
-        for (int b = 1; b < parts; b++) acc += part[b * n + r];
-        u[r] = acc;
+      if (op.fuse & FUSE_BETA) {
+        __syncthreads();
+        eng_dot_beta<T, LDS>(M, n, C);
       }
       break;
     }
@@ -1051,23 +1130,13 @@ __device__ __forceinline__ void eng_step(const EngOp &op, const EngLevel<T> *LV,
       break;
     }
     case EO_UPDATE1: {
-      const T a0 = static_cast<T>(C.sc[ES_A0]);
-      const T *p0 = M.vec(EV_P0), *q0 = M.vec(EV_Q0), *g = M.vec(EV_G);
-      T *e = M.vec(EV_E), *r = M.vec(EV_R);
-      for (int i = tid; i < n; i += kStride) {
-        e[i] = a0 * p0[i];
-        r[i] = g[i] - a0 * q0[i];
-      }
+      const EngUpd1<T, LDS> U(M, C);
+      for (int i = tid; i < n; i += kStride) U.store(i);
       break;
     }
-    case EO_DOT_BETA: {
-      const T *p1 = M.vec(EV_P1), *q0 = M.vec(EV_Q0);
-      double t[1] = {0.0};
-      for (int i = tid; i < n; i += kStride) t[0] += static_cast<double>(p1[i]) * static_cast<double>(q0[i]);
-      eng_reduce<1>(t, C.red);
-      if (tid == 0) C.sc[ES_BETA] = (C.sc[ES_STOP] != 0.0) ? 0.0 : -t[0] / C.sc[ES_D0];
+    case EO_DOT_BETA:
+      eng_dot_beta<T, LDS>(M, n, C);
       break;
-    }
     case EO_UPDATE2: {
       const T a1 = static_cast<T>(C.sc[ES_A1]), beta = static_cast<T>(C.sc[ES_BETA]);
       const T *p1 = M.vec(EV_P1), *p0 = M.vec(EV_P0);
@@ -1171,10 +1240,24 @@ static void emit_bhat(std::vector<EngOp> &ops, const EmitCtx &E, int l, int f, i
 static void emit_btilde(std::vector<EngOp> &ops, const EmitCtx &E, int l, bool defer_update2) {
   emit_bhat(ops, E, l, EV_G, EV_P0);
   ops.push_back({EO_SPMV_DOT0, l, 0, 0, 0});
-  ops.push_back({EO_UPDATE1, l, 0, 0, 0});
-  if (E.inner < 2) return;
+  if (E.inner < 2) {
+    ops.push_back({EO_UPDATE1, l, 0, 0, 0});
+    return;
+  }
+  // the update folds into the first step of the second B^ and the inner product for beta into its last, when those
+  // are steps on this level that take the fold (a relaxation from zero or the B^ matrix; a color phase or the B^
+  // matrix)
+  const size_t first = ops.size();
   emit_bhat(ops, E, l, EV_R, EV_P1);
-  ops.push_back({EO_DOT_BETA, l, 0, 0, 0});
+  EngOp &a = ops[first];
+  if (a.lvl == l && (a.type == EO_GS_FIRST || a.type == EO_GS_FIRST2 || a.type == EO_BHAT_M)) {
+    a.fuse |= FUSE_UPD1;
+  } else {
+    ops.insert(ops.begin() + static_cast<std::ptrdiff_t>(first), EngOp{EO_UPDATE1, l, 0, 0, 0, 0});
+  }
+  EngOp &z = ops.back();
+  if (z.lvl == l && (z.type == EO_GS || z.type == EO_BHAT_M)) z.fuse |= FUSE_BETA;
+  else ops.push_back({EO_DOT_BETA, l, 0, 0, 0});
   ops.push_back({EO_SPMV_DOT1, l, 0, 0, 0});
   if (!defer_update2) ops.push_back({EO_UPDATE2, l, 0, 0, 0});
 }
