@@ -216,6 +216,7 @@ struct amg_hierarchy {
   int engine_top[2] = {-1, -1};
   int engine_lds_top[2] = {-1, -1};  // first level index whose operators and vectors live in LDS
   int engine_ainv_lds[2] = {0, 0};
+  int engine_lvec[2] = {0, 0};       // work vectors of a global engine top level held in LDS (bit per vector slot)
   void *engine_ops[2] = {nullptr, nullptr};
   int engine_nops[2] = {0, 0};
   int64_t engine_global_rows = 4096;  // a top level this small may run from global memory

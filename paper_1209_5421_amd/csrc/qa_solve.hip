@@ -125,6 +125,28 @@ __global__ void __launch_bounds__(kBlock) k_finish(unsigned nb, Red R) {
   if (threadIdx.x == 0) epilogue(acc, R);
 }
 
+// r = g - a0 q0 of the first inner update of Algorithm 2.1 (one expression, so the separate and the folded forms
+// round alike)
+template <class T>
+__device__ __forceinline__ T upd1_r(T g, T a0, T q0) {
+  return g - a0 * q0;
+}
+
+// the first inner update e = a0 p0, r = g - a0 q0 left for the first relaxation of the second B^ (null sc: none):
+// that kernel writes e and r and reads its right-hand side r formed on the fly
+template <class T>
+struct Upd1 {
+  const double *sc;
+  const T *g, *q0, *p0;
+  T *e, *r;
+  __device__ T a0() const { return static_cast<T>(sc[S_A0]); }
+  __device__ T rv(T a, uint32_t i) const { return upd1_r(g[i], a, q0[i]); }
+  __device__ void store(T a, int64_t i) const {
+    e[i] = a * p0[i];
+    r[i] = upd1_r(g[i], a, q0[i]);
+  }
+};
+
 // the child's pending last update e_c + a1 (p1 + beta p0) of Algorithm 2.1, formed where the prolongation reads e_c
 // (null sc: nothing pending)
 template <class T>
@@ -255,6 +277,13 @@ __global__ void __launch_bounds__(kBlock) k_fine_apply(SellView<T> S, SliceSched
 // In-cell substitution of one color phase: thread per cell q in [q_begin, q_end). FWD: delta_p = (r_p - sum_{c<p}
 // a_pc delta_c) / a_pp over the cell's rows ascending; else descending with c > p. r comes from src (the
 // residual pass, or f itself for the first phase of a sweep from zero); delta overwrites d; x += delta.
+// The rows of a workgroup's cells are one contiguous range, and so are their in-cell entries: the workgroup stages
+// both in LDS with coalesced loads, each thread runs its cell's substitution there (same order of operations), and
+// the deltas go back with coalesced stores. Rows of cells left to k_fine_subst_big are not touched. A range larger
+// than the staging arrays takes the same loop on global memory.
+constexpr int kSubstRows = 2048;
+constexpr int kSubstEnt = 4096;
+
 template <class T, bool FWD>
 __global__ void __launch_bounds__(kBlock) k_fine_subst(const int32_t *__restrict__ crow,
                                                         const int32_t *__restrict__ icp,
@@ -262,9 +291,97 @@ __global__ void __launch_bounds__(kBlock) k_fine_subst(const int32_t *__restrict
                                                         const T *__restrict__ diag, const T *__restrict__ src,
                                                         T *__restrict__ d, T *__restrict__ x, int64_t q_begin,
                                                         int64_t q_end) {
-  const int64_t q = q_begin + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= q_end) return;
-  const int32_t a = crow[q], b = crow[q + 1];
+  __shared__ T s_r[kSubstRows], s_dg[kSubstRows], s_d[kSubstRows], s_val[kSubstEnt];
+  __shared__ int32_t s_ep[kSubstRows + 1];
+  __shared__ int16_t s_col[kSubstEnt];
+  __shared__ uint8_t s_mine[kSubstRows];
+  const int t = threadIdx.x;
+  const int64_t qb = q_begin + static_cast<int64_t>(blockIdx.x) * kBlock;
+  const int64_t qe = std::min<int64_t>(qb + kBlock, q_end);
+  const int64_t q = qb + t;
+  const int32_t r0 = crow[qb], r1 = crow[qe];
+  const int32_t ca = q < qe ? crow[q] : 0, cb = q < qe ? crow[q + 1] : 0;  // this thread's cell
+  const int32_t e0 = icp[r0], e1 = icp[r1];
+  const int nr = r1 - r0, ne = e1 - e0;
+  if (nr <= kSubstRows && ne <= kSubstEnt) {  // uniform over the workgroup
+    // every load of a thread is issued before the first store to LDS (unrolled over the staging capacity)
+    constexpr int kRowIt = kSubstRows / kBlock, kEntIt = kSubstEnt / kBlock;
+    T rv[kRowIt], dv[kRowIt], vv[kEntIt];
+    int32_t pv[kRowIt], cv[kEntIt];
+#pragma unroll
+    for (int u = 0; u < kRowIt; u++) {
+      const int i = t + u * kBlock;
+      if (i < nr) {
+        rv[u] = src[r0 + i];
+        dv[u] = diag[r0 + i];
+        pv[u] = icp[r0 + i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kEntIt; u++) {
+      const int k = t + u * kBlock;
+      if (k < ne) {
+        cv[u] = icc[e0 + k];
+        vv[u] = icv[e0 + k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kRowIt; u++) {
+      const int i = t + u * kBlock;
+      if (i < nr) {
+        s_r[i] = rv[u];
+        s_dg[i] = dv[u];
+        s_ep[i] = pv[u] - e0;
+        s_mine[i] = 0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kEntIt; u++) {
+      const int k = t + u * kBlock;
+      if (k < ne) {
+        s_col[k] = static_cast<int16_t>(cv[u] - r0);
+        s_val[k] = vv[u];
+      }
+    }
+    if (t == 0) s_ep[nr] = ne;
+    __syncthreads();
+    if (q < qe) {
+      const int a = ca - r0, b = cb - r0;
+      if (b - a <= kBigCell) {
+        if (FWD) {
+          for (int p = a; p < b; p++) {
+            T acc = s_r[p];
+            for (int k = s_ep[p]; k < s_ep[p + 1]; k++) {
+              const int c = s_col[k];
+              if (c < p) acc -= s_val[k] * s_d[c];
+            }
+            s_d[p] = acc / s_dg[p];
+            s_mine[p] = 1;
+          }
+        } else {
+          for (int p = b - 1; p >= a; p--) {
+            T acc = s_r[p];
+            for (int k = s_ep[p]; k < s_ep[p + 1]; k++) {
+              const int c = s_col[k];
+              if (c > p) acc -= s_val[k] * s_d[c];
+            }
+            s_d[p] = acc / s_dg[p];
+            s_mine[p] = 1;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = t; i < nr; i += kBlock)
+      if (s_mine[i]) {
+        const T di = s_d[i];
+        d[r0 + i] = di;
+        x[r0 + i] += di;
+      }
+    return;
+  }
+  if (q >= qe) return;
+  const int32_t a = ca, b = cb;
   if (b - a > kBigCell) return;  // k_fine_subst_big
   if (FWD) {
     for (int32_t p = a; p < b; p++) {
@@ -385,30 +502,49 @@ __device__ inline int row_color(uint32_t q, int sh) {
   return sh >= 6 ? __builtin_amdgcn_readfirstlane(c) : c;
 }
 
-// first phase of a sweep from zero: x = f / diag on color 0, zero elsewhere
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_cgs_first(QView<T> Q, const T *__restrict__ f, T *__restrict__ x) {
+// first phase of a sweep from zero: x = f / diag on color 0, zero elsewhere (UPD: f is the pending update's r)
+template <class T, bool UPD>
+__global__ void __launch_bounds__(kBlock) k_cgs_first(QView<T> Q, const T *__restrict__ f, T *__restrict__ x,
+                                                       Upd1<T> U) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= Q.n) return;
-  x[q] = (q < (Q.n >> 2)) ? f[q] / Q.ax[q] : T(0);
+  if constexpr (UPD) {
+    const T a = U.a0();
+    x[q] = (q < (Q.n >> 2)) ? U.rv(a, static_cast<uint32_t>(q)) / Q.ax[q] : T(0);
+    U.store(a, q);
+  } else {
+    x[q] = (q < (Q.n >> 2)) ? f[q] / Q.ax[q] : T(0);
+  }
 }
 
 // the first two phases of a sweep from zero (levels without same-color couplings): x = f / diag on color 0, zero on
 // colors 2 and 3, and the color-1 rows relaxed against the color-0 values formed on the fly (nothing reads x here)
-template <class T>
-__global__ void __launch_bounds__(kBlock) k_cgs_first2(QView<T> Q, const T *__restrict__ f, T *__restrict__ x) {
-  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (q >= Q.n) return;
+template <class T, class FV>
+__device__ inline void cgs_first2_row(const QView<T> &Q, int64_t q, FV fv, T *__restrict__ x) {
   const int64_t n4 = Q.n >> 2;
   if (q < n4) {
-    x[q] = f[q] / Q.ax[q];
+    x[q] = fv(static_cast<uint32_t>(q)) / Q.ax[q];
   } else if (q < 2 * n4) {
     const uint32_t n4u = static_cast<uint32_t>(n4);
     const T *ax = Q.ax;
-    auto first = [f, ax, n4u](uint32_t i) { return i < n4u ? f[i] / ax[i] : T(0); };
-    x[q] = T(0) + (f[q] - row_apply_f<T>(Q, static_cast<uint32_t>(q), 1, first)) / Q.ax[q];
+    auto first = [fv, ax, n4u](uint32_t i) { return i < n4u ? fv(i) / ax[i] : T(0); };
+    x[q] = T(0) + (fv(static_cast<uint32_t>(q)) - row_apply_f<T>(Q, static_cast<uint32_t>(q), 1, first)) / Q.ax[q];
   } else {
     x[q] = T(0);
+  }
+}
+
+template <class T, bool UPD>
+__global__ void __launch_bounds__(kBlock) k_cgs_first2(QView<T> Q, const T *__restrict__ f, T *__restrict__ x,
+                                                        Upd1<T> U) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= Q.n) return;
+  if constexpr (UPD) {
+    const T a = U.a0();
+    cgs_first2_row<T>(Q, q, [U, a](uint32_t i) { return U.rv(a, i); }, x);
+    U.store(a, q);
+  } else {
+    cgs_first2_row<T>(Q, q, [f](uint32_t i) { return f[i]; }, x);
   }
 }
 
@@ -424,6 +560,70 @@ __global__ void __launch_bounds__(kBlock) k_cgs(QView<T> Q, const T *__restrict_
   const T dl = (f[q] - row_apply(Q, q, c, x)) / Q.ax[q];
   if (delta) delta[q] = dl;
   else x[q] += dl;
+}
+
+// the last color phase (c = 0) of the second B^ with the inner product (p1, q0) of Algorithm 2.1 for beta: thread j
+// relaxes row j and adds the products of rows j + c n/4 of all four colors (colors 1 to 3 are final already)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cgs0_beta(QView<T> Q, const T *__restrict__ f, T *__restrict__ x,
+                                                      const T *__restrict__ q0, Red R) {
+  const int64_t n4 = Q.n >> 2;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  double v[1] = {0.0};
+  if (j < n4) {
+    const uint32_t q = static_cast<uint32_t>(j);
+    const T xn = x[q] + (f[q] - row_apply(Q, q, 0, x)) / Q.ax[q];
+    x[q] = xn;
+    v[0] = static_cast<double>(xn) * static_cast<double>(q0[q]);
+#pragma unroll
+    for (int c = 1; c < 4; c++) v[0] += static_cast<double>(x[c * n4 + j]) * static_cast<double>(q0[c * n4 + j]);
+  }
+  reduce_finish<1>(v, R);
+}
+
+// A color phase of the first post-smoothing sweep (no same-color couplings) with the prolongation u += P e_c folded
+// in: the rows of colors <= C have not been corrected yet (the backward sweep has only passed colors > C), so their
+// values are read as u + (P e_c) formed on the fly, each equal to what the separate prolongation stores; the phase
+// stores the corrected and relaxed values of its own rows. With BETA (C = 0, the last phase of the second B^) it also
+// forms (p1, q0) for beta over the rows j + c n/4 of the four colors.
+template <class T, int C, bool BETA>
+__global__ void __launch_bounds__(kBlock) k_cgs_post(QView<T> Q, const T *__restrict__ f, T *__restrict__ x,
+                                                     const T *__restrict__ ec, Pending<T> pend,
+                                                     const T *__restrict__ q0, Red R) {
+  const int64_t n4 = Q.n >> 2;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int sh = 2 * Q.k - 2;
+  const uint32_t mask = static_cast<uint32_t>(n4 - 1);
+  const int kc = Q.k - 1;
+  auto pe = [ec, pend, mask, kc](uint32_t i) { return pend.apply(ec, q_of_m(i & mask, kc)); };
+  double v[1] = {0.0};
+  if (j < n4) {
+    const uint32_t q = static_cast<uint32_t>(C * n4 + j);
+    uint32_t nb[9];
+    stencil_q(q, static_cast<uint32_t>(j), C, sh, nb);
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < 9; s++) {
+      const int cn = (((C & 1) + slot_dx(s)) & 1) | ((((C >> 1) + slot_dy(s)) & 1) << 1);
+      const T xn = x[nb[s]];
+      acc += Q.ax[s * Q.n + q] * (cn <= C ? xn + pe(nb[s]) : xn);
+    }
+    if (Q.optr)
+      for (int32_t e = Q.optr[q]; e < Q.optr[q + 1]; e++) {
+        const uint32_t i = static_cast<uint32_t>(Q.ocol[e]);
+        const T xn = x[i];
+        acc += Q.oval[e] * (static_cast<int>(i >> sh) <= C ? xn + pe(i) : xn);
+      }
+    const T xq = x[q] + pe(q);
+    const T xr = xq + (f[q] - acc) / Q.ax[q];
+    x[q] = xr;
+    if constexpr (BETA) {
+      v[0] = static_cast<double>(xr) * static_cast<double>(q0[q]);
+#pragma unroll
+      for (int c = 1; c < 4; c++) v[0] += static_cast<double>(x[c * n4 + j]) * static_cast<double>(q0[c * n4 + j]);
+    }
+  }
+  if constexpr (BETA) reduce_finish<1>(v, R);
 }
 
 template <class T>
@@ -510,7 +710,7 @@ __global__ void __launch_bounds__(kBlock) k_update1(int64_t n, const double *__r
   if (i >= n) return;
   const T a = static_cast<T>(sc[S_A0]);
   e[i] = a * p0[i];
-  r[i] = g[i] - a * q0[i];
+  r[i] = upd1_r(g[i], a, q0[i]);
 }
 
 template <class T>
@@ -763,7 +963,8 @@ static void launch_timed(amg_hierarchy *h, int kind, F kern, unsigned grid, Args
 constexpr int kEngThreads = 1024;
 constexpr int kEngWaves = kEngThreads / 64;
 constexpr int kEngMaxLevels = 8;
-constexpr int kEngMaxOps = 512;  // step list staged in LDS (20 bytes each)
+constexpr int kEngMaxOps = 512;  // step list staged in LDS (24 bytes each)
+constexpr int kEngRows = 4;      // rows per thread whose loads an SpMV step issues together
 
 enum EngOpType : int32_t {
   EO_GS_FIRST = 0, EO_GS, EO_RES_RESTRICT, EO_DENSE, EO_PROLONG, EO_SPMV_DOT0, EO_UPDATE1, EO_DOT_BETA,
@@ -795,6 +996,9 @@ struct EngLevel {
   int same_color;
   int ax_off, vec_off;         // LDS offsets (T units) of the 9 x n operator and of the vectors when in_lds
   T *vec[EV_COUNT];            // global vectors when not in LDS
+  // a level run from global memory may still hold some of its work vectors in LDS: the vectors whose bits are set
+  // lie at vec_off, one after another in slot order, and the workgroup points vec[] at them when it starts
+  int lvec_mask;
 };
 
 template <class T>
@@ -867,12 +1071,6 @@ struct EngCtx {
   double *sc_child; // the next coarser level's scalars
   double *red;
 };
-
-// r = g - a0 q0 of the first inner update (one expression, so the separate and the folded forms round alike)
-template <class T>
-__device__ __forceinline__ T upd1_r(T g, T a0, T q0) {
-  return g - a0 * q0;
-}
 
 // the first inner update of Algorithm 2.1 on an engine level, as a value source (r) and a store of e and r
 template <class T, bool LDS>
@@ -1094,12 +1292,25 @@ __device__ __forceinline__ void eng_step(const EngOp &op, const EngLevel<T> *LV,
       T *y = M.vec(EV_Q0);
       const T *w = M.vec(EV_G);
       double v[2] = {0.0, 0.0};
-      for (int q = tid; q < n; q += kStride) {
-        const T yq = eng_row(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q),
-                             row_color(static_cast<uint32_t>(q), 2 * k - 2), x);
-        y[q] = yq;
-        v[0] += static_cast<double>(x[q]) * static_cast<double>(yq);
-        v[1] += static_cast<double>(w[q]) * static_cast<double>(x[q]);
+      // a thread's rows (up to kEngRows per pass) are all loaded before any is stored, so their loads overlap
+      for (int q0 = tid; q0 < n; q0 += kEngRows * kStride) {
+        T yq[kEngRows];
+#pragma unroll
+        for (int r = 0; r < kEngRows; r++) {
+          const int q = q0 + r * kStride;
+          if (q < n)
+            yq[r] = eng_row(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q),
+                            row_color(static_cast<uint32_t>(q), 2 * k - 2), x);
+        }
+#pragma unroll
+        for (int r = 0; r < kEngRows; r++) {
+          const int q = q0 + r * kStride;
+          if (q < n) {
+            y[q] = yq[r];
+            v[0] += static_cast<double>(x[q]) * static_cast<double>(yq[r]);
+            v[1] += static_cast<double>(w[q]) * static_cast<double>(x[q]);
+          }
+        }
       }
       eng_reduce<2>(v, C.red);
       if (tid == 0) {
@@ -1118,12 +1329,24 @@ __device__ __forceinline__ void eng_step(const EngOp &op, const EngLevel<T> *LV,
       const T *w = M.vec(EV_R);
       auto dir = [p1, p0, beta](uint32_t i) { return p1[i] + beta * p0[i]; };
       double v[2] = {0.0, 0.0};
-      for (int q = tid; q < n; q += kStride) {
-        const T yq = eng_row_f<T>(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q),
-                                  row_color(static_cast<uint32_t>(q), 2 * k - 2), dir);
-        const T xq = dir(static_cast<uint32_t>(q));
-        v[0] += static_cast<double>(xq) * static_cast<double>(yq);
-        v[1] += static_cast<double>(w[q]) * static_cast<double>(xq);
+      for (int q0 = tid; q0 < n; q0 += kEngRows * kStride) {
+        T yq[kEngRows], xq[kEngRows], wq[kEngRows];
+#pragma unroll
+        for (int r = 0; r < kEngRows; r++) {
+          const int q = q0 + r * kStride;
+          if (q < n) {
+            yq[r] = eng_row_f<T>(k, n, ax, L.optr, L.ocol, L.oval, static_cast<uint32_t>(q),
+                                 row_color(static_cast<uint32_t>(q), 2 * k - 2), dir);
+            xq[r] = dir(static_cast<uint32_t>(q));
+            wq[r] = w[q];
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < kEngRows; r++)
+          if (q0 + r * kStride < n) {
+            v[0] += static_cast<double>(xq[r]) * static_cast<double>(yq[r]);
+            v[1] += static_cast<double>(wq[r]) * static_cast<double>(xq[r]);
+          }
       }
       eng_reduce<2>(v, C.red);
       if (tid == 0) C.sc[ES_A1] = (C.sc[ES_STOP] != 0.0 || !(v[0] > 0.0)) ? 0.0 : v[1] / v[0];
@@ -1170,7 +1393,12 @@ template <class T>
 __device__ inline void eng_stage(const EngPlan<T> &P, EngOp *ops, EngLevel<T> *LV, T *S, double *ainv_lds) {
   const int tid = threadIdx.x;
   for (int i = tid; i < P.nops; i += kEngThreads) ops[i] = P.ops[i];
-  if (tid < P.nlev) LV[tid] = P.lv[tid];
+  if (tid < P.nlev) {
+    EngLevel<T> L = P.lv[tid];
+    for (int v = 0, j = 0; v < EV_COUNT; v++)
+      if ((L.lvec_mask >> v) & 1) L.vec[v] = S + L.vec_off + (j++) * L.n;
+    LV[tid] = L;
+  }
   if (P.ainv_in_lds)
     for (int i = tid; i < P.nc * P.nc; i += kEngThreads) ainv_lds[i] = P.ainv[i];
   for (int l = 0; l < P.nlev; l++) {
@@ -1336,6 +1564,19 @@ amg_status plan_engine(amg_hierarchy *h) {
     }
     // the coarsest inverse is staged into LDS only when the step list uses it (no B^ matrix)
     const bool ainv = !mhat && bytes + static_cast<size_t>(h->nc * h->nc) * 8 <= budget;
+    const size_t ainv_bytes = ainv ? static_cast<size_t>(h->nc * h->nc) * 8 : 0;
+    // an FP32 top level run from global memory keeps the work vectors it gathers most (the two B^ outputs, then q0
+    // and r) in whatever LDS is left; g and e stay in global memory, where the caller reads and writes them (in
+    // FP64 the generic accesses this needs measured slower than the L2-resident vectors)
+    int lvec = 0;
+    if (top < lds_top && pi == 1) {
+      const size_t vb = static_cast<size_t>(h->lev[top].n) * ts;
+      for (int v : {EV_P0, EV_P1, EV_Q0, EV_R})
+        if (bytes + ainv_bytes + vb <= budget) {
+          lvec |= 1 << v;
+          bytes += vb;
+        }
+    }
     EngOp *d = static_cast<EngOp *>(dalloc(h, sizeof(EngOp) * ops.size()));
     if (!d) return AMG_ERR_NOMEM;
     QA_HIP(hipMemcpyAsync(d, ops.data(), sizeof(EngOp) * ops.size(), hipMemcpyHostToDevice, h->stream));
@@ -1343,7 +1584,8 @@ amg_status plan_engine(amg_hierarchy *h) {
     h->engine_top[pi] = top;
     h->engine_lds_top[pi] = lds_top;
     h->engine_ainv_lds[pi] = ainv ? 1 : 0;
-    h->engine_lds[pi] = bytes + (ainv ? static_cast<size_t>(h->nc * h->nc) * 8 : 0);
+    h->engine_lvec[pi] = lvec;
+    h->engine_lds[pi] = bytes + ainv_bytes;
     h->engine_ops[pi] = d;
     h->engine_nops[pi] = static_cast<int>(ops.size());
   }
@@ -1363,7 +1605,7 @@ __global__ void __launch_bounds__(kBlock) k_round(int64_t n, const double *__res
 }
 
 template <class T>
-static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, EngPlan<T> &E);
+static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, EngPlan<T> &E, int lvec = 0);
 
 // B^ on the level just above the coarsest is linear (smoothing, restriction, the exact coarsest solve, prolongation,
 // smoothing: Algorithm 2.2 with no nonlinear inner iteration below it). When that level is small it is evaluated
@@ -1415,7 +1657,7 @@ amg_status build_mhat(amg_hierarchy *h) {
 
 // Level table of an engine whose top is hierarchy level `top`, levels from `lds_top` down LDS-resident.
 template <class T>
-static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, EngPlan<T> &E) {
+static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, EngPlan<T> &E, int lvec) {
   const int pi = std::is_same<T, float>::value ? 1 : 0;
   E.nlev = h->nlev - top;
   E.nc = static_cast<int>(h->nc);
@@ -1436,6 +1678,7 @@ static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, En
     L.oval = P<T>::oval(Q);
     L.same_color = Q.same_color_ovf;
     L.in_lds = l >= lds_top ? 1 : 0;
+    L.lvec_mask = 0;
     if (L.in_lds) {
       if (i + 1 < E.nlev) {  // operator and the eight vectors
         L.ax_off = off;
@@ -1459,6 +1702,12 @@ static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, En
     // four rows per thread: n / 4 row groups, the columns split over the rest of the workgroup (at most n runs)
     E.mhat_parts = std::max(1, std::min(kEngThreads / std::max(n / 4, 1), std::min(n, kMhatPart / n)));
     E.mpart_off = off;
+    off += kMhatPart;
+  }
+  // the work vectors of a global top level held in LDS (lvec: bit per vector slot) come last
+  if (!E.lv[0].in_lds && lvec) {
+    E.lv[0].lvec_mask = lvec;
+    E.lv[0].vec_off = off;
   }
 }
 
@@ -1466,7 +1715,7 @@ template <class T>
 static void launch_engine(amg_hierarchy *h, int top) {
   const int pi = std::is_same<T, float>::value ? 1 : 0;
   EngPlan<T> E{};
-  fill_engine(h, top, h->engine_lds_top[pi], h->engine_ainv_lds[pi], E);
+  fill_engine(h, top, h->engine_lds_top[pi], h->engine_ainv_lds[pi], E, h->engine_lvec[pi]);
   E.nops = h->engine_nops[pi];
   E.ops = static_cast<const EngOp *>(h->engine_ops[pi]);
   std::vector<LevelWork<T>> &W = P<T>::W(h);
@@ -1801,19 +2050,25 @@ static void gs_phase_coarse(amg_hierarchy *h, int l, const T *f, T *u, int c) {
   }
 }
 
-// B^_l for a quadtree level l (not the coarsest): Algorithm 2.2
+// B^_l for a quadtree level l (not the coarsest): Algorithm 2.2. `upd` (sc non-null): the pending first inner update
+// of the caller, done by the first relaxation (needs sweeps >= 1). `beta` (non-null): the last color phase also
+// forms (p1, q0) for beta (needs sweeps >= 1 and no same-color couplings).
 template <class T>
-static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u) {
+static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u, const Upd1<T> &upd = Upd1<T>{},
+                        const T *beta_q0 = nullptr) {
   const QuadLevel &Q = h->lev[l];
   hipStream_t s = h->stream;
   const int sweeps = h->opt.sweeps;
+  const bool U = upd.sc != nullptr;
   for (int sw = 0; sw < sweeps; sw++)
     for (int c = 0; c < 4; c++) {
       if (sw == 0 && c == 0 && !Q.same_color_ovf) {
-        k_cgs_first2<T><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u);
+        if (U) k_cgs_first2<T, true><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u, upd);
+        else k_cgs_first2<T, false><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u, upd);
         c = 1;
       } else if (sw == 0 && c == 0) {
-        k_cgs_first<T><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u);
+        if (U) k_cgs_first<T, true><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u, upd);
+        else k_cgs_first<T, false><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u, upd);
       } else {
         gs_phase_coarse<T>(h, l, f, u, c);
       }
@@ -1821,9 +2076,31 @@ static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u) {
   LevelWork<T> &wc = P<T>::W(h)[l + 1];
   k_cres_restrict<T><<<nblk(Q.n >> 2), kBlock, 0, s>>>(qview<T>(Q), f, u, wc.g);
   const Pending<T> pend = coarse_solve_or_cycle<T>(h, l + 1);
-  k_cprolong<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, wc.e, pend, u);
+  // without same-color couplings the prolongation folds into the first post-smoothing sweep
+  const bool fold_prolong = !Q.same_color_ovf && sweeps >= 1;
+  if (!fold_prolong) k_cprolong<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, wc.e, pend, u);
+  const int64_t n4 = Q.n >> 2;
+  const Red rb = red(h, l, EPI_BETA);
   for (int sw = 0; sw < sweeps; sw++)
-    for (int c = 3; c >= 0; c--) gs_phase_coarse<T>(h, l, f, u, c);
+    for (int c = 3; c >= 0; c--) {
+      const bool beta_here = beta_q0 && sw == sweeps - 1 && c == 0;
+      if (fold_prolong && sw == 0) {
+        const QView<T> V = qview<T>(Q);
+        switch (c) {
+          case 3: k_cgs_post<T, 3, false><<<nblk(n4), kBlock, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb); break;
+          case 2: k_cgs_post<T, 2, false><<<nblk(n4), kBlock, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb); break;
+          case 1: k_cgs_post<T, 1, false><<<nblk(n4), kBlock, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb); break;
+          default:
+            if (beta_here) k_cgs_post<T, 0, true><<<nblk(n4), kBlock, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb);
+            else k_cgs_post<T, 0, false><<<nblk(n4), kBlock, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb);
+        }
+      } else if (beta_here) {
+        k_cgs0_beta<T><<<nblk(n4), kBlock, 0, s>>>(qview<T>(Q), f, u, beta_q0, rb);
+      } else {
+        gs_phase_coarse<T>(h, l, f, u, c);
+      }
+      if (beta_here) finish<1>(h, nblk(n4), rb);
+    }
 }
 
 template <class T>
@@ -1901,11 +2178,19 @@ static void btilde(amg_hierarchy *h, int l, const T *g, T *e, bool defer_update2
   bhat<T>(h, l, g, w.p0);
   k_cspmv_dot<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), w.p0, w.q0, g, red(h, l, EPI_ALPHA0));
   finish<2>(h, nred(Q.n), red(h, l, EPI_ALPHA0));
-  k_update1<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p0, w.q0, g, e, w.r);
-  if (h->opt.inner_iters < 2) return;
-  bhat<T>(h, l, w.r, w.p1);
-  k_dot<T><<<nred(Q.n), kBlock, 0, s>>>(Q.n, w.p1, w.q0, red(h, l, EPI_BETA));
-  finish<1>(h, nred(Q.n), red(h, l, EPI_BETA));
+  // with two inner steps the update below and the inner product for beta fold into the second B^ (first and last
+  // relaxation) where its sweeps allow
+  const bool two = h->opt.inner_iters >= 2;
+  const bool fold_upd = two && h->opt.sweeps >= 1;
+  const bool fold_beta = two && h->opt.sweeps >= 1 && !Q.same_color_ovf;
+  if (!fold_upd) k_update1<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p0, w.q0, g, e, w.r);
+  if (!two) return;
+  bhat_coarse<T>(h, l, w.r, w.p1, fold_upd ? Upd1<T>{sc, g, w.q0, w.p0, e, w.r} : Upd1<T>{},
+                 fold_beta ? w.q0 : nullptr);
+  if (!fold_beta) {
+    k_dot<T><<<nred(Q.n), kBlock, 0, s>>>(Q.n, w.p1, w.q0, red(h, l, EPI_BETA));
+    finish<1>(h, nred(Q.n), red(h, l, EPI_BETA));
+  }
   k_cspmv_dir<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), sc, w.p1, w.p0, w.r, red(h, l, EPI_ALPHA1));
   finish<2>(h, nred(Q.n), red(h, l, EPI_ALPHA1));
   if (!defer_update2) k_update2<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p1, w.p0, e);
