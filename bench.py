@@ -33,6 +33,9 @@ WORKLOADS = {
     "c3": ("graded Delaunay ~4.0M points, density (r+0.01)^-1.5, P1 Poisson", lambda mg: mg.graded_problem(4_000_000)),
     "c4": ("jittered Delaunay 1416x1416, kappa 10^U[-3,3] 16x16 checkerboard (1,999,396 DOF)",
            lambda mg: mg.jittered_problem(1416, kappa_tiles=16)),
+    "disk": ("Delaunay mesh of the disk r = 1/2 inside the unit square, jittered 1156x1156 lattice points plus 3,629 "
+             "on the circle, P1 Poisson (about 1.05M DOF; a fifth of the quadtree cells empty)",
+             lambda mg: mg.disk_problem(1156)),
     "c5": ("serving stream: 512 Poisson-arrival requests, jittered-lattice P1 Poisson systems with DOF log-uniform in "
            "[1e4, 2e6], 30% repeat right-hand sides on a cached hierarchy", None),
 }

@@ -91,6 +91,26 @@ def jittered_points(side: int, seed: int = SEED_MESH, jitter: float = 0.3):
     return P.reshape(-1, 2)
 
 
+def disk_points(side: int, seed: int = SEED_MESH, jitter: float = 0.3):
+    """Points of the disk of radius 1/2 centred at (1/2, 1/2): a side x side lattice of spacing h = 1/(side-1),
+    jittered by U[-jitter h, jitter h] and kept where it lies more than h/2 inside the circle, plus round(pi / h)
+    points evenly spaced on the circle. Returns (points, boundary mask). The disk covers pi/4 of its bounding box,
+    so about a fifth of the quadtree cells over it are empty."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / (side - 1)
+    g = np.arange(side, dtype=np.float64) / (side - 1)
+    X, Y = np.meshgrid(g, g)
+    P = np.stack([X.ravel(), Y.ravel()], 1) + rng.uniform(-jitter * h, jitter * h, size=(side * side, 2))
+    inner = P[np.hypot(P[:, 0] - 0.5, P[:, 1] - 0.5) < 0.5 - 0.5 * h]
+    nb = max(8, int(round(math.pi / h)))
+    th = 2.0 * math.pi * np.arange(nb) / nb
+    bd = np.stack([0.5 + 0.5 * np.cos(th), 0.5 + 0.5 * np.sin(th)], 1)
+    pts = np.concatenate([inner, bd])
+    mask = np.zeros(len(pts), dtype=bool)
+    mask[len(inner):] = True
+    return pts, mask
+
+
 def delaunay(pts: np.ndarray) -> np.ndarray:
     from scipy.spatial import Delaunay
     return np.ascontiguousarray(Delaunay(pts).simplices.astype(np.int64))
@@ -420,6 +440,16 @@ def jittered_problem(side: int = 1024, seed: int = SEED_MESH, rhs_seed: int = SE
     tris = delaunay(pts)
     kap = checkerboard_kappa(pts, tris, kappa_tiles) if kappa_tiles else None
     return _problem(name, pts, tris, kap, rhs_seed=rhs_seed, **meta)
+
+
+def disk_problem(side: int = 1024, seed: int = SEED_MESH, rhs_seed: int = SEED_RHS) -> Problem:
+    """Poisson on a Delaunay mesh of the disk (Dirichlet on the circle); the quadtree box is the unit square, so
+    the cells outside the disk are empty aggregates on every level."""
+    pts, mask = disk_points(side, seed)
+    tris = delaunay(pts)
+    coords, rp, col, val = p1_assemble(pts, tris, None, dirichlet=mask)
+    return Problem(f"disk{side}", coords, rp, col, val, rhs(len(coords), rhs_seed), UNIT_BOX,
+                   dict(kind="disk", side=side, seed=seed, n_points=len(pts), n_tris=len(tris)))
 
 
 def lattice_system(side: int, seed: int = SEED_MESH, kappa_tiles: int = 0, device=None):

@@ -29,6 +29,7 @@ PROBLEMS = {
     "graded20k": lambda: mg.graded_problem(20000),                    # level-L overflow, big cells
     "longrange6k": lambda: H.longrange_problem(6000),                 # overflow on every level, no box given
     "two_level": lambda: mg.jittered_problem(16),                     # 196 unknowns: fine + coarsest
+    "disk130": lambda: mg.disk_problem(130),                          # a fifth of the cells empty on every level
 }
 
 _cache = {}
@@ -73,7 +74,7 @@ def test_hierarchy_bit_exact(name):
     g.close()
 
 
-@pytest.mark.parametrize("name", ["uniform65", "jittered177_kappa", "graded20k", "longrange6k"])
+@pytest.mark.parametrize("name", ["uniform65", "jittered177_kappa", "graded20k", "longrange6k", "disk130"])
 def test_level_spmv_and_smoother(name):
     prob = problem(name)
     g = gpu_hier(prob)
@@ -129,7 +130,7 @@ def test_solve_parity_fp64(name):
     g.close()
 
 
-@pytest.mark.parametrize("name", ["uniform65", "jittered130", "jittered177_kappa", "graded20k"])
+@pytest.mark.parametrize("name", ["uniform65", "jittered130", "jittered177_kappa", "graded20k", "disk130"])
 def test_solve_mixed_precision(name):
     prob = problem(name)
     g = gpu_hier(prob, precision=1)
@@ -147,7 +148,7 @@ def test_solve_mixed_precision(name):
     g.close()
 
 
-@pytest.mark.parametrize("name", ["uniform65", "jittered130", "longrange6k"])
+@pytest.mark.parametrize("name", ["uniform65", "jittered130", "longrange6k", "disk130"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_engine_matches_per_step_launches(name, precision):
     """The persistent small-level workgroup and the launch-per-step path compute the same preconditioner (their

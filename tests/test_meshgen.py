@@ -55,3 +55,30 @@ def test_torch_backend_is_bitwise_numpy():
         for a, b in zip((f.coords, f.row_ptr, f.col, f.val), out):
             assert a.dtype == b.numpy().dtype
             np.testing.assert_array_equal(a, b.numpy())
+
+
+def test_disk_mesh_properties():
+    """The disk mesh: unknowns strictly inside the circle, as many as lattice points fit there; an SPD P1 Laplacian whose rows
+    away from the circle sum to zero; the triangulation covers the disk (total area within the inscribed polygon's)."""
+    side = 80
+    pts, mask = mg.disk_points(side, 0)
+    r = np.hypot(pts[:, 0] - 0.5, pts[:, 1] - 0.5)
+    np.testing.assert_allclose(r[mask], 0.5, rtol=1e-15)
+    assert (r[~mask] < 0.5).all()
+    n_in = int((~mask).sum())
+    h = 1.0 / (side - 1)
+    expect = np.pi * (0.5 - 0.5 * h) ** 2 / h ** 2  # lattice points within radius 1/2 - h/2
+    assert abs(n_in / expect - 1) < 0.02
+    tris = mg.delaunay(pts)
+    area = 0.5 * np.abs(mg._signed_area2(pts, tris)).sum()
+    nb = int(mask.sum())
+    polygon = 0.5 * nb * 0.25 * np.sin(2 * np.pi / nb)
+    assert abs(area - polygon) <= 1e-12
+    p = mg.disk_problem(side)
+    assert p.n == n_in
+    A = p.scipy()
+    assert abs(A - A.T).max() <= 1e-15 * abs(A).max()
+    far = np.hypot(p.coords[:, 0] - 0.5, p.coords[:, 1] - 0.5) < 0.5 - 3 * h
+    rs = np.asarray(A.sum(1)).ravel()
+    assert np.abs(rs[far]).max() <= 1e-13 * A.diagonal().max()
+    assert np.linalg.eigvalsh(A.toarray()).min() > 0

@@ -156,12 +156,15 @@ def _hierarchy_views(o, prob):
     ex0 = o.export_level(0)
     agg = ex0["agg"]
     Aprev, absprev = A, absA
+    alive = np.ones(A.shape[0])  # 1 where a row holds fine unknowns
     for level in range(1, o.num_levels):
         ex = o.export_level(level)
         P = H.prolongation(agg, ex["n"])
         G = (P.T @ Aprev @ P).tocsr()
         Gabs = (P.T @ absprev @ P).tocsr()
-        nonempty = np.asarray(P.sum(0)).ravel() > 0
+        # a cell is empty when none of its children holds a fine unknown (all children empty counts too)
+        alive = (P.T @ alive > 0).astype(np.float64)
+        nonempty = alive > 0
         out.append((ex, G, Gabs, ~nonempty, P))
         # the next level is summed from this level's true operator (empty rows zero)
         Aprev, absprev = G, Gabs
@@ -180,6 +183,7 @@ def _gamma(m):
     lambda: mg.jittered_problem(40, kappa_tiles=16),
     lambda: mg.graded_problem(6000),
     lambda: H.longrange_problem(3000, 150),
+    lambda: mg.disk_problem(48),
 ])
 def test_galerkin_matches_scipy_triple_product(orc, maker):
     prob = maker()
@@ -406,7 +410,8 @@ def test_single_level_direct(orc):
 
 
 @pytest.mark.parametrize("maker", [lambda: mg.uniform_problem(64), lambda: mg.jittered_problem(64),
-                                   lambda: mg.jittered_problem(60, kappa_tiles=16), lambda: mg.graded_problem(20000)])
+                                   lambda: mg.jittered_problem(60, kappa_tiles=16), lambda: mg.graded_problem(20000),
+                                   lambda: mg.disk_problem(72)])
 def test_solve_matches_direct_solver(orc, maker):
     prob = maker()
     o = orc.setup_problem(prob)
@@ -439,6 +444,24 @@ def test_zero_rhs_and_verbatim_mode(orc):
     xa, ia = o.solve(prob.b, mmax=-1)
     assert i1["status"] == ia["status"] == 0
     np.testing.assert_allclose(x1, xa, rtol=1e-6, atol=1e-9)
+
+
+def test_disk_empty_cells(orc):
+    """On the disk inside the unit square, the level-L cells without a point are the ones outside the circle or
+    nearly so: their share approaches 1 - pi/4 (0.215) as L grows; every quadtree level keeps exactly 4^k rows, and
+    each empty row is the identity row (eq. 10 on a non-rectangular domain)."""
+    prob = mg.disk_problem(130)
+    o = orc.setup_problem(prob)
+    agg = o.export_level(0)["agg"]
+    ex1 = o.export_level(1)
+    assert ex1["n"] == 4 ** ex1["k"]
+    share = (np.bincount(agg, minlength=ex1["n"]) == 0).mean()
+    assert 0.17 < share < 0.215, share
+    for ex, G, Gabs, empty, P in _hierarchy_views(o, prob):
+        assert ex["n"] == 4 ** ex["k"]
+        assert empty.any()
+        A = H.level_matrix(ex).toarray()
+        np.testing.assert_array_equal(A[np.ix_(empty, np.arange(ex["n"]))], np.eye(ex["n"])[empty])
 
 
 def test_empty_cells_equal_compacted_operator(orc):
