@@ -8,8 +8,10 @@ right-hand side U[-1, 1]. Inputs are resident in HBM before the timed region sta
 
 Printed: one JSON line. value = unknowns x steps / wall time of the K timed steps (DOF/s of setup + solve). Extra
 fields give solve-only rates on a resident hierarchy for both forms (solves/s, DOF/s, p50/p99 latency), the
-roofline of the dominant kernel (HIP-event timing of its launches inside the timed steps) and the oracle timed on
-the host (cpu_baseline).
+roofline of the dominant kernel (the persistent small-level workgroup: algorithmic flops per launch over its
+duration), the same for the HBM-bound fine residual with its counter-measured traffic (roofline_hbm), both from
+HIP-event timing of their launches inside the timed steps (alternate steps time one or the other), and the oracle
+timed on the host (cpu_baseline).
 """
 from __future__ import annotations
 
@@ -39,8 +41,10 @@ WORKLOADS = {
     "c5": ("serving stream: 512 Poisson-arrival requests, jittered-lattice P1 Poisson systems with DOF log-uniform in "
            "[1e4, 2e6], 30% repeat right-hand sides on a cached hierarchy", None),
 }
-ROOFLINE_KERNELS = {"spmv64": "k_outer_spmv_dot", "resid_fine32": "k_fine_resid_full<float>",
-                    "gs_fine32": "k_fine_resid<float> (color phase)"}
+ROOFLINE_KERNELS = {"engine32": "k_engine<float>", "spmv64": "k_outer_spmv_dot",
+                    "resid_fine32": "k_fine_resid_full<float>", "gs_fine32": "k_fine_resid<float> (color phase)"}
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X dense FP32 vector, 256 CUs at 2.4 GHz
+N_CU = 256
 
 
 def log(msg):
@@ -167,7 +171,11 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--repeats", type=int, default=20, help="resident-hierarchy solves per form for latency")
-    ap.add_argument("--roofline-kernel", default="resid_fine32", choices=sorted(ROOFLINE_KERNELS))
+    ap.add_argument("--roofline-kernel", default="engine32", choices=sorted(ROOFLINE_KERNELS),
+                    help="kernel of the roofline entry: the dominant one by time (the persistent small-level "
+                         "workgroup of the FP32 preconditioner)")
+    ap.add_argument("--hbm-kernel", default="resid_fine32", choices=["resid_fine32", "spmv64", "gs_fine32"],
+                    help="HBM-bound kernel reported beside it (roofline_hbm), with counter-measured traffic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--requests", type=int, default=512, help="c5: requests in the stream")
     ap.add_argument("--rate", type=float, default=40.0, help="c5: Poisson arrival rate (requests/s)")
@@ -180,8 +188,8 @@ def main():
     ap.add_argument("--traffic-commands", nargs="*", default=[], help="commands that produced the counter runs")
     args = ap.parse_args()
     if args.traffic_from:
-        rec = traffic_record(*args.traffic_from, args.roofline_kernel, args.workload, args.traffic_commands)
-        out = os.path.join(ROOT, "profiles", f"traffic_{args.roofline_kernel}_{args.workload}.json")
+        rec = traffic_record(*args.traffic_from, args.hbm_kernel, args.workload, args.traffic_commands)
+        out = os.path.join(ROOT, "profiles", f"traffic_{args.hbm_kernel}_{args.workload}.json")
         with open(out, "w") as f:
             json.dump(rec, f, indent=1)
         print(json.dumps(rec))
@@ -233,18 +241,22 @@ def main():
         info, _ = step()
         log(f"warmup {w}: setup {info['setup_ms']:.2f} ms solve {info['solve_ms']:.2f} ms iters {info['iters']}")
 
-    launches, kern_ms, bytes_per_launch = 0, 0.0, 0.0
+    # the timed steps alternate between timing the launches of the roofline kernel and of the HBM kernel
+    timed = {args.roofline_kernel: [0, 0.0, 0.0, 0], args.hbm_kernel: [0, 0.0, 0.0, 0]}
     infos = []
     for v in wall.values():
         v.clear()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        info, tm = step(args.roofline_kernel)
+        kind = args.roofline_kernel if k % 2 == 0 else args.hbm_kernel
+        info, tm = step(kind)
         infos.append(info)
-        launches += tm["launches"]
-        kern_ms += tm["total_ms"]
-        bytes_per_launch = tm["bytes_per_launch"]
+        acc = timed[kind]
+        acc[0] += tm["launches"]
+        acc[1] += tm["total_ms"]
+        acc[2] = tm["bytes_per_launch"]
+        acc[3] += 1
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -276,12 +288,30 @@ def main():
     x_gpu = x.cpu().numpy()
     h.close()
 
-    avg_ms = kern_ms / max(launches, 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
-    roofline = {"bound": "hbm", "kernel": ROOFLINE_KERNELS[args.roofline_kernel], "achieved": achieved,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                "traffic": traffic_from_profiles(args.roofline_kernel, args.workload),
-                "launches": launches, "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": bytes_per_launch}
+    solve_ms = float(np.median([i["solve_ms"] for i in infos]))
+
+    def entry(kind):
+        launches, kern_ms, per_launch, nsteps = timed[kind]
+        avg_ms = kern_ms / max(launches, 1)
+        if kind.startswith("engine"):
+            # one workgroup runs the cycle below ~4,096 cells as a chain of dependent steps (barrier after each):
+            # its limit is that chain's latency on one CU; the entry gives the chip-wide and the one-CU fractions
+            tf = per_launch / (avg_ms * 1e-3) / 1e12 if launches else None
+            peak = FP32_VECTOR_PEAK_TFLOPS
+            return {"bound": "alu", "kernel": ROOFLINE_KERNELS[kind], "achieved": tf, "peak": peak,
+                    "unit": "TFLOP/s", "frac": (tf / peak) if tf else None, "traffic": None,
+                    "launches": launches, "avg_us": avg_ms * 1e3, "algorithmic_flops_per_launch": per_launch,
+                    "peak_one_cu": peak / N_CU, "frac_one_cu": (tf / (peak / N_CU)) if tf else None,
+                    "share_of_solve": (kern_ms / max(nsteps, 1)) / solve_ms if nsteps else None,
+                    "limit": "latency of one workgroup's chain of dependent steps"}
+        gbs = per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
+        return {"bound": "hbm", "kernel": ROOFLINE_KERNELS[kind], "achieved": gbs, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": (gbs / HBM_PEAK_GBS) if gbs else None,
+                "traffic": traffic_from_profiles(kind, args.workload),
+                "launches": launches, "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch}
+
+    roofline = entry(args.roofline_kernel)
+    roofline_hbm = entry(args.hbm_kernel) if args.hbm_kernel != args.roofline_kernel else None
 
     if args.copy_calibration:
         copy_calibration()
@@ -301,13 +331,14 @@ def main():
         "config": {"workload": f"{args.workload}: {desc}", "n": prob.n, "nnz": prob.nnz, "tol": args.tol,
                    "step": "amg_setup + amg_solve (FP32 preconditioner, FP64 outer)",
                    "setup_ms_median": float(np.median([i["setup_ms"] for i in infos])),
-                   "solve_ms_median": float(np.median([i["solve_ms"] for i in infos])),
+                   "solve_ms_median": solve_ms,
                    "iters": infos[-1]["iters"], "relres": infos[-1]["relres"]},
         "step_wall_ms": {k: float(np.median(v)) for k, v in wall.items()},
         "solve_resident": forms,
         "engine": engine,
         "err_vs_oracle": err_vs_oracle,
         "roofline": roofline,
+        "roofline_hbm": roofline_hbm,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -157,7 +157,11 @@ amg_status amg_level_spmv(amg_hierarchy *h, int32_t level, const double *x, doub
 /* Kernel timing of one named kernel family for roofline measurement: while enabled, every launch of that
  * kernel on h's stream is bracketed by HIP events; amg_kernel_timing_read returns the number of launches and
  * their summed device time since the last enable. name: "spmv64" (outer FP64 sliced-ELL SpMV), "gs_fine32",
- * "gs_fine64" (fine-level smoother residual pass), "resid_fine32", "resid_fine64". name NULL disables. */
+ * "gs_fine64" (fine-level smoother residual pass), "resid_fine32", "resid_fine64", "engine32", "engine64" (the
+ * persistent small-level workgroup of that precision). name NULL disables. bytes_per_launch is the kernel's
+ * algorithmic HBM bytes per launch; for the engine kinds it is its algorithmic floating-point operations per
+ * launch instead (the engine works out of LDS and L2). Timing one family takes up to 4,096 launches; later
+ * launches run untimed. */
 amg_status amg_kernel_timing_enable(amg_hierarchy *h, const char *name);
 amg_status amg_kernel_timing_read(amg_hierarchy *h, int64_t *launches, double *total_ms, double *bytes_per_launch);
 

@@ -175,7 +175,8 @@ struct Timing {
   double bytes_per_launch = 0.0;
 };
 
-enum KernelKind { KK_SPMV64 = 0, KK_GS_FINE32, KK_GS_FINE64, KK_RESID_FINE32, KK_RESID_FINE64, KK_COUNT };
+enum KernelKind { KK_SPMV64 = 0, KK_GS_FINE32, KK_GS_FINE64, KK_RESID_FINE32, KK_RESID_FINE64, KK_ENGINE64, KK_ENGINE32,
+                  KK_COUNT };
 
 struct Chunk {                  // a device allocation that several arrays are carved from
   char *base = nullptr;
@@ -219,6 +220,7 @@ struct amg_hierarchy {
   int engine_lvec[2] = {0, 0};       // work vectors of a global engine top level held in LDS (bit per vector slot)
   void *engine_ops[2] = {nullptr, nullptr};
   int engine_nops[2] = {0, 0};
+  double engine_flops[2] = {0.0, 0.0};  // algorithmic floating-point operations of one engine launch
   int64_t engine_global_rows = 4096;  // a top level this small may run from global memory
   size_t engine_lds[2] = {0, 0};
   size_t lds_max = 0;
