@@ -1035,6 +1035,35 @@ __device__ inline void eng_reduce(double (&v)[ND], double *red) {
   }
 }
 
+// The same sum delivered to thread 0 only, for steps whose result thread 0 stores: waves at or past `waves` hold
+// zeros (their threads had no rows) and skip the shuffles, and one thread adds the wave sums, so the waves that do
+// the work do not share their SIMDs with idle ones. The sum equals eng_reduce's (adding zeros changes nothing).
+template <int ND>
+__device__ inline void eng_reduce_t0(double (&v)[ND], double *red, int waves) {
+  if (static_cast<int>(threadIdx.x >> 6) < waves) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+      for (int j = 0; j < ND; j++) v[j] += __shfl_down(v[j], off, 64);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int j = 0; j < ND; j++) red[j * kEngWaves + (threadIdx.x >> 6)] = v[j];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int j = 0; j < ND; j++) {
+      double acc = 0.0;
+      for (int w = 0; w < waves; w++) acc += red[j * kEngWaves + w];
+      v[j] = acc;
+    }
+}
+
+// waves of the workgroup that hold rows of an n-row level (threads tid < n)
+__device__ inline int eng_waves(int n) {
+  return n >= kEngThreads ? kEngWaves : (n + 63) >> 6;
+}
+
 // (A x)_q on an engine level, x given by a function of the index (a stored vector, or values formed on the fly)
 template <class T, class XV>
 __device__ __forceinline__ T eng_row_f(int k, int n, const T *ax, const int32_t *optr, const int32_t *ocol, const T *oval,
@@ -1094,7 +1123,7 @@ __device__ __forceinline__ void eng_dot_beta(const EngMem<T, LDS> &M, int n, con
   const T *p1 = M.vec(EV_P1), *q0 = M.vec(EV_Q0);
   double t[1] = {0.0};
   for (int i = threadIdx.x; i < n; i += kEngThreads) t[0] += static_cast<double>(p1[i]) * static_cast<double>(q0[i]);
-  eng_reduce<1>(t, C.red);
+  eng_reduce_t0<1>(t, C.red, eng_waves(n));
   if (threadIdx.x == 0) C.sc[ES_BETA] = (C.sc[ES_STOP] != 0.0) ? 0.0 : -t[0] / C.sc[ES_D0];
 }
 
@@ -1312,7 +1341,7 @@ __device__ __forceinline__ void eng_step(const EngOp &op, const EngLevel<T> *LV,
           }
         }
       }
-      eng_reduce<2>(v, C.red);
+      eng_reduce_t0<2>(v, C.red, eng_waves(n));
       if (tid == 0) {
         const bool stop = !(v[0] > 0.0);
         C.sc[ES_D0] = v[0];
@@ -1348,7 +1377,7 @@ __device__ __forceinline__ void eng_step(const EngOp &op, const EngLevel<T> *LV,
             v[1] += static_cast<double>(wq[r]) * static_cast<double>(xq[r]);
           }
       }
-      eng_reduce<2>(v, C.red);
+      eng_reduce_t0<2>(v, C.red, eng_waves(n));
       if (tid == 0) C.sc[ES_A1] = (C.sc[ES_STOP] != 0.0 || !(v[0] > 0.0)) ? 0.0 : v[1] / v[0];
       break;
     }
