@@ -50,6 +50,7 @@ def lib():
         L.orc_level_info.argtypes = [p, i32, C.POINTER(i64), C.POINTER(i32), C.POINTER(i64), C.POINTER(i32)]
         L.orc_export_level.argtypes = [p, i32, p, p, p, p, p, p, p]
         L.orc_smooth.argtypes = [p, i32, p, p, i32]
+        L.orc_set_block_smoother.argtypes = [p, i32]
         L.orc_level_spmv.argtypes = [p, i32, p, p]
         L.orc_nlpcg_test.argtypes = [i64, p, p, p, p, i32, i32, p]
         _lib = L
@@ -147,6 +148,12 @@ class Oracle:
         if st != OK:
             raise OracleError(st, "orc_apply_precond")
         return z
+
+    def set_block_smoother(self, on=True):
+        """Exact solves of the cells' diagonal blocks in the fine smoother (cells of at most 32 unknowns)."""
+        st = lib().orc_set_block_smoother(self._h, 1 if on else 0)
+        if st:
+            raise OracleError(st, "orc_set_block_smoother")
 
     def smooth(self, level, f, x, forward=True):
         f = np.ascontiguousarray(f, dtype=np.float64)

@@ -31,6 +31,10 @@
  *     earlier directions, and a step whose (p, Ap) <= 0 ends the iteration with the current iterate.
  *  R10 outer iteration: Algorithm 2.1 as a flexible CG at the fine level keeping the last mmax directions; stop on
  *     the recurrence residual ||r|| <= tol ||b||, confirm with the true residual, restart from it if it fails.
+ *  R11 the other reading of "block-wise Gauss-Seidel" (Section 4.5), optional (orc_set_block_smoother): the cells
+ *     of a color phase take the exact solve of their diagonal block, u_cell += A_cc^{-1} r_cell, through a dense
+ *     Cholesky factor made once (the block in ascending unknown order, entries summed in CSR order); R_k and R_k^t
+ *     then differ only in the color order. Cells of more than ORC_BLOCK_MAX unknowns keep the substitution of R7.
  */
 #include "oracle.h"
 
@@ -68,6 +72,9 @@ struct orc_h {
     double *chol;    /* Cholesky factor of the coarsest level, row-major lower */
     int64_t nc;
     int inner, sweeps;
+    int block;       /* R11: exact block solves on cells of at most ORC_BLOCK_MAX unknowns */
+    int64_t *boff;   /* cell -> offset of its m x m factor in bfac (4^L + 1) */
+    double *bfac;
 };
 
 static int64_t pow4(int k) { return (int64_t)1 << (2 * k); }
@@ -359,6 +366,14 @@ static void smooth(const orc_h *h, int l, const double *f, double *x, int forwar
             for (int64_t I = 0; I < nL; I++) {
                 if (cell_color_lex(I, sL) != c) continue;
                 int64_t a0 = h->cstart[I], a1 = h->cstart[I + 1];
+                if (h->block && a1 - a0 <= ORC_BLOCK_MAX) { /* R11: exact solve of the cell's block */
+                    double rc[ORC_BLOCK_MAX], dc[ORC_BLOCK_MAX];
+                    int64_t m = a1 - a0;
+                    for (int64_t a = 0; a < m; a++) rc[a] = r[h->cdofs[a0 + a]];
+                    chol_solve(h->bfac + h->boff[I], m, rc, dc);
+                    for (int64_t a = 0; a < m; a++) x[h->cdofs[a0 + a]] += dc[a];
+                    continue;
+                }
                 for (int64_t q = 0; q < a1 - a0; q++) {
                     int32_t i = h->cdofs[forward ? a0 + q : a1 - 1 - q];
                     double acc = r[i];
@@ -508,10 +523,47 @@ static int bhat(orc_h *h, int l, const double *f, double *u) {
 /* ------------------------------------------------------------------------------------------------------------ */
 /* setup                                                                                                          */
 
+/* R11: factor every cell of at most ORC_BLOCK_MAX unknowns (on = 1), or return to R7 (on = 0) */
+int orc_set_block_smoother(orc_h *h, int on) {
+    if (!h || (on != 0 && on != 1)) return ORC_INVALID;
+    h->block = 0;
+    if (!on || h->nlev == 1) return ORC_OK;
+    if (!h->bfac) {
+        int64_t nL = pow4(h->L);
+        h->boff = calloc(nL + 1, sizeof(int64_t));
+        if (!h->boff) return ORC_NOMEM;
+        for (int64_t I = 0; I < nL; I++) {
+            int64_t m = h->cstart[I + 1] - h->cstart[I];
+            h->boff[I + 1] = h->boff[I] + (m <= ORC_BLOCK_MAX ? m * m : 0);
+        }
+        h->bfac = calloc(h->boff[nL] ? h->boff[nL] : 1, sizeof(double));
+        if (!h->bfac) { free(h->boff); h->boff = NULL; return ORC_NOMEM; }
+        for (int64_t I = 0; I < nL; I++) {
+            int64_t a0 = h->cstart[I], m = h->cstart[I + 1] - a0;
+            if (m > ORC_BLOCK_MAX) continue;
+            double *blk = h->bfac + h->boff[I];
+            for (int64_t a = 0; a < m; a++) {
+                int32_t i = h->cdofs[a0 + a];
+                for (int64_t e = h->rp[i]; e < h->rp[i + 1]; e++) {
+                    int32_t j = h->ci[e];
+                    if (h->cell[j] != (int32_t)I) continue;
+                    int64_t b = 0;
+                    while (h->cdofs[a0 + b] != j) b++;  /* position of j in the cell */
+                    blk[a * m + b] += h->va[e];
+                }
+            }
+            int st = cholesky(blk, m);
+            if (st) { free(h->bfac); free(h->boff); h->bfac = NULL; h->boff = NULL; return st; }
+        }
+    }
+    h->block = 1;
+    return ORC_OK;
+}
+
 void orc_free(orc_h *h) {
     if (!h) return;
     free(h->rp); free(h->ci); free(h->va); free(h->diag);
-    free(h->cell); free(h->cstart); free(h->cdofs); free(h->chol);
+    free(h->cell); free(h->cstart); free(h->cdofs); free(h->chol); free(h->boff); free(h->bfac);
     if (h->lev)
         for (int l = 1; l < h->nlev; l++) {
             olev *lv = &h->lev[l];

@@ -53,6 +53,11 @@ int orc_export_level(const orc_h *h, int level, int32_t *agg, uint8_t *color, in
 /* One smoothing sweep at a level on vectors in that level's numbering: forward = R (colors 0..3, forward
  * substitution inside cells), else R^t (colors 3..0, backward). x is updated in place. */
 int orc_smooth(orc_h *h, int level, const double *f, double *x, int forward);
+/* The other reading of the fine smoother (Section 4.5): on = 1 makes each cell of at most ORC_BLOCK_MAX unknowns
+ * take the exact solve of its diagonal block in every color phase (a dense Cholesky factor per cell, made on the
+ * first call); larger cells keep the forward / backward substitution. on = 0 returns to the substitution. */
+#define ORC_BLOCK_MAX 32
+int orc_set_block_smoother(orc_h *h, int on);
 /* y = A_level x */
 int orc_level_spmv(orc_h *h, int level, const double *x, double *y);
 

@@ -270,6 +270,76 @@ def test_galerkin_invariants(orc, maker):
 # smoother (Section 4.5)
 # ---------------------------------------------------------------------------------------------------------------
 
+def _block_splitting(A, color, cell, forward, block_max=32):
+    """Matrix form of one sweep of the exact-block smoother: x_new = x + M^{-1}(f - A x), where M keeps, for the
+    forward sweep, the couplings to earlier colors and the whole diagonal block of every cell of at most block_max
+    unknowns (the cells of one color see each other's phase-start values, so couplings between distinct cells of
+    one color are dropped); larger cells keep the lower (forward) / upper (backward) triangle of their block.
+    Backward: later colors."""
+    A = sp.csr_matrix(A)
+    C = A.tocoo()
+    i, j, v = C.row, C.col, C.data
+    size = np.bincount(cell)[cell]
+    same = cell[i] == cell[j]
+    earlier = (color[j] < color[i]) if forward else (color[j] > color[i])
+    tri = (j <= i) if forward else (j >= i)
+    keep = (earlier & ~same) | (same & ((size[i] <= block_max) | tri))
+    return sp.csr_matrix((v[keep], (i[keep], j[keep])), shape=A.shape)
+
+
+@pytest.mark.parametrize("maker", [lambda: mg.jittered_problem(40), lambda: mg.graded_problem(6000),
+                                   lambda: mg.jittered_problem(30, kappa_tiles=16), lambda: mg.disk_problem(48)])
+def test_block_smoother_is_block_splitting(orc, maker):
+    """The exact-block reading of the fine smoother (the cells' diagonal blocks solved exactly): one sweep equals
+    the block splitting above, forward and backward, from zero and from a nonzero start."""
+    prob = maker()
+    o = orc.setup_problem(prob)
+    o.set_block_smoother(True)
+    A = H.csr_of(prob)
+    ex0 = o.export_level(0)
+    cell, color = ex0["agg"].astype(np.int64), ex0["color"].astype(np.int64)
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal(prob.n)
+    x0 = rng.standard_normal(prob.n)
+    for forward in (True, False):
+        M = _block_splitting(A, color, cell, forward).tocsc()
+        np.testing.assert_allclose(o.smooth(0, f, np.zeros(prob.n), forward), spla.spsolve(M, f),
+                                   rtol=1e-9, atol=1e-11)
+        np.testing.assert_allclose(o.smooth(0, f, x0, forward), x0 + spla.spsolve(M, f - A @ x0),
+                                   rtol=1e-9, atol=1e-10)
+
+
+def test_block_smoother_single_cell_is_exact(orc):
+    """When every unknown lies in one level-L cell (a cluster in a large box), one forward sweep from zero is the
+    exact solve of A x = f (only that cell's color has unknowns); the substitution reading is not."""
+    pts = 0.05 + 0.05 * H.scattered_points(30, 8)
+    A = H.graph_laplacian_problem(pts, 8)
+    o = orc.Oracle(pts, A.indptr.astype(np.int64), A.indices.astype(np.int32), A.data, box=(0, 1, 0, 1),
+                   coarse_max=4)
+    assert o.num_levels > 1 and len(np.unique(o.export_level(0)["agg"])) == 1
+    f = np.random.default_rng(2).standard_normal(30)
+    xs = np.linalg.solve(A.toarray(), f)
+    assert np.linalg.norm(o.smooth(0, f, np.zeros(30), True) - xs) > 1e-6 * np.linalg.norm(xs)
+    o.set_block_smoother(True)
+    np.testing.assert_allclose(o.smooth(0, f, np.zeros(30), True), xs, rtol=1e-12, atol=1e-14)
+    o.set_block_smoother(False)
+    assert np.linalg.norm(o.smooth(0, f, np.zeros(30), True) - xs) > 1e-6 * np.linalg.norm(xs)
+
+
+def test_block_smoother_preconditioner_symmetric(orc):
+    """R_k and R_k^t stay adjoint with exact blocks, so the two-level B^ (fine smoothing around the exact coarsest
+    solve, a linear map) stays symmetric: (B u, v) = (u, B v)."""
+    prob = mg.jittered_problem(16, kappa_tiles=4)
+    o = orc.setup_problem(prob)
+    assert o.num_levels == 2
+    o.set_block_smoother(True)
+    rng = np.random.default_rng(9)
+    u, v = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
+    bu, bv = o.apply_precond(u), o.apply_precond(v)
+    assert abs(bu @ v - u @ bv) <= 1e-11 * abs(bu @ v)
+    assert u @ bu > 0 and v @ bv > 0
+
+
 @pytest.mark.parametrize("maker", [lambda: mg.jittered_problem(40), lambda: mg.graded_problem(6000),
                                    lambda: mg.jittered_problem(30, kappa_tiles=16)])
 def test_fine_sweep_is_triangular_solve(orc, maker):
