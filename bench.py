@@ -2,7 +2,9 @@
 
 A step is one pass of the whole hot path over the workload: amg_setup (box, cell keys, counting sort, sliced ELL,
 Galerkin hierarchy, coarsest factor) followed by one amg_solve to a 1e-8 relative residual with the FP32
-preconditioner / FP64 outer iteration. The default workload is the quasi-uniform 2D P1 Poisson system: a 1024 x 1024
+preconditioner / FP64 outer iteration, the fine smoother solving each cell's diagonal block exactly (the 4-color
+block Gauss-Seidel of Section 4.5 with the aggregates as blocks; --smoother 0 takes the substitution reading). The
+default workload is the quasi-uniform 2D P1 Poisson system: a 1024 x 1024
 lattice jittered by U[-0.3h, 0.3h], Delaunay-triangulated, Dirichlet boundary eliminated (1,044,484 unknowns),
 right-hand side U[-1, 1]. Inputs are resident in HBM before the timed region starts.
 
@@ -137,7 +139,7 @@ def traffic_record(fetch_dir, write_dir, kernel, workload, commands):
             "bytes_per_launch": (f_k * sf + w_k * sw) * 1024.0, "commands": commands}
 
 
-def cpu_baseline(prob, tol):
+def cpu_baseline(prob, tol, smoother):
     import oracle
     cores = len(os.sched_getaffinity(0))
     model = ""
@@ -151,13 +153,16 @@ def cpu_baseline(prob, tol):
         pass
     t0 = time.perf_counter()
     o = oracle.setup_problem(prob)
+    if smoother:
+        o.set_block_smoother(True)  # the same reading of the fine smoother as the GPU run (its factors: setup)
     t1 = time.perf_counter()
     x, info = o.solve(prob.b, tol=tol)
     t2 = time.perf_counter()
     o.close()
     total = t2 - t0
     return {"value": prob.n / total, "unit": "DOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full oracle setup + FP64 solve of the same {prob.n}-unknown system to {tol:g} "
+            "sample": f"one full oracle setup + FP64 solve of the same {prob.n}-unknown system to {tol:g}, same "
+                      f"fine smoother "
                       f"(setup {t1 - t0:.2f} s, solve {t2 - t1:.2f} s, {info['iters']} iterations); "
                       f"single-threaded, 1 of {cores} host cores ({model})",
             "setup_s": t1 - t0, "solve_s": t2 - t1, "iters": info["iters"]}, x
@@ -170,6 +175,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--smoother", type=int, default=1, choices=[0, 1],
+                    help="fine block Gauss-Seidel of Section 4.5: 1 (default) the exact solve of each cell's diagonal "
+                         "block (cells of at most 32 unknowns), 0 one substitution over each cell's unknowns")
     ap.add_argument("--repeats", type=int, default=20, help="resident-hierarchy solves per form for latency")
     ap.add_argument("--roofline-kernel", default="engine32", choices=sorted(ROOFLINE_KERNELS),
                     help="kernel of the roofline entry: the dominant one by time (the persistent small-level "
@@ -222,7 +230,7 @@ def main():
 
     def step(timing_kernel=None):
         c0 = time.perf_counter()
-        h = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=1, stream=stream)
+        h = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=1, stream=stream, smoother=args.smoother)
         c1 = time.perf_counter()
         if timing_kernel:
             h.timing_enable(timing_kernel)
@@ -266,7 +274,7 @@ def main():
 
     # resident-hierarchy solves: both forms
     forms = {}
-    h = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=0, stream=stream)
+    h = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=0, stream=stream, smoother=args.smoother)
     engine = {name: h.engine_info(prec) for name, prec in (("fp64", 0), ("fp32_precond", 1))}
     levels = [h.level_info(l) for l in range(h.num_levels)]
     log(f"levels {[(lv['k'], lv['n']) for lv in levels]} engine {engine}")
@@ -320,7 +328,7 @@ def main():
     err_vs_oracle = None
     if not args.no_cpu_baseline:
         log("oracle (CPU baseline) ...")
-        cpu, x_orc = cpu_baseline(prob, args.tol)
+        cpu, x_orc = cpu_baseline(prob, args.tol, args.smoother)
         err_vs_oracle = float(np.linalg.norm(x_gpu - x_orc) / np.linalg.norm(x_orc))
         log(f"oracle: {cpu['sample']}; fp32-precond solution vs oracle rel err {err_vs_oracle:.2e}")
 
@@ -330,6 +338,7 @@ def main():
         "vs_baseline": None, "dtype": "f32/f64", "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n": prob.n, "nnz": prob.nnz, "tol": args.tol,
                    "step": "amg_setup + amg_solve (FP32 preconditioner, FP64 outer)",
+                   "smoother": ["cell substitution", "exact cell blocks"][args.smoother],
                    "setup_ms_median": float(np.median([i["setup_ms"] for i in infos])),
                    "solve_ms_median": solve_ms,
                    "iters": infos[-1]["iters"], "relres": infos[-1]["relres"]},

@@ -55,6 +55,11 @@ typedef struct {
     int32_t batch;       /* 1 (default): amg_solve_batch runs this system, when it has at most 65,536 unknowns, as
                             one workgroup of a whole-solve launch shared with the batch's other small systems;
                             0: it runs as its own amg_solve */
+    int32_t smoother;    /* fine-level block smoother of Section 4.5: 0 (default) one forward (R_k) / backward
+                            (R_k^t) substitution over each cell's unknowns per color phase; 1 the exact solve of
+                            each cell's diagonal block (a dense Cholesky factor per cell made at setup) for cells of
+                            at most 32 unknowns, the substitution for larger ones. With 1 the system never takes the
+                            whole-solve workgroup of amg_solve_batch. */
     const double *box;   /* host {a1, b1, a2, b2}: the auxiliary box of eq. (5); NULL = bounding box of coords
                             (eq. 6). Points outside a given box are rejected. */
     void *stream;        /* hipStream_t used for every launch; NULL = default stream */

@@ -25,7 +25,8 @@ EXPORTED = ["amg_default_options", "amg_setup", "amg_solve", "amg_free", "amg_se
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("coarse_max", C.c_int32), ("inner_iters", C.c_int32),
                 ("sweeps", C.c_int32), ("outer_mmax", C.c_int32), ("max_iters", C.c_int32),
-                ("engine", C.c_int32), ("batch", C.c_int32), ("box", C.POINTER(C.c_double)), ("stream", C.c_void_p)]
+                ("engine", C.c_int32), ("batch", C.c_int32), ("smoother", C.c_int32), ("box", C.POINTER(C.c_double)),
+                ("stream", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -107,10 +108,11 @@ def estimate_bytes(n: int, nnz: int, **opts) -> int:
 
 
 def _options(precision=0, coarse_max=64, inner_iters=2, sweeps=1, outer_mmax=1, max_iters=1000, box=None,
-             stream=None, engine=1, batch=1):
+             stream=None, engine=1, batch=1, smoother=0):
     o = default_options()
     o.precision, o.coarse_max, o.inner_iters = precision, coarse_max, inner_iters
     o.sweeps, o.outer_mmax, o.max_iters, o.engine, o.batch = sweeps, outer_mmax, max_iters, engine, batch
+    o.smoother = smoother
     o._box = None
     if box is not None:
         o._box = (C.c_double * 4)(*[float(v) for v in box])
@@ -133,7 +135,7 @@ class Hierarchy:
     """
 
     def __init__(self, coords, row_ptr, col, val, box=None, precision=0, coarse_max=64, inner_iters=2, sweeps=1,
-                 outer_mmax=1, max_iters=1000, stream=None, engine=1, batch=1):
+                 outer_mmax=1, max_iters=1000, stream=None, engine=1, batch=1, smoother=0):
         import torch
         L = load()
         if not torch.cuda.is_available():
@@ -147,7 +149,7 @@ class Hierarchy:
         self.nnz = int(col.numel())
         self._stream = stream
         o = _options(precision, coarse_max, inner_iters, sweeps, outer_mmax, max_iters, box,
-                     _stream_handle(stream), engine, batch)
+                     _stream_handle(stream), engine, batch, smoother)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             _check(L.amg_setup(self.n, _ptr(coords), _ptr(row_ptr), _ptr(col), _ptr(val), self.nnz, C.byref(o),

@@ -225,6 +225,7 @@ void amg_default_options(amg_options *opt) {
   opt->max_iters = 1000;
   opt->engine = 1;
   opt->batch = 1;
+  opt->smoother = 0;
   opt->box = nullptr;
   opt->stream = nullptr;
 }

@@ -23,6 +23,7 @@ constexpr int kBlock = 256;        // threads per workgroup for elementwise / re
 constexpr int kSliceRows = 64;
 constexpr int kSellWindow = 256;    // rows are sorted by length inside windows of this many positions (4 slices)     // sliced-ELL slice height = one wavefront
 constexpr int kRedBlocksMax = 1024;
+constexpr int kBlockMax = 32;      // exact-block smoother: cells of at most this many unknowns are factored
 constexpr int kBigCell = 10;        // cells with more unknowns get a level-scheduled in-cell substitution
 constexpr int kScalars = 16;       // device scalars per level
 
@@ -158,6 +159,11 @@ struct FineLevel {
   int32_t *big_lofs[2] = {nullptr, nullptr};    // per big cell, its first entry in big_lptr (nbig + 1)
   int32_t *big_lptr[2] = {nullptr, nullptr};    // level starts as row positions, then the cell's end
   int32_t *big_sched[2] = {nullptr, nullptr};   // the big cells' rows ordered by level (indexed by row position)
+  // exact-block smoother: the cell's Cholesky factor (packed lower triangle, row-major) at boff[q] for cells of at most
+  // kBlockMax unknowns (empty otherwise); cells above kBlockMax are the big cells and keep the substitution
+  int64_t *boff = nullptr;                      // 4^L + 1
+  double *bfac64 = nullptr;
+  float *bfac32 = nullptr;
 };
 
 template <class T>

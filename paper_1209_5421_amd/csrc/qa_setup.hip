@@ -877,11 +877,93 @@ static amg_status cell_list(amg_hierarchy *h, int32_t threshold, int32_t **cells
   return AMG_OK;
 }
 
+// factor size of a cell for the exact-block smoother (packed lower triangle, m (m + 1) / 2 for m <= kBlockMax,
+// else 0)
+__global__ void __launch_bounds__(kBlock) k_block_size(int64_t nL, const int32_t *__restrict__ crow,
+                                                        int64_t *__restrict__ size) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nL) return;
+  const int64_t m = crow[q + 1] - crow[q];
+  size[q] = m <= kBlockMax ? m * (m + 1) / 2 : 0;
+}
+
+// position of (i, j), j <= i, in a packed lower triangle (row-major)
+__device__ inline int packed_ij(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// The lower triangle of a cell's diagonal block (its unknowns ascending; the diagonal as summed for the smoother,
+// each in-cell coupling below the diagonal added in the caller's entry order) and its Cholesky factor in place:
+// column by column, each entry's inner product over the earlier columns in ascending order, then the division by
+// the diagonal (the coarsest factor's order, which reads only the lower triangle). One thread per cell.
+__global__ void __launch_bounds__(kBlock) k_block_factor(int64_t nL, const int32_t *__restrict__ crow,
+                                                          const int32_t *__restrict__ icp,
+                                                          const int32_t *__restrict__ icc,
+                                                          const double *__restrict__ icv,
+                                                          const double *__restrict__ diag,
+                                                          const int64_t *__restrict__ boff, double *__restrict__ fac,
+                                                          int *flag) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nL) return;
+  const int32_t r0 = crow[q];
+  const int m = crow[q + 1] - r0;
+  if (m == 0 || m > kBlockMax) return;
+  double *a = fac + boff[q];
+  for (int i = 0; i < m; i++) {
+    a[packed_ij(i, i)] = diag[r0 + i];
+    for (int32_t e = icp[r0 + i]; e < icp[r0 + i + 1]; e++) {
+      const int j = icc[e] - r0;
+      if (j < i) a[packed_ij(i, j)] += icv[e];
+    }
+  }
+  for (int j = 0; j < m; j++) {
+    double d = a[packed_ij(j, j)];
+    for (int k = 0; k < j; k++) d -= a[packed_ij(j, k)] * a[packed_ij(j, k)];
+    if (!(d > 0.0)) {
+      atomicOr(flag, F_NOT_SPD);
+      d = 1.0;
+    }
+    const double ljj = sqrt(d);
+    a[packed_ij(j, j)] = ljj;
+    for (int i = j + 1; i < m; i++) {
+      double s = a[packed_ij(i, j)];
+      for (int k = 0; k < j; k++) s -= a[packed_ij(i, k)] * a[packed_ij(j, k)];
+      a[packed_ij(i, j)] = s / ljj;
+    }
+  }
+}
+
+static amg_status build_block_factors(amg_hierarchy *h) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
+  int64_t *size = dalloc_n<int64_t>(h, nL);
+  F.boff = dalloc_n<int64_t>(h, nL + 1);
+  if (!size || !F.boff) return AMG_ERR_NOMEM;
+  k_block_size<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, size);
+  QA_LAUNCH_CHECK();
+  QA_TRY(scan_exclusive_i64(size, F.boff, nL, s, h));
+  int64_t total = 0;
+  QA_HIP(hipMemcpyAsync(&total, F.boff + nL, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  QA_HIP(hipStreamSynchronize(s));
+  F.bfac64 = dalloc_n<double>(h, std::max<int64_t>(total, 1));
+  F.bfac32 = dalloc_n<float>(h, std::max<int64_t>(total, 1));
+  if (!F.bfac64 || !F.bfac32) return AMG_ERR_NOMEM;
+  QA_HIP(hipMemsetAsync(F.bfac64, 0, sizeof(double) * std::max<int64_t>(total, 1), s));
+  k_block_factor<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, F.ic_ptr, F.ic_col, F.ic_val64, F.diag64, F.boff, F.bfac64,
+                                             h->dflag);
+  QA_LAUNCH_CHECK();
+  if (total > 0) {
+    k_convert<double, float><<<nblk(total), kBlock, 0, s>>>(total, F.bfac64, F.bfac32);
+    QA_LAUNCH_CHECK();
+  }
+  return AMG_OK;
+}
+
 static amg_status build_big_cells(amg_hierarchy *h) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
   const int64_t n = h->n;
-  QA_TRY(cell_list(h, kBigCell, &F.big_cells, &F.nbig, F.big_color));
+  // cells the smoother's per-cell kernels leave to the level-scheduled substitution
+  QA_TRY(cell_list(h, h->opt.smoother ? kBlockMax : kBigCell, &F.big_cells, &F.nbig, F.big_color));
   if (F.nbig == 0) return AMG_OK;
   int32_t *lv = dalloc_n<int32_t>(h, n);
   int32_t *cnt = dalloc_n<int32_t>(h, F.nbig);
@@ -994,6 +1076,7 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
     QA_LAUNCH_CHECK();
   }
   QA_TRY(build_big_cells(h));
+  if (h->opt.smoother) QA_TRY(build_block_factors(h));
 
   // Galerkin operators, level L first, then coarser
   h->lev.assign(h->nlev, QuadLevel{});
@@ -1137,6 +1220,9 @@ extern "C" amg_status amg_estimate_bytes(int64_t n, int64_t nnz, const amg_optio
   } else {
     b += 4.0 * n * n * 8;
   }
+  // exact-block smoother: a packed factor of m (m + 1) / 2 FP64 + FP32 values per cell of m <= kBlockMax unknowns
+  // (at most (kBlockMax + 1) / 2 values per unknown) and the cell offsets
+  if (o.smoother == 1 && nlev > 1) b += static_cast<double>(n) * (kBlockMax + 1) * 6 + std::ldexp(1.0, 2 * L) * 16;
   b += 1 << 20;  // scalars, partial sums, alignment slack
   // arrays are carved from shared chunks of about b / 8 bytes (see chunk_unit_for): allow a chunk and a half unused
   b += 1.5 * static_cast<double>(chunk_unit_for(static_cast<size_t>(b)));
@@ -1155,7 +1241,7 @@ extern "C" amg_status amg_setup(int64_t n, const double *coords, const int64_t *
     return AMG_ERR_INVALID;
   if ((o.precision != 0 && o.precision != 1) || o.coarse_max < 4 || o.coarse_max > 1024 || o.inner_iters < 1 ||
       o.inner_iters > 2 || o.sweeps < 1 || o.sweeps > 8 || (o.outer_mmax != 0 && o.outer_mmax != 1) ||
-      o.max_iters < 1)
+      o.max_iters < 1 || (o.smoother != 0 && o.smoother != 1))
     return AMG_ERR_INVALID;
   if (o.box) {
     for (int t = 0; t < 4; t++)

@@ -405,6 +405,99 @@ __global__ void __launch_bounds__(kBlock) k_fine_subst(const int32_t *__restrict
   for (int32_t p = a; p < b; p++) x[p] += d[p];
 }
 
+// Exact-block smoother (the other reading of Section 4.5's block Gauss-Seidel): each cell of at most kBlockMax
+// unknowns in [q_begin, q_end) solves L L^t delta = r with its Cholesky factor (forward, then backward, each row's
+// products over the earlier rows in ascending order); delta overwrites d; x += delta. The same in both sweep
+// directions. One thread per cell. A workgroup's cells hold a contiguous range of rows and of factor values: both
+// are staged in LDS with coalesced loads, each thread solves in place there, and the deltas go back with coalesced
+// stores (rows of cells left to k_fine_subst_big untouched). A range larger than the staging arrays takes the same
+// arithmetic on global memory.
+constexpr int kBlkRows = 2048;
+constexpr int kBlkFac = 8192;
+
+// L L^t v = v in place, L packed lower triangle (row i holds L_i0 .. L_ii), v with the given element stride
+template <class T>
+__device__ inline void block_solve(const T *Lf, int m, T *v, int stride) {
+  for (int i = 0; i < m; i++) {
+    const T *Li = Lf + i * (i + 1) / 2;
+    T s = v[i * stride];
+    for (int k = 0; k < i; k++) s -= Li[k] * v[k * stride];
+    v[i * stride] = s / Li[i];
+  }
+  for (int i = m - 1; i >= 0; i--) {
+    T s = v[i * stride];
+    for (int k = i + 1; k < m; k++) s -= Lf[k * (k + 1) / 2 + i] * v[k * stride];
+    v[i * stride] = s / Lf[i * (i + 1) / 2 + i];
+  }
+}
+
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_fine_block(const int32_t *__restrict__ crow,
+                                                        const int64_t *__restrict__ boff, const T *__restrict__ fac,
+                                                        const T *__restrict__ src, T *__restrict__ d,
+                                                        T *__restrict__ x, int64_t q_begin, int64_t q_end) {
+  __shared__ T s_r[kBlkRows];
+  __shared__ T s_f[kBlkFac];
+  __shared__ uint8_t s_mine[kBlkRows];
+  const int t = threadIdx.x;
+  const int64_t qb = q_begin + static_cast<int64_t>(blockIdx.x) * kBlock;
+  const int64_t qe = std::min<int64_t>(qb + kBlock, q_end);
+  const int64_t q = qb + t;
+  const int32_t r0 = crow[qb], r1 = crow[qe];
+  const int64_t f0 = boff[qb], f1 = boff[qe];
+  const int32_t ca = q < qe ? crow[q] : 0, cb = q < qe ? crow[q + 1] : 0;
+  const int64_t fo = q < qe ? boff[q] : 0;
+  const int nr = r1 - r0;
+  const int64_t nf = f1 - f0;
+  const int m = cb - ca;
+  if (nr <= kBlkRows && nf <= kBlkFac) {  // uniform over the workgroup
+    constexpr int kRowIt = kBlkRows / kBlock, kFacIt = kBlkFac / kBlock;
+    T rv[kRowIt];
+#pragma unroll
+    for (int u = 0; u < kRowIt; u++) {
+      const int i = t + u * kBlock;
+      if (i < nr) rv[u] = src[r0 + i];
+    }
+#pragma unroll
+    for (int u = 0; u < kFacIt; u++) {
+      const int k = t + u * kBlock;
+      if (k < nf) s_f[k] = fac[f0 + k];
+    }
+#pragma unroll
+    for (int u = 0; u < kRowIt; u++) {
+      const int i = t + u * kBlock;
+      if (i < nr) {
+        s_r[i] = rv[u];
+        s_mine[i] = 0;
+      }
+    }
+    __syncthreads();
+    if (q < qe && m > 0 && m <= kBlockMax) {
+      block_solve<T>(s_f + (fo - f0), m, s_r + (ca - r0), 1);
+      for (int i = 0; i < m; i++) s_mine[ca - r0 + i] = 1;
+    }
+    __syncthreads();
+    for (int i = t; i < nr; i += kBlock)
+      if (s_mine[i]) {
+        const T v = s_r[i];
+        d[r0 + i] = v;
+        x[r0 + i] += v;
+      }
+    return;
+  }
+  // the staging arrays are free here: the factor array becomes one kBlockMax slice per thread
+  static_assert(kBlkFac >= kBlockMax * kBlock, "per-thread slices");
+  if (q >= qe || m == 0 || m > kBlockMax) return;  // empty, or left to k_fine_subst_big
+  T *v = s_f + t;
+  for (int i = 0; i < m; i++) v[i * kBlock] = src[ca + i];
+  block_solve<T>(fac + fo, m, v, kBlock);
+  for (int i = 0; i < m; i++) {
+    const T di = v[i * kBlock];
+    d[ca + i] = di;
+    x[ca + i] += di;
+  }
+}
+
 // The same substitution for the big cells of one color, one wavefront-sized workgroup per cell (barriers between
 // levels are then nearly free): rows are taken level by level of the cell's dependency schedule (the rows of a level
 // use only values of earlier levels), with a barrier between levels;
@@ -881,6 +974,7 @@ template <> struct P<double> {
   static const double *sval(const FineLevel &F) { return F.s_val64; }
   static const double *diag(const FineLevel &F) { return F.diag64; }
   static const double *icv(const FineLevel &F) { return F.ic_val64; }
+  static const double *bfac(const FineLevel &F) { return F.bfac64; }
   static constexpr int kResid = KK_RESID_FINE64, kGs = KK_GS_FINE64;
 };
 template <> struct P<float> {
@@ -890,6 +984,7 @@ template <> struct P<float> {
   static const float *sval(const FineLevel &F) { return F.s_val32; }
   static const float *diag(const FineLevel &F) { return F.diag32; }
   static const float *icv(const FineLevel &F) { return F.ic_val32; }
+  static const float *bfac(const FineLevel &F) { return F.bfac32; }
   static constexpr int kResid = KK_RESID_FINE32, kGs = KK_GS_FINE32;
 };
 
@@ -2047,7 +2142,8 @@ __global__ void __launch_bounds__(kEngThreads) k_solve_wg(const WgSys<T> *system
 // deepest ones from LDS.
 amg_status plan_wg(amg_hierarchy *h) {
   h->wg_nops[0] = h->wg_nops[1] = 0;
-  if (h->nlev < 3 || h->n > kWgMaxRows) return AMG_OK;
+  // the whole-solve workgroup carries the substitution smoother only
+  if (h->nlev < 3 || h->n > kWgMaxRows || h->opt.smoother) return AMG_OK;
   if (h->lds_max == 0) {
     int lds = 0;
     QA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
@@ -2188,7 +2284,9 @@ static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd
   if (from_f) src = f;
   else fine_resid<T>(h, f, u, d, c, c + 1, P<T>::kGs);
   const int64_t q0 = c * nL4, q1 = (c + 1) * nL4;
-  if (fwd)
+  if (h->opt.smoother)
+    k_fine_block<T><<<nblk(nL4), kBlock, 0, h->stream>>>(F.crow, F.boff, P<T>::bfac(F), src, d, u, q0, q1);
+  else if (fwd)
     k_fine_subst<T, true><<<nblk(nL4), kBlock, 0, h->stream>>>(F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F),
                                                                 P<T>::diag(F), src, d, u, q0, q1);
   else

@@ -42,8 +42,8 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_host_only_entry_points(lib):
     o = amg.default_options()
-    assert (o.precision, o.coarse_max, o.inner_iters, o.sweeps, o.outer_mmax, o.max_iters, o.engine, o.batch) == \
-        (0, 64, 2, 1, 1, 1000, 1, 1)
+    assert (o.precision, o.coarse_max, o.inner_iters, o.sweeps, o.outer_mmax, o.max_iters, o.engine, o.batch,
+            o.smoother) == (0, 64, 2, 1, 1, 1000, 1, 1, 0)
     assert lib.amg_status_string(0) == b"AMG_OK"
     assert lib.amg_status_string(4) == b"AMG_ERR_NOT_SPD"
     small = amg.estimate_bytes(3969, 27281)

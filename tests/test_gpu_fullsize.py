@@ -1,5 +1,5 @@
-"""Parity at the benchmark configurations' full sizes, in the launch configuration bench.py times (default options,
-engine on).
+"""Parity at the benchmark configurations' full sizes, in the launch configuration bench.py times (engine on, the
+exact-block fine smoother bench.py uses by default; the 1M-unknown system also with the substitution smoother).
 
 - quasi-uniform 1024x1024 jittered Delaunay (1,044,484 unknowns) and the 16x16 kappa checkerboard on 1416x1416
   (1,999,396 unknowns): whole hierarchy bit-exact, FP64 solve vs the oracle's solve (iterations +-1, relative error
@@ -59,11 +59,13 @@ def assert_hierarchy_equal(g, o):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("name", ["c2", "c4"])
-def test_fullsize_solve_parity(name):
+@pytest.mark.parametrize("name,smoother", [("c2", 1), ("c2", 0), ("c4", 1)])
+def test_fullsize_solve_parity(name, smoother):
     prob = problem(name)
-    g = hier(prob)
+    g = hier(prob, smoother=smoother)
     o = oracle.setup_problem(prob)
+    if smoother:
+        o.set_block_smoother(True)
     assert_hierarchy_equal(g, o)
     log(f"{name}: hierarchy bit-exact over {g.num_levels} levels")
     t = time.time()
@@ -81,7 +83,8 @@ def test_fullsize_solve_parity(name):
     A = H.csr_of(prob)
     assert im["status"] == 0 and np.linalg.norm(A @ x_m - prob.b) <= 1e-8 * np.linalg.norm(prob.b) * (1 + 1e-6)
     err_m = np.linalg.norm(x_m - x_o) / np.linalg.norm(x_o)
-    log(f"{name}: fp64 iters {ig['iters']} err {err:.2e}; fp32-precond iters {im['iters']} relres {im['relres']:.2e} "
+    log(f"{name} smoother {smoother}: fp64 iters {ig['iters']} err {err:.2e}; fp32-precond iters {im['iters']} "
+        f"relres {im['relres']:.2e} "
         f"err vs fp64 oracle {err_m:.2e}")
     assert err_m <= 1e-6
     g.close()
@@ -92,8 +95,9 @@ def test_fullsize_solve_parity(name):
 def test_fullsize_graded():
     prob = problem("c3")
     assert 4 ** 10 < prob.n <= 4 ** 11
-    g = hier(prob)
+    g = hier(prob, smoother=1)
     o = oracle.setup_problem(prob)
+    o.set_block_smoother(True)
     assert_hierarchy_equal(g, o)
     log(f"c3: hierarchy bit-exact over {g.num_levels} levels, level-L overflow {g.level_info(1)['ovf_nnz']}")
     r = np.random.default_rng(5).standard_normal(prob.n)

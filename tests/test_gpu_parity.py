@@ -99,6 +99,40 @@ def test_level_spmv_and_smoother(name):
     g.close()
 
 
+@pytest.mark.parametrize("name", ["jittered130", "jittered177_kappa", "graded20k", "longrange6k", "disk130"])
+def test_block_smoother_parity(name):
+    """The exact-block fine smoother (smoother=1): sweeps in both directions, the preconditioner and both solve
+    precisions against the oracle's exact-block reading (graded20k also has cells above 32 unknowns, which keep the
+    substitution on both sides)."""
+    prob = problem(name)
+    g = gpu_hier(prob, smoother=1)
+    o = oracle.setup_problem(prob)
+    o.set_block_smoother(True)
+    rng = np.random.default_rng(7)
+    x, f = rng.standard_normal(prob.n), rng.standard_normal(prob.n)
+    for fwd in (True, False):
+        s_o = o.smooth(0, f, x, fwd)
+        s_g = g.smooth(0, T(f), T(x), fwd).cpu().numpy()
+        np.testing.assert_allclose(s_g, s_o, rtol=0, atol=1e-11 * np.abs(s_o).max(), err_msg=f"fwd={fwd}")
+        s32 = g.smooth(0, T(f), T(x), fwd, precision=1).cpu().numpy()
+        np.testing.assert_allclose(s32, s_o, rtol=0, atol=1e-4 * np.abs(s_o).max(), err_msg=f"fp32 fwd={fwd}")
+    r = rng.standard_normal(prob.n)
+    z_o = o.apply_precond(r)
+    z_g = g.apply_precond(T(r)).cpu().numpy()
+    assert np.linalg.norm(z_g - z_o) <= 1e-10 * np.linalg.norm(z_o)
+    x_o, io = o.solve(prob.b, tol=1e-8)
+    A = H.csr_of(prob)
+    for prec in (0, 1):
+        g.set_precision(prec)
+        x_g, ig = g.solve(T(prob.b), tol=1e-8)
+        x_g = x_g.cpu().numpy()
+        assert ig["status"] == 0 and ig["relres"] <= 1e-8
+        assert np.linalg.norm(A @ x_g - prob.b) <= 1e-8 * np.linalg.norm(prob.b) * (1 + 1e-6)
+        assert abs(ig["iters"] - io["iters"]) <= 1, (prec, ig, io)
+        assert np.linalg.norm(x_g - x_o) <= 1e-6 * np.linalg.norm(x_o)
+    g.close()
+
+
 @pytest.mark.parametrize("name", list(PROBLEMS))
 def test_preconditioner_parity(name):
     prob = problem(name)
