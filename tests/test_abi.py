@@ -50,6 +50,9 @@ def test_host_only_entry_points(lib):
     big = amg.estimate_bytes(1_044_484, 7_300_000)
     assert 0 < small < big
     assert big < 2 * 1024 ** 3
+    # the exact-block smoother's factors (at most 16.5 values of 12 bytes per unknown) raise the bound
+    blk = amg.estimate_bytes(1_044_484, 7_300_000, smoother=1)
+    assert big < blk <= big + 1_044_484 * 33 * 6 + 4 ** 9 * 16 + (64 << 20)
     # invalid arguments are rejected before any device work
     h = C.c_void_p()
     assert lib.amg_setup(0, None, None, None, None, 0, None, C.byref(h)) == amg.INVALID

@@ -250,6 +250,9 @@ def test_error_paths():
     with pytest.raises(amg.AMGError) as e:
         gpu_hier(neg)
     assert e.value.code == amg.NOT_SPD
+    with pytest.raises(amg.AMGError) as e:
+        gpu_hier(prob, smoother=2)
+    assert e.value.code == amg.INVALID
     badcol = mg.jittered_problem(20)
     badcol.col = badcol.col.copy()
     badcol.col[10] = badcol.n + 5
@@ -262,21 +265,23 @@ def test_error_paths():
     g.close()
 
 
+@pytest.mark.parametrize("smoother", [0, 1])
 @pytest.mark.parametrize("name", list(PROBLEMS))
-def test_footprint_within_estimate(name):
+def test_footprint_within_estimate(name, smoother):
     """amg_estimate_bytes (used for admission by HBM footprint) bounds what a hierarchy actually holds."""
     prob = problem(name)
-    g = gpu_hier(prob)
-    est = _amg().estimate_bytes(prob.n, prob.nnz)
-    print(f"[gpu] {name}: {g.bytes()} bytes held, estimate {est}", flush=True)
+    g = gpu_hier(prob, smoother=smoother)
+    est = _amg().estimate_bytes(prob.n, prob.nnz, smoother=smoother)
+    print(f"[gpu] {name} smoother {smoother}: {g.bytes()} bytes held, estimate {est}", flush=True)
     assert 0 < g.bytes() <= est
     g.close()
 
 
-def test_footprint_within_estimate_large():
+@pytest.mark.parametrize("smoother", [0, 1])
+def test_footprint_within_estimate_large(smoother):
     prob = mg.jittered_problem(700, fast=True)
-    g = gpu_hier(prob)
-    est = _amg().estimate_bytes(prob.n, prob.nnz)
+    g = gpu_hier(prob, smoother=smoother)
+    est = _amg().estimate_bytes(prob.n, prob.nnz, smoother=smoother)
     print(f"[gpu] jittered700: {g.bytes()} bytes held ({g.bytes() / prob.n:.0f} per unknown), estimate {est}",
           flush=True)
     assert 0 < g.bytes() <= est
