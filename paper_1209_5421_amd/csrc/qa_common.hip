@@ -31,7 +31,55 @@ static hipMemPool_t pool_for(int device) {
   return pools[device];
 }
 
-static void *raw_alloc(amg_hierarchy *h, size_t bytes) {
+// Allocations of freed hierarchies are kept per device (up to kCacheCap bytes) and handed to the next allocation of
+// exactly the same size: a request stream re-creates hierarchies of the sizes it has seen (repeated meshes, the
+// benchmark's steps), and each stream-ordered free and allocation costs tens of microseconds of driver time. A block
+// enters the cache only after its hierarchy's stream has drained (release), so any stream may reuse it at once.
+constexpr size_t kCacheCap = static_cast<size_t>(32) << 30;
+struct CachedBlock {
+  void *p;
+  size_t size;
+};
+static std::vector<CachedBlock> g_cache[64];
+static size_t g_cache_bytes[64];
+
+static void *cached_block(int device, size_t bytes) {
+  if (device < 0 || device >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  std::vector<CachedBlock> &c = g_cache[device];
+  for (size_t i = c.size(); i-- > 0;)
+    if (c[i].size == bytes) {
+      void *p = c[i].p;
+      c.erase(c.begin() + static_cast<std::ptrdiff_t>(i));
+      g_cache_bytes[device] -= bytes;
+      return p;
+    }
+  return nullptr;
+}
+
+static bool cache_block(int device, void *p, size_t bytes) {
+  if (device < 0 || device >= 64) return false;
+  std::lock_guard<std::mutex> lock(g_pool_mu);
+  if (g_cache_bytes[device] + bytes > kCacheCap) return false;
+  g_cache[device].push_back(CachedBlock{p, bytes});
+  g_cache_bytes[device] += bytes;
+  return true;
+}
+
+// return every cached block of a device to the driver (an allocation failed: the cache must not be what starves it)
+static void flush_cache(int device) {
+  std::vector<CachedBlock> blocks;
+  {
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    blocks.swap(g_cache[device]);
+    g_cache_bytes[device] = 0;
+  }
+  const bool pooled = pool_for(device) != nullptr;  // then every block came from the device's pool
+  for (const CachedBlock &b : blocks) (void)(pooled ? hipFreeAsync(b.p, nullptr) : hipFree(b.p));
+  if (pooled && !blocks.empty()) (void)hipStreamSynchronize(nullptr);
+}
+
+static void *fresh_block(amg_hierarchy *h, size_t bytes) {
   void *p = nullptr;
   hipMemPool_t pool = pool_for(h->device);
   if (pool) {
@@ -39,7 +87,20 @@ static void *raw_alloc(amg_hierarchy *h, size_t bytes) {
   } else if (hipMalloc(&p, bytes) != hipSuccess) {
     return nullptr;
   }
+  return p;
+}
+
+static void *raw_alloc(amg_hierarchy *h, size_t bytes) {
+  void *p = cached_block(h->device, bytes);
+  if (!p) p = fresh_block(h, bytes);
+  if (!p && h->device >= 0 && h->device < 64) {
+    (void)hipGetLastError();  // clear the failed allocation's error before retrying
+    flush_cache(h->device);
+    p = fresh_block(h, bytes);
+  }
+  if (!p) return nullptr;
   h->allocs.push_back(p);
+  h->alloc_sizes.push_back(bytes);
   h->bytes += bytes;
   return p;
 }
@@ -65,9 +126,16 @@ void *dalloc(amg_hierarchy *h, size_t bytes) {
 
 amg_status release(amg_hierarchy *h) {
   const bool pooled = pool_for(h->device) != nullptr;
-  for (void *p : h->allocs) (void)(pooled ? hipFreeAsync(p, h->stream) : hipFree(p));
-  if (pooled) (void)hipStreamSynchronize(h->stream);
+  (void)hipStreamSynchronize(h->stream);  // the hierarchy's work has drained: its blocks are idle
+  bool freed = false;
+  for (size_t i = 0; i < h->allocs.size(); i++) {
+    if (cache_block(h->device, h->allocs[i], h->alloc_sizes[i])) continue;
+    (void)(pooled ? hipFreeAsync(h->allocs[i], h->stream) : hipFree(h->allocs[i]));
+    freed = true;
+  }
+  if (pooled && freed) (void)hipStreamSynchronize(h->stream);
   h->allocs.clear();
+  h->alloc_sizes.clear();
   h->chunks.clear();
   if (h->host_scal) return_pinned_scalars(h->host_scal);
   h->host_scal = nullptr;

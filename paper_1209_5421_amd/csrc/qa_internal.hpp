@@ -214,6 +214,7 @@ struct amg_hierarchy {
   double *host_scal = nullptr;         // pinned mirror for convergence checks
   int *dflag = nullptr;                // device error flags
   std::vector<void *> allocs;           // device chunks (freed by amg_free)
+  std::vector<size_t> alloc_sizes;      // their sizes
   size_t bytes = 0;                     // device bytes held (chunks, including unused tails)
   std::vector<qa::Chunk> chunks;        // shared chunks that small arrays are carved from
   size_t chunk_unit = 8u << 20;         // size of a shared chunk (set from the size estimate at setup)
