@@ -205,6 +205,33 @@ def test_engine_matches_per_step_launches(name, precision):
     gb.close()
 
 
+@pytest.mark.parametrize("sweeps,inner", [(2, 2), (1, 1), (3, 1)])
+@pytest.mark.parametrize("engine", [1, 0])
+@pytest.mark.parametrize("name", ["jittered130", "jittered177_kappa"])
+def test_cycle_options_parity(name, engine, sweeps, inner):
+    """Non-default cycle options against the oracle with the same options: several smoothing sweeps (the folds of
+    the first and last relaxation then apply to one sweep only) and one inner step of Algorithm 2.1 (nothing
+    folded, no deferred update); engine on (small levels in the persistent workgroup) and off (every level per
+    step)."""
+    prob = problem(name)
+    g = gpu_hier(prob, engine=engine, sweeps=sweeps, inner_iters=inner)
+    o = oracle.setup_problem(prob, sweeps=sweeps, inner_iters=inner)
+    r = np.random.default_rng(11).standard_normal(prob.n)
+    z_o = o.apply_precond(r)
+    z_g = g.apply_precond(T(r)).cpu().numpy()
+    assert np.linalg.norm(z_g - z_o) <= 1e-10 * np.linalg.norm(z_o)
+    x_o, io = o.solve(prob.b, tol=1e-8)
+    A = H.csr_of(prob)
+    for prec in (0, 1):
+        g.set_precision(prec)
+        x_g, ig = g.solve(T(prob.b), tol=1e-8)
+        x_g = x_g.cpu().numpy()
+        assert ig["status"] == 0 and np.linalg.norm(A @ x_g - prob.b) <= 1e-8 * np.linalg.norm(prob.b) * (1 + 1e-6)
+        assert abs(ig["iters"] - io["iters"]) <= 1, (prec, ig, io)
+        assert np.linalg.norm(x_g - x_o) <= 1e-6 * np.linalg.norm(x_o)
+    g.close()
+
+
 def test_single_level_direct():
     prob = mg.jittered_problem(9)  # 49 unknowns <= 64
     g = gpu_hier(prob)
