@@ -243,6 +243,30 @@ def test_single_level_direct():
     g.close()
 
 
+def test_repeated_setup_reuses_memory():
+    """Freed hierarchies leave their blocks for later ones of the same size: a run of setup / solve / free cycles
+    on one system holds the device memory of one hierarchy (plus the cache), not one per cycle, and every cycle
+    gives the same solution."""
+    prob = problem("jittered177_kappa")
+    b = T(prob.b)
+    xs, used = [], []
+    for cycle in range(6):
+        g = gpu_hier(prob, smoother=cycle % 2)
+        x, info = g.solve(b, tol=1e-8)
+        assert info["status"] == 0
+        xs.append((cycle % 2, x.cpu().numpy()))
+        g.close()
+        torch.cuda.synchronize()
+        free, total = torch.cuda.mem_get_info()
+        used.append(total - free)
+    # after the first cycle of each smoother, device use stays flat (within 1 MiB of slack)
+    assert max(used[2:]) - used[1] <= 1 << 20, used
+    for sm in (0, 1):
+        same = [x for s_, x in xs if s_ == sm]
+        for x in same[1:]:
+            np.testing.assert_array_equal(x, same[0])
+
+
 def test_zero_rhs_and_determinism():
     prob = problem("jittered130")
     g = gpu_hier(prob)
