@@ -95,7 +95,10 @@ amg_status amg_setup(int64_t n, const double *coords, const int64_t *row_ptr, co
  * AMG_ERR_DEVICE. */
 amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_info *info);
 
-/* Release every resource of h (NULL is allowed). Synchronises the hierarchy's stream first. */
+/* Release every resource of h (NULL is allowed). Synchronises the hierarchy's stream first. The device blocks go to
+ * a per-device cache owned by the library (at most 32 GiB per device, kept until the process ends) and serve later
+ * hierarchies' allocations of exactly the same sizes; blocks beyond the cap return to the driver, and an allocation
+ * that fails returns the whole cache to the driver before it tries again. */
 void amg_free(amg_hierarchy *h);
 
 /* Change the solve precision of an existing hierarchy (0 = FP64, 1 = FP32 preconditioner / FP64 outer). */
