@@ -87,6 +87,20 @@ void amg_default_options(amg_options *opt);
 amg_status amg_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
                      const double *vals, int64_t nnz, const amg_options *opt, amg_hierarchy **out);
 
+/* Replace the matrix values of h with those of a new matrix on the same sparsity pattern and the same points (a
+ * time step with changed coefficients, Example 2 of Section 5): the aggregates of Section 3 depend on the points and
+ * the pattern only, so only the numeric part of setup runs again (the Galerkin sums of eq. 11 on every level, the
+ * smoother's data, the coarsest factor). The result is bit-identical to amg_setup on the new values with h's
+ * points and options. row_ptr, col_idx, vals: device CSR of n rows with exactly the row lengths and, row by row, the
+ * column order given to setup; nnz must equal setup's. Borrowed for the call. Blocks until done; later solves report
+ * its wall time as setup_ms. Errors, with h unchanged: AMG_ERR_INVALID (h NULL, nnz or the pattern differs, row_ptr
+ * not monotone, column out of range), AMG_ERR_NOT_SPD (a diagonal entry <= 0). Errors after the values began to
+ * change (AMG_ERR_NOT_SPD from a failed cell or coarsest factor, AMG_ERR_NOMEM, AMG_ERR_DEVICE) leave h holding
+ * partial values: solves on it return AMG_ERR_INVALID until an update succeeds. Temporary device memory (at most
+ * the coarsest level's dense matrix and one count per level-L cell) is returned before the call ends. */
+amg_status amg_update_values(amg_hierarchy *h, const int64_t *row_ptr, const int32_t *col_idx, const double *vals,
+                             int64_t nnz);
+
 /* Solve A x = b with the outer flexible CG preconditioned by the nonlinear AMLI-cycle (Algorithms 2.1 and 2.2),
  * from x = 0, until ||r|| <= tol ||b|| holds for the recurrence residual and for the true FP64 residual (the
  * iteration restarts from the true residual when only the former holds). b, x: device, n entries; x is output

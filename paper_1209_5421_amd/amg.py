@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libquadamg.so")
 OK, INVALID, NOMEM, DEVICE, NOT_SPD, BREAKDOWN, NOCONV = range(7)
 STATUS = {0: "AMG_OK", 1: "AMG_ERR_INVALID", 2: "AMG_ERR_NOMEM", 3: "AMG_ERR_DEVICE", 4: "AMG_ERR_NOT_SPD",
           5: "AMG_ERR_BREAKDOWN", 6: "AMG_ERR_NOCONV"}
-EXPORTED = ["amg_default_options", "amg_setup", "amg_solve", "amg_free", "amg_set_precision", "amg_set_stream",
+EXPORTED = ["amg_default_options", "amg_setup", "amg_update_values", "amg_solve", "amg_free", "amg_set_precision", "amg_set_stream",
             "amg_solve_batch", "amg_estimate_bytes", "amg_hierarchy_bytes", "amg_num_levels", "amg_level_info",
             "amg_export_level", "amg_export_level_f32", "amg_apply_precond", "amg_level_smooth", "amg_level_spmv",
             "amg_kernel_timing_enable", "amg_kernel_timing_read", "amg_engine_info", "amg_status_string"]
@@ -58,6 +58,7 @@ def load(path: str = LIB_PATH):
     L.amg_default_options.argtypes = [C.POINTER(Options)]
     L.amg_default_options.restype = None
     L.amg_setup.argtypes = [i64, p, p, p, p, i64, C.POINTER(Options), C.POINTER(p)]
+    L.amg_update_values.argtypes = [p, p, p, p, i64]
     L.amg_solve.argtypes = [p, p, p, d, C.POINTER(Info)]
     L.amg_free.argtypes = [p]
     L.amg_free.restype = None
@@ -177,6 +178,22 @@ class Hierarchy:
             self.close()
         except Exception:
             pass
+
+    def update_values(self, row_ptr, col, val):
+        """New matrix values on the pattern given to setup (same rows, same column order): amg_update_values."""
+        import torch
+        for t, dt in ((row_ptr, torch.int64), (col, torch.int32), (val, torch.float64)):
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+                raise TypeError("inputs must be contiguous CUDA tensors: row_ptr i64, col i32, val f64")
+        with torch.cuda.device(self.device):
+            _check(load().amg_update_values(self._h, _ptr(row_ptr), _ptr(col), _ptr(val), int(col.numel())),
+                   "amg_update_values")
+
+    def update_problem(self, prob):
+        """update_values from a host problem of the same mesh (meshgen.Problem)."""
+        import torch
+        t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=self.device)
+        self.update_values(t(prob.row_ptr, torch.int64), t(prob.col, torch.int32), t(prob.val, torch.float64))
 
     # -- solve --------------------------------------------------------------------------------------------------
     def set_precision(self, precision: int):

@@ -143,6 +143,29 @@ amg_status release(amg_hierarchy *h) {
   return AMG_OK;
 }
 
+ArenaMark arena_mark(const amg_hierarchy *h) {
+  ArenaMark m;
+  m.allocs = h->allocs.size();
+  m.bytes = h->bytes;
+  for (const Chunk &c : h->chunks) m.used.push_back(c.used);
+  return m;
+}
+
+void arena_rollback(amg_hierarchy *h, const ArenaMark &m) {
+  (void)hipStreamSynchronize(h->stream);  // the temporaries' last readers have finished
+  const bool pooled = pool_for(h->device) != nullptr;
+  for (size_t i = m.allocs; i < h->allocs.size(); i++) {
+    if (cache_block(h->device, h->allocs[i], h->alloc_sizes[i])) continue;
+    (void)(pooled ? hipFreeAsync(h->allocs[i], h->stream) : hipFree(h->allocs[i]));
+  }
+  if (pooled) (void)hipStreamSynchronize(h->stream);
+  h->allocs.resize(m.allocs);
+  h->alloc_sizes.resize(m.allocs);
+  h->bytes = m.bytes;
+  h->chunks.resize(m.used.size());  // chunks opened after the mark were among the blocks just released
+  for (size_t c = 0; c < m.used.size(); c++) h->chunks[c].used = m.used[c];
+}
+
 // Timing events are kept in a process-wide pool per device: a hierarchy borrows a block while kernel timing is on
 // and returns it when freed, so a stream of short-lived timed hierarchies creates events only once.
 static std::vector<hipEvent_t> g_free_events[64];

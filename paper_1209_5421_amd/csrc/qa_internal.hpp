@@ -164,6 +164,7 @@ struct FineLevel {
   int64_t *boff = nullptr;                      // 4^L + 1
   double *bfac64 = nullptr;
   float *bfac32 = nullptr;
+  int64_t bfac_n = 0;                           // packed factor values in all (boff[4^L])
 };
 
 template <class T>
@@ -219,6 +220,7 @@ struct amg_hierarchy {
   std::vector<qa::Chunk> chunks;        // shared chunks that small arrays are carved from
   size_t chunk_unit = 8u << 20;         // size of a shared chunk (set from the size estimate at setup)
   double setup_ms = 0.0;
+  int stale = 0;                        // a values update failed after it began to overwrite: solves are refused
   qa::Timing timing;
   // persistent small-level engine: top level index per precision (0 = FP64, 1 = FP32), -1 = not used
   int engine_top[2] = {-1, -1};
@@ -258,6 +260,15 @@ T *dalloc_n(amg_hierarchy *h, int64_t count) {
 amg_status scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s, amg_hierarchy *h);
 amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, amg_hierarchy *h);
 amg_status release(amg_hierarchy *h);
+// the allocation state of a hierarchy, and the return to it: arrays allocated after the mark go back to the
+// chunks' free tails or to the block cache (the stream is synchronised first)
+struct ArenaMark {
+  size_t allocs = 0;
+  size_t bytes = 0;
+  std::vector<size_t> used;
+};
+ArenaMark arena_mark(const amg_hierarchy *h);
+void arena_rollback(amg_hierarchy *h, const ArenaMark &m);
 amg_status borrow_events(int device, size_t count, std::vector<hipEvent_t> &out);
 void return_events(int device, std::vector<hipEvent_t> &ev);
 amg_status borrow_pinned_scalars(double **out);

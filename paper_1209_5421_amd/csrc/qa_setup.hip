@@ -57,6 +57,37 @@ __global__ void __launch_bounds__(kBlock) k_validate(int64_t n, int64_t nnz, con
   if (f) atomicOr(flag, f);
 }
 
+// A values update's input against the stored pattern: row i of the new CSR must hold, in the same order, the
+// entries that setup placed at permuted row iperm[i] (k_permute_csr keeps each row's entry order). Also the checks
+// of k_validate that do not involve coordinates, and a positive diagonal of the new values.
+__global__ void __launch_bounds__(kBlock) k_same_pattern(int64_t n, int64_t nnz, const int64_t *__restrict__ rp_in,
+                                                          const int32_t *__restrict__ ci_in,
+                                                          const double *__restrict__ va_in,
+                                                          const int32_t *__restrict__ iperm,
+                                                          const int64_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ ci, int *flag) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int f = 0;
+  const int64_t r0 = rp_in[i], r1 = rp_in[i + 1];
+  if (i == 0 && r0 != 0) f |= F_INVALID;
+  if (i == n - 1 && r1 != nnz) f |= F_INVALID;
+  if (r1 < r0 || r0 < 0 || r1 > nnz) f |= F_INVALID;
+  if (!f) {
+    const int64_t p = iperm[i];
+    const int64_t o0 = rp[p];
+    if (rp[p + 1] - o0 != r1 - r0) f |= F_INVALID;
+    double dg = 0.0;
+    for (int64_t e = r0; e < r1 && !f; e++) {
+      const int32_t c = ci_in[e];
+      if (c < 0 || c >= n || iperm[c] != ci[o0 + (e - r0)]) f |= F_INVALID;
+      else if (c == i) dg += va_in[e];
+    }
+    if (!f && !(dg > 0.0)) f |= F_NOT_SPD;
+  }
+  if (f) atomicOr(flag, f);
+}
+
 __global__ void __launch_bounds__(kBlock) k_bbox_partial(int64_t n, const double *__restrict__ coords,
                                                           double *__restrict__ part) {
   double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY;
@@ -763,6 +794,8 @@ static amg_status read_flag(amg_hierarchy *h, int &f) {
   return AMG_OK;
 }
 
+static amg_status sell_values(amg_hierarchy *h);
+
 static amg_status build_sell(amg_hierarchy *h) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
@@ -794,6 +827,15 @@ static amg_status build_sell(amg_hierarchy *h) {
   F.s_val64 = dalloc_n<double>(h, F.sell_entries);
   F.s_val32 = dalloc_n<float>(h, F.sell_entries);
   if (!F.s_col || !F.s_val64 || !F.s_val32) return AMG_ERR_NOMEM;
+  return sell_values(h);
+}
+
+// the sliced ELL's entries (columns and values, FP64 and FP32) and the FP32 diagonal from the permuted CSR
+static amg_status sell_values(amg_hierarchy *h) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  Regions R;
+  for (int c = 0; c < 5; c++) { R.row[c] = F.color_row[c]; R.slice[c] = F.color_slice[c]; }
   k_fill_sell<<<nblk(F.n), kBlock, 0, s>>>(R, F.n, F.rp, F.ci, F.va, F.diag64, F.slice_ptr, F.s_row, F.s_col,
                                             F.s_val64);
   QA_LAUNCH_CHECK();
@@ -807,7 +849,7 @@ static amg_status build_sell(amg_hierarchy *h) {
 static amg_status build_coarsest_inverse(amg_hierarchy *h, const double *dense_src_filled, int64_t nc) {
   hipStream_t s = h->stream;
   double *y = dalloc_n<double>(h, nc * nc);
-  h->ainv = dalloc_n<double>(h, nc * nc);
+  if (!h->ainv) h->ainv = dalloc_n<double>(h, nc * nc);  // kept by a values update
   if (!y || !h->ainv) return AMG_ERR_NOMEM;
   k_chol_inverse<<<1, kCholThreads, 0, s>>>(static_cast<int>(nc), const_cast<double *>(dense_src_filled), y, h->ainv,
                                        h->dflag);
@@ -931,6 +973,112 @@ __global__ void __launch_bounds__(kBlock) k_block_factor(int64_t nL, const int32
   }
 }
 
+// in-cell couplings' values (FP64 and FP32) from the permuted CSR
+static amg_status ic_values(amg_hierarchy *h) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  k_ic_fill<<<nblk(F.n), kBlock, 0, s>>>(F.n, F.rp, F.ci, F.va, F.agg_q, F.ic_ptr, F.ic_col, F.ic_val64);
+  QA_LAUNCH_CHECK();
+  if (F.ic_nnz) {
+    k_convert<double, float><<<nblk(F.ic_nnz), kBlock, 0, s>>>(F.ic_nnz, F.ic_val64, F.ic_val32);
+    QA_LAUNCH_CHECK();
+  }
+  return AMG_OK;
+}
+
+// the cells' packed Cholesky factors (FP64, then rounded to FP32) into the arrays sized at setup
+static amg_status block_values(amg_hierarchy *h) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
+  QA_HIP(hipMemsetAsync(F.bfac64, 0, sizeof(double) * std::max<int64_t>(F.bfac_n, 1), s));
+  k_block_factor<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, F.ic_ptr, F.ic_col, F.ic_val64, F.diag64, F.boff, F.bfac64,
+                                             h->dflag);
+  QA_LAUNCH_CHECK();
+  if (F.bfac_n > 0) {
+    k_convert<double, float><<<nblk(F.bfac_n), kBlock, 0, s>>>(F.bfac_n, F.bfac64, F.bfac32);
+    QA_LAUNCH_CHECK();
+  }
+  return AMG_OK;
+}
+
+// Galerkin operator of hierarchy level l (eq. 11 from the fine level, restriction of level l-1 below it), FP64 and
+// FP32. fresh: allocate the level and size its overflow list; otherwise refill the arrays in place (a values update
+// on the same pattern, whose overflow positions and colour flags are unchanged).
+static amg_status level_values(amg_hierarchy *h, int l, bool fresh) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  const int L = h->L;
+  QuadLevel &Q = h->lev[l];
+  if (fresh) {
+    Q.k = L - (l - 1);
+    Q.n = static_cast<int64_t>(1) << (2 * Q.k);
+    Q.ax64 = dalloc_n<double>(h, 9 * Q.n);
+    Q.ax32 = dalloc_n<float>(h, 9 * Q.n);
+    Q.empty = dalloc_n<uint8_t>(h, Q.n);
+    Q.optr = dalloc_n<int32_t>(h, Q.n + 1);
+    if (!Q.ax64 || !Q.ax32 || !Q.empty || !Q.optr) return AMG_ERR_NOMEM;
+  }
+  int32_t *ocnt = dalloc_n<int32_t>(h, Q.n);
+  if (!ocnt) return AMG_ERR_NOMEM;
+  CoarseSrc src{};
+  if (l == 1) {
+    k_galerkin_fine<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.ax64, Q.empty, ocnt,
+                                                  h->dflag);
+  } else {
+    const QuadLevel &P = h->lev[l - 1];
+    src = CoarseSrc{P.k, P.n, P.ax64, P.empty, P.ovf_nnz ? P.optr : nullptr, P.ocol, P.oval64};
+    k_galerkin_coarse<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.ax64, Q.empty, ocnt, h->dflag);
+  }
+  QA_LAUNCH_CHECK();
+  if (fresh) {
+    QA_TRY(scan_exclusive_i32(ocnt, Q.optr, Q.n, s, h));
+    int32_t on = 0;
+    QA_HIP(hipMemcpyAsync(&on, Q.optr + Q.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
+    Q.ovf_nnz = on;
+    if (on) {
+      Q.ocol = dalloc_n<int32_t>(h, on);
+      Q.oval64 = dalloc_n<double>(h, on);
+      Q.oval32 = dalloc_n<float>(h, on);
+      if (!Q.ocol || !Q.oval64 || !Q.oval32) return AMG_ERR_NOMEM;
+    }
+  }
+  if (Q.ovf_nnz) {
+    QA_HIP(hipMemsetAsync(h->dflag + 1, 0, sizeof(int), s));
+    if (l == 1)
+      k_galerkin_fine_ovf<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.optr, Q.ocol,
+                                                        Q.oval64, h->dflag + 1);
+    else
+      k_galerkin_coarse_ovf<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.optr, Q.ocol, Q.oval64, h->dflag + 1);
+    QA_LAUNCH_CHECK();
+    if (fresh) {
+      int sc = 0;
+      QA_HIP(hipMemcpyAsync(&sc, h->dflag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+      QA_HIP(hipStreamSynchronize(s));
+      Q.same_color_ovf = (sc & F_SAMECOLOR) ? 1 : 0;
+    }
+    k_convert<double, float><<<nblk(Q.ovf_nnz), kBlock, 0, s>>>(Q.ovf_nnz, Q.oval64, Q.oval32);
+    QA_LAUNCH_CHECK();
+  }
+  k_convert<double, float><<<nblk(9 * Q.n), kBlock, 0, s>>>(9 * Q.n, Q.ax64, Q.ax32);
+  QA_LAUNCH_CHECK();
+  return AMG_OK;
+}
+
+// the coarsest level densified and inverted through its Cholesky factor
+static amg_status coarsest_values(amg_hierarchy *h) {
+  hipStream_t s = h->stream;
+  const QuadLevel &C = h->lev[h->nlev - 1];
+  double *dense = dalloc_n<double>(h, C.n * C.n);
+  if (!dense) return AMG_ERR_NOMEM;
+  QA_HIP(hipMemsetAsync(dense, 0, sizeof(double) * C.n * C.n, s));
+  k_densify_level<<<nblk(C.n), kBlock, 0, s>>>(C.k, C.n, C.ax64, C.ovf_nnz ? C.optr : nullptr, C.ocol, C.oval64,
+                                               dense);
+  QA_LAUNCH_CHECK();
+  return build_coarsest_inverse(h, dense, C.n);
+}
+
 static amg_status build_block_factors(amg_hierarchy *h) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
@@ -944,18 +1092,11 @@ static amg_status build_block_factors(amg_hierarchy *h) {
   int64_t total = 0;
   QA_HIP(hipMemcpyAsync(&total, F.boff + nL, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   QA_HIP(hipStreamSynchronize(s));
+  F.bfac_n = total;
   F.bfac64 = dalloc_n<double>(h, std::max<int64_t>(total, 1));
   F.bfac32 = dalloc_n<float>(h, std::max<int64_t>(total, 1));
   if (!F.bfac64 || !F.bfac32) return AMG_ERR_NOMEM;
-  QA_HIP(hipMemsetAsync(F.bfac64, 0, sizeof(double) * std::max<int64_t>(total, 1), s));
-  k_block_factor<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, F.ic_ptr, F.ic_col, F.ic_val64, F.diag64, F.boff, F.bfac64,
-                                             h->dflag);
-  QA_LAUNCH_CHECK();
-  if (total > 0) {
-    k_convert<double, float><<<nblk(total), kBlock, 0, s>>>(total, F.bfac64, F.bfac32);
-    QA_LAUNCH_CHECK();
-  }
-  return AMG_OK;
+  return block_values(h);
 }
 
 static amg_status build_big_cells(amg_hierarchy *h) {
@@ -1069,73 +1210,14 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
   F.ic_val64 = dalloc_n<double>(h, F.ic_nnz);
   F.ic_val32 = dalloc_n<float>(h, F.ic_nnz);
   if (!F.ic_col || !F.ic_val64 || !F.ic_val32) return AMG_ERR_NOMEM;
-  k_ic_fill<<<nblk(n), kBlock, 0, s>>>(n, F.rp, F.ci, F.va, F.agg_q, F.ic_ptr, F.ic_col, F.ic_val64);
-  QA_LAUNCH_CHECK();
-  if (F.ic_nnz) {
-    k_convert<double, float><<<nblk(F.ic_nnz), kBlock, 0, s>>>(F.ic_nnz, F.ic_val64, F.ic_val32);
-    QA_LAUNCH_CHECK();
-  }
+  QA_TRY(ic_values(h));
   QA_TRY(build_big_cells(h));
   if (h->opt.smoother) QA_TRY(build_block_factors(h));
 
   // Galerkin operators, level L first, then coarser
   h->lev.assign(h->nlev, QuadLevel{});
-  for (int l = 1; l < h->nlev; l++) {
-    QuadLevel &Q = h->lev[l];
-    Q.k = L - (l - 1);
-    Q.n = static_cast<int64_t>(1) << (2 * Q.k);
-    Q.ax64 = dalloc_n<double>(h, 9 * Q.n);
-    Q.ax32 = dalloc_n<float>(h, 9 * Q.n);
-    Q.empty = dalloc_n<uint8_t>(h, Q.n);
-    int32_t *ocnt = dalloc_n<int32_t>(h, Q.n);
-    Q.optr = dalloc_n<int32_t>(h, Q.n + 1);
-    if (!Q.ax64 || !Q.ax32 || !Q.empty || !ocnt || !Q.optr) return AMG_ERR_NOMEM;
-    CoarseSrc src{};
-    if (l == 1) {
-      k_galerkin_fine<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.ax64, Q.empty, ocnt,
-                                                    h->dflag);
-    } else {
-      const QuadLevel &P = h->lev[l - 1];
-      src = CoarseSrc{P.k, P.n, P.ax64, P.empty, P.ovf_nnz ? P.optr : nullptr, P.ocol, P.oval64};
-      k_galerkin_coarse<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.ax64, Q.empty, ocnt, h->dflag);
-    }
-    QA_LAUNCH_CHECK();
-    QA_TRY(scan_exclusive_i32(ocnt, Q.optr, Q.n, s, h));
-    int32_t on = 0;
-    QA_HIP(hipMemcpyAsync(&on, Q.optr + Q.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
-    Q.ovf_nnz = on;
-    if (on) {
-      Q.ocol = dalloc_n<int32_t>(h, on);
-      Q.oval64 = dalloc_n<double>(h, on);
-      Q.oval32 = dalloc_n<float>(h, on);
-      if (!Q.ocol || !Q.oval64 || !Q.oval32) return AMG_ERR_NOMEM;
-      QA_HIP(hipMemsetAsync(h->dflag + 1, 0, sizeof(int), s));
-      if (l == 1)
-        k_galerkin_fine_ovf<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.optr, Q.ocol,
-                                                          Q.oval64, h->dflag + 1);
-      else
-        k_galerkin_coarse_ovf<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.optr, Q.ocol, Q.oval64, h->dflag + 1);
-      QA_LAUNCH_CHECK();
-      int sc = 0;
-      QA_HIP(hipMemcpyAsync(&sc, h->dflag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-      QA_HIP(hipStreamSynchronize(s));
-      Q.same_color_ovf = (sc & F_SAMECOLOR) ? 1 : 0;
-      k_convert<double, float><<<nblk(on), kBlock, 0, s>>>(on, Q.oval64, Q.oval32);
-      QA_LAUNCH_CHECK();
-    }
-    k_convert<double, float><<<nblk(9 * Q.n), kBlock, 0, s>>>(9 * Q.n, Q.ax64, Q.ax32);
-    QA_LAUNCH_CHECK();
-  }
-  // coarsest
-  const QuadLevel &C = h->lev[h->nlev - 1];
-  double *dense = dalloc_n<double>(h, C.n * C.n);
-  if (!dense) return AMG_ERR_NOMEM;
-  QA_HIP(hipMemsetAsync(dense, 0, sizeof(double) * C.n * C.n, s));
-  k_densify_level<<<nblk(C.n), kBlock, 0, s>>>(C.k, C.n, C.ax64, C.ovf_nnz ? C.optr : nullptr, C.ocol, C.oval64,
-                                               dense);
-  QA_LAUNCH_CHECK();
-  return build_coarsest_inverse(h, dense, C.n);
+  for (int l = 1; l < h->nlev; l++) QA_TRY(level_values(h, l, true));
+  return coarsest_values(h);
 }
 
 static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
@@ -1182,6 +1264,48 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
   QA_TRY(plan_engine(h));
   QA_TRY(plan_wg(h));
   QA_HIP(hipStreamSynchronize(s));
+  return AMG_OK;
+}
+
+// New values on the stored pattern: the numeric half of setup_impl (permuted CSR, sliced ELL, in-cell couplings,
+// cell factors, Galerkin operators, coarsest inverse, B^ matrix), into the hierarchy's own arrays, with the same
+// kernels and hence the same results as a setup from scratch. The aggregation, orderings, layouts and plans depend on
+// the pattern only and are kept. Temporaries are returned before the call ends.
+static amg_status update_impl(amg_hierarchy *h, const int64_t *row_ptr, const int32_t *col_idx, const double *vals) {
+  FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
+  const int64_t n = h->n;
+  QA_HIP(hipMemsetAsync(h->dflag, 0, 4 * sizeof(int), s));
+  k_same_pattern<<<nblk(n), kBlock, 0, s>>>(n, F.nnz, row_ptr, col_idx, vals, F.iperm, F.rp, F.ci, h->dflag);
+  QA_LAUNCH_CHECK();
+  int f = 0;
+  QA_TRY(read_flag(h, f));
+  if (f & F_INVALID) return AMG_ERR_INVALID;
+  if (f & F_NOT_SPD) return AMG_ERR_NOT_SPD;
+  h->stale = 1;  // from here on the stored values change
+  k_permute_csr<<<nblk(8 * n), kBlock, 0, s>>>(n, F.perm, F.iperm, row_ptr, col_idx, vals, F.rp, F.ci, F.va,
+                                               F.diag64);
+  k_row_diag<<<nblk(n), kBlock, 0, s>>>(n, F.rp, F.ci, F.va, F.diag64);
+  QA_LAUNCH_CHECK();
+  QA_TRY(sell_values(h));
+  if (h->nlev == 1) {
+    double *dense = dalloc_n<double>(h, n * n);
+    if (!dense) return AMG_ERR_NOMEM;
+    QA_HIP(hipMemsetAsync(dense, 0, sizeof(double) * n * n, s));
+    k_densify_csr<<<nblk(n), kBlock, 0, s>>>(n, row_ptr, col_idx, vals, dense);
+    QA_LAUNCH_CHECK();
+    QA_TRY(build_coarsest_inverse(h, dense, n));
+  } else {
+    QA_TRY(ic_values(h));
+    if (h->opt.smoother) QA_TRY(block_values(h));
+    for (int l = 1; l < h->nlev; l++) QA_TRY(level_values(h, l, false));
+    QA_TRY(coarsest_values(h));
+  }
+  QA_TRY(read_flag(h, f));
+  if (f & F_NOT_SPD) return AMG_ERR_NOT_SPD;
+  QA_TRY(build_mhat(h));
+  QA_HIP(hipStreamSynchronize(s));
+  h->stale = 0;
   return AMG_OK;
 }
 
@@ -1280,6 +1404,19 @@ extern "C" amg_status amg_setup(int64_t n, const double *coords, const int64_t *
   h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h;
   return AMG_OK;
+}
+
+extern "C" amg_status amg_update_values(amg_hierarchy *h, const int64_t *row_ptr, const int32_t *col_idx,
+                                        const double *vals, int64_t nnz) {
+  if (!h || !row_ptr || !col_idx || !vals || nnz != h->fine.nnz) return AMG_ERR_INVALID;
+  QA_HIP(hipSetDevice(h->device));
+  const auto t0 = std::chrono::steady_clock::now();
+  const ArenaMark mark = arena_mark(h);
+  const amg_status st = update_impl(h, row_ptr, col_idx, vals);
+  arena_rollback(h, mark);
+  if (st == AMG_OK)
+    h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  return st;
 }
 
 // ---------------------------------------------------------------------------------------------------------------

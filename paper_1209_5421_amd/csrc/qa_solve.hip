@@ -1783,8 +1783,9 @@ amg_status build_mhat(amg_hierarchy *h) {
   emit_bhat(ops, EmitCtx{2, h->opt.sweeps, h->opt.inner_iters, 0, same_l.data()}, 0, EV_G, EV_E);
   if (ops.size() > static_cast<size_t>(kEngMaxOps)) return AMG_OK;
   double *ident = dalloc_n<double>(h, n * n);
-  double *m64 = dalloc_n<double>(h, n * n);
-  float *m32 = dalloc_n<float>(h, n * n);
+  // a values update refills the matrices made at setup
+  double *m64 = h->mhat[0] ? static_cast<double *>(h->mhat[0]) : dalloc_n<double>(h, n * n);
+  float *m32 = h->mhat[1] ? static_cast<float *>(h->mhat[1]) : dalloc_n<float>(h, n * n);
   EngOp *d = static_cast<EngOp *>(dalloc(h, sizeof(EngOp) * ops.size()));
   if (!ident || !m64 || !m32 || !d) return AMG_ERR_NOMEM;
   QA_HIP(hipMemcpyAsync(d, ops.data(), sizeof(EngOp) * ops.size(), hipMemcpyHostToDevice, s));
@@ -2599,7 +2600,7 @@ amg_status level_spmv_internal(amg_hierarchy *h, int level, const double *x, dou
 using namespace qa;
 
 extern "C" amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, double tol, amg_info *info) {
-  if (!h || !b || !x || !(tol > 0.0) || !std::isfinite(tol)) return AMG_ERR_INVALID;
+  if (!h || !b || !x || !(tol > 0.0) || !std::isfinite(tol) || h->stale) return AMG_ERR_INVALID;
   QA_HIP(hipSetDevice(h->device));
   const amg_status st = solve_impl(h, b, x, tol, info);
   if (info) info->status = st;
@@ -2607,7 +2608,7 @@ extern "C" amg_status amg_solve(amg_hierarchy *h, const double *b, double *x, do
 }
 
 extern "C" amg_status amg_apply_precond(amg_hierarchy *h, const double *r, double *z, int32_t precision) {
-  if (!h || !r || !z || (precision != 0 && precision != 1)) return AMG_ERR_INVALID;
+  if (!h || !r || !z || (precision != 0 && precision != 1) || h->stale) return AMG_ERR_INVALID;
   QA_HIP(hipSetDevice(h->device));
   const int64_t n = h->n;
   hipStream_t s = h->stream;
@@ -2621,14 +2622,16 @@ extern "C" amg_status amg_apply_precond(amg_hierarchy *h, const double *r, doubl
 
 extern "C" amg_status amg_level_smooth(amg_hierarchy *h, int32_t level, const double *f, double *x, int32_t forward,
                                        int32_t precision) {
-  if (!h || !f || !x || level < 0 || level >= h->nlev - 1 || h->nlev == 1 || (precision != 0 && precision != 1))
+  if (!h || !f || !x || level < 0 || level >= h->nlev - 1 || h->nlev == 1 || (precision != 0 && precision != 1) ||
+      h->stale)
     return AMG_ERR_INVALID;
   QA_HIP(hipSetDevice(h->device));
   return level_smooth_internal(h, level, f, x, forward, precision);
 }
 
 extern "C" amg_status amg_level_spmv(amg_hierarchy *h, int32_t level, const double *x, double *y, int32_t precision) {
-  if (!h || !x || !y || level < 0 || level >= h->nlev || (precision != 0 && precision != 1)) return AMG_ERR_INVALID;
+  if (!h || !x || !y || level < 0 || level >= h->nlev || (precision != 0 && precision != 1) || h->stale)
+    return AMG_ERR_INVALID;
   if (level == 0 && h->nlev == 1 && precision == 1) return AMG_ERR_INVALID;
   QA_HIP(hipSetDevice(h->device));
   return level_spmv_internal(h, level, x, y, precision);
@@ -2702,7 +2705,7 @@ extern "C" amg_status amg_solve_batch(amg_hierarchy *const *hs, const double *co
   if (count == 0) return AMG_OK;
   const auto t0 = std::chrono::steady_clock::now();
   for (int32_t i = 0; i < count; i++) {
-    if (!hs[i] || !b[i] || !x[i] || !(tol[i] > 0.0) || !std::isfinite(tol[i])) return AMG_ERR_INVALID;
+    if (!hs[i] || !b[i] || !x[i] || !(tol[i] > 0.0) || !std::isfinite(tol[i]) || hs[i]->stale) return AMG_ERR_INVALID;
     for (int32_t j = 0; j < i; j++)
       if (hs[j] == hs[i]) return AMG_ERR_INVALID;  // one workspace per hierarchy
     if (hs[i]->device != hs[0]->device) return AMG_ERR_INVALID;
