@@ -9,8 +9,8 @@ lattice jittered by U[-0.3h, 0.3h], Delaunay-triangulated, Dirichlet boundary el
 right-hand side U[-1, 1]. Inputs are resident in HBM before the timed region starts.
 
 Printed: one JSON line. value = unknowns x steps / wall time of the K timed steps (DOF/s of setup + solve). Extra
-fields give solve-only rates on a resident hierarchy for both forms (solves/s, DOF/s, p50/p99 latency), the
-roofline of the dominant kernel (the persistent small-level workgroup: algorithmic flops per launch over its
+fields give solve-only rates on a resident hierarchy for both forms (solves/s, DOF/s, p50/p99 latency), the time of
+a values update on the resident hierarchy followed by a solve (a time step with new coefficients), the roofline of the dominant kernel (the persistent small-level workgroup: algorithmic flops per launch over its
 duration), the same for the HBM-bound fine residual with its counter-measured traffic (roofline_hbm), both from
 HIP-event timing of their launches inside the timed steps (alternate steps time one or the other), and the oracle
 timed on the host (cpu_baseline).
@@ -294,6 +294,30 @@ def main():
                        "dof_per_s": float(prob.n * 1e3 / np.median(lat))}
         log(f"resident {name}: {forms[name]}")
     x_gpu = x.cpu().numpy()
+    # time stepping with changing coefficients: new values on the same pattern (amg_update_values), then a solve;
+    # the values alternate between a_ij sqrt(kappa_i kappa_j) for the smooth field kappa = 1 + sin(2 pi x)
+    # sin(2 pi y) / 2 at the unknowns' points, and A, in the mixed form
+    rows = torch.repeat_interleave(torch.arange(prob.n, device=dev), rp[1:] - rp[:-1])
+    d = torch.sqrt(1.0 + 0.5 * torch.sin(2 * np.pi * coords[:, 0]) * torch.sin(2 * np.pi * coords[:, 1]))
+    va2 = va * (d[rows] * d[ci.long()])
+    del rows
+    h.set_precision(1)
+    upd, upd_solve, upd_iters = [], [], []
+    for k in range(args.repeats):
+        torch.cuda.synchronize()
+        s0 = time.perf_counter()
+        h.update_values(rp, ci, va2 if k % 2 == 0 else va)
+        s1 = time.perf_counter()
+        _, info = h.solve(b, tol=args.tol, x=x)
+        torch.cuda.synchronize()
+        upd.append((s1 - s0) * 1e3)
+        upd_solve.append((time.perf_counter() - s0) * 1e3)
+        upd_iters.append(info["iters"])
+    update = {"values": "alternately a_ij sqrt(kappa_i kappa_j), kappa = 1 + sin(2 pi x) sin(2 pi y) / 2, and A", "update_ms_p50": float(np.median(upd)),
+              "update_ms_p99": float(np.percentile(upd, 99)), "update_and_solve_ms_p50": float(np.median(upd_solve)),
+              "iters": sorted(set(upd_iters))}
+    log(f"values update: {update}")
+    del va2
     h.close()
 
     solve_ms = float(np.median([i["solve_ms"] for i in infos]))
@@ -344,6 +368,7 @@ def main():
                    "iters": infos[-1]["iters"], "relres": infos[-1]["relres"]},
         "step_wall_ms": {k: float(np.median(v)) for k, v in wall.items()},
         "solve_resident": forms,
+        "update_resident": update,
         "engine": engine,
         "err_vs_oracle": err_vs_oracle,
         "roofline": roofline,
