@@ -125,3 +125,75 @@ def longrange_problem(n=6000, extra=300, seed=11):
     b = rng.uniform(-1, 1, n)
     return mg.Problem(f"longrange{n}", pts, A.indptr.astype(np.int64), A.indices.astype(np.int32),
                       A.data.astype(np.float64), b, None, dict(kind="longrange"))
+
+
+def wheel_mesh(spokes=40, rings=3, seed=4):
+    """A disk of `rings` rings of `spokes` points around a centre, each ring joined to the next by 2 * spokes
+    triangles and the centre to the first ring by a fan: the centre lies in `spokes` triangles, so its diagonal entry
+    sums `spokes` element entries. The outer ring is the Dirichlet boundary. Returns (points, tris, dirichlet)."""
+    rng = np.random.default_rng(seed)
+    pts = [(0.5, 0.5)]
+    for r in range(1, rings + 1):
+        rad = 0.45 * r / rings
+        for k in range(spokes):
+            a = 2 * np.pi * (k + 0.2 * rng.uniform(-1, 1) * (r < rings)) / spokes + 0.1 * r
+            pts.append((0.5 + rad * np.cos(a), 0.5 + rad * np.sin(a)))
+    pts = np.array(pts)
+    ring = lambda r, k: 1 + (r - 1) * spokes + (k % spokes)
+    tris = [(0, ring(1, k), ring(1, k + 1)) for k in range(spokes)]
+    for r in range(1, rings):
+        for k in range(spokes):
+            tris.append((ring(r, k), ring(r + 1, k), ring(r + 1, k + 1)))
+            tris.append((ring(r, k), ring(r + 1, k + 1), ring(r, k + 1)))
+    tris = np.array(tris, dtype=np.int64)
+    tris[1::2] = tris[1::2][:, [0, 2, 1]]  # mixed orientation: half the triangles clockwise
+    dirichlet = np.zeros(len(pts), dtype=bool)
+    dirichlet[1 + (rings - 1) * spokes:] = True
+    return pts, tris, dirichlet
+
+
+def assembly_in_stated_order(pts, tris, kappa, dirichlet):
+    """Stored entries of the P1 stiffness matrix in the evaluation order the device assembly states: element
+    entries in the order (a, b, triangle) per stored (row, column); the first entry plus the others' sum, sequential
+    from 0 below eight terms, else eight interleaved partial sums combined pairwise, then the remainder."""
+    tris = np.asarray(tris, dtype=np.int64).copy()
+    a0, b0, c0 = pts[tris[:, 0]], pts[tris[:, 1]], pts[tris[:, 2]]
+    s = (b0[:, 0] - a0[:, 0]) * (c0[:, 1] - a0[:, 1]) - (b0[:, 1] - a0[:, 1]) * (c0[:, 0] - a0[:, 0])
+    tris[s < 0] = tris[s < 0][:, [0, 2, 1]]
+    P = [pts[tris[:, k]] for k in range(3)]
+    E = [P[2] - P[1], P[0] - P[2], P[1] - P[0]]
+    kap = np.ones(len(tris)) if kappa is None else kappa
+    dof = np.full(len(pts), -1)
+    dof[~dirichlet] = np.arange(int((~dirichlet).sum()))
+    terms = {}
+    for a in range(3):
+        for b in range(3):
+            v = kap * (E[a][:, 0] * E[b][:, 0] + E[a][:, 1] * E[b][:, 1]) / (2.0 * np.abs(s))
+            for t in range(len(tris)):
+                r, c = dof[tris[t, a]], dof[tris[t, b]]
+                if r >= 0 and c >= 0:
+                    terms.setdefault((r, c), []).append(v[t])
+
+    def rest_sum(x):
+        if len(x) < 8:
+            acc = 0.0
+            for v in x:
+                acc = acc + v
+            return acc
+        p = list(x[:8])
+        i = 8
+        while i + 8 <= len(x):
+            for j in range(8):
+                p[j] = p[j] + x[i + j]
+            i += 8
+        acc = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]))
+        for v in x[i:]:
+            acc = acc + v
+        return acc
+
+    keys = sorted(terms)
+    vals = np.array([terms[k][0] + rest_sum(terms[k][1:]) if len(terms[k]) > 1 else terms[k][0] for k in keys])
+    n = int((~dirichlet).sum())
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, np.array([k[0] for k in keys]) + 1, 1)
+    return np.cumsum(row_ptr), np.array([k[1] for k in keys], dtype=np.int32), vals

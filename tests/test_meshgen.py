@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 from paper_1209_5421_amd import meshgen as mg
+from tests import helpers as H
 
 
 @pytest.mark.parametrize("side,kappa,seed", [(12, 0, 0), (40, 0, 0), (40, 16, 2), (30, 16, 1)])
@@ -82,3 +83,23 @@ def test_disk_mesh_properties():
     rs = np.asarray(A.sum(1)).ravel()
     assert np.abs(rs[far]).max() <= 1e-13 * A.diagonal().max()
     assert np.linalg.eigvalsh(A.toarray()).min() > 0
+
+
+@pytest.mark.parametrize("mesh", ["wheel40", "wheel100", "jittered40_kappa"])
+def test_p1_assembly_follows_the_stated_summation_order(mesh):
+    """The host generator's assembly equals, bit for bit, the evaluation order the device assembly states (long
+    sums included: the wheel's centre sums 40 or 100 element entries), so the device result can be compared with
+    the generator's exactly."""
+    if mesh.startswith("wheel"):
+        pts, tris, dirichlet = H.wheel_mesh(spokes=int(mesh[5:]))
+        kap = None
+    else:
+        pts = mg.jittered_points(40)
+        tris = mg.delaunay(pts)
+        kap = mg.checkerboard_kappa(pts, tris, 4)
+        dirichlet = mg._on_unit_boundary(pts)
+    _, rp, col, val = mg.p1_assemble(pts, tris, kap, dirichlet=dirichlet)
+    rp2, col2, val2 = H.assembly_in_stated_order(pts, tris, kap, dirichlet)
+    np.testing.assert_array_equal(rp, rp2)
+    np.testing.assert_array_equal(col, col2)
+    np.testing.assert_array_equal(val, val2)
