@@ -194,6 +194,34 @@ amg_status amg_engine_info(const amg_hierarchy *h, int32_t precision, int32_t *t
                            int32_t *steps, size_t *lds_bytes);
 
 /* Human-readable name of a status. */
+/* ---- P1 assembly on the device (the step before the hierarchy in time stepping) ----
+ * Stiffness matrix of -div(kappa grad u) with linear triangles: element entries kappa_T (E_a . E_b) / (4 |T|), E_a
+ * the edge opposite vertex a, summed per (row, column) over the triangles sharing both vertices, with every vertex
+ * pair of a triangle stored (zero values included). Unknowns are the vertices with dof[v] >= 0, numbered dof[v];
+ * rows and columns of the others (eliminated Dirichlet vertices) are dropped. Columns ascend inside each row. The
+ * summation order is fixed (see qa_assemble.hip), so repeated assembly is bit-identical. Example 2 of Section 5
+ * solves one such system per time step; the pattern is built once and each step assembles new values. */
+typedef struct amg_p1_mesh amg_p1_mesh;
+
+/* Build the pattern of a triangle mesh. points: device, nv x 2 (x, y interleaved); tris: device, nt x 3 vertex ids
+ * (either orientation); dof: device, nv entries, -1 or an unknown index in [0, ndof), each index used once. The
+ * handle copies what it needs (inputs borrowed for the call) and keeps about 12 bytes per element entry (9 per
+ * triangle) for later assembly. stream: hipStream_t of all its work. Errors: AMG_ERR_INVALID (sizes, a vertex id out
+ * of range, a degenerate triangle, a bad dof map, an entry summing more than 128 element entries), AMG_ERR_NOMEM,
+ * AMG_ERR_DEVICE. */
+amg_status amg_p1_mesh_create(int64_t nv, const double *points, int64_t nt, const int32_t *tris, const int32_t *dof,
+                              int64_t ndof, void *stream, amg_p1_mesh **out);
+
+/* The pattern: *nnz (host), and, where not NULL, row_ptr (device, ndof + 1) and col_idx (device, nnz) copied out. */
+amg_status amg_p1_mesh_pattern(const amg_p1_mesh *m, int64_t *nnz, int64_t *row_ptr, int32_t *col_idx);
+
+/* Values for per-triangle coefficients kappa (device, nt entries in the order of tris; NULL = 1) into vals (device,
+ * nnz, the order of the pattern). Blocks until done. Errors: AMG_ERR_INVALID (NULL handle or vals). */
+amg_status amg_p1_assemble(amg_p1_mesh *m, const double *kappa, double *vals);
+
+/* Release the handle and its device memory (NULL is allowed). */
+void amg_p1_mesh_free(amg_p1_mesh *m);
+
 const char *amg_status_string(amg_status s);
 
 #ifdef __cplusplus

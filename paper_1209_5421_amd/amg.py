@@ -19,7 +19,8 @@ STATUS = {0: "AMG_OK", 1: "AMG_ERR_INVALID", 2: "AMG_ERR_NOMEM", 3: "AMG_ERR_DEV
 EXPORTED = ["amg_default_options", "amg_setup", "amg_update_values", "amg_solve", "amg_free", "amg_set_precision", "amg_set_stream",
             "amg_solve_batch", "amg_estimate_bytes", "amg_hierarchy_bytes", "amg_num_levels", "amg_level_info",
             "amg_export_level", "amg_export_level_f32", "amg_apply_precond", "amg_level_smooth", "amg_level_spmv",
-            "amg_kernel_timing_enable", "amg_kernel_timing_read", "amg_engine_info", "amg_status_string"]
+            "amg_kernel_timing_enable", "amg_kernel_timing_read", "amg_engine_info", "amg_p1_mesh_create",
+            "amg_p1_mesh_pattern", "amg_p1_assemble", "amg_p1_mesh_free", "amg_status_string"]
 
 
 class Options(C.Structure):
@@ -77,10 +78,15 @@ def load(path: str = LIB_PATH):
     L.amg_kernel_timing_enable.argtypes = [p, C.c_char_p]
     L.amg_kernel_timing_read.argtypes = [p, C.POINTER(i64), C.POINTER(d), C.POINTER(d)]
     L.amg_engine_info.argtypes = [p, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32), C.POINTER(C.c_size_t)]
+    L.amg_p1_mesh_create.argtypes = [i64, p, i64, p, p, i64, p, C.POINTER(p)]
+    L.amg_p1_mesh_pattern.argtypes = [p, C.POINTER(i64), p, p]
+    L.amg_p1_assemble.argtypes = [p, p, p]
+    L.amg_p1_mesh_free.argtypes = [p]
+    L.amg_p1_mesh_free.restype = None
     L.amg_status_string.argtypes = [i32]
     L.amg_status_string.restype = C.c_char_p
     for name in EXPORTED:
-        if name not in ("amg_default_options", "amg_free", "amg_status_string"):
+        if name not in ("amg_default_options", "amg_free", "amg_p1_mesh_free", "amg_status_string"):
             getattr(L, name).restype = i32
     _lib = L
     return L
@@ -295,3 +301,58 @@ def solve_batch(hiers, bs, xs, tols):
     infos = (Info * n)()
     code = load().amg_solve_batch(H, B, X, T, n, infos)
     return code, [i.as_dict() for i in infos]
+
+
+class P1Mesh:
+    """Device P1 assembly for a fixed triangle mesh (amg_p1_mesh_*): pattern once, values per coefficient field.
+
+    points: (nv, 2) float64, tris: (nt, 3) int32, dof: (nv,) int32 (-1 = eliminated vertex), CUDA tensors.
+    """
+
+    def __init__(self, points, tris, dof, ndof, stream=None):
+        import torch
+        L = load()
+        for t, dt in ((points, torch.float64), (tris, torch.int32), (dof, torch.int32)):
+            if not (t.is_cuda and t.dtype == dt and t.is_contiguous()):
+                raise TypeError("inputs must be contiguous CUDA tensors: points f64 (nv,2), tris i32 (nt,3), dof i32")
+        self.device = points.device
+        self.nv, self.nt, self.ndof = int(points.shape[0]), int(tris.shape[0]), int(ndof)
+        m = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(L.amg_p1_mesh_create(self.nv, _ptr(points), self.nt, _ptr(tris), _ptr(dof), self.ndof,
+                                        _stream_handle(stream), C.byref(m)), "amg_p1_mesh_create")
+        self._m = m
+        nnz = C.c_int64()
+        _check(L.amg_p1_mesh_pattern(m, C.byref(nnz), None, None), "amg_p1_mesh_pattern")
+        self.nnz = nnz.value
+
+    def pattern(self):
+        """(row_ptr int64 (ndof+1,), col int32 (nnz,)) on the mesh's device."""
+        import torch
+        rp = torch.empty(self.ndof + 1, dtype=torch.int64, device=self.device)
+        col = torch.empty(self.nnz, dtype=torch.int32, device=self.device)
+        nnz = C.c_int64()
+        _check(load().amg_p1_mesh_pattern(self._m, C.byref(nnz), _ptr(rp), _ptr(col)), "amg_p1_mesh_pattern")
+        return rp, col
+
+    def assemble(self, kappa=None, out=None):
+        """Values (float64, (nnz,)) for per-triangle coefficients kappa (CUDA float64 (nt,), None = 1)."""
+        import torch
+        if out is None:
+            out = torch.empty(self.nnz, dtype=torch.float64, device=self.device)
+        if kappa is not None and not (kappa.is_cuda and kappa.dtype == torch.float64 and kappa.is_contiguous()
+                                      and kappa.numel() == self.nt):
+            raise TypeError("kappa must be a contiguous CUDA float64 tensor of one value per triangle")
+        _check(load().amg_p1_assemble(self._m, None if kappa is None else _ptr(kappa), _ptr(out)), "amg_p1_assemble")
+        return out
+
+    def close(self):
+        if getattr(self, "_m", None):
+            load().amg_p1_mesh_free(self._m)
+            self._m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -414,10 +414,16 @@ def rhs(n: int, seed: int = SEED_RHS) -> np.ndarray:
 # workloads
 # ----------------------------------------------------------------------------------------------------------------
 
+def _mesh_meta(pts, tris, kappa, dirichlet):
+    """The mesh behind an assembled problem, for assembling it again (on the device, with new coefficients)."""
+    return dict(points=pts, tris=np.ascontiguousarray(tris, dtype=np.int32), kappa=kappa, dirichlet=dirichlet)
+
+
 def _problem(name, pts, tris, kappa=None, rhs_seed=SEED_RHS, **meta):
     coords, rp, col, val = p1_assemble(pts, tris, kappa)
     return Problem(name, coords, rp, col, val, rhs(len(coords), rhs_seed), UNIT_BOX,
-                   dict(meta, n_points=len(pts), n_tris=len(tris)))
+                   dict(meta, n_points=len(pts), n_tris=len(tris),
+                        **_mesh_meta(pts, tris, kappa, _on_unit_boundary(pts))))
 
 
 def uniform_problem(m: int = 64, rhs_seed: int = SEED_RHS) -> Problem:
@@ -449,7 +455,8 @@ def disk_problem(side: int = 1024, seed: int = SEED_MESH, rhs_seed: int = SEED_R
     tris = delaunay(pts)
     coords, rp, col, val = p1_assemble(pts, tris, None, dirichlet=mask)
     return Problem(f"disk{side}", coords, rp, col, val, rhs(len(coords), rhs_seed), UNIT_BOX,
-                   dict(kind="disk", side=side, seed=seed, n_points=len(pts), n_tris=len(tris)))
+                   dict(kind="disk", side=side, seed=seed, n_points=len(pts), n_tris=len(tris),
+                        **_mesh_meta(pts, tris, None, mask)))
 
 
 def lattice_system(side: int, seed: int = SEED_MESH, kappa_tiles: int = 0, device=None):

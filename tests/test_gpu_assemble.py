@@ -1,0 +1,157 @@
+"""Device P1 assembly (amg_p1_mesh_*) and the time-stepping loop it feeds.
+
+Bars: the pattern equals the host generator's bit for bit, and so do the values. Both take the element entries in
+the same IEEE order and sum each stored entry in the same order, stated in qa_assemble.hip. Repeated assembly is
+bit-identical. In a time-stepping loop (assemble new coefficients, amg_update_values, solve) each step's solution
+meets the solve parity bar against the oracle on the host-assembled system.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1209_5421_amd import meshgen as mg
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _amg():
+    from paper_1209_5421_amd import amg
+    return amg
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a, dt=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev())
+
+
+def _jittered(side, tiles=0):
+    pts = mg.jittered_points(side)
+    tris = mg.delaunay(pts)
+    return pts, tris, (mg.checkerboard_kappa(pts, tris, tiles) if tiles else None), mg._on_unit_boundary(pts)
+
+
+def _uniform(m):
+    pts, tris = mg.uniform_mesh(m)
+    return pts, tris, None, mg._on_unit_boundary(pts)
+
+
+def _graded(n):
+    pts, _ = mg.graded_points(n)
+    return pts, mg.delaunay(pts), None, mg._on_unit_boundary(pts)
+
+
+def _disk(side):
+    pts, mask = mg.disk_points(side)
+    return pts, mg.delaunay(pts), None, mask
+
+
+def _wheel(spokes):
+    pts, tris, dirichlet = H.wheel_mesh(spokes=spokes)
+    return pts, tris, None, dirichlet
+
+
+MESHES = {
+    "uniform65": lambda: _uniform(64),
+    "jittered130": lambda: _jittered(130),
+    "kappa177": lambda: _jittered(177, tiles=16),
+    "graded20k": lambda: _graded(20000),
+    "disk130": lambda: _disk(130),
+    "wheel100": lambda: _wheel(100),   # the centre's diagonal sums 100 element entries (the pairwise branch)
+}
+
+
+def dof_map(mask):
+    dof = np.full(len(mask), -1, dtype=np.int32)
+    dof[~mask] = np.arange(int((~mask).sum()), dtype=np.int32)
+    return dof
+
+
+def device_mesh(pts, tris, mask):
+    dof = dof_map(mask)
+    print(f"[gpu] p1 mesh nv={len(pts)} nt={len(tris)} ndof={int((dof >= 0).sum())}", flush=True)
+    return _amg().P1Mesh(T(pts), T(tris, torch.int32), T(dof, torch.int32), int((dof >= 0).sum()))
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_assembly_equals_host_generator(name):
+    pts, tris, kap, mask = MESHES[name]()
+    coords, rp, col, val = mg.p1_assemble(pts, tris, kap, dirichlet=mask)
+    M = device_mesh(pts, tris, mask)
+    assert M.nnz == len(col)
+    rp_g, col_g = M.pattern()
+    np.testing.assert_array_equal(rp_g.cpu().numpy(), rp)
+    np.testing.assert_array_equal(col_g.cpu().numpy(), col)
+    kt = None if kap is None else T(kap)
+    v1 = M.assemble(kt)
+    np.testing.assert_array_equal(v1.cpu().numpy(), val)
+    v2 = M.assemble(kt)
+    assert torch.equal(v1, v2)
+    M.close()
+
+
+def test_time_stepping_loop():
+    """Coefficients that change every step, kappa = 1 + sin(2 pi (x + s / 8)) sin(2 pi y) / 2 at the triangles'
+    centroids: assemble on the device, update the resident hierarchy's values, solve; each step against the oracle
+    on the host-assembled system and against a fresh setup on the same values."""
+    amg = _amg()
+    pts, tris, _, mask = _jittered(177)
+    M = device_mesh(pts, tris, mask)
+    rp, col = M.pattern()
+    coords = T(pts[~mask])
+    cen = (pts[tris[:, 0]] + pts[tris[:, 1]] + pts[tris[:, 2]]) / 3.0
+    kappas = [1.0 + 0.5 * np.sin(2 * np.pi * (cen[:, 0] + s / 8.0)) * np.sin(2 * np.pi * cen[:, 1]) for s in range(4)]
+    b = mg.rhs(int((~mask).sum()))
+    h = amg.Hierarchy(coords, rp, col, M.assemble(T(kappas[0])), box=mg.UNIT_BOX, precision=1, smoother=1)
+    for s, kap in enumerate(kappas):
+        vals = M.assemble(T(kap))
+        if s:
+            h.update_values(rp, col, vals)
+        x, info = h.solve(T(b), tol=1e-8)
+        f = amg.Hierarchy(coords, rp, col, vals, box=mg.UNIT_BOX, precision=1, smoother=1)
+        xf, info_f = f.solve(T(b), tol=1e-8)
+        assert torch.equal(x, xf) and info["iters"] == info_f["iters"]
+        f.close()
+        _, hrp, hcol, hval = mg.p1_assemble(pts, tris, kap, dirichlet=mask)
+        prob = mg.Problem(f"step{s}", pts[~mask], hrp, hcol, hval, b, mg.UNIT_BOX, {})
+        o = oracle.setup_problem(prob)
+        o.set_block_smoother(True)
+        x_o, io = o.solve(b, tol=1e-8)
+        x = x.cpu().numpy()
+        assert info["status"] == 0 and abs(info["iters"] - io["iters"]) <= 1, (s, info, io)
+        assert np.linalg.norm(H.csr_of(prob) @ x - b) <= 1e-8 * np.linalg.norm(b) * (1 + 1e-6)
+        assert np.linalg.norm(x - x_o) <= 1e-6 * np.linalg.norm(x_o)
+    h.close()
+    M.close()
+
+
+def test_assembly_rejects_bad_meshes():
+    amg = _amg()
+    pts, tris, _, mask = _uniform(8)
+    dof = dof_map(mask)
+    ndof = int((dof >= 0).sum())
+
+    def make(p, t, d, n=ndof):
+        return amg.P1Mesh(T(p), T(t, torch.int32), T(d, torch.int32), n)
+
+    bad_tri = tris.copy()
+    bad_tri[3, 1] = bad_tri[3, 0]            # degenerate: a repeated vertex
+    far = tris.copy()
+    far[5, 2] = len(pts)                      # vertex id out of range
+    twice = dof.copy()
+    twice[np.nonzero(dof >= 0)[0][1]] = 0     # two vertices share an unknown (and one unknown is unused)
+    for p, t, d in ((pts, bad_tri, dof), (pts, far, dof), (pts, tris, twice)):
+        with pytest.raises(amg.AMGError) as e:
+            make(p, t, d)
+        assert e.value.code == amg.INVALID
+    with pytest.raises(amg.AMGError) as e:
+        make(pts, tris, dof, n=ndof + 1)      # an unknown no vertex takes
+    assert e.value.code == amg.INVALID
+    M = make(pts, tris, dof)                  # the good mesh still works
+    assert M.nnz > 0
+    M.close()
