@@ -119,3 +119,43 @@ def test_fullsize_graded():
     assert diff <= 1e-5
     g.close()
     o.close()
+
+
+@pytest.mark.timeout(600)
+def test_fullsize_time_step():
+    """The benchmark's time step on the 1M-unknown mesh: device assembly of a smooth coefficient field (bit-exact
+    against the host generator's assembly), a values update of the resident hierarchy (whole hierarchy bit-exact
+    against the oracle's setup of the new system), then the FP64 solve against the oracle's."""
+    from paper_1209_5421_amd import amg
+    prob = problem("c2")
+    mesh = prob.meta
+    pts, tris, dirichlet = mesh["points"], mesh["tris"], mesh["dirichlet"]
+    dof = np.full(len(pts), -1, dtype=np.int32)
+    dof[~dirichlet] = np.arange(prob.n, dtype=np.int32)
+    ti = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.int32, device="cuda:0")
+    pm = amg.P1Mesh(T(pts), ti(tris), ti(dof), prob.n)
+    rp, col = pm.pattern()
+    np.testing.assert_array_equal(rp.cpu().numpy(), prob.row_ptr)
+    np.testing.assert_array_equal(col.cpu().numpy(), prob.col)
+    cen = (pts[tris[:, 0]] + pts[tris[:, 1]] + pts[tris[:, 2]]) / 3.0
+    kap = 1.0 + 0.5 * np.sin(2 * np.pi * cen[:, 0]) * np.sin(2 * np.pi * cen[:, 1])
+    vals = pm.assemble(T(kap))
+    _, hrp, hcol, hval = mg.p1_assemble(pts, tris, kap, dirichlet=dirichlet)
+    np.testing.assert_array_equal(vals.cpu().numpy(), hval)
+    new = mg.Problem("c2_kappa_smooth", prob.coords, hrp, hcol, hval, prob.b, prob.box, {})
+    g = hier(prob, precision=1, smoother=1)
+    g.solve(T(prob.b), tol=1e-8)
+    log("update")
+    g.update_values(rp, col, vals)
+    o = oracle.setup_problem(new)
+    o.set_block_smoother(True)
+    assert_hierarchy_equal(g, o)
+    x_o, io = o.solve(new.b, tol=1e-8)
+    g.set_precision(0)
+    x_g, ig = g.solve(T(new.b), tol=1e-8)
+    x_g = x_g.cpu().numpy()
+    assert ig["status"] == 0 and abs(ig["iters"] - io["iters"]) <= 1, (ig, io)
+    assert np.linalg.norm(x_g - x_o) <= 1e-6 * np.linalg.norm(x_o)
+    log(f"time step: iters {ig['iters']} (oracle {io['iters']})")
+    g.close()
+    pm.close()
