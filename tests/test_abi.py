@@ -58,6 +58,15 @@ def test_host_only_entry_points(lib):
     assert lib.amg_setup(0, None, None, None, None, 0, None, C.byref(h)) == amg.INVALID
     assert lib.amg_solve(None, None, None, 1e-8, None) == amg.INVALID
     lib.amg_free(None)
+    # values update and device assembly: rejected without a handle or buffers, before any device work
+    assert lib.amg_update_values(None, None, None, None, 0) == amg.INVALID
+    m = C.c_void_p()
+    assert lib.amg_p1_mesh_create(0, None, 0, None, None, 0, None, C.byref(m)) == amg.INVALID and not m.value
+    assert lib.amg_p1_mesh_create(10, None, 4, None, None, 11, None, C.byref(m)) == amg.INVALID  # ndof > nv
+    n = C.c_int64()
+    assert lib.amg_p1_mesh_pattern(None, C.byref(n), None, None) == amg.INVALID
+    assert lib.amg_p1_assemble(None, None, None) == amg.INVALID
+    lib.amg_p1_mesh_free(None)
 
 
 def test_product_path_does_not_import_the_oracle():
