@@ -96,8 +96,10 @@ amg_status amg_setup(int64_t n, const double *coords, const int64_t *row_ptr, co
  * its wall time as setup_ms. Errors, with h unchanged: AMG_ERR_INVALID (h NULL, nnz or the pattern differs, row_ptr
  * not monotone, column out of range), AMG_ERR_NOT_SPD (a diagonal entry <= 0). Errors after the values began to
  * change (AMG_ERR_NOT_SPD from a failed cell or coarsest factor, AMG_ERR_NOMEM, AMG_ERR_DEVICE) leave h holding
- * partial values: solves on it return AMG_ERR_INVALID until an update succeeds. Temporary device memory (at most
- * the coarsest level's dense matrix and one count per level-L cell) is returned before the call ends. */
+ * partial values: solves on it return AMG_ERR_INVALID until an update succeeds. Temporary device memory (the
+ * coarsest level's dense matrix and factor scratch, one count per cell of a level, and, when B^ is kept as a matrix,
+ * its identity and step list: about 1 MB with the default coarse size) is returned before the call ends; the
+ * hierarchy's own footprint does not change. Must not overlap another call on h. */
 amg_status amg_update_values(amg_hierarchy *h, const int64_t *row_ptr, const int32_t *col_idx, const double *vals,
                              int64_t nnz);
 
