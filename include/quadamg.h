@@ -205,10 +205,11 @@ amg_status amg_engine_info(const amg_hierarchy *h, int32_t precision, int32_t *t
  * solves one such system per time step; the pattern is built once and each step assembles new values. */
 typedef struct amg_p1_mesh amg_p1_mesh;
 
-/* Build the pattern of a triangle mesh. points: device, nv x 2 (x, y interleaved); tris: device, nt x 3 vertex ids
- * (either orientation); dof: device, nv entries, -1 or an unknown index in [0, ndof), each index used once. The
- * handle copies what it needs (inputs borrowed for the call) and keeps about 12 bytes per element entry (9 per
- * triangle) for later assembly. stream: hipStream_t of all its work. Errors: AMG_ERR_INVALID (sizes, a vertex id out
+/* Build the pattern of a triangle mesh on the current device. points: device, nv x 2 (x, y interleaved); tris:
+ * device, nt x 3 vertex ids (either orientation); dof: device, nv entries, -1 or an unknown index in [0, ndof), each
+ * index used once. The handle copies what it needs (inputs borrowed for the call) and keeps about 12 bytes per
+ * element entry (9 per triangle) for later assembly. stream: hipStream_t of all its work. Calls on one handle must
+ * not overlap (assembly uses the handle's element buffer). Errors: AMG_ERR_INVALID (sizes, a vertex id out
  * of range, a degenerate triangle, a bad dof map, an entry summing more than 128 element entries), AMG_ERR_NOMEM,
  * AMG_ERR_DEVICE. */
 amg_status amg_p1_mesh_create(int64_t nv, const double *points, int64_t nt, const int32_t *tris, const int32_t *dof,
