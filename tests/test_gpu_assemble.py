@@ -155,3 +155,22 @@ def test_assembly_rejects_bad_meshes():
     M = make(pts, tris, dof)                  # the good mesh still works
     assert M.nnz > 0
     M.close()
+
+
+def test_assembly_edge_cases():
+    """A single triangle; an unknown in no triangle (an empty row); all coefficients zero (the pattern stays, the
+    values are zero): pattern and values equal the host generator's."""
+    pts = np.array([[0.1, 0.1], [0.9, 0.2], [0.3, 0.8], [0.6, 0.6]])
+    cases = [
+        ("one triangle", pts[:3], np.array([[0, 1, 2]]), None, np.zeros(3, dtype=bool)),
+        ("isolated unknown", pts, np.array([[0, 2, 1]]), None, np.zeros(4, dtype=bool)),
+        ("zero coefficients", pts, np.array([[0, 1, 3], [0, 3, 2]]), np.zeros(2), np.zeros(4, dtype=bool)),
+    ]
+    for what, p, t, kap, mask in cases:
+        _, rp, col, val = mg.p1_assemble(p, t, kap, dirichlet=mask)
+        M = device_mesh(p, t, mask)
+        rp_g, col_g = M.pattern()
+        np.testing.assert_array_equal(rp_g.cpu().numpy(), rp, err_msg=what)
+        np.testing.assert_array_equal(col_g.cpu().numpy(), col, err_msg=what)
+        np.testing.assert_array_equal(M.assemble(None if kap is None else T(kap)).cpu().numpy(), val, err_msg=what)
+        M.close()
