@@ -52,6 +52,10 @@ def lib():
         L.orc_smooth.argtypes = [p, i32, p, p, i32]
         L.orc_set_block_smoother.argtypes = [p, i32]
         L.orc_level_spmv.argtypes = [p, i32, p, p]
+        L.orc_restrict.argtypes = [p, i32, p, p]
+        L.orc_prolong_add.argtypes = [p, i32, p, p]
+        L.orc_test_force_restart.argtypes = [i32]
+        L.orc_test_force_restart.restype = None
         L.orc_nlpcg_test.argtypes = [i64, p, p, p, p, i32, i32, p]
         _lib = L
     return _lib
@@ -162,6 +166,32 @@ class Oracle:
         if st != OK:
             raise OracleError(st, "orc_smooth")
         return x
+
+    def restrict(self, level, r):
+        """P^t r from level `level` to level + 1."""
+        r = np.ascontiguousarray(r, dtype=np.float64)
+        fc = np.empty(self.level_info(level + 1)["n"])
+        st = lib().orc_restrict(self._h, level, _ptr(r), _ptr(fc))
+        if st != OK:
+            raise OracleError(st, "orc_restrict")
+        return fc
+
+    def prolong_add(self, level, e, u):
+        """u + P e from level + 1 to level `level` (u is not modified)."""
+        e = np.ascontiguousarray(e, dtype=np.float64)
+        u = np.array(u, dtype=np.float64, copy=True)
+        st = lib().orc_prolong_add(self._h, level, _ptr(e), _ptr(u))
+        if st != OK:
+            raise OracleError(st, "orc_prolong_add")
+        return u
+
+    def solve_forced_restart(self, b, at_iter, tol=1e-8, max_iters=1000, mmax=1):
+        """solve() with the recurrence residual zeroed once after `at_iter` iterations (test of the restart)."""
+        lib().orc_test_force_restart(int(at_iter))
+        try:
+            return self.solve(b, tol=tol, max_iters=max_iters, mmax=mmax)
+        finally:
+            lib().orc_test_force_restart(0)
 
     def spmv(self, level, x):
         x = np.ascontiguousarray(x, dtype=np.float64)

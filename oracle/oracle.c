@@ -682,6 +682,13 @@ int orc_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int
 
 int orc_apply_precond(orc_h *h, const double *r, double *z) { return bhat(h, 0, r, z); }
 
+/* test knob: after this many outer iterations the recurrence residual is set to zero once (a recurrence that has
+ * drifted from the true residual and reports convergence), so the true-residual check and the restart from the
+ * true residual run (0 = off; cleared when used) */
+static int force_restart_at = 0;
+
+void orc_test_force_restart(int at_iter) { force_restart_at = at_iter > 0 ? at_iter : 0; }
+
 int orc_solve(orc_h *h, const double *b, double *x, double tol, int max_iters, int mmax, int *iters,
               double *relres) {
     int64_t n = h->n;
@@ -730,6 +737,10 @@ int orc_solve(orc_h *h, const double *b, double *x, double tol, int max_iters, i
             memcpy(P + (size_t)slot * n, p, n * sizeof(double));
             memcpy(Q + (size_t)slot * n, q, n * sizeof(double));
             D[slot] = d;
+        }
+        if (force_restart_at > 0 && it == force_restart_at) {
+            force_restart_at = 0;
+            for (int64_t i = 0; i < n; i++) r[i] = 0.0;
         }
         if (sqrt(dot(n, r, r)) <= tol * bn) {
             spmv(h, 0, x, t);
@@ -806,6 +817,18 @@ int orc_smooth(orc_h *h, int level, const double *f, double *x, int forward) {
     if (!r || !d) { free(r); free(d); return ORC_NOMEM; }
     smooth(h, level, f, x, forward, r, d);
     free(r); free(d);
+    return ORC_OK;
+}
+
+int orc_restrict(orc_h *h, int level, const double *r, double *fc) {
+    if (level < 0 || level >= h->nlev - 1) return ORC_INVALID;
+    restrict_res(h, level, r, fc);
+    return ORC_OK;
+}
+
+int orc_prolong_add(orc_h *h, int level, const double *e, double *u) {
+    if (level < 0 || level >= h->nlev - 1) return ORC_INVALID;
+    prolong_add(h, level, e, u);
     return ORC_OK;
 }
 

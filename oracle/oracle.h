@@ -61,6 +61,14 @@ int orc_set_block_smoother(orc_h *h, int on);
 /* y = A_level x */
 int orc_level_spmv(orc_h *h, int level, const double *x, double *y);
 
+/* Transfer between level `level` and level + 1 (Section 4.3), vectors in those levels' numberings:
+ * fc = P^t r (sum over each aggregate), u += P e (each unknown takes its aggregate's value). */
+int orc_restrict(orc_h *h, int level, const double *r, double *fc);
+int orc_prolong_add(orc_h *h, int level, const double *e, double *u);
+/* Test knob: after `at_iter` iterations of the next orc_solve the recurrence residual is set to zero once (0 = off),
+ * so the true-residual check and the restart from the true residual are exercised. */
+void orc_test_force_restart(int at_iter);
+
 /* Test hook: Algorithm 2.1 with n steps on a CSR matrix and a trivial preconditioner: mode 0 = identity,
  * mode 1 = exact inverse (dense Cholesky; small n only). */
 int orc_nlpcg_test(int64_t n, const int64_t *row_ptr, const int32_t *col, const double *val, const double *f,

@@ -419,6 +419,31 @@ def test_nlpcg_exact_preconditioner_one_step(orc):
 
 
 # ---------------------------------------------------------------------------------------------------------------
+# restriction and prolongation on every level (Section 4.3)
+# ---------------------------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("maker", [lambda: mg.jittered_problem(70), lambda: mg.graded_problem(6000),
+                                   lambda: H.longrange_problem(3000, 150), lambda: mg.disk_problem(48)])
+def test_transfers_equal_aggregation_matrix_on_every_level(orc, maker):
+    """fc = P^t r and u + P e at every level l (fine -> L and every k -> k-1), with P_{i,agg(i)} = 1 built from the
+    exported aggregates (pinned above by exact containment), element by element."""
+    prob = maker()
+    o = orc.setup_problem(prob)
+    assert o.num_levels >= 4
+    rng = np.random.default_rng(7)
+    for level in range(o.num_levels - 1):
+        n = prob.n if level == 0 else o.level_info(level)["n"]
+        nc = o.level_info(level + 1)["n"]
+        P = H.prolongation(o.export_level(level)["agg"], nc)
+        # integers in FP64: every sum is exact, so the comparison is exact whatever the summation order
+        r = rng.integers(-1000, 1000, n).astype(np.float64)
+        e = rng.integers(-1000, 1000, nc).astype(np.float64)
+        u = rng.integers(-1000, 1000, n).astype(np.float64)
+        np.testing.assert_array_equal(o.restrict(level, r), P.T @ r, err_msg=f"restriction at level {level}")
+        np.testing.assert_array_equal(o.prolong_add(level, e, u), u + P @ e, err_msg=f"prolongation at level {level}")
+
+
+# ---------------------------------------------------------------------------------------------------------------
 # Algorithm 2.2: closed forms
 # ---------------------------------------------------------------------------------------------------------------
 
@@ -514,6 +539,26 @@ def test_zero_rhs_and_verbatim_mode(orc):
     xa, ia = o.solve(prob.b, mmax=-1)
     assert i1["status"] == ia["status"] == 0
     np.testing.assert_allclose(x1, xa, rtol=1e-6, atol=1e-9)
+
+
+def test_restart_from_true_residual(orc):
+    """A forced restart after k iterations: the iteration must continue from the true residual b - A x_k with its
+    direction history cleared, i.e. equal x_k plus a fresh solve of A d = b - A x_k stopped at the same absolute
+    residual; both end at the true-residual tolerance."""
+    prob = mg.jittered_problem(66)
+    o = orc.setup_problem(prob)
+    A = H.csr_of(prob)
+    b, tol, k = prob.b, 1e-8, 4
+    x_k, i_k = o.solve(b, tol=tol, max_iters=k)
+    assert i_k["status"] == orc.NOCONV and i_k["iters"] == k
+    t = b - A @ x_k
+    d, i_d = o.solve(t, tol=tol * np.linalg.norm(b) / np.linalg.norm(t))
+    x_r, i_r = o.solve_forced_restart(b, k, tol=tol)
+    assert i_r["status"] == 0 and i_r["relres"] <= tol
+    assert abs(i_r["iters"] - (k + i_d["iters"])) <= 1, (i_r, i_d)
+    assert np.linalg.norm(x_r - (x_k + d)) <= 1e-10 * np.linalg.norm(x_r)
+    x_n, i_n = o.solve(b, tol=tol)
+    assert np.linalg.norm(x_r - x_n) <= 1e-6 * np.linalg.norm(x_n)
 
 
 def test_disk_empty_cells(orc):
