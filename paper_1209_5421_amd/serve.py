@@ -78,6 +78,12 @@ class Scheduler:
         self.lock = threading.Condition()
         self.setups = 0
         self.evictions = 0
+        self.retired = []  # evicted hierarchies not yet closed
+
+    def drain_retired(self):
+        """Evicted hierarchies, to be closed outside the lock (closing one waits for its stream)."""
+        out, self.retired = self.retired, []
+        return out
 
     def _admit_new(self, req) -> bool:
         need = self.estimate(req.problem)
@@ -89,7 +95,8 @@ class Scheduler:
                 return False
             e = self.cache.pop(victim)
             self.mem_used -= e.bytes
-            self.close_h(e.h)
+            if e.h is not None:
+                self.retired.append(e.h)  # closed by the caller once it has released the lock
             self.evictions += 1
         self.mem_used += need
         self.cache[req.mesh_id] = _Entry(None, need)  # reserved; set up by the dispatcher that took it
@@ -133,14 +140,28 @@ class Scheduler:
         e = self.cache.pop(mesh_id)
         self.mem_used -= e.bytes
         if e.h is not None:
-            self.close_h(e.h)
+            self.retired.append(e.h)
 
     def done(self, mesh_id):
         e = self.cache[mesh_id]
         e.busy = False
         e.last_use = time.perf_counter()
 
+    def release(self, mesh_ids):
+        """End of a batch, whatever happened in it: a mesh whose hierarchy never came up loses its reservation, an
+        installed one becomes idle; meshes already dropped are skipped."""
+        for m in mesh_ids:
+            e = self.cache.get(m)
+            if e is None:
+                continue
+            if e.h is None:
+                self.failed(m)
+            else:
+                self.done(m)
+
     def close_all(self):
+        for h in self.drain_retired():
+            self.close_h(h)
         for e in self.cache.values():
             if e.h is not None:
                 self.close_h(e.h)
@@ -191,50 +212,65 @@ class Server:
                     if not batch:
                         self.lock.wait(0.002)
                         continue
-                t_start = time.perf_counter() - t0
-                hs, bs, xs, ok = [], [], [], []
-                for j, (r, hit) in enumerate(batch):
-                    st = streams[j % len(streams)]
-                    with torch.cuda.stream(st):
-                        if not hit:
-                            p = r.problem
-                            try:
-                                h = amg.Hierarchy(_dev(torch, p.coords, torch.float64, self.device),
-                                                  _dev(torch, p.row_ptr, torch.int64, self.device),
-                                                  _dev(torch, p.col, torch.int32, self.device),
-                                                  _dev(torch, p.val, torch.float64, self.device), box=p.box,
-                                                  precision=self.precision, stream=st, batch=self.batch)
-                            except amg.AMGError as exc:
-                                with self.lock:
-                                    sched.failed(r.mesh_id)
-                                    self.results[r.rid] = Result(r.rid, None, 0, float("nan"), exc.code,
-                                                                 r.arrival, t_start, time.perf_counter() - t0, False,
-                                                                 len(batch))
-                                    self.lock.notify_all()
-                                continue
-                            with self.lock:
-                                sched.installed(r.mesh_id, h, h.bytes())
-                        else:
-                            h = sched.cache[r.mesh_id].h
-                            h.set_stream(st)
-                            h.set_precision(self.precision)
-                        b = _dev(torch, r.rhs, torch.float64, self.device)
-                        hs.append(h)
-                        ok.append((r, hit))
-                        bs.append(b)
-                        xs.append(torch.empty_like(b))
-                for st in streams:
-                    st.synchronize()
-                code, infos = amg.solve_batch(hs, bs, xs, [self.tol] * len(hs)) if hs else (0, [])
-                xs_host = [x.cpu().numpy() for x in xs] if self.keep_x else [None] * len(xs)
-                t_end = time.perf_counter() - t0
-                with self.lock:
-                    for (r, hit), x, info in zip(ok, xs_host, infos):
-                        self.results[r.rid] = Result(r.rid, x, info["iters"], info["relres"], info["status"], r.arrival,
-                                                     t_start, t_end, hit, len(batch))
-                        sched.done(r.mesh_id)
-                    self.batches.append(len(batch))
-                    self.lock.notify_all()
+                    retired = sched.drain_retired()
+                for h in retired:
+                    h.close()
+                self._run_batch(batch, streams, t0, errors)
+
+    def _run_batch(self, batch, streams, t0, errors):
+        """Set up the batch's new hierarchies and solve it with one amg_solve_batch call. Whatever happens, every
+        request of the batch gets a result and every mesh it holds is released (done, or dropped if its hierarchy
+        never came up), so no mesh stays marked in flight."""
+        torch, sched = self.torch, self.sched
+        t_start = time.perf_counter() - t0
+        results = {}
+        try:
+            hs, bs, xs, ok = [], [], [], []
+            for j, (r, hit) in enumerate(batch):
+                st = streams[j % len(streams)]
+                with torch.cuda.stream(st):
+                    if not hit:
+                        p = r.problem
+                        try:
+                            h = amg.Hierarchy(_dev(torch, p.coords, torch.float64, self.device),
+                                              _dev(torch, p.row_ptr, torch.int64, self.device),
+                                              _dev(torch, p.col, torch.int32, self.device),
+                                              _dev(torch, p.val, torch.float64, self.device), box=p.box,
+                                              precision=self.precision, stream=st, batch=self.batch)
+                        except amg.AMGError as exc:
+                            results[r.rid] = Result(r.rid, None, 0, float("nan"), exc.code, r.arrival, t_start,
+                                                    time.perf_counter() - t0, False, len(batch))
+                            continue
+                        with self.lock:
+                            sched.installed(r.mesh_id, h, h.bytes())
+                    else:
+                        h = sched.cache[r.mesh_id].h
+                        h.set_stream(st)
+                        h.set_precision(self.precision)
+                    b = _dev(torch, r.rhs, torch.float64, self.device)
+                    hs.append(h)
+                    ok.append((r, hit))
+                    bs.append(b)
+                    xs.append(torch.empty_like(b))
+            for st in streams:
+                st.synchronize()
+            code, infos = amg.solve_batch(hs, bs, xs, [self.tol] * len(hs)) if hs else (0, [])
+            xs_host = [x.cpu().numpy() for x in xs] if self.keep_x else [None] * len(xs)
+            t_end = time.perf_counter() - t0
+            for (r, hit), x, info in zip(ok, xs_host, infos):
+                results[r.rid] = Result(r.rid, x, info["iters"], info["relres"], info["status"], r.arrival, t_start,
+                                        t_end, hit, len(batch))
+        except Exception as exc:  # recorded; serve() raises the first one after the stream ends
+            errors.append(exc)
+        finally:
+            t_end = time.perf_counter() - t0
+            with self.lock:
+                for r, hit in batch:
+                    self.results[r.rid] = results.get(r.rid) or Result(r.rid, None, 0, float("nan"), amg.DEVICE,
+                                                                       r.arrival, t_start, t_end, hit, len(batch))
+                sched.release([r.mesh_id for r, _ in batch])
+                self.batches.append(len(batch))
+                self.lock.notify_all()
 
     def serve(self, requests):
         """Serve requests at their arrival times (seconds from now); returns {rid: Result}."""

@@ -51,7 +51,10 @@ def test_admission_and_lru_eviction():
     s.pending.append(req(3, "c", 40))        # needs 40 more: evict b (idle, LRU), not a
     b = s.take_batch()
     assert [(r.rid, hit) for r, hit in b] == [(3, False)]
-    assert closed == ["hb"] and s.evictions == 1 and s.mem_used == 80
+    # eviction only retires the hierarchy under the lock; the dispatcher closes it after releasing the lock
+    assert closed == [] and s.retired == ["hb"] and s.evictions == 1 and s.mem_used == 80
+    closed.extend(s.drain_retired())
+    assert closed == ["hb"] and s.retired == []
     assert list(s.cache) == ["a", "c"]
 
 
@@ -64,7 +67,7 @@ def test_busy_hierarchies_are_not_evicted_request_waits():
     assert s.take_batch() == [] and closed == [] and [r.rid for r in s.pending] == [1]
     run_batch(s, b1)
     b2 = s.take_batch()                       # a idle now: evicted for b
-    assert [(r.rid, hit) for r, hit in b2] == [(1, False)] and closed == ["ha"]
+    assert [(r.rid, hit) for r, hit in b2] == [(1, False)] and s.drain_retired() == ["ha"]
 
 
 def test_measured_size_replaces_estimate_and_failed_setup_releases():
@@ -95,3 +98,16 @@ def test_summarize():
     m = summarize(res)
     assert m["requests"] == 10 and m["all_converged"] and m["cache_hit_rate"] == 0.5
     assert abs(m["p50_ms"] - 55.0) < 1e-9
+
+
+def test_failed_batch_releases_its_meshes():
+    """A batch whose work raised still releases every mesh: a reservation that never got a hierarchy is dropped
+    (its memory returned), an installed one is marked idle, so later requests for those meshes can start."""
+    s, _ = make(budget=100)
+    s.pending.extend([req(0, "a", 30), req(1, "b", 30)])
+    b1 = s.take_batch()
+    s.installed("a", "ha", 30)        # b's setup never finished
+    s.release([r.mesh_id for r, _ in b1])
+    assert list(s.cache) == ["a"] and not s.cache["a"].busy and s.mem_used == 30
+    s.pending.extend([req(2, "a", 30), req(3, "b", 30)])
+    assert [(r.rid, hit) for r, hit in s.take_batch()] == [(2, True), (3, False)]
