@@ -78,6 +78,28 @@ def test_whole_solve_route_matches_oracle_and_amg_solve():
         h.close()
 
 
+def test_whole_solve_route_fp32_preconditioner_matches_oracle():
+    """The serving default (FP32 preconditioner, FP64 outer) through the whole-solve workgroup: true residual at the
+    tolerance and error <= 1e-6 against the FP64 oracle solved to 1e-12."""
+    probs = [prob(s) for s in (40, 140, 258)] + [prob(120, 16)]
+    hs = [hier(p, precision=1) for p in probs]
+    code, xs, infos = solve_batch(hs, probs)
+    assert code == 0
+    for p, x, info in zip(probs, xs, infos):
+        o = oracle.setup_problem(p)
+        x12, _ = o.solve(p.b, tol=1e-12)
+        _, i8 = o.solve(p.b, tol=1e-8)
+        A = H.csr_of(p)
+        err = np.linalg.norm(x - x12) / np.linalg.norm(x12)
+        print(f"[batch] fp32-precond whole-solve n={p.n}: iters {info['iters']} (oracle fp64 {i8['iters']}), "
+              f"relres {info['relres']:.2e}, err vs oracle {err:.2e}", flush=True)
+        assert info["relres"] <= 1e-8
+        assert np.linalg.norm(A @ x - p.b) <= 1e-8 * np.linalg.norm(p.b) * (1 + 1e-6)
+        assert err <= 1e-6
+    for h in hs:
+        h.close()
+
+
 def test_mix_of_small_and_large_systems():
     small = [prob(s) for s in (66, 140)]
     large = [prob(300), prob(420)]          # > 65,536 unknowns: threaded amg_solve route
