@@ -39,9 +39,14 @@ def lib():
         L = C.CDLL(_LIB)
         p, i64, i32, d = C.c_void_p, C.c_int64, C.c_int, C.c_double
         L.orc_depth.argtypes = [i64, i32, C.POINTER(i32), C.POINTER(i32)]
+        L.orc_depth_dim.argtypes = [i64, i32, i32, C.POINTER(i32), C.POINTER(i32)]
         L.orc_cell_index.argtypes = [i64, p, p, i32, p]
         L.orc_cell_index.restype = None
+        L.orc_cell_index_dim.argtypes = [i64, i32, p, p, i32, p]
+        L.orc_cell_index_dim.restype = None
         L.orc_setup.argtypes = [i64, p, p, p, p, p, i32, i32, i32, C.POINTER(p)]
+        L.orc_setup_dim.argtypes = [i64, i32, p, p, p, p, p, i32, i32, i32, C.POINTER(p)]
+        L.orc_dim.argtypes = [p]
         L.orc_free.argtypes = [p]
         L.orc_free.restype = None
         L.orc_solve.argtypes = [p, p, p, d, i32, i32, C.POINTER(i32), C.POINTER(d)]
@@ -71,17 +76,18 @@ class OracleError(RuntimeError):
         self.code = code
 
 
-def depth(n: int, coarse_max: int = 64):
+def depth(n: int, coarse_max: int = 64, dim: int = 2):
     L, kc = C.c_int(), C.c_int()
-    nlev = lib().orc_depth(n, coarse_max, C.byref(L), C.byref(kc))
+    nlev = lib().orc_depth_dim(n, dim, coarse_max, C.byref(L), C.byref(kc))
     return nlev, L.value, kc.value
 
 
 def cell_index(coords: np.ndarray, box, L: int) -> np.ndarray:
+    """Level-L cell of each point; coords (n, 2) or (n, 3), box {a1, b1, a2, b2[, a3, b3]}."""
     coords = np.ascontiguousarray(coords, dtype=np.float64)
     bx = np.ascontiguousarray(box, dtype=np.float64)
     out = np.empty(len(coords), dtype=np.int32)
-    lib().orc_cell_index(len(coords), _ptr(coords), _ptr(bx), L, _ptr(out))
+    lib().orc_cell_index_dim(len(coords), coords.shape[1], _ptr(coords), _ptr(bx), L, _ptr(out))
     return out
 
 
@@ -94,9 +100,11 @@ class Oracle:
                       np.ascontiguousarray(col, dtype=np.int32), np.ascontiguousarray(val, dtype=np.float64)]
         bx = None if box is None else np.ascontiguousarray(box, dtype=np.float64)
         self.n = len(self._keep[0])
+        self.dim = self._keep[0].shape[1] if self._keep[0].ndim == 2 else 2
+        self.slots = 27 if self.dim == 3 else 9
         h = C.c_void_p()
-        st = lib().orc_setup(self.n, *[_ptr(a) for a in self._keep], _ptr(bx), coarse_max, inner_iters, sweeps,
-                             C.byref(h))
+        st = lib().orc_setup_dim(self.n, self.dim, *[_ptr(a) for a in self._keep], _ptr(bx), coarse_max,
+                                 inner_iters, sweeps, C.byref(h))
         if st != OK:
             raise OracleError(st, "orc_setup")
         self._h = h
@@ -126,8 +134,8 @@ class Oracle:
             st = lib().orc_export_level(self._h, 0, _ptr(out["agg"]), _ptr(out["color"]), None, None, None, None,
                                         None)
         else:
-            out["aj"] = np.empty((n, 9), dtype=np.int32)
-            out["ax"] = np.empty((n, 9), dtype=np.float64)
+            out["aj"] = np.empty((n, self.slots), dtype=np.int32)
+            out["ax"] = np.empty((n, self.slots), dtype=np.float64)
             out["ovf_ptr"] = np.empty(n + 1, dtype=np.int64)
             out["ovf_col"] = np.empty(info["ovf_nnz"], dtype=np.int32)
             out["ovf_val"] = np.empty(info["ovf_nnz"], dtype=np.float64)

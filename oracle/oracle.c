@@ -35,6 +35,13 @@
  *     of a color phase take the exact solve of their diagonal block, u_cell += A_cc^{-1} r_cell, through a dense
  *     Cholesky factor made once (the block in ascending unknown order, entries summed in CSR order); R_k and R_k^t
  *     then differ only in the color order. Cells of more than ORC_BLOCK_MAX unknowns keep the substitution of R7.
+ *  R12 the octree (3D) variant, which the paper states only as the generalisation of the quadtree (Sections 1 and
+ *     3.1: an octree, 8^L aggregates, a 27-point coarse stencil): depth L = max{l : 8^l < N} (the strict reading of
+ *     R1), coarsest = first k with 8^k <= coarse_max; cell id (t3 2^k + t2) 2^k + t1; parent (t1>>1, t2>>1, t3>>1);
+ *     27 slots = the 9-slot plane order of Section 4.4 at dz = 0, then at dz = +1, then at dz = -1 (self first, as
+ *     Section 4.1 puts the diagonal first); 8 colors (t1 & 1) + 2 (t2 & 1) + 4 (t3 & 1), valid when couplings reach
+ *     one cell; children summed in the 2D order on the lower layer (2 t3), then the same on the upper layer.
+ *     Everything else (smoother, cycle, outer iteration) is the 2D method with 2^d colors and 2^d children.
  */
 #include "oracle.h"
 
@@ -42,16 +49,23 @@
 #include <stdlib.h>
 #include <string.h>
 
-/* neighbour offsets of Section 4.4: self, E, NE, N, NW, W, SW, S, SE */
+/* neighbour offsets of Section 4.4: self, E, NE, N, NW, W, SW, S, SE; in 3D (R12) slot 9 z + t is plane offset t at
+ * dz = 0, +1, -1 for z = 0, 1, 2 */
 static const int ODX[9] = {0, 1, 1, 0, -1, -1, -1, 0, 1};
 static const int ODY[9] = {0, 0, 1, 1, 1, 0, -1, -1, -1};
+static const int ODZ[3] = {0, 1, -1};
+static int slot_dx(int t) { return ODX[t % 9]; }
+static int slot_dy(int t) { return ODY[t % 9]; }
+static int slot_dz(int t) { return ODZ[t / 9]; }
 
 typedef struct {
-    int64_t n;      /* 4^k rows */
+    int64_t n;      /* 4^k rows (8^k in 3D) */
     int k;          /* quadtree level */
     int64_t side;   /* 2^k */
-    int32_t *aj;    /* n x 9, lexicographic neighbour id or -1 */
-    double *ax;     /* n x 9 */
+    int dim;        /* 2 or 3 */
+    int ns;         /* slots per row: 9 or 27 */
+    int32_t *aj;    /* n x ns, lexicographic neighbour id or -1 */
+    double *ax;     /* n x ns */
     int64_t *optr;  /* overflow CSR (n + 1) */
     int32_t *ocol;
     double *oval;
@@ -59,12 +73,14 @@ typedef struct {
 } olev;
 
 struct orc_h {
+    int dim;         /* 2: quadtree, 3: octree (R12) */
+    int ns, nchild;  /* slots per coarse row (9 / 27), children per cell and colors (4 / 8) */
     int64_t n, nnz;
     int64_t *rp;
     int32_t *ci;
     double *va, *diag;
     int L, kc, nlev;
-    double box[4];
+    double box[6];
     int32_t *cell;   /* fine unknown -> level-L cell */
     int64_t *cstart; /* cell -> first position in cdofs (4^L + 1) */
     int32_t *cdofs;  /* unknowns grouped by cell, ascending inside a cell */
@@ -77,21 +93,24 @@ struct orc_h {
     double *bfac;
 };
 
-static int64_t pow4(int k) { return (int64_t)1 << (2 * k); }
+/* cells of a level-k grid in d dimensions: (2^d)^k */
+static int64_t ncells(int dim, int k) { return (int64_t)1 << (dim * k); }
 
-int orc_depth(int64_t n, int coarse_max, int *L, int *kc) {
+int orc_depth_dim(int64_t n, int dim, int coarse_max, int *L, int *kc) {
     if (coarse_max < 1) coarse_max = 1;
     if (n <= coarse_max) {
         *L = -1; *kc = -1;
         return 1;
     }
     int l = 0;
-    while (pow4(l + 1) < n) l++;
+    while (ncells(dim, l + 1) < n) l++;
     int k = l;
-    while (k > 0 && pow4(k) > coarse_max) k--;
+    while (k > 0 && ncells(dim, k) > coarse_max) k--;
     *L = l; *kc = k;
     return 1 + (l - k + 1);
 }
+
+int orc_depth(int64_t n, int coarse_max, int *L, int *kc) { return orc_depth_dim(n, 2, coarse_max, L, kc); }
 
 static int32_t axis_index(double v, double a, double b, int64_t s) {
     if (!(b > a)) return 0;
@@ -103,13 +122,25 @@ static int32_t axis_index(double v, double a, double b, int64_t s) {
     return (int32_t)i;
 }
 
-void orc_cell_index(int64_t n, const double *coords, const double *box, int L, int32_t *cell) {
+void orc_cell_index_dim(int64_t n, int dim, const double *coords, const double *box, int L, int32_t *cell) {
     int64_t s = (int64_t)1 << L;
     for (int64_t i = 0; i < n; i++) {
-        int32_t xi = axis_index(coords[2 * i], box[0], box[1], s);
-        int32_t yi = axis_index(coords[2 * i + 1], box[2], box[3], s);
-        cell[i] = (int32_t)(yi * s + xi);
+        int64_t id = 0;
+        for (int a = dim - 1; a >= 0; a--)  /* (t3 s + t2) s + t1 */
+            id = id * s + axis_index(coords[dim * i + a], box[2 * a], box[2 * a + 1], s);
+        cell[i] = (int32_t)id;
     }
+}
+
+void orc_cell_index(int64_t n, const double *coords, const double *box, int L, int32_t *cell) {
+    orc_cell_index_dim(n, 2, coords, box, L, cell);
+}
+
+/* grid coordinates (t1, t2, t3) of lexicographic cell I on a level of side s (t3 = 0 in 2D) */
+static void cell_coords(int64_t I, int64_t s, int64_t t[3]) {
+    t[0] = I % s;
+    t[1] = (I / s) % s;
+    t[2] = I / (s * s);
 }
 
 /* ------------------------------------------------------------------------------------------------------------ */
@@ -216,45 +247,61 @@ static int ovf_flush(ovfstore *s, rowbuf *b) {
     return 0;
 }
 
-/* add coupling value v between cell I and cell J of a level with side s: a 9-point slot or the overflow row */
+/* add coupling value v between cell I and cell J of a level: a stencil slot or the overflow row */
 static int add_coupling(olev *lv, int64_t I, int64_t J, double v, rowbuf *ob) {
-    int64_t s = lv->side;
-    int64_t dx = (J % s) - (I % s), dy = (J / s) - (I / s);
-    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1) {
-        for (int t = 0; t < 9; t++)
-            if (ODX[t] == dx && ODY[t] == dy) {
-                lv->ax[I * 9 + t] += v;
+    int64_t ti[3], tj[3];
+    cell_coords(I, lv->side, ti);
+    cell_coords(J, lv->side, tj);
+    int64_t dx = tj[0] - ti[0], dy = tj[1] - ti[1], dz = tj[2] - ti[2];
+    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
+        for (int t = 0; t < lv->ns; t++)
+            if (slot_dx(t) == dx && slot_dy(t) == dy && slot_dz(t) == dz) {
+                lv->ax[I * lv->ns + t] += v;
                 return 0;
             }
     }
     return rowbuf_add(ob, (int32_t)J, v);
 }
 
-static int level_alloc(olev *lv, int k) {
+static int level_alloc(olev *lv, int k, int dim) {
     lv->k = k;
+    lv->dim = dim;
+    lv->ns = dim == 3 ? 27 : 9;
     lv->side = (int64_t)1 << k;
-    lv->n = pow4(k);
-    lv->aj = malloc(lv->n * 9 * sizeof(int32_t));
-    lv->ax = calloc(lv->n * 9, sizeof(double));
+    lv->n = ncells(dim, k);
+    lv->aj = malloc(lv->n * lv->ns * sizeof(int32_t));
+    lv->ax = calloc(lv->n * lv->ns, sizeof(double));
     lv->optr = calloc(lv->n + 1, sizeof(int64_t));
     lv->empty = calloc(lv->n, 1);
     lv->ocol = NULL;
     lv->oval = NULL;
     if (!lv->aj || !lv->ax || !lv->optr || !lv->empty) return ORC_NOMEM;
+    int64_t s = lv->side;
     for (int64_t I = 0; I < lv->n; I++) {
-        int64_t t1 = I % lv->side, t2 = I / lv->side;
-        for (int t = 0; t < 9; t++) {
-            int64_t u1 = t1 + ODX[t], u2 = t2 + ODY[t];
-            lv->aj[I * 9 + t] =
-                (u1 >= 0 && u1 < lv->side && u2 >= 0 && u2 < lv->side) ? (int32_t)(u2 * lv->side + u1) : -1;
+        int64_t t[3];
+        cell_coords(I, s, t);
+        for (int q = 0; q < lv->ns; q++) {
+            int64_t u1 = t[0] + slot_dx(q), u2 = t[1] + slot_dy(q), u3 = t[2] + slot_dz(q);
+            int in = u1 >= 0 && u1 < s && u2 >= 0 && u2 < s && u3 >= 0 && (dim == 2 ? u3 == 0 : u3 < s);
+            lv->aj[I * lv->ns + q] = in ? (int32_t)((u3 * s + u2) * s + u1) : -1;
         }
     }
     return ORC_OK;
 }
 
+/* eq. (10): the parent (t1 >> 1, t2 >> 1[, t3 >> 1]) on the level of side s / 2 */
 static int64_t parent_of(int64_t J, int64_t side) {
-    int64_t t1 = J % side, t2 = J / side;
-    return (t2 >> 1) * (side >> 1) + (t1 >> 1);
+    int64_t t[3], h = side >> 1;
+    cell_coords(J, side, t);
+    return ((t[2] >> 1) * h + (t[1] >> 1)) * h + (t[0] >> 1);
+}
+
+/* child c (0 .. 2^d - 1) of coarse cell (T1, T2, T3), in the order of Section 4.3's restriction formula:
+ * (2T1, 2T2), (2T1+1, 2T2), (2T1+1, 2T2+1), (2T1, 2T2+1) on the layer 2 T3, then the same on the layer 2 T3 + 1 */
+static int64_t child_of(const int64_t T[3], int c, int64_t fine_side) {
+    static const int CX[4] = {0, 1, 1, 0}, CY[4] = {0, 0, 1, 1};
+    int64_t t1 = 2 * T[0] + CX[c & 3], t2 = 2 * T[1] + CY[c & 3], t3 = 2 * T[2] + (c >> 2);
+    return (t3 * fine_side + t2) * fine_side + t1;
 }
 
 /* fine CSR -> level L: (A_L)_{IJ} = sum_{i in G_I} sum_{j in G_J} a_ij */
@@ -271,7 +318,7 @@ static int galerkin_fine(orc_h *h, olev *lv) {
         }
         if (ovf_flush(&os, &ob)) { st = ORC_NOMEM; goto out; }
         lv->optr[I + 1] = os.cnt;
-        if (lv->empty[I]) lv->ax[I * 9] = 1.0;
+        if (lv->empty[I]) lv->ax[I * lv->ns] = 1.0;
     }
     lv->ocol = os.col;
     lv->oval = os.val;
@@ -281,25 +328,24 @@ out:
     return st;
 }
 
-/* level k -> level k-1: sums over the four children (the action of restriction, Section 4.4) */
+/* level k -> level k-1: sums over the 2^d children (the action of restriction, Section 4.4) */
 static int galerkin_coarse(const olev *fl, olev *lv) {
     rowbuf ob = {0};
     ovfstore os = {0};
     int st = ORC_OK;
-    int64_t sc = lv->side;
+    const int nchild = 1 << lv->dim;
     for (int64_t I = 0; I < lv->n; I++) {
-        int64_t T1 = I % sc, T2 = I / sc;
-        int64_t ch[4] = {(2 * T2) * fl->side + 2 * T1, (2 * T2) * fl->side + 2 * T1 + 1,
-                         (2 * T2 + 1) * fl->side + 2 * T1 + 1, (2 * T2 + 1) * fl->side + 2 * T1};
+        int64_t T[3];
+        cell_coords(I, lv->side, T);
         int all_empty = 1;
-        for (int c = 0; c < 4; c++) {
-            int64_t C = ch[c];
+        for (int c = 0; c < nchild; c++) {
+            int64_t C = child_of(T, c, fl->side);
             if (fl->empty[C]) continue;
             all_empty = 0;
-            for (int t = 0; t < 9; t++) {
-                int32_t J = fl->aj[C * 9 + t];
+            for (int t = 0; t < fl->ns; t++) {
+                int32_t J = fl->aj[C * fl->ns + t];
                 if (J < 0) continue;
-                if (add_coupling(lv, I, parent_of(J, fl->side), fl->ax[C * 9 + t], &ob)) { st = ORC_NOMEM; goto out; }
+                if (add_coupling(lv, I, parent_of(J, fl->side), fl->ax[C * fl->ns + t], &ob)) { st = ORC_NOMEM; goto out; }
             }
             for (int64_t e = fl->optr[C]; e < fl->optr[C + 1]; e++)
                 if (add_coupling(lv, I, parent_of(fl->ocol[e], fl->side), fl->oval[e], &ob)) { st = ORC_NOMEM; goto out; }
@@ -307,7 +353,7 @@ static int galerkin_coarse(const olev *fl, olev *lv) {
         lv->empty[I] = (uint8_t)all_empty;
         if (ovf_flush(&os, &ob)) { st = ORC_NOMEM; goto out; }
         lv->optr[I + 1] = os.cnt;
-        if (all_empty) lv->ax[I * 9] = 1.0;
+        if (all_empty) lv->ax[I * lv->ns] = 1.0;
     }
     lv->ocol = os.col;
     lv->oval = os.val;
@@ -322,7 +368,12 @@ out:
 
 static int64_t level_n(const orc_h *h, int l) { return l == 0 ? h->n : h->lev[l].n; }
 
-static int cell_color_lex(int64_t I, int64_t side) { return (int)((I % side) & 1) + 2 * (int)((I / side) & 1); }
+/* color (t1 & 1) + 2 (t2 & 1) [+ 4 (t3 & 1)] of a lexicographic cell (Section 4.5; R12 in 3D) */
+static int cell_color_lex(int64_t I, int64_t side) {
+    int64_t t[3];
+    cell_coords(I, side, t);
+    return (int)(t[0] & 1) + 2 * (int)(t[1] & 1) + 4 * (int)(t[2] & 1);
+}
 
 static double row_dot(const orc_h *h, int l, int64_t i, const double *x) {
     double acc = 0.0;
@@ -330,9 +381,9 @@ static double row_dot(const orc_h *h, int l, int64_t i, const double *x) {
         for (int64_t e = h->rp[i]; e < h->rp[i + 1]; e++) acc += h->va[e] * x[h->ci[e]];
     } else {
         const olev *lv = &h->lev[l];
-        for (int t = 0; t < 9; t++) {
-            int32_t J = lv->aj[i * 9 + t];
-            if (J >= 0) acc += lv->ax[i * 9 + t] * x[J];
+        for (int t = 0; t < lv->ns; t++) {
+            int32_t J = lv->aj[i * lv->ns + t];
+            if (J >= 0) acc += lv->ax[i * lv->ns + t] * x[J];
         }
         for (int64_t e = lv->optr[i]; e < lv->optr[i + 1]; e++) acc += lv->oval[e] * x[lv->ocol[e]];
     }
@@ -352,10 +403,10 @@ static double dot(int64_t n, const double *a, const double *b) {
 
 /* one colored sweep (reading R7); r and d are scratch vectors of the level's size */
 static void smooth(const orc_h *h, int l, const double *f, double *x, int forward, double *r, double *d) {
-    for (int ph = 0; ph < 4; ph++) {
-        int c = forward ? ph : 3 - ph;
+    for (int ph = 0; ph < h->nchild; ph++) {
+        int c = forward ? ph : h->nchild - 1 - ph;
         if (l == 0) {
-            int64_t nL = pow4(h->L), sL = (int64_t)1 << h->L;
+            int64_t nL = ncells(h->dim, h->L), sL = (int64_t)1 << h->L;
             for (int64_t I = 0; I < nL; I++) {
                 if (cell_color_lex(I, sL) != c) continue;
                 for (int64_t a = h->cstart[I]; a < h->cstart[I + 1]; a++) {
@@ -391,7 +442,7 @@ static void smooth(const orc_h *h, int l, const double *f, double *x, int forwar
             for (int64_t I = 0; I < lv->n; I++)
                 if (cell_color_lex(I, lv->side) == c) r[I] = f[I] - row_dot(h, l, I, x);
             for (int64_t I = 0; I < lv->n; I++)
-                if (cell_color_lex(I, lv->side) == c) x[I] += r[I] / lv->ax[I * 9];
+                if (cell_color_lex(I, lv->side) == c) x[I] += r[I] / lv->ax[I * lv->ns];
         }
     }
 }
@@ -408,12 +459,10 @@ static void restrict_res(const orc_h *h, int l, const double *r, double *fc) {
     } else {
         const olev *fl = &h->lev[l];
         for (int64_t I = 0; I < cl->n; I++) {
-            int64_t T1 = I % cl->side, T2 = I / cl->side;
+            int64_t T[3];
+            cell_coords(I, cl->side, T);
             double acc = 0.0;
-            acc += r[(2 * T2) * fl->side + 2 * T1];
-            acc += r[(2 * T2) * fl->side + 2 * T1 + 1];
-            acc += r[(2 * T2 + 1) * fl->side + 2 * T1 + 1];
-            acc += r[(2 * T2 + 1) * fl->side + 2 * T1];
+            for (int c = 0; c < h->nchild; c++) acc += r[child_of(T, c, fl->side)];
             fc[I] = acc;
         }
     }
@@ -529,7 +578,7 @@ int orc_set_block_smoother(orc_h *h, int on) {
     h->block = 0;
     if (!on || h->nlev == 1) return ORC_OK;
     if (!h->bfac) {
-        int64_t nL = pow4(h->L);
+        int64_t nL = ncells(h->dim, h->L);
         h->boff = calloc(nL + 1, sizeof(int64_t));
         if (!h->boff) return ORC_NOMEM;
         for (int64_t I = 0; I < nL; I++) {
@@ -573,42 +622,44 @@ void orc_free(orc_h *h) {
     free(h);
 }
 
-int orc_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col, const double *val,
-              const double *box, int coarse_max, int inner_iters, int sweeps, orc_h **out) {
+int orc_setup_dim(int64_t n, int dim, const double *coords, const int64_t *row_ptr, const int32_t *col,
+                  const double *val, const double *box, int coarse_max, int inner_iters, int sweeps, orc_h **out) {
     *out = NULL;
-    if (n < 1 || !coords || !row_ptr || !col || !val || inner_iters < 1 || sweeps < 1) return ORC_INVALID;
+    if (n < 1 || (dim != 2 && dim != 3) || !coords || !row_ptr || !col || !val || inner_iters < 1 || sweeps < 1)
+        return ORC_INVALID;
     if (row_ptr[0] != 0) return ORC_INVALID;
     for (int64_t i = 0; i < n; i++)
         if (row_ptr[i + 1] < row_ptr[i]) return ORC_INVALID;
     int64_t nnz = row_ptr[n];
     for (int64_t e = 0; e < nnz; e++)
         if (col[e] < 0 || col[e] >= n) return ORC_INVALID;
-    for (int64_t i = 0; i < 2 * n; i++)
+    for (int64_t i = 0; i < dim * n; i++)
         if (!isfinite(coords[i])) return ORC_INVALID;
-    double bx[4];
+    double bx[6] = {0, 0, 0, 0, 0, 0};
     if (box) {
-        for (int t = 0; t < 4; t++)
-            if (!isfinite(box[t])) return ORC_INVALID;
-        if (box[1] < box[0] || box[3] < box[2]) return ORC_INVALID;
-        for (int64_t i = 0; i < n; i++)
-            if (coords[2 * i] < box[0] || coords[2 * i] > box[1] || coords[2 * i + 1] < box[2] ||
-                coords[2 * i + 1] > box[3])
-                return ORC_INVALID;
-        memcpy(bx, box, sizeof bx);
+        for (int a = 0; a < dim; a++) {
+            if (!isfinite(box[2 * a]) || !isfinite(box[2 * a + 1]) || box[2 * a + 1] < box[2 * a]) return ORC_INVALID;
+            for (int64_t i = 0; i < n; i++)
+                if (coords[dim * i + a] < box[2 * a] || coords[dim * i + a] > box[2 * a + 1]) return ORC_INVALID;
+            bx[2 * a] = box[2 * a];
+            bx[2 * a + 1] = box[2 * a + 1];
+        }
     } else { /* eq. (6): the bounding box */
-        bx[0] = bx[1] = coords[0];
-        bx[2] = bx[3] = coords[1];
-        for (int64_t i = 1; i < n; i++) {
-            double x = coords[2 * i], y = coords[2 * i + 1];
-            if (x < bx[0]) bx[0] = x;
-            if (x > bx[1]) bx[1] = x;
-            if (y < bx[2]) bx[2] = y;
-            if (y > bx[3]) bx[3] = y;
+        for (int a = 0; a < dim; a++) {
+            bx[2 * a] = bx[2 * a + 1] = coords[a];
+            for (int64_t i = 1; i < n; i++) {
+                double v = coords[dim * i + a];
+                if (v < bx[2 * a]) bx[2 * a] = v;
+                if (v > bx[2 * a + 1]) bx[2 * a + 1] = v;
+            }
         }
     }
     orc_h *h = calloc(1, sizeof(orc_h));
     if (!h) return ORC_NOMEM;
     h->n = n; h->nnz = nnz; h->inner = inner_iters; h->sweeps = sweeps;
+    h->dim = dim;
+    h->ns = dim == 3 ? 27 : 9;
+    h->nchild = 1 << dim;
     memcpy(h->box, bx, sizeof bx);
     h->rp = malloc((n + 1) * sizeof(int64_t));
     h->ci = malloc((nnz ? nnz : 1) * sizeof(int32_t));
@@ -624,7 +675,7 @@ int orc_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int
     for (int64_t i = 0; i < n; i++)
         if (!(h->diag[i] > 0.0)) { orc_free(h); return ORC_NOT_SPD; }
 
-    h->nlev = orc_depth(n, coarse_max, &h->L, &h->kc);
+    h->nlev = orc_depth_dim(n, dim, coarse_max, &h->L, &h->kc);
     if (h->nlev == 1) {
         h->nc = n;
         h->chol = calloc((size_t)n * n, sizeof(double));
@@ -637,13 +688,13 @@ int orc_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int
         return ORC_OK;
     }
     /* level-L aggregates, grouped by cell with a stable counting sort */
-    int64_t nL = pow4(h->L);
+    int64_t nL = ncells(dim, h->L);
     h->cell = malloc(n * sizeof(int32_t));
     h->cstart = calloc(nL + 1, sizeof(int64_t));
     h->cdofs = malloc(n * sizeof(int32_t));
     h->lev = calloc(h->nlev, sizeof(olev));
     if (!h->cell || !h->cstart || !h->cdofs || !h->lev) { orc_free(h); return ORC_NOMEM; }
-    orc_cell_index(n, coords, bx, h->L, h->cell);
+    orc_cell_index_dim(n, dim, coords, bx, h->L, h->cell);
     for (int64_t i = 0; i < n; i++) h->cstart[h->cell[i] + 1]++;
     for (int64_t I = 0; I < nL; I++) h->cstart[I + 1] += h->cstart[I];
     {
@@ -655,11 +706,11 @@ int orc_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int
     }
     /* coarse operators */
     for (int l = 1; l < h->nlev; l++) {
-        int st = level_alloc(&h->lev[l], h->L - (l - 1));
+        int st = level_alloc(&h->lev[l], h->L - (l - 1), dim);
         if (!st) st = (l == 1) ? galerkin_fine(h, &h->lev[1]) : galerkin_coarse(&h->lev[l - 1], &h->lev[l]);
         if (st) { orc_free(h); return st; }
         for (int64_t I = 0; I < h->lev[l].n; I++)
-            if (!(h->lev[l].ax[I * 9] > 0.0)) { orc_free(h); return ORC_NOT_SPD; }
+            if (!(h->lev[l].ax[I * h->ns] > 0.0)) { orc_free(h); return ORC_NOT_SPD; }
     }
     /* coarsest: dense Cholesky */
     olev *cl = &h->lev[h->nlev - 1];
@@ -667,14 +718,19 @@ int orc_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int
     h->chol = calloc((size_t)cl->n * cl->n, sizeof(double));
     if (!h->chol) { orc_free(h); return ORC_NOMEM; }
     for (int64_t I = 0; I < cl->n; I++) {
-        for (int t = 0; t < 9; t++)
-            if (cl->aj[I * 9 + t] >= 0) h->chol[I * cl->n + cl->aj[I * 9 + t]] += cl->ax[I * 9 + t];
+        for (int t = 0; t < cl->ns; t++)
+            if (cl->aj[I * cl->ns + t] >= 0) h->chol[I * cl->n + cl->aj[I * cl->ns + t]] += cl->ax[I * cl->ns + t];
         for (int64_t e = cl->optr[I]; e < cl->optr[I + 1]; e++) h->chol[I * cl->n + cl->ocol[e]] += cl->oval[e];
     }
     int st = cholesky(h->chol, cl->n);
     if (st) { orc_free(h); return st; }
     *out = h;
     return ORC_OK;
+}
+
+int orc_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col, const double *val,
+              const double *box, int coarse_max, int inner_iters, int sweeps, orc_h **out) {
+    return orc_setup_dim(n, 2, coords, row_ptr, col, val, box, coarse_max, inner_iters, sweeps, out);
 }
 
 /* ------------------------------------------------------------------------------------------------------------ */
@@ -763,6 +819,8 @@ int orc_solve(orc_h *h, const double *b, double *x, double tol, int max_iters, i
 
 int orc_num_levels(const orc_h *h) { return h->nlev; }
 
+int orc_dim(const orc_h *h) { return h->dim; }
+
 int orc_level_info(const orc_h *h, int level, int64_t *n, int *k, int64_t *ovf_nnz, int *L) {
     if (level < 0 || level >= h->nlev) return ORC_INVALID;
     if (L) *L = h->L;
@@ -802,8 +860,8 @@ int orc_export_level(const orc_h *h, int level, int32_t *agg, uint8_t *color, in
         if (agg) agg[I] = (level < h->nlev - 1) ? (int32_t)parent_of(I, lv->side) : -1;
         if (color) color[I] = (uint8_t)cell_color_lex(I, lv->side);
     }
-    if (aj) memcpy(aj, lv->aj, lv->n * 9 * sizeof(int32_t));
-    if (ax) memcpy(ax, lv->ax, lv->n * 9 * sizeof(double));
+    if (aj) memcpy(aj, lv->aj, lv->n * lv->ns * sizeof(int32_t));
+    if (ax) memcpy(ax, lv->ax, lv->n * lv->ns * sizeof(double));
     if (ovf_ptr) memcpy(ovf_ptr, lv->optr, (lv->n + 1) * sizeof(int64_t));
     if (ovf_col && lv->optr[lv->n]) memcpy(ovf_col, lv->ocol, lv->optr[lv->n] * sizeof(int32_t));
     if (ovf_val && lv->optr[lv->n]) memcpy(ovf_val, lv->oval, lv->optr[lv->n] * sizeof(double));

@@ -24,14 +24,22 @@ typedef struct orc_h orc_h;
  * level is the first k (counting down from L) with 4^k <= coarse_max. Returns the number of levels (fine + quadtree
  * levels L..kc), or 1. */
 int orc_depth(int64_t n, int coarse_max, int *L, int *kc);
+/* The same for dim = 2 (quadtree, 4^l) or dim = 3 (octree, 8^l; the paper's 3D generalisation, Section 3.1). */
+int orc_depth_dim(int64_t n, int dim, int coarse_max, int *L, int *kc);
 
 /* Level-L aggregation of Section 4.2 (eq. 9): lexicographic cell id of each point. box = {a1,b1,a2,b2}. */
 void orc_cell_index(int64_t n, const double *coords, const double *box, int L, int32_t *cell);
+/* The same in dim dimensions: coords n x dim, box {a1,b1,a2,b2[,a3,b3]}, id (t3 2^L + t2) 2^L + t1. */
+void orc_cell_index_dim(int64_t n, int dim, const double *coords, const double *box, int L, int32_t *cell);
 
 /* Setup (Section 3, Section 4.2-4.4). coords n x 2 interleaved, CSR 0-based. box NULL = bounding box of coords.
  * Returns ORC_* and *out = NULL on failure. */
 int orc_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col, const double *val,
               const double *box, int coarse_max, int inner_iters, int sweeps, orc_h **out);
+/* The same for dim = 2 or 3 (octree: 8^k cells per level, 27 coarse slots, 8 colors): coords n x dim, box
+ * {a1,b1,a2,b2[,a3,b3]}. orc_setup is orc_setup_dim with dim = 2. */
+int orc_setup_dim(int64_t n, int dim, const double *coords, const int64_t *row_ptr, const int32_t *col,
+                  const double *val, const double *box, int coarse_max, int inner_iters, int sweeps, orc_h **out);
 void orc_free(orc_h *h);
 
 /* Outer flexible CG (Algorithm 2.1 with the K-cycle of Algorithm 2.2 as preconditioner), x0 = 0, stop when
@@ -43,11 +51,13 @@ int orc_solve(orc_h *h, const double *b, double *x, double tol, int max_iters, i
 int orc_apply_precond(orc_h *h, const double *r, double *z);
 
 int orc_num_levels(const orc_h *h);
+int orc_dim(const orc_h *h);
 /* n rows, quadtree level k (-1 for the fine level), overflow entry count, depth L. */
 int orc_level_info(const orc_h *h, int level, int64_t *n, int *k, int64_t *ovf_nnz, int *L);
 /* Export in lexicographic numbering. level 0: agg = level-L cell per unknown, color per unknown (aj/ax ignored).
  * level >= 1: agg = parent cell at the next coarser level (NULL allowed; undefined on the coarsest), color per
- * cell, aj/ax n x 9 row-major, overflow CSR sorted by column. Any pointer may be NULL. */
+ * cell, aj/ax n x 9 row-major (n x 27 in 3D: the 9-slot order at dz = 0, +1, -1), overflow CSR sorted by column.
+ * Any pointer may be NULL. */
 int orc_export_level(const orc_h *h, int level, int32_t *agg, uint8_t *color, int32_t *aj, double *ax,
                      int64_t *ovf_ptr, int32_t *ovf_col, double *ovf_val);
 /* One smoothing sweep at a level on vectors in that level's numbering: forward = R (colors 0..3, forward

@@ -13,6 +13,9 @@ are not published, so these generators build stand-ins of the same kind:
 * ``graded``: quadtree-leaf sampling with local spacing c*(r+0.01)^0.75 towards the corner (0,0), Delaunay-
   triangulated (shape-regular with strong grading, Table 4's kind).
 * ``kappa``: a 16x16 checkerboard of diffusion coefficients 10^U[-3,3] for -div(kappa grad u) = f.
+* ``cube``: the 3D variant (Example 2's unit cube, Tables 6-7): one implicit Euler step of the heat equation,
+  (M / dt + K) T = f, on a jittered (m+1)^3 lattice cut into six tetrahedra per cube (Kuhn), linear elements with a
+  lumped mass, the inlet face x = 0 held fixed (eliminated), no-flux elsewhere.
 
 Seeds follow ``numpy.random.default_rng``: mesh 0, right-hand side 1, kappa 2, request stream 3.
 """
@@ -25,15 +28,16 @@ import numpy as np
 
 SEED_MESH, SEED_RHS, SEED_KAPPA, SEED_STREAM = 0, 1, 2, 3
 UNIT_BOX = (0.0, 1.0, 0.0, 1.0)
+UNIT_CUBE = (0.0, 1.0, 0.0, 1.0, 0.0, 1.0)
 
 
 @dataclasses.dataclass
 class Problem:
     """An SPD system A x = b with the coordinates of its unknowns.
 
-    ``coords`` is (n, 2) float64 (x, y interleaved); ``row_ptr`` int64 (n+1), ``col`` int32, ``val`` float64 form a
-    0-based CSR matrix with columns ascending inside each row (explicit zeros of the stencil kept); ``box`` is the
-    domain's bounding box (a1, b1, a2, b2).
+    ``coords`` is (n, 2) float64 (x, y interleaved), or (n, 3) for the 3D workload; ``row_ptr`` int64 (n+1),
+    ``col`` int32, ``val`` float64 form a 0-based CSR matrix with columns ascending inside each row (explicit zeros
+    of the stencil kept); ``box`` is the domain's bounding box (a1, b1, a2, b2[, a3, b3]).
     """
     name: str
     coords: np.ndarray
@@ -477,6 +481,74 @@ def graded_problem(target_n: int = 4_000_000, seed: int = SEED_MESH, rhs_seed: i
                     seed=seed)
 
 
+# ----------------------------------------------------------------------------------------------------------------
+# 3D: heat-transfer step on the unit cube
+# ----------------------------------------------------------------------------------------------------------------
+
+# the six tetrahedra of a unit cube around its diagonal (0,0,0)-(1,1,1): vertex path 0 -> +e_a -> +e_b -> (1,1,1)
+# for every order (a, b, c) of the axes; corners numbered x + 2 y + 4 z
+_KUHN = np.array([[0, 1, 3, 7], [0, 1, 5, 7], [0, 2, 3, 7], [0, 2, 6, 7], [0, 4, 5, 7], [0, 4, 6, 7]], dtype=np.int64)
+
+
+def cube_mesh(m: int, seed: int = SEED_MESH, jitter: float = 0.15):
+    """(points (m+1)^3 x 3, tetrahedra (6 m^3) x 4 positively oriented, inlet mask) of a jittered lattice of the unit
+    cube: interior points move by U[-jitter h, jitter h] per coordinate, boundary points stay on their faces (moved
+    only along them)."""
+    h = 1.0 / m
+    g = np.arange(m + 1, dtype=np.float64) * h
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    pts = np.stack([x.ravel(), y.ravel(), z.ravel()], 1)
+    rng = np.random.default_rng(seed)
+    d = rng.uniform(-jitter * h, jitter * h, size=pts.shape)
+    on_face = (pts <= 0.0) | (pts >= 1.0)
+    d[on_face] = 0.0  # a boundary coordinate stays on its face
+    pts = pts + d
+    i = np.arange(m)
+    kk, jj, ii = np.meshgrid(i, i, i, indexing="ij")
+    base = (kk * (m + 1) + jj) * (m + 1) + ii
+    corner = np.array([(c & 1) + ((c >> 1) & 1) * (m + 1) + (c >> 2) * (m + 1) ** 2 for c in range(8)])
+    tets = (base.ravel()[:, None, None] + corner[_KUHN][None, :, :]).reshape(-1, 4)
+    e = pts[tets[:, 1:]] - pts[tets[:, :1]]
+    vol6 = np.einsum("ij,ij->i", e[:, 0], np.cross(e[:, 1], e[:, 2]))
+    if not (np.abs(vol6) > 0.05 * h ** 3).all():
+        raise ValueError("degenerate tetrahedron")
+    neg = vol6 < 0
+    tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
+    return pts, tets, pts[:, 0] <= 0.0
+
+
+def heat_step_assemble(pts, tets, dt, fixed):
+    """CSR (columns ascending) of M / dt + K over the unknowns (vertices not ``fixed``, in vertex order): K the
+    linear-element stiffness of -div(grad T), sum over tetrahedra of |T| grad(phi_a) . grad(phi_b), M the lumped
+    mass |T| / 4 per vertex and tetrahedron. Returns (coords, row_ptr, col, val)."""
+    import scipy.sparse as sp
+    e = pts[tets[:, 1:]] - pts[tets[:, :1]]                      # (nt, 3, 3): edges from vertex 0
+    vol = np.abs(np.linalg.det(e)) / 6.0
+    inv = np.linalg.inv(e)                                       # columns: gradients of phi_1..3
+    g = np.concatenate([-inv.sum(axis=2, keepdims=True), inv], axis=2)  # (nt, 3, 4): grad phi_a as column a
+    k = vol[:, None, None] * np.einsum("tia,tib->tab", g, g)
+    nv = len(pts)
+    rows = np.repeat(tets, 4, axis=1).ravel()
+    cols = np.tile(tets, (1, 4)).ravel()
+    K = sp.csr_matrix((k.ravel(), (rows, cols)), shape=(nv, nv))
+    mass = np.bincount(tets.ravel(), weights=np.repeat(vol / 4.0, 4), minlength=nv)
+    A = (K + sp.diags(mass / dt)).tocsr()
+    keep = np.flatnonzero(~fixed)
+    A = A[keep][:, keep].tocsr()
+    A.sort_indices()
+    return (np.ascontiguousarray(pts[keep]), A.indptr.astype(np.int64), A.indices.astype(np.int32),
+            A.data.astype(np.float64))
+
+
+def cube_problem(m: int = 100, seed: int = SEED_MESH, rhs_seed: int = SEED_RHS) -> Problem:
+    """One implicit Euler step (dt = h) of the heat equation on the unit cube (the 3D variant): m = 100 gives
+    101^3 - 101^2 = 1,020,100 unknowns."""
+    pts, tets, inlet = cube_mesh(m, seed)
+    coords, rp, col, val = heat_step_assemble(pts, tets, 1.0 / m, inlet)
+    return Problem(f"cube{m + 1}", coords, rp, col, val, rhs(len(coords), rhs_seed), UNIT_CUBE,
+                   dict(kind="cube", m=m, seed=seed, n_points=len(pts), n_tets=len(tets)))
+
+
 def serving_sides(n_req: int = 512, seed: int = SEED_STREAM, dof_lo: float = 1e4, dof_hi: float = 2e6,
                   repeat_p: float = 0.3):
     """Request stream shape: per request a lattice side (DOF log-uniform in [dof_lo, dof_hi], side ~ sqrt(DOF)+2)
@@ -504,4 +576,6 @@ def config(name: str, scale: float = 1.0) -> Problem:
         return graded_problem(int(4_000_000 * scale))
     if name == "c4":
         return jittered_problem(max(8, int(round(1416 * math.sqrt(scale)))), kappa_tiles=16)
+    if name == "cube":
+        return cube_problem(max(4, int(round(100 * scale ** (1.0 / 3.0)))))
     raise KeyError(name)

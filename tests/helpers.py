@@ -28,8 +28,9 @@ def level_matrix(ex):
     """Sparse matrix of an exported quadtree level (9 slots + overflow), lexicographic numbering."""
     n = ex["n"]
     aj, ax = ex["aj"], ex["ax"]
+    ns = aj.shape[1]
     m = aj >= 0
-    rows = np.repeat(np.arange(n), 9).reshape(n, 9)[m]
+    rows = np.repeat(np.arange(n), ns).reshape(n, ns)[m]
     A = sp.csr_matrix((ax[m], (rows, aj[m])), shape=(n, n))
     if ex["ovf_ptr"][-1]:
         orow = np.repeat(np.arange(n), np.diff(ex["ovf_ptr"]))
@@ -41,8 +42,9 @@ def level_matrix_structure(ex):
     """Boolean structure (slots present + overflow) of an exported level."""
     n = ex["n"]
     aj = ex["aj"]
+    ns = aj.shape[1]
     m = aj >= 0
-    rows = np.repeat(np.arange(n), 9).reshape(n, 9)[m]
+    rows = np.repeat(np.arange(n), ns).reshape(n, ns)[m]
     S = sp.csr_matrix((np.ones(m.sum()), (rows, aj[m])), shape=(n, n))
     if ex["ovf_ptr"][-1]:
         orow = np.repeat(np.arange(n), np.diff(ex["ovf_ptr"]))
@@ -77,6 +79,35 @@ def sweep_splitting(A, color, cell, order_key):
 
 def csr_of(prob):
     return sp.csr_matrix((prob.val, prob.col, prob.row_ptr), shape=(prob.n, prob.n))
+
+
+def scattered_points_3d(n, seed):
+    return np.random.default_rng(seed).uniform(0.0, 1.0, (n, 3))
+
+
+def longrange_problem_3d(n=3000, extra=200, seed=12):
+    """Scattered points in the unit cube, 3D Delaunay graph Laplacian with random positive weights plus `extra`
+    long-range couplings and a positive shift: SPD, overflowing the 27-point pattern on every octree level."""
+    from paper_1209_5421_amd import meshgen as mg
+    from scipy.spatial import Delaunay
+    rng = np.random.default_rng(seed)
+    pts = scattered_points_3d(n, seed)
+    tet = Delaunay(pts).simplices
+    e = np.concatenate([tet[:, [a, b]] for a in range(4) for b in range(a + 1, 4)])
+    e = np.unique(np.sort(e, 1), axis=0)
+    i = rng.integers(0, n, extra)
+    j = rng.integers(0, n, extra)
+    e = np.concatenate([e, np.stack([i[i != j], j[i != j]], 1)])
+    w = rng.uniform(0.5, 2.0, len(e))
+    W = sp.csr_matrix((np.concatenate([-w, -w]), (np.concatenate([e[:, 0], e[:, 1]]),
+                                                   np.concatenate([e[:, 1], e[:, 0]]))), shape=(n, n))
+    d = -np.asarray(W.sum(1)).ravel() + rng.uniform(0.01, 0.1, n)
+    A = (W + sp.diags(d)).tocsr()
+    A.sum_duplicates()
+    A.sort_indices()
+    b = rng.uniform(-1, 1, n)
+    return mg.Problem(f"longrange3d{n}", pts, A.indptr.astype(np.int64), A.indices.astype(np.int32),
+                      A.data.astype(np.float64), b, None, dict(kind="longrange3d"))
 
 
 def scattered_points(n, seed, box=(0.0, 1.0, 0.0, 1.0)):
