@@ -48,6 +48,24 @@ ROOFLINE_KERNELS = {"engine32": "k_engine<float>", "spmv64": "k_outer_spmv_dot",
                     "resid_fine32": "k_fine_resid_full<float>", "gs_fine32": "k_fine_resid<float> (color phase)"}
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X dense FP32 vector, 256 CUs at 2.4 GHz
 N_CU = 256
+# c5 arrival rate: 0.7 x the saturated FP32-preconditioned served throughput measured by --calibrate (frozen)
+C5_RATE = 40.0
+MALL_BYTES = 256 << 20           # Infinity Cache: operands smaller than this may be served from it
+ROW_VISIT_BYTES = 250.0          # algorithmic bytes per visit of a tree-level row (9 FP32 values, its vectors)
+
+
+def coarse_row_visits(levels, top):
+    """Tree-level rows one launch of the small-level workgroup passes over: B~ at level `top` runs B^ there twice,
+    and each B^ one B~ below, so level top + j is visited 2^(j+1) times (the coarsest, a dense solve, not counted)."""
+    return sum(2 ** (l - top + 1) * levels[l]["n"] for l in range(top, len(levels) - 1))
+
+
+def solve_bytes_per_iteration(n, nnz, n_level_L):
+    """Algorithmic bytes of one outer iteration of the FP32-preconditioned solve: the outer FP64 SpMV (12 B per
+    entry + 24 B per row), the outer vector work of FCG(1) (about 108 B per row), the fine preconditioner's three
+    FP32 passes over the matrix (8 B per entry + 12 B per row each), and the tree levels (about 1000 B per level-L
+    row: 4 N_L row visits of about 250 B)."""
+    return (12.0 * nnz + 24.0 * n) + 108.0 * n + 3 * (8.0 * nnz + 12.0 * n) + 1000.0 * n_level_L
 
 
 def log(msg):
@@ -186,8 +204,17 @@ def main():
     ap.add_argument("--hbm-kernel", default="resid_fine32", choices=["resid_fine32", "spmv64", "gs_fine32"],
                     help="HBM-bound kernel reported beside it (roofline_hbm), with counter-measured traffic")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--big-leg", default="c3", choices=["c3", "c4", "none"],
+                    help="after the timed steps: a system beyond the Infinity Cache solved for 8 right-hand sides, "
+                         "with per-kernel HBM fractions")
     ap.add_argument("--requests", type=int, default=512, help="c5: requests in the stream")
-    ap.add_argument("--rate", type=float, default=40.0, help="c5: Poisson arrival rate (requests/s)")
+    ap.add_argument("--rate", type=float, default=C5_RATE,
+                    help="c5: Poisson arrival rate (requests/s); the default is frozen at 0.7 x the saturated "
+                         "throughput of the FP32-preconditioned served form (--calibrate measures it)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="c5: serve the stream with every request arriving at once and report the saturated "
+                         "solves/s and the rate 0.7 x that")
+    ap.add_argument("--oracle-sample", type=int, default=32, help="c5: requests in the oracle latency sample")
     ap.add_argument("--dispatchers", type=int, default=4, help="c5: concurrent batch dispatchers")
     ap.add_argument("--mem-gb", type=float, default=200.0, help="c5: HBM budget for resident hierarchies")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -299,6 +326,27 @@ def main():
                        "dof_per_s": float(prob.n * 1e3 / np.median(lat))}
         log(f"resident {name}: {forms[name]}")
     x_gpu = x.cpu().numpy()
+    # the other reading of the fine smoother on the same resident system (both forms)
+    other = 1 - args.smoother
+    ho = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=0, stream=stream, smoother=other)
+    forms_other = {}
+    for name, prec in (("fp64", 0), ("fp32_precond", 1)):
+        ho.set_precision(prec)
+        ho.solve(b, tol=args.tol, x=x)
+        lat = []
+        for _ in range(args.repeats):
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            _, info = ho.solve(b, tol=args.tol, x=x)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - s0) * 1e3)
+        forms_other[name] = {"iters": info["iters"], "relres": info["relres"],
+                             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                             "solves_per_s": float(1e3 / np.median(lat)),
+                             "dof_per_s": float(prob.n * 1e3 / np.median(lat))}
+    forms_other = {"smoother": ["cell substitution", "exact cell blocks"][other], **forms_other}
+    log(f"resident, other smoother: {forms_other}")
+    ho.close()
     # time stepping with changing coefficients on the same mesh: per step the device assembly of the new
     # coefficients (amg_p1_assemble), a values update of the resident hierarchy (amg_update_values) and a solve, in
     # the mixed form; kappa alternates between 1 + sin(2 pi x) sin(2 pi y) / 2 at the triangles' centroids and the
@@ -348,24 +396,38 @@ def main():
         launches, kern_ms, per_launch, nsteps = timed[kind]
         avg_ms = kern_ms / max(launches, 1)
         if kind.startswith("engine"):
-            # one workgroup runs the cycle below ~4,096 cells as a chain of dependent steps (barrier after each):
-            # its limit is that chain's latency on one CU; the entry gives the chip-wide and the one-CU fractions
-            tf = per_launch / (avg_ms * 1e-3) / 1e12 if launches else None
-            peak = FP32_VECTOR_PEAK_TFLOPS
-            return {"bound": "alu", "kernel": ROOFLINE_KERNELS[kind], "achieved": tf, "peak": peak,
-                    "unit": "TFLOP/s", "frac": (tf / peak) if tf else None, "traffic": None,
-                    "launches": launches, "avg_us": avg_ms * 1e3, "algorithmic_flops_per_launch": per_launch,
-                    "peak_one_cu": peak / N_CU, "frac_one_cu": (tf / (peak / N_CU)) if tf else None,
+            # one workgroup runs the cycle below ~4,096 cells as a chain of dependent steps (barrier after each);
+            # its algorithmic bytes are the tree-level row visits of one launch at 250 B each
+            top = engine["fp32_precond" if kind == "engine32" else "fp64"]["top_level"]
+            rows = coarse_row_visits(levels, top) if top >= 0 else 0
+            nbytes = rows * ROW_VISIT_BYTES
+            gbs = nbytes / (avg_ms * 1e-3) / 1e9 if launches else None
+            return {"bound": "hbm", "kernel": ROOFLINE_KERNELS[kind], "achieved": gbs, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": (gbs / HBM_PEAK_GBS) if gbs else None, "traffic": None,
+                    "launches": launches, "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": nbytes,
+                    "row_visits_per_launch": rows, "bytes_per_row_visit": ROW_VISIT_BYTES,
                     "share_of_solve": (kern_ms / max(nsteps, 1)) / solve_ms if nsteps else None,
-                    "limit": "latency of one workgroup's chain of dependent steps"}
+                    "operands_fit_infinity_cache": True,
+                    "limit": "latency of one workgroup's chain of dependent steps (operands in LDS and L2)"}
         gbs = per_launch / (avg_ms * 1e-3) / 1e9 if launches else None
         return {"bound": "hbm", "kernel": ROOFLINE_KERNELS[kind], "achieved": gbs, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": (gbs / HBM_PEAK_GBS) if gbs else None,
                 "traffic": traffic_from_profiles(kind, args.workload),
-                "launches": launches, "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch}
+                "launches": launches, "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": per_launch,
+                "operands_fit_infinity_cache": bool(per_launch < MALL_BYTES)}
 
     roofline = entry(args.roofline_kernel)
     roofline_hbm = entry(args.hbm_kernel) if args.hbm_kernel != args.roofline_kernel else None
+    it_med = float(np.median([i["iters"] for i in infos]))
+    bpi = solve_bytes_per_iteration(prob.n, prob.nnz, levels[1]["n"] if len(levels) > 1 else 0)
+    solve_roofline = {"bytes_per_iteration": bpi, "bytes_per_dof_per_iteration": bpi / prob.n,
+                      "iterations": it_med, "solve_ms": solve_ms,
+                      "achieved_gbs": bpi * it_med / (solve_ms * 1e-3) / 1e9,
+                      "frac": bpi * it_med / (solve_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log(f"solve-level roofline: {solve_roofline}")
+    big = None
+    if args.big_leg != "none":
+        big = big_leg(args, amg, meshgen, torch, stream)
 
     if args.copy_calibration:
         copy_calibration()
@@ -394,11 +456,114 @@ def main():
         "update_resident": update,
         "engine": engine,
         "err_vs_oracle": err_vs_oracle,
+        "solve_resident_other_smoother": forms_other,
         "roofline": roofline,
         "roofline_hbm": roofline_hbm,
+        "solve_roofline": solve_roofline,
+        "beyond_cache": big,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def big_leg(args, amg, meshgen, torch, stream):
+    """A system whose operands exceed the 256 MB Infinity Cache, on one resident hierarchy (FP32 preconditioner):
+    the graded 4.0M-unknown mesh (default) solved for 8 right-hand sides in sequence (each solve, p50/p99, aggregate
+    solves/s), then one solve per HBM-bound kernel family with its launches timed by HIP events, giving each family's
+    HBM fraction from its algorithmic bytes and the solve-level fraction."""
+    name = args.big_leg
+    desc, make = WORKLOADS[name]
+    t = time.time()
+    prob = make(meshgen)
+    log(f"{name} leg: n={prob.n} nnz={prob.nnz} generated in {time.time() - t:.1f}s")
+    dev = torch.device("cuda:0")
+    tt = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    coords, rp, ci, va = tt(prob.coords, torch.float64), tt(prob.row_ptr, torch.int64), tt(prob.col, torch.int32), \
+        tt(prob.val, torch.float64)
+    h = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=1, stream=stream, smoother=args.smoother)
+    levels = [h.level_info(l) for l in range(h.num_levels)]
+    x = torch.empty(prob.n, dtype=torch.float64, device=dev)
+    rhs = [tt(meshgen.rhs(prob.n, 1000 + j), torch.float64) for j in range(8)]
+    h.solve(rhs[0], tol=args.tol, x=x)  # warm
+    lat, its = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for bj in rhs:
+        s0 = time.perf_counter()
+        _, info = h.solve(bj, tol=args.tol, x=x)
+        lat.append((time.perf_counter() - s0) * 1e3)
+        its.append(info["iters"])
+        assert info["status"] == 0 and info["relres"] <= args.tol
+    wall = time.perf_counter() - t0
+    lat = np.array(lat)
+    seq = {"solve_ms": [float(v) for v in lat], "iters": its, "p50_ms": float(np.percentile(lat, 50)),
+           "p99_ms": float(np.percentile(lat, 99)), "solves_per_s": len(rhs) / wall,
+           "dof_per_s": prob.n * len(rhs) / wall}
+    log(f"{name} 8 sequential right-hand sides: {seq}")
+    kernels = {}
+    for kind in ("spmv64", "resid_fine32", "gs_fine32"):
+        h.timing_enable(kind)
+        h.solve(rhs[0], tol=args.tol, x=x)
+        tm = h.timing_read()
+        h.timing_enable(None)
+        avg_ms = tm["total_ms"] / max(tm["launches"], 1)
+        gbs = tm["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9
+        kernels[kind] = {"kernel": ROOFLINE_KERNELS[kind], "launches": tm["launches"], "avg_us": avg_ms * 1e3,
+                         "algorithmic_bytes_per_launch": tm["bytes_per_launch"], "achieved": gbs,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                         "traffic": traffic_from_profiles(kind, name)}
+        log(f"{name} {kind}: {kernels[kind]}")
+    bpi = solve_bytes_per_iteration(prob.n, prob.nnz, levels[1]["n"] if len(levels) > 1 else 0)
+    it_med = float(np.median(its))
+    med_ms = float(np.median(lat))
+    h.close()
+    return {"workload": f"{name}: {desc}", "n": prob.n, "nnz": prob.nnz, "precision": "fp32_precond",
+            "smoother": ["cell substitution", "exact cell blocks"][args.smoother],
+            "levels": [(lv["k"], lv["n"]) for lv in levels], "sequential_rhs": seq, "kernels": kernels,
+            "solve_roofline": {"bytes_per_iteration": bpi, "iterations": it_med, "solve_ms": med_ms,
+                               "achieved_gbs": bpi * it_med / (med_ms * 1e-3) / 1e9,
+                               "frac": bpi * it_med / (med_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
+
+
+def _oracle_request(item):
+    """One request on the CPU oracle: lattice mesh generated on the host, setup and FP64 solve (test infrastructure:
+    the baseline of the served form)."""
+    import oracle
+    from paper_1209_5421_amd import meshgen as mg
+    mid, side, rs, tol = item
+    c, rp, ci, va = mg.lattice_system(side, seed=100 + mid)
+    b = mg.rhs(len(c), rs)
+    t0 = time.perf_counter()
+    o = oracle.Oracle(c, rp, ci, va, box=mg.UNIT_BOX)
+    _, info = o.solve(b, tol=tol)
+    o.close()
+    return len(c), time.perf_counter() - t0, info["status"]
+
+
+def oracle_serving_baseline(stream, sample, tol):
+    """The oracle on the host: throughput of a pool of one worker per host core over the whole request list (each
+    request set up and solved from scratch, no cache), and the latency of one request at a time on a sample of the
+    first `sample` requests."""
+    import multiprocessing as mp
+    import oracle
+    oracle.build(force=False)
+    cores = len(os.sched_getaffinity(0))
+    items = [(mid, side, rs, tol) for mid, side, rs in stream]
+    log(f"c5 oracle: latency sample of {sample} requests ...")
+    lat = [_oracle_request(it)[1] for it in items[:sample]]
+    log(f"c5 oracle: pool of {cores} processes over {len(items)} requests ...")
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_request, items, chunksize=1)
+    wall = time.perf_counter() - t0
+    ok = all(r[2] == 0 for r in res)
+    lat_ms = np.array(lat) * 1e3
+    return {"value": len(items) / wall, "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole {len(items)}-request stream solved by the oracle in a pool of {cores} processes "
+                      f"(setup + FP64 solve per request, meshes generated outside the timing); latency p50/p99 from "
+                      f"the first {sample} requests one at a time",
+            "dof_per_s": sum(r[0] for r in res) / wall, "wall_s": wall, "all_converged": ok,
+            "latency_p50_ms": float(np.percentile(lat_ms, 50)), "latency_p99_ms": float(np.percentile(lat_ms, 99))}
 
 
 def serve_bench(args):
@@ -444,6 +609,17 @@ def serve_bench(args):
         srv.serve(warm)
         srv.close()
 
+    if args.calibrate:
+        # saturation: the whole stream queued at t = 0, the FP32-preconditioned served form
+        sat_reqs = [Request(r.rid, r.mesh_id, r.problem, r.rhs, 0.0) for r in reqs]
+        srv = Server(mem_budget=int(args.mem_gb * 2**30), precision=1, dispatchers=args.dispatchers)
+        m = summarize(srv.serve(sat_reqs), dof=dof)
+        srv.close()
+        out = {"saturated_fp32_precond": m, "rate_0p7": 0.7 * m["solves_per_s"]}
+        log(f"c5 calibration: {out}")
+        print(json.dumps(out), flush=True)
+        return
+
     passes = {"fp32_precond": dict(precision=1, dispatchers=args.dispatchers),
               "fp64": dict(precision=0, dispatchers=args.dispatchers),
               "plain_fp64_fifo": dict(precision=0, dispatchers=1, max_batch=1, batch=0)}
@@ -459,6 +635,7 @@ def serve_bench(args):
         torch.cuda.synchronize()
 
     main_pass = served["fp32_precond"]
+    cpu = None if args.no_cpu_baseline else oracle_serving_baseline(stream, args.oracle_sample, args.tol)
     out = {
         "metric": METRIC, "value": main_pass["dof_per_s"], "unit": "DOF/s", "n_gpus": 1, "steps": 1, "warmup": 1,
         "ms_per_step": main_pass["makespan_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -468,7 +645,7 @@ def serve_bench(args):
                    "step": "the whole stream served once (FP32 preconditioner, FP64 outer)"},
         "serving": served,
         "roofline": None,
-        "cpu_baseline": None,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
