@@ -35,7 +35,8 @@ HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "c1": ("uniform 65x65 vertices P1 Poisson (3,969 DOF)", lambda mg: mg.uniform_problem(64)),
     "c2": ("quasi-uniform jittered Delaunay 1024x1024 P1 Poisson (1,044,484 DOF)", lambda mg: mg.jittered_problem(1024)),
-    "c3": ("graded Delaunay ~4.0M points, density (r+0.01)^-1.5, P1 Poisson", lambda mg: mg.graded_problem(4_000_000)),
+    "c3": ("graded Delaunay ~4.0M points, density (r+0.01)^-1.5, P1 Poisson",
+           lambda mg: mg.graded_problem(4_000_000, progress=log)),
     "c4": ("jittered Delaunay 1416x1416, kappa 10^U[-3,3] 16x16 checkerboard (1,999,396 DOF)",
            lambda mg: mg.jittered_problem(1416, kappa_tiles=16)),
     "disk": ("Delaunay mesh of the disk r = 1/2 inside the unit square, jittered 1156x1156 lattice points plus 3,629 "
@@ -241,6 +242,7 @@ def main():
     if args.workload == "c5":
         return serve_bench(args)
     desc, make = WORKLOADS[args.workload]
+    log(f"workload {args.workload}: generating the mesh and its system on the host ...")
     t = time.time()
     prob = make(meshgen)
     log(f"workload {args.workload}: n={prob.n} nnz={prob.nnz} generated in {time.time() - t:.1f}s")
@@ -473,6 +475,7 @@ def big_leg(args, amg, meshgen, torch, stream):
     HBM fraction from its algorithmic bytes and the solve-level fraction."""
     name = args.big_leg
     desc, make = WORKLOADS[name]
+    log(f"{name} leg: generating the mesh and its system on the host ...")
     t = time.time()
     prob = make(meshgen)
     log(f"{name} leg: n={prob.n} nnz={prob.nnz} generated in {time.time() - t:.1f}s")

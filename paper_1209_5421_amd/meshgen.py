@@ -115,9 +115,27 @@ def disk_points(side: int, seed: int = SEED_MESH, jitter: float = 0.3):
     return pts, mask
 
 
-def delaunay(pts: np.ndarray) -> np.ndarray:
+def _morton_order(pts: np.ndarray) -> np.ndarray:
+    """Permutation sorting 2D points in [0,1]^2 along the Z-order curve of a 2^16 x 2^16 grid."""
+    q = np.clip((pts * 65536.0).astype(np.int64), 0, 65535).astype(np.uint64)
+
+    def spread(v):
+        for shift, mask in ((8, 0x00FF00FF), (4, 0x0F0F0F0F), (2, 0x33333333), (1, 0x55555555)):
+            v = (v | (v << np.uint64(shift))) & np.uint64(mask)
+        return v
+
+    return np.argsort(spread(q[:, 0]) | (spread(q[:, 1]) << np.uint64(1)), kind="stable")
+
+
+def delaunay(pts: np.ndarray, local_order: bool = False) -> np.ndarray:
+    """Delaunay triangles (Qhull) as an index array into ``pts``. ``local_order`` hands Qhull the points in Z-order
+    (same triangles for points in general position, faster for millions of points; the triangles come out in
+    another order)."""
     from scipy.spatial import Delaunay
-    return np.ascontiguousarray(Delaunay(pts).simplices.astype(np.int64))
+    if not local_order:
+        return np.ascontiguousarray(Delaunay(pts).simplices.astype(np.int64))
+    perm = _morton_order(pts)
+    return np.ascontiguousarray(perm[Delaunay(pts[perm]).simplices].astype(np.int64))
 
 
 def _lattice_corners(side: int, pts: np.ndarray):
@@ -248,9 +266,10 @@ def p1_assemble(pts: np.ndarray, tris: np.ndarray, kappa_t: np.ndarray | None = 
     keep = keep_v[rows] & keep_v[cols]
     r = newid[rows[keep]]; cc = newid[cols[keep]]; v = vals[keep]
     n = int(keep_v.sum())
-    order = np.lexsort((np.arange(len(r)), cc, r))
-    r, cc, v = r[order], cc[order], v[order]
+    # (row, column) pairs in ascending order, equal pairs kept in element order (a stable sort of the pair key)
     key = r * n + cc
+    order = np.argsort(key, kind="stable")
+    r, cc, v, key = r[order], cc[order], v[order], key[order]
     first = np.ones(len(key), dtype=bool)
     first[1:] = key[1:] != key[:-1]
     starts = np.nonzero(first)[0]
@@ -473,10 +492,15 @@ def lattice_system(side: int, seed: int = SEED_MESH, kappa_tiles: int = 0, devic
     return lattice_p1_assemble(side, pts, lattice_diagonals(side, pts), kappa_tiles)
 
 
-def graded_problem(target_n: int = 4_000_000, seed: int = SEED_MESH, rhs_seed: int = SEED_RHS) -> Problem:
-    """Poisson on a graded Delaunay mesh refined towards (0,0)."""
+def graded_problem(target_n: int = 4_000_000, seed: int = SEED_MESH, rhs_seed: int = SEED_RHS,
+                   progress=None) -> Problem:
+    """Poisson on a graded Delaunay mesh refined towards (0,0). ``progress(msg)`` is told when each stage ends (a
+    few million points take minutes on one core)."""
+    say = progress or (lambda msg: None)
     pts, c = graded_points(target_n, seed)
-    tris = delaunay(pts)
+    say(f"graded mesh: {len(pts)} points sampled")
+    tris = delaunay(pts, local_order=True)
+    say(f"graded mesh: {len(tris)} Delaunay triangles")
     return _problem(f"graded{target_n}", pts, tris, rhs_seed=rhs_seed, kind="graded", target_n=target_n, c=c,
                     seed=seed)
 

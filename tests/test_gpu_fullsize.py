@@ -34,7 +34,7 @@ def problem(name):
         t = time.time()
         _cache[name] = {"c2": lambda: mg.jittered_problem(1024),
                         "c4": lambda: mg.jittered_problem(1416, kappa_tiles=16),
-                        "c3": lambda: mg.graded_problem(4_000_000)}[name]()
+                        "c3": lambda: mg.graded_problem(4_000_000, progress=log)}[name]()
         log(f"{name}: n={_cache[name].n} generated in {time.time() - t:.1f}s")
     return _cache[name]
 
