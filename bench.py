@@ -44,6 +44,8 @@ WORKLOADS = {
              lambda mg: mg.disk_problem(1156)),
     "c5": ("serving stream: 512 Poisson-arrival requests, jittered-lattice P1 Poisson systems with DOF log-uniform in "
            "[1e4, 2e6], 30% repeat right-hand sides on a cached hierarchy", None),
+    "cube": ("octree variant: one implicit heat step (dt = h) on a jittered 101^3 lattice of the unit cube, P1 "
+             "tetrahedra, Dirichlet inlet face (1,020,100 DOF)", lambda mg: mg.cube_problem(100)),
 }
 ROOFLINE_KERNELS = {"engine32": "k_engine<float>", "spmv64": "k_outer_spmv_dot",
                     "resid_fine32": "k_fine_resid_full<float>", "gs_fine32": "k_fine_resid<float> (color phase)"}
@@ -353,43 +355,45 @@ def main():
     # coefficients (amg_p1_assemble), a values update of the resident hierarchy (amg_update_values) and a solve, in
     # the mixed form; kappa alternates between 1 + sin(2 pi x) sin(2 pi y) / 2 at the triangles' centroids and the
     # workload's own coefficients. The device assembly of the workload's coefficients is checked against its matrix.
-    mesh = prob.meta
-    dof = np.full(len(mesh["points"]), -1, dtype=np.int32)
-    dof[~mesh["dirichlet"]] = np.arange(prob.n, dtype=np.int32)
-    c0 = time.perf_counter()
-    pm = amg.P1Mesh(tt(mesh["points"], torch.float64), tt(mesh["tris"], torch.int32), tt(dof, torch.int32), prob.n,
-                    stream=stream)
-    pattern_ms = (time.perf_counter() - c0) * 1e3
-    prp, pcol = pm.pattern()
-    kap0 = None if mesh["kappa"] is None else tt(mesh["kappa"], torch.float64)
-    same = bool(torch.equal(prp, rp) and torch.equal(pcol, ci) and torch.equal(pm.assemble(kap0), va))
-    del prp, pcol
-    pts_, tri_ = mesh["points"], mesh["tris"]
-    cen = (pts_[tri_[:, 0]] + pts_[tri_[:, 1]] + pts_[tri_[:, 2]]) / 3.0
-    kap1 = tt(1.0 + 0.5 * np.sin(2 * np.pi * cen[:, 0]) * np.sin(2 * np.pi * cen[:, 1]), torch.float64)
-    vals = torch.empty_like(va)
-    h.set_precision(1)
-    asm, upd, step_ms, upd_iters = [], [], [], []
-    for k in range(args.repeats):
-        torch.cuda.synchronize()
-        s0 = time.perf_counter()
-        pm.assemble(kap1 if k % 2 == 0 else kap0, out=vals)
-        s1 = time.perf_counter()
-        h.update_values(rp, ci, vals)
-        s2 = time.perf_counter()
-        _, info = h.solve(b, tol=args.tol, x=x)
-        torch.cuda.synchronize()
-        asm.append((s1 - s0) * 1e3)
-        upd.append((s2 - s1) * 1e3)
-        step_ms.append((time.perf_counter() - s0) * 1e3)
-        upd_iters.append(info["iters"])
-    pm.close()
-    update = {"coefficients": "alternately 1 + sin(2 pi x) sin(2 pi y) / 2 at the centroids and the workload's own",
-              "device_assembly_equals_matrix": same, "pattern_ms": pattern_ms,
-              "assemble_ms_p50": float(np.median(asm)), "update_ms_p50": float(np.median(upd)),
-              "update_ms_p99": float(np.percentile(upd, 99)), "step_ms_p50": float(np.median(step_ms)),
-              "iters": sorted(set(upd_iters))}
-    log(f"values update: {update}")
+    update = None
+    if prob.coords.shape[1] == 2:  # device P1 assembly is for triangle meshes
+        mesh = prob.meta
+        dof = np.full(len(mesh["points"]), -1, dtype=np.int32)
+        dof[~mesh["dirichlet"]] = np.arange(prob.n, dtype=np.int32)
+        c0 = time.perf_counter()
+        pm = amg.P1Mesh(tt(mesh["points"], torch.float64), tt(mesh["tris"], torch.int32), tt(dof, torch.int32), prob.n,
+                        stream=stream)
+        pattern_ms = (time.perf_counter() - c0) * 1e3
+        prp, pcol = pm.pattern()
+        kap0 = None if mesh["kappa"] is None else tt(mesh["kappa"], torch.float64)
+        same = bool(torch.equal(prp, rp) and torch.equal(pcol, ci) and torch.equal(pm.assemble(kap0), va))
+        del prp, pcol
+        pts_, tri_ = mesh["points"], mesh["tris"]
+        cen = (pts_[tri_[:, 0]] + pts_[tri_[:, 1]] + pts_[tri_[:, 2]]) / 3.0
+        kap1 = tt(1.0 + 0.5 * np.sin(2 * np.pi * cen[:, 0]) * np.sin(2 * np.pi * cen[:, 1]), torch.float64)
+        vals = torch.empty_like(va)
+        h.set_precision(1)
+        asm, upd, step_ms, upd_iters = [], [], [], []
+        for k in range(args.repeats):
+            torch.cuda.synchronize()
+            s0 = time.perf_counter()
+            pm.assemble(kap1 if k % 2 == 0 else kap0, out=vals)
+            s1 = time.perf_counter()
+            h.update_values(rp, ci, vals)
+            s2 = time.perf_counter()
+            _, info = h.solve(b, tol=args.tol, x=x)
+            torch.cuda.synchronize()
+            asm.append((s1 - s0) * 1e3)
+            upd.append((s2 - s1) * 1e3)
+            step_ms.append((time.perf_counter() - s0) * 1e3)
+            upd_iters.append(info["iters"])
+        pm.close()
+        update = {"coefficients": "alternately 1 + sin(2 pi x) sin(2 pi y) / 2 at the centroids and the workload's own",
+                  "device_assembly_equals_matrix": same, "pattern_ms": pattern_ms,
+                  "assemble_ms_p50": float(np.median(asm)), "update_ms_p50": float(np.median(upd)),
+                  "update_ms_p99": float(np.percentile(upd, 99)), "step_ms_p50": float(np.median(step_ms)),
+                  "iters": sorted(set(upd_iters))}
+        log(f"values update: {update}")
     h.close()
 
     solve_ms = float(np.median([i["solve_ms"] for i in infos]))

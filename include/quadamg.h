@@ -48,10 +48,15 @@ typedef struct {
                             n <= coarse_max is solved directly (default 64) */
     int32_t inner_iters; /* steps n of Algorithm 2.1 inside the cycle: 1 or 2 (default 2, the K-cycle) */
     int32_t sweeps;      /* smoothing sweeps before and after the coarse correction (default 1) */
-    int32_t outer_mmax;  /* directions kept by the outer flexible CG: 0 or 1 (default 1) */
+    int32_t outer_mmax;  /* directions the outer flexible CG orthogonalises against (Algorithm 2.1, Step 2): 0 or 1
+                            (default 1: the last one); -1 every earlier direction since the start or the last
+                            restart, as Algorithm 2.1 is written (2 n doubles of device memory per iteration, made on
+                            first use and kept by the hierarchy) */
     int32_t max_iters;   /* outer iteration cap (default 1000) */
     int32_t engine;      /* 1 (default): the small coarse levels of the cycle run inside one persistent workgroup
-                            with LDS-resident operators; 0: one kernel launch per step on every level */
+                            with LDS-resident operators, specialised at compile time to the level shape where the
+                            levels allow it; 2: the same workgroup always through its generic step interpreter;
+                            0: one kernel launch per step on every level */
     int32_t batch;       /* 1 (default): amg_solve_batch runs this system, when it has at most 65,536 unknowns, as
                             one workgroup of a whole-solve launch shared with the batch's other small systems;
                             0: it runs as its own amg_solve */
@@ -63,6 +68,12 @@ typedef struct {
     const double *box;   /* host {a1, b1, a2, b2}: the auxiliary box of eq. (5); NULL = bounding box of coords
                             (eq. 6). Points outside a given box are rejected. */
     void *stream;        /* hipStream_t used for every launch; NULL = default stream */
+    void *(*alloc)(size_t bytes, void *ctx);  /* device allocator for all of the hierarchy's memory and its calls'
+                            temporaries (for example a framework's caching allocator); it returns device memory of
+                            the hierarchy's device usable on `stream`, or NULL on failure. NULL (default): the
+                            library's own stream-ordered pool and block cache. Set alloc and dealloc together. */
+    void (*dealloc)(void *ptr, void *ctx);    /* returns a block of alloc; called once the stream has drained */
+    void *ctx;           /* passed to alloc and dealloc */
 } amg_options;
 
 typedef struct {
@@ -86,6 +97,21 @@ void amg_default_options(amg_options *opt);
  * AMG_ERR_NOT_SPD, AMG_ERR_NOMEM, AMG_ERR_DEVICE. */
 amg_status amg_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
                      const double *vals, int64_t nnz, const amg_options *opt, amg_hierarchy **out);
+
+/* The octree variant (Sections 1 and 3.1: the region quadtree generalised to three dimensions) for an SPD system from
+ * a 3D discretisation: auxiliary box {a1, b1, a2, b2, a3, b3} (host; NULL = bounding box of coords), depth
+ * L = max{l : 8^l < n}, level-L aggregates by the cell index of Section 4.2 on each axis, coarse aggregates by
+ * octree parent (t1 >> 1, t2 >> 1, t3 >> 1), Galerkin operators with a 27-point pattern (the nine plane offsets of
+ * Section 4.4 at dz = 0, +1, -1, self first) plus an overflow list, an 8-coloring (t1 & 1) + 2 (t2 & 1) + 4 (t3 & 1)
+ * for the Gauss-Seidel smoother, and the same cycle and outer iteration as amg_setup. The coarsest level is the first
+ * k with 8^k <= coarse_max. coords: device, n x 3 interleaved (x, y, z). opt may be NULL; opt->box must be NULL (the
+ * box argument replaces it). Octree levels always run one kernel launch per step (options engine and batch have no
+ * effect). amg_solve, amg_apply_precond, amg_update_values, amg_export_level (27 slots per row, lexicographic id
+ * t1 + 2^k t2 + 4^k t3), amg_level_smooth, amg_level_spmv and amg_free take the hierarchy as for amg_setup. Errors
+ * as amg_setup. */
+amg_status amg_setup3d(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
+                       const double *vals, int64_t nnz, const double *box, const amg_options *opt,
+                       amg_hierarchy **out);
 
 /* Replace the matrix values of h with those of a new matrix on the same sparsity pattern and the same points (a
  * time step with changed coefficients, Example 2 of Section 5): the aggregates of Section 3 depend on the points and

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_PKG, "libquadamg.so")
 OK, INVALID, NOMEM, DEVICE, NOT_SPD, BREAKDOWN, NOCONV = range(7)
 STATUS = {0: "AMG_OK", 1: "AMG_ERR_INVALID", 2: "AMG_ERR_NOMEM", 3: "AMG_ERR_DEVICE", 4: "AMG_ERR_NOT_SPD",
           5: "AMG_ERR_BREAKDOWN", 6: "AMG_ERR_NOCONV"}
-EXPORTED = ["amg_default_options", "amg_setup", "amg_update_values", "amg_solve", "amg_free", "amg_set_precision", "amg_set_stream",
+EXPORTED = ["amg_default_options", "amg_setup", "amg_setup3d", "amg_update_values", "amg_solve", "amg_free", "amg_set_precision", "amg_set_stream",
             "amg_solve_batch", "amg_estimate_bytes", "amg_hierarchy_bytes", "amg_num_levels", "amg_level_info",
             "amg_export_level", "amg_export_level_f32", "amg_apply_precond", "amg_level_smooth", "amg_level_spmv",
             "amg_kernel_timing_enable", "amg_kernel_timing_read", "amg_engine_info", "amg_p1_mesh_create",
@@ -27,7 +27,44 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("coarse_max", C.c_int32), ("inner_iters", C.c_int32),
                 ("sweeps", C.c_int32), ("outer_mmax", C.c_int32), ("max_iters", C.c_int32),
                 ("engine", C.c_int32), ("batch", C.c_int32), ("smoother", C.c_int32), ("box", C.POINTER(C.c_double)),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("alloc", C.c_void_p), ("dealloc", C.c_void_p), ("ctx", C.c_void_p)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class TorchAllocator:
+    """amg_options.alloc / dealloc backed by torch's caching allocator: the hierarchy's device memory then comes from
+    (and returns to) the same cache as the caller's tensors, on the hierarchy's device and stream. The callback
+    objects must outlive every hierarchy set up with them (Hierarchy keeps a reference)."""
+
+    def __init__(self, device, stream=None):
+        import torch
+        self.device = torch.device(device).index or 0
+        self.stream = stream
+        self.live = 0  # blocks handed out and not yet returned
+
+        def _alloc(nbytes, _ctx):
+            try:
+                s = self.stream if self.stream is not None else torch.cuda.current_stream(self.device)
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device, s)
+                self.live += 1
+                return p
+            except Exception:
+                return None
+
+        def _dealloc(ptr, _ctx):
+            torch.cuda.caching_allocator_delete(ptr)
+            self.live -= 1
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._dealloc = DEALLOC_FN(_dealloc)
+
+    def install(self, o):
+        o.alloc = C.cast(self._alloc, C.c_void_p)
+        o.dealloc = C.cast(self._dealloc, C.c_void_p)
+        o.ctx = None
 
 
 class Info(C.Structure):
@@ -59,6 +96,7 @@ def load(path: str = LIB_PATH):
     L.amg_default_options.argtypes = [C.POINTER(Options)]
     L.amg_default_options.restype = None
     L.amg_setup.argtypes = [i64, p, p, p, p, i64, C.POINTER(Options), C.POINTER(p)]
+    L.amg_setup3d.argtypes = [i64, p, p, p, p, i64, C.POINTER(C.c_double), C.POINTER(Options), C.POINTER(p)]
     L.amg_update_values.argtypes = [p, p, p, p, i64]
     L.amg_solve.argtypes = [p, p, p, d, C.POINTER(Info)]
     L.amg_free.argtypes = [p]
@@ -138,11 +176,12 @@ def _stream_handle(stream):
 class Hierarchy:
     """Device-resident hierarchy built by amg_setup from device tensors.
 
-    coords: (n, 2) float64, row_ptr: (n+1,) int64, col: (nnz,) int32, val: (nnz,) float64, all on one CUDA device.
+    coords: (n, 2) float64 (quadtree, amg_setup) or (n, 3) float64 (octree, amg_setup3d; box = 6 values), row_ptr:
+    (n+1,) int64, col: (nnz,) int32, val: (nnz,) float64, all on one CUDA device.
     """
 
     def __init__(self, coords, row_ptr, col, val, box=None, precision=0, coarse_max=64, inner_iters=2, sweeps=1,
-                 outer_mmax=1, max_iters=1000, stream=None, engine=1, batch=1, smoother=0):
+                 outer_mmax=1, max_iters=1000, stream=None, engine=1, batch=1, smoother=0, allocator=None):
         import torch
         L = load()
         if not torch.cuda.is_available():
@@ -155,12 +194,27 @@ class Hierarchy:
         self.n = int(coords.shape[0])
         self.nnz = int(col.numel())
         self._stream = stream
-        o = _options(precision, coarse_max, inner_iters, sweeps, outer_mmax, max_iters, box,
+        dim = int(coords.shape[1])
+        if dim not in (2, 3):
+            raise TypeError("coords must be (n, 2) or (n, 3)")
+        self.dim = dim
+        o = _options(precision, coarse_max, inner_iters, sweeps, outer_mmax, max_iters, box if dim == 2 else None,
                      _stream_handle(stream), engine, batch, smoother)
+        # allocator: None = the library's pool; "torch" = torch's caching allocator; or a TorchAllocator
+        if allocator == "torch":
+            allocator = TorchAllocator(self.device, stream)
+        self._allocator = allocator
+        if allocator is not None:
+            allocator.install(o)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            _check(L.amg_setup(self.n, _ptr(coords), _ptr(row_ptr), _ptr(col), _ptr(val), self.nnz, C.byref(o),
-                               C.byref(h)), "amg_setup")
+            if dim == 3:  # the octree variant: the box (6 values) is an argument of its own
+                box6 = None if box is None else (C.c_double * 6)(*[float(v) for v in box])
+                _check(L.amg_setup3d(self.n, _ptr(coords), _ptr(row_ptr), _ptr(col), _ptr(val), self.nnz, box6,
+                                     C.byref(o), C.byref(h)), "amg_setup3d")
+            else:
+                _check(L.amg_setup(self.n, _ptr(coords), _ptr(row_ptr), _ptr(col), _ptr(val), self.nnz,
+                                   C.byref(o), C.byref(h)), "amg_setup")
         self._h = h
         lv = C.c_int32()
         _check(L.amg_num_levels(h, C.byref(lv)), "amg_num_levels")
@@ -263,15 +317,16 @@ class Hierarchy:
             _check(L.amg_export_level(self._h, 0, p(out["agg"]), p(out["color"]), None, None, None, None, None),
                    "amg_export_level")
             return out
-        out["aj"] = np.empty((n, 9), dtype=np.int32)
-        out["ax"] = np.empty((n, 9), dtype=np.float64)
+        ns = 27 if getattr(self, "dim", 2) == 3 else 9
+        out["aj"] = np.empty((n, ns), dtype=np.int32)
+        out["ax"] = np.empty((n, ns), dtype=np.float64)
         out["ovf_ptr"] = np.empty(n + 1, dtype=np.int64)
         out["ovf_col"] = np.empty(info["ovf_nnz"], dtype=np.int32)
         out["ovf_val"] = np.empty(info["ovf_nnz"], dtype=np.float64)
         _check(L.amg_export_level(self._h, level, *[p(out[k]) for k in ("agg", "color", "aj", "ax", "ovf_ptr",
                                                                        "ovf_col", "ovf_val")]), "amg_export_level")
         if f32:
-            out["ax32"] = np.empty((n, 9), dtype=np.float32)
+            out["ax32"] = np.empty((n, ns), dtype=np.float32)
             _check(L.amg_export_level_f32(self._h, level, p(out["ax32"])), "amg_export_level_f32")
         return out
 

@@ -25,6 +25,7 @@ SOURCES = {
     # the cell index must be the plain IEEE sequence and the Galerkin sums plain additions
     "qa_setup.hip": ["-ffp-contract=off"],
     "qa_solve.hip": [],
+    "qa_engine.hip": [],
     # element entries and their sums in a fixed IEEE order
     "qa_assemble.hip": ["-ffp-contract=off"],
 }

@@ -74,9 +74,14 @@ static void flush_cache(int device) {
     blocks.swap(g_cache[device]);
     g_cache_bytes[device] = 0;
   }
-  const bool pooled = pool_for(device) != nullptr;  // then every block came from the device's pool
+  hipMemPool_t pool = pool_for(device);
+  const bool pooled = pool != nullptr;  // then every block came from the device's pool
   for (const CachedBlock &b : blocks) (void)(pooled ? hipFreeAsync(b.p, nullptr) : hipFree(b.p));
-  if (pooled && !blocks.empty()) (void)hipStreamSynchronize(nullptr);
+  if (pooled) {
+    (void)hipStreamSynchronize(nullptr);
+    // the pool keeps what it was given back (its release threshold is unlimited); hand it to the driver now
+    (void)hipMemPoolTrimTo(pool, 0);
+  }
 }
 
 static void *fresh_block(amg_hierarchy *h, size_t bytes) {
@@ -91,6 +96,14 @@ static void *fresh_block(amg_hierarchy *h, size_t bytes) {
 }
 
 static void *raw_alloc(amg_hierarchy *h, size_t bytes) {
+  if (h->opt.alloc) {  // the caller's device allocator: no cache, no pool
+    void *p = h->opt.alloc(bytes, h->opt.ctx);
+    if (!p) return nullptr;
+    h->allocs.push_back(p);
+    h->alloc_sizes.push_back(bytes);
+    h->bytes += bytes;
+    return p;
+  }
   void *p = cached_block(h->device, bytes);
   if (!p) p = fresh_block(h, bytes);
   if (!p && h->device >= 0 && h->device < 64) {
@@ -124,15 +137,49 @@ void *dalloc(amg_hierarchy *h, size_t bytes) {
   return base;
 }
 
+// give one of h's blocks back: to the caller's allocator, the block cache, or the pool / driver; true when it went to
+// the pool or the driver (the caller then synchronises the stream)
+static bool give_back(amg_hierarchy *h, void *p, size_t bytes, bool pooled) {
+  if (h->opt.dealloc) {
+    h->opt.dealloc(p, h->opt.ctx);
+    return false;
+  }
+  if (cache_block(h->device, p, bytes)) return false;
+  (void)(pooled ? hipFreeAsync(p, h->stream) : hipFree(p));
+  return true;
+}
+
+void *tmp_alloc(amg_hierarchy *h, hipStream_t s, size_t bytes) {
+  void *p = nullptr;
+  if (h && h->opt.alloc) return h->opt.alloc(bytes, h->opt.ctx);
+  hipMemPool_t pool = h ? pool_for(h->device) : nullptr;
+  if (pool) {
+    if (hipMallocFromPoolAsync(&p, bytes, pool, s) != hipSuccess) {
+      (void)hipGetLastError();
+      flush_cache(h->device);
+      p = nullptr;
+      if (hipMallocFromPoolAsync(&p, bytes, pool, s) != hipSuccess) return nullptr;
+    }
+    return p;
+  }
+  return hipMallocAsync(&p, bytes, s) == hipSuccess ? p : nullptr;
+}
+
+void tmp_free(amg_hierarchy *h, hipStream_t s, void *p) {
+  if (!p) return;
+  if (h && h->opt.dealloc) {
+    (void)hipStreamSynchronize(s);  // the temporary's last reader has finished before the caller reuses it
+    h->opt.dealloc(p, h->opt.ctx);
+    return;
+  }
+  (void)hipFreeAsync(p, s);
+}
+
 amg_status release(amg_hierarchy *h) {
   const bool pooled = pool_for(h->device) != nullptr;
   (void)hipStreamSynchronize(h->stream);  // the hierarchy's work has drained: its blocks are idle
   bool freed = false;
-  for (size_t i = 0; i < h->allocs.size(); i++) {
-    if (cache_block(h->device, h->allocs[i], h->alloc_sizes[i])) continue;
-    (void)(pooled ? hipFreeAsync(h->allocs[i], h->stream) : hipFree(h->allocs[i]));
-    freed = true;
-  }
+  for (size_t i = 0; i < h->allocs.size(); i++) freed |= give_back(h, h->allocs[i], h->alloc_sizes[i], pooled);
   if (pooled && freed) (void)hipStreamSynchronize(h->stream);
   h->allocs.clear();
   h->alloc_sizes.clear();
@@ -154,11 +201,9 @@ ArenaMark arena_mark(const amg_hierarchy *h) {
 void arena_rollback(amg_hierarchy *h, const ArenaMark &m) {
   (void)hipStreamSynchronize(h->stream);  // the temporaries' last readers have finished
   const bool pooled = pool_for(h->device) != nullptr;
-  for (size_t i = m.allocs; i < h->allocs.size(); i++) {
-    if (cache_block(h->device, h->allocs[i], h->alloc_sizes[i])) continue;
-    (void)(pooled ? hipFreeAsync(h->allocs[i], h->stream) : hipFree(h->allocs[i]));
-  }
-  if (pooled) (void)hipStreamSynchronize(h->stream);
+  bool freed = false;
+  for (size_t i = m.allocs; i < h->allocs.size(); i++) freed |= give_back(h, h->allocs[i], h->alloc_sizes[i], pooled);
+  if (pooled && freed) (void)hipStreamSynchronize(h->stream);
   h->allocs.resize(m.allocs);
   h->alloc_sizes.resize(m.allocs);
   h->bytes = m.bytes;
@@ -277,22 +322,24 @@ static amg_status scan_impl(const T *in, T *out, int64_t n, hipStream_t s, amg_h
     return AMG_OK;
   }
   const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
-  T *bsum = nullptr;
-  QA_HIP(hipMallocAsync(reinterpret_cast<void **>(&bsum), sizeof(T) * (2 * nb + 2), s));
+  T *bsum = static_cast<T *>(tmp_alloc(h, s, sizeof(T) * (2 * nb + 2)));
+  if (!bsum) return AMG_ERR_NOMEM;
   T *bsum_ex = bsum + nb;
+  amg_status st = AMG_OK;
   k_scan_block<T><<<nb, kBlock, 0, s>>>(in, out, bsum, n);
-  QA_LAUNCH_CHECK();
-  if (nb == 1) {
+  if (hipGetLastError() != hipSuccess) st = AMG_ERR_DEVICE;
+  if (st == AMG_OK && nb == 1) {
     k_scan_single_tail<T><<<1, 1, 0, s>>>(out, bsum, n);
-    QA_LAUNCH_CHECK();
-  } else {
-    amg_status st = scan_impl<T>(bsum, bsum_ex, nb, s, h);
-    if (st != AMG_OK) return st;
-    k_scan_add<T><<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(out, bsum_ex, n);
-    QA_LAUNCH_CHECK();
+    if (hipGetLastError() != hipSuccess) st = AMG_ERR_DEVICE;
+  } else if (st == AMG_OK) {
+    st = scan_impl<T>(bsum, bsum_ex, nb, s, h);
+    if (st == AMG_OK) {
+      k_scan_add<T><<<(n + kBlock - 1) / kBlock, kBlock, 0, s>>>(out, bsum_ex, n);
+      if (hipGetLastError() != hipSuccess) st = AMG_ERR_DEVICE;
+    }
   }
-  QA_HIP(hipFreeAsync(bsum, s));
-  return AMG_OK;
+  tmp_free(h, s, bsum);  // on every path
+  return st;
 }
 
 amg_status scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s, amg_hierarchy *h) {
@@ -319,6 +366,9 @@ void amg_default_options(amg_options *opt) {
   opt->smoother = 0;
   opt->box = nullptr;
   opt->stream = nullptr;
+  opt->alloc = nullptr;
+  opt->dealloc = nullptr;
+  opt->ctx = nullptr;
 }
 
 const char *amg_status_string(amg_status s) {

@@ -26,6 +26,7 @@ constexpr int kRedBlocksMax = 1024;
 constexpr int kBlockMax = 32;      // exact-block smoother: cells of at most this many unknowns are factored
 constexpr int kBigCell = 10;        // cells with more unknowns get a level-scheduled in-cell substitution
 constexpr int kScalars = 16;       // device scalars per level
+constexpr int kMaxColors = 8;      // colors of the smoother: 4 on a quadtree, 8 on an octree
 
 // ---------------------------------------------------------------------------------------------------------------
 // Morton / color-major index helpers (k <= 15)
@@ -106,12 +107,59 @@ __host__ __device__ inline void stencil_q(uint32_t q, uint32_t j, int c, int sh,
 }
 
 // ---------------------------------------------------------------------------------------------------------------
+// Octree (3D) levels. A cell (t1, t2, t3) of level k has Morton key m = interleave(t1 -> bits 0, 3, 6, ...,
+// t2 -> bits 1, 4, ..., t3 -> bits 2, 5, ...) and storage index q = (m & 7) 8^(k-1) + (m >> 3): the low three key
+// bits are its color (t1 & 1) + 2 (t2 & 1) + 4 (t3 & 1) of the 8-coloring, so every color is one contiguous eighth,
+// and the eight children of a level-(k-1) cell M sit at q = c 8^(k-1) + M. The 27 coarse slots are the nine plane
+// offsets of Section 4.4 (self, E, NE, N, NW, W, SW, S, SE) at dz = 0, then at dz = +1, then at dz = -1 (k <= 10).
+
+__host__ __device__ inline uint32_t spread3(uint32_t v) {
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+__host__ __device__ inline uint32_t compact3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030C30C3u;
+  v = (v | (v >> 4)) & 0x0300F00Fu;
+  v = (v | (v >> 8)) & 0x030000FFu;
+  v = (v | (v >> 16)) & 0x000003FFu;
+  return v;
+}
+__host__ __device__ inline uint32_t morton3(uint32_t t1, uint32_t t2, uint32_t t3) {
+  return spread3(t1) | (spread3(t2) << 1) | (spread3(t3) << 2);
+}
+__host__ __device__ inline uint32_t q_of_m3(uint32_t m, int k) {
+  return k == 0 ? 0u : (((m & 7u) << (3 * k - 3)) | (m >> 3));
+}
+__host__ __device__ inline uint32_t m_of_q3(uint32_t q, int k) {
+  return k == 0 ? 0u : (((q & ((1u << (3 * k - 3)) - 1u)) << 3) | (q >> (3 * k - 3)));
+}
+__host__ __device__ inline int slot3_dx(int t) { return slot_dx(t % 9); }
+__host__ __device__ inline int slot3_dy(int t) { return slot_dy(t % 9); }
+__host__ __device__ inline int slot3_dz(int t) { return t < 9 ? 0 : (t < 18 ? 1 : -1); }
+// slot of offset (dx, dy, dz), each in [-1, 1]
+__host__ __device__ inline int slot3_of(int dx, int dy, int dz) {
+  return (dz == 0 ? 0 : (dz > 0 ? 9 : 18)) + slot_of(dx, dy);
+}
+// order in which the children of a cell are summed: the 2D restriction order (0, 1, 3, 2) on the layer 2 T3, then on
+// the layer 2 T3 + 1
+__host__ __device__ inline int child3_order(int i) {
+  const int o2[4] = {0, 1, 3, 2};
+  return o2[i & 3] | (i & 4);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
 // hierarchy
 
-struct QuadLevel {              // quadtree level k, color-major numbering
+struct QuadLevel {              // quadtree (octree in 3D) level k, color-major numbering
   int k = 0;
-  int64_t n = 0;                // 4^k
-  double *ax64 = nullptr;       // 9 x n, slot-major: ax[s * n + q]
+  int64_t n = 0;                // 4^k (8^k)
+  int ns = 9;                   // slots per row: 9, or 27 on an octree level
+  double *ax64 = nullptr;       // ns x n, slot-major: ax[s * n + q]
   float *ax32 = nullptr;
   uint8_t *empty = nullptr;     // 1 = aggregate without fine unknowns (identity row)
   int64_t ovf_nnz = 0;          // couplings beyond one cell: CSR over rows q, columns q, sorted by lexicographic id
@@ -139,8 +187,9 @@ struct FineLevel {
   double *s_val64 = nullptr;
   float *s_val32 = nullptr;
   int64_t sell_entries = 0;
-  int64_t color_row[5] = {0, 0, 0, 0, 0};
-  int64_t color_slice[5] = {0, 0, 0, 0, 0};
+  int ncolor = 4;               // 2^dim colors; each is a contiguous range of cells and rows
+  int64_t color_row[kMaxColors + 1] = {};
+  int64_t color_slice[kMaxColors + 1] = {};
   double *diag64 = nullptr;
   float *diag32 = nullptr;
   // couplings inside a cell (off-diagonal), caller's entry order, for the in-cell substitution
@@ -154,7 +203,7 @@ struct FineLevel {
   // cells of more than kBigCell unknowns: their in-cell substitution runs level by level (rows on one level of the
   // substitution's dependency graph are independent), one workgroup per cell; [0] forward, [1] backward
   int64_t nbig = 0;
-  int64_t big_color[5] = {0, 0, 0, 0, 0};       // first big cell of each color (big cells ascend by cell id)
+  int64_t big_color[kMaxColors + 1] = {};      // first big cell of each color (big cells ascend by cell id)
   int32_t *big_cells = nullptr;                 // cell ids
   int32_t *big_lofs[2] = {nullptr, nullptr};    // per big cell, its first entry in big_lptr (nbig + 1)
   int32_t *big_lptr[2] = {nullptr, nullptr};    // level starts as row positions, then the cell's end
@@ -194,9 +243,10 @@ struct Chunk {                  // a device allocation that several arrays are c
 
 struct amg_hierarchy {
   int device = 0;
+  int dim = 2;                          // 2: quadtree levels (4^k cells); 3: octree levels (8^k cells)
   hipStream_t stream = nullptr;
   amg_options opt{};
-  double box[4] = {0, 0, 0, 0};
+  double box[6] = {0, 0, 0, 0, 0, 0};   // {a1, b1, a2, b2[, a3, b3]}
   int64_t n = 0;
   int L = -1, kc = -1, nlev = 1;
   int precision = 0;
@@ -233,7 +283,11 @@ struct amg_hierarchy {
   int64_t engine_global_rows = 4096;  // a top level this small may run from global memory
   size_t engine_lds[2] = {0, 0};
   size_t lds_max = 0;
-  int use_engine = 1;
+  int use_engine = 1;                 // 0 off, 1 on (specialised engine where eligible), 2 the step interpreter only
+  // specialised engine (qa_engine.hip): configuration id per precision (-1 = the interpreter), its step list
+  int fe_cfg[2] = {-1, -1};
+  void *fe_ops[2] = {nullptr, nullptr};
+  int fe_nops[2] = {0, 0};
   int use_batch = 1;
   // whole-solve workgroup (batched serving of small systems), per precision
   void *wg_ops[2] = {nullptr, nullptr};
@@ -241,6 +295,12 @@ struct amg_hierarchy {
   int wg_lds_top[2] = {-1, -1};
   int wg_ainv_lds[2] = {0, 0};
   size_t wg_lds[2] = {0, 0};
+  // all-directions outer iteration (outer_mmax < 0): kept directions p_j, q_j = A p_j, their device address table,
+  // the inner products (z, q_j) of the current step and (p_j, q_j)
+  std::vector<double *> dir_p, dir_q;
+  double **dir_pp = nullptr;
+  double *dir_zq = nullptr;
+  double *dir_d = nullptr;
   // B^ of the level above the coarsest as an explicit matrix (column-major, FP64 and FP32), or none
   int mhat_level = -1;
   int64_t mhat_n = 0;
@@ -260,6 +320,10 @@ T *dalloc_n(amg_hierarchy *h, int64_t count) {
 amg_status scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s, amg_hierarchy *h);
 amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s, amg_hierarchy *h);
 amg_status release(amg_hierarchy *h);
+// temporary device memory of one call on h (the caller's allocator when one is set, else the library's pool on
+// stream s); tmp_free returns it on s
+void *tmp_alloc(amg_hierarchy *h, hipStream_t s, size_t bytes);
+void tmp_free(amg_hierarchy *h, hipStream_t s, void *p);
 // the allocation state of a hierarchy, and the return to it: arrays allocated after the mark go back to the
 // chunks' free tails or to the block cache (the stream is synchronised first)
 struct ArenaMark {
@@ -279,6 +343,8 @@ amg_status alloc_workspaces(amg_hierarchy *h);
 amg_status build_mhat(amg_hierarchy *h);
 amg_status plan_engine(amg_hierarchy *h);
 amg_status plan_wg(amg_hierarchy *h);
+amg_status plan_engine_fast(amg_hierarchy *h);   // qa_engine.hip
+void launch_engine_fast(amg_hierarchy *h, int precision);
 amg_status precond_apply(amg_hierarchy *h, int precision, const double *r_p, double *z_p);
 amg_status level_smooth_internal(amg_hierarchy *h, int level, const double *f, double *x, int forward, int prec);
 amg_status level_spmv_internal(amg_hierarchy *h, int level, const double *x, double *y, int prec);

@@ -22,6 +22,10 @@ namespace qa {
 
 enum { F_INVALID = 1, F_NOT_SPD = 2, F_SAMECOLOR = 4 };
 
+struct Box3 {  // {a1, b1, a2, b2, a3, b3} of an octree's auxiliary box
+  double v[6];
+};
+
 __device__ inline void q_to_t(uint32_t q, int k, uint32_t &t1, uint32_t &t2) {
   const uint32_t m = m_of_q(q, k);
   t1 = compact_bits(m);
@@ -246,16 +250,10 @@ __global__ void __launch_bounds__(kBlock) k_row_diag(int64_t n, const int64_t *_
 // sliced ELL of the fine level
 
 struct Regions {
-  int64_t row[5];
-  int64_t slice[5];
+  int nc;                        // colors
+  int64_t row[kMaxColors + 1];
+  int64_t slice[kMaxColors + 1];
 };
-
-__device__ inline int region_of_row(const Regions &R, int64_t p) {
-  return (p >= R.row[1]) + (p >= R.row[2]) + (p >= R.row[3]);
-}
-__device__ inline int region_of_slice(const Regions &R, int64_t s) {
-  return (s >= R.slice[1]) + (s >= R.slice[2]) + (s >= R.slice[3]);
-}
 
 // Rows of each window of kSellWindow positions inside a color region, sorted by length (longest first, ascending
 // row among equal lengths), so that the four 64-row slices of a window hold rows of similar length and the padding
@@ -286,12 +284,12 @@ __global__ void __launch_bounds__(kBlock) k_slice_meta(Regions R, int64_t nslice
   const int lane = threadIdx.x & 63;
   if (s > nslices) return;
   if (s == nslices) {
-    if (lane == 0) row0[s] = static_cast<int32_t>(R.row[4]);
+    if (lane == 0) row0[s] = static_cast<int32_t>(R.row[R.nc]);
     return;
   }
   // empty regions own no slices, so the region of s is found among the non-empty ones
   int c = 0;
-  while (c < 3 && s >= R.slice[c + 1]) c++;
+  while (c < R.nc - 1 && s >= R.slice[c + 1]) c++;
   const int64_t r0 = R.row[c] + (s - R.slice[c]) * kSliceRows;
   const int64_t r1 = min(r0 + kSliceRows, R.row[c + 1]);
   int w = 1;
@@ -318,7 +316,7 @@ __global__ void __launch_bounds__(kBlock) k_fill_sell(Regions R, int64_t n, cons
   if (pos >= n) return;
   const int64_t p = s_row[pos];  // the row at this position
   int c = 0;
-  while (c < 3 && pos >= R.row[c + 1]) c++;
+  while (c < R.nc - 1 && pos >= R.row[c + 1]) c++;
   const int64_t rel = pos - R.row[c];
   const int64_t s = R.slice[c] + rel / kSliceRows;
   const int lane = static_cast<int>(rel % kSliceRows);
@@ -670,6 +668,334 @@ __global__ void __launch_bounds__(kBlock) k_galerkin_coarse_ovf(CoarseSrc F, con
 }
 
 // ---------------------------------------------------------------------------------------------------------------
+// Octree (3D) variant of the setup kernels: the same steps with three coordinates, 8^k cells, 8 children and 27
+// slots (the numbering and slot order are those of qa_internal.hpp). Sums are taken in the order of the 2D kernels:
+// cells in order, a cell's rows ascending and each row's entries in the caller's order; below level L the children
+// in child3_order, each child's 27 slots in order, then its overflow entries.
+
+__device__ inline void q_to_t3(uint32_t q, int k, uint32_t &t1, uint32_t &t2, uint32_t &t3) {
+  const uint32_t m = m_of_q3(q, k);
+  t1 = compact3(m);
+  t2 = compact3(m >> 1);
+  t3 = compact3(m >> 2);
+}
+
+__device__ inline uint32_t lex_of_q3(uint32_t q, int k) {
+  uint32_t t1, t2, t3;
+  q_to_t3(q, k, t1, t2, t3);
+  return (((t3 << k) | t2) << k) | t1;
+}
+
+__device__ inline void add_slot27(double (&acc)[27], int s, double v) {
+#pragma unroll
+  for (int j = 0; j < 27; j++) acc[j] += (j == s) ? v : 0.0;
+}
+
+__device__ inline void sort_ovf_row3(int32_t *col, double *val, int32_t a, int32_t b, int k) {
+  for (int32_t i = a + 1; i < b; i++) {
+    const int32_t c = col[i];
+    const double v = val[i];
+    const uint32_t lc = lex_of_q3(static_cast<uint32_t>(c), k);
+    int32_t j = i - 1;
+    while (j >= a && lex_of_q3(static_cast<uint32_t>(col[j]), k) > lc) {
+      col[j + 1] = col[j];
+      val[j + 1] = val[j];
+      j--;
+    }
+    col[j + 1] = c;
+    val[j + 1] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_validate3(int64_t n, int64_t nnz, const double *__restrict__ coords,
+                                                       const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                       const double *__restrict__ va, int has_box, Box3 B,
+                                                       int *flag) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int f = 0;
+  const int64_t r0 = rp[i], r1 = rp[i + 1];
+  if (i == 0 && r0 != 0) f |= F_INVALID;
+  if (i == n - 1 && r1 != nnz) f |= F_INVALID;
+  if (r1 < r0 || r0 < 0 || r1 > nnz) f |= F_INVALID;
+  for (int a = 0; a < 3; a++) {
+    const double v = coords[3 * i + a];
+    if (!isfinite(v)) f |= F_INVALID;
+    else if (has_box && (v < B.v[2 * a] || v > B.v[2 * a + 1])) f |= F_INVALID;
+  }
+  if (!(f & F_INVALID)) {
+    double dg = 0.0;
+    for (int64_t e = r0; e < r1; e++) {
+      const int32_t c = ci[e];
+      if (c < 0 || c >= n) f |= F_INVALID;
+      else if (c == i) dg += va[e];
+    }
+    if (!(dg > 0.0)) f |= F_NOT_SPD;
+  }
+  if (f) atomicOr(flag, f);
+}
+
+// bounding box of 3D points: per-workgroup min / max of each coordinate, then one workgroup over those
+__global__ void __launch_bounds__(kBlock) k_bbox3_partial(int64_t n, const double *__restrict__ coords,
+                                                           double *__restrict__ part) {
+  double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; i < n;
+       i += static_cast<int64_t>(gridDim.x) * kBlock)
+    for (int a = 0; a < 3; a++) {
+      mn[a] = fmin(mn[a], coords[3 * i + a]);
+      mx[a] = fmax(mx[a], coords[3 * i + a]);
+    }
+  __shared__ double sm[6][kBlock];
+  for (int a = 0; a < 3; a++) {
+    sm[2 * a][threadIdx.x] = mn[a];
+    sm[2 * a + 1][threadIdx.x] = mx[a];
+  }
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int a = 0; a < 3; a++) {
+        sm[2 * a][threadIdx.x] = fmin(sm[2 * a][threadIdx.x], sm[2 * a][threadIdx.x + off]);
+        sm[2 * a + 1][threadIdx.x] = fmax(sm[2 * a + 1][threadIdx.x], sm[2 * a + 1][threadIdx.x + off]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int t = 0; t < 6; t++) part[blockIdx.x * 6 + t] = sm[t][0];
+}
+
+__global__ void k_bbox3_final(int nb, const double *__restrict__ part, double *__restrict__ box) {
+  double b[6] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY};
+  for (int i = 0; i < nb; i++)
+    for (int a = 0; a < 3; a++) {
+      b[2 * a] = fmin(b[2 * a], part[6 * i + 2 * a]);
+      b[2 * a + 1] = fmax(b[2 * a + 1], part[6 * i + 2 * a + 1]);
+    }
+  for (int t = 0; t < 6; t++) box[t] = b[t];
+}
+
+// level-L cell of each unknown (the index formula of Section 4.2 on each of the three axes), as a color-major octree
+// index, with its count
+__global__ void __launch_bounds__(kBlock) k_cell_key3(int64_t n, const double *__restrict__ coords, Box3 B, int L,
+                                                       int32_t *__restrict__ key, int32_t *__restrict__ cnt) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t t1 = axis_cell(coords[3 * i], B.v[0], B.v[1], L);
+  const uint32_t t2 = axis_cell(coords[3 * i + 1], B.v[2], B.v[3], L);
+  const uint32_t t3 = axis_cell(coords[3 * i + 2], B.v[4], B.v[5], L);
+  const uint32_t q = q_of_m3(morton3(t1, t2, t3), L);
+  key[i] = static_cast<int32_t>(q);
+  atomicAdd(&cnt[q], 1);
+}
+
+// fine -> level L on an octree: one thread per cell, its rows' entries in order, 27 slots, far couplings counted
+__global__ void __launch_bounds__(kBlock) k_galerkin_fine3(int L, int64_t nL, const int32_t *__restrict__ crow,
+                                                            const int64_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ ci,
+                                                            const double *__restrict__ va,
+                                                            const int32_t *__restrict__ agg_q,
+                                                            double *__restrict__ ax, uint8_t *__restrict__ empty,
+                                                            int32_t *__restrict__ ovf_cnt, int *flag) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nL) return;
+  uint32_t t1, t2, t3;
+  q_to_t3(static_cast<uint32_t>(q), L, t1, t2, t3);
+  const int64_t e0 = rp[crow[q]], e1 = rp[crow[q + 1]];
+  double acc[27];
+#pragma unroll
+  for (int j = 0; j < 27; j++) acc[j] = 0.0;
+  int32_t cnt = 0;
+  for (int64_t e = e0; e < e1; e++) {
+    const uint32_t qq = static_cast<uint32_t>(agg_q[ci[e]]);
+    uint32_t u1, u2, u3;
+    q_to_t3(qq, L, u1, u2, u3);
+    const int dx = static_cast<int>(u1) - static_cast<int>(t1), dy = static_cast<int>(u2) - static_cast<int>(t2),
+              dz = static_cast<int>(u3) - static_cast<int>(t3);
+    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) {
+      add_slot27(acc, slot3_of(dx, dy, dz), va[e]);
+    } else {
+      bool first = true;
+      for (int64_t e2 = e0; e2 < e; e2++)
+        if (static_cast<uint32_t>(agg_q[ci[e2]]) == qq) { first = false; break; }
+      cnt += first;
+    }
+  }
+  const bool emp = (crow[q] == crow[q + 1]);
+  empty[q] = emp ? 1 : 0;
+  if (emp) acc[0] = 1.0;
+#pragma unroll
+  for (int j = 0; j < 27; j++) ax[j * nL + q] = acc[j];
+  ovf_cnt[q] = cnt;
+  if (!emp && !(acc[0] > 0.0)) atomicOr(flag, F_NOT_SPD);
+}
+
+__global__ void __launch_bounds__(kBlock) k_galerkin_fine3_ovf(int L, int64_t nL, const int32_t *__restrict__ crow,
+                                                                const int64_t *__restrict__ rp,
+                                                                const int32_t *__restrict__ ci,
+                                                                const double *__restrict__ va,
+                                                                const int32_t *__restrict__ agg_q,
+                                                                const int32_t *__restrict__ optr,
+                                                                int32_t *__restrict__ ocol, double *__restrict__ oval,
+                                                                int *flag) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nL) return;
+  int32_t o = optr[q];
+  if (optr[q + 1] == o) return;
+  uint32_t t1, t2, t3;
+  q_to_t3(static_cast<uint32_t>(q), L, t1, t2, t3);
+  const int64_t e0 = rp[crow[q]], e1 = rp[crow[q + 1]];
+  const uint32_t my_color = static_cast<uint32_t>(q) >> (3 * L - 3);
+  for (int64_t e = e0; e < e1; e++) {
+    const uint32_t qq = static_cast<uint32_t>(agg_q[ci[e]]);
+    uint32_t u1, u2, u3;
+    q_to_t3(qq, L, u1, u2, u3);
+    const int dx = static_cast<int>(u1) - static_cast<int>(t1), dy = static_cast<int>(u2) - static_cast<int>(t2),
+              dz = static_cast<int>(u3) - static_cast<int>(t3);
+    if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
+    bool first = true;
+    for (int64_t e2 = e0; e2 < e; e2++)
+      if (static_cast<uint32_t>(agg_q[ci[e2]]) == qq) { first = false; break; }
+    if (!first) continue;
+    double sum = 0.0;
+    for (int64_t e2 = e; e2 < e1; e2++)
+      if (static_cast<uint32_t>(agg_q[ci[e2]]) == qq) sum += va[e2];
+    ocol[o] = static_cast<int32_t>(qq);
+    oval[o] = sum;
+    o++;
+    if ((qq >> (3 * L - 3)) == my_color) atomicOr(flag, F_SAMECOLOR);
+  }
+  sort_ovf_row3(ocol, oval, optr[q], optr[q + 1], L);
+}
+
+// level k -> level k-1 on an octree: one thread per coarse cell M (Morton at level k-1), its 8 children in
+// child3_order, each child's 27 slots then its overflow entries
+__global__ void __launch_bounds__(kBlock) k_galerkin_coarse3(CoarseSrc F, double *__restrict__ ax,
+                                                              uint8_t *__restrict__ empty,
+                                                              int32_t *__restrict__ ovf_cnt, int *flag) {
+  const int kc = F.k - 1;
+  const int64_t nc = F.n >> 3;
+  const int64_t M = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (M >= nc) return;
+  const uint32_t Mu = static_cast<uint32_t>(M);
+  const int T1 = static_cast<int>(compact3(Mu)), T2 = static_cast<int>(compact3(Mu >> 1)),
+            T3 = static_cast<int>(compact3(Mu >> 2));
+  const int side = 1 << F.k;
+  double acc[27];
+#pragma unroll
+  for (int j = 0; j < 27; j++) acc[j] = 0.0;
+  int32_t cnt = 0;
+  bool all_empty = true;
+  for (int oi = 0; oi < 8; oi++) {
+    const int c = child3_order(oi);
+    const int64_t q = c * nc + M;
+    if (F.empty[q]) continue;
+    all_empty = false;
+    const uint32_t m = (Mu << 3) | static_cast<uint32_t>(c);
+    const int t1 = static_cast<int>(compact3(m)), t2 = static_cast<int>(compact3(m >> 1)),
+              t3 = static_cast<int>(compact3(m >> 2));
+    for (int s = 0; s < 27; s++) {
+      const int u1 = t1 + slot3_dx(s), u2 = t2 + slot3_dy(s), u3 = t3 + slot3_dz(s);
+      if (u1 < 0 || u2 < 0 || u3 < 0 || u1 >= side || u2 >= side || u3 >= side) continue;
+      add_slot27(acc, slot3_of((u1 >> 1) - T1, (u2 >> 1) - T2, (u3 >> 1) - T3), F.ax[s * F.n + q]);
+    }
+    if (F.optr)
+      for (int32_t e = F.optr[q]; e < F.optr[q + 1]; e++) {
+        const uint32_t P = m_of_q3(static_cast<uint32_t>(F.ocol[e]), F.k) >> 3;
+        const int dX = static_cast<int>(compact3(P)) - T1, dY = static_cast<int>(compact3(P >> 1)) - T2,
+                  dZ = static_cast<int>(compact3(P >> 2)) - T3;
+        if (dX >= -1 && dX <= 1 && dY >= -1 && dY <= 1 && dZ >= -1 && dZ <= 1) {
+          add_slot27(acc, slot3_of(dX, dY, dZ), F.oval[e]);
+        } else {
+          bool first = true;
+          for (int oj = 0; oj <= oi && first; oj++) {
+            const int64_t qj = child3_order(oj) * nc + M;
+            if (F.empty[qj]) continue;
+            const int32_t eend = (oj == oi) ? e : F.optr[qj + 1];
+            for (int32_t e2 = F.optr[qj]; e2 < eend; e2++)
+              if ((m_of_q3(static_cast<uint32_t>(F.ocol[e2]), F.k) >> 3) == P) { first = false; break; }
+          }
+          cnt += first;
+        }
+      }
+  }
+  const uint32_t qc = q_of_m3(Mu, kc);
+  empty[qc] = all_empty ? 1 : 0;
+  if (all_empty) acc[0] = 1.0;
+#pragma unroll
+  for (int j = 0; j < 27; j++) ax[j * nc + qc] = acc[j];
+  ovf_cnt[qc] = cnt;
+  if (!all_empty && !(acc[0] > 0.0)) atomicOr(flag, F_NOT_SPD);
+}
+
+__global__ void __launch_bounds__(kBlock) k_galerkin_coarse3_ovf(CoarseSrc F, const int32_t *__restrict__ optr,
+                                                                  int32_t *__restrict__ ocol,
+                                                                  double *__restrict__ oval, int *flag) {
+  const int kc = F.k - 1;
+  const int64_t nc = F.n >> 3;
+  const int64_t M = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (M >= nc) return;
+  const uint32_t Mu = static_cast<uint32_t>(M);
+  const uint32_t qc = q_of_m3(Mu, kc);
+  int32_t o = optr[qc];
+  if (optr[qc + 1] == o) return;
+  const int T1 = static_cast<int>(compact3(Mu)), T2 = static_cast<int>(compact3(Mu >> 1)),
+            T3 = static_cast<int>(compact3(Mu >> 2));
+  const uint32_t my_color = (kc >= 1) ? (qc >> (3 * kc - 3)) : 0u;
+  for (int oi = 0; oi < 8; oi++) {
+    const int64_t q = child3_order(oi) * nc + M;
+    if (F.empty[q]) continue;
+    for (int32_t e = F.optr[q]; e < F.optr[q + 1]; e++) {
+      const uint32_t P = m_of_q3(static_cast<uint32_t>(F.ocol[e]), F.k) >> 3;
+      const int dX = static_cast<int>(compact3(P)) - T1, dY = static_cast<int>(compact3(P >> 1)) - T2,
+                dZ = static_cast<int>(compact3(P >> 2)) - T3;
+      if (dX >= -1 && dX <= 1 && dY >= -1 && dY <= 1 && dZ >= -1 && dZ <= 1) continue;
+      bool first = true;
+      for (int oj = 0; oj <= oi && first; oj++) {
+        const int64_t qj = child3_order(oj) * nc + M;
+        if (F.empty[qj]) continue;
+        const int32_t eend = (oj == oi) ? e : F.optr[qj + 1];
+        for (int32_t e2 = F.optr[qj]; e2 < eend; e2++)
+          if ((m_of_q3(static_cast<uint32_t>(F.ocol[e2]), F.k) >> 3) == P) { first = false; break; }
+      }
+      if (!first) continue;
+      double sum = 0.0;
+      for (int oj = oi; oj < 8; oj++) {
+        const int64_t qj = child3_order(oj) * nc + M;
+        if (F.empty[qj]) continue;
+        const int32_t ebeg = (oj == oi) ? e : F.optr[qj];
+        for (int32_t e2 = ebeg; e2 < F.optr[qj + 1]; e2++)
+          if ((m_of_q3(static_cast<uint32_t>(F.ocol[e2]), F.k) >> 3) == P) sum += F.oval[e2];
+      }
+      const uint32_t target = q_of_m3(P, kc);
+      ocol[o] = static_cast<int32_t>(target);
+      oval[o] = sum;
+      o++;
+      if (kc >= 1 && (target >> (3 * kc - 3)) == my_color) atomicOr(flag, F_SAMECOLOR);
+    }
+  }
+  sort_ovf_row3(ocol, oval, optr[qc], optr[qc + 1], kc);
+}
+
+__global__ void __launch_bounds__(kBlock) k_densify_level3(int k, int64_t n, const double *__restrict__ ax,
+                                                            const int32_t *__restrict__ optr,
+                                                            const int32_t *__restrict__ ocol,
+                                                            const double *__restrict__ oval,
+                                                            double *__restrict__ dense) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  uint32_t t1, t2, t3;
+  q_to_t3(static_cast<uint32_t>(q), k, t1, t2, t3);
+  const int side = 1 << k;
+  for (int s = 0; s < 27; s++) {
+    const int u1 = static_cast<int>(t1) + slot3_dx(s), u2 = static_cast<int>(t2) + slot3_dy(s),
+              u3 = static_cast<int>(t3) + slot3_dz(s);
+    if (u1 < 0 || u2 < 0 || u3 < 0 || u1 >= side || u2 >= side || u3 >= side) continue;
+    dense[q * n + q_of_m3(morton3(u1, u2, u3), k)] = ax[s * n + q];
+  }
+  if (optr)
+    for (int32_t e = optr[q]; e < optr[q + 1]; e++) dense[q * n + ocol[e]] = oval[e];
+}
+
+// ---------------------------------------------------------------------------------------------------------------
 // coarsest level: dense matrix, Cholesky, explicit inverse (one workgroup; n <= 1024)
 
 __global__ void __launch_bounds__(kBlock) k_densify_level(int k, int64_t n, const double *__restrict__ ax,
@@ -774,15 +1100,16 @@ __global__ void __launch_bounds__(kBlock) k_iota(int64_t n, T *__restrict__ v) {
 
 static inline unsigned nblk(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
 
-static int depth_rule(int64_t n, int coarse_max, int &L, int &kc) {
+// Section 3.1: L = max{l : (2^dim)^l < n}; the coarsest level is the first k with (2^dim)^k <= coarse_max
+static int depth_rule(int64_t n, int coarse_max, int &L, int &kc, int dim = 2) {
   if (n <= coarse_max) {
     L = kc = -1;
     return 1;
   }
   int l = 0;
-  while ((static_cast<int64_t>(1) << (2 * (l + 1))) < n) l++;
+  while ((static_cast<int64_t>(1) << (dim * (l + 1))) < n) l++;
   int k = l;
-  while (k > 0 && (static_cast<int64_t>(1) << (2 * k)) > coarse_max) k--;
+  while (k > 0 && (static_cast<int64_t>(1) << (dim * k)) > coarse_max) k--;
   L = l;
   kc = k;
   return 1 + (l - k + 1);
@@ -799,20 +1126,22 @@ static amg_status sell_values(amg_hierarchy *h);
 static amg_status build_sell(amg_hierarchy *h) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
+  const int nc = F.ncolor;
   F.nslices = 0;
-  for (int c = 0; c < 4; c++) {
+  for (int c = 0; c < nc; c++) {
     F.color_slice[c] = F.nslices;
     F.nslices += (F.color_row[c + 1] - F.color_row[c] + kSliceRows - 1) / kSliceRows;
   }
-  F.color_slice[4] = F.nslices;
-  Regions R;
-  for (int c = 0; c < 5; c++) { R.row[c] = F.color_row[c]; R.slice[c] = F.color_slice[c]; }
+  F.color_slice[nc] = F.nslices;
+  Regions R{};
+  R.nc = nc;
+  for (int c = 0; c <= nc; c++) { R.row[c] = F.color_row[c]; R.slice[c] = F.color_slice[c]; }
   int64_t *size = dalloc_n<int64_t>(h, F.nslices + 1);
   F.slice_row0 = dalloc_n<int32_t>(h, F.nslices + 1);
   F.slice_ptr = dalloc_n<int64_t>(h, F.nslices + 1);
   F.s_row = dalloc_n<int32_t>(h, F.n);
   if (!size || !F.slice_row0 || !F.slice_ptr || !F.s_row) return AMG_ERR_NOMEM;
-  for (int c = 0; c < 4; c++) {
+  for (int c = 0; c < nc; c++) {
     const int64_t windows = (F.color_row[c + 1] - F.color_row[c] + kSellWindow - 1) / kSellWindow;
     if (windows > 0)
       k_sell_sort<<<static_cast<unsigned>(windows), kSellWindow, 0, s>>>(F.color_row[c], F.color_row[c + 1], F.rp,
@@ -834,8 +1163,9 @@ static amg_status build_sell(amg_hierarchy *h) {
 static amg_status sell_values(amg_hierarchy *h) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
-  Regions R;
-  for (int c = 0; c < 5; c++) { R.row[c] = F.color_row[c]; R.slice[c] = F.color_slice[c]; }
+  Regions R{};
+  R.nc = F.ncolor;
+  for (int c = 0; c <= F.ncolor; c++) { R.row[c] = F.color_row[c]; R.slice[c] = F.color_slice[c]; }
   k_fill_sell<<<nblk(F.n), kBlock, 0, s>>>(R, F.n, F.rp, F.ci, F.va, F.diag64, F.slice_ptr, F.s_row, F.s_col,
                                             F.s_val64);
   QA_LAUNCH_CHECK();
@@ -884,7 +1214,7 @@ static amg_status build_single_level(amg_hierarchy *h, const int64_t *row_ptr, c
   k_row_diag<<<nblk(n), kBlock, 0, s>>>(n, F.rp, F.ci, F.va, F.diag64);
   QA_LAUNCH_CHECK();
   F.color_row[0] = 0;
-  for (int c = 1; c < 5; c++) F.color_row[c] = n;
+  for (int c = 1; c <= F.ncolor; c++) F.color_row[c] = n;
   QA_TRY(build_sell(h));
   QA_HIP(hipMemsetAsync(dense, 0, sizeof(double) * n * n, s));
   k_densify_csr<<<nblk(n), kBlock, 0, s>>>(n, row_ptr, col_idx, vals, dense);
@@ -894,22 +1224,24 @@ static amg_status build_single_level(amg_hierarchy *h, const int64_t *row_ptr, c
 
 // cells of more than `threshold` unknowns, ascending: *cells (device), *count, and the first of each color in
 // first[0..4] (first[4] = count)
-static amg_status cell_list(amg_hierarchy *h, int32_t threshold, int32_t **cells, int64_t *count, int64_t first[5]) {
+static amg_status cell_list(amg_hierarchy *h, int32_t threshold, int32_t **cells, int64_t *count,
+                            int64_t first[kMaxColors + 1]) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
-  const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
+  const int64_t nL = static_cast<int64_t>(1) << (h->dim * h->L);
+  const int nc = F.ncolor;
   int32_t *flag = dalloc_n<int32_t>(h, nL);
   int32_t *pos = dalloc_n<int32_t>(h, nL + 1);
   if (!flag || !pos) return AMG_ERR_NOMEM;
   k_big_flag<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, threshold, flag);
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i32(flag, pos, nL, s, h));
-  int32_t bc[5];
-  for (int c = 0; c < 5; c++)
-    QA_HIP(hipMemcpyAsync(&bc[c], pos + c * (nL / 4), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t bc[kMaxColors + 1];
+  for (int c = 0; c <= nc; c++)
+    QA_HIP(hipMemcpyAsync(&bc[c], pos + c * (nL / nc), sizeof(int32_t), hipMemcpyDeviceToHost, s));
   QA_HIP(hipStreamSynchronize(s));
-  for (int c = 0; c < 5; c++) first[c] = bc[c];
-  *count = bc[4];
+  for (int c = 0; c <= nc; c++) first[c] = bc[c];
+  *count = bc[nc];
   *cells = nullptr;
   if (*count == 0) return AMG_OK;
   *cells = dalloc_n<int32_t>(h, *count);
@@ -990,7 +1322,7 @@ static amg_status ic_values(amg_hierarchy *h) {
 static amg_status block_values(amg_hierarchy *h) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
-  const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
+  const int64_t nL = static_cast<int64_t>(1) << (h->dim * h->L);
   QA_HIP(hipMemsetAsync(F.bfac64, 0, sizeof(double) * std::max<int64_t>(F.bfac_n, 1), s));
   k_block_factor<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, F.ic_ptr, F.ic_col, F.ic_val64, F.diag64, F.boff, F.bfac64,
                                              h->dflag);
@@ -1010,11 +1342,13 @@ static amg_status level_values(amg_hierarchy *h, int l, bool fresh) {
   hipStream_t s = h->stream;
   const int L = h->L;
   QuadLevel &Q = h->lev[l];
+  const bool oct = h->dim == 3;
   if (fresh) {
     Q.k = L - (l - 1);
-    Q.n = static_cast<int64_t>(1) << (2 * Q.k);
-    Q.ax64 = dalloc_n<double>(h, 9 * Q.n);
-    Q.ax32 = dalloc_n<float>(h, 9 * Q.n);
+    Q.n = static_cast<int64_t>(1) << (h->dim * Q.k);
+    Q.ns = oct ? 27 : 9;
+    Q.ax64 = dalloc_n<double>(h, Q.ns * Q.n);
+    Q.ax32 = dalloc_n<float>(h, Q.ns * Q.n);
     Q.empty = dalloc_n<uint8_t>(h, Q.n);
     Q.optr = dalloc_n<int32_t>(h, Q.n + 1);
     if (!Q.ax64 || !Q.ax32 || !Q.empty || !Q.optr) return AMG_ERR_NOMEM;
@@ -1023,12 +1357,17 @@ static amg_status level_values(amg_hierarchy *h, int l, bool fresh) {
   if (!ocnt) return AMG_ERR_NOMEM;
   CoarseSrc src{};
   if (l == 1) {
-    k_galerkin_fine<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.ax64, Q.empty, ocnt,
-                                                  h->dflag);
+    if (oct)
+      k_galerkin_fine3<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.ax64, Q.empty,
+                                                     ocnt, h->dflag);
+    else
+      k_galerkin_fine<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.ax64, Q.empty, ocnt,
+                                                    h->dflag);
   } else {
     const QuadLevel &P = h->lev[l - 1];
     src = CoarseSrc{P.k, P.n, P.ax64, P.empty, P.ovf_nnz ? P.optr : nullptr, P.ocol, P.oval64};
-    k_galerkin_coarse<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.ax64, Q.empty, ocnt, h->dflag);
+    if (oct) k_galerkin_coarse3<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.ax64, Q.empty, ocnt, h->dflag);
+    else k_galerkin_coarse<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.ax64, Q.empty, ocnt, h->dflag);
   }
   QA_LAUNCH_CHECK();
   if (fresh) {
@@ -1046,9 +1385,14 @@ static amg_status level_values(amg_hierarchy *h, int l, bool fresh) {
   }
   if (Q.ovf_nnz) {
     QA_HIP(hipMemsetAsync(h->dflag + 1, 0, sizeof(int), s));
-    if (l == 1)
+    if (l == 1 && oct)
+      k_galerkin_fine3_ovf<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.optr, Q.ocol,
+                                                         Q.oval64, h->dflag + 1);
+    else if (l == 1)
       k_galerkin_fine_ovf<<<nblk(Q.n), kBlock, 0, s>>>(L, Q.n, F.crow, F.rp, F.ci, F.va, F.agg_q, Q.optr, Q.ocol,
                                                         Q.oval64, h->dflag + 1);
+    else if (oct)
+      k_galerkin_coarse3_ovf<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.optr, Q.ocol, Q.oval64, h->dflag + 1);
     else
       k_galerkin_coarse_ovf<<<nblk(Q.n), kBlock, 0, s>>>(src, Q.optr, Q.ocol, Q.oval64, h->dflag + 1);
     QA_LAUNCH_CHECK();
@@ -1061,7 +1405,7 @@ static amg_status level_values(amg_hierarchy *h, int l, bool fresh) {
     k_convert<double, float><<<nblk(Q.ovf_nnz), kBlock, 0, s>>>(Q.ovf_nnz, Q.oval64, Q.oval32);
     QA_LAUNCH_CHECK();
   }
-  k_convert<double, float><<<nblk(9 * Q.n), kBlock, 0, s>>>(9 * Q.n, Q.ax64, Q.ax32);
+  k_convert<double, float><<<nblk(Q.ns * Q.n), kBlock, 0, s>>>(Q.ns * Q.n, Q.ax64, Q.ax32);
   QA_LAUNCH_CHECK();
   return AMG_OK;
 }
@@ -1073,8 +1417,12 @@ static amg_status coarsest_values(amg_hierarchy *h) {
   double *dense = dalloc_n<double>(h, C.n * C.n);
   if (!dense) return AMG_ERR_NOMEM;
   QA_HIP(hipMemsetAsync(dense, 0, sizeof(double) * C.n * C.n, s));
-  k_densify_level<<<nblk(C.n), kBlock, 0, s>>>(C.k, C.n, C.ax64, C.ovf_nnz ? C.optr : nullptr, C.ocol, C.oval64,
-                                               dense);
+  if (h->dim == 3)
+    k_densify_level3<<<nblk(C.n), kBlock, 0, s>>>(C.k, C.n, C.ax64, C.ovf_nnz ? C.optr : nullptr, C.ocol,
+                                                   C.oval64, dense);
+  else
+    k_densify_level<<<nblk(C.n), kBlock, 0, s>>>(C.k, C.n, C.ax64, C.ovf_nnz ? C.optr : nullptr, C.ocol, C.oval64,
+                                                 dense);
   QA_LAUNCH_CHECK();
   return build_coarsest_inverse(h, dense, C.n);
 }
@@ -1082,7 +1430,7 @@ static amg_status coarsest_values(amg_hierarchy *h) {
 static amg_status build_block_factors(amg_hierarchy *h) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
-  const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
+  const int64_t nL = static_cast<int64_t>(1) << (h->dim * h->L);
   int64_t *size = dalloc_n<int64_t>(h, nL);
   F.boff = dalloc_n<int64_t>(h, nL + 1);
   if (!size || !F.boff) return AMG_ERR_NOMEM;
@@ -1136,7 +1484,7 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
   hipStream_t s = h->stream;
   const int64_t n = h->n;
   const int L = h->L;
-  const int64_t nL = static_cast<int64_t>(1) << (2 * L);
+  const int64_t nL = static_cast<int64_t>(1) << (h->dim * L);
   // level-L cells and the stable counting sort
   int32_t *key = dalloc_n<int32_t>(h, n);
   int32_t *cnt = dalloc_n<int32_t>(h, nL);
@@ -1156,7 +1504,11 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
     return AMG_ERR_NOMEM;
   QA_HIP(hipMemsetAsync(cnt, 0, sizeof(int32_t) * nL, s));
   QA_HIP(hipMemsetAsync(fill, 0, sizeof(int32_t) * nL, s));
-  k_cell_key<<<nblk(n), kBlock, 0, s>>>(n, coords, h->box[0], h->box[1], h->box[2], h->box[3], L, key, cnt);
+  if (h->dim == 3)
+    k_cell_key3<<<nblk(n), kBlock, 0, s>>>(n, coords, Box3{{h->box[0], h->box[1], h->box[2], h->box[3], h->box[4],
+                                                             h->box[5]}}, L, key, cnt);
+  else
+    k_cell_key<<<nblk(n), kBlock, 0, s>>>(n, coords, h->box[0], h->box[1], h->box[2], h->box[3], L, key, cnt);
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i32(cnt, F.crow, nL, s, h));
   k_scatter<<<nblk(n), kBlock, 0, s>>>(n, key, F.crow, fill, F.perm);
@@ -1165,7 +1517,7 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
   QA_LAUNCH_CHECK();
   {
     int32_t *large = nullptr;
-    int64_t nlarge = 0, first[5];
+    int64_t nlarge = 0, first[kMaxColors + 1];
     QA_TRY(cell_list(h, kSortCell, &large, &nlarge, first));
     if (nlarge > 0) {
       int32_t *sorted = dalloc_n<int32_t>(h, n);
@@ -1183,14 +1535,15 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
                                                F.diag64);
   k_row_diag<<<nblk(n), kBlock, 0, s>>>(n, F.rp, F.ci, F.va, F.diag64);
   QA_LAUNCH_CHECK();
-  // color regions: cells of color c are the quarter [c nL/4, (c+1) nL/4) of the color-major order
+  // color regions: cells of color c are the range [c nL/nc, (c+1) nL/nc) of the color-major order
   {
-    int32_t cr[4];
-    for (int c = 0; c < 4; c++)
-      QA_HIP(hipMemcpyAsync(&cr[c], F.crow + c * (nL / 4), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    const int nc = F.ncolor;
+    int32_t cr[kMaxColors];
+    for (int c = 0; c < nc; c++)
+      QA_HIP(hipMemcpyAsync(&cr[c], F.crow + c * (nL / nc), sizeof(int32_t), hipMemcpyDeviceToHost, s));
     QA_HIP(hipStreamSynchronize(s));
-    for (int c = 0; c < 4; c++) F.color_row[c] = cr[c];
-    F.color_row[4] = n;
+    for (int c = 0; c < nc; c++) F.color_row[c] = cr[c];
+    F.color_row[nc] = n;
   }
   QA_TRY(build_sell(h));
   // in-cell couplings
@@ -1228,15 +1581,32 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
   if (!h->dflag) return AMG_ERR_NOMEM;
   QA_HIP(hipMemsetAsync(h->dflag, 0, 4 * sizeof(int), s));
   const double *ub = h->opt.box;
-  k_validate<<<nblk(n), kBlock, 0, s>>>(n, nnz, coords, row_ptr, col_idx, vals, ub ? 1 : 0, ub ? ub[0] : 0.0,
-                                         ub ? ub[1] : 0.0, ub ? ub[2] : 0.0, ub ? ub[3] : 0.0, h->dflag);
+  const int nbox = 2 * h->dim;
+  if (h->dim == 3) {
+    Box3 B{};
+    for (int t = 0; t < 6 && ub; t++) B.v[t] = ub[t];
+    k_validate3<<<nblk(n), kBlock, 0, s>>>(n, nnz, coords, row_ptr, col_idx, vals, ub ? 1 : 0, B, h->dflag);
+  } else {
+    k_validate<<<nblk(n), kBlock, 0, s>>>(n, nnz, coords, row_ptr, col_idx, vals, ub ? 1 : 0, ub ? ub[0] : 0.0,
+                                           ub ? ub[1] : 0.0, ub ? ub[2] : 0.0, ub ? ub[3] : 0.0, h->dflag);
+  }
   QA_LAUNCH_CHECK();
   int f = 0;
   QA_TRY(read_flag(h, f));
   if (f & F_INVALID) return AMG_ERR_INVALID;
   if (f & F_NOT_SPD) return AMG_ERR_NOT_SPD;
   if (ub) {
-    for (int t = 0; t < 4; t++) h->box[t] = ub[t];
+    for (int t = 0; t < nbox; t++) h->box[t] = ub[t];
+  } else if (h->dim == 3) {
+    const int nb = static_cast<int>(std::min<int64_t>(nblk(n), kRedBlocksMax));
+    double *part = dalloc_n<double>(h, 6 * nb + 6);
+    if (!part) return AMG_ERR_NOMEM;
+    k_bbox3_partial<<<nb, kBlock, 0, s>>>(n, coords, part);
+    QA_LAUNCH_CHECK();
+    k_bbox3_final<<<1, 1, 0, s>>>(nb, part, part + 6 * nb);
+    QA_LAUNCH_CHECK();
+    QA_HIP(hipMemcpyAsync(h->box, part + 6 * nb, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
   } else {
     const int nb = static_cast<int>(std::min<int64_t>(nblk(n), kRedBlocksMax));
     double *part = dalloc_n<double>(h, 4 * nb + 4);
@@ -1248,8 +1618,9 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
     QA_HIP(hipMemcpyAsync(h->box, part + 4 * nb, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     QA_HIP(hipStreamSynchronize(s));
   }
-  h->nlev = depth_rule(n, h->opt.coarse_max, h->L, h->kc);
+  h->nlev = depth_rule(n, h->opt.coarse_max, h->L, h->kc, h->dim);
   h->fine.n = n;
+  h->fine.ncolor = 1 << h->dim;
   h->fine.nnz = nnz;
   if (h->nlev == 1) {
     QA_TRY(build_single_level(h, row_ptr, col_idx, vals, nnz));
@@ -1354,8 +1725,10 @@ extern "C" amg_status amg_estimate_bytes(int64_t n, int64_t nnz, const amg_optio
   return AMG_OK;
 }
 
-extern "C" amg_status amg_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
-                                const double *vals, int64_t nnz, const amg_options *opt, amg_hierarchy **out) {
+// shared by the quadtree (dim 2) and octree (dim 3) entry points; box: 2 dim values or NULL
+static amg_status setup_dim(int dim, int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
+                            const double *vals, int64_t nnz, const double *box, const amg_options *opt,
+                            amg_hierarchy **out) {
   if (!out) return AMG_ERR_INVALID;
   *out = nullptr;
   amg_options o;
@@ -1364,13 +1737,15 @@ extern "C" amg_status amg_setup(int64_t n, const double *coords, const int64_t *
   if (n < 1 || n > (static_cast<int64_t>(1) << 31) - 2 || nnz < 0 || !coords || !row_ptr || !col_idx || !vals)
     return AMG_ERR_INVALID;
   if ((o.precision != 0 && o.precision != 1) || o.coarse_max < 4 || o.coarse_max > 1024 || o.inner_iters < 1 ||
-      o.inner_iters > 2 || o.sweeps < 1 || o.sweeps > 8 || (o.outer_mmax != 0 && o.outer_mmax != 1) ||
-      o.max_iters < 1 || (o.smoother != 0 && o.smoother != 1))
+      o.inner_iters > 2 || o.sweeps < 1 || o.sweeps > 8 || (o.outer_mmax < -1 || o.outer_mmax > 1) ||
+      o.max_iters < 1 || (o.smoother != 0 && o.smoother != 1) || o.engine < 0 || o.engine > 2 ||
+      !o.alloc != !o.dealloc)
     return AMG_ERR_INVALID;
-  if (o.box) {
-    for (int t = 0; t < 4; t++)
-      if (!std::isfinite(o.box[t])) return AMG_ERR_INVALID;
-    if (o.box[1] < o.box[0] || o.box[3] < o.box[2]) return AMG_ERR_INVALID;
+  if (box) {
+    for (int t = 0; t < 2 * dim; t++)
+      if (!std::isfinite(box[t])) return AMG_ERR_INVALID;
+    for (int a = 0; a < dim; a++)
+      if (box[2 * a + 1] < box[2 * a]) return AMG_ERR_INVALID;
   }
   const auto t0 = std::chrono::steady_clock::now();
   amg_hierarchy *h = new (std::nothrow) amg_hierarchy();
@@ -1379,20 +1754,23 @@ extern "C" amg_status amg_setup(int64_t n, const double *coords, const int64_t *
     delete h;
     return AMG_ERR_DEVICE;
   }
+  h->dim = dim;
   h->opt = o;
   h->opt.box = nullptr;  // borrowed pointer: do not keep
   h->stream = static_cast<hipStream_t>(o.stream);
   h->precision = o.precision;
-  h->use_engine = o.engine ? 1 : 0;
-  h->use_batch = o.batch ? 1 : 0;
+  // the persistent small-level workgroups and the batched whole-solve route carry the quadtree's 9-point levels
+  h->use_engine = dim == 2 ? o.engine : 0;
+  h->use_batch = (dim == 2 && o.batch) ? 1 : 0;
   h->n = n;
   {
     size_t est = 0;
     amg_options eo = o;
     eo.box = nullptr;
-    if (amg_estimate_bytes(n, nnz, &eo, &est) == AMG_OK) h->chunk_unit = chunk_unit_for(est);
+    if (amg_estimate_bytes(n, nnz, &eo, &est) == AMG_OK)
+      h->chunk_unit = chunk_unit_for(dim == 3 ? est + est / 2 : est);
   }
-  h->opt.box = o.box;
+  h->opt.box = box;
   amg_status st = setup_impl(h, coords, row_ptr, col_idx, vals, nnz);
   h->opt.box = nullptr;
   if (st != AMG_OK) {
@@ -1404,6 +1782,18 @@ extern "C" amg_status amg_setup(int64_t n, const double *coords, const int64_t *
   h->setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   *out = h;
   return AMG_OK;
+}
+
+extern "C" amg_status amg_setup(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
+                                const double *vals, int64_t nnz, const amg_options *opt, amg_hierarchy **out) {
+  return setup_dim(2, n, coords, row_ptr, col_idx, vals, nnz, opt ? opt->box : nullptr, opt, out);
+}
+
+extern "C" amg_status amg_setup3d(int64_t n, const double *coords, const int64_t *row_ptr, const int32_t *col_idx,
+                                  const double *vals, int64_t nnz, const double *box, const amg_options *opt,
+                                  amg_hierarchy **out) {
+  if (opt && opt->box) return AMG_ERR_INVALID;  // the octree's box is the box argument
+  return setup_dim(3, n, coords, row_ptr, col_idx, vals, nnz, box, opt, out);
 }
 
 extern "C" amg_status amg_update_values(amg_hierarchy *h, const int64_t *row_ptr, const int32_t *col_idx,
@@ -1446,30 +1836,56 @@ static amg_status to_host(std::vector<T> &v, const T *d, int64_t count, hipStrea
   return AMG_OK;
 }
 
-static uint32_t host_q_of_lex(uint32_t lex, int k) {
-  const uint32_t t1 = lex & ((1u << k) - 1u), t2 = lex >> k;
-  return q_of_m(morton(t1, t2), k);
+// lexicographic id (eq. 8: t1 + 2^k t2 [+ 4^k t3]) <-> color-major storage index on a level of dimension dim
+static uint32_t host_q_of_lex(uint32_t lex, int k, int dim = 2) {
+  const uint32_t mask = (1u << k) - 1u;
+  if (dim == 3) return q_of_m3(morton3(lex & mask, (lex >> k) & mask, lex >> (2 * k)), k);
+  return q_of_m(morton(lex & mask, lex >> k), k);
 }
-static uint32_t host_lex_of_q(uint32_t q, int k) {
+static uint32_t host_lex_of_q(uint32_t q, int k, int dim = 2) {
+  if (dim == 3) {
+    const uint32_t m = m_of_q3(q, k);
+    return (((compact3(m >> 2) << k) | compact3(m >> 1)) << k) | compact3(m);
+  }
   const uint32_t m = m_of_q(q, k);
   return (compact_bits(m >> 1) << k) | compact_bits(m);
+}
+// grid coordinates of lexicographic cell I of side `side`
+static void host_coords(uint32_t I, uint32_t side, int dim, int t[3]) {
+  t[0] = static_cast<int>(I % side);
+  t[1] = static_cast<int>((I / side) % side);
+  t[2] = dim == 3 ? static_cast<int>(I / side / side) : 0;
+}
+static int host_slot_d(int sl, int a, int dim) {
+  if (dim == 3) return a == 0 ? slot3_dx(sl) : (a == 1 ? slot3_dy(sl) : slot3_dz(sl));
+  return a == 0 ? slot_dx(sl) : (a == 1 ? slot_dy(sl) : 0);
+}
+// lexicographic neighbour of I in slot sl, or -1 outside the grid
+static int32_t host_neighbour(uint32_t I, int sl, uint32_t side, int dim) {
+  int t[3];
+  host_coords(I, side, dim, t);
+  int u[3];
+  for (int a = 0; a < 3; a++) {
+    u[a] = t[a] + host_slot_d(sl, a, dim);
+    if (u[a] < 0 || (a < dim && u[a] >= static_cast<int>(side)) || (a >= dim && u[a] != 0)) return -1;
+  }
+  return static_cast<int32_t>((static_cast<uint32_t>(u[2]) * side + static_cast<uint32_t>(u[1])) * side +
+                              static_cast<uint32_t>(u[0]));
 }
 
 template <class V>
 static amg_status export_values(const amg_hierarchy *h, int32_t level, const V *dev_ax, V *ax) {
   const QuadLevel &Q = h->lev[level];
+  const int ns = Q.ns, dim = h->dim;
   std::vector<V> hax;
-  QA_TRY(to_host(hax, dev_ax, 9 * Q.n, h->stream));
+  QA_TRY(to_host(hax, dev_ax, ns * Q.n, h->stream));
   QA_HIP(hipStreamSynchronize(h->stream));
   const uint32_t side = 1u << Q.k;
   for (uint32_t I = 0; I < static_cast<uint32_t>(Q.n); I++) {
-    const uint32_t q = host_q_of_lex(I, Q.k);
-    const int t1 = static_cast<int>(I % side), t2 = static_cast<int>(I / side);
-    for (int sl = 0; sl < 9; sl++) {
-      const int u1 = t1 + slot_dx(sl), u2 = t2 + slot_dy(sl);
-      const bool in = u1 >= 0 && u2 >= 0 && u1 < static_cast<int>(side) && u2 < static_cast<int>(side);
-      ax[static_cast<size_t>(I) * 9 + sl] = in ? hax[static_cast<size_t>(sl) * Q.n + q] : V(0);
-    }
+    const uint32_t q = host_q_of_lex(I, Q.k, dim);
+    for (int sl = 0; sl < ns; sl++)
+      ax[static_cast<size_t>(I) * ns + sl] =
+          host_neighbour(I, sl, side, dim) >= 0 ? hax[static_cast<size_t>(sl) * Q.n + q] : V(0);
   }
   return AMG_OK;
 }
@@ -1494,23 +1910,25 @@ extern "C" amg_status amg_export_level(const amg_hierarchy *h, int32_t level, in
     QA_HIP(hipStreamSynchronize(s));
     for (int64_t i = 0; i < h->n; i++) {
       const uint32_t q = static_cast<uint32_t>(aggq[iperm[i]]);
-      if (agg) agg[i] = static_cast<int32_t>(host_lex_of_q(q, h->L));
-      if (color) color[i] = static_cast<uint8_t>(m_of_q(q, h->L) & 3u);
+      if (agg) agg[i] = static_cast<int32_t>(host_lex_of_q(q, h->L, h->dim));
+      if (color) color[i] = static_cast<uint8_t>(h->dim == 3 ? (m_of_q3(q, h->L) & 7u) : (m_of_q(q, h->L) & 3u));
     }
     return AMG_OK;
   }
   const QuadLevel &Q = h->lev[level];
-  const uint32_t side = 1u << Q.k;
+  const int dim = h->dim, ns = Q.ns;
+  const uint32_t side = 1u << Q.k, half = side >> 1;
   for (uint32_t I = 0; I < static_cast<uint32_t>(Q.n); I++) {
-    const uint32_t t1 = I % side, t2 = I / side;
-    if (agg) agg[I] = (level < h->nlev - 1) ? static_cast<int32_t>((t2 >> 1) * (side >> 1) + (t1 >> 1)) : -1;
-    if (color) color[I] = static_cast<uint8_t>((t1 & 1u) + 2u * (t2 & 1u));
+    int t[3];
+    host_coords(I, side, dim, t);
+    if (agg) {  // eq. (10): the parent (t1 >> 1, t2 >> 1[, t3 >> 1])
+      const uint32_t p1 = static_cast<uint32_t>(t[0]) >> 1, p2 = static_cast<uint32_t>(t[1]) >> 1,
+                     p3 = static_cast<uint32_t>(t[2]) >> 1;
+      agg[I] = (level < h->nlev - 1) ? static_cast<int32_t>((p3 * half + p2) * half + p1) : -1;
+    }
+    if (color) color[I] = static_cast<uint8_t>((t[0] & 1) + 2 * (t[1] & 1) + 4 * (t[2] & 1));
     if (aj)
-      for (int sl = 0; sl < 9; sl++) {
-        const int u1 = static_cast<int>(t1) + slot_dx(sl), u2 = static_cast<int>(t2) + slot_dy(sl);
-        const bool in = u1 >= 0 && u2 >= 0 && u1 < static_cast<int>(side) && u2 < static_cast<int>(side);
-        aj[static_cast<size_t>(I) * 9 + sl] = in ? static_cast<int32_t>(u2 * side + u1) : -1;
-      }
+      for (int sl = 0; sl < ns; sl++) aj[static_cast<size_t>(I) * ns + sl] = host_neighbour(I, sl, side, dim);
   }
   if (ax) QA_TRY(export_values<double>(h, level, Q.ax64, ax));
   if (ovf_ptr || ovf_col || ovf_val) {
@@ -1523,9 +1941,9 @@ extern "C" amg_status amg_export_level(const amg_hierarchy *h, int32_t level, in
     int64_t o = 0;
     if (ovf_ptr) ovf_ptr[0] = 0;
     for (uint32_t I = 0; I < static_cast<uint32_t>(Q.n); I++) {
-      const uint32_t q = host_q_of_lex(I, Q.k);
+      const uint32_t q = host_q_of_lex(I, Q.k, dim);
       for (int32_t e = optr[q]; e < optr[q + 1]; e++, o++) {
-        if (ovf_col) ovf_col[o] = static_cast<int32_t>(host_lex_of_q(static_cast<uint32_t>(ocol[e]), Q.k));
+        if (ovf_col) ovf_col[o] = static_cast<int32_t>(host_lex_of_q(static_cast<uint32_t>(ocol[e]), Q.k, dim));
         if (ovf_val) ovf_val[o] = oval[e];
       }
       if (ovf_ptr) ovf_ptr[I + 1] = o;

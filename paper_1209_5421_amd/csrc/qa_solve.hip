@@ -206,7 +206,7 @@ __device__ inline XT sell_row(const SellView<T> &S, int64_t off, int w, int lane
 // own eighth of x instead of all of it. Small passes keep the plain order (one grid-ordered run of slices, which also
 // keeps single-workgroup reductions in one launch).
 struct SliceSched {
-  int64_t cs[5];  // first slice of each color; cs[4] = number of slices
+  int64_t cs[kMaxColors + 1];  // first slice of each color; cs[ncolor] = number of slices
   int c0, c1;
   int xcd;        // 1: XCD-aware order (grid = 8 x the largest per-XCD share), 0: slices in grid order
 };
@@ -793,6 +793,116 @@ __global__ void __launch_bounds__(kBlock) k_cspmv_dir(QView<T> Q, const double *
 }
 
 // ---------------------------------------------------------------------------------------------------------------
+// octree (3D) level kernels: 27 slots, 8 colors, 8 children (numbering of qa_internal.hpp). Neighbour indices are
+// recomputed from the row's grid coordinates; a neighbour outside the grid is replaced by the row itself (its slot
+// holds 0), as on quadtree levels.
+
+template <class T, class XV>
+__device__ inline T row_apply3_f(const QView<T> &Q, uint32_t q, XV xv) {
+  const uint32_t m = m_of_q3(q, Q.k);
+  const int t1 = static_cast<int>(compact3(m)), t2 = static_cast<int>(compact3(m >> 1)),
+            t3 = static_cast<int>(compact3(m >> 2));
+  const int side = 1 << Q.k;
+  T acc = 0;
+#pragma unroll 9
+  for (int s = 0; s < 27; s++) {
+    const int u1 = t1 + slot3_dx(s), u2 = t2 + slot3_dy(s), u3 = t3 + slot3_dz(s);
+    const bool in = u1 >= 0 && u2 >= 0 && u3 >= 0 && u1 < side && u2 < side && u3 < side;
+    const uint32_t qn = in ? q_of_m3(morton3(static_cast<uint32_t>(u1), static_cast<uint32_t>(u2),
+                                             static_cast<uint32_t>(u3)), Q.k)
+                           : q;
+    acc += Q.ax[s * Q.n + q] * xv(qn);
+  }
+  if (Q.optr)
+    for (int32_t e = Q.optr[q]; e < Q.optr[q + 1]; e++) acc += Q.oval[e] * xv(static_cast<uint32_t>(Q.ocol[e]));
+  return acc;
+}
+
+template <class T>
+__device__ inline T row_apply3(const QView<T> &Q, uint32_t q, const T *__restrict__ x) {
+  return row_apply3_f<T>(Q, q, [x](uint32_t i) { return x[i]; });
+}
+
+// one color phase of the pointwise 8-color Gauss-Seidel on an octree level (delta: see k_cgs)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cgs3(QView<T> Q, const T *__restrict__ f, T *__restrict__ x,
+                                                 T *__restrict__ delta, int c) {
+  const int64_t n8 = Q.n >> 3;
+  const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n8) return;
+  const uint32_t q = static_cast<uint32_t>(c * n8 + j);
+  const T dl = (f[q] - row_apply3(Q, q, x)) / Q.ax[q];
+  if (delta) delta[q] = dl;
+  else x[q] += dl;
+}
+
+// residual of the eight children of coarse cell M, summed in child3_order (Section 4.3's restriction order on each
+// layer), into the parent's color-major slot
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cres_restrict3(QView<T> Q, const T *__restrict__ f,
+                                                           const T *__restrict__ u, T *__restrict__ gc) {
+  const int64_t n8 = Q.n >> 3;
+  const int64_t M = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (M >= n8) return;
+  T acc = 0;
+  for (int o = 0; o < 8; o++) {
+    const uint32_t q = static_cast<uint32_t>(child3_order(o) * n8 + M);
+    acc += f[q] - row_apply3(Q, q, u);
+  }
+  gc[q_of_m3(static_cast<uint32_t>(M), Q.k - 1)] = acc;
+}
+
+// u += P e_c: row q = c 8^(k-1) + M takes its parent's value
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cprolong3(int k, int64_t n, const T *__restrict__ e, T *__restrict__ u) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  u[q] += e[q_of_m3(static_cast<uint32_t>(q & ((n >> 3) - 1)), k - 1)];
+}
+
+// y = A x on an octree level with (x, y) and (w, x)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cspmv_dot3(QView<T> Q, const T *__restrict__ x, T *__restrict__ y,
+                                                       const T *__restrict__ w, Red R) {
+  double v[2] = {0.0, 0.0};
+  for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < Q.n;
+       q += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const T yq = row_apply3(Q, static_cast<uint32_t>(q), x);
+    y[q] = yq;
+    const double xq = static_cast<double>(x[q]);
+    v[0] += xq * static_cast<double>(yq);
+    v[1] += static_cast<double>(w[q]) * xq;
+  }
+  reduce_finish<2>(v, R);
+}
+
+// A d for d = p1 + beta p0 formed on the fly, with (d, A d) and (r, d)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_cspmv_dir3(QView<T> Q, const double *__restrict__ sc,
+                                                       const T *__restrict__ p1, const T *__restrict__ p0,
+                                                       const T *__restrict__ r, Red R) {
+  const T beta = static_cast<T>(sc[S_BETA]);
+  auto dir = [p1, p0, beta](uint32_t i) { return p1[i] + beta * p0[i]; };
+  double v[2] = {0.0, 0.0};
+  for (int64_t q = static_cast<int64_t>(blockIdx.x) * kBlock + threadIdx.x; q < Q.n;
+       q += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const uint32_t qu = static_cast<uint32_t>(q);
+    const T yq = row_apply3_f<T>(Q, qu, dir);
+    const double dq = static_cast<double>(dir(qu));
+    v[0] += dq * static_cast<double>(yq);
+    v[1] += static_cast<double>(r[q]) * dq;
+  }
+  reduce_finish<2>(v, R);
+}
+
+// y = A x on an octree level (level hook)
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_capply3(QView<T> Q, const T *__restrict__ x, T *__restrict__ y) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q < Q.n) y[q] = row_apply3(Q, static_cast<uint32_t>(q), x);
+}
+
+// ---------------------------------------------------------------------------------------------------------------
 // vector kernels of Algorithm 2.1 (n = 2); scalars are read from device memory
 
 template <class T>
@@ -918,6 +1028,20 @@ __global__ void __launch_bounds__(kBlock) k_outer_dir(int64_t n, const double *_
   p[i] = use_beta ? zi + sc[O_BETA] * pprev[i] : zi;
 }
 
+// p = z + sum_j beta_j P_j over all m stored directions, beta_j = -(z, Q_j) / (P_j, Q_j) (Algorithm 2.1, Step 2, as
+// written: z is orthogonalised against every earlier direction; the terms are added in order j = 0, 1, ...)
+__global__ void __launch_bounds__(kBlock) k_outer_dir_all(int64_t n, const double *__restrict__ z,
+                                                           const double *const *__restrict__ P,
+                                                           const double *__restrict__ zq,
+                                                           const double *__restrict__ d, int m,
+                                                           double *__restrict__ p) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double pi = z[i];
+  for (int j = 0; j < m; j++) pi += (-zq[j] / d[j]) * P[j][i];
+  p[i] = pi;
+}
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_dot_mixed(int64_t n, const T *__restrict__ a, const double *__restrict__ b,
                                                        Red R) {
@@ -951,11 +1075,12 @@ __global__ void __launch_bounds__(kBlock) k_cast(int64_t n, const S *__restrict_
 // lexicographic <-> color-major numbering of a quadtree level (tests and level hooks)
 template <class S, class D>
 __global__ void __launch_bounds__(kBlock) k_lex_to_q(int k, int64_t n, const S *__restrict__ src, D *__restrict__ dst,
-                                                      int inverse) {
+                                                      int inverse, int dim = 2) {
   const int64_t I = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (I >= n) return;
-  const uint32_t t1 = static_cast<uint32_t>(I) & ((1u << k) - 1u), t2 = static_cast<uint32_t>(I) >> k;
-  const uint32_t q = q_of_m(morton(t1, t2), k);
+  const uint32_t mask = (1u << k) - 1u, Iu = static_cast<uint32_t>(I);
+  const uint32_t q = dim == 3 ? q_of_m3(morton3(Iu & mask, (Iu >> k) & mask, Iu >> (2 * k)), k)
+                              : q_of_m(morton(Iu & mask, Iu >> k), k);
   if (inverse) dst[I] = static_cast<D>(src[q]);
   else dst[q] = static_cast<D>(src[I]);
 }
@@ -1009,7 +1134,7 @@ static void finish(amg_hierarchy *h, unsigned nb, const Red &R) {
 // Schedule of a fine-level pass over colors [c0, c1); the XCD-aware order from 256 slices (16,384 rows) up.
 static SliceSched slice_sched(const FineLevel &F, int c0, int c1) {
   SliceSched Z{};
-  for (int c = 0; c < 5; c++) Z.cs[c] = F.color_slice[c];
+  for (int c = 0; c <= F.ncolor; c++) Z.cs[c] = F.color_slice[c];
   Z.c0 = c0;
   Z.c1 = c1;
   Z.xcd = (Z.cs[c1] - Z.cs[c0]) >= 256 ? 1 : 0;
@@ -1677,7 +1802,8 @@ static double engine_flops(const amg_hierarchy *h, int top, const std::vector<En
 
 amg_status plan_engine(amg_hierarchy *h) {
   h->engine_top[0] = h->engine_top[1] = -1;
-  if (h->nlev < 3) return AMG_OK;  // nothing between the fine level and the coarsest
+  // nothing between the fine level and the coarsest; octree levels run per step
+  if (h->nlev < 3 || h->dim != 2) return AMG_OK;
   int lds = 0;
   QA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
   h->lds_max = static_cast<size_t>(lds);
@@ -1742,7 +1868,9 @@ amg_status plan_engine(amg_hierarchy *h) {
     h->engine_nops[pi] = static_cast<int>(ops.size());
     h->engine_flops[pi] = engine_flops(h, top, ops);
   }
-  return engine_lds_limits(h);
+  QA_TRY(engine_lds_limits(h));
+  // the specialised engine replaces the interpreter where the levels have its shape
+  return plan_engine_fast(h);
 }
 
 template <class T>
@@ -1767,7 +1895,7 @@ static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, En
 // steps. The FP32 copy is the rounded FP64 matrix.
 amg_status build_mhat(amg_hierarchy *h) {
   h->mhat_level = -1;
-  if (h->nlev < 3) return AMG_OK;
+  if (h->nlev < 3 || h->dim != 2) return AMG_OK;
   const int l = h->nlev - 2;
   const int64_t n = h->lev[l].n;
   if (n > kMhatMaxRows) return AMG_OK;
@@ -1868,6 +1996,10 @@ static void fill_engine(amg_hierarchy *h, int top, int lds_top, int ainv_lds, En
 template <class T>
 static void launch_engine(amg_hierarchy *h, int top) {
   const int pi = std::is_same<T, float>::value ? 1 : 0;
+  if (h->fe_cfg[pi] >= 0) {
+    launch_engine_fast(h, pi);
+    return;
+  }
   EngPlan<T> E{};
   fill_engine(h, top, h->engine_lds_top[pi], h->engine_ainv_lds[pi], E, h->engine_lvec[pi]);
   E.nops = h->engine_nops[pi];
@@ -2143,8 +2275,8 @@ __global__ void __launch_bounds__(kEngThreads) k_solve_wg(const WgSys<T> *system
 // deepest ones from LDS.
 amg_status plan_wg(amg_hierarchy *h) {
   h->wg_nops[0] = h->wg_nops[1] = 0;
-  // the whole-solve workgroup carries the substitution smoother only
-  if (h->nlev < 3 || h->n > kWgMaxRows || h->opt.smoother) return AMG_OK;
+  // the whole-solve workgroup carries the substitution smoother and at most one kept direction only
+  if (h->nlev < 3 || h->n > kWgMaxRows || h->opt.smoother || h->opt.outer_mmax < 0 || h->dim != 2) return AMG_OK;
   if (h->lds_max == 0) {
     int lds = 0;
     QA_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
@@ -2181,6 +2313,7 @@ amg_status plan_wg(amg_hierarchy *h) {
 }
 
 template <class T> static void btilde(amg_hierarchy *h, int l, const T *g, T *e, bool defer_update2);
+template <class T> static void btilde_oct(amg_hierarchy *h, int l, const T *g, T *e);
 
 // Solve or cycle on level l for the correction of level l - 1. Returns the pending last update of B~ on level l when
 // it was left for the parent's prolongation (only levels that run per step, with two inner iterations).
@@ -2190,6 +2323,8 @@ static Pending<T> coarse_solve_or_cycle(amg_hierarchy *h, int l) {
   const int pi = std::is_same<T, float>::value ? 1 : 0;
   if (l == h->nlev - 1) {
     k_dense_solve<T><<<1, kBlock, 0, h->stream>>>(static_cast<int>(h->nc), h->ainv, w.g, w.e);
+  } else if (h->dim == 3) {
+    btilde_oct<T>(h, l, w.g, w.e);
   } else if (h->use_engine && l == h->engine_top[pi]) {
     launch_engine<T>(h, l);
   } else {
@@ -2280,7 +2415,7 @@ static void fine_resid(amg_hierarchy *h, const T *f, const T *x, T *d, int c0, i
 template <class T>
 static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd, bool from_f) {
   const FineLevel &F = h->fine;
-  const int64_t nL4 = static_cast<int64_t>(1) << (2 * h->L - 2);
+  const int64_t nL4 = (static_cast<int64_t>(1) << (h->dim * h->L)) / F.ncolor;  // cells of one color
   const T *src = d;
   if (from_f) src = f;
   else fine_resid<T>(h, f, u, d, c, c + 1, P<T>::kGs);
@@ -2315,16 +2450,17 @@ static void bhat_fine(amg_hierarchy *h, const T *f, T *u) {
   LevelWork<T> &w = P<T>::W(h)[0];
   k_fill<T><<<nblk(F.n), kBlock, 0, s>>>(F.n, u, T(0));
   const int sweeps = h->opt.sweeps;
+  const int nc = F.ncolor;
   for (int sw = 0; sw < sweeps; sw++)
-    for (int c = 0; c < 4; c++) fine_phase<T>(h, f, u, w.d, c, true, sw == 0 && c == 0);
+    for (int c = 0; c < nc; c++) fine_phase<T>(h, f, u, w.d, c, true, sw == 0 && c == 0);
   LevelWork<T> &wc = P<T>::W(h)[1];
-  fine_resid<T>(h, f, u, w.d, 0, 4, P<T>::kResid);
-  const int64_t nL = static_cast<int64_t>(1) << (2 * h->L);
+  fine_resid<T>(h, f, u, w.d, 0, F.ncolor, P<T>::kResid);
+  const int64_t nL = static_cast<int64_t>(1) << (h->dim * h->L);
   k_fine_restrict<T><<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, w.d, wc.g);
   const Pending<T> pend = coarse_solve_or_cycle<T>(h, 1);
   k_fine_prolong<T><<<nblk(F.n), kBlock, 0, s>>>(F.n, F.agg_q, wc.e, pend, u);
   for (int sw = 0; sw < sweeps; sw++)
-    for (int c = 3; c >= 0; c--) fine_phase<T>(h, f, u, w.d, c, false, false);
+    for (int c = nc - 1; c >= 0; c--) fine_phase<T>(h, f, u, w.d, c, false, false);
 }
 
 template <class T>
@@ -2359,6 +2495,60 @@ static void btilde(amg_hierarchy *h, int l, const T *g, T *e, bool defer_update2
   k_cspmv_dir<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), sc, w.p1, w.p0, w.r, red(h, l, EPI_ALPHA1));
   finish<2>(h, nred(Q.n), red(h, l, EPI_ALPHA1));
   if (!defer_update2) k_update2<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p1, w.p0, e);
+}
+
+// Octree levels (per-step launches): one color phase, B^ (Algorithm 2.2) and B~ (Algorithm 2.1 with n = inner
+// iterations), with the same readings as the quadtree levels and no step fusions.
+template <class T>
+static void gs_phase_oct(amg_hierarchy *h, int l, const T *f, T *u, int c) {
+  const QuadLevel &Q = h->lev[l];
+  const int64_t n8 = Q.n >> 3;
+  if (Q.same_color_ovf) {
+    T *dl = P<T>::W(h)[l].d;
+    k_cgs3<T><<<nblk(n8), kBlock, 0, h->stream>>>(qview<T>(Q), f, u, dl, c);
+    k_add_range<T><<<nblk(n8), kBlock, 0, h->stream>>>(c * n8, n8, dl, u);
+  } else {
+    k_cgs3<T><<<nblk(n8), kBlock, 0, h->stream>>>(qview<T>(Q), f, u, nullptr, c);
+  }
+}
+
+template <class T> static void btilde_oct(amg_hierarchy *h, int l, const T *g, T *e);
+
+template <class T>
+static void bhat_oct(amg_hierarchy *h, int l, const T *f, T *u) {
+  const QuadLevel &Q = h->lev[l];
+  hipStream_t s = h->stream;
+  k_fill<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, u, T(0));
+  for (int sw = 0; sw < h->opt.sweeps; sw++)
+    for (int c = 0; c < 8; c++) gs_phase_oct<T>(h, l, f, u, c);
+  LevelWork<T> &wc = P<T>::W(h)[l + 1];
+  k_cres_restrict3<T><<<nblk(Q.n >> 3), kBlock, 0, s>>>(qview<T>(Q), f, u, wc.g);
+  if (l + 1 == h->nlev - 1)
+    k_dense_solve<T><<<1, kBlock, 0, s>>>(static_cast<int>(h->nc), h->ainv, wc.g, wc.e);
+  else
+    btilde_oct<T>(h, l + 1, wc.g, wc.e);
+  k_cprolong3<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, wc.e, u);
+  for (int sw = 0; sw < h->opt.sweeps; sw++)
+    for (int c = 7; c >= 0; c--) gs_phase_oct<T>(h, l, f, u, c);
+}
+
+template <class T>
+static void btilde_oct(amg_hierarchy *h, int l, const T *g, T *e) {
+  const QuadLevel &Q = h->lev[l];
+  LevelWork<T> &w = P<T>::W(h)[l];
+  hipStream_t s = h->stream;
+  const double *sc = h->scal + static_cast<size_t>(l) * kScalars;
+  bhat_oct<T>(h, l, g, w.p0);
+  k_cspmv_dot3<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), w.p0, w.q0, g, red(h, l, EPI_ALPHA0));
+  finish<2>(h, nred(Q.n), red(h, l, EPI_ALPHA0));
+  k_update1<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p0, w.q0, g, e, w.r);
+  if (h->opt.inner_iters < 2) return;
+  bhat_oct<T>(h, l, w.r, w.p1);
+  k_dot<T><<<nred(Q.n), kBlock, 0, s>>>(Q.n, w.p1, w.q0, red(h, l, EPI_BETA));
+  finish<1>(h, nred(Q.n), red(h, l, EPI_BETA));
+  k_cspmv_dir3<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), sc, w.p1, w.p0, w.r, red(h, l, EPI_ALPHA1));
+  finish<2>(h, nred(Q.n), red(h, l, EPI_ALPHA1));
+  k_update2<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, sc, w.p1, w.p0, e);
 }
 
 // z = B^_F[r] in the requested precision (r, z: FP64, permuted numbering)
@@ -2419,7 +2609,7 @@ amg_status alloc_workspaces(amg_hierarchy *h) {
   }
   h->scal = dalloc_n<double>(h, (h->nlev + 1) * kScalars);
   // two values per workgroup of the largest reduction launch (a scheduled pass over all slices)
-  h->partials_cap = std::max<int64_t>(kRedBlocksMax, sched_grid(slice_sched(h->fine, 0, 4)) + 1) * 2;
+  h->partials_cap = std::max<int64_t>(kRedBlocksMax, sched_grid(slice_sched(h->fine, 0, h->fine.ncolor)) + 1) * 2;
   h->partials = dalloc_n<double>(h, h->partials_cap);
   if (!h->scal || !h->partials) return AMG_ERR_NOMEM;
   QA_HIP(hipMemsetAsync(h->scal, 0, sizeof(double) * (h->nlev + 1) * kScalars, h->stream));
@@ -2448,6 +2638,29 @@ static amg_status read_scalars(amg_hierarchy *h, int first, int count) {
   return AMG_OK;
 }
 
+// Direction storage of the all-directions outer iteration (outer_mmax < 0): pairs (p_j, A p_j) of n doubles, made
+// when first needed and kept by the hierarchy for later solves, with a device table of their addresses.
+static amg_status outer_dirs_reserve(amg_hierarchy *h, int count) {
+  const int cap = h->opt.max_iters;
+  if (!h->dir_pp) {
+    h->dir_pp = dalloc_n<double *>(h, cap);
+    h->dir_zq = dalloc_n<double>(h, cap);
+    h->dir_d = dalloc_n<double>(h, cap);
+    if (!h->dir_pp || !h->dir_zq || !h->dir_d) return AMG_ERR_NOMEM;
+  }
+  if (count > cap) return AMG_ERR_INVALID;
+  while (static_cast<int>(h->dir_p.size()) < count) {
+    double *pj = dalloc_n<double>(h, h->n), *qj = dalloc_n<double>(h, h->n);
+    if (!pj || !qj) return AMG_ERR_NOMEM;
+    h->dir_p.push_back(pj);
+    h->dir_q.push_back(qj);
+    const size_t j = h->dir_p.size() - 1;
+    QA_HIP(hipMemcpyAsync(h->dir_pp + j, &h->dir_p[j], sizeof(double *), hipMemcpyHostToDevice, h->stream));
+    QA_HIP(hipStreamSynchronize(h->stream));  // the source is a host vector that may grow
+  }
+  return AMG_OK;
+}
+
 static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, double tol, amg_info *info) {
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t n = h->n;
@@ -2455,7 +2668,7 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
   hipStream_t s = h->stream;
   const int L0 = h->nlev;  // outer scalar block
   const double *osc = h->scal + static_cast<size_t>(L0) * kScalars;
-  const SliceSched Zall = slice_sched(F, 0, 4);
+  const SliceSched Zall = slice_sched(F, 0, F.ncolor);
   const unsigned nsl_blocks = sched_grid(Zall);
   SellView<double> A64 = sview<double>(F, F.s_val64);
   amg_info inf{};
@@ -2481,14 +2694,28 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
   bool have_prev = false;
   double *p = h->pp, *q = h->qp, *pprev = h->pprev, *qprev = h->qprev;
   const int prec = h->precision;
+  const bool all_dirs = h->opt.outer_mmax < 0;
+  int stored = 0;  // all-directions form: directions kept since the start or the last restart
   while (it < h->opt.max_iters) {
     QA_TRY(precond_apply(h, prec, h->rp, h->zp));
-    const bool use_beta = have_prev && h->opt.outer_mmax == 1;
-    if (use_beta) {
-      k_dot<double><<<nred(n), kBlock, 0, s>>>(n, h->zp, qprev, red(h, L0, EPI_OUT_BETA));
-      finish<1>(h, nred(n), red(h, L0, EPI_OUT_BETA));
+    if (all_dirs) {
+      QA_TRY(outer_dirs_reserve(h, stored + 1));
+      p = h->dir_p[stored];
+      q = h->dir_q[stored];
+      for (int j = 0; j < stored; j++) {
+        const Red R{h->partials, h->dir_zq, EPI_STORE, j};
+        k_dot<double><<<nred(n), kBlock, 0, s>>>(n, h->zp, h->dir_q[j], R);
+        finish<1>(h, nred(n), R);
+      }
+      k_outer_dir_all<<<nblk(n), kBlock, 0, s>>>(n, h->zp, h->dir_pp, h->dir_zq, h->dir_d, stored, p);
+    } else {
+      const bool use_beta = have_prev && h->opt.outer_mmax == 1;
+      if (use_beta) {
+        k_dot<double><<<nred(n), kBlock, 0, s>>>(n, h->zp, qprev, red(h, L0, EPI_OUT_BETA));
+        finish<1>(h, nred(n), red(h, L0, EPI_OUT_BETA));
+      }
+      k_outer_dir<double><<<nblk(n), kBlock, 0, s>>>(n, osc, h->zp, pprev, p, use_beta ? 1 : 0);
     }
-    k_outer_dir<double><<<nblk(n), kBlock, 0, s>>>(n, osc, h->zp, pprev, p, use_beta ? 1 : 0);
     launch_timed(h, KK_SPMV64, k_outer_spmv_dot, nsl_blocks, A64, Zall, static_cast<const double *>(p), q,
                  static_cast<const double *>(h->rp), red(h, L0, EPI_OUT_ALPHA));
     finish<2>(h, nsl_blocks, red(h, L0, EPI_OUT_ALPHA));
@@ -2501,9 +2728,14 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
       break;
     }
     it++;
-    have_prev = true;
-    std::swap(p, pprev);
-    std::swap(q, qprev);
+    if (all_dirs) {  // keep (p, q) and (p, A p) of this step
+      QA_HIP(hipMemcpyAsync(h->dir_d + stored, osc + O_D, sizeof(double), hipMemcpyDeviceToDevice, s));
+      stored++;
+    } else {
+      have_prev = true;
+      std::swap(p, pprev);
+      std::swap(q, qprev);
+    }
     if (std::sqrt(h->host_scal[O_RR]) <= tol * bn) {
       k_outer_true_resid<<<nsl_blocks, kBlock, 0, s>>>(A64, Zall, h->bp, h->xp, h->tp,
                                                         red(h, L0, EPI_STORE, O_TT));
@@ -2516,6 +2748,7 @@ static amg_status solve_impl(amg_hierarchy *h, const double *b, double *x, doubl
       }
       QA_HIP(hipMemcpyAsync(h->rp, h->tp, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
       have_prev = false;
+      stored = 0;
       inf.restarts++;
     }
   }
@@ -2544,15 +2777,20 @@ static amg_status level_smooth_t(amg_hierarchy *h, int level, const double *f, d
     T *ff = W[0].f, *xx = W[0].u;
     k_gather<double, T><<<nblk(n), kBlock, 0, s>>>(n, F.perm, f, ff);
     k_gather<double, T><<<nblk(n), kBlock, 0, s>>>(n, F.perm, x, xx);
-    for (int c = 0; c < 4; c++) fine_phase<T>(h, ff, xx, W[0].d, forward ? c : 3 - c, forward != 0, false);
+    const int nc = h->fine.ncolor;
+    for (int c = 0; c < nc; c++) fine_phase<T>(h, ff, xx, W[0].d, forward ? c : nc - 1 - c, forward != 0, false);
     k_scatter_back<T, double><<<nblk(n), kBlock, 0, s>>>(n, F.perm, xx, x);
   } else {
     const QuadLevel &Q = h->lev[level];
+    const int dim = h->dim, nc = 1 << dim;
     T *ff = W[level].r, *xx = W[level].p0;
-    k_lex_to_q<double, T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, f, ff, 0);
-    k_lex_to_q<double, T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, x, xx, 0);
-    for (int c = 0; c < 4; c++) gs_phase_coarse<T>(h, level, ff, xx, forward ? c : 3 - c);
-    k_lex_to_q<T, double><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, xx, x, 1);
+    k_lex_to_q<double, T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, f, ff, 0, dim);
+    k_lex_to_q<double, T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, x, xx, 0, dim);
+    for (int c = 0; c < nc; c++) {
+      if (dim == 3) gs_phase_oct<T>(h, level, ff, xx, forward ? c : nc - 1 - c);
+      else gs_phase_coarse<T>(h, level, ff, xx, forward ? c : nc - 1 - c);
+    }
+    k_lex_to_q<T, double><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, xx, x, 1, dim);
   }
   QA_LAUNCH_CHECK();
   QA_HIP(hipStreamSynchronize(s));
@@ -2572,7 +2810,7 @@ static amg_status level_spmv_t(amg_hierarchy *h, int level, const double *x, dou
     const int64_t n = F.n;
     T *xx = W[0].f, *yy = W[0].u;
     k_gather<double, T><<<nblk(n), kBlock, 0, s>>>(n, F.perm, x, xx);
-    const SliceSched Z = slice_sched(F, 0, 4);
+    const SliceSched Z = slice_sched(F, 0, F.ncolor);
     k_fine_apply<T><<<sched_grid(Z), kBlock, 0, s>>>(sview<T>(F, P<T>::sval(F)), Z, xx, yy);
     k_scatter_back<T, double><<<nblk(n), kBlock, 0, s>>>(n, F.perm, yy, y);
     QA_LAUNCH_CHECK();
@@ -2580,12 +2818,17 @@ static amg_status level_spmv_t(amg_hierarchy *h, int level, const double *x, dou
     return AMG_OK;
   }
   const QuadLevel &Q = h->lev[level];
+  const int dim = h->dim;
   T *xx = W[level].g, *yy = W[level].e;
-  k_lex_to_q<double, T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, x, xx, 0);
-  // reuse the dot kernel's SpMV (the inner products are discarded into the scratch slot of level 0)
-  k_cspmv_dot<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), xx, yy, xx, red(h, h->nlev, EPI_STORE, 15));
-  finish<2>(h, nred(Q.n), red(h, h->nlev, EPI_STORE, 15));
-  k_lex_to_q<T, double><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, yy, y, 1);
+  k_lex_to_q<double, T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, x, xx, 0, dim);
+  if (dim == 3) {
+    k_capply3<T><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), xx, yy);
+  } else {
+    // reuse the dot kernel's SpMV (the inner products are discarded into the scratch slot of level 0)
+    k_cspmv_dot<T><<<nred(Q.n), kBlock, 0, s>>>(qview<T>(Q), xx, yy, xx, red(h, h->nlev, EPI_STORE, 15));
+    finish<2>(h, nred(Q.n), red(h, h->nlev, EPI_STORE, 15));
+  }
+  k_lex_to_q<T, double><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, yy, y, 1, dim);
   QA_LAUNCH_CHECK();
   QA_HIP(hipStreamSynchronize(s));
   return AMG_OK;
@@ -2667,18 +2910,21 @@ static void fill_wg(amg_hierarchy *h, const double *b, double *x, double tol, do
   Y.E.ops = static_cast<const EngOp *>(h->wg_ops[pi]);
 }
 
-// one launch, one workgroup per system; info of system i -> out[4 i .. 4 i + 3]
+// one launch, one workgroup per system; info of system i -> out[4 i .. 4 i + 3]. buf: device memory of at least
+// wg_batch_bytes<T>(ids.size()) bytes for the system descriptors and the info words.
 template <class T>
-static amg_status launch_wg_batch(amg_hierarchy *const *hs, const double *const *b, double *const *x,
-                                  const double *tol, const std::vector<int> &ids, std::vector<double> &out) {
+static size_t wg_batch_bytes(size_t m) {
+  return sizeof(WgSys<T>) * m + sizeof(double) * 4 * m;
+}
+
+template <class T>
+static amg_status launch_wg_batch_in(amg_hierarchy *const *hs, const double *const *b, double *const *x,
+                                     const double *tol, const std::vector<int> &ids, void *buf,
+                                     std::vector<double> &out) {
   const int pi = std::is_same<T, float>::value ? 1 : 0;
   const int m = static_cast<int>(ids.size());
-  const int device = hs[ids[0]]->device;
-  QA_HIP(hipSetDevice(device));
   hipStream_t s = hs[ids[0]]->stream;
-  void *buf = nullptr;
   const size_t sys_bytes = sizeof(WgSys<T>) * m;
-  QA_HIP(hipMallocAsync(&buf, sys_bytes + sizeof(double) * 4 * m, s));
   double *info_d = reinterpret_cast<double *>(static_cast<char *>(buf) + sys_bytes);
   std::vector<WgSys<T>> sys(m);
   size_t lds = 0;
@@ -2693,7 +2939,45 @@ static amg_status launch_wg_batch(amg_hierarchy *const *hs, const double *const 
   out.assign(4 * m, 0.0);
   QA_HIP(hipMemcpyAsync(out.data(), info_d, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, s));
   QA_HIP(hipStreamSynchronize(s));
-  QA_HIP(hipFreeAsync(buf, s));
+  return AMG_OK;
+}
+
+template <class T>
+static amg_status launch_wg_batch(amg_hierarchy *const *hs, const double *const *b, double *const *x,
+                                  const double *tol, const std::vector<int> &ids, std::vector<double> &out) {
+  QA_HIP(hipSetDevice(hs[ids[0]]->device));
+  hipStream_t s = hs[ids[0]]->stream;
+  void *buf = tmp_alloc(hs[ids[0]], s, wg_batch_bytes<T>(ids.size()));
+  if (!buf) return AMG_ERR_NOMEM;
+  const amg_status st = launch_wg_batch_in<T>(hs, b, x, tol, ids, buf, out);
+  tmp_free(hs[ids[0]], s, buf);  // on every path
+  return st;
+}
+
+// Per-system results of whole-solve launches into st / inf.
+static void wg_results(amg_hierarchy *const *hs, const std::vector<int> &ids, const std::vector<double> &out,
+                       double ms, std::vector<amg_status> &st, std::vector<amg_info> &inf) {
+  for (size_t j = 0; j < ids.size(); j++) {
+    const int i = ids[j];
+    st[i] = static_cast<amg_status>(static_cast<int>(out[4 * j]));
+    inf[i].iters = static_cast<int32_t>(out[4 * j + 1]);
+    inf[i].restarts = static_cast<int32_t>(out[4 * j + 2]);
+    inf[i].relres = out[4 * j + 3];
+    inf[i].setup_ms = hs[i]->setup_ms;
+    inf[i].solve_ms = ms;
+  }
+}
+
+// Arguments of a batch call: each hierarchy given once, all on one device, every input present.
+static amg_status check_batch_args(amg_hierarchy *const *hs, const double *const *b, double *const *x,
+                                   const double *tol, int32_t count) {
+  if (count < 0 || (count > 0 && (!hs || !b || !x || !tol))) return AMG_ERR_INVALID;
+  for (int32_t i = 0; i < count; i++) {
+    if (!hs[i] || !b[i] || !x[i] || !(tol[i] > 0.0) || !std::isfinite(tol[i]) || hs[i]->stale) return AMG_ERR_INVALID;
+    for (int32_t j = 0; j < i; j++)
+      if (hs[j] == hs[i]) return AMG_ERR_INVALID;  // one workspace per hierarchy
+    if (hs[i]->device != hs[0]->device) return AMG_ERR_INVALID;
+  }
   return AMG_OK;
 }
 
@@ -2701,15 +2985,9 @@ static amg_status launch_wg_batch(amg_hierarchy *const *hs, const double *const 
 
 extern "C" amg_status amg_solve_batch(amg_hierarchy *const *hs, const double *const *b, double *const *x,
                                       const double *tol, int32_t count, amg_info *info) {
-  if (count < 0 || (count > 0 && (!hs || !b || !x || !tol))) return AMG_ERR_INVALID;
+  QA_TRY(check_batch_args(hs, b, x, tol, count));
   if (count == 0) return AMG_OK;
   const auto t0 = std::chrono::steady_clock::now();
-  for (int32_t i = 0; i < count; i++) {
-    if (!hs[i] || !b[i] || !x[i] || !(tol[i] > 0.0) || !std::isfinite(tol[i]) || hs[i]->stale) return AMG_ERR_INVALID;
-    for (int32_t j = 0; j < i; j++)
-      if (hs[j] == hs[i]) return AMG_ERR_INVALID;  // one workspace per hierarchy
-    if (hs[i]->device != hs[0]->device) return AMG_ERR_INVALID;
-  }
   // inputs are complete once each hierarchy's stream has drained
   for (int32_t i = 0; i < count; i++) {
     QA_HIP(hipSetDevice(hs[i]->device));
@@ -2736,16 +3014,8 @@ extern "C" amg_status amg_solve_batch(amg_hierarchy *const *hs, const double *co
     launch_st = pi == 0 ? launch_wg_batch<double>(hs, b, x, tol, small[pi], out)
                         : launch_wg_batch<float>(hs, b, x, tol, small[pi], out);
     if (launch_st != AMG_OK) break;
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    for (size_t j = 0; j < small[pi].size(); j++) {
-      const int i = small[pi][j];
-      st[i] = static_cast<amg_status>(static_cast<int>(out[4 * j]));
-      inf[i].iters = static_cast<int32_t>(out[4 * j + 1]);
-      inf[i].restarts = static_cast<int32_t>(out[4 * j + 2]);
-      inf[i].relres = out[4 * j + 3];
-      inf[i].setup_ms = hs[i]->setup_ms;
-      inf[i].solve_ms = ms;
-    }
+    wg_results(hs, small[pi], out,
+               std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(), st, inf);
   }
   for (auto &t : threads) t.join();
   amg_status first = launch_st;

@@ -44,6 +44,9 @@ def test_host_only_entry_points(lib):
     o = amg.default_options()
     assert (o.precision, o.coarse_max, o.inner_iters, o.sweeps, o.outer_mmax, o.max_iters, o.engine, o.batch,
             o.smoother) == (0, 64, 2, 1, 1, 1000, 1, 1, 0)
+    assert not o.alloc and not o.dealloc and not o.ctx
+    # the options struct of the binding has the size of the C one (alloc / dealloc / ctx at its end)
+    assert C.sizeof(amg.Options) == 4 * 9 + 4 + 8 * 5
     assert lib.amg_status_string(0) == b"AMG_OK"
     assert lib.amg_status_string(4) == b"AMG_ERR_NOT_SPD"
     small = amg.estimate_bytes(3969, 27281)
