@@ -7,8 +7,11 @@
 // constant:
 //  - the coarsest level is the 64-cell level k = 3, one smoothing sweep, two inner steps of Algorithm 2.1;
 //  - on the engine's levels no coupling reaches beyond one cell, so no two cells of one color are coupled;
-//  - the top level is k = KT (4, 5 or 6); the levels k <= KL keep their operators and vectors in LDS, a top level
-//    above them reads its operator from global memory (L2-resident at these sizes).
+//  - the top level is k = KT (4, 5 or 6); the levels k <= KL keep their operators and vectors in LDS. A top level
+//    above them is held in registers: each thread owns TR rows of every color block of it (k = 6 in FP32: 512
+//    threads, two rows each; k = 5 in FP64: 256 threads, one row each) and keeps their nine operator entries and
+//    their entries of g, e, r and q0 for the whole launch; only p0 and p1, whose neighbours every color phase
+//    gathers, are in LDS. The engine then reads global memory once, in its prologue.
 // A step on level k runs on the threads j < 4^(k-1): thread j owns row j of each of the four color blocks, so the
 // color of every row a thread touches is a compile-time constant and the neighbour indices of Section 4.4 fold to a
 // few integer operations; no level table, no loop over a run-time row count. The whole of B~ on the 256-cell level
@@ -33,8 +36,8 @@ namespace qa {
 
 namespace {
 
-constexpr int kFeThreads = 256;
-constexpr int kFeWaves = kFeThreads / 64;
+constexpr int kFeMaxThreads = 1024;
+constexpr int kFeMaxWaves = kFeMaxThreads / 64;
 constexpr int kFeMaxOps = 256;
 constexpr int kFeCoarse = 64;                 // cells of the coarsest level k = 3
 constexpr int kFeAinvBytes = kFeCoarse * kFeCoarse * 8;
@@ -55,19 +58,20 @@ constexpr int popc(unsigned v) { return v ? static_cast<int>(v & 1u) + popc(v >>
 
 // LDS layout of one configuration. Byte 0: the coarsest inverse (64 x 64 FP64). Then, in units of T: for every LDS
 // level down to k = 4 its operator (9 x n, slot-major, color-major rows) and its six vectors; the coarsest level's
-// g and e; and, for a top level in global memory, the work vectors of it that are kept in LDS.
+// g and e; and, for a top level held in registers, its p0 and p1.
 template <class T, int KT, int KL>
 struct FeLayout {
   static constexpr int lw = KT - 4;            // level index of k = 4 (B~ in one wavefront)
   static constexpr int first_lds = KT - KL;    // first level index in LDS
   __host__ __device__ static constexpr int n(int i) { return 1 << (2 * (KT - i)); }
   __host__ __device__ static constexpr bool lds(int i) { return i >= first_lds; }
-  // vectors of a global top level held in LDS: the B^ outputs p0, p1, whose nine neighbours every color phase
-  // gathers (and, in FP64 where the level is 1,024 rows, also r and q0)
-  static constexpr unsigned lvec_mask =
-      lds(0) ? 0u
-             : (std::is_same<T, float>::value ? ((1u << V_P0) | (1u << V_P1))
-                                               : ((1u << V_R) | (1u << V_P0) | (1u << V_Q0) | (1u << V_P1)));
+  // top level in registers (TR rows of each color block per thread), else 256 threads
+  static constexpr bool reg_top = !lds(0);
+  static constexpr int TR = (reg_top && n(0) > 1024) ? 2 : 1;
+  static constexpr int threads = reg_top ? n(0) / 4 / TR : 256;
+  // vectors of a register top level held in LDS: the B^ outputs p0, p1, whose nine neighbours every color phase
+  // gathers
+  static constexpr unsigned lvec_mask = reg_top ? ((1u << V_P0) | (1u << V_P1)) : 0u;
   __host__ __device__ static constexpr int ax_off(int i) {
     int o = 0;
     for (int j = first_lds; j < i; j++) o += 15 * n(j);
@@ -79,6 +83,15 @@ struct FeLayout {
   static constexpr int t_units = lvec_off + popc(lvec_mask) * n(0);
   static constexpr size_t bytes = kFeAinvBytes + sizeof(T) * static_cast<size_t>(t_units);
 };
+
+// registers of a top level: thread t's rows j + c 4^(k-1) (c = 0..3, j = t + i NT for i < TR), their nine operator
+// entries (slot order) and their entries of g, e, r, q0
+template <class T, int TR>
+struct FeTop {
+  T a[TR][4][9];
+  T v[TR][4][4];
+};
+__host__ __device__ constexpr int fe_rv(int v) { return v == V_G ? 0 : v == V_E ? 1 : v == V_R ? 2 : 3; }
 
 template <class T>
 struct FeArgs {
@@ -92,15 +105,29 @@ struct FeArgs {
 template <int C>
 using IC = std::integral_constant<int, C>;
 
-// f(j) for the rows j < N4 of a color block, thread j owning j, j + 256, ... (compile-time trip count)
-template <int N4, class F>
+// the thread index, opaque to the optimiser: row and neighbour indices derived from it are formed inside each step
+// rather than hoisted out of the step loop, where they would stay live across the whole launch
+__device__ __forceinline__ int fe_tid() {
+  int t;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"(static_cast<int>(threadIdx.x)));
+  return t;
+}
+
+// f(j) for the rows j < N4 of a color block, thread j owning j, j + NT, ... (compile-time trip count)
+template <int N4, int NT, class F>
 __device__ __forceinline__ void for_rows(F f) {
-  constexpr int trips = (N4 + kFeThreads - 1) / kFeThreads;
+  constexpr int trips = (N4 + NT - 1) / NT;
+  const int t0 = fe_tid();
 #pragma unroll 1
   for (int it = 0; it < trips; it++) {
-    const int j = static_cast<int>(threadIdx.x) + it * kFeThreads;
-    if (N4 % kFeThreads == 0 || j < N4) f(j);
+    const int j = t0 + it * NT;
+    if (N4 % NT == 0 || j < N4) f(j);
   }
+}
+
+template <class F>
+__device__ __forceinline__ void for_slots(F f) {
+  f(IC<0>{}); f(IC<1>{}); f(IC<2>{}); f(IC<3>{}); f(IC<4>{}); f(IC<5>{}); f(IC<6>{}); f(IC<7>{}); f(IC<8>{});
 }
 
 template <class F>
@@ -143,7 +170,7 @@ __device__ __forceinline__ void fe_reduce_t0(double (&v)[ND], double *red) {
       for (int j = 0; j < ND; j++) v[j] += __shfl_down(v[j], off, 64);
     if (W > 1 && (threadIdx.x & 63) == 0)
 #pragma unroll
-      for (int j = 0; j < ND; j++) red[j * kFeWaves + (threadIdx.x >> 6)] = v[j];
+      for (int j = 0; j < ND; j++) red[j * kFeMaxWaves + (threadIdx.x >> 6)] = v[j];
   }
   if constexpr (W > 1) {
     __syncthreads();
@@ -152,7 +179,7 @@ __device__ __forceinline__ void fe_reduce_t0(double (&v)[ND], double *red) {
       for (int j = 0; j < ND; j++) {
         double acc = 0.0;
 #pragma unroll
-        for (int w = 0; w < W; w++) acc += red[j * kFeWaves + w];
+        for (int w = 0; w < W; w++) acc += red[j * kFeMaxWaves + w];
         v[j] = acc;
       }
   }
@@ -180,15 +207,24 @@ template <class T, int KT, int KL>
 struct FeEngine {
   using Lay = FeLayout<T, KT, KL>;
   static constexpr int lw = Lay::lw;
+  static constexpr int NT = Lay::threads;
+  static constexpr int TR = Lay::TR;
 
   T *S;                 // T arrays in LDS
   const double *Ainv;   // LDS
   const FeArgs<T> &A;
   double (*sc)[8];
   double *red;
+  FeTop<T, TR> &R;      // the top level's registers (unused unless Lay::reg_top)
+
+  template <int I>
+  static constexpr bool reg() {
+    return Lay::reg_top && I == 0;
+  }
 
   template <int I, int V>
   __device__ __forceinline__ T *vec() const {
+    static_assert(!reg<I>() || V == V_P0 || V == V_P1, "register vector of the top level");
     if constexpr (Lay::lds(I)) {
       return S + Lay::vec_off(I) + V * Lay::n(I);
     } else if constexpr ((Lay::lvec_mask >> V) & 1u) {
@@ -203,58 +239,133 @@ struct FeEngine {
     else return A.ax[I];
   }
 
+  // f(j, t) for the rows j < 4^(k-1) of a color block of level I: on the register top level the thread's TR rows
+  // (t = IC<i> for the i-th, unrolled), elsewhere a loop with t = IC<0>
+  template <int I, class F>
+  __device__ __forceinline__ void rows(F f) const {
+    if constexpr (reg<I>()) {
+      const int t = fe_tid();
+      f(t, IC<0>{});
+      if constexpr (TR > 1) f(t + NT, IC<1>{});
+    } else {
+      for_rows<Lay::n(I) / 4, NT>([&](int j) { f(j, IC<0>{}); });
+    }
+  }
+
+  // entry V of row C 4^(k-1) + j of level I (a register of the top level, else LDS or global memory)
+  template <int I, int V, int C, int Tr>
+  __device__ __forceinline__ T &own(int j, IC<Tr>) const {
+    if constexpr (reg<I>() && V != V_P0 && V != V_P1) return R.v[Tr][fe_rv(V)][C];
+    else return vec<I, V>()[C * (Lay::n(I) / 4) + j];
+  }
+  // operator entry in slot Sl of that row
+  template <int I, int C, int Sl, int Tr>
+  __device__ __forceinline__ T aop(int j, IC<Tr>) const {
+    if constexpr (reg<I>()) return R.a[Tr][C][Sl];
+    else return ax<I>()[Sl * Lay::n(I) + C * (Lay::n(I) / 4) + j];
+  }
+
+  // (A x)_q for row q = C 4^(k-1) + j of level I (slots in order 0..8; an absent slot holds 0 and its product is
+  // taken with x[q])
+  template <int I, int C, int Tr, class XV>
+  __device__ __forceinline__ T row(int j, IC<Tr> tr, XV xv) const {
+    constexpr int K = KT - I, sh = 2 * K - 2;
+    const uint32_t ju = static_cast<uint32_t>(j);
+    const uint32_t q = (static_cast<uint32_t>(C) << sh) | ju;
+    uint32_t nb[9];
+    stencil_q(q, ju, C, sh, nb);
+    T acc = 0;
+    for_slots([&](auto ss) {
+      constexpr int sl = decltype(ss)::value;
+      acc += aop<I, C, sl>(j, tr) * xv(nb[sl]);
+    });
+    return acc;
+  }
+
   // ---- steps on a level run by the workgroup (k >= 5) ----
 
-  // the first two color phases of B^ from zero: color 0 takes f / diag, the color-1 rows read those values formed on
-  // the fly (their color-0 neighbours are E and W; every other neighbour is still 0), colors 2 and 3 are 0. For the
-  // second B^ of B~ the right-hand side is r = g - a0 q0 formed on the fly, and e = a0 p0 and r are stored here.
+  // the first two color phases of B^ from zero: color 0 takes f / diag, the color-1 rows read those values (their
+  // color-0 neighbours are E and W; every other neighbour is still 0), colors 2 and 3 are 0. For the second B^ of B~
+  // the right-hand side is r = g - a0 q0, and e = a0 p0 and r are stored here. On an LDS level the color-1 rows form
+  // their neighbours' values on the fly (one step); on a register top level the color-0 values go through LDS first.
   template <int I, int B2>
   __device__ __forceinline__ void first2() const {
     constexpr int K = KT - I, N = Lay::n(I), N4 = N / 4, SH = 2 * K - 2;
-    const T *a = ax<I>();
     T *u = vec<I, B2 ? V_P1 : V_P0>();
-    const T *g = vec<I, V_G>(), *q0 = vec<I, V_Q0>(), *p0 = vec<I, V_P0>();
-    T *e = vec<I, V_E>(), *r = vec<I, V_R>();
+    const T *p0 = vec<I, V_P0>();
     const T a0 = B2 ? static_cast<T>(sc[I][S_A0]) : T(0);
-    auto fv = [=](uint32_t i) -> T {
-      if constexpr (B2) return fe_upd1_r(g[i], a0, q0[i]);
-      else return g[i];
-    };
-    for_rows<N4>([&](int j) {
-      const uint32_t q1 = static_cast<uint32_t>(N4 + j);
-      uint32_t nb[9];
-      stencil_q(q1, static_cast<uint32_t>(j), 1, SH, nb);
-      auto first = [=](uint32_t i) -> T { return i < static_cast<uint32_t>(N4) ? fv(i) / a[i] : T(0); };
-      T acc = a[1 * N + q1] * first(nb[1]);
-      acc += a[5 * N + q1] * first(nb[5]);
-      const T u1 = T(0) + (fv(q1) - acc) / a[q1];
-      u[j] = fv(static_cast<uint32_t>(j)) / a[j];
-      u[q1] = u1;
-      u[2 * N4 + j] = T(0);
-      u[3 * N4 + j] = T(0);
-      if constexpr (B2) {
-        for_colors([&](auto cc) {
-          constexpr int c = decltype(cc)::value;
-          const int q = c * N4 + j;
-          e[q] = a0 * p0[q];
-          r[q] = fe_upd1_r(g[q], a0, q0[q]);
-        });
-      }
-    });
+    if constexpr (reg<I>()) {
+      auto fo = [&](auto cc, auto tr) -> T {
+        constexpr int c = decltype(cc)::value, t = decltype(tr)::value;
+        if constexpr (B2) return fe_upd1_r(R.v[t][0][c], a0, R.v[t][3][c]);
+        else return R.v[t][0][c];
+      };
+      rows<I>([&](int j, auto tr) {
+        constexpr int t = decltype(tr)::value;
+        u[j] = fo(IC<0>{}, tr) / R.a[t][0][0];
+        u[2 * N4 + j] = T(0);
+        u[3 * N4 + j] = T(0);
+        if constexpr (B2) {
+          for_colors([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            R.v[t][1][c] = a0 * p0[c * N4 + j];
+            R.v[t][2][c] = fe_upd1_r(R.v[t][0][c], a0, R.v[t][3][c]);
+          });
+        }
+      });
+      __syncthreads();
+      rows<I>([&](int j, auto tr) {
+        constexpr int t = decltype(tr)::value;
+        const uint32_t q1 = static_cast<uint32_t>(N4 + j);
+        uint32_t nb[9];
+        stencil_q(q1, static_cast<uint32_t>(j), 1, SH, nb);
+        auto first = [=](uint32_t i) -> T { return i < static_cast<uint32_t>(N4) ? u[i] : T(0); };
+        T acc = R.a[t][1][1] * first(nb[1]);
+        acc += R.a[t][1][5] * first(nb[5]);
+        u[q1] = T(0) + (fo(IC<1>{}, tr) - acc) / R.a[t][1][0];
+      });
+    } else {
+      const T *a = ax<I>();
+      const T *g = vec<I, V_G>(), *q0 = vec<I, V_Q0>();
+      T *e = vec<I, V_E>(), *r = vec<I, V_R>();
+      auto fv = [=](uint32_t i) -> T {
+        if constexpr (B2) return fe_upd1_r(g[i], a0, q0[i]);
+        else return g[i];
+      };
+      for_rows<N4, NT>([&](int j) {
+        const uint32_t q1 = static_cast<uint32_t>(N4 + j);
+        uint32_t nb[9];
+        stencil_q(q1, static_cast<uint32_t>(j), 1, SH, nb);
+        auto first = [=](uint32_t i) -> T { return i < static_cast<uint32_t>(N4) ? fv(i) / a[i] : T(0); };
+        T acc = a[1 * N + q1] * first(nb[1]);
+        acc += a[5 * N + q1] * first(nb[5]);
+        const T u1 = T(0) + (fv(q1) - acc) / a[q1];
+        u[j] = fv(static_cast<uint32_t>(j)) / a[j];
+        u[q1] = u1;
+        u[2 * N4 + j] = T(0);
+        u[3 * N4 + j] = T(0);
+        if constexpr (B2) {
+          for_colors([&](auto cc) {
+            constexpr int c = decltype(cc)::value;
+            const int q = c * N4 + j;
+            e[q] = a0 * p0[q];
+            r[q] = fe_upd1_r(g[q], a0, q0[q]);
+          });
+        }
+      });
+    }
   }
 
   // one color phase of the pointwise Gauss-Seidel (Section 4.5): x += (f - A x) / diag on the rows of color C; for
   // the second B^'s last phase also beta = -(p1, q0) / d0 of Algorithm 2.1
   template <int I, int C, int B2>
   __device__ __forceinline__ void gs() const {
-    constexpr int K = KT - I, N4 = Lay::n(I) / 4;
-    const T *a = ax<I>();
-    const T *f = vec<I, B2 ? V_R : V_G>();
+    constexpr int N4 = Lay::n(I) / 4;
     T *u = vec<I, B2 ? V_P1 : V_P0>();
-    for_rows<N4>([&](int j) {
-      const int q = C * N4 + j;
-      const T dl = (f[q] - fe_row<T, K, C>(a, static_cast<uint32_t>(j), [u](uint32_t i) { return u[i]; })) / a[q];
-      u[q] += dl;
+    rows<I>([&](int j, auto tr) {
+      const T f = own<I, B2 ? V_R : V_G, C>(j, tr);
+      const T dl = (f - row<I, C>(j, tr, [u](uint32_t i) { return u[i]; })) / aop<I, C, 0>(j, tr);
+      u[C * N4 + j] += dl;
     });
     if constexpr (B2 && C == 0) {
       __syncthreads();
@@ -265,15 +376,15 @@ struct FeEngine {
   template <int I>
   __device__ __forceinline__ void dot_beta() const {
     constexpr int N4 = Lay::n(I) / 4;
-    const T *p1 = vec<I, V_P1>(), *q0 = vec<I, V_Q0>();
+    const T *p1 = vec<I, V_P1>();
     double t[1] = {0.0};
-    for_rows<N4>([&](int j) {
+    rows<I>([&](int j, auto tr) {
       for_colors([&](auto cc) {
         constexpr int c = decltype(cc)::value;
-        t[0] += static_cast<double>(p1[c * N4 + j]) * static_cast<double>(q0[c * N4 + j]);
+        t[0] += static_cast<double>(p1[c * N4 + j]) * static_cast<double>(own<I, V_Q0, c>(j, tr));
       });
     });
-    fe_reduce_t0<1, (N4 < kFeThreads ? N4 : kFeThreads) / 64>(t, red);
+    fe_reduce_t0<1, (N4 < NT ? N4 : NT) / 64>(t, red);
     if (threadIdx.x == 0) {
       const double d0 = sc[I][S_D0];
       sc[I][S_BETA] = (d0 > 0.0) ? -t[0] / d0 : 0.0;
@@ -284,24 +395,22 @@ struct FeEngine {
   // explicit restriction) into the parent's g
   template <int I, int B2>
   __device__ __forceinline__ void res_restrict() const {
-    constexpr int K = KT - I, N4 = Lay::n(I) / 4;
-    const T *a = ax<I>();
-    const T *f = vec<I, B2 ? V_R : V_G>();
+    constexpr int K = KT - I;
+    constexpr int F = B2 ? V_R : V_G;
     const T *u = vec<I, B2 ? V_P1 : V_P0>();
     T *gc = vec<I + 1, V_G>();
     auto uv = [u](uint32_t i) { return u[i]; };
-    for_rows<N4>([&](int m) {
-      const uint32_t mu = static_cast<uint32_t>(m);
-      const T r0 = f[0 * N4 + m] - fe_row<T, K, 0>(a, mu, uv);
-      const T r1 = f[1 * N4 + m] - fe_row<T, K, 1>(a, mu, uv);
-      const T r3 = f[3 * N4 + m] - fe_row<T, K, 3>(a, mu, uv);
-      const T r2 = f[2 * N4 + m] - fe_row<T, K, 2>(a, mu, uv);
+    rows<I>([&](int m, auto tr) {
+      const T r0 = own<I, F, 0>(m, tr) - row<I, 0>(m, tr, uv);
+      const T r1 = own<I, F, 1>(m, tr) - row<I, 1>(m, tr, uv);
+      const T r3 = own<I, F, 3>(m, tr) - row<I, 3>(m, tr, uv);
+      const T r2 = own<I, F, 2>(m, tr) - row<I, 2>(m, tr, uv);
       T acc = 0;
       acc += r0;
       acc += r1;
       acc += r3;
       acc += r2;
-      gc[q_of_m(mu, K - 1)] = acc;
+      gc[q_of_m(static_cast<uint32_t>(m), K - 1)] = acc;
     });
   }
 
@@ -315,7 +424,7 @@ struct FeEngine {
     const T *p1c = vec<I + 1, V_P1>(), *p0c = vec<I + 1, V_P0>();
     const T a1 = defer ? static_cast<T>(sc[I + 1][S_A1]) : T(0);
     const T beta = defer ? static_cast<T>(sc[I + 1][S_BETA]) : T(0);
-    for_rows<N4>([&](int j) {
+    rows<I>([&](int j, auto) {
       const uint32_t m = q_of_m(static_cast<uint32_t>(j), K - 1);
       T ecm = ec[m];
       if constexpr (defer) ecm = ec[m] + a1 * (p1c[m] + beta * p0c[m]);
@@ -329,22 +438,20 @@ struct FeEngine {
   // q0 = A p0 with (p0, q0) and (g, p0); alpha0 of Algorithm 2.1
   template <int I>
   __device__ __forceinline__ void spmv0() const {
-    constexpr int K = KT - I, N4 = Lay::n(I) / 4;
-    const T *a = ax<I>();
-    const T *x = vec<I, V_P0>(), *w = vec<I, V_G>();
-    T *y = vec<I, V_Q0>();
+    constexpr int N4 = Lay::n(I) / 4;
+    const T *x = vec<I, V_P0>();
     double v[2] = {0.0, 0.0};
-    for_rows<N4>([&](int j) {
+    rows<I>([&](int j, auto tr) {
       for_colors([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         const int q = c * N4 + j;
-        const T yq = fe_row<T, K, c>(a, static_cast<uint32_t>(j), [x](uint32_t i) { return x[i]; });
-        y[q] = yq;
+        const T yq = row<I, c>(j, tr, [x](uint32_t i) { return x[i]; });
+        own<I, V_Q0, c>(j, tr) = yq;
         v[0] += static_cast<double>(x[q]) * static_cast<double>(yq);
-        v[1] += static_cast<double>(w[q]) * static_cast<double>(x[q]);
+        v[1] += static_cast<double>(own<I, V_G, c>(j, tr)) * static_cast<double>(x[q]);
       });
     });
-    fe_reduce_t0<2, (N4 < kFeThreads ? N4 : kFeThreads) / 64>(v, red);
+    fe_reduce_t0<2, (N4 < NT ? N4 : NT) / 64>(v, red);
     if (threadIdx.x == 0) {
       sc[I][S_D0] = v[0];
       sc[I][S_A0] = (v[0] > 0.0) ? v[1] / v[0] : 0.0;
@@ -354,23 +461,22 @@ struct FeEngine {
   // A d for the direction d = p1 + beta p0 formed on the fly, with (d, A d) and (r, d); alpha1
   template <int I>
   __device__ __forceinline__ void spmv1() const {
-    constexpr int K = KT - I, N4 = Lay::n(I) / 4;
-    const T *a = ax<I>();
+    constexpr int N4 = Lay::n(I) / 4;
     const T beta = static_cast<T>(sc[I][S_BETA]);
-    const T *p1 = vec<I, V_P1>(), *p0 = vec<I, V_P0>(), *w = vec<I, V_R>();
+    const T *p1 = vec<I, V_P1>(), *p0 = vec<I, V_P0>();
     auto dir = [p1, p0, beta](uint32_t i) { return p1[i] + beta * p0[i]; };
     double v[2] = {0.0, 0.0};
-    for_rows<N4>([&](int j) {
+    rows<I>([&](int j, auto tr) {
       for_colors([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         const uint32_t q = static_cast<uint32_t>(c * N4 + j);
-        const T yq = fe_row<T, K, c>(a, static_cast<uint32_t>(j), dir);
+        const T yq = row<I, c>(j, tr, dir);
         const T xq = dir(q);
         v[0] += static_cast<double>(xq) * static_cast<double>(yq);
-        v[1] += static_cast<double>(w[q]) * static_cast<double>(xq);
+        v[1] += static_cast<double>(own<I, V_R, c>(j, tr)) * static_cast<double>(xq);
       });
     });
-    fe_reduce_t0<2, (N4 < kFeThreads ? N4 : kFeThreads) / 64>(v, red);
+    fe_reduce_t0<2, (N4 < NT ? N4 : NT) / 64>(v, red);
     if (threadIdx.x == 0) sc[I][S_A1] = (sc[I][S_D0] > 0.0 && v[0] > 0.0) ? v[1] / v[0] : 0.0;
   }
 
@@ -380,12 +486,11 @@ struct FeEngine {
     constexpr int N4 = Lay::n(I) / 4;
     const T a1 = static_cast<T>(sc[I][S_A1]), beta = static_cast<T>(sc[I][S_BETA]);
     const T *p1 = vec<I, V_P1>(), *p0 = vec<I, V_P0>();
-    T *e = vec<I, V_E>();
-    for_rows<N4>([&](int j) {
+    rows<I>([&](int j, auto tr) {
       for_colors([&](auto cc) {
         constexpr int c = decltype(cc)::value;
         const int q = c * N4 + j;
-        e[q] += a1 * (p1[q] + beta * p0[q]);
+        own<I, V_E, c>(j, tr) += a1 * (p1[q] + beta * p0[q]);
       });
     });
   }
@@ -567,17 +672,33 @@ struct FeEngine {
 };
 
 template <class T, int KT, int KL>
-__global__ void __launch_bounds__(kFeThreads) k_engine_fast(FeArgs<T> A) {
+__global__ void __launch_bounds__((FeLayout<T, KT, KL>::threads)) k_engine_fast(FeArgs<T> A) {
   using Lay = FeLayout<T, KT, KL>;
+  constexpr int NT = Lay::threads;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double sc[4][8];
-  __shared__ double red[2 * kFeWaves];
+  __shared__ double red[2 * kFeMaxWaves];
   __shared__ int32_t ops[kFeMaxOps];
   double *ainv = reinterpret_cast<double *>(smem);
   T *S = reinterpret_cast<T *>(smem + kFeAinvBytes);
   const int tid = static_cast<int>(threadIdx.x);
-  for (int i = tid; i < A.nops; i += kFeThreads) ops[i] = A.ops[i];
-  for (int i = tid; i < kFeCoarse * kFeCoarse; i += kFeThreads) ainv[i] = A.ainv[i];
+  FeTop<T, Lay::TR> R;
+  if constexpr (Lay::reg_top) {  // the top level's rows of this thread
+    constexpr int N = Lay::n(0), N4 = N / 4;
+#pragma unroll
+    for (int t = 0; t < Lay::TR; t++)
+      for_colors([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        const int j = tid + t * NT;
+        for_slots([&](auto ss) {
+          constexpr int sl = decltype(ss)::value;
+          R.a[t][c][sl] = A.ax[0][sl * N + c * N4 + j];
+        });
+        R.v[t][0][c] = A.gv[V_G][c * N4 + j];
+      });
+  }
+  for (int i = tid; i < A.nops; i += NT) ops[i] = A.ops[i];
+  for (int i = tid; i < kFeCoarse * kFeCoarse; i += NT) ainv[i] = A.ainv[i];
   // operators of the LDS levels
 #pragma unroll
   for (int l = 0; l < 3; l++)
@@ -585,21 +706,29 @@ __global__ void __launch_bounds__(kFeThreads) k_engine_fast(FeArgs<T> A) {
       const int n9 = 9 * Lay::n(l);
       T *dst = S + Lay::ax_off(l);
       const T *src = A.ax[l];
-      for (int i = tid; i < n9; i += kFeThreads) dst[i] = src[i];
+      for (int i = tid; i < n9; i += NT) dst[i] = src[i];
     }
   if constexpr (Lay::lds(0)) {
     T *g = S + Lay::vec_off(0) + V_G * Lay::n(0);
-    for (int i = tid; i < Lay::n(0); i += kFeThreads) g[i] = A.gv[V_G][i];
+    for (int i = tid; i < Lay::n(0); i += NT) g[i] = A.gv[V_G][i];
   }
   __syncthreads();
-  const FeEngine<T, KT, KL> E{S, ainv, A, sc, red};
+  const FeEngine<T, KT, KL> E{S, ainv, A, sc, red, R};
   for (int oi = 0; oi < A.nops; oi++) {
     E.step(__builtin_amdgcn_readfirstlane(ops[oi]));
     __syncthreads();
   }
-  if constexpr (Lay::lds(0)) {
+  if constexpr (Lay::reg_top) {
+    constexpr int N4 = Lay::n(0) / 4;
+#pragma unroll
+    for (int t = 0; t < Lay::TR; t++)
+      for_colors([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        A.gv[V_E][c * N4 + tid + t * NT] = R.v[t][1][c];
+      });
+  } else {
     const T *e = S + Lay::vec_off(0) + V_E * Lay::n(0);
-    for (int i = tid; i < Lay::n(0); i += kFeThreads) A.gv[V_E][i] = e[i];
+    for (int i = tid; i < Lay::n(0); i += NT) A.gv[V_E][i] = e[i];
   }
 }
 
@@ -664,7 +793,7 @@ const void *fe_kernel(int id) {
   }
 }
 
-constexpr size_t kFeStatic = sizeof(double) * 4 * 8 + sizeof(double) * 2 * kFeWaves + sizeof(int32_t) * kFeMaxOps;
+constexpr size_t kFeStatic = sizeof(double) * 4 * 8 + sizeof(double) * 2 * kFeMaxWaves + sizeof(int32_t) * kFeMaxOps;
 
 amg_status fe_lds_limits(int device, size_t lds_max) {
   static std::once_flag once[64];
@@ -717,11 +846,12 @@ void fe_launch(amg_hierarchy *h, int pi) {
   Timing &t = h->timing;
   const int kind = pi ? KK_ENGINE32 : KK_ENGINE64;
   if (t.kind == kind && t.used + 2 <= t.ev.size()) {  // dispatch-stamped start / stop
-    hipExtLaunchKernelGGL(k_engine_fast<T, KT, KL>, dim3(1), dim3(kFeThreads), lds, h->stream, t.ev[t.used],
+    hipExtLaunchKernelGGL(k_engine_fast<T, KT, KL>, dim3(1), dim3(FeLayout<T, KT, KL>::threads), lds, h->stream,
+                          t.ev[t.used],
                           t.ev[t.used + 1], 0, A);
     t.used += 2;
   } else {
-    k_engine_fast<T, KT, KL><<<1, kFeThreads, lds, h->stream>>>(A);
+    k_engine_fast<T, KT, KL><<<1, FeLayout<T, KT, KL>::threads, lds, h->stream>>>(A);
   }
 }
 
