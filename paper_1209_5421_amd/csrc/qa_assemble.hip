@@ -13,7 +13,12 @@
 // ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)) followed by the remainder in order (pairwise summation with
 // eight accumulators). This is the order of a stable sort of the element entries by (row, column) followed by
 // NumPy's add.reduceat over the segments, so the host generator's assembly and this one agree bit for bit.
-#include <hipcub/hipcub.hpp>
+//
+// The sort is a counting sort by row: each vertex's corners count their kept entries into the row of the vertex's
+// unknown, an exclusive scan gives each row's first position, the corners drop their entries into their row's
+// range in any order, and each entry's final place in its row is the number of entries of that row with a smaller
+// (column, entry index) pair. The (row, column, entry index) order that results is the stable sort's, whatever
+// order the atomics took.
 
 #include <algorithm>
 
@@ -82,17 +87,70 @@ __global__ void __launch_bounds__(kAsmBlock) k_dof_once(int64_t ndof, const int3
   if (d < ndof && cnt[d] != 1) atomicOr(flag, F_INVALID);
 }
 
-// sort key of each element entry: row * ndof + column, or `drop` (sorts last) when either vertex has no unknown
-__global__ void __launch_bounds__(kAsmBlock) k_entry_keys(int64_t nt, int64_t ndof, const int32_t *__restrict__ tri,
-                                                           const int32_t *__restrict__ dof, uint64_t drop,
-                                                           uint64_t *__restrict__ key, int32_t *__restrict__ idx) {
+// kept entries (a, b, t) of corner (a, t) whose vertex has an unknown: the b with an unknown
+__device__ inline int corner_kept(const int32_t *tri, const int32_t *dof, int64_t t) {
+  return (dof[tri[3 * t]] >= 0) + (dof[tri[3 * t + 1]] >= 0) + (dof[tri[3 * t + 2]] >= 0);
+}
+
+// per row, the number of kept element entries (corner i = a nt + t)
+__global__ void __launch_bounds__(kAsmBlock) k_row_counts(int64_t nt, const int32_t *__restrict__ tri,
+                                                           const int32_t *__restrict__ dof,
+                                                           int32_t *__restrict__ cnt) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= 9 * nt) return;
+  if (i >= 3 * nt) return;
   const int64_t t = i % nt;
-  const int ab = static_cast<int>(i / nt);
-  const int32_t r = dof[tri[3 * t + ab / 3]], c = dof[tri[3 * t + ab % 3]];
-  key[i] = (r < 0 || c < 0) ? drop : static_cast<uint64_t>(r) * static_cast<uint64_t>(ndof) + static_cast<uint64_t>(c);
-  idx[i] = static_cast<int32_t>(i);
+  const int a = static_cast<int>(i / nt);
+  const int32_t r = dof[tri[3 * t + a]];
+  if (r >= 0) atomicAdd(&cnt[r], corner_kept(tri, dof, t));
+}
+
+// each corner's kept entries into its row's range, in arrival order: the pair (column, entry index) packed as
+// column << 32 | index (both below 2^31) and the row of each position
+__global__ void __launch_bounds__(kAsmBlock) k_row_fill(int64_t nt, const int32_t *__restrict__ tri,
+                                                         const int32_t *__restrict__ dof,
+                                                         const int32_t *__restrict__ start, int32_t *__restrict__ fill,
+                                                         uint64_t *__restrict__ ckey, int32_t *__restrict__ rowid) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= 3 * nt) return;
+  const int64_t t = i % nt;
+  const int a = static_cast<int>(i / nt);
+  const int32_t r = dof[tri[3 * t + a]];
+  if (r < 0) return;
+  int32_t p = start[r] + atomicAdd(&fill[r], corner_kept(tri, dof, t));
+  for (int b = 0; b < 3; b++) {
+    const int32_t c = dof[tri[3 * t + b]];
+    if (c < 0) continue;
+    const uint64_t e = static_cast<uint64_t>((3 * a + b) * nt + t);
+    ckey[p] = (static_cast<uint64_t>(c) << 32) | e;
+    rowid[p] = r;
+    p++;
+  }
+}
+
+// each kept entry to its place: its row's first position plus the number of that row's entries with a smaller
+// (column, entry index); the sorted key row * ndof + column and the entry index
+__global__ void __launch_bounds__(kAsmBlock) k_row_rank(int64_t mk, int64_t ndof, const int32_t *__restrict__ start,
+                                                         const uint64_t *__restrict__ ckey,
+                                                         const int32_t *__restrict__ rowid,
+                                                         uint64_t *__restrict__ key, int32_t *__restrict__ perm) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= mk) return;
+  const int32_t r = rowid[p];
+  const uint64_t k = ckey[p];
+  const int32_t lo = start[r], hi = start[r + 1];
+  int32_t rank = 0;
+  for (int32_t q = lo; q < hi; q++) rank += ckey[q] < k;
+  key[lo + rank] = static_cast<uint64_t>(r) * static_cast<uint64_t>(ndof) + (k >> 32);
+  perm[lo + rank] = static_cast<int32_t>(k & 0xffffffffu);
+}
+
+// positions past the kept entries: key `drop` (they close the last segment), entry index 0 (never summed)
+__global__ void __launch_bounds__(kAsmBlock) k_drop_tail(int64_t mk, int64_t m, uint64_t drop,
+                                                          uint64_t *__restrict__ key, int32_t *__restrict__ perm) {
+  const int64_t p = mk + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= m) return;
+  key[p] = drop;
+  perm[p] = 0;
 }
 
 // first sorted position of each distinct kept key
@@ -201,7 +259,7 @@ amg_status mesh_build(amg_p1_mesh *M, const double *points, const int32_t *tris,
   if (!dflag || !M->pts || !M->tri || !M->elem || !M->perm || !M->row_ptr) return AMG_ERR_NOMEM;
   QA_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
   QA_HIP(hipMemcpyAsync(M->pts, points, sizeof(double) * 2 * nv, hipMemcpyDeviceToDevice, s));
-  Temp cnt(s), key(s), key2(s), idx(s), head(s), pos(s), rowcnt(s), sortbuf(s);
+  Temp cnt(s), start(s), key2(s), ckey(s), rowid(s), head(s), pos(s), rowcnt(s);
   if (!cnt.get(sizeof(int32_t) * ndof)) return AMG_ERR_NOMEM;
   QA_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * ndof, s));
   k_tri_orient<<<ablk(nt), kAsmBlock, 0, s>>>(nt, nv, tris, M->pts, M->tri, dflag);
@@ -211,19 +269,25 @@ amg_status mesh_build(amg_p1_mesh *M, const double *points, const int32_t *tris,
   int f = 0;
   QA_TRY(read_flag(M, dflag, f));
   if (f) return AMG_ERR_INVALID;
-  // stable sort of the element entries by (row, column): equal keys keep the (a, b, triangle) order
+  // stable sort of the element entries by (row, column): equal keys keep the (a, b, triangle) order; entries with
+  // a vertex without unknown are dropped (key `drop` after the kept ones)
   const uint64_t drop = static_cast<uint64_t>(ndof) * static_cast<uint64_t>(ndof);
-  int end_bit = 1;
-  while (end_bit < 64 && (drop >> end_bit) != 0) end_bit++;
-  if (!key.get(8 * m) || !key2.get(8 * m) || !idx.get(4 * m)) return AMG_ERR_NOMEM;
-  k_entry_keys<<<ablk(m), kAsmBlock, 0, s>>>(nt, ndof, M->tri, dof, drop, key.as<uint64_t>(), idx.as<int32_t>());
+  if (!start.get(4 * (ndof + 1)) || !key2.get(8 * m)) return AMG_ERR_NOMEM;
+  QA_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * ndof, s));
+  k_row_counts<<<ablk(3 * nt), kAsmBlock, 0, s>>>(nt, M->tri, dof, cnt.as<int32_t>());
   QA_LAUNCH_CHECK();
-  size_t sort_bytes = 0;
-  QA_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, key.as<uint64_t>(), key2.as<uint64_t>(),
-                                            idx.as<int32_t>(), M->perm, static_cast<int>(m), 0, end_bit, s));
-  if (!sortbuf.get(sort_bytes)) return AMG_ERR_NOMEM;
-  QA_HIP(hipcub::DeviceRadixSort::SortPairs(sortbuf.p, sort_bytes, key.as<uint64_t>(), key2.as<uint64_t>(),
-                                            idx.as<int32_t>(), M->perm, static_cast<int>(m), 0, end_bit, s));
+  QA_TRY(scan_exclusive_i32(cnt.as<int32_t>(), start.as<int32_t>(), ndof, s, h));
+  int32_t mk = 0;
+  QA_HIP(hipMemcpyAsync(&mk, start.as<int32_t>() + ndof, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  QA_HIP(hipStreamSynchronize(s));
+  if (mk < 0 || mk > m) return AMG_ERR_INVALID;
+  if (!ckey.get(8 * static_cast<size_t>(mk)) || !rowid.get(4 * static_cast<size_t>(mk))) return AMG_ERR_NOMEM;
+  QA_HIP(hipMemsetAsync(cnt.p, 0, sizeof(int32_t) * ndof, s));  // reused as the fill counters
+  k_row_fill<<<ablk(3 * nt), kAsmBlock, 0, s>>>(nt, M->tri, dof, start.as<int32_t>(), cnt.as<int32_t>(),
+                                                ckey.as<uint64_t>(), rowid.as<int32_t>());
+  if (mk) k_row_rank<<<ablk(mk), kAsmBlock, 0, s>>>(mk, ndof, start.as<int32_t>(), ckey.as<uint64_t>(),
+                                                    rowid.as<int32_t>(), key2.as<uint64_t>(), M->perm);
+  if (mk < m) k_drop_tail<<<ablk(m - mk), kAsmBlock, 0, s>>>(mk, m, drop, key2.as<uint64_t>(), M->perm);
   // distinct kept keys are the stored entries, already in row-major, column-ascending order
   if (!head.get(4 * m) || !pos.get(4 * (m + 1)) || !rowcnt.get(8 * ndof)) return AMG_ERR_NOMEM;
   k_heads<<<ablk(m), kAsmBlock, 0, s>>>(m, key2.as<uint64_t>(), drop, head.as<int32_t>());

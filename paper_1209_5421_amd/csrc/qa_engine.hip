@@ -159,15 +159,45 @@ __device__ __forceinline__ T fe_upd1_r(T g, T a0, T q0) {
   return g - a0 * q0;
 }
 
-// sum over the first W wavefronts, delivered to thread 0 (fixed tree: wavefront shuffles, then the wavefront sums in
-// order). Every thread calls it.
+// a lane's double moved by a DPP lane pattern (two 32-bit moves)
+template <int Ctrl>
+__device__ __forceinline__ double fe_dpp(double x) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(u & 0xffffffffu), Ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(u >> 32), Ctrl, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                        static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ double fe_readlane(double x, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u & 0xffffffffu), lane));
+  const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(u >> 32), lane));
+  return __builtin_bit_cast(double, (static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// sum over one wavefront, the same value in every lane: within each row of 16 lanes a butterfly over DPP lane
+// patterns (pairs, quads, half-row mirror, row mirror: every lane of the row ends with the row sum, added in an
+// order that gives the same value in each), then the four row sums (R0 + R1) + (R2 + R3) read from lanes 0, 16, 32,
+// 48. A fixed tree: the result depends only on the lanes' values.
+template <int ND>
+__device__ __forceinline__ void fe_wave_allreduce(double (&v)[ND]) {
+#pragma unroll
+  for (int j = 0; j < ND; j++) {
+    double x = v[j];
+    x += fe_dpp<0xb1>(x);   // quad_perm [1, 0, 3, 2]
+    x += fe_dpp<0x4e>(x);   // quad_perm [2, 3, 0, 1]
+    x += fe_dpp<0x141>(x);  // row_half_mirror
+    x += fe_dpp<0x140>(x);  // row_mirror
+    v[j] = (fe_readlane(x, 0) + fe_readlane(x, 16)) + (fe_readlane(x, 32) + fe_readlane(x, 48));
+  }
+}
+
+// sum over the first W wavefronts, delivered to thread 0 (fixed tree: each wavefront's sum as above, then the
+// wavefront sums in order). Every thread calls it.
 template <int ND, int W>
 __device__ __forceinline__ void fe_reduce_t0(double (&v)[ND], double *red) {
   if (static_cast<int>(threadIdx.x >> 6) < W) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-      for (int j = 0; j < ND; j++) v[j] += __shfl_down(v[j], off, 64);
+    fe_wave_allreduce<ND>(v);
     if (W > 1 && (threadIdx.x & 63) == 0)
 #pragma unroll
       for (int j = 0; j < ND; j++) red[j * kFeMaxWaves + (threadIdx.x >> 6)] = v[j];
@@ -183,15 +213,6 @@ __device__ __forceinline__ void fe_reduce_t0(double (&v)[ND], double *red) {
         v[j] = acc;
       }
   }
-}
-
-// sum over one wavefront, delivered to every lane (butterfly)
-template <int ND>
-__device__ __forceinline__ void fe_wave_allreduce(double (&v)[ND]) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int j = 0; j < ND; j++) v[j] += __shfl_xor(v[j], off, 64);
 }
 
 // Order between the sub-steps of the one-wavefront B~: a wavefront's LDS accesses are performed in issue order, so
@@ -558,11 +579,14 @@ struct FeEngine {
       g3[q_of_m(ju, 3)] = acc;
     }
     fe_wsync();
-    {  // coarsest solve e3 = A_3^{-1} g3 in FP64 (row j of the symmetric inverse read as column j)
-      double acc = 0.0;
-#pragma unroll 8
-      for (int i = 0; i < kFeCoarse; i++) acc += Ainv[i * kFeCoarse + j] * static_cast<double>(g3[i]);
-      e3[j] = static_cast<T>(acc);
+    {  // coarsest solve e3 = A_3^{-1} g3 in FP64 (row j of the symmetric inverse read as column j), four partial
+       // sums over i mod 4 (independent FMA chains), added pairwise
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < kFeCoarse; i += 4)
+#pragma unroll
+        for (int k = 0; k < 4; k++) acc[k] += Ainv[(i + k) * kFeCoarse + j] * static_cast<double>(g3[i + k]);
+      e3[j] = static_cast<T>((acc[0] + acc[1]) + (acc[2] + acc[3]));
     }
     fe_wsync();
     {  // prolongation

@@ -177,13 +177,23 @@ struct FineLevel {
   int64_t *rp = nullptr;        // permuted CSR (caller's entry order inside a row)
   int32_t *ci = nullptr;
   double *va = nullptr;
-  // sliced ELL: slices of 64 consecutive rows inside each color's row range, column-major inside a slice,
-  // diagonal first; padding entries point at the row itself with value 0
+  // sliced ELL: each color's rows in windows (runs of whole cells whose first rows lie in one band of win_band
+  // rows; 256 rows on a single level), each window in slices of 64 positions (the last one partial), column-major
+  // inside a slice, diagonal first; padding entries point at the row itself with value 0
+  int64_t nwin = 0;
+  int win_band = 0;
+  int32_t *win_q = nullptr;     // nwin + 1: first cell of each window (null on a single level)
+  int32_t *win_row = nullptr;   // nwin + 1: first row of each window
+  int64_t *win_slice = nullptr; // nwin + 1: first slice of each window
+  int64_t *win_ent = nullptr;   // nwin + 1: first factor value (exact blocks) or in-cell coupling of each window
+  int64_t color_win[kMaxColors + 1] = {};
+  bool same_color = false;      // some row is coupled to a row of another cell of its own color
   int64_t nslices = 0;
   int64_t *slice_ptr = nullptr; // nslices + 1 (entry offsets)
   int32_t *slice_row0 = nullptr;// nslices + 1 (first row)
   int32_t *s_col = nullptr;
-  int32_t *s_row = nullptr;     // SELL position -> row: rows sorted by length within windows of kSellWindow
+  int32_t *s_row = nullptr;     // SELL position -> row: rows sorted by length within runs of kSellWindow positions
+                                // of a window
   double *s_val64 = nullptr;
   float *s_val32 = nullptr;
   int64_t sell_entries = 0;

@@ -249,49 +249,115 @@ __global__ void __launch_bounds__(kBlock) k_row_diag(int64_t n, const int64_t *_
 // ---------------------------------------------------------------------------------------------------------------
 // sliced ELL of the fine level
 
-struct Regions {
-  int nc;                        // colors
-  int64_t row[kMaxColors + 1];
-  int64_t slice[kMaxColors + 1];
-};
+// Windows: each color's rows are cut into windows, and every window into slices of 64 positions (the last one
+// partial). On a multi-level hierarchy a window is a run of whole cells of one color: the cells whose first row lies
+// in one band of `band` rows, counted from the color's first row. A window then holds at most band - 1 + m rows, m
+// its last cell's size, so with band = 257 - (largest cell the smoother solves per thread) every window without a
+// larger cell fits 256 rows, and the fused smoother phase can take a window per workgroup with its cells whole.
+// On a single level (no cells) the windows are 256 consecutive rows.
 
-// Rows of each window of kSellWindow positions inside a color region, sorted by length (longest first, ascending
-// row among equal lengths), so that the four 64-row slices of a window hold rows of similar length and the padding
-// of sliced ELL stays small (sliced ELL with sorting windows, "SELL-C-sigma"). One thread per window.
-__global__ void __launch_bounds__(kSellWindow) k_sell_sort(int64_t begin, int64_t end,
+// 1 if some row is coupled to a row of another cell of its own color (cells are color-major: color = cell /
+// per_color)
+__global__ void __launch_bounds__(kBlock) k_same_color(int64_t n, int64_t per_color, const int64_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci,
+                                                        const int32_t *__restrict__ agg_q, int *__restrict__ flag) {
+  const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int32_t qp = agg_q[p];
+  bool hit = false;
+  for (int64_t e = rp[p]; e < rp[p + 1]; e++) {
+    const int32_t qc = agg_q[ci[e]];
+    hit = hit || (qc != qp && qc / per_color == qp / per_color);
+  }
+  if (hit) atomicOr(flag, 1);
+}
+
+// a cell starts a window when it is its color's first cell or its first row lies in another band than the
+// previous cell's
+__global__ void __launch_bounds__(kBlock) k_win_mark(int64_t nL, int64_t per_color, const int32_t *__restrict__ crow,
+                                                      int band, int32_t *__restrict__ mark) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nL) return;
+  const int64_t c0 = (q / per_color) * per_color;
+  const int32_t base = crow[c0];
+  mark[q] = (q == c0 || (crow[q] - base) / band != (crow[q - 1] - base) / band) ? 1 : 0;
+}
+
+// first cell and first row of each window; the end (nL, n) after the last
+__global__ void __launch_bounds__(kBlock) k_win_fill(int64_t nL, const int32_t *__restrict__ crow,
+                                                      const int32_t *__restrict__ mark,
+                                                      const int32_t *__restrict__ widx, int32_t *__restrict__ win_q,
+                                                      int32_t *__restrict__ win_row) {
+  const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= nL) return;
+  if (mark[q]) {
+    win_q[widx[q]] = static_cast<int32_t>(q);
+    win_row[widx[q]] = crow[q];
+  }
+  if (q == nL - 1) {
+    win_q[widx[nL]] = static_cast<int32_t>(nL);
+    win_row[widx[nL]] = crow[nL];
+  }
+}
+
+// single level: windows of kSellWindow consecutive rows
+__global__ void __launch_bounds__(kBlock) k_win_fixed(int64_t nwin, int64_t n, int32_t *__restrict__ win_row) {
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w > nwin) return;
+  win_row[w] = static_cast<int32_t>(w < nwin ? w * kSellWindow : n);
+}
+
+__global__ void __launch_bounds__(kBlock) k_win_nslices(int64_t nwin, const int32_t *__restrict__ win_row,
+                                                         int64_t *__restrict__ nsl) {
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= nwin) return;
+  nsl[w] = (win_row[w + 1] - win_row[w] + kSliceRows - 1) / kSliceRows;
+}
+
+// first position of each slice; row0[nslices] = n
+__global__ void __launch_bounds__(kBlock) k_slice_starts(int64_t nwin, const int32_t *__restrict__ win_row,
+                                                          const int64_t *__restrict__ win_slice,
+                                                          int32_t *__restrict__ row0) {
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= nwin) return;
+  for (int64_t k = 0; k < win_slice[w + 1] - win_slice[w]; k++)
+    row0[win_slice[w] + k] = win_row[w] + static_cast<int32_t>(k * kSliceRows);
+  if (w == nwin - 1) row0[win_slice[nwin]] = win_row[nwin];
+}
+
+// Rows of each run of kSellWindow positions of a window, sorted by length (longest first, ascending row among equal
+// lengths), so that the slices of a run hold rows of similar length and the padding of sliced ELL stays small
+// (sliced ELL with sorting windows, "SELL-C-sigma"). One workgroup per window.
+__global__ void __launch_bounds__(kSellWindow) k_sell_sort(const int32_t *__restrict__ win_row,
                                                              const int64_t *__restrict__ rp,
                                                              int32_t *__restrict__ s_row) {
   __shared__ int32_t len[kSellWindow];
-  const int64_t w0 = begin + static_cast<int64_t>(blockIdx.x) * kSellWindow;
-  const int64_t w1 = min(w0 + static_cast<int64_t>(kSellWindow), end);
-  const int m = static_cast<int>(w1 - w0);
-  const int i = threadIdx.x;
-  if (i < m) len[i] = static_cast<int32_t>(rp[w0 + i + 1] - rp[w0 + i]);
-  __syncthreads();
-  if (i >= m) return;
-  // place of row i: rows that are longer, or as long and earlier, come first
-  const int32_t li = len[i];
-  int rank = 0;
-  for (int j = 0; j < m; j++) rank += (len[j] > li || (len[j] == li && j < i)) ? 1 : 0;
-  s_row[w0 + rank] = static_cast<int32_t>(w0 + i);
+  const int64_t end = win_row[blockIdx.x + 1];
+  for (int64_t w0 = win_row[blockIdx.x]; w0 < end; w0 += kSellWindow) {
+    const int m = static_cast<int>(min(static_cast<int64_t>(kSellWindow), end - w0));
+    const int i = threadIdx.x;
+    __syncthreads();
+    if (i < m) len[i] = static_cast<int32_t>(rp[w0 + i + 1] - rp[w0 + i]);
+    __syncthreads();
+    if (i < m) {
+      // place of row i: rows that are longer, or as long and earlier, come first
+      const int32_t li = len[i];
+      int rank = 0;
+      for (int j = 0; j < m; j++) rank += (len[j] > li || (len[j] == li && j < i)) ? 1 : 0;
+      s_row[w0 + rank] = static_cast<int32_t>(w0 + i);
+    }
+  }
 }
 
-__global__ void __launch_bounds__(kBlock) k_slice_meta(Regions R, int64_t nslices, const int64_t *__restrict__ rp,
-                                                        const int32_t *__restrict__ ci, const int32_t *__restrict__ s_row,
-                                                        int32_t *__restrict__ row0, int64_t *__restrict__ size) {
+__global__ void __launch_bounds__(kBlock) k_slice_meta(int64_t nslices, const int32_t *__restrict__ row0,
+                                                        const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                        const int32_t *__restrict__ s_row,
+                                                        int64_t *__restrict__ size) {
   // one wavefront per slice: each lane counts the off-diagonal entries of one row, the width is their maximum + 1
   const int64_t s = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (s > nslices) return;
-  if (s == nslices) {
-    if (lane == 0) row0[s] = static_cast<int32_t>(R.row[R.nc]);
-    return;
-  }
-  // empty regions own no slices, so the region of s is found among the non-empty ones
-  int c = 0;
-  while (c < R.nc - 1 && s >= R.slice[c + 1]) c++;
-  const int64_t r0 = R.row[c] + (s - R.slice[c]) * kSliceRows;
-  const int64_t r1 = min(r0 + kSliceRows, R.row[c + 1]);
+  if (s >= nslices) return;
+  const int64_t r0 = row0[s], r1 = row0[s + 1];
   int w = 1;
   if (r0 + lane < r1) {
     const int64_t p = s_row[r0 + lane];
@@ -300,26 +366,21 @@ __global__ void __launch_bounds__(kBlock) k_slice_meta(Regions R, int64_t nslice
     w = offd + 1;
   }
   for (int off = 32; off > 0; off >>= 1) w = max(w, __shfl_xor(w, off, 64));
-  if (lane == 0) {
-    row0[s] = static_cast<int32_t>(r0);
-    size[s] = static_cast<int64_t>(w) * kSliceRows;
-  }
+  if (lane == 0) size[s] = static_cast<int64_t>(w) * kSliceRows;
 }
 
-__global__ void __launch_bounds__(kBlock) k_fill_sell(Regions R, int64_t n, const int64_t *__restrict__ rp,
-                                                       const int32_t *__restrict__ ci, const double *__restrict__ va,
-                                                       const double *__restrict__ diag,
+// one thread per (slice, lane)
+__global__ void __launch_bounds__(kBlock) k_fill_sell(int64_t nslices, const int32_t *__restrict__ row0,
+                                                       const int64_t *__restrict__ rp, const int32_t *__restrict__ ci,
+                                                       const double *__restrict__ va, const double *__restrict__ diag,
                                                        const int64_t *__restrict__ slice_ptr,
                                                        const int32_t *__restrict__ s_row,
                                                        int32_t *__restrict__ s_col, double *__restrict__ s_val) {
-  const int64_t pos = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (pos >= n) return;
-  const int64_t p = s_row[pos];  // the row at this position
-  int c = 0;
-  while (c < R.nc - 1 && pos >= R.row[c + 1]) c++;
-  const int64_t rel = pos - R.row[c];
-  const int64_t s = R.slice[c] + rel / kSliceRows;
-  const int lane = static_cast<int>(rel % kSliceRows);
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t s = g / kSliceRows;
+  const int lane = static_cast<int>(g % kSliceRows);
+  if (s >= nslices || row0[s] + lane >= row0[s + 1]) return;
+  const int64_t p = s_row[row0[s] + lane];  // the row at this position
   const int64_t off = slice_ptr[s];
   const int64_t w = (slice_ptr[s + 1] - off) / kSliceRows;
   s_col[off + lane] = static_cast<int32_t>(p);
@@ -1123,31 +1184,93 @@ static amg_status read_flag(amg_hierarchy *h, int &f) {
 
 static amg_status sell_values(amg_hierarchy *h);
 
+// a temporary device buffer of the build, returned on every path
+struct BuildTmp {
+  amg_hierarchy *h;
+  void *p;
+  BuildTmp(amg_hierarchy *hh, size_t bytes) : h(hh), p(tmp_alloc(hh, hh->stream, std::max<size_t>(bytes, 8))) {}
+  ~BuildTmp() { tmp_free(h, h->stream, p); }
+  template <class T>
+  T *as() const { return static_cast<T *>(p); }
+};
+
 static amg_status build_sell(amg_hierarchy *h) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
   const int nc = F.ncolor;
-  F.nslices = 0;
-  for (int c = 0; c < nc; c++) {
-    F.color_slice[c] = F.nslices;
-    F.nslices += (F.color_row[c + 1] - F.color_row[c] + kSliceRows - 1) / kSliceRows;
+  const int64_t n = h->n;
+  // windows
+  if (F.crow) {
+    const int64_t nL = static_cast<int64_t>(1) << (h->dim * h->L);
+    const int largest = h->opt.smoother ? kBlockMax : kBigCell;  // cells solved by one thread
+    F.win_band = kSellWindow + 1 - largest;
+    BuildTmp tmark(h, sizeof(int32_t) * nL), twidx(h, sizeof(int32_t) * (nL + 1));
+    int32_t *mark = tmark.as<int32_t>(), *widx = twidx.as<int32_t>();
+    if (!mark || !widx) return AMG_ERR_NOMEM;
+    k_win_mark<<<nblk(nL), kBlock, 0, s>>>(nL, nL / nc, F.crow, F.win_band, mark);
+    QA_LAUNCH_CHECK();
+    QA_TRY(scan_exclusive_i32(mark, widx, nL, s, h));
+    int32_t cw[kMaxColors + 1];
+    for (int c = 0; c < nc; c++)
+      QA_HIP(hipMemcpyAsync(&cw[c], widx + c * (nL / nc), sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipMemcpyAsync(&cw[nc], widx + nL, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
+    F.nwin = cw[nc];
+    for (int c = 0; c <= nc; c++) F.color_win[c] = cw[c];
+    F.win_q = dalloc_n<int32_t>(h, F.nwin + 1);
+    F.win_row = dalloc_n<int32_t>(h, F.nwin + 1);
+    if (!F.win_q || !F.win_row) return AMG_ERR_NOMEM;
+    k_win_fill<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, mark, widx, F.win_q, F.win_row);
+    // couplings between cells of one color: the fused smoother phase then takes its residual from a separate pass
+    BuildTmp tflag(h, sizeof(int));
+    int *flag = tflag.as<int>();
+    if (!flag) return AMG_ERR_NOMEM;
+    QA_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
+    k_same_color<<<nblk(n), kBlock, 0, s>>>(n, nL / nc, F.rp, F.ci, F.agg_q, flag);
+    QA_LAUNCH_CHECK();
+    int hf = 0;
+    QA_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
+    F.same_color = hf != 0;
+  } else {
+    F.win_band = kSellWindow;
+    F.nwin = (n + kSellWindow - 1) / kSellWindow;
+    F.color_win[0] = 0;
+    for (int c = 1; c <= nc; c++) F.color_win[c] = F.nwin;
+    F.win_row = dalloc_n<int32_t>(h, F.nwin + 1);
+    if (!F.win_row) return AMG_ERR_NOMEM;
+    k_win_fixed<<<nblk(F.nwin + 1), kBlock, 0, s>>>(F.nwin, n, F.win_row);
   }
-  F.color_slice[nc] = F.nslices;
-  Regions R{};
-  R.nc = nc;
-  for (int c = 0; c <= nc; c++) { R.row[c] = F.color_row[c]; R.slice[c] = F.color_slice[c]; }
+  QA_LAUNCH_CHECK();
+  // slices
+  BuildTmp tnsl(h, sizeof(int64_t) * std::max<int64_t>(F.nwin, 1));
+  int64_t *nsl = tnsl.as<int64_t>();
+  F.win_slice = dalloc_n<int64_t>(h, F.nwin + 1);
+  if (!nsl || !F.win_slice) return AMG_ERR_NOMEM;
+  if (F.nwin) k_win_nslices<<<nblk(F.nwin), kBlock, 0, s>>>(F.nwin, F.win_row, nsl);
+  QA_LAUNCH_CHECK();
+  QA_TRY(scan_exclusive_i64(nsl, F.win_slice, F.nwin, s, h));
+  {
+    int64_t cs[kMaxColors + 1];
+    for (int c = 0; c <= nc; c++)
+      QA_HIP(hipMemcpyAsync(&cs[c], F.win_slice + F.color_win[c], sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c <= nc; c++) F.color_slice[c] = cs[c];
+    F.nslices = cs[nc];
+  }
   int64_t *size = dalloc_n<int64_t>(h, F.nslices + 1);
   F.slice_row0 = dalloc_n<int32_t>(h, F.nslices + 1);
   F.slice_ptr = dalloc_n<int64_t>(h, F.nslices + 1);
-  F.s_row = dalloc_n<int32_t>(h, F.n);
+  F.s_row = dalloc_n<int32_t>(h, std::max<int64_t>(n, 1));
   if (!size || !F.slice_row0 || !F.slice_ptr || !F.s_row) return AMG_ERR_NOMEM;
-  for (int c = 0; c < nc; c++) {
-    const int64_t windows = (F.color_row[c + 1] - F.color_row[c] + kSellWindow - 1) / kSellWindow;
-    if (windows > 0)
-      k_sell_sort<<<static_cast<unsigned>(windows), kSellWindow, 0, s>>>(F.color_row[c], F.color_row[c + 1], F.rp,
-                                                                          F.s_row);
+  if (F.nwin) {
+    k_slice_starts<<<nblk(F.nwin), kBlock, 0, s>>>(F.nwin, F.win_row, F.win_slice, F.slice_row0);
+    k_sell_sort<<<static_cast<unsigned>(F.nwin), kSellWindow, 0, s>>>(F.win_row, F.rp, F.s_row);
+  } else {
+    QA_HIP(hipMemsetAsync(F.slice_row0, 0, sizeof(int32_t), s));
   }
-  k_slice_meta<<<nblk(64 * (F.nslices + 1)), kBlock, 0, s>>>(R, F.nslices, F.rp, F.ci, F.s_row, F.slice_row0, size);
+  if (F.nslices) k_slice_meta<<<nblk(64 * F.nslices), kBlock, 0, s>>>(F.nslices, F.slice_row0, F.rp, F.ci, F.s_row,
+                                                                      size);
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i64(size, F.slice_ptr, F.nslices, s, h));
   QA_HIP(hipMemcpyAsync(&F.sell_entries, F.slice_ptr + F.nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1163,11 +1286,9 @@ static amg_status build_sell(amg_hierarchy *h) {
 static amg_status sell_values(amg_hierarchy *h) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
-  Regions R{};
-  R.nc = F.ncolor;
-  for (int c = 0; c <= F.ncolor; c++) { R.row[c] = F.color_row[c]; R.slice[c] = F.color_slice[c]; }
-  k_fill_sell<<<nblk(F.n), kBlock, 0, s>>>(R, F.n, F.rp, F.ci, F.va, F.diag64, F.slice_ptr, F.s_row, F.s_col,
-                                            F.s_val64);
+  if (F.nslices)
+    k_fill_sell<<<nblk(64 * F.nslices), kBlock, 0, s>>>(F.nslices, F.slice_row0, F.rp, F.ci, F.va, F.diag64,
+                                                        F.slice_ptr, F.s_row, F.s_col, F.s_val64);
   QA_LAUNCH_CHECK();
   k_convert<double, float><<<nblk(F.sell_entries), kBlock, 0, s>>>(F.sell_entries, F.s_val64, F.s_val32);
   QA_LAUNCH_CHECK();
@@ -1447,6 +1568,28 @@ static amg_status build_block_factors(amg_hierarchy *h) {
   return block_values(h);
 }
 
+// first cell-data entry of each window: its first cell's factor offset (exact blocks) or its first row's in-cell
+// coupling offset (substitution)
+__global__ void __launch_bounds__(kBlock) k_win_entries(int64_t nwin, const int32_t *__restrict__ win_q,
+                                                         const int32_t *__restrict__ win_row,
+                                                         const int64_t *__restrict__ boff,
+                                                         const int32_t *__restrict__ icp,
+                                                         int64_t *__restrict__ win_ent) {
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w > nwin) return;
+  win_ent[w] = boff ? boff[win_q[w]] : static_cast<int64_t>(icp[win_row[w]]);
+}
+
+static amg_status build_window_entries(amg_hierarchy *h) {
+  FineLevel &F = h->fine;
+  F.win_ent = dalloc_n<int64_t>(h, F.nwin + 1);
+  if (!F.win_ent) return AMG_ERR_NOMEM;
+  k_win_entries<<<nblk(F.nwin + 1), kBlock, 0, h->stream>>>(F.nwin, F.win_q, F.win_row,
+                                                             h->opt.smoother ? F.boff : nullptr, F.ic_ptr, F.win_ent);
+  QA_LAUNCH_CHECK();
+  return AMG_OK;
+}
+
 static amg_status build_big_cells(amg_hierarchy *h) {
   FineLevel &F = h->fine;
   hipStream_t s = h->stream;
@@ -1566,6 +1709,7 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
   QA_TRY(ic_values(h));
   QA_TRY(build_big_cells(h));
   if (h->opt.smoother) QA_TRY(build_block_factors(h));
+  QA_TRY(build_window_entries(h));
 
   // Galerkin operators, level L first, then coarser
   h->lev.assign(h->nlev, QuadLevel{});

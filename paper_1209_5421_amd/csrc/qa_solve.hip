@@ -245,7 +245,8 @@ __device__ inline void fine_resid_body(const SellView<T> &S, const SliceSched &Z
   d[row] = f[row] - acc;
 }
 
-// residual of one color's rows (a smoother phase)
+// residual of one color's rows, for a smoother phase whose color has couplings between its own cells (the fused
+// phase below then reads it from d)
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_fine_resid(SellView<T> S, SliceSched Z, const T *__restrict__ f,
                                                         const T *__restrict__ x, T *__restrict__ d) {
@@ -274,147 +275,6 @@ __global__ void __launch_bounds__(kBlock) k_fine_apply(SellView<T> S, SliceSched
   y[row] = acc;
 }
 
-// In-cell substitution of one color phase: thread per cell q in [q_begin, q_end). FWD: delta_p = (r_p - sum_{c<p}
-// a_pc delta_c) / a_pp over the cell's rows ascending; else descending with c > p. r comes from src (the
-// residual pass, or f itself for the first phase of a sweep from zero); delta overwrites d; x += delta.
-// The rows of a workgroup's cells are one contiguous range, and so are their in-cell entries: the workgroup stages
-// both in LDS with coalesced loads, each thread runs its cell's substitution there (same order of operations), and
-// the deltas go back with coalesced stores. Rows of cells left to k_fine_subst_big are not touched. A range larger
-// than the staging arrays takes the same loop on global memory.
-constexpr int kSubstRows = 2048;
-constexpr int kSubstEnt = 4096;
-
-template <class T, bool FWD>
-__global__ void __launch_bounds__(kBlock) k_fine_subst(const int32_t *__restrict__ crow,
-                                                        const int32_t *__restrict__ icp,
-                                                        const int32_t *__restrict__ icc, const T *__restrict__ icv,
-                                                        const T *__restrict__ diag, const T *__restrict__ src,
-                                                        T *__restrict__ d, T *__restrict__ x, int64_t q_begin,
-                                                        int64_t q_end) {
-  __shared__ T s_r[kSubstRows], s_dg[kSubstRows], s_d[kSubstRows], s_val[kSubstEnt];
-  __shared__ int32_t s_ep[kSubstRows + 1];
-  __shared__ int16_t s_col[kSubstEnt];
-  __shared__ uint8_t s_mine[kSubstRows];
-  const int t = threadIdx.x;
-  const int64_t qb = q_begin + static_cast<int64_t>(blockIdx.x) * kBlock;
-  const int64_t qe = std::min<int64_t>(qb + kBlock, q_end);
-  const int64_t q = qb + t;
-  const int32_t r0 = crow[qb], r1 = crow[qe];
-  const int32_t ca = q < qe ? crow[q] : 0, cb = q < qe ? crow[q + 1] : 0;  // this thread's cell
-  const int32_t e0 = icp[r0], e1 = icp[r1];
-  const int nr = r1 - r0, ne = e1 - e0;
-  if (nr <= kSubstRows && ne <= kSubstEnt) {  // uniform over the workgroup
-    // every load of a thread is issued before the first store to LDS (unrolled over the staging capacity)
-    constexpr int kRowIt = kSubstRows / kBlock, kEntIt = kSubstEnt / kBlock;
-    T rv[kRowIt], dv[kRowIt], vv[kEntIt];
-    int32_t pv[kRowIt], cv[kEntIt];
-#pragma unroll
-    for (int u = 0; u < kRowIt; u++) {
-      const int i = t + u * kBlock;
-      if (i < nr) {
-        rv[u] = src[r0 + i];
-        dv[u] = diag[r0 + i];
-        pv[u] = icp[r0 + i];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kEntIt; u++) {
-      const int k = t + u * kBlock;
-      if (k < ne) {
-        cv[u] = icc[e0 + k];
-        vv[u] = icv[e0 + k];
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kRowIt; u++) {
-      const int i = t + u * kBlock;
-      if (i < nr) {
-        s_r[i] = rv[u];
-        s_dg[i] = dv[u];
-        s_ep[i] = pv[u] - e0;
-        s_mine[i] = 0;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < kEntIt; u++) {
-      const int k = t + u * kBlock;
-      if (k < ne) {
-        s_col[k] = static_cast<int16_t>(cv[u] - r0);
-        s_val[k] = vv[u];
-      }
-    }
-    if (t == 0) s_ep[nr] = ne;
-    __syncthreads();
-    if (q < qe) {
-      const int a = ca - r0, b = cb - r0;
-      if (b - a <= kBigCell) {
-        if (FWD) {
-          for (int p = a; p < b; p++) {
-            T acc = s_r[p];
-            for (int k = s_ep[p]; k < s_ep[p + 1]; k++) {
-              const int c = s_col[k];
-              if (c < p) acc -= s_val[k] * s_d[c];
-            }
-            s_d[p] = acc / s_dg[p];
-            s_mine[p] = 1;
-          }
-        } else {
-          for (int p = b - 1; p >= a; p--) {
-            T acc = s_r[p];
-            for (int k = s_ep[p]; k < s_ep[p + 1]; k++) {
-              const int c = s_col[k];
-              if (c > p) acc -= s_val[k] * s_d[c];
-            }
-            s_d[p] = acc / s_dg[p];
-            s_mine[p] = 1;
-          }
-        }
-      }
-    }
-    __syncthreads();
-    for (int i = t; i < nr; i += kBlock)
-      if (s_mine[i]) {
-        const T di = s_d[i];
-        d[r0 + i] = di;
-        x[r0 + i] += di;
-      }
-    return;
-  }
-  if (q >= qe) return;
-  const int32_t a = ca, b = cb;
-  if (b - a > kBigCell) return;  // k_fine_subst_big
-  if (FWD) {
-    for (int32_t p = a; p < b; p++) {
-      T acc = src[p];
-      for (int32_t e = icp[p]; e < icp[p + 1]; e++) {
-        const int32_t c = icc[e];
-        if (c < p) acc -= icv[e] * d[c];
-      }
-      d[p] = acc / diag[p];
-    }
-  } else {
-    for (int32_t p = b - 1; p >= a; p--) {
-      T acc = src[p];
-      for (int32_t e = icp[p]; e < icp[p + 1]; e++) {
-        const int32_t c = icc[e];
-        if (c > p) acc -= icv[e] * d[c];
-      }
-      d[p] = acc / diag[p];
-    }
-  }
-  for (int32_t p = a; p < b; p++) x[p] += d[p];
-}
-
-// Exact-block smoother (the other reading of Section 4.5's block Gauss-Seidel): each cell of at most kBlockMax
-// unknowns in [q_begin, q_end) solves L L^t delta = r with its Cholesky factor (forward, then backward, each row's
-// products over the earlier rows in ascending order); delta overwrites d; x += delta. The same in both sweep
-// directions. One thread per cell. A workgroup's cells hold a contiguous range of rows and of factor values: both
-// are staged in LDS with coalesced loads, each thread solves in place there, and the deltas go back with coalesced
-// stores (rows of cells left to k_fine_subst_big untouched). A range larger than the staging arrays takes the same
-// arithmetic on global memory.
-constexpr int kBlkRows = 2048;
-constexpr int kBlkFac = 8192;
-
 // L L^t v = v in place, L packed lower triangle (row i holds L_i0 .. L_ii), v with the given element stride
 template <class T>
 __device__ inline void block_solve(const T *Lf, int m, T *v, int stride) {
@@ -431,70 +291,171 @@ __device__ inline void block_solve(const T *Lf, int m, T *v, int stride) {
   }
 }
 
+// One color phase of the fine-level smoother (Section 4.5), fused: a workgroup per window (a run of whole cells of
+// the color and the sliced-ELL slices of exactly their rows).
+//  1. The residual r = f - A u of the window's rows, one wavefront per slice with the residual pass's arithmetic,
+//     kept in LDS; with GIVEN, r is read from src instead (f for the first phase of a sweep from zero, or d filled
+//     by k_fine_resid when cells of the color are coupled to each other, which a fused residual would race with).
+//  2. Each cell of at most CMAX unknowns is solved there by one thread: SM = 1, the exact block L L^t delta = r with
+//     the cell's Cholesky factor; SM = 0, the in-cell substitution, delta_p = (r_p - sum a_pc delta_c) / a_pp over
+//     the cell's rows ascending (FWD, c < p) or descending (c > p).
+//  3. u += delta with coalesced stores. The rows of larger cells get r in d instead, for k_fine_subst_big.
+// The window's cell bounds, rows of u, factor values and in-cell couplings are contiguous and staged in LDS with
+// coalesced loads issued together with the residual's, so the kernel waits on few dependent round trips to memory;
+// a window beyond the staging arrays (only around cells larger than CMAX, or many empty cells) takes the same
+// arithmetic on global memory. Without GIVEN the color's cells are not coupled to each other, so the workgroups are
+// independent; u of a window's rows changes only in its own workgroup.
+constexpr int kFuseRows = 512;
+constexpr int kFuseEnt = 2048;   // factor values (exact blocks) or in-cell couplings (substitution) staged
+constexpr int kFuseCells = 512;
+
 template <class T>
-__global__ void __launch_bounds__(kBlock) k_fine_block(const int32_t *__restrict__ crow,
-                                                        const int64_t *__restrict__ boff, const T *__restrict__ fac,
-                                                        const T *__restrict__ src, T *__restrict__ d,
-                                                        T *__restrict__ x, int64_t q_begin, int64_t q_end) {
-  __shared__ T s_r[kBlkRows];
-  __shared__ T s_f[kBlkFac];
-  __shared__ uint8_t s_mine[kBlkRows];
-  const int t = threadIdx.x;
-  const int64_t qb = q_begin + static_cast<int64_t>(blockIdx.x) * kBlock;
-  const int64_t qe = std::min<int64_t>(qb + kBlock, q_end);
-  const int64_t q = qb + t;
-  const int32_t r0 = crow[qb], r1 = crow[qe];
-  const int64_t f0 = boff[qb], f1 = boff[qe];
-  const int32_t ca = q < qe ? crow[q] : 0, cb = q < qe ? crow[q + 1] : 0;
-  const int64_t fo = q < qe ? boff[q] : 0;
-  const int nr = r1 - r0;
-  const int64_t nf = f1 - f0;
-  const int m = cb - ca;
-  if (nr <= kBlkRows && nf <= kBlkFac) {  // uniform over the workgroup
-    constexpr int kRowIt = kBlkRows / kBlock, kFacIt = kBlkFac / kBlock;
-    T rv[kRowIt];
-#pragma unroll
-    for (int u = 0; u < kRowIt; u++) {
-      const int i = t + u * kBlock;
-      if (i < nr) rv[u] = src[r0 + i];
-    }
-#pragma unroll
-    for (int u = 0; u < kFacIt; u++) {
-      const int k = t + u * kBlock;
-      if (k < nf) s_f[k] = fac[f0 + k];
-    }
-#pragma unroll
-    for (int u = 0; u < kRowIt; u++) {
-      const int i = t + u * kBlock;
-      if (i < nr) {
-        s_r[i] = rv[u];
-        s_mine[i] = 0;
-      }
-    }
-    __syncthreads();
-    if (q < qe && m > 0 && m <= kBlockMax) {
-      block_solve<T>(s_f + (fo - f0), m, s_r + (ca - r0), 1);
-      for (int i = 0; i < m; i++) s_mine[ca - r0 + i] = 1;
-    }
-    __syncthreads();
-    for (int i = t; i < nr; i += kBlock)
-      if (s_mine[i]) {
-        const T v = s_r[i];
-        d[r0 + i] = v;
-        x[r0 + i] += v;
-      }
-    return;
+struct FuseArgs {
+  const int32_t *win_q, *win_row, *crow;
+  const int64_t *win_slice, *win_ent;
+  int64_t win0, nwin;            // this color's windows
+  int xcd;                       // 1: XCD-aware window order (grid = 8 x the largest per-XCD share)
+  int big;                       // the color has cells left to k_fine_subst_big: write their residual to d
+  const T *f, *src;              // src: the given residual (GIVEN)
+  T *u, *d;
+  const T *diag, *icv, *fac;
+  const int32_t *icp, *icc;
+  const int64_t *boff;
+};
+
+template <class T, int SM, bool FWD, bool GIVEN>
+__global__ void __launch_bounds__(kBlock) k_fine_gs(SellView<T> S, FuseArgs<T> A) {
+  constexpr int CMAX = SM ? kBlockMax : kBigCell;
+  __shared__ T s_r[kFuseRows];                   // residual (SM = 1: then the delta, in place)
+  __shared__ T s_u[kFuseRows];                   // u of the window's rows
+  __shared__ T s_x[SM ? kFuseEnt : kFuseRows];   // factor values (SM = 1) or the deltas (SM = 0)
+  __shared__ T s_dg[SM ? 1 : kFuseRows];
+  __shared__ T s_val[SM ? 1 : kFuseEnt];
+  __shared__ int32_t s_ep[SM ? 1 : kFuseRows + 1];
+  __shared__ int16_t s_col[SM ? 1 : kFuseEnt];
+  __shared__ int32_t s_cr[kFuseCells + 1];       // cell bounds relative to the first row
+  __shared__ int32_t s_cf[SM ? kFuseCells + 1 : 1];  // factor offsets relative to the first value
+  __shared__ uint8_t s_mine[kFuseRows];
+  int64_t w;
+  if (A.xcd) {
+    const int64_t x = blockIdx.x & 7u, p = blockIdx.x >> 3;
+    const int64_t b0 = A.nwin * x / 8, b1 = A.nwin * (x + 1) / 8;
+    if (p >= b1 - b0) return;
+    w = A.win0 + b0 + p;
+  } else {
+    w = A.win0 + blockIdx.x;
   }
-  // the staging arrays are free here: the factor array becomes one kBlockMax slice per thread
-  static_assert(kBlkFac >= kBlockMax * kBlock, "per-thread slices");
-  if (q >= qe || m == 0 || m > kBlockMax) return;  // empty, or left to k_fine_subst_big
-  T *v = s_f + t;
-  for (int i = 0; i < m; i++) v[i * kBlock] = src[ca + i];
-  block_solve<T>(fac + fo, m, v, kBlock);
-  for (int i = 0; i < m; i++) {
-    const T di = v[i * kBlock];
-    d[ca + i] = di;
-    x[ca + i] += di;
+  const int t = threadIdx.x, lane = t & 63;
+  const int32_t q0 = A.win_q[w], q1 = A.win_q[w + 1];
+  const int32_t r0 = A.win_row[w], r1 = A.win_row[w + 1];
+  const int64_t sl0 = A.win_slice[w], sl1 = A.win_slice[w + 1];
+  const int64_t e0 = A.win_ent[w], ne = A.win_ent[w + 1] - e0;
+  const int nr = r1 - r0, nq = q1 - q0;
+  const bool staged = nr <= kFuseRows && ne <= kFuseEnt && nq <= kFuseCells;  // uniform over the workgroup
+  if (staged) {
+    for (int k = t; k <= nq; k += kBlock) {
+      s_cr[k] = A.crow[q0 + k] - r0;
+      if constexpr (SM) s_cf[k] = static_cast<int32_t>(A.boff[q0 + k] - e0);
+    }
+    for (int k = t; k < ne; k += kBlock) {
+      if constexpr (SM) {
+        s_x[k] = A.fac[e0 + k];
+      } else {
+        s_col[k] = static_cast<int16_t>(A.icc[e0 + k] - r0);
+        s_val[k] = A.icv[e0 + k];
+      }
+    }
+    for (int i = t; i < nr; i += kBlock) {
+      s_u[i] = A.u[r0 + i];
+      if constexpr (!SM) {
+        s_dg[i] = A.diag[r0 + i];
+        s_ep[i] = static_cast<int32_t>(A.icp[r0 + i] - e0);
+      }
+      if constexpr (GIVEN) s_r[i] = A.src[r0 + i];
+      s_mine[i] = 0;
+    }
+    if constexpr (!SM)
+      if (t == 0) s_ep[nr] = static_cast<int32_t>(ne);
+  }
+  if constexpr (!GIVEN) {
+    // slice k of the window holds the positions r0 + 64 k .. (rows of the window, sorted by length)
+    for (int64_t sl = sl0 + (t >> 6); sl < sl1; sl += kBlock / 64) {
+      const int32_t p = r0 + static_cast<int32_t>(sl - sl0) * kSliceRows + lane;
+      if (p < r1) {
+        const int32_t row = S.srow[p];
+        const int64_t off = S.ptr[sl];
+        const int wd = static_cast<int>((S.ptr[sl + 1] - off) >> 6);
+        const T r = A.f[row] - sell_row<T, T>(S, off, wd, lane, A.u);
+        if (staged) s_r[row - r0] = r;
+        else A.d[row] = r;
+      }
+    }
+  } else {
+    if (!staged && A.src != A.d)
+      for (int i = t; i < nr; i += kBlock) A.d[r0 + i] = A.src[r0 + i];
+  }
+  __syncthreads();  // also orders the global residual writes of the unstaged path within the workgroup
+  for (int j = t; j < nq; j += kBlock) {
+    if (staged) {
+      const int a = s_cr[j], b = s_cr[j + 1];
+      const int m = b - a;
+      if (m == 0 || m > CMAX) continue;
+      if constexpr (SM) {
+        block_solve<T>(s_x + s_cf[j], m, s_r + a, 1);
+      } else if constexpr (FWD) {
+        for (int p = a; p < b; p++) {
+          T acc = s_r[p];
+          for (int k = s_ep[p]; k < s_ep[p + 1]; k++) {
+            const int c = s_col[k];
+            if (c < p) acc -= s_val[k] * s_x[c];
+          }
+          s_x[p] = acc / s_dg[p];
+        }
+      } else {
+        for (int p = b - 1; p >= a; p--) {
+          T acc = s_r[p];
+          for (int k = s_ep[p]; k < s_ep[p + 1]; k++) {
+            const int c = s_col[k];
+            if (c > p) acc -= s_val[k] * s_x[c];
+          }
+          s_x[p] = acc / s_dg[p];
+        }
+      }
+      for (int i = a; i < b; i++) s_mine[i] = 1;
+    } else {
+      const int32_t ca = A.crow[q0 + j], cb = A.crow[q0 + j + 1];
+      const int m = cb - ca;
+      if (m == 0 || m > CMAX) continue;
+      T *dd = A.d;
+      if constexpr (SM) {
+        block_solve<T>(A.fac + A.boff[q0 + j], m, dd + ca, 1);
+      } else if constexpr (FWD) {
+        for (int32_t p = ca; p < cb; p++) {
+          T acc = dd[p];
+          for (int32_t e = A.icp[p]; e < A.icp[p + 1]; e++) {
+            const int32_t c = A.icc[e];
+            if (c < p) acc -= A.icv[e] * dd[c];
+          }
+          dd[p] = acc / A.diag[p];
+        }
+      } else {
+        for (int32_t p = cb - 1; p >= ca; p--) {
+          T acc = dd[p];
+          for (int32_t e = A.icp[p]; e < A.icp[p + 1]; e++) {
+            const int32_t c = A.icc[e];
+            if (c > p) acc -= A.icv[e] * dd[c];
+          }
+          dd[p] = acc / A.diag[p];
+        }
+      }
+      for (int32_t p = ca; p < cb; p++) A.u[p] += dd[p];
+    }
+  }
+  if (!staged) return;
+  __syncthreads();
+  for (int i = t; i < nr; i += kBlock) {
+    if (s_mine[i]) A.u[r0 + i] = s_u[i] + (SM ? s_r[i] : s_x[i]);
+    else if (A.big && !GIVEN) A.d[r0 + i] = s_r[i];
   }
 }
 
@@ -2412,23 +2373,53 @@ static void fine_resid(amg_hierarchy *h, const T *f, const T *x, T *d, int c0, i
     launch_timed(h, kind, k_fine_resid<T>, grid, sview<T>(h->fine, P<T>::sval(h->fine)), Z, f, x, d);
 }
 
+template <class T, int SM, bool FWD, bool GIVEN>
+static void fine_gs_launch(amg_hierarchy *h, unsigned grid, const FuseArgs<T> &A) {
+  launch_timed(h, P<T>::kGs, k_fine_gs<T, SM, FWD, GIVEN>, grid, sview<T>(h->fine, P<T>::sval(h->fine)), A);
+}
+
+// One color phase of the fine smoother: the fused residual and cell solves (k_fine_gs), then the cells left to the
+// level-scheduled substitution. from_f: the first phase of a sweep from zero, whose residual is f.
 template <class T>
 static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd, bool from_f) {
   const FineLevel &F = h->fine;
-  const int64_t nL4 = (static_cast<int64_t>(1) << (h->dim * h->L)) / F.ncolor;  // cells of one color
-  const T *src = d;
-  if (from_f) src = f;
-  else fine_resid<T>(h, f, u, d, c, c + 1, P<T>::kGs);
-  const int64_t q0 = c * nL4, q1 = (c + 1) * nL4;
-  if (h->opt.smoother)
-    k_fine_block<T><<<nblk(nL4), kBlock, 0, h->stream>>>(F.crow, F.boff, P<T>::bfac(F), src, d, u, q0, q1);
-  else if (fwd)
-    k_fine_subst<T, true><<<nblk(nL4), kBlock, 0, h->stream>>>(F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F),
-                                                                P<T>::diag(F), src, d, u, q0, q1);
-  else
-    k_fine_subst<T, false><<<nblk(nL4), kBlock, 0, h->stream>>>(F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F),
-                                                                 P<T>::diag(F), src, d, u, q0, q1);
+  const T *src = from_f ? f : d;
+  const bool given = from_f || F.same_color;
+  if (!from_f && F.same_color) fine_resid<T>(h, f, u, d, c, c + 1, -1);
   const int64_t b0 = F.big_color[c], nb = F.big_color[c + 1] - b0;
+  FuseArgs<T> A{};
+  A.win_q = F.win_q;
+  A.win_row = F.win_row;
+  A.crow = F.crow;
+  A.win_slice = F.win_slice;
+  A.win_ent = F.win_ent;
+  A.win0 = F.color_win[c];
+  A.nwin = F.color_win[c + 1] - F.color_win[c];
+  A.xcd = A.nwin >= 64 ? 1 : 0;
+  A.big = nb > 0 ? 1 : 0;
+  A.f = f;
+  A.src = src;
+  A.u = u;
+  A.d = d;
+  A.diag = P<T>::diag(F);
+  A.icv = P<T>::icv(F);
+  A.fac = P<T>::bfac(F);
+  A.icp = F.ic_ptr;
+  A.icc = F.ic_col;
+  A.boff = F.boff;
+  if (A.nwin > 0) {
+    const unsigned grid = static_cast<unsigned>(A.xcd ? 8 * ((A.nwin + 7) / 8) : A.nwin);
+    if (h->opt.smoother) {
+      if (given) fine_gs_launch<T, 1, true, true>(h, grid, A);
+      else fine_gs_launch<T, 1, true, false>(h, grid, A);
+    } else if (fwd) {
+      if (given) fine_gs_launch<T, 0, true, true>(h, grid, A);
+      else fine_gs_launch<T, 0, true, false>(h, grid, A);
+    } else {
+      if (given) fine_gs_launch<T, 0, false, true>(h, grid, A);
+      else fine_gs_launch<T, 0, false, false>(h, grid, A);
+    }
+  }
   if (nb > 0) {
     const int dir = fwd ? 0 : 1;
     if (fwd)
@@ -2623,8 +2614,14 @@ double kernel_bytes(const amg_hierarchy *h, int kind) {
     case KK_SPMV64: return 12.0 * nnz + 24.0 * n;   // values + columns, x, q written, r read for (r, p)
     case KK_RESID_FINE64: return 12.0 * nnz + 24.0 * n;
     case KK_RESID_FINE32: return 8.0 * nnz + 12.0 * n;
-    case KK_GS_FINE64: return (12.0 * nnz + 24.0 * n) / 4.0;
-    case KK_GS_FINE32: return (8.0 * nnz + 12.0 * n) / 4.0;
+    // one fused color phase: the color's share of the residual pass (f read, x read, x written) and of the cell
+    // solves' data (factor values, or in-cell couplings and the diagonal)
+    case KK_GS_FINE64:
+      return (12.0 * nnz + 24.0 * n +
+              (h->opt.smoother ? 8.0 * h->fine.bfac_n : 12.0 * h->fine.ic_nnz + 8.0 * n)) / h->fine.ncolor;
+    case KK_GS_FINE32:
+      return (8.0 * nnz + 12.0 * n +
+              (h->opt.smoother ? 4.0 * h->fine.bfac_n : 8.0 * h->fine.ic_nnz + 4.0 * n)) / h->fine.ncolor;
     case KK_ENGINE64: return h->engine_flops[0];
     case KK_ENGINE32: return h->engine_flops[1];
   }
@@ -2917,27 +2914,26 @@ static size_t wg_batch_bytes(size_t m) {
   return sizeof(WgSys<T>) * m + sizeof(double) * 4 * m;
 }
 
+// sys: host staging for the m descriptors, out: 4 m doubles
 template <class T>
 static amg_status launch_wg_batch_in(amg_hierarchy *const *hs, const double *const *b, double *const *x,
-                                     const double *tol, const std::vector<int> &ids, void *buf,
-                                     std::vector<double> &out) {
+                                     const double *tol, const int *ids, int m, void *buf, WgSys<T> *sys,
+                                     double *out) {
   const int pi = std::is_same<T, float>::value ? 1 : 0;
-  const int m = static_cast<int>(ids.size());
   hipStream_t s = hs[ids[0]]->stream;
   const size_t sys_bytes = sizeof(WgSys<T>) * m;
   double *info_d = reinterpret_cast<double *>(static_cast<char *>(buf) + sys_bytes);
-  std::vector<WgSys<T>> sys(m);
   size_t lds = 0;
   for (int j = 0; j < m; j++) {
     const int i = ids[j];
     fill_wg<T>(hs[i], b[i], x[i], tol[i], info_d + 4 * j, sys[j]);
     lds = std::max(lds, hs[i]->wg_lds[pi]);
   }
-  QA_HIP(hipMemcpyAsync(buf, sys.data(), sys_bytes, hipMemcpyHostToDevice, s));
+  QA_HIP(hipMemcpyAsync(buf, sys, sys_bytes, hipMemcpyHostToDevice, s));
   k_solve_wg<T><<<m, kEngThreads, lds, s>>>(static_cast<const WgSys<T> *>(buf));
   QA_LAUNCH_CHECK();
-  out.assign(4 * m, 0.0);
-  QA_HIP(hipMemcpyAsync(out.data(), info_d, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, s));
+  for (int j = 0; j < 4 * m; j++) out[j] = 0.0;
+  QA_HIP(hipMemcpyAsync(out, info_d, sizeof(double) * 4 * m, hipMemcpyDeviceToHost, s));
   QA_HIP(hipStreamSynchronize(s));
   return AMG_OK;
 }
@@ -2949,15 +2945,18 @@ static amg_status launch_wg_batch(amg_hierarchy *const *hs, const double *const 
   hipStream_t s = hs[ids[0]]->stream;
   void *buf = tmp_alloc(hs[ids[0]], s, wg_batch_bytes<T>(ids.size()));
   if (!buf) return AMG_ERR_NOMEM;
-  const amg_status st = launch_wg_batch_in<T>(hs, b, x, tol, ids, buf, out);
+  std::vector<WgSys<T>> sys(ids.size());
+  out.assign(4 * ids.size(), 0.0);
+  const amg_status st =
+      launch_wg_batch_in<T>(hs, b, x, tol, ids.data(), static_cast<int>(ids.size()), buf, sys.data(), out.data());
   tmp_free(hs[ids[0]], s, buf);  // on every path
   return st;
 }
 
 // Per-system results of whole-solve launches into st / inf.
-static void wg_results(amg_hierarchy *const *hs, const std::vector<int> &ids, const std::vector<double> &out,
-                       double ms, std::vector<amg_status> &st, std::vector<amg_info> &inf) {
-  for (size_t j = 0; j < ids.size(); j++) {
+static void wg_results(amg_hierarchy *const *hs, const int *ids, int m, const double *out, double ms,
+                       amg_status *st, amg_info *inf) {
+  for (int j = 0; j < m; j++) {
     const int i = ids[j];
     st[i] = static_cast<amg_status>(static_cast<int>(out[4 * j]));
     inf[i].iters = static_cast<int32_t>(out[4 * j + 1]);
@@ -3014,8 +3013,9 @@ extern "C" amg_status amg_solve_batch(amg_hierarchy *const *hs, const double *co
     launch_st = pi == 0 ? launch_wg_batch<double>(hs, b, x, tol, small[pi], out)
                         : launch_wg_batch<float>(hs, b, x, tol, small[pi], out);
     if (launch_st != AMG_OK) break;
-    wg_results(hs, small[pi], out,
-               std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(), st, inf);
+    wg_results(hs, small[pi].data(), static_cast<int>(small[pi].size()), out.data(),
+               std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(), st.data(),
+               inf.data());
   }
   for (auto &t : threads) t.join();
   amg_status first = launch_st;
