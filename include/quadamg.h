@@ -163,6 +163,17 @@ amg_status amg_set_stream(amg_hierarchy *h, void *stream);
 amg_status amg_solve_batch(amg_hierarchy *const *h, const double *const *b, double *const *x, const double *tol,
                            int32_t count, amg_info *info);
 
+/* amg_solve_batch for callers that cannot allocate device memory (code under HIP graph capture, serving loops that
+ * forbid allocation): the same whole-solve launches and results, with the per-call system descriptors and info words
+ * held in a device array of the library's own (about 400 KB per device, kept until the process ends) instead of
+ * memory allocated per call. No hipMalloc, hipFree or other allocating call is made. Every system must take the
+ * whole-solve route (options.batch = 1, the default fine smoother, at most 65,536 unknowns); count must not exceed
+ * 256. Errors, before any device work: AMG_ERR_INVALID for those conditions or the arguments amg_solve_batch
+ * rejects. All calls on one device share the array: calls that overlap in time on one device race and must be
+ * serialised by the caller. */
+amg_status amg_solve_batch_noalloc(amg_hierarchy *const *h, const double *const *b, double *const *x,
+                                   const double *tol, int32_t count, amg_info *info);
+
 /* Upper estimate of the device bytes a hierarchy for an n-unknown, nnz-entry system needs, workspace included
  * (used for admission by memory footprint). */
 amg_status amg_estimate_bytes(int64_t n, int64_t nnz, const amg_options *opt, size_t *bytes);

@@ -17,7 +17,7 @@ OK, INVALID, NOMEM, DEVICE, NOT_SPD, BREAKDOWN, NOCONV = range(7)
 STATUS = {0: "AMG_OK", 1: "AMG_ERR_INVALID", 2: "AMG_ERR_NOMEM", 3: "AMG_ERR_DEVICE", 4: "AMG_ERR_NOT_SPD",
           5: "AMG_ERR_BREAKDOWN", 6: "AMG_ERR_NOCONV"}
 EXPORTED = ["amg_default_options", "amg_setup", "amg_setup3d", "amg_update_values", "amg_solve", "amg_free", "amg_set_precision", "amg_set_stream",
-            "amg_solve_batch", "amg_estimate_bytes", "amg_hierarchy_bytes", "amg_num_levels", "amg_level_info",
+            "amg_solve_batch", "amg_solve_batch_noalloc", "amg_estimate_bytes", "amg_hierarchy_bytes", "amg_num_levels", "amg_level_info",
             "amg_export_level", "amg_export_level_f32", "amg_apply_precond", "amg_level_smooth", "amg_level_spmv",
             "amg_kernel_timing_enable", "amg_kernel_timing_read", "amg_engine_info", "amg_p1_mesh_create",
             "amg_p1_mesh_pattern", "amg_p1_assemble", "amg_p1_mesh_free", "amg_status_string"]
@@ -104,6 +104,8 @@ def load(path: str = LIB_PATH):
     L.amg_set_precision.argtypes = [p, i32]
     L.amg_set_stream.argtypes = [p, p]
     L.amg_solve_batch.argtypes = [C.POINTER(p), C.POINTER(p), C.POINTER(p), C.POINTER(d), i32, C.POINTER(Info)]
+    L.amg_solve_batch_noalloc.argtypes = [C.POINTER(p), C.POINTER(p), C.POINTER(p), C.POINTER(d), i32,
+                                          C.POINTER(Info)]
     L.amg_estimate_bytes.argtypes = [i64, i64, C.POINTER(Options), C.POINTER(C.c_size_t)]
     L.amg_hierarchy_bytes.argtypes = [p, C.POINTER(C.c_size_t)]
     L.amg_num_levels.argtypes = [p, C.POINTER(i32)]
@@ -346,15 +348,17 @@ class Hierarchy:
         return dict(launches=n.value, total_ms=ms.value, bytes_per_launch=b.value)
 
 
-def solve_batch(hiers, bs, xs, tols):
-    """amg_solve_batch over distinct hierarchies; returns (first status, list of info dicts)."""
+def solve_batch(hiers, bs, xs, tols, noalloc=False):
+    """amg_solve_batch (or amg_solve_batch_noalloc) over distinct hierarchies; returns (first status, list of info
+    dicts)."""
     n = len(hiers)
     H = (C.c_void_p * n)(*[h._h for h in hiers])
     B = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
     X = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
     T = (C.c_double * n)(*[float(t) for t in tols])
     infos = (Info * n)()
-    code = load().amg_solve_batch(H, B, X, T, n, infos)
+    fn = load().amg_solve_batch_noalloc if noalloc else load().amg_solve_batch
+    code = fn(H, B, X, T, n, infos)
     return code, [i.as_dict() for i in infos]
 
 

@@ -2980,6 +2980,45 @@ static amg_status check_batch_args(amg_hierarchy *const *hs, const double *const
   return AMG_OK;
 }
 
+// ---------------------------------------------------------------------------------------------------------------
+// Batch solve without allocation. The system descriptors and info words of the whole-solve launches live in a
+// file-scope device array instead of memory allocated per call. The array's name is only a host-side handle: its
+// device address is looked up once per device (with that device current) and every use goes through that address.
+
+constexpr int kNoAllocMaxSystems = 256;
+constexpr size_t kNoAllocBytes =
+    (std::max(sizeof(WgSys<double>), sizeof(WgSys<float>)) + sizeof(double) * 4) * kNoAllocMaxSystems;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static void *g_scratch_ptr[kMaxDevices];
+static std::once_flag g_scratch_once[kMaxDevices];
+static hipError_t g_scratch_err[kMaxDevices];
+
+// device address of `scratch` on `device` (made current by the caller), or null
+static void *scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::call_once(g_scratch_once[device], [device]() {
+    void *p = nullptr;
+    g_scratch_err[device] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_scratch_ptr[device] = g_scratch_err[device] == hipSuccess ? p : nullptr;
+  });
+  return g_scratch_ptr[device];
+}
+
+// Host staging of the calls, also static (no heap use per call). Calls are serialised by g_noalloc_mu: they share
+// these arrays and, on one device, the device array.
+struct NoAllocStage {
+  WgSys<double> sys64[kNoAllocMaxSystems];
+  WgSys<float> sys32[kNoAllocMaxSystems];
+  double out[4 * kNoAllocMaxSystems];
+  int ids[2][kNoAllocMaxSystems];
+  amg_status st[kNoAllocMaxSystems];
+  amg_info inf[kNoAllocMaxSystems];
+};
+static NoAllocStage g_stage;
+static std::mutex g_noalloc_mu;
+
 }  // namespace qa
 
 extern "C" amg_status amg_solve_batch(amg_hierarchy *const *hs, const double *const *b, double *const *x,
@@ -3024,6 +3063,50 @@ extern "C" amg_status amg_solve_batch(amg_hierarchy *const *hs, const double *co
     inf[i].status = st[i];
     if (info) info[i] = inf[i];
     if (first == AMG_OK && st[i] != AMG_OK) first = st[i];
+  }
+  return first;
+}
+
+extern "C" amg_status amg_solve_batch_noalloc(amg_hierarchy *const *hs, const double *const *b, double *const *x,
+                                              const double *tol, int32_t count, amg_info *info) {
+  QA_TRY(check_batch_args(hs, b, x, tol, count));
+  if (count > kNoAllocMaxSystems) return AMG_ERR_INVALID;
+  if (count == 0) return AMG_OK;
+  for (int32_t i = 0; i < count; i++) {
+    const int pi = hs[i]->precision;
+    if (!(hs[i]->use_batch && hs[i]->wg_nops[pi] > 0)) return AMG_ERR_INVALID;  // only whole-solve systems
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  NoAllocStage &G = g_stage;
+  int nsmall[2] = {0, 0};
+  for (int32_t i = 0; i < count; i++) {
+    const int pi = hs[i]->precision;
+    G.ids[pi][nsmall[pi]++] = i;
+    G.st[i] = AMG_OK;
+    G.inf[i] = amg_info{};
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  QA_HIP(hipSetDevice(hs[0]->device));
+  char *base = static_cast<char *>(scratch_ptr(hs[0]->device));
+  if (!base) return AMG_ERR_DEVICE;
+  for (int32_t i = 0; i < count; i++) QA_HIP(hipStreamSynchronize(hs[i]->stream));
+  // the FP64 group's descriptors first, the FP32 group's after them: disjoint parts of the array
+  const size_t off[2] = {0, wg_batch_bytes<double>(nsmall[0])};
+  amg_status first = AMG_OK;
+  for (int pi = 0; pi < 2 && first == AMG_OK; pi++) {
+    if (nsmall[pi] == 0) continue;
+    first = pi == 0 ? launch_wg_batch_in<double>(hs, b, x, tol, G.ids[0], nsmall[0], base + off[0], G.sys64, G.out)
+                    : launch_wg_batch_in<float>(hs, b, x, tol, G.ids[1], nsmall[1], base + off[1], G.sys32, G.out);
+    if (first == AMG_OK)
+      wg_results(hs, G.ids[pi], nsmall[pi], G.out,
+                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count(), G.st,
+                 G.inf);
+  }
+  for (int32_t i = 0; i < count; i++) {
+    if (first != AMG_OK) G.st[i] = first;
+    G.inf[i].status = G.st[i];
+    if (info) info[i] = G.inf[i];
+    if (first == AMG_OK && G.st[i] != AMG_OK) first = G.st[i];
   }
   return first;
 }
