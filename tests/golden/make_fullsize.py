@@ -7,8 +7,9 @@ Test infrastructure: this script calls only the CPU oracle (oracle/) and the see
   same system;
 - SHA-256 digests of every exported level of the oracle's hierarchy: the aggregates and colors, and per quadtree
   level the 9-slot columns, the FP64 values, their FP32 rounding and the overflow lists;
-- the oracle's FP64 solves (Algorithm 2.1 with the K-cycle of Algorithm 2.2) to 1e-8, and to 1e-12 where a mixed
-  precision solve is compared, as iteration counts, true relative residuals, solution norms and the solution at
+- the oracle's FP64 solves (Algorithm 2.1 with the K-cycle of Algorithm 2.2) to 1e-8, and to a tighter reference
+  tolerance (1e-12, or 1e-11 where FP64 cannot reach 1e-12) against which the mixed-precision solve is compared, as
+  iteration counts, true relative residuals, solution norms and the solution at
   512 seeded sample indices;
 - one application of the preconditioner to a seeded vector, at the same sample indices.
 
@@ -36,11 +37,14 @@ N_SAMPLES = 512
 SAMPLE_SEED = 17
 PRECOND_SEED = 5
 
+# workload: (description, generator, tolerance of the reference solve the mixed-precision form is compared with, or
+# None). On the checkerboard (coefficients spanning six decades) the FP64 true residual stalls near 5e-12, so its
+# reference is solved to 1e-11, the smallest attainable power of ten.
 WORKLOADS = {
-    "c2": ("quasi-uniform jittered Delaunay 1024x1024", lambda: mg.jittered_problem(1024), True),
+    "c2": ("quasi-uniform jittered Delaunay 1024x1024", lambda: mg.jittered_problem(1024), 1e-12),
     "c4": ("jittered Delaunay 1416x1416, 16x16 kappa checkerboard", lambda: mg.jittered_problem(1416, kappa_tiles=16),
-           True),
-    "c3": ("graded Delaunay, 4.0M points", lambda: mg.graded_problem(4_000_000), False),
+           1e-11),
+    "c3": ("graded Delaunay, 4.0M points", lambda: mg.graded_problem(4_000_000), None),
 }
 
 
@@ -76,7 +80,7 @@ def log(msg):
 
 
 def make(name):
-    desc, gen, with_12 = WORKLOADS[name]
+    desc, gen, ref_tol = WORKLOADS[name]
     t = time.time()
     prob = gen()
     log(f"{name}: n={prob.n} nnz={prob.nnz} generated in {time.time() - t:.1f}s")
@@ -96,12 +100,13 @@ def make(name):
              "precond": {"z_samples": z[idx].tolist(), "z_norm": float(np.linalg.norm(z))},
              "tol_1e-8": {"iters": i8["iters"], "relres": i8["relres"], "x_norm": float(np.linalg.norm(x8)),
                           "x_samples": x8[idx].tolist()}}
-        if with_12:
+        if ref_tol:
             t = time.time()
-            x12, i12 = o.solve(prob.b, tol=1e-12)
-            log(f"{name} smoother {smoother}: 1e-12 in {i12['iters']} iterations, {time.time() - t:.1f}s")
-            s["tol_1e-12"] = {"iters": i12["iters"], "relres": i12["relres"], "x_norm": float(np.linalg.norm(x12)),
-                              "x_samples": x12[idx].tolist()}
+            xr, ir = o.solve(prob.b, tol=ref_tol)
+            assert ir["status"] == 0, ir
+            log(f"{name} smoother {smoother}: {ref_tol:g} in {ir['iters']} iterations, {time.time() - t:.1f}s")
+            s["reference"] = {"tol": ref_tol, "iters": ir["iters"], "relres": ir["relres"],
+                              "x_norm": float(np.linalg.norm(xr)), "x_samples": xr[idx].tolist()}
         rec["smoothers"][str(smoother)] = s
     o.close()
     path = os.path.join(OUT, f"fullsize_{name}.json")

@@ -10,7 +10,8 @@ readings of the fine smoother), against expected values the oracle wrote (tests/
   - the FP64 solve to 1e-8 takes the oracle's iteration count +-1 and is within 1e-6 of the oracle's solution
     (relative error over the same 512 entries, and of the norm);
   - the mixed-precision solve (FP32 preconditioner, FP64 outer iteration) reaches a true relative residual of 1e-8
-    and is within 1e-6 of the oracle's FP64 solution (solved to 1e-12 where stored, else to 1e-8).
+    and is within 1e-6 of the oracle's FP64 solution solved to the stored reference tolerance (1e-12 on the
+    quasi-uniform mesh, 1e-11 on the checkerboard, where FP64 stalls near 5e-12), else to 1e-8.
 The oracle itself takes minutes per solve at these sizes; its results are stored, not recomputed here.
 """
 import json
@@ -150,11 +151,10 @@ def test_fullsize_parity(name):
         h.set_precision(1)
         xm, im = h.solve(T(prob.b), tol=1e-8)
         xm = xm.cpu().numpy()
-        rm = ref.get("tol_1e-12", r8)
+        rm = ref.get("reference", dict(r8, tol=1e-8))
         em, emn = sampled_err(xm, rm["x_samples"], rm["x_norm"], idx)
         log(f"{name} smoother {smoother}: precond err {ez:.1e}; fp64 iters {info['iters']} (oracle {r8['iters']}) "
-            f"err {e:.1e}; fp32-precond iters {im['iters']} err vs fp64 oracle "
-            f"({'1e-12' if 'tol_1e-12' in ref else '1e-8'}) {em:.1e}")
+            f"err {e:.1e}; fp32-precond iters {im['iters']} err vs fp64 oracle ({rm['tol']:g}) {em:.1e}")
         assert im["status"] == 0 and np.linalg.norm(A @ xm - prob.b) <= 1e-8 * bn * (1 + 1e-6)
         assert em <= 1e-6 and emn <= 1e-6, (em, emn)
         h.close()
