@@ -47,12 +47,13 @@ WORKLOADS = {
     "cube": ("octree variant: one implicit heat step (dt = h) on a jittered 101^3 lattice of the unit cube, P1 "
              "tetrahedra, Dirichlet inlet face (1,020,100 DOF)", lambda mg: mg.cube_problem(100)),
 }
-ROOFLINE_KERNELS = {"engine32": "k_engine<float>", "spmv64": "k_outer_spmv_dot",
-                    "resid_fine32": "k_fine_resid_full<float>", "gs_fine32": "k_fine_resid<float> (color phase)"}
+ROOFLINE_KERNELS = {"engine32": "k_engine_fast<float>", "spmv64": "k_outer_spmv_dot",
+                    "resid_fine32": "k_fine_resid_full<float>", "gs_fine32": "k_fine_gs<float> (fused color phase)"}
+GOLDEN = os.path.join(ROOT, "tests", "golden")
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # MI355X dense FP32 vector, 256 CUs at 2.4 GHz
 N_CU = 256
 # c5 arrival rate: 0.7 x the saturated FP32-preconditioned served throughput measured by --calibrate (frozen)
-C5_RATE = 40.0
+C5_RATE = 112.2
 MALL_BYTES = 256 << 20           # Infinity Cache: operands smaller than this may be served from it
 ROW_VISIT_BYTES = 250.0          # algorithmic bytes per visit of a tree-level row (9 FP32 values, its vectors)
 
@@ -75,17 +76,43 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_hash():
-    """Hash of the sources the fine-level kernels depend on: their section of qa_solve.hip, the sliced-ELL layout
-    built in qa_setup.hip and the shared header. A counter record taken on other sources is not used."""
+def err_vs_oracle_reference(workload, smoother, n, x):
+    """Relative error of a solution of the workload's own right-hand side against the oracle's FP64 solve stored in
+    tests/golden/fullsize_<workload>.json (written by the oracle alone): over its 512 seeded sample entries, and of
+    the norm. The reference is the tightest stored solve (1e-12 on the quasi-uniform mesh, 1e-11 on the
+    checkerboard, else 1e-8)."""
+    path = os.path.join(GOLDEN, f"fullsize_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        g = json.load(f)
+    if g["n"] != n:
+        return None
+    ref = g["smoothers"][str(smoother)]
+    r = ref.get("reference") or dict(ref["tol_1e-8"], tol=1e-8)
+    idx = np.asarray(g["samples"])
+    xs = np.asarray(r["x_samples"])
+    return {"oracle_tol": r["tol"], "oracle_iters": r["iters"], "samples": len(idx),
+            "rel_err_samples": float(np.linalg.norm(x[idx] - xs) / np.linalg.norm(xs)),
+            "rel_err_norm": float(abs(np.linalg.norm(x) - r["x_norm"]) / r["x_norm"])}
+
+
+def kernel_source_hash(kernel="resid_fine32"):
+    """Hash of the sources a kernel family depends on: for the small-level engine qa_engine.hip, else the fine-level
+    section of qa_solve.hip and the sliced-ELL layout built in qa_setup.hip; the shared header for both. A counter
+    record taken on other sources is not used."""
     csrc = os.path.join(ROOT, "paper_1209_5421_amd", "csrc")
     h = hashlib.sha256()
-    with open(os.path.join(csrc, "qa_solve.hip")) as f:
-        text = f.read()
-    start = text.index("\n// fine level kernels\n")
-    end = text.index("\n// -----", start + 1)
-    h.update(text[start:end].encode())
-    for name in ("qa_setup.hip", "qa_internal.hpp"):
+    if kernel.startswith("engine"):
+        names = ("qa_engine.hip", "qa_internal.hpp")
+    else:
+        with open(os.path.join(csrc, "qa_solve.hip")) as f:
+            text = f.read()
+        start = text.index("\n// fine level kernels\n")
+        end = text.index("\n// -----", start + 1)
+        h.update(text[start:end].encode())
+        names = ("qa_setup.hip", "qa_internal.hpp")
+    for name in names:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -98,7 +125,7 @@ def traffic_from_profiles(kernel, workload):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("source_hash") != kernel_source_hash():
+    if rec.get("source_hash") != kernel_source_hash(kernel):
         return None
     return rec.get("bytes_per_launch")
 
@@ -145,7 +172,7 @@ def _per_dispatch(rows, counter, tag):
 def traffic_record(fetch_dir, write_dir, kernel, workload, commands):
     """Combine a FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch) into HBM bytes per launch of `kernel`,
     each counter scaled by what it reads for the calibration copy (expected / measured)."""
-    tag = ROOFLINE_KERNELS[kernel].split(" ")[0]
+    tag = ROOFLINE_KERNELS[kernel].split(" ")[0].rstrip(">")
     fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
     f_k, nf = _per_dispatch(fr, "FETCH_SIZE", tag)
     w_k, nw = _per_dispatch(wr, "WRITE_SIZE", tag)
@@ -154,7 +181,7 @@ def traffic_record(fetch_dir, write_dir, kernel, workload, commands):
     expect_kib = COPY_ELEMS * 4 / 1024.0
     sf, sw = expect_kib / f_c, expect_kib / w_c
     return {"kernel": kernel, "kernel_name": ROOFLINE_KERNELS[kernel], "workload": workload,
-            "source_hash": kernel_source_hash(),
+            "source_hash": kernel_source_hash(kernel),
             "fetch_kib_per_launch": f_k, "write_kib_per_launch": w_k, "dispatches": [nf, nw],
             "copy_calibration": {"bytes_read": COPY_ELEMS * 4, "bytes_written": COPY_ELEMS * 4,
                                  "fetch_kib": f_c, "write_kib": w_c, "fetch_scale": sf, "write_scale": sw},
@@ -225,10 +252,13 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/traffic_<kernel>_<workload>.json from two rocprofv3 --pmc runs and exit")
     ap.add_argument("--traffic-commands", nargs="*", default=[], help="commands that produced the counter runs")
+    ap.add_argument("--traffic-kernel", default=None, choices=sorted(ROOFLINE_KERNELS),
+                    help="--traffic-from: the kernel family the counters are for (default: --hbm-kernel)")
     args = ap.parse_args()
     if args.traffic_from:
-        rec = traffic_record(*args.traffic_from, args.hbm_kernel, args.workload, args.traffic_commands)
-        out = os.path.join(ROOT, "profiles", f"traffic_{args.hbm_kernel}_{args.workload}.json")
+        tk = args.traffic_kernel or args.hbm_kernel
+        rec = traffic_record(*args.traffic_from, tk, args.workload, args.traffic_commands)
+        out = os.path.join(ROOT, "profiles", f"traffic_{tk}_{args.workload}.json")
         with open(out, "w") as f:
             json.dump(rec, f, indent=1)
         print(json.dumps(rec))
@@ -330,6 +360,8 @@ def main():
                        "dof_per_s": float(prob.n * 1e3 / np.median(lat))}
         log(f"resident {name}: {forms[name]}")
     x_gpu = x.cpu().numpy()
+    err_ref = err_vs_oracle_reference(args.workload, args.smoother, prob.n, x_gpu)
+    log(f"fp32-precond solution against the stored oracle reference: {err_ref}")
     # the other reading of the fine smoother on the same resident system (both forms)
     other = 1 - args.smoother
     ho = amg.Hierarchy(coords, rp, ci, va, box=prob.box, precision=0, stream=stream, smoother=other)
@@ -404,12 +436,17 @@ def main():
         if kind.startswith("engine"):
             # one workgroup runs the cycle below ~4,096 cells as a chain of dependent steps (barrier after each);
             # its algorithmic bytes are the tree-level row visits of one launch at 250 B each
-            top = engine["fp32_precond" if kind == "engine32" else "fp64"]["top_level"]
+            eng = engine["fp32_precond" if kind == "engine32" else "fp64"]
+            top = eng["top_level"]
             rows = coarse_row_visits(levels, top) if top >= 0 else 0
             nbytes = rows * ROW_VISIT_BYTES
             gbs = nbytes / (avg_ms * 1e-3) / 1e9 if launches else None
-            return {"bound": "hbm", "kernel": ROOFLINE_KERNELS[kind], "achieved": gbs, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": (gbs / HBM_PEAK_GBS) if gbs else None, "traffic": None,
+            name = ROOFLINE_KERNELS[kind]
+            if top >= 0:  # the specialised engine's instance: <precision, top level k, last LDS level k>
+                name = f"{name[:-1]}, {levels[top]['k']}, {levels[eng['lds_level']]['k']}>"
+            return {"bound": "hbm", "kernel": name, "achieved": gbs, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": (gbs / HBM_PEAK_GBS) if gbs else None,
+                    "traffic": traffic_from_profiles(kind, args.workload),
                     "launches": launches, "avg_us": avg_ms * 1e3, "algorithmic_bytes_per_launch": nbytes,
                     "row_visits_per_launch": rows, "bytes_per_row_visit": ROW_VISIT_BYTES,
                     "share_of_solve": (kern_ms / max(nsteps, 1)) / solve_ms if nsteps else None,
@@ -462,6 +499,7 @@ def main():
         "update_resident": update,
         "engine": engine,
         "err_vs_oracle": err_vs_oracle,
+        "err_vs_oracle_reference": err_ref,
         "solve_resident_other_smoother": forms_other,
         "roofline": roofline,
         "roofline_hbm": roofline_hbm,
@@ -507,6 +545,10 @@ def big_leg(args, amg, meshgen, torch, stream):
            "p99_ms": float(np.percentile(lat, 99)), "solves_per_s": len(rhs) / wall,
            "dof_per_s": prob.n * len(rhs) / wall}
     log(f"{name} 8 sequential right-hand sides: {seq}")
+    b0 = tt(prob.b, torch.float64)
+    _, info0 = h.solve(b0, tol=args.tol, x=x)
+    err_ref = err_vs_oracle_reference(name, args.smoother, prob.n, x.cpu().numpy())
+    log(f"{name} own right-hand side: iters {info0['iters']}, against the stored oracle reference {err_ref}")
     kernels = {}
     for kind in ("spmv64", "resid_fine32", "gs_fine32"):
         h.timing_enable(kind)
@@ -526,7 +568,8 @@ def big_leg(args, amg, meshgen, torch, stream):
     h.close()
     return {"workload": f"{name}: {desc}", "n": prob.n, "nnz": prob.nnz, "precision": "fp32_precond",
             "smoother": ["cell substitution", "exact cell blocks"][args.smoother],
-            "levels": [(lv["k"], lv["n"]) for lv in levels], "sequential_rhs": seq, "kernels": kernels,
+            "levels": [(lv["k"], lv["n"]) for lv in levels], "sequential_rhs": seq,
+            "own_rhs": {"iters": info0["iters"], "err_vs_oracle_reference": err_ref}, "kernels": kernels,
             "solve_roofline": {"bytes_per_iteration": bpi, "iterations": it_med, "solve_ms": med_ms,
                                "achieved_gbs": bpi * it_med / (med_ms * 1e-3) / 1e9,
                                "frac": bpi * it_med / (med_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}}
