@@ -250,11 +250,12 @@ __global__ void __launch_bounds__(kBlock) k_row_diag(int64_t n, const int64_t *_
 // sliced ELL of the fine level
 
 // Windows: each color's rows are cut into windows, and every window into slices of 64 positions (the last one
-// partial). On a multi-level hierarchy a window is a run of whole cells of one color: the cells whose first row lies
-// in one band of `band` rows, counted from the color's first row. A window then holds at most band - 1 + m rows, m
-// its last cell's size, so with band = 257 - (largest cell the smoother solves per thread) every window without a
-// larger cell fits 256 rows, and the fused smoother phase can take a window per workgroup with its cells whole.
-// On a single level (no cells) the windows are 256 consecutive rows.
+// partial). On a multi-level hierarchy a window is a run of whole cells of one color: consecutive cells whose first
+// rows lie in one band of `band` rows (counted from the color's first row), at most kWinCells of them, and a cell
+// larger than the smoother solves per thread (`largest`) is a window of its own. With band = 257 - largest a window
+// of small cells holds at most band - 1 + largest = 256 rows, so the fused smoother phase can take a window per
+// workgroup with its cells whole and staged in LDS. On a single level (no cells) the windows are 256 consecutive rows.
+constexpr int kWinCells = 512;
 
 // 1 if some row is coupled to a row of another cell of its own color (cells are color-major: color = cell /
 // per_color)
@@ -275,12 +276,17 @@ __global__ void __launch_bounds__(kBlock) k_same_color(int64_t n, int64_t per_co
 // a cell starts a window when it is its color's first cell or its first row lies in another band than the
 // previous cell's
 __global__ void __launch_bounds__(kBlock) k_win_mark(int64_t nL, int64_t per_color, const int32_t *__restrict__ crow,
-                                                      int band, int32_t *__restrict__ mark) {
+                                                      int band, int largest, int32_t *__restrict__ mark) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= nL) return;
   const int64_t c0 = (q / per_color) * per_color;
+  if (q == c0 || (q - c0) % kWinCells == 0) {
+    mark[q] = 1;
+    return;
+  }
   const int32_t base = crow[c0];
-  mark[q] = (q == c0 || (crow[q] - base) / band != (crow[q - 1] - base) / band) ? 1 : 0;
+  const bool big = crow[q + 1] - crow[q] > largest, prev_big = crow[q] - crow[q - 1] > largest;
+  mark[q] = (big || prev_big || (crow[q] - base) / band != (crow[q - 1] - base) / band) ? 1 : 0;
 }
 
 // first cell and first row of each window; the end (nL, n) after the last
@@ -1207,7 +1213,7 @@ static amg_status build_sell(amg_hierarchy *h) {
     BuildTmp tmark(h, sizeof(int32_t) * nL), twidx(h, sizeof(int32_t) * (nL + 1));
     int32_t *mark = tmark.as<int32_t>(), *widx = twidx.as<int32_t>();
     if (!mark || !widx) return AMG_ERR_NOMEM;
-    k_win_mark<<<nblk(nL), kBlock, 0, s>>>(nL, nL / nc, F.crow, F.win_band, mark);
+    k_win_mark<<<nblk(nL), kBlock, 0, s>>>(nL, nL / nc, F.crow, F.win_band, largest, mark);
     QA_LAUNCH_CHECK();
     QA_TRY(scan_exclusive_i32(mark, widx, nL, s, h));
     int32_t cw[kMaxColors + 1];

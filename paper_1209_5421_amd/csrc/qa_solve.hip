@@ -301,13 +301,18 @@ __device__ inline void block_solve(const T *Lf, int m, T *v, int stride) {
 //     the cell's rows ascending (FWD, c < p) or descending (c > p).
 //  3. u += delta with coalesced stores. The rows of larger cells get r in d instead, for k_fine_subst_big.
 // The window's cell bounds, rows of u, factor values and in-cell couplings are contiguous and staged in LDS with
-// coalesced loads issued together with the residual's, so the kernel waits on few dependent round trips to memory;
-// a window beyond the staging arrays (only around cells larger than CMAX, or many empty cells) takes the same
-// arithmetic on global memory. Without GIVEN the color's cells are not coupled to each other, so the workgroups are
-// independent; u of a window's rows changes only in its own workgroup.
-constexpr int kFuseRows = 512;
-constexpr int kFuseEnt = 2048;   // factor values (exact blocks) or in-cell couplings (substitution) staged
+// coalesced loads issued together with the residual's, so the kernel waits on few dependent round trips to memory.
+// The staging arrays hold any window of cells of at most CMAX unknowns (at most 256 rows and 512 cells, hence at
+// most 8 factors of 32 x 33 / 2 values, or 9 in-cell couplings per row); a window of one larger cell, which has
+// nothing to solve here, may exceed them and then takes the same arithmetic on global memory. Without GIVEN the
+// color's cells are not coupled to each other, so the workgroups are independent; u of a window's rows changes only
+// in its own workgroup.
+constexpr int kFuseRows = 256;
 constexpr int kFuseCells = 512;
+template <int SM>
+constexpr int fuse_ent() {  // factor values (exact blocks) or in-cell couplings (substitution) staged
+  return SM ? (kFuseRows / kBlockMax) * (kBlockMax * (kBlockMax + 1) / 2) : kFuseRows * (kBigCell - 1);
+}
 
 template <class T>
 struct FuseArgs {
@@ -326,6 +331,7 @@ struct FuseArgs {
 template <class T, int SM, bool FWD, bool GIVEN>
 __global__ void __launch_bounds__(kBlock) k_fine_gs(SellView<T> S, FuseArgs<T> A) {
   constexpr int CMAX = SM ? kBlockMax : kBigCell;
+  constexpr int kFuseEnt = fuse_ent<SM>();
   __shared__ T s_r[kFuseRows];                   // residual (SM = 1: then the delta, in place)
   __shared__ T s_u[kFuseRows];                   // u of the window's rows
   __shared__ T s_x[SM ? kFuseEnt : kFuseRows];   // factor values (SM = 1) or the deltas (SM = 0)
@@ -495,15 +501,42 @@ __global__ void __launch_bounds__(kSubstLanes) k_fine_subst_big(const int32_t *_
   for (int32_t p = a + static_cast<int32_t>(threadIdx.x); p < e; p += kSubstLanes) x[p] += d[p];
 }
 
-// g[q] = sum of d over the rows of level-L cell q (rows ascending)
+// g[q] = sum of d over the rows of level-L cell q (rows ascending); cells of more than `big` rows are left to
+// k_fine_restrict_big
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_fine_restrict(int64_t nL, const int32_t *__restrict__ crow,
-                                                           const T *__restrict__ d, T *__restrict__ g) {
+                                                           const T *__restrict__ d, T *__restrict__ g, int big) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= nL) return;
+  const int32_t a = crow[q], b = crow[q + 1];
+  if (b - a > big) return;
   T acc = 0;
-  for (int32_t p = crow[q]; p < crow[q + 1]; p++) acc += d[p];
+  for (int32_t p = a; p < b; p++) acc += d[p];
   g[q] = acc;
+}
+
+// the same sum for the listed cells, one wavefront per cell: the wavefront stages the cell's d in LDS with coalesced
+// loads, 1,024 rows at a time, and lane 0 adds them in ascending order (the thread-per-cell order), so a cell of a
+// thousand rows costs LDS reads instead of a chain of dependent global loads
+constexpr int kRestrictChunk = 1024;
+
+template <class T>
+__global__ void __launch_bounds__(64) k_fine_restrict_big(const int32_t *__restrict__ cells,
+                                                           const int32_t *__restrict__ crow,
+                                                           const T *__restrict__ d, T *__restrict__ g) {
+  __shared__ T s_d[kRestrictChunk];
+  const int32_t q = cells[blockIdx.x];
+  const int32_t a = crow[q], b = crow[q + 1];
+  T acc = 0;
+  for (int32_t c0 = a; c0 < b; c0 += kRestrictChunk) {
+    const int m = min(kRestrictChunk, b - c0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += 64) s_d[i] = d[c0 + i];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int i = 0; i < m; i++) acc += s_d[i];
+  }
+  if (threadIdx.x == 0) g[q] = acc;
 }
 
 template <class T>
@@ -2447,7 +2480,9 @@ static void bhat_fine(amg_hierarchy *h, const T *f, T *u) {
   LevelWork<T> &wc = P<T>::W(h)[1];
   fine_resid<T>(h, f, u, w.d, 0, F.ncolor, P<T>::kResid);
   const int64_t nL = static_cast<int64_t>(1) << (h->dim * h->L);
-  k_fine_restrict<T><<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, w.d, wc.g);
+  const int big = h->opt.smoother ? kBlockMax : kBigCell;  // the big-cell list's threshold
+  k_fine_restrict<T><<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, w.d, wc.g, F.nbig ? big : INT32_MAX);
+  if (F.nbig) k_fine_restrict_big<T><<<static_cast<unsigned>(F.nbig), 64, 0, s>>>(F.big_cells, F.crow, w.d, wc.g);
   const Pending<T> pend = coarse_solve_or_cycle<T>(h, 1);
   k_fine_prolong<T><<<nblk(F.n), kBlock, 0, s>>>(F.n, F.agg_q, wc.e, pend, u);
   for (int sw = 0; sw < sweeps; sw++)
@@ -2615,12 +2650,13 @@ double kernel_bytes(const amg_hierarchy *h, int kind) {
     case KK_RESID_FINE64: return 12.0 * nnz + 24.0 * n;
     case KK_RESID_FINE32: return 8.0 * nnz + 12.0 * n;
     // one fused color phase: the color's share of the residual pass (f read, x read, x written) and of the cell
-    // solves' data (factor values, or in-cell couplings and the diagonal)
+    // solves' data (factor values, or in-cell couplings and the diagonal); where the colour's cells are coupled to
+    // each other the residual comes from a separate pass, and the phase reads it (4 or 8 B per row) instead
     case KK_GS_FINE64:
-      return (12.0 * nnz + 24.0 * n +
+      return ((h->fine.same_color ? 24.0 * n : 12.0 * nnz + 24.0 * n) +
               (h->opt.smoother ? 8.0 * h->fine.bfac_n : 12.0 * h->fine.ic_nnz + 8.0 * n)) / h->fine.ncolor;
     case KK_GS_FINE32:
-      return (8.0 * nnz + 12.0 * n +
+      return ((h->fine.same_color ? 12.0 * n : 8.0 * nnz + 12.0 * n) +
               (h->opt.smoother ? 4.0 * h->fine.bfac_n : 8.0 * h->fine.ic_nnz + 4.0 * n)) / h->fine.ncolor;
     case KK_ENGINE64: return h->engine_flops[0];
     case KK_ENGINE32: return h->engine_flops[1];

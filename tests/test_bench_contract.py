@@ -19,12 +19,15 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_counter_records_are_used_only_on_the_sources_they_were_taken_on():
     sys.path.insert(0, ROOT)
     import bench
-    h = bench.kernel_source_hash()
-    assert len(h) == 16 and h == bench.kernel_source_hash()
+    for kind in bench.ROOFLINE_KERNELS:
+        h = bench.kernel_source_hash(kind)
+        assert len(h) == 16 and h == bench.kernel_source_hash(kind)
+    # the engine's record depends on the engine's sources only, the fine-level records on the fine-level ones
+    assert bench.kernel_source_hash("engine32") != bench.kernel_source_hash("resid_fine32")
     for name in os.listdir(os.path.join(ROOT, "profiles")):
         if name.startswith("traffic_") and name.endswith(".json"):
             with open(os.path.join(ROOT, "profiles", name)) as f:
                 rec = json.load(f)
             assert rec["bytes_per_launch"] > 0 and rec["dispatches"][0] > 0
-            want = rec["bytes_per_launch"] if rec["source_hash"] == h else None
+            want = rec["bytes_per_launch"] if rec["source_hash"] == bench.kernel_source_hash(rec["kernel"]) else None
             assert bench.traffic_from_profiles(rec["kernel"], rec["workload"]) == want, name
