@@ -174,6 +174,14 @@ amg_status amg_solve_batch(amg_hierarchy *const *h, const double *const *b, doub
 amg_status amg_solve_batch_noalloc(amg_hierarchy *const *h, const double *const *b, double *const *x,
                                    const double *tol, int32_t count, amg_info *info);
 
+/* The library keeps the device blocks of freed hierarchies (those allocated from its own pool, not through caller
+ * callbacks) in a per-device cache for reuse by the next allocation of exactly the same size; it is emptied whenever
+ * one of its own allocations fails. amg_cache_control: limit_bytes >= 0 sets the cache's limit on `device` (default
+ * 32 GiB) and returns the blocks beyond it to the driver, oldest first; limit_bytes < 0 leaves it. cached_bytes
+ * (may be NULL) receives the bytes the cache holds afterwards. Callers that also allocate device memory outside the
+ * library (and admission by memory footprint) bound it this way. AMG_ERR_INVALID for a device outside [0, 64). */
+amg_status amg_cache_control(int32_t device, int64_t limit_bytes, size_t *cached_bytes);
+
 /* Upper estimate of the device bytes a hierarchy for an n-unknown, nnz-entry system needs, workspace included
  * (used for admission by memory footprint). */
 amg_status amg_estimate_bytes(int64_t n, int64_t nnz, const amg_options *opt, size_t *bytes);

@@ -17,7 +17,7 @@ OK, INVALID, NOMEM, DEVICE, NOT_SPD, BREAKDOWN, NOCONV = range(7)
 STATUS = {0: "AMG_OK", 1: "AMG_ERR_INVALID", 2: "AMG_ERR_NOMEM", 3: "AMG_ERR_DEVICE", 4: "AMG_ERR_NOT_SPD",
           5: "AMG_ERR_BREAKDOWN", 6: "AMG_ERR_NOCONV"}
 EXPORTED = ["amg_default_options", "amg_setup", "amg_setup3d", "amg_update_values", "amg_solve", "amg_free", "amg_set_precision", "amg_set_stream",
-            "amg_solve_batch", "amg_solve_batch_noalloc", "amg_estimate_bytes", "amg_hierarchy_bytes", "amg_num_levels", "amg_level_info",
+            "amg_solve_batch", "amg_solve_batch_noalloc", "amg_cache_control", "amg_estimate_bytes", "amg_hierarchy_bytes", "amg_num_levels", "amg_level_info",
             "amg_export_level", "amg_export_level_f32", "amg_apply_precond", "amg_level_smooth", "amg_level_spmv",
             "amg_kernel_timing_enable", "amg_kernel_timing_read", "amg_engine_info", "amg_p1_mesh_create",
             "amg_p1_mesh_pattern", "amg_p1_assemble", "amg_p1_mesh_free", "amg_status_string"]
@@ -106,6 +106,7 @@ def load(path: str = LIB_PATH):
     L.amg_solve_batch.argtypes = [C.POINTER(p), C.POINTER(p), C.POINTER(p), C.POINTER(d), i32, C.POINTER(Info)]
     L.amg_solve_batch_noalloc.argtypes = [C.POINTER(p), C.POINTER(p), C.POINTER(p), C.POINTER(d), i32,
                                           C.POINTER(Info)]
+    L.amg_cache_control.argtypes = [i32, i64, C.POINTER(C.c_size_t)]
     L.amg_estimate_bytes.argtypes = [i64, i64, C.POINTER(Options), C.POINTER(C.c_size_t)]
     L.amg_hierarchy_bytes.argtypes = [p, C.POINTER(C.c_size_t)]
     L.amg_num_levels.argtypes = [p, C.POINTER(i32)]
@@ -346,6 +347,14 @@ class Hierarchy:
         n, ms, b = C.c_int64(), C.c_double(), C.c_double()
         _check(load().amg_kernel_timing_read(self._h, C.byref(n), C.byref(ms), C.byref(b)), "amg_kernel_timing_read")
         return dict(launches=n.value, total_ms=ms.value, bytes_per_launch=b.value)
+
+
+def cache_control(device: int = 0, limit_bytes: int = -1) -> int:
+    """amg_cache_control: set the library's freed-block cache limit on `device` (limit_bytes >= 0, returning blocks
+    beyond it to the driver) and return the bytes it holds."""
+    out = C.c_size_t()
+    _check(load().amg_cache_control(int(device), int(limit_bytes), C.byref(out)), "amg_cache_control")
+    return out.value
 
 
 def solve_batch(hiers, bs, xs, tols, noalloc=False):

@@ -42,6 +42,9 @@ struct CachedBlock {
 };
 static std::vector<CachedBlock> g_cache[64];
 static size_t g_cache_bytes[64];
+static size_t g_cache_cap[64];  // 0: the default kCacheCap
+
+static size_t cache_cap(int device) { return g_cache_cap[device] ? g_cache_cap[device] - 1 : kCacheCap; }
 
 static void *cached_block(int device, size_t bytes) {
   if (device < 0 || device >= 64) return nullptr;
@@ -60,7 +63,7 @@ static void *cached_block(int device, size_t bytes) {
 static bool cache_block(int device, void *p, size_t bytes) {
   if (device < 0 || device >= 64) return false;
   std::lock_guard<std::mutex> lock(g_pool_mu);
-  if (g_cache_bytes[device] + bytes > kCacheCap) return false;
+  if (g_cache_bytes[device] + bytes > cache_cap(device)) return false;
   g_cache[device].push_back(CachedBlock{p, bytes});
   g_cache_bytes[device] += bytes;
   return true;
@@ -352,6 +355,40 @@ amg_status scan_exclusive_i32(const int32_t *in, int32_t *out, int64_t n, hipStr
 }  // namespace qa
 
 extern "C" {
+
+amg_status amg_cache_control(int32_t device, int64_t limit_bytes, size_t *cached_bytes) {
+  if (device < 0 || device >= 64) return AMG_ERR_INVALID;
+  if (limit_bytes >= 0) {
+    std::vector<qa::CachedBlock> out;
+    {
+      std::lock_guard<std::mutex> lock(qa::g_pool_mu);
+      qa::g_cache_cap[device] = static_cast<size_t>(limit_bytes) + 1;
+      std::vector<qa::CachedBlock> &c = qa::g_cache[device];
+      // the oldest blocks go first
+      while (!c.empty() && qa::g_cache_bytes[device] > static_cast<size_t>(limit_bytes)) {
+        out.push_back(c.front());
+        qa::g_cache_bytes[device] -= c.front().size;
+        c.erase(c.begin());
+      }
+    }
+    if (!out.empty()) {
+      int cur = 0;
+      if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(device) != hipSuccess) return AMG_ERR_DEVICE;
+      hipMemPool_t pool = qa::pool_for(device);
+      for (const qa::CachedBlock &b : out) (void)(pool ? hipFreeAsync(b.p, nullptr) : hipFree(b.p));
+      if (pool) {
+        (void)hipStreamSynchronize(nullptr);
+        (void)hipMemPoolTrimTo(pool, 0);
+      }
+      (void)hipSetDevice(cur);
+    }
+  }
+  if (cached_bytes) {
+    std::lock_guard<std::mutex> lock(qa::g_pool_mu);
+    *cached_bytes = qa::g_cache_bytes[device];
+  }
+  return AMG_OK;
+}
 
 void amg_default_options(amg_options *opt) {
   if (!opt) return;

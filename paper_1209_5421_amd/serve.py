@@ -169,12 +169,20 @@ class Scheduler:
         self.mem_used = 0
 
 
+# share of the HBM budget the library's freed-block cache may hold; hierarchies are admitted against the rest, so the
+# cache never takes memory the admitted hierarchies or the caller's own tensors were counted on
+CACHE_SHARE = 0.1
+
+
 class Server:
     def __init__(self, device="cuda:0", mem_budget=64 << 30, dispatchers=4, max_batch=128, precision=1, tol=1e-8,
                  keep_x=True, streams_per_dispatcher=4, batch=1):
         import torch
         self.torch = torch
         self.device = torch.device(device)
+        cache_limit = int(CACHE_SHARE * mem_budget)
+        amg.cache_control(self.device.index or 0, cache_limit)
+        mem_budget = int(mem_budget) - cache_limit
         self.dispatchers = int(dispatchers)
         self.streams_per_dispatcher = int(streams_per_dispatcher)
         self.batch = int(batch)

@@ -83,3 +83,23 @@ def test_serving_under_tight_memory_budget():
         A = H.csr_of(r.problem)
         assert np.linalg.norm(A @ res[r.rid].x - r.rhs) <= 1e-8 * np.linalg.norm(r.rhs) * (1 + 1e-6)
     srv.close()
+
+
+def test_cache_limit_bounds_the_freed_block_cache():
+    """amg_cache_control: freed hierarchies' blocks stay cached up to the limit, a lower limit returns the excess to
+    the driver at once, and with limit 0 nothing is kept."""
+    from paper_1209_5421_amd import amg
+    prob = mg.jittered_problem(130, fast=True)
+    try:
+        amg.cache_control(0, 8 << 30)
+        before = amg.cache_control(0)
+        h = amg.Hierarchy.from_problem(prob, device="cuda:0")
+        h.close()
+        held = amg.cache_control(0)
+        assert held > before
+        assert amg.cache_control(0, 0) == 0
+        h = amg.Hierarchy.from_problem(prob, device="cuda:0")
+        h.close()
+        assert amg.cache_control(0) == 0
+    finally:
+        amg.cache_control(0, 32 << 30)
