@@ -20,11 +20,12 @@
 namespace qa {
 
 constexpr int kBlock = 256;        // threads per workgroup for elementwise / reduction kernels
-constexpr int kSliceRows = 64;
-constexpr int kSellWindow = 256;    // rows are sorted by length inside windows of this many positions (4 slices)     // sliced-ELL slice height = one wavefront
+constexpr int kSliceRows = 64;     // sliced-ELL slice height = one wavefront
+constexpr int kSellWindow = 256;   // rows are sorted by length inside runs of this many positions (4 slices)
 constexpr int kRedBlocksMax = 1024;
 constexpr int kBlockMax = 32;      // exact-block smoother: cells of at most this many unknowns are factored
 constexpr int kBigCell = 10;        // cells with more unknowns get a level-scheduled in-cell substitution
+constexpr int kFuseStageRows = 512; // rows of a window the fused smoother phase stages in LDS
 constexpr int kScalars = 16;       // device scalars per level
 constexpr int kMaxColors = 8;      // colors of the smoother: 4 on a quadtree, 8 on an octree
 
@@ -186,6 +187,7 @@ struct FineLevel {
   int32_t *win_row = nullptr;   // nwin + 1: first row of each window
   int64_t *win_slice = nullptr; // nwin + 1: first slice of each window
   int64_t *win_ent = nullptr;   // nwin + 1: first factor value (exact blocks) or in-cell coupling of each window
+  int win_ent_max = 0;          // the most factor values / couplings of a window the fused phase stages
   int64_t color_win[kMaxColors + 1] = {};
   bool same_color = false;      // some row is coupled to a row of another cell of its own color
   int64_t nslices = 0;

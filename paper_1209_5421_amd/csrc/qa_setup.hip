@@ -251,9 +251,10 @@ __global__ void __launch_bounds__(kBlock) k_row_diag(int64_t n, const int64_t *_
 
 // Windows: each color's rows are cut into windows, and every window into slices of 64 positions (the last one
 // partial). On a multi-level hierarchy a window is a run of whole cells of one color: consecutive cells whose first
-// rows lie in one band of `band` rows (counted from the color's first row), at most kWinCells of them, and a cell
-// larger than the smoother solves per thread (`largest`) is a window of its own. With band = 257 - largest a window
-// of small cells holds at most band - 1 + largest = 256 rows, so the fused smoother phase can take a window per
+// rows lie in one band of `band` rows (counted from the color's first row), at most kWinCells of them, and a cell of
+// more than kSellWindow unknowns is a window of its own. With band = 257 - largest (the largest cell the smoother
+// solves per thread) the cells it solves in a window hold at most band - 1 + largest = 256 rows, and a window at
+// most band - 1 + kSellWindow < 512 rows unless it is one huge cell: the fused smoother phase takes a window per
 // workgroup with its cells whole and staged in LDS. On a single level (no cells) the windows are 256 consecutive rows.
 constexpr int kWinCells = 512;
 
@@ -276,7 +277,7 @@ __global__ void __launch_bounds__(kBlock) k_same_color(int64_t n, int64_t per_co
 // a cell starts a window when it is its color's first cell or its first row lies in another band than the
 // previous cell's
 __global__ void __launch_bounds__(kBlock) k_win_mark(int64_t nL, int64_t per_color, const int32_t *__restrict__ crow,
-                                                      int band, int largest, int32_t *__restrict__ mark) {
+                                                      int band, int32_t *__restrict__ mark) {
   const int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= nL) return;
   const int64_t c0 = (q / per_color) * per_color;
@@ -285,7 +286,7 @@ __global__ void __launch_bounds__(kBlock) k_win_mark(int64_t nL, int64_t per_col
     return;
   }
   const int32_t base = crow[c0];
-  const bool big = crow[q + 1] - crow[q] > largest, prev_big = crow[q] - crow[q - 1] > largest;
+  const bool big = crow[q + 1] - crow[q] > kSellWindow, prev_big = crow[q] - crow[q - 1] > kSellWindow;
   mark[q] = (big || prev_big || (crow[q] - base) / band != (crow[q - 1] - base) / band) ? 1 : 0;
 }
 
@@ -1213,7 +1214,7 @@ static amg_status build_sell(amg_hierarchy *h) {
     BuildTmp tmark(h, sizeof(int32_t) * nL), twidx(h, sizeof(int32_t) * (nL + 1));
     int32_t *mark = tmark.as<int32_t>(), *widx = twidx.as<int32_t>();
     if (!mark || !widx) return AMG_ERR_NOMEM;
-    k_win_mark<<<nblk(nL), kBlock, 0, s>>>(nL, nL / nc, F.crow, F.win_band, largest, mark);
+    k_win_mark<<<nblk(nL), kBlock, 0, s>>>(nL, nL / nc, F.crow, F.win_band, mark);
     QA_LAUNCH_CHECK();
     QA_TRY(scan_exclusive_i32(mark, widx, nL, s, h));
     int32_t cw[kMaxColors + 1];
@@ -1586,13 +1587,33 @@ __global__ void __launch_bounds__(kBlock) k_win_entries(int64_t nwin, const int3
   win_ent[w] = boff ? boff[win_q[w]] : static_cast<int64_t>(icp[win_row[w]]);
 }
 
+// the largest cell-data count of a window the fused phase stages (at most kFuseStageRows rows and kWinCells cells)
+__global__ void __launch_bounds__(kBlock) k_win_entmax(int64_t nwin, const int32_t *__restrict__ win_q,
+                                                        const int32_t *__restrict__ win_row,
+                                                        const int64_t *__restrict__ win_ent, int *__restrict__ out) {
+  const int64_t w = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (w >= nwin) return;
+  if (win_row[w + 1] - win_row[w] <= kFuseStageRows && win_q[w + 1] - win_q[w] <= kWinCells)
+    atomicMax(out, static_cast<int>(win_ent[w + 1] - win_ent[w]));
+}
+
 static amg_status build_window_entries(amg_hierarchy *h) {
   FineLevel &F = h->fine;
+  hipStream_t s = h->stream;
   F.win_ent = dalloc_n<int64_t>(h, F.nwin + 1);
   if (!F.win_ent) return AMG_ERR_NOMEM;
-  k_win_entries<<<nblk(F.nwin + 1), kBlock, 0, h->stream>>>(F.nwin, F.win_q, F.win_row,
-                                                             h->opt.smoother ? F.boff : nullptr, F.ic_ptr, F.win_ent);
+  k_win_entries<<<nblk(F.nwin + 1), kBlock, 0, s>>>(F.nwin, F.win_q, F.win_row, h->opt.smoother ? F.boff : nullptr,
+                                                     F.ic_ptr, F.win_ent);
+  BuildTmp tmax(h, sizeof(int));
+  int *dmax = tmax.as<int>();
+  if (!dmax) return AMG_ERR_NOMEM;
+  QA_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
+  if (F.nwin) k_win_entmax<<<nblk(F.nwin), kBlock, 0, s>>>(F.nwin, F.win_q, F.win_row, F.win_ent, dmax);
   QA_LAUNCH_CHECK();
+  int hmax = 0;
+  QA_HIP(hipMemcpyAsync(&hmax, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
+  QA_HIP(hipStreamSynchronize(s));
+  F.win_ent_max = hmax;
   return AMG_OK;
 }
 

@@ -302,16 +302,18 @@ __device__ inline void block_solve(const T *Lf, int m, T *v, int stride) {
 //  3. u += delta with coalesced stores. The rows of larger cells get r in d instead, for k_fine_subst_big.
 // The window's cell bounds, rows of u, factor values and in-cell couplings are contiguous and staged in LDS with
 // coalesced loads issued together with the residual's, so the kernel waits on few dependent round trips to memory.
-// The staging arrays hold any window of cells of at most CMAX unknowns (at most 256 rows and 512 cells, hence at
-// most 8 factors of 32 x 33 / 2 values, or 9 in-cell couplings per row); a window of one larger cell, which has
-// nothing to solve here, may exceed them and then takes the same arithmetic on global memory. Without GIVEN the
-// color's cells are not coupled to each other, so the workgroups are independent; u of a window's rows changes only
-// in its own workgroup.
-constexpr int kFuseRows = 256;
+// A window holds at most kFuseStageRows rows and kFuseCells cells unless it is a single cell of more unknowns than a
+// fused window stages; its factor values or in-cell couplings go to dynamic LDS sized by the setup's largest window
+// (at most kFuseDynBytes). A window that exceeds the staging arrays takes the same arithmetic on global memory; a
+// window of one cell too large to solve here has, with GIVEN, nothing to do (k_fine_subst_big reads the given
+// residual itself). Without GIVEN the color's cells are not coupled to each other, so the workgroups are
+// independent; u of a window's rows changes only in its own workgroup.
+constexpr int kFuseRows = kFuseStageRows;
 constexpr int kFuseCells = 512;
-template <int SM>
-constexpr int fuse_ent() {  // factor values (exact blocks) or in-cell couplings (substitution) staged
-  return SM ? (kFuseRows / kBlockMax) * (kBlockMax * (kBlockMax + 1) / 2) : kFuseRows * (kBigCell - 1);
+constexpr int kFuseDynBytes = 48 * 1024;
+template <class T, int SM>
+constexpr int fuse_ent_bytes() {  // LDS bytes per staged factor value (exact blocks) or in-cell coupling
+  return SM ? static_cast<int>(sizeof(T)) : static_cast<int>(sizeof(T) + sizeof(int16_t));
 }
 
 template <class T>
@@ -321,6 +323,7 @@ struct FuseArgs {
   int64_t win0, nwin;            // this color's windows
   int xcd;                       // 1: XCD-aware window order (grid = 8 x the largest per-XCD share)
   int big;                       // the color has cells left to k_fine_subst_big: write their residual to d
+  int ent_cap;                   // factor values / couplings the dynamic LDS holds
   const T *f, *src;              // src: the given residual (GIVEN)
   T *u, *d;
   const T *diag, *icv, *fac;
@@ -331,14 +334,15 @@ struct FuseArgs {
 template <class T, int SM, bool FWD, bool GIVEN>
 __global__ void __launch_bounds__(kBlock) k_fine_gs(SellView<T> S, FuseArgs<T> A) {
   constexpr int CMAX = SM ? kBlockMax : kBigCell;
-  constexpr int kFuseEnt = fuse_ent<SM>();
+  extern __shared__ __align__(16) unsigned char smem[];
   __shared__ T s_r[kFuseRows];                   // residual (SM = 1: then the delta, in place)
   __shared__ T s_u[kFuseRows];                   // u of the window's rows
-  __shared__ T s_x[SM ? kFuseEnt : kFuseRows];   // factor values (SM = 1) or the deltas (SM = 0)
+  __shared__ T s_dx[SM ? 1 : kFuseRows];         // the deltas (SM = 0)
   __shared__ T s_dg[SM ? 1 : kFuseRows];
-  __shared__ T s_val[SM ? 1 : kFuseEnt];
   __shared__ int32_t s_ep[SM ? 1 : kFuseRows + 1];
-  __shared__ int16_t s_col[SM ? 1 : kFuseEnt];
+  T *s_x = SM ? reinterpret_cast<T *>(smem) : s_dx;        // factor values (SM = 1) or the deltas (SM = 0)
+  T *s_val = reinterpret_cast<T *>(smem);                  // in-cell couplings (SM = 0)
+  int16_t *s_col = reinterpret_cast<int16_t *>(smem + sizeof(T) * A.ent_cap);
   __shared__ int32_t s_cr[kFuseCells + 1];       // cell bounds relative to the first row
   __shared__ int32_t s_cf[SM ? kFuseCells + 1 : 1];  // factor offsets relative to the first value
   __shared__ uint8_t s_mine[kFuseRows];
@@ -357,7 +361,8 @@ __global__ void __launch_bounds__(kBlock) k_fine_gs(SellView<T> S, FuseArgs<T> A
   const int64_t sl0 = A.win_slice[w], sl1 = A.win_slice[w + 1];
   const int64_t e0 = A.win_ent[w], ne = A.win_ent[w + 1] - e0;
   const int nr = r1 - r0, nq = q1 - q0;
-  const bool staged = nr <= kFuseRows && ne <= kFuseEnt && nq <= kFuseCells;  // uniform over the workgroup
+  if (GIVEN && nq == 1 && nr > CMAX) return;  // one cell left to k_fine_subst_big, which reads src
+  const bool staged = nr <= kFuseRows && ne <= A.ent_cap && nq <= kFuseCells;  // uniform over the workgroup
   if (staged) {
     for (int k = t; k <= nq; k += kBlock) {
       s_cr[k] = A.crow[q0 + k] - r0;
@@ -1155,14 +1160,20 @@ static unsigned sched_grid(const SliceSched &Z) {
 // the dispatch packet itself, so the interval is the kernel's own execution window (the same span a kernel-trace
 // profiler reports), not the gap between two markers queued around it.
 template <typename F, typename... Args>
-static void launch_timed(amg_hierarchy *h, int kind, F kern, unsigned grid, Args... args) {
+static void launch_timed_lds(amg_hierarchy *h, int kind, F kern, unsigned grid, size_t lds, Args... args) {
   Timing &t = h->timing;
   if (kind >= 0 && t.kind == kind && t.used + 2 <= t.ev.size()) {
-    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, h->stream, t.ev[t.used], t.ev[t.used + 1], 0, args...);
+    hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), lds, h->stream, t.ev[t.used], t.ev[t.used + 1], 0,
+                          args...);
     t.used += 2;
   } else {
-    kern<<<grid, kBlock, 0, h->stream>>>(args...);
+    kern<<<grid, kBlock, lds, h->stream>>>(args...);
   }
+}
+
+template <class F, class... Args>
+static void launch_timed(amg_hierarchy *h, int kind, F kern, unsigned grid, Args... args) {
+  launch_timed_lds(h, kind, kern, grid, 0, args...);
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -2407,8 +2418,11 @@ static void fine_resid(amg_hierarchy *h, const T *f, const T *x, T *d, int c0, i
 }
 
 template <class T, int SM, bool FWD, bool GIVEN>
-static void fine_gs_launch(amg_hierarchy *h, unsigned grid, const FuseArgs<T> &A) {
-  launch_timed(h, P<T>::kGs, k_fine_gs<T, SM, FWD, GIVEN>, grid, sview<T>(h->fine, P<T>::sval(h->fine)), A);
+static void fine_gs_launch(amg_hierarchy *h, unsigned grid, FuseArgs<T> A) {
+  A.ent_cap = std::min(h->fine.win_ent_max, kFuseDynBytes / fuse_ent_bytes<T, SM>());
+  const size_t lds = (static_cast<size_t>(A.ent_cap) * fuse_ent_bytes<T, SM>() + 15) / 16 * 16;
+  launch_timed_lds(h, P<T>::kGs, k_fine_gs<T, SM, FWD, GIVEN>, grid, lds, sview<T>(h->fine, P<T>::sval(h->fine)),
+                   A);
 }
 
 // One color phase of the fine smoother: the fused residual and cell solves (k_fine_gs), then the cells left to the
