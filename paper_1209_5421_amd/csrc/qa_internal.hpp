@@ -24,7 +24,7 @@ constexpr int kSliceRows = 64;     // sliced-ELL slice height = one wavefront
 constexpr int kSellWindow = 256;   // rows are sorted by length inside runs of this many positions (4 slices)
 constexpr int kRedBlocksMax = 1024;
 constexpr int kBlockMax = 32;      // exact-block smoother: cells of at most this many unknowns are factored
-constexpr int kBigCell = 10;        // cells with more unknowns get a level-scheduled in-cell substitution
+constexpr int kBigCell = 32;       // cells with more unknowns get a level-scheduled in-cell substitution
 constexpr int kFuseStageRows = 512; // rows of a window the fused smoother phase stages in LDS
 constexpr int kScalars = 16;       // device scalars per level
 constexpr int kMaxColors = 8;      // colors of the smoother: 4 on a quadtree, 8 on an octree
@@ -217,6 +217,7 @@ struct FineLevel {
   int64_t nbig = 0;
   int64_t big_color[kMaxColors + 1] = {};      // first big cell of each color (big cells ascend by cell id)
   int32_t *big_cells = nullptr;                 // cell ids
+  int big_max_rows = 0;                         // rows of the largest big cell
   int32_t *big_lofs[2] = {nullptr, nullptr};    // per big cell, its first entry in big_lptr (nbig + 1)
   int32_t *big_lptr[2] = {nullptr, nullptr};    // level starts as row positions, then the cell's end
   int32_t *big_sched[2] = {nullptr, nullptr};   // the big cells' rows ordered by level (indexed by row position)

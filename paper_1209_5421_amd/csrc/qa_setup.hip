@@ -472,6 +472,12 @@ __global__ void __launch_bounds__(kBlock) k_big_levels(int64_t nbig, const int32
   nptr[b] = depth + 1;  // level starts plus the end
 }
 
+__global__ void __launch_bounds__(kBlock) k_big_rows_max(int64_t nbig, const int32_t *__restrict__ cells,
+                                                          const int32_t *__restrict__ crow, int *__restrict__ out) {
+  const int64_t b = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (b < nbig) atomicMax(out, crow[cells[b] + 1] - crow[cells[b]]);
+}
+
 // rows of each big cell sorted by level (stable: ascending row within a level); lptr gets the level starts
 __global__ void __launch_bounds__(kBlock) k_big_sched(int64_t nbig, const int32_t *__restrict__ cells,
                                                        const int32_t *__restrict__ crow, const int32_t *__restrict__ lv,
@@ -1627,6 +1633,16 @@ static amg_status build_big_cells(amg_hierarchy *h) {
   int32_t *lv = dalloc_n<int32_t>(h, n);
   int32_t *cnt = dalloc_n<int32_t>(h, F.nbig);
   if (!lv || !cnt) return AMG_ERR_NOMEM;
+  {
+    BuildTmp tmax(h, sizeof(int));
+    int *dmax = tmax.as<int>();
+    if (!dmax) return AMG_ERR_NOMEM;
+    QA_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
+    k_big_rows_max<<<nblk(F.nbig), kBlock, 0, s>>>(F.nbig, F.big_cells, F.crow, dmax);
+    QA_LAUNCH_CHECK();
+    QA_HIP(hipMemcpyAsync(&F.big_max_rows, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
+    QA_HIP(hipStreamSynchronize(s));
+  }
   for (int dir = 0; dir < 2; dir++) {
     if (dir == 0)
       k_big_levels<true><<<nblk(F.nbig), kBlock, 0, s>>>(F.nbig, F.big_cells, F.crow, F.ic_ptr, F.ic_col, lv, cnt);

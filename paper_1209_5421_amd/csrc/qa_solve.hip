@@ -286,9 +286,91 @@ __device__ inline void block_solve(const T *Lf, int m, T *v, int stride) {
   }
   for (int i = m - 1; i >= 0; i--) {
     T s = v[i * stride];
-    for (int k = i + 1; k < m; k++) s -= Lf[k * (k + 1) / 2 + i] * v[k * stride];
+    for (int k = m - 1; k > i; k--) s -= Lf[k * (k + 1) / 2 + i] * v[k * stride];
     v[i * stride] = s / Lf[i * (i + 1) / 2 + i];
   }
+}
+
+// block_solve with the cell's vector in registers, for cells of at most MC unknowns: the same operations in the same
+// order (the loops are unrolled to MC and guarded by m), so the results are identical, but the substitutions wait on
+// register operands instead of a chain of LDS round trips; only the factor values are read from memory.
+template <class T, int MC>
+__device__ __forceinline__ void block_solve_reg(const T *Lf, int m, T *v) {
+  T y[MC];
+#pragma unroll
+  for (int i = 0; i < MC; i++) y[i] = i < m ? v[i] : T(0);
+#pragma unroll
+  for (int i = 0; i < MC; i++) {
+    if (i < m) {
+      const T *Li = Lf + i * (i + 1) / 2;
+      T s = y[i];
+#pragma unroll
+      for (int k = 0; k < i; k++) s -= Li[k] * y[k];
+      y[i] = s / Li[i];
+    }
+    __builtin_amdgcn_sched_barrier(0);  // one row's factor values in flight at a time
+  }
+  // backward by columns: x_k is final once the columns above it are subtracted; row k of the factor then updates
+  // the rows below it (each row's subtractions in descending k, the order of block_solve)
+#pragma unroll
+  for (int k = MC - 1; k >= 0; k--) {
+    if (k < m) {
+      const T *Lk = Lf + k * (k + 1) / 2;
+      y[k] = y[k] / Lk[k];
+#pragma unroll
+      for (int i = 0; i < k; i++) y[i] -= Lk[i] * y[k];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int i = 0; i < MC; i++)
+    if (i < m) v[i] = y[i];
+}
+
+// register classes up to kRegCell unknowns, the cells one thread solves in the fused phase (a 32-unknown class needs
+// more registers than a thread holds without spilling)
+constexpr int kRegCell = 16;
+template <class T>
+__device__ inline void block_solve_small(const T *Lf, int m, T *v) {
+  static_assert(kRegCell == 16, "register classes 4, 8, 16");
+  if (m <= 4) block_solve_reg<T, 4>(Lf, m, v);
+  else if (m <= 8) block_solve_reg<T, 8>(Lf, m, v);
+  else block_solve_reg<T, 16>(Lf, m, v);
+}
+
+template <class T>
+__device__ __forceinline__ T wave_lane_value(T v, int k) {  // v of lane k (k uniform over the wavefront)
+  if constexpr (sizeof(T) == 4) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+  } else {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), k);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), k);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+  }
+}
+
+// block_solve by one wavefront, lane i holding row i (m <= kBlockMax <= 64): column k is finished, broadcast, and
+// subtracted from the rows it couples to, so each row sees the same subtractions in the same order as block_solve
+// (columns ascending forward, descending backward) and the results are identical; the dependent chain is 2 m
+// broadcast steps instead of m^2 dependent memory operations of one thread.
+template <class T>
+__device__ inline void block_solve_wave(const T *Lf, int m, T *v, int lane) {
+  static_assert(kBlockMax <= 64, "one row per lane");
+  T y = lane < m ? v[lane] : T(0);
+#pragma unroll 2
+  for (int k = 0; k < m; k++) {
+    const T yk = wave_lane_value(y, k) / Lf[k * (k + 1) / 2 + k];
+    if (lane == k) y = yk;
+    else if (lane > k && lane < m) y -= Lf[lane * (lane + 1) / 2 + k] * yk;
+  }
+#pragma unroll 2
+  for (int k = m - 1; k >= 0; k--) {
+    const T xk = wave_lane_value(y, k) / Lf[k * (k + 1) / 2 + k];
+    if (lane == k) y = xk;
+    else if (lane < k) y -= Lf[k * (k + 1) / 2 + lane] * xk;
+  }
+  if (lane < m) v[lane] = y;
 }
 
 // One color phase of the fine-level smoother (Section 4.5), fused: a workgroup per window (a run of whole cells of
@@ -314,6 +396,34 @@ constexpr int kFuseDynBytes = 48 * 1024;
 template <class T, int SM>
 constexpr int fuse_ent_bytes() {  // LDS bytes per staged factor value (exact blocks) or in-cell coupling
   return SM ? static_cast<int>(sizeof(T)) : static_cast<int>(sizeof(T) + sizeof(int16_t));
+}
+
+// r_p - sum of a_pc x_c over the in-cell couplings k0 <= k < k1 of row p with c < p (FWD) or c > p, in entry order:
+// the couplings of a chunk are read together, then the x_c they need, then the products are subtracted in order, so
+// a row waits on two LDS round trips per chunk of kSubstChunk couplings instead of two per coupling
+constexpr int kSubstChunk = 8;
+template <class T, bool FWD>
+__device__ __forceinline__ T subst_row(T acc, int k0, int k1, int p, const int16_t *s_col, const T *s_val,
+                                       const T *s_x) {
+  for (int kb = k0; kb < k1; kb += kSubstChunk) {
+    int c[kSubstChunk];
+    T v[kSubstChunk], x[kSubstChunk];
+#pragma unroll
+    for (int u = 0; u < kSubstChunk; u++) {
+      c[u] = p;
+      v[u] = T(0);
+      if (kb + u < k1) {
+        c[u] = s_col[kb + u];
+        v[u] = s_val[kb + u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kSubstChunk; u++) x[u] = (FWD ? c[u] < p : c[u] > p) ? s_x[c[u]] : T(0);
+#pragma unroll
+    for (int u = 0; u < kSubstChunk; u++)
+      if (FWD ? c[u] < p : c[u] > p) acc -= v[u] * x[u];
+  }
+  return acc;
 }
 
 template <class T>
@@ -346,6 +456,9 @@ __global__ void __launch_bounds__(kBlock) k_fine_gs(SellView<T> S, FuseArgs<T> A
   __shared__ int32_t s_cr[kFuseCells + 1];       // cell bounds relative to the first row
   __shared__ int32_t s_cf[SM ? kFuseCells + 1 : 1];  // factor offsets relative to the first value
   __shared__ uint8_t s_mine[kFuseRows];
+  constexpr int kTeamCells = kFuseRows / (kRegCell + 1) + 1;  // cells a wavefront solves (more than kRegCell rows)
+  __shared__ int16_t s_team[SM ? kTeamCells : 1];
+  __shared__ int s_nteam;
   int64_t w;
   if (A.xcd) {
     const int64_t x = blockIdx.x & 7u, p = blockIdx.x >> 3;
@@ -387,6 +500,8 @@ __global__ void __launch_bounds__(kBlock) k_fine_gs(SellView<T> S, FuseArgs<T> A
     }
     if constexpr (!SM)
       if (t == 0) s_ep[nr] = static_cast<int32_t>(ne);
+    if constexpr (SM)
+      if (t == 0) s_nteam = 0;
   }
   if constexpr (!GIVEN) {
     // slice k of the window holds the positions r0 + 64 k .. (rows of the window, sorted by length)
@@ -412,24 +527,12 @@ __global__ void __launch_bounds__(kBlock) k_fine_gs(SellView<T> S, FuseArgs<T> A
       const int m = b - a;
       if (m == 0 || m > CMAX) continue;
       if constexpr (SM) {
-        block_solve<T>(s_x + s_cf[j], m, s_r + a, 1);
-      } else if constexpr (FWD) {
-        for (int p = a; p < b; p++) {
-          T acc = s_r[p];
-          for (int k = s_ep[p]; k < s_ep[p + 1]; k++) {
-            const int c = s_col[k];
-            if (c < p) acc -= s_val[k] * s_x[c];
-          }
-          s_x[p] = acc / s_dg[p];
-        }
+        if (m > kRegCell) s_team[atomicAdd(&s_nteam, 1)] = static_cast<int16_t>(j);
+        else block_solve_small<T>(s_x + s_cf[j], m, s_r + a);
       } else {
-        for (int p = b - 1; p >= a; p--) {
-          T acc = s_r[p];
-          for (int k = s_ep[p]; k < s_ep[p + 1]; k++) {
-            const int c = s_col[k];
-            if (c > p) acc -= s_val[k] * s_x[c];
-          }
-          s_x[p] = acc / s_dg[p];
+        for (int i = 0; i < m; i++) {
+          const int p = FWD ? a + i : b - 1 - i;
+          s_x[p] = subst_row<T, FWD>(s_r[p], s_ep[p], s_ep[p + 1], p, s_col, s_val, s_x) / s_dg[p];
         }
       }
       for (int i = a; i < b; i++) s_mine[i] = 1;
@@ -464,18 +567,36 @@ __global__ void __launch_bounds__(kBlock) k_fine_gs(SellView<T> S, FuseArgs<T> A
   }
   if (!staged) return;
   __syncthreads();
+  if constexpr (SM) {  // the window's larger cells, one wavefront each
+    const int nt = s_nteam;
+    if (nt > 0) {
+      for (int k = t >> 6; k < nt; k += kBlock / 64) {
+        const int j = s_team[k];
+        const int a = s_cr[j];
+        block_solve_wave<T>(s_x + s_cf[j], s_cr[j + 1] - a, s_r + a, lane);
+      }
+      __syncthreads();
+    }
+  }
   for (int i = t; i < nr; i += kBlock) {
     if (s_mine[i]) A.u[r0 + i] = s_u[i] + (SM ? s_r[i] : s_x[i]);
     else if (A.big && !GIVEN) A.d[r0 + i] = s_r[i];
   }
 }
 
-// The same substitution for the big cells of one color, one wavefront-sized workgroup per cell (barriers between
-// levels are then nearly free): rows are taken level by level of the cell's dependency schedule (the rows of a level
-// use only values of earlier levels), with a barrier between levels;
-// each row's arithmetic is the thread-per-cell kernel's, so the results are identical. Global memory is coherent
-// within a workgroup at the barrier (all its wavefronts share one CU).
-constexpr int kSubstLanes = 64;
+// The same substitution for the big cells of one color, one workgroup per cell: rows are taken level by level of the
+// cell's dependency schedule (the rows of a level use only values of earlier levels), with a barrier between levels;
+// each row's arithmetic is the thread-per-cell kernel's (the same couplings in the same order), so the results are
+// identical. The cell's vector lives in LDS while it is solved, and each thread loads the rows of its first
+// kSubstRegRows schedule positions (row, diagonal, first kSubstRegCouplings in-cell couplings) into registers before
+// the first level, so a level costs LDS reads and a barrier instead of a chain of dependent global loads. A cell of
+// more rows than the LDS holds, or with a deeper schedule than kSubstLevels, takes the same arithmetic on global
+// memory (coherent within a workgroup at the barrier: all its wavefronts share one CU).
+constexpr int kSubstLanes = 256;
+constexpr int kSubstRegRows = 4;
+constexpr int kSubstRegCouplings = 8;
+constexpr int kSubstLevels = 256;
+constexpr int kSubstDynBytes = 48 * 1024;
 
 template <class T, bool FWD>
 __global__ void __launch_bounds__(kSubstLanes) k_fine_subst_big(const int32_t *__restrict__ crow,
@@ -486,24 +607,105 @@ __global__ void __launch_bounds__(kSubstLanes) k_fine_subst_big(const int32_t *_
                                                             const int32_t *__restrict__ cells, int64_t b_begin,
                                                             const int32_t *__restrict__ lofs,
                                                             const int32_t *__restrict__ lptr,
-                                                            const int32_t *__restrict__ sched) {
+                                                            const int32_t *__restrict__ sched, int lds_rows) {
+  constexpr int R = kSubstRegRows, KM = kSubstRegCouplings;
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int32_t s_lp[kSubstLevels + 1];
+  T *s_d = reinterpret_cast<T *>(smem);
+  const int32_t t = static_cast<int32_t>(threadIdx.x);
   const int64_t b = b_begin + blockIdx.x;
   const int32_t q = cells[b];
   const int32_t a = crow[q], e = crow[q + 1];
   const int32_t l0 = lofs[b], l1 = lofs[b + 1];
-  for (int32_t lv = l0; lv + 1 < l1; lv++) {
-    for (int32_t i = lptr[lv] + static_cast<int32_t>(threadIdx.x); i < lptr[lv + 1]; i += kSubstLanes) {
-      const int32_t p = sched[i];
-      T acc = src[p];
-      for (int32_t k = icp[p]; k < icp[p + 1]; k++) {
-        const int32_t c = icc[k];
-        if (FWD ? c < p : c > p) acc -= icv[k] * d[c];
+  const int32_t nl = l1 - l0;  // level starts and the end
+  if (e - a > lds_rows || nl > kSubstLevels + 1) {
+    for (int32_t lv = l0; lv + 1 < l1; lv++) {
+      for (int32_t i = lptr[lv] + t; i < lptr[lv + 1]; i += kSubstLanes) {
+        const int32_t p = sched[i];
+        T acc = src[p];
+        for (int32_t k = icp[p]; k < icp[p + 1]; k++) {
+          const int32_t c = icc[k];
+          if (FWD ? c < p : c > p) acc -= icv[k] * d[c];
+        }
+        d[p] = acc / diag[p];
       }
-      d[p] = acc / diag[p];
+      __syncthreads();
+    }
+    for (int32_t p = a + t; p < e; p += kSubstLanes) x[p] += d[p];
+    return;
+  }
+  for (int32_t p = a + t; p < e; p += kSubstLanes) s_d[p - a] = src[p];
+  for (int32_t k = t; k < nl; k += kSubstLanes) s_lp[k] = lptr[l0 + k];
+  // schedule positions a + t + kSubstLanes j (j < R), rows and couplings relative to a
+  int32_t rp[R], rk[R], rn[R], rc[R][KM];
+  T rdg[R], rv[R][KM];
+#pragma unroll
+  for (int j = 0; j < R; j++) {
+    const int32_t i = a + t + kSubstLanes * j;
+    rp[j] = 0;
+    rk[j] = 0;
+    rn[j] = 0;
+    rdg[j] = T(1);
+#pragma unroll
+    for (int k = 0; k < KM; k++) {
+      rc[j][k] = 0;
+      rv[j][k] = T(0);
+    }
+    if (i < e) {
+      const int32_t p = sched[i];
+      rp[j] = p - a;
+      rdg[j] = diag[p];
+      rk[j] = icp[p];
+      rn[j] = icp[p + 1] - rk[j];
+#pragma unroll
+      for (int k = 0; k < KM; k++)
+        if (k < rn[j]) {
+          rc[j][k] = icc[rk[j] + k] - a;
+          rv[j][k] = icv[rk[j] + k];
+        }
+    }
+  }
+  __syncthreads();
+  for (int32_t lv = 0; lv + 1 < nl; lv++) {
+    const int32_t lo = s_lp[lv], hi = s_lp[lv + 1];
+#pragma unroll
+    for (int j = 0; j < R; j++) {
+      const int32_t i = a + t + kSubstLanes * j;
+      if (i >= lo && i < hi) {
+        const int32_t p = rp[j];
+        T acc = s_d[p];
+#pragma unroll
+        for (int k = 0; k < KM; k++)
+          if (k < rn[j]) {
+            const int32_t c = rc[j][k];
+            if (FWD ? c < p : c > p) acc -= rv[j][k] * s_d[c];
+          }
+        for (int32_t k = rk[j] + KM; k < rk[j] + rn[j]; k++) {
+          const int32_t c = icc[k] - a;
+          if (FWD ? c < p : c > p) acc -= icv[k] * s_d[c];
+        }
+        s_d[p] = acc / rdg[j];
+      }
+    }
+    // positions past the register-held ones
+    int32_t i = a + t + kSubstLanes * R;
+    if (i < lo) i += (lo - i + kSubstLanes - 1) / kSubstLanes * kSubstLanes;
+    for (; i < hi; i += kSubstLanes) {
+      const int32_t pa = sched[i], p = pa - a;
+      T acc = s_d[p];
+      for (int32_t k = icp[pa]; k < icp[pa + 1]; k++) {
+        const int32_t c = icc[k] - a;
+        if (FWD ? c < p : c > p) acc -= icv[k] * s_d[c];
+      }
+      s_d[p] = acc / diag[pa];
     }
     __syncthreads();
   }
-  for (int32_t p = a + static_cast<int32_t>(threadIdx.x); p < e; p += kSubstLanes) x[p] += d[p];
+  for (int32_t p = a + t; p < e; p += kSubstLanes) {
+    const T v = s_d[p - a];
+    d[p] = v;
+    x[p] += v;
+  }
 }
 
 // g[q] = sum of d over the rows of level-L cell q (rows ascending); cells of more than `big` rows are left to
@@ -2469,14 +2671,16 @@ static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd
   }
   if (nb > 0) {
     const int dir = fwd ? 0 : 1;
+    const int lds_rows = std::min(F.big_max_rows, kSubstDynBytes / static_cast<int>(sizeof(T)));
+    const size_t lds = (static_cast<size_t>(lds_rows) * sizeof(T) + 15) / 16 * 16;
     if (fwd)
-      k_fine_subst_big<T, true><<<static_cast<unsigned>(nb), kSubstLanes, 0, h->stream>>>(
+      k_fine_subst_big<T, true><<<static_cast<unsigned>(nb), kSubstLanes, lds, h->stream>>>(
           F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F), P<T>::diag(F), src, d, u, F.big_cells, b0, F.big_lofs[dir],
-          F.big_lptr[dir], F.big_sched[dir]);
+          F.big_lptr[dir], F.big_sched[dir], lds_rows);
     else
-      k_fine_subst_big<T, false><<<static_cast<unsigned>(nb), kSubstLanes, 0, h->stream>>>(
+      k_fine_subst_big<T, false><<<static_cast<unsigned>(nb), kSubstLanes, lds, h->stream>>>(
           F.crow, F.ic_ptr, F.ic_col, P<T>::icv(F), P<T>::diag(F), src, d, u, F.big_cells, b0, F.big_lofs[dir],
-          F.big_lptr[dir], F.big_sched[dir]);
+          F.big_lptr[dir], F.big_sched[dir], lds_rows);
   }
 }
 
