@@ -477,26 +477,85 @@ __global__ void __launch_bounds__(kBlock) k_fine_gs(SellView<T> S, FuseArgs<T> A
   if (GIVEN && nq == 1 && nr > CMAX) return;  // one cell left to k_fine_subst_big, which reads src
   const bool staged = nr <= kFuseRows && ne <= A.ent_cap && nq <= kFuseCells;  // uniform over the workgroup
   if (staged) {
-    for (int k = t; k <= nq; k += kBlock) {
-      s_cr[k] = A.crow[q0 + k] - r0;
-      if constexpr (SM) s_cf[k] = static_cast<int32_t>(A.boff[q0 + k] - e0);
-    }
-    for (int k = t; k < ne; k += kBlock) {
-      if constexpr (SM) {
-        s_x[k] = A.fac[e0 + k];
-      } else {
-        s_col[k] = static_cast<int16_t>(A.icc[e0 + k] - r0);
-        s_val[k] = A.icv[e0 + k];
+    // every thread issues all its loads of a batch before its LDS stores, so the staging waits on one round trip to
+    // memory per batch instead of one per element
+    constexpr int kCellIt = (kFuseCells + 1 + kBlock - 1) / kBlock, kRowIt = kFuseRows / kBlock, kEntBatch = 8;
+    {
+      int32_t cr[kCellIt];
+      int64_t cf[kCellIt];
+#pragma unroll
+      for (int u = 0; u < kCellIt; u++) {
+        const int k = t + u * kBlock;
+        if (k <= nq) {
+          cr[u] = A.crow[q0 + k];
+          if constexpr (SM) cf[u] = A.boff[q0 + k];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kCellIt; u++) {
+        const int k = t + u * kBlock;
+        if (k <= nq) {
+          s_cr[k] = cr[u] - r0;
+          if constexpr (SM) s_cf[k] = static_cast<int32_t>(cf[u] - e0);
+        }
       }
     }
-    for (int i = t; i < nr; i += kBlock) {
-      s_u[i] = A.u[r0 + i];
-      if constexpr (!SM) {
-        s_dg[i] = A.diag[r0 + i];
-        s_ep[i] = static_cast<int32_t>(A.icp[r0 + i] - e0);
+    for (int kb = t; kb < ne; kb += kEntBatch * kBlock) {
+      T v[kEntBatch];
+      int32_t c[kEntBatch];
+#pragma unroll
+      for (int u = 0; u < kEntBatch; u++) {
+        const int k = kb + u * kBlock;
+        if (k < ne) {
+          if constexpr (SM) {
+            v[u] = A.fac[e0 + k];
+          } else {
+            c[u] = A.icc[e0 + k];
+            v[u] = A.icv[e0 + k];
+          }
+        }
       }
-      if constexpr (GIVEN) s_r[i] = A.src[r0 + i];
-      s_mine[i] = 0;
+#pragma unroll
+      for (int u = 0; u < kEntBatch; u++) {
+        const int k = kb + u * kBlock;
+        if (k < ne) {
+          if constexpr (SM) {
+            s_x[k] = v[u];
+          } else {
+            s_col[k] = static_cast<int16_t>(c[u] - r0);
+            s_val[k] = v[u];
+          }
+        }
+      }
+    }
+    {
+      T uu[kRowIt], dg[kRowIt], rr[kRowIt];
+      int32_t ep[kRowIt];
+#pragma unroll
+      for (int u = 0; u < kRowIt; u++) {
+        const int i = t + u * kBlock;
+        if (i < nr) {
+          uu[u] = A.u[r0 + i];
+          if constexpr (!SM) {
+            dg[u] = A.diag[r0 + i];
+            ep[u] = A.icp[r0 + i];
+          }
+          if constexpr (GIVEN) rr[u] = A.src[r0 + i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kRowIt; u++) {
+        const int i = t + u * kBlock;
+        if (i < nr) {
+          s_u[i] = uu[u];
+          if constexpr (!SM) {
+            s_dg[i] = dg[u];
+            s_ep[i] = static_cast<int32_t>(ep[u] - e0);
+          }
+          if constexpr (GIVEN) s_r[i] = rr[u];
+          s_mine[i] = 0;
+        }
+      }
     }
     if constexpr (!SM)
       if (t == 0) s_ep[nr] = static_cast<int32_t>(ne);
@@ -634,7 +693,15 @@ __global__ void __launch_bounds__(kSubstLanes) k_fine_subst_big(const int32_t *_
     for (int32_t p = a + t; p < e; p += kSubstLanes) x[p] += d[p];
     return;
   }
-  for (int32_t p = a + t; p < e; p += kSubstLanes) s_d[p - a] = src[p];
+  for (int32_t p0 = a + t; p0 < e; p0 += 4 * kSubstLanes) {  // four loads in flight per thread
+    T v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (p0 + u * kSubstLanes < e) v[u] = src[p0 + u * kSubstLanes];
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+      if (p0 + u * kSubstLanes < e) s_d[p0 + u * kSubstLanes - a] = v[u];
+  }
   for (int32_t k = t; k < nl; k += kSubstLanes) s_lp[k] = lptr[l0 + k];
   // schedule positions a + t + kSubstLanes j (j < R), rows and couplings relative to a
   int32_t rp[R], rk[R], rn[R], rc[R][KM];
@@ -738,7 +805,17 @@ __global__ void __launch_bounds__(64) k_fine_restrict_big(const int32_t *__restr
   for (int32_t c0 = a; c0 < b; c0 += kRestrictChunk) {
     const int m = min(kRestrictChunk, b - c0);
     __syncthreads();
-    for (int i = threadIdx.x; i < m; i += 64) s_d[i] = d[c0 + i];
+    T v[kRestrictChunk / 64];  // all loads of the chunk in flight before the LDS stores
+#pragma unroll
+    for (int u = 0; u < kRestrictChunk / 64; u++) {
+      const int i = static_cast<int>(threadIdx.x) + 64 * u;
+      if (i < m) v[u] = d[c0 + i];
+    }
+#pragma unroll
+    for (int u = 0; u < kRestrictChunk / 64; u++) {
+      const int i = static_cast<int>(threadIdx.x) + 64 * u;
+      if (i < m) s_d[i] = v[u];
+    }
     __syncthreads();
     if (threadIdx.x == 0)
       for (int i = 0; i < m; i++) acc += s_d[i];
