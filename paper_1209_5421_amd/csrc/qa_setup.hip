@@ -1887,11 +1887,11 @@ extern "C" amg_status amg_estimate_bytes(int64_t n, int64_t nnz, const amg_optio
   const int nlev = depth_rule(n, o.coarse_max, L, kc);
   double b = 0;
   // fine: permuted CSR (12 B/nnz + 8 B/row), sliced ELL (padding allowance 1.35) in FP64 + FP32 + columns,
-  // in-cell lists (<= nnz), vectors (3 FP64 + 3 FP32 workspace, 9 FP64 outer), indices
+  // in-cell lists (<= nnz), vectors (4 FP64 + 4 FP32 workspace, 9 FP64 outer), indices
   b += 12.0 * nnz + 8.0 * (n + 1);
   b += 1.35 * (nnz + n) * (8 + 4 + 4);
   b += 16.0 * nnz;
-  b += n * (3 * 8 + 3 * 4 + 9 * 8 + 4 * 4 + 8);
+  b += n * (4 * 8 + 4 * 4 + 9 * 8 + 4 * 4 + 8);
   if (nlev > 1) {
     const double nL = std::ldexp(1.0, 2 * L);
     // quadtree levels: 9 FP64 + 9 FP32 + flags + 8 vectors per precision; geometric sum 4/3

@@ -199,6 +199,35 @@ __device__ inline XT sell_row(const SellView<T> &S, int64_t off, int w, int lane
   return acc;
 }
 
+// sell_row with the entries of columns in [lo, hi) taken from alt (from zero when alt is null) instead of x: the
+// same products in the same order, so with alt holding what x held there the result is the same bit for bit
+template <class T>
+__device__ inline T sell_row_split(const SellView<T> &S, int64_t off, int w, int lane, const T *__restrict__ x,
+                                   const T *__restrict__ alt, int32_t lo, int32_t hi) {
+  const T *vp = S.val + off + lane;
+  const int32_t *cp = S.col + off + lane;
+  auto get = [&](int32_t c) -> T { return (c >= lo && c < hi) ? (alt ? alt[c] : T(0)) : x[c]; };
+  T acc = 0;
+  int k = 0;
+  for (; k + 4 <= w; k += 4) {
+    const int32_t c0 = cp[0], c1 = cp[64], c2 = cp[128], c3 = cp[192];
+    const T v0 = vp[0], v1 = vp[64], v2 = vp[128], v3 = vp[192];
+    const T x0 = get(c0), x1 = get(c1), x2 = get(c2), x3 = get(c3);
+    acc += v0 * x0;
+    acc += v1 * x1;
+    acc += v2 * x2;
+    acc += v3 * x3;
+    vp += 256;
+    cp += 256;
+  }
+  for (; k < w; k++) {
+    acc += vp[0] * get(cp[0]);
+    vp += 64;
+    cp += 64;
+  }
+  return acc;
+}
+
 // Which slices a launch over the colors [c0, c1) gives to which workgroup. Workgroups are dispatched to the eight
 // XCDs round-robin (workgroup b runs on XCD b mod 8) and every XCD has an L2 of its own. In the XCD-aware order,
 // workgroup b takes its slices from chunk b mod 8 of every color in [c0, c1), the same eighth of the Morton range in
@@ -388,8 +417,10 @@ __device__ inline void block_solve_wave(const T *Lf, int m, T *v, int lane) {
 // fused window stages; its factor values or in-cell couplings go to dynamic LDS sized by the setup's largest window
 // (at most kFuseDynBytes). A window that exceeds the staging arrays takes the same arithmetic on global memory; a
 // window of one cell too large to solve here has, with GIVEN, nothing to do (k_fine_subst_big reads the given
-// residual itself). Without GIVEN the color's cells are not coupled to each other, so the workgroups are
-// independent; u of a window's rows changes only in its own workgroup.
+// residual itself). Without GIVEN either the color's cells are not coupled to each other, or (split) the residual
+// reads the color's own rows from alt, which holds their values from before the phase (zero in a sweep from zero;
+// the copy the prolongation makes before the backward sweep), so no workgroup reads another's corrections and the
+// residual is the separate pass's value for value; u of a window's rows changes only in its own workgroup.
 constexpr int kFuseRows = kFuseStageRows;
 constexpr int kFuseCells = 512;
 constexpr int kFuseDynBytes = 48 * 1024;
@@ -434,6 +465,9 @@ struct FuseArgs {
   int xcd;                       // 1: XCD-aware window order (grid = 8 x the largest per-XCD share)
   int big;                       // the color has cells left to k_fine_subst_big: write their residual to d
   int ent_cap;                   // factor values / couplings the dynamic LDS holds
+  int split;                     // 1: the residual reads the color's own rows [clo, chi) from alt (zero when null)
+  int32_t clo, chi;
+  const T *alt;
   const T *f, *src;              // src: the given residual (GIVEN)
   T *u, *d;
   const T *diag, *icv, *fac;
@@ -570,7 +604,8 @@ __global__ void __launch_bounds__(kBlock) k_fine_gs(SellView<T> S, FuseArgs<T> A
         const int32_t row = S.srow[p];
         const int64_t off = S.ptr[sl];
         const int wd = static_cast<int>((S.ptr[sl + 1] - off) >> 6);
-        const T r = A.f[row] - sell_row<T, T>(S, off, wd, lane, A.u);
+        const T r = A.f[row] - (A.split ? sell_row_split<T>(S, off, wd, lane, A.u, A.alt, A.clo, A.chi)
+                                        : sell_row<T, T>(S, off, wd, lane, A.u));
         if (staged) s_r[row - r0] = r;
         else A.d[row] = r;
       }
@@ -823,14 +858,17 @@ __global__ void __launch_bounds__(64) k_fine_restrict_big(const int32_t *__restr
   if (threadIdx.x == 0) g[q] = acc;
 }
 
+// u += P e on the fine level; snap (when not null) gets a copy of the new u
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_fine_prolong(int64_t n, const int32_t *__restrict__ agg_q,
                                                           const T *__restrict__ e, Pending<T> pend,
-                                                          T *__restrict__ u) {
+                                                          T *__restrict__ u, T *__restrict__ snap) {
   const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= n) return;
   const T em = pend.apply(e, static_cast<uint32_t>(agg_q[p]));
-  u[p] += em;
+  const T v = u[p] + em;
+  u[p] = v;
+  if (snap) snap[p] = v;
 }
 
 // ---------------------------------------------------------------------------------------------------------------
@@ -2705,13 +2743,18 @@ static void fine_gs_launch(amg_hierarchy *h, unsigned grid, FuseArgs<T> A) {
 }
 
 // One color phase of the fine smoother: the fused residual and cell solves (k_fine_gs), then the cells left to the
-// level-scheduled substitution. from_f: the first phase of a sweep from zero, whose residual is f.
+// level-scheduled substitution. from_f: the first phase of a sweep from zero, whose residual is f. Where cells of a
+// color are coupled to each other, `old` says where the values of the color's rows from before the phase are:
+// kOldZero (a sweep from zero: still zero) or kOldSnap (the fine workspace's snapshot) let the fused phase form the
+// residual itself; kOldNone takes a separate residual pass first.
+enum { kOldNone = 0, kOldZero = 1, kOldSnap = 2 };
 template <class T>
-static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd, bool from_f) {
+static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd, bool from_f, int old = kOldNone) {
   const FineLevel &F = h->fine;
   const T *src = from_f ? f : d;
-  const bool given = from_f || F.same_color;
-  if (!from_f && F.same_color) fine_resid<T>(h, f, u, d, c, c + 1, -1);
+  const bool split = !from_f && F.same_color && old != kOldNone;
+  const bool given = from_f || (F.same_color && !split);
+  if (!from_f && F.same_color && !split) fine_resid<T>(h, f, u, d, c, c + 1, -1);
   const int64_t b0 = F.big_color[c], nb = F.big_color[c + 1] - b0;
   FuseArgs<T> A{};
   A.win_q = F.win_q;
@@ -2733,6 +2776,10 @@ static void fine_phase(amg_hierarchy *h, const T *f, T *u, T *d, int c, bool fwd
   A.icp = F.ic_ptr;
   A.icc = F.ic_col;
   A.boff = F.boff;
+  A.split = split ? 1 : 0;
+  A.clo = static_cast<int32_t>(F.color_row[c]);
+  A.chi = static_cast<int32_t>(F.color_row[c + 1]);
+  A.alt = old == kOldSnap ? P<T>::W(h)[0].r : nullptr;
   if (A.nwin > 0) {
     const unsigned grid = static_cast<unsigned>(A.xcd ? 8 * ((A.nwin + 7) / 8) : A.nwin);
     if (h->opt.smoother) {
@@ -2770,8 +2817,12 @@ static void bhat_fine(amg_hierarchy *h, const T *f, T *u) {
   k_fill<T><<<nblk(F.n), kBlock, 0, s>>>(F.n, u, T(0));
   const int sweeps = h->opt.sweeps;
   const int nc = F.ncolor;
+  // one sweep each way: the pre-smoothing's color rows are zero before their phase, and the post-smoothing's hold
+  // the prolongation's values, which it copies to the snapshot
+  const bool one = sweeps == 1 && F.same_color;
   for (int sw = 0; sw < sweeps; sw++)
-    for (int c = 0; c < nc; c++) fine_phase<T>(h, f, u, w.d, c, true, sw == 0 && c == 0);
+    for (int c = 0; c < nc; c++)
+      fine_phase<T>(h, f, u, w.d, c, true, sw == 0 && c == 0, one ? kOldZero : kOldNone);
   LevelWork<T> &wc = P<T>::W(h)[1];
   fine_resid<T>(h, f, u, w.d, 0, F.ncolor, P<T>::kResid);
   const int64_t nL = static_cast<int64_t>(1) << (h->dim * h->L);
@@ -2779,9 +2830,9 @@ static void bhat_fine(amg_hierarchy *h, const T *f, T *u) {
   k_fine_restrict<T><<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, w.d, wc.g, F.nbig ? big : INT32_MAX);
   if (F.nbig) k_fine_restrict_big<T><<<static_cast<unsigned>(F.nbig), 64, 0, s>>>(F.big_cells, F.crow, w.d, wc.g);
   const Pending<T> pend = coarse_solve_or_cycle<T>(h, 1);
-  k_fine_prolong<T><<<nblk(F.n), kBlock, 0, s>>>(F.n, F.agg_q, wc.e, pend, u);
+  k_fine_prolong<T><<<nblk(F.n), kBlock, 0, s>>>(F.n, F.agg_q, wc.e, pend, u, one ? w.r : nullptr);
   for (int sw = 0; sw < sweeps; sw++)
-    for (int c = nc - 1; c >= 0; c--) fine_phase<T>(h, f, u, w.d, c, false, false);
+    for (int c = nc - 1; c >= 0; c--) fine_phase<T>(h, f, u, w.d, c, false, false, one ? kOldSnap : kOldNone);
 }
 
 template <class T>
@@ -2904,6 +2955,10 @@ amg_status alloc_workspaces(amg_hierarchy *h) {
       W[0].u = dalloc_n<T>(h, n);
       W[0].d = dalloc_n<T>(h, n);
       if (!W[0].f || !W[0].u || !W[0].d) return false;
+      if (h->fine.same_color) {  // the fine smoother's snapshot of u before the backward sweep
+        W[0].r = dalloc_n<T>(h, n);
+        if (!W[0].r) return false;
+      }
       for (int l = 1; l < h->nlev; l++) {
         const int64_t m = h->lev[l].n;
         W[l].g = dalloc_n<T>(h, m);
@@ -2940,18 +2995,20 @@ amg_status alloc_workspaces(amg_hierarchy *h) {
 
 double kernel_bytes(const amg_hierarchy *h, int kind) {
   const double n = static_cast<double>(h->n), nnz = static_cast<double>(h->fine.nnz);
+  const bool given_resid = h->fine.same_color && h->opt.sweeps != 1;
   switch (kind) {
     case KK_SPMV64: return 12.0 * nnz + 24.0 * n;   // values + columns, x, q written, r read for (r, p)
     case KK_RESID_FINE64: return 12.0 * nnz + 24.0 * n;
     case KK_RESID_FINE32: return 8.0 * nnz + 12.0 * n;
     // one fused color phase: the color's share of the residual pass (f read, x read, x written) and of the cell
     // solves' data (factor values, or in-cell couplings and the diagonal); where the colour's cells are coupled to
-    // each other the residual comes from a separate pass, and the phase reads it (4 or 8 B per row) instead
-    case KK_GS_FINE64:
-      return ((h->fine.same_color ? 24.0 * n : 12.0 * nnz + 24.0 * n) +
+    // each other and the smoother makes more than one sweep, the residual comes from a separate pass, and the phase
+    // reads it (4 or 8 B per row) instead
+    case KK_GS_FINE64:  // the residual is given only where coupled cells of a color take a separate pass
+      return ((given_resid ? 24.0 * n : 12.0 * nnz + 24.0 * n) +
               (h->opt.smoother ? 8.0 * h->fine.bfac_n : 12.0 * h->fine.ic_nnz + 8.0 * n)) / h->fine.ncolor;
     case KK_GS_FINE32:
-      return ((h->fine.same_color ? 12.0 * n : 8.0 * nnz + 12.0 * n) +
+      return ((given_resid ? 12.0 * n : 8.0 * nnz + 12.0 * n) +
               (h->opt.smoother ? 4.0 * h->fine.bfac_n : 8.0 * h->fine.ic_nnz + 4.0 * n)) / h->fine.ncolor;
     case KK_ENGINE64: return h->engine_flops[0];
     case KK_ENGINE32: return h->engine_flops[1];
