@@ -266,8 +266,8 @@ def main():
         print(json.dumps(rec))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: multi-GPU sharding is not implemented "
-                                   "(see the design notes); run with --gpus 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU: sharding across GPUs is not implemented; "
+                                   "run with --gpus 1"}))
         sys.exit(2)
 
     from paper_1209_5421_amd import amg, meshgen

@@ -4,7 +4,7 @@
  * by the HIP library, which shares no code with it. Build with -O2 -ffp-contract=off (no fused multiply-add, no
  * fast-math), so every floating-point step is the plain IEEE operation written here.
  *
- * Readings taken where the paper is silent, ambiguous or garbled (each is also listed in the design notes):
+ * Readings taken where the paper is silent, ambiguous or garbled:
  *  R1 depth (Section 3.1): L = max{l : 4^l < N} (the stated strict constraint), not floor(log N / log 4); they
  *     differ only when N is a power of 4. Single level when N <= coarse_max.
  *  R2 cell index (Section 4.2, level-L listing): t = (x - a1)/(b1 - a1) in IEEE double, then floor(t * 2^L),
