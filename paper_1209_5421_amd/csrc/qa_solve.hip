@@ -174,29 +174,38 @@ struct SellView {
 
 // (A x)_row for the row of `lane` in a slice of width w starting at entry `off`: the loop is unrolled by four with the
 // column and value loads of a group issued before its gathers, so each wavefront keeps several gathers in flight
-template <class T, class XT>
-__device__ inline XT sell_row(const SellView<T> &S, int64_t off, int w, int lane, const XT *__restrict__ x) {
+// sum over a slice row's entries of value x gathered entry, in entry order. Entries go in batches of kSellBatch:
+// a batch's columns and values are loaded together, then its gathers, then its products are added one by one, so a
+// row waits on two memory round trips per batch. The last batch's loads past the row's width are clamped to its last
+// entry and their products skipped, so the sum is the plain loop's bit for bit. get(c) returns the gathered entry.
+constexpr int kSellBatch = 8;
+template <class T, class XT, class Get>
+__device__ __forceinline__ XT sell_row_batched(const SellView<T> &S, int64_t off, int w, int lane, Get get) {
   const T *vp = S.val + off + lane;
   const int32_t *cp = S.col + off + lane;
   XT acc = 0;
-  int k = 0;
-  for (; k + 4 <= w; k += 4) {
-    const int32_t c0 = cp[0], c1 = cp[64], c2 = cp[128], c3 = cp[192];
-    const T v0 = vp[0], v1 = vp[64], v2 = vp[128], v3 = vp[192];
-    const XT x0 = x[c0], x1 = x[c1], x2 = x[c2], x3 = x[c3];
-    acc += v0 * x0;
-    acc += v1 * x1;
-    acc += v2 * x2;
-    acc += v3 * x3;
-    vp += 256;
-    cp += 256;
-  }
-  for (; k < w; k++) {
-    acc += vp[0] * x[cp[0]];
-    vp += 64;
-    cp += 64;
+  for (int k = 0; k < w; k += kSellBatch) {
+    int32_t c[kSellBatch];
+    T v[kSellBatch];
+    XT xv[kSellBatch];
+#pragma unroll
+    for (int u = 0; u < kSellBatch; u++) {
+      const int e = min(k + u, w - 1) * 64;
+      c[u] = cp[e];
+      v[u] = vp[e];
+    }
+#pragma unroll
+    for (int u = 0; u < kSellBatch; u++) xv[u] = get(c[u]);
+#pragma unroll
+    for (int u = 0; u < kSellBatch; u++)
+      if (k + u < w) acc += v[u] * xv[u];
   }
   return acc;
+}
+
+template <class T, class XT>
+__device__ inline XT sell_row(const SellView<T> &S, int64_t off, int w, int lane, const XT *__restrict__ x) {
+  return sell_row_batched<T, XT>(S, off, w, lane, [&](int32_t c) -> XT { return x[c]; });
 }
 
 // sell_row with the entries of columns in [lo, hi) taken from alt (from zero when alt is null) instead of x: the
@@ -204,28 +213,9 @@ __device__ inline XT sell_row(const SellView<T> &S, int64_t off, int w, int lane
 template <class T>
 __device__ inline T sell_row_split(const SellView<T> &S, int64_t off, int w, int lane, const T *__restrict__ x,
                                    const T *__restrict__ alt, int32_t lo, int32_t hi) {
-  const T *vp = S.val + off + lane;
-  const int32_t *cp = S.col + off + lane;
-  auto get = [&](int32_t c) -> T { return (c >= lo && c < hi) ? (alt ? alt[c] : T(0)) : x[c]; };
-  T acc = 0;
-  int k = 0;
-  for (; k + 4 <= w; k += 4) {
-    const int32_t c0 = cp[0], c1 = cp[64], c2 = cp[128], c3 = cp[192];
-    const T v0 = vp[0], v1 = vp[64], v2 = vp[128], v3 = vp[192];
-    const T x0 = get(c0), x1 = get(c1), x2 = get(c2), x3 = get(c3);
-    acc += v0 * x0;
-    acc += v1 * x1;
-    acc += v2 * x2;
-    acc += v3 * x3;
-    vp += 256;
-    cp += 256;
-  }
-  for (; k < w; k++) {
-    acc += vp[0] * get(cp[0]);
-    vp += 64;
-    cp += 64;
-  }
-  return acc;
+  return sell_row_batched<T, T>(S, off, w, lane, [&](int32_t c) -> T {
+    return (c >= lo && c < hi) ? (alt ? alt[c] : T(0)) : x[c];
+  });
 }
 
 // Which slices a launch over the colors [c0, c1) gives to which workgroup. Workgroups are dispatched to the eight
