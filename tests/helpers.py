@@ -228,3 +228,16 @@ def assembly_in_stated_order(pts, tris, kappa, dirichlet):
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.add.at(row_ptr, np.array([k[0] for k in keys]) + 1, 1)
     return np.cumsum(row_ptr), np.array([k[1] for k in keys], dtype=np.int32), vals
+
+
+def cluster_problem(side=100, cluster=13000, seed=21):
+    """Poisson on a Delaunay mesh of a jittered side x side lattice of the unit square plus `cluster` uniform random
+    points inside one level-L cell (L = 7 for the sizes here: cell (51, 51), [51/128, 52/128)^2), so that one cell
+    holds more unknowns than the big-cell substitution stages in LDS. Dirichlet on the square's boundary."""
+    from paper_1209_5421_amd import meshgen as mg
+    lat = mg.jittered_points(side, seed)
+    rng = np.random.default_rng(seed)
+    lo, hi = 51 / 128 + 1e-4, 52 / 128 - 1e-4
+    pts = np.vstack([lat, lo + (hi - lo) * rng.random((cluster, 2))])
+    tris = mg.delaunay(pts)
+    return mg._problem(f"cluster{side}_{cluster}", pts, tris, kind="cluster", side=side, cluster=cluster, seed=seed)

@@ -419,3 +419,46 @@ def test_footprint_within_estimate_large(smoother):
           flush=True)
     assert 0 < g.bytes() <= est
     g.close()
+
+
+_cluster = {}
+
+
+@pytest.mark.parametrize("smoother", [1, 0])
+def test_big_cell_beyond_lds(smoother):
+    """One level-L cell of 13,001 unknowns (a random cluster inside a jittered lattice): more than the big-cell
+    substitution stages in LDS (12,288 FP32 or 6,144 FP64 values), so its in-cell substitution takes the kernel's
+    global-memory path in both precisions. Hierarchy bit-exact; one preconditioner application against the oracle's
+    (FP64 1e-10, FP32 1e-4); the FP64 solve to 1e-8 within one iteration of the oracle's and 1e-6 of its solution."""
+    if "p" not in _cluster:
+        _cluster["p"] = H.cluster_problem()
+    prob = _cluster["p"]
+    g = gpu_hier(prob, smoother=smoother)
+    agg = g.export_level(0)["agg"]
+    assert np.bincount(agg).max() > 12288, "the cluster does not exceed the LDS staging"
+    o = oracle.setup_problem(prob)
+    o.set_block_smoother(bool(smoother))
+    for level in range(g.num_levels):
+        assert _level_bytes(g.export_level(level)) == _level_bytes(o.export_level(level)), level
+    r = np.random.default_rng(7).standard_normal(prob.n)
+    z_o = o.apply_precond(r)
+    z64 = g.apply_precond(T(r), precision=0).cpu().numpy()
+    z32 = g.apply_precond(T(r), precision=1).cpu().numpy()
+    e64 = np.linalg.norm(z64 - z_o) / np.linalg.norm(z_o)
+    e32 = np.linalg.norm(z32 - z_o) / np.linalg.norm(z_o)
+    x_o, io = o.solve(prob.b, tol=1e-8)
+    x, info = g.solve(T(prob.b), tol=1e-8)
+    x = x.cpu().numpy()
+    ex = np.linalg.norm(x - x_o) / np.linalg.norm(x_o)
+    print(f"[gpu] cluster smoother {smoother}: precond {e64:.1e} (FP32 {e32:.1e}); iters {info['iters']} "
+          f"(oracle {io['iters']}), solution {ex:.1e}", flush=True)
+    assert e64 <= 1e-10 and e32 <= 1e-4
+    assert info["status"] == 0 and abs(info["iters"] - io["iters"]) <= 1 and ex <= 1e-6
+    g.close()
+    o.close()
+
+
+def _level_bytes(lv):
+    """Integer and value arrays of an exported level, for an exact comparison."""
+    keys = [k for k in ("agg", "color", "aj", "ax", "ovf_ptr", "ovf_col", "ovf_val") if k in lv]
+    return [(k, lv[k].tobytes()) for k in keys]
