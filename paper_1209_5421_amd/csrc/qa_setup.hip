@@ -1189,10 +1189,43 @@ static int depth_rule(int64_t n, int coarse_max, int &L, int &kc, int dim = 2) {
   return 1 + (l - k + 1);
 }
 
+// Small device-to-host reads of setup (counts, flags, the box) go through the hierarchy's pinned scalar slot. A copy
+// into pageable memory is staged by the runtime and waits on its own, so a loop of them drains the stream once per
+// value; into the pinned slot the copies of one batch are queued together and waited on once.
+struct ReadBatch {
+  amg_hierarchy *h;
+  struct Item {
+    void *dst;
+    size_t off, bytes;
+  };
+  Item items[2 * kMaxColors + 2];
+  int count = 0;
+  size_t used = 0;
+  explicit ReadBatch(amg_hierarchy *hh) : h(hh) {}
+  amg_status add(void *dst, const void *src, size_t bytes) {
+    if (!h->host_scal || count == static_cast<int>(sizeof(items) / sizeof(items[0])) ||
+        used + bytes > sizeof(double) * kScalars)
+      return AMG_ERR_INVALID;  // a batch larger than the slot is a bug of the caller
+    QA_HIP(hipMemcpyAsync(reinterpret_cast<char *>(h->host_scal) + used, src, bytes, hipMemcpyDeviceToHost,
+                          h->stream));
+    items[count++] = Item{dst, used, bytes};
+    used += (bytes + 7) & ~static_cast<size_t>(7);
+    return AMG_OK;
+  }
+  amg_status finish() {
+    QA_HIP(hipStreamSynchronize(h->stream));
+    for (int i = 0; i < count; i++)
+      std::memcpy(items[i].dst, reinterpret_cast<const char *>(h->host_scal) + items[i].off, items[i].bytes);
+    count = 0;
+    used = 0;
+    return AMG_OK;
+  }
+};
+
 static amg_status read_flag(amg_hierarchy *h, int &f) {
-  QA_HIP(hipMemcpyAsync(&f, h->dflag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-  QA_HIP(hipStreamSynchronize(h->stream));
-  return AMG_OK;
+  ReadBatch rb(h);
+  QA_TRY(rb.add(&f, h->dflag, sizeof(int)));
+  return rb.finish();
 }
 
 static amg_status sell_values(amg_hierarchy *h);
@@ -1224,17 +1257,17 @@ static amg_status build_sell(amg_hierarchy *h) {
     QA_LAUNCH_CHECK();
     QA_TRY(scan_exclusive_i32(mark, widx, nL, s, h));
     int32_t cw[kMaxColors + 1];
-    for (int c = 0; c < nc; c++)
-      QA_HIP(hipMemcpyAsync(&cw[c], widx + c * (nL / nc), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipMemcpyAsync(&cw[nc], widx + nL, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
+    ReadBatch rb(h);
+    for (int c = 0; c < nc; c++) QA_TRY(rb.add(&cw[c], widx + c * (nL / nc), sizeof(int32_t)));
+    QA_TRY(rb.add(&cw[nc], widx + nL, sizeof(int32_t)));
+    QA_TRY(rb.finish());
     F.nwin = cw[nc];
     for (int c = 0; c <= nc; c++) F.color_win[c] = cw[c];
     F.win_q = dalloc_n<int32_t>(h, F.nwin + 1);
     F.win_row = dalloc_n<int32_t>(h, F.nwin + 1);
     if (!F.win_q || !F.win_row) return AMG_ERR_NOMEM;
     k_win_fill<<<nblk(nL), kBlock, 0, s>>>(nL, F.crow, mark, widx, F.win_q, F.win_row);
-    // couplings between cells of one color: the fused smoother phase then takes its residual from a separate pass
+    // couplings between cells of one color: the fused smoother phase must then not read the color's own rows from u
     BuildTmp tflag(h, sizeof(int));
     int *flag = tflag.as<int>();
     if (!flag) return AMG_ERR_NOMEM;
@@ -1242,8 +1275,8 @@ static amg_status build_sell(amg_hierarchy *h) {
     k_same_color<<<nblk(n), kBlock, 0, s>>>(n, nL / nc, F.rp, F.ci, F.agg_q, flag);
     QA_LAUNCH_CHECK();
     int hf = 0;
-    QA_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
+    QA_TRY(rb.add(&hf, flag, sizeof(int)));
+    QA_TRY(rb.finish());
     F.same_color = hf != 0;
   } else {
     F.win_band = kSellWindow;
@@ -1265,9 +1298,9 @@ static amg_status build_sell(amg_hierarchy *h) {
   QA_TRY(scan_exclusive_i64(nsl, F.win_slice, F.nwin, s, h));
   {
     int64_t cs[kMaxColors + 1];
-    for (int c = 0; c <= nc; c++)
-      QA_HIP(hipMemcpyAsync(&cs[c], F.win_slice + F.color_win[c], sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
+    ReadBatch rb(h);
+    for (int c = 0; c <= nc; c++) QA_TRY(rb.add(&cs[c], F.win_slice + F.color_win[c], sizeof(int64_t)));
+    QA_TRY(rb.finish());
     for (int c = 0; c <= nc; c++) F.color_slice[c] = cs[c];
     F.nslices = cs[nc];
   }
@@ -1286,8 +1319,11 @@ static amg_status build_sell(amg_hierarchy *h) {
                                                                       size);
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i64(size, F.slice_ptr, F.nslices, s, h));
-  QA_HIP(hipMemcpyAsync(&F.sell_entries, F.slice_ptr + F.nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  QA_HIP(hipStreamSynchronize(s));
+  {
+    ReadBatch rb(h);
+    QA_TRY(rb.add(&F.sell_entries, F.slice_ptr + F.nslices, sizeof(int64_t)));
+    QA_TRY(rb.finish());
+  }
   F.s_col = dalloc_n<int32_t>(h, F.sell_entries);
   F.s_val64 = dalloc_n<double>(h, F.sell_entries);
   F.s_val32 = dalloc_n<float>(h, F.sell_entries);
@@ -1371,9 +1407,9 @@ static amg_status cell_list(amg_hierarchy *h, int32_t threshold, int32_t **cells
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i32(flag, pos, nL, s, h));
   int32_t bc[kMaxColors + 1];
-  for (int c = 0; c <= nc; c++)
-    QA_HIP(hipMemcpyAsync(&bc[c], pos + c * (nL / nc), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  QA_HIP(hipStreamSynchronize(s));
+  ReadBatch rb(h);
+  for (int c = 0; c <= nc; c++) QA_TRY(rb.add(&bc[c], pos + c * (nL / nc), sizeof(int32_t)));
+  QA_TRY(rb.finish());
   for (int c = 0; c <= nc; c++) first[c] = bc[c];
   *count = bc[nc];
   *cells = nullptr;
@@ -1507,8 +1543,11 @@ static amg_status level_values(amg_hierarchy *h, int l, bool fresh) {
   if (fresh) {
     QA_TRY(scan_exclusive_i32(ocnt, Q.optr, Q.n, s, h));
     int32_t on = 0;
-    QA_HIP(hipMemcpyAsync(&on, Q.optr + Q.n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
+    {
+      ReadBatch rb(h);
+      QA_TRY(rb.add(&on, Q.optr + Q.n, sizeof(int32_t)));
+      QA_TRY(rb.finish());
+    }
     Q.ovf_nnz = on;
     if (on) {
       Q.ocol = dalloc_n<int32_t>(h, on);
@@ -1532,8 +1571,9 @@ static amg_status level_values(amg_hierarchy *h, int l, bool fresh) {
     QA_LAUNCH_CHECK();
     if (fresh) {
       int sc = 0;
-      QA_HIP(hipMemcpyAsync(&sc, h->dflag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-      QA_HIP(hipStreamSynchronize(s));
+      ReadBatch rb(h);
+      QA_TRY(rb.add(&sc, h->dflag + 1, sizeof(int)));
+      QA_TRY(rb.finish());
       Q.same_color_ovf = (sc & F_SAMECOLOR) ? 1 : 0;
     }
     k_convert<double, float><<<nblk(Q.ovf_nnz), kBlock, 0, s>>>(Q.ovf_nnz, Q.oval64, Q.oval32);
@@ -1572,8 +1612,11 @@ static amg_status build_block_factors(amg_hierarchy *h) {
   QA_LAUNCH_CHECK();
   QA_TRY(scan_exclusive_i64(size, F.boff, nL, s, h));
   int64_t total = 0;
-  QA_HIP(hipMemcpyAsync(&total, F.boff + nL, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-  QA_HIP(hipStreamSynchronize(s));
+  {
+    ReadBatch rb(h);
+    QA_TRY(rb.add(&total, F.boff + nL, sizeof(int64_t)));
+    QA_TRY(rb.finish());
+  }
   F.bfac_n = total;
   F.bfac64 = dalloc_n<double>(h, std::max<int64_t>(total, 1));
   F.bfac32 = dalloc_n<float>(h, std::max<int64_t>(total, 1));
@@ -1617,8 +1660,9 @@ static amg_status build_window_entries(amg_hierarchy *h) {
   if (F.nwin) k_win_entmax<<<nblk(F.nwin), kBlock, 0, s>>>(F.nwin, F.win_q, F.win_row, F.win_ent, dmax);
   QA_LAUNCH_CHECK();
   int hmax = 0;
-  QA_HIP(hipMemcpyAsync(&hmax, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
-  QA_HIP(hipStreamSynchronize(s));
+  ReadBatch rb(h);
+  QA_TRY(rb.add(&hmax, dmax, sizeof(int)));
+  QA_TRY(rb.finish());
   F.win_ent_max = hmax;
   return AMG_OK;
 }
@@ -1640,8 +1684,9 @@ static amg_status build_big_cells(amg_hierarchy *h) {
     QA_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
     k_big_rows_max<<<nblk(F.nbig), kBlock, 0, s>>>(F.nbig, F.big_cells, F.crow, dmax);
     QA_LAUNCH_CHECK();
-    QA_HIP(hipMemcpyAsync(&F.big_max_rows, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
+    ReadBatch rb(h);
+    QA_TRY(rb.add(&F.big_max_rows, dmax, sizeof(int)));
+    QA_TRY(rb.finish());
   }
   for (int dir = 0; dir < 2; dir++) {
     if (dir == 0)
@@ -1652,8 +1697,11 @@ static amg_status build_big_cells(amg_hierarchy *h) {
     if (!F.big_lofs[dir]) return AMG_ERR_NOMEM;
     QA_TRY(scan_exclusive_i32(cnt, F.big_lofs[dir], F.nbig, s, h));
     int32_t total = 0;
-    QA_HIP(hipMemcpyAsync(&total, F.big_lofs[dir] + F.nbig, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
+    {
+      ReadBatch rb(h);
+      QA_TRY(rb.add(&total, F.big_lofs[dir] + F.nbig, sizeof(int32_t)));
+      QA_TRY(rb.finish());
+    }
     F.big_lptr[dir] = dalloc_n<int32_t>(h, total);
     F.big_sched[dir] = dalloc_n<int32_t>(h, n);
     if (!F.big_lptr[dir] || !F.big_sched[dir]) return AMG_ERR_NOMEM;
@@ -1725,9 +1773,9 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
   {
     const int nc = F.ncolor;
     int32_t cr[kMaxColors];
-    for (int c = 0; c < nc; c++)
-      QA_HIP(hipMemcpyAsync(&cr[c], F.crow + c * (nL / nc), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
+    ReadBatch rb(h);
+    for (int c = 0; c < nc; c++) QA_TRY(rb.add(&cr[c], F.crow + c * (nL / nc), sizeof(int32_t)));
+    QA_TRY(rb.finish());
     for (int c = 0; c < nc; c++) F.color_row[c] = cr[c];
     F.color_row[nc] = n;
   }
@@ -1741,8 +1789,9 @@ static amg_status build_multi_level(amg_hierarchy *h, const double *coords, cons
   QA_TRY(scan_exclusive_i32(iccnt, F.ic_ptr, n, s, h));
   {
     int32_t icn = 0;
-    QA_HIP(hipMemcpyAsync(&icn, F.ic_ptr + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
+    ReadBatch rb(h);
+    QA_TRY(rb.add(&icn, F.ic_ptr + n, sizeof(int32_t)));
+    QA_TRY(rb.finish());
     F.ic_nnz = icn;
   }
   F.ic_col = dalloc_n<int32_t>(h, F.ic_nnz);
@@ -1792,8 +1841,9 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
     QA_LAUNCH_CHECK();
     k_bbox3_final<<<1, 1, 0, s>>>(nb, part, part + 6 * nb);
     QA_LAUNCH_CHECK();
-    QA_HIP(hipMemcpyAsync(h->box, part + 6 * nb, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
+    ReadBatch rb(h);
+    QA_TRY(rb.add(h->box, part + 6 * nb, 6 * sizeof(double)));
+    QA_TRY(rb.finish());
   } else {
     const int nb = static_cast<int>(std::min<int64_t>(nblk(n), kRedBlocksMax));
     double *part = dalloc_n<double>(h, 4 * nb + 4);
@@ -1802,8 +1852,9 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
     QA_LAUNCH_CHECK();
     k_bbox_final<<<1, 1, 0, s>>>(nb, part, part + 4 * nb);
     QA_LAUNCH_CHECK();
-    QA_HIP(hipMemcpyAsync(h->box, part + 4 * nb, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
-    QA_HIP(hipStreamSynchronize(s));
+    ReadBatch rb(h);
+    QA_TRY(rb.add(h->box, part + 4 * nb, 4 * sizeof(double)));
+    QA_TRY(rb.finish());
   }
   h->nlev = depth_rule(n, h->opt.coarse_max, h->L, h->kc, h->dim);
   h->fine.n = n;
@@ -1958,7 +2009,8 @@ static amg_status setup_dim(int dim, int64_t n, const double *coords, const int6
       h->chunk_unit = chunk_unit_for(dim == 3 ? est + est / 2 : est);
   }
   h->opt.box = box;
-  amg_status st = setup_impl(h, coords, row_ptr, col_idx, vals, nnz);
+  amg_status st = borrow_pinned_scalars(&h->host_scal);  // the readbacks of setup use it first
+  if (st == AMG_OK) st = setup_impl(h, coords, row_ptr, col_idx, vals, nnz);
   h->opt.box = nullptr;
   if (st != AMG_OK) {
     (void)hipStreamSynchronize(h->stream);

@@ -3007,7 +3007,7 @@ amg_status alloc_workspaces(amg_hierarchy *h) {
   h->partials = dalloc_n<double>(h, h->partials_cap);
   if (!h->scal || !h->partials) return AMG_ERR_NOMEM;
   QA_HIP(hipMemsetAsync(h->scal, 0, sizeof(double) * (h->nlev + 1) * kScalars, h->stream));
-  QA_TRY(borrow_pinned_scalars(&h->host_scal));
+  if (!h->host_scal) QA_TRY(borrow_pinned_scalars(&h->host_scal));
   return AMG_OK;
 }
 
