@@ -1653,17 +1653,9 @@ static amg_status build_window_entries(amg_hierarchy *h) {
   if (!F.win_ent) return AMG_ERR_NOMEM;
   k_win_entries<<<nblk(F.nwin + 1), kBlock, 0, s>>>(F.nwin, F.win_q, F.win_row, h->opt.smoother ? F.boff : nullptr,
                                                      F.ic_ptr, F.win_ent);
-  BuildTmp tmax(h, sizeof(int));
-  int *dmax = tmax.as<int>();
-  if (!dmax) return AMG_ERR_NOMEM;
-  QA_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
-  if (F.nwin) k_win_entmax<<<nblk(F.nwin), kBlock, 0, s>>>(F.nwin, F.win_q, F.win_row, F.win_ent, dmax);
+  // the maximum goes to the device flags' slot 2, read back with them at the end of setup
+  if (F.nwin) k_win_entmax<<<nblk(F.nwin), kBlock, 0, s>>>(F.nwin, F.win_q, F.win_row, F.win_ent, h->dflag + 2);
   QA_LAUNCH_CHECK();
-  int hmax = 0;
-  ReadBatch rb(h);
-  QA_TRY(rb.add(&hmax, dmax, sizeof(int)));
-  QA_TRY(rb.finish());
-  F.win_ent_max = hmax;
   return AMG_OK;
 }
 
@@ -1677,17 +1669,9 @@ static amg_status build_big_cells(amg_hierarchy *h) {
   int32_t *lv = dalloc_n<int32_t>(h, n);
   int32_t *cnt = dalloc_n<int32_t>(h, F.nbig);
   if (!lv || !cnt) return AMG_ERR_NOMEM;
-  {
-    BuildTmp tmax(h, sizeof(int));
-    int *dmax = tmax.as<int>();
-    if (!dmax) return AMG_ERR_NOMEM;
-    QA_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
-    k_big_rows_max<<<nblk(F.nbig), kBlock, 0, s>>>(F.nbig, F.big_cells, F.crow, dmax);
-    QA_LAUNCH_CHECK();
-    ReadBatch rb(h);
-    QA_TRY(rb.add(&F.big_max_rows, dmax, sizeof(int)));
-    QA_TRY(rb.finish());
-  }
+  // the largest big cell goes to the device flags' slot 3, read back with them at the end of setup
+  k_big_rows_max<<<nblk(F.nbig), kBlock, 0, s>>>(F.nbig, F.big_cells, F.crow, h->dflag + 3);
+  QA_LAUNCH_CHECK();
   for (int dir = 0; dir < 2; dir++) {
     if (dir == 0)
       k_big_levels<true><<<nblk(F.nbig), kBlock, 0, s>>>(F.nbig, F.big_cells, F.crow, F.ic_ptr, F.ic_col, lv, cnt);
@@ -1827,10 +1811,10 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
                                            ub ? ub[1] : 0.0, ub ? ub[2] : 0.0, ub ? ub[3] : 0.0, h->dflag);
   }
   QA_LAUNCH_CHECK();
+  // the validation flag and the bounding box (eq. 6) come back in one read: the box kernels only read coords[0, n)
   int f = 0;
-  QA_TRY(read_flag(h, f));
-  if (f & F_INVALID) return AMG_ERR_INVALID;
-  if (f & F_NOT_SPD) return AMG_ERR_NOT_SPD;
+  ReadBatch rb(h);
+  QA_TRY(rb.add(&f, h->dflag, sizeof(int)));
   if (ub) {
     for (int t = 0; t < nbox; t++) h->box[t] = ub[t];
   } else if (h->dim == 3) {
@@ -1841,9 +1825,7 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
     QA_LAUNCH_CHECK();
     k_bbox3_final<<<1, 1, 0, s>>>(nb, part, part + 6 * nb);
     QA_LAUNCH_CHECK();
-    ReadBatch rb(h);
     QA_TRY(rb.add(h->box, part + 6 * nb, 6 * sizeof(double)));
-    QA_TRY(rb.finish());
   } else {
     const int nb = static_cast<int>(std::min<int64_t>(nblk(n), kRedBlocksMax));
     double *part = dalloc_n<double>(h, 4 * nb + 4);
@@ -1852,10 +1834,11 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
     QA_LAUNCH_CHECK();
     k_bbox_final<<<1, 1, 0, s>>>(nb, part, part + 4 * nb);
     QA_LAUNCH_CHECK();
-    ReadBatch rb(h);
     QA_TRY(rb.add(h->box, part + 4 * nb, 4 * sizeof(double)));
-    QA_TRY(rb.finish());
   }
+  QA_TRY(rb.finish());
+  if (f & F_INVALID) return AMG_ERR_INVALID;
+  if (f & F_NOT_SPD) return AMG_ERR_NOT_SPD;
   h->nlev = depth_rule(n, h->opt.coarse_max, h->L, h->kc, h->dim);
   h->fine.n = n;
   h->fine.ncolor = 1 << h->dim;
@@ -1866,7 +1849,14 @@ static amg_status setup_impl(amg_hierarchy *h, const double *coords, const int64
   } else {
     QA_TRY(build_multi_level(h, coords, row_ptr, col_idx, vals, nnz));
   }
-  QA_TRY(read_flag(h, f));
+  {
+    int fl[4] = {0, 0, 0, 0};  // error flags; [2], [3]: the largest staged window's cell data, the largest big cell
+    QA_TRY(rb.add(fl, h->dflag, sizeof(fl)));
+    QA_TRY(rb.finish());
+    f = fl[0];
+    h->fine.win_ent_max = fl[2];
+    h->fine.big_max_rows = fl[3];
+  }
   if (f & F_NOT_SPD) return AMG_ERR_NOT_SPD;
   QA_TRY(alloc_workspaces(h));
   QA_TRY(build_mhat(h));
