@@ -1163,6 +1163,31 @@ __global__ void __launch_bounds__(kBlock) k_cgs3(QView<T> Q, const T *__restrict
   else x[q] += dl;
 }
 
+// One sweep of the eight color phases of a small octree level in one workgroup: each row's arithmetic is
+// k_cgs3's (and k_add_range's where cells of a color are coupled), the phases in the same order, with a barrier where
+// the launches ended, so the result is theirs bit for bit at one launch instead of eight (or sixteen).
+constexpr int kOctSweepThreads = 1024;
+constexpr int64_t kOctSweepMax = 8 * 2048;  // levels of at most this many cells sweep in one workgroup
+template <class T, bool FWD>
+__global__ void __launch_bounds__(kOctSweepThreads) k_cgs3_sweep(QView<T> Q, const T *__restrict__ f, T *x,
+                                                                  T *delta) {
+  const int64_t n8 = Q.n >> 3;
+  for (int cc = 0; cc < 8; cc++) {
+    const int c = FWD ? cc : 7 - cc;
+    for (int64_t j = threadIdx.x; j < n8; j += kOctSweepThreads) {
+      const uint32_t q = static_cast<uint32_t>(c * n8 + j);
+      const T dl = (f[q] - row_apply3(Q, q, x)) / Q.ax[q];
+      if (delta) delta[q] = dl;
+      else x[q] += dl;
+    }
+    if (delta) {
+      __syncthreads();
+      for (int64_t j = threadIdx.x; j < n8; j += kOctSweepThreads) x[c * n8 + j] += delta[c * n8 + j];
+    }
+    __syncthreads();
+  }
+}
+
 // residual of the eight children of coarse cell M, summed in child3_order (Section 4.3's restriction order on each
 // layer), into the parent's color-major slot
 template <class T>
@@ -2888,7 +2913,7 @@ static void btilde(amg_hierarchy *h, int l, const T *g, T *e, bool defer_update2
 }
 
 // Octree levels (per-step launches): one color phase, B^ (Algorithm 2.2) and B~ (Algorithm 2.1 with n = inner
-// iterations), with the same readings as the quadtree levels and no step fusions.
+// iterations), with the same readings as the quadtree levels; a small level's sweep is one launch (k_cgs3_sweep).
 template <class T>
 static void gs_phase_oct(amg_hierarchy *h, int l, const T *f, T *u, int c) {
   const QuadLevel &Q = h->lev[l];
@@ -2909,8 +2934,13 @@ static void bhat_oct(amg_hierarchy *h, int l, const T *f, T *u) {
   const QuadLevel &Q = h->lev[l];
   hipStream_t s = h->stream;
   k_fill<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, u, T(0));
-  for (int sw = 0; sw < h->opt.sweeps; sw++)
-    for (int c = 0; c < 8; c++) gs_phase_oct<T>(h, l, f, u, c);
+  const bool small = Q.n <= kOctSweepMax;
+  T *dl = Q.same_color_ovf ? P<T>::W(h)[l].d : nullptr;
+  for (int sw = 0; sw < h->opt.sweeps; sw++) {
+    if (small) k_cgs3_sweep<T, true><<<1, kOctSweepThreads, 0, s>>>(qview<T>(Q), f, u, dl);
+    else
+      for (int c = 0; c < 8; c++) gs_phase_oct<T>(h, l, f, u, c);
+  }
   LevelWork<T> &wc = P<T>::W(h)[l + 1];
   k_cres_restrict3<T><<<nblk(Q.n >> 3), kBlock, 0, s>>>(qview<T>(Q), f, u, wc.g);
   if (l + 1 == h->nlev - 1)
@@ -2918,8 +2948,11 @@ static void bhat_oct(amg_hierarchy *h, int l, const T *f, T *u) {
   else
     btilde_oct<T>(h, l + 1, wc.g, wc.e);
   k_cprolong3<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, wc.e, u);
-  for (int sw = 0; sw < h->opt.sweeps; sw++)
-    for (int c = 7; c >= 0; c--) gs_phase_oct<T>(h, l, f, u, c);
+  for (int sw = 0; sw < h->opt.sweeps; sw++) {
+    if (small) k_cgs3_sweep<T, false><<<1, kOctSweepThreads, 0, s>>>(qview<T>(Q), f, u, dl);
+    else
+      for (int c = 7; c >= 0; c--) gs_phase_oct<T>(h, l, f, u, c);
+  }
 }
 
 template <class T>
