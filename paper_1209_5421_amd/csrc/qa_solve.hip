@@ -1163,14 +1163,13 @@ __global__ void __launch_bounds__(kBlock) k_cgs3(QView<T> Q, const T *__restrict
   else x[q] += dl;
 }
 
-// One sweep of the eight color phases of a small octree level in one workgroup: each row's arithmetic is
+// One sweep of the eight color phases of a small octree level inside one workgroup: each row's arithmetic is
 // k_cgs3's (and k_add_range's where cells of a color are coupled), the phases in the same order, with a barrier where
-// the launches ended, so the result is theirs bit for bit at one launch instead of eight (or sixteen).
+// the launches ended, so the result is theirs bit for bit.
 constexpr int kOctSweepThreads = 1024;
 constexpr int64_t kOctSweepMax = 8 * 2048;  // levels of at most this many cells sweep in one workgroup
 template <class T, bool FWD>
-__global__ void __launch_bounds__(kOctSweepThreads) k_cgs3_sweep(QView<T> Q, const T *__restrict__ f, T *x,
-                                                                  T *delta) {
+__device__ inline void oct_sweep(const QView<T> &Q, const T *__restrict__ f, T *x, T *delta) {
   const int64_t n8 = Q.n >> 3;
   for (int cc = 0; cc < 8; cc++) {
     const int c = FWD ? cc : 7 - cc;
@@ -1186,6 +1185,52 @@ __global__ void __launch_bounds__(kOctSweepThreads) k_cgs3_sweep(QView<T> Q, con
     }
     __syncthreads();
   }
+}
+
+// the residual of coarse cell M's eight children, summed in child3_order (Section 4.3's restriction order on each
+// layer), into the parent's color-major slot (k_cres_restrict3's row)
+template <class T>
+__device__ inline void oct_restrict(const QView<T> &Q, const T *__restrict__ f, const T *u, T *gc, int64_t M) {
+  const int64_t n8 = Q.n >> 3;
+  T acc = 0;
+  for (int o = 0; o < 8; o++) {
+    const uint32_t q = static_cast<uint32_t>(child3_order(o) * n8 + M);
+    acc += f[q] - row_apply3(Q, q, u);
+  }
+  gc[q_of_m3(static_cast<uint32_t>(M), Q.k - 1)] = acc;
+}
+
+// B^ of a small octree level (Algorithm 2.2) in one workgroup, its steps those of the per-step launches in their
+// order with a barrier for each launch boundary: u = 0; `sweeps` forward sweeps; the restricted residual into gc;
+// then, when the next level is the coarsest (whole), e_c = A_c^{-1} g_c with k_dense_solve's sums, u += P e_c and the
+// backward sweeps. Without whole the kernel ends after the restriction (pre) or starts at the prolongation (post),
+// and the next level's B~ runs between the two.
+template <class T, int PART>  // PART 0: whole, 1: pre, 2: post
+__global__ void __launch_bounds__(kOctSweepThreads) k_bhat3_small(QView<T> Q, const T *__restrict__ f, T *u, T *dl,
+                                                                   T *gc, T *ec, const double *__restrict__ ainv,
+                                                                   int nc, int sweeps) {
+  __shared__ double sg[1024];
+  const int64_t n = Q.n, n8 = n >> 3;
+  const int tid = static_cast<int>(threadIdx.x);
+  if (PART != 2) {
+    for (int64_t q = tid; q < n; q += kOctSweepThreads) u[q] = T(0);
+    __syncthreads();
+    for (int sw = 0; sw < sweeps; sw++) oct_sweep<T, true>(Q, f, u, dl);
+    for (int64_t M = tid; M < n8; M += kOctSweepThreads) oct_restrict<T>(Q, f, u, gc, M);
+    if (PART == 1) return;
+    __syncthreads();
+    for (int i = tid; i < nc; i += kOctSweepThreads) sg[i] = static_cast<double>(gc[i]);
+    __syncthreads();
+    for (int i = tid; i < nc; i += kOctSweepThreads) {
+      double acc = 0.0;
+      for (int j = 0; j < nc; j++) acc += ainv[static_cast<size_t>(i) * nc + j] * sg[j];
+      ec[i] = static_cast<T>(acc);
+    }
+    __syncthreads();
+  }
+  for (int64_t q = tid; q < n; q += kOctSweepThreads) u[q] += ec[q_of_m3(static_cast<uint32_t>(q & (n8 - 1)), Q.k - 1)];
+  __syncthreads();
+  for (int sw = 0; sw < sweeps; sw++) oct_sweep<T, false>(Q, f, u, dl);
 }
 
 // residual of the eight children of coarse cell M, summed in child3_order (Section 4.3's restriction order on each
@@ -2913,7 +2958,8 @@ static void btilde(amg_hierarchy *h, int l, const T *g, T *e, bool defer_update2
 }
 
 // Octree levels (per-step launches): one color phase, B^ (Algorithm 2.2) and B~ (Algorithm 2.1 with n = inner
-// iterations), with the same readings as the quadtree levels; a small level's sweep is one launch (k_cgs3_sweep).
+// iterations), with the same readings as the quadtree levels; a small level's B^ runs in one workgroup
+// (k_bhat3_small).
 template <class T>
 static void gs_phase_oct(amg_hierarchy *h, int l, const T *f, T *u, int c) {
   const QuadLevel &Q = h->lev[l];
@@ -2933,26 +2979,32 @@ template <class T>
 static void bhat_oct(amg_hierarchy *h, int l, const T *f, T *u) {
   const QuadLevel &Q = h->lev[l];
   hipStream_t s = h->stream;
-  k_fill<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, u, T(0));
   const bool small = Q.n <= kOctSweepMax;
   T *dl = Q.same_color_ovf ? P<T>::W(h)[l].d : nullptr;
-  for (int sw = 0; sw < h->opt.sweeps; sw++) {
-    if (small) k_cgs3_sweep<T, true><<<1, kOctSweepThreads, 0, s>>>(qview<T>(Q), f, u, dl);
-    else
-      for (int c = 0; c < 8; c++) gs_phase_oct<T>(h, l, f, u, c);
-  }
   LevelWork<T> &wc = P<T>::W(h)[l + 1];
+  if (small) {  // B^ in one workgroup: whole when the next level is the coarsest, else around its B~
+    const bool whole = l + 1 == h->nlev - 1;
+    const int nc = whole ? static_cast<int>(h->nc) : 0, sw = h->opt.sweeps;
+    if (whole) {
+      k_bhat3_small<T, 0><<<1, kOctSweepThreads, 0, s>>>(qview<T>(Q), f, u, dl, wc.g, wc.e, h->ainv, nc, sw);
+    } else {
+      k_bhat3_small<T, 1><<<1, kOctSweepThreads, 0, s>>>(qview<T>(Q), f, u, dl, wc.g, wc.e, nullptr, 0, sw);
+      btilde_oct<T>(h, l + 1, wc.g, wc.e);
+      k_bhat3_small<T, 2><<<1, kOctSweepThreads, 0, s>>>(qview<T>(Q), f, u, dl, wc.g, wc.e, nullptr, 0, sw);
+    }
+    return;
+  }
+  k_fill<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.n, u, T(0));
+  for (int sw = 0; sw < h->opt.sweeps; sw++)
+    for (int c = 0; c < 8; c++) gs_phase_oct<T>(h, l, f, u, c);
   k_cres_restrict3<T><<<nblk(Q.n >> 3), kBlock, 0, s>>>(qview<T>(Q), f, u, wc.g);
   if (l + 1 == h->nlev - 1)
     k_dense_solve<T><<<1, kBlock, 0, s>>>(static_cast<int>(h->nc), h->ainv, wc.g, wc.e);
   else
     btilde_oct<T>(h, l + 1, wc.g, wc.e);
   k_cprolong3<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, wc.e, u);
-  for (int sw = 0; sw < h->opt.sweeps; sw++) {
-    if (small) k_cgs3_sweep<T, false><<<1, kOctSweepThreads, 0, s>>>(qview<T>(Q), f, u, dl);
-    else
-      for (int c = 7; c >= 0; c--) gs_phase_oct<T>(h, l, f, u, c);
-  }
+  for (int sw = 0; sw < h->opt.sweeps; sw++)
+    for (int c = 7; c >= 0; c--) gs_phase_oct<T>(h, l, f, u, c);
 }
 
 template <class T>
