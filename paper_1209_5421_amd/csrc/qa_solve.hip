@@ -1168,14 +1168,14 @@ __global__ void __launch_bounds__(kBlock) k_cgs3(QView<T> Q, const T *__restrict
 // the launches ended, so the result is theirs bit for bit.
 constexpr int kOctSweepThreads = 1024;
 constexpr int64_t kOctSweepMax = 8 * 2048;  // levels of at most this many cells sweep in one workgroup
-template <class T, bool FWD>
-__device__ inline void oct_sweep(const QView<T> &Q, const T *__restrict__ f, T *x, T *delta) {
+template <class T, bool FWD, class Apply>
+__device__ inline void oct_sweep(const QView<T> &Q, const T *__restrict__ f, T *x, T *delta, Apply apply) {
   const int64_t n8 = Q.n >> 3;
   for (int cc = 0; cc < 8; cc++) {
     const int c = FWD ? cc : 7 - cc;
     for (int64_t j = threadIdx.x; j < n8; j += kOctSweepThreads) {
       const uint32_t q = static_cast<uint32_t>(c * n8 + j);
-      const T dl = (f[q] - row_apply3(Q, q, x)) / Q.ax[q];
+      const T dl = (f[q] - apply(q, x)) / Q.ax[q];
       if (delta) delta[q] = dl;
       else x[q] += dl;
     }
@@ -1189,13 +1189,14 @@ __device__ inline void oct_sweep(const QView<T> &Q, const T *__restrict__ f, T *
 
 // the residual of coarse cell M's eight children, summed in child3_order (Section 4.3's restriction order on each
 // layer), into the parent's color-major slot (k_cres_restrict3's row)
-template <class T>
-__device__ inline void oct_restrict(const QView<T> &Q, const T *__restrict__ f, const T *u, T *gc, int64_t M) {
+template <class T, class Apply>
+__device__ inline void oct_restrict(const QView<T> &Q, const T *__restrict__ f, const T *u, T *gc, int64_t M,
+                                    Apply apply) {
   const int64_t n8 = Q.n >> 3;
   T acc = 0;
   for (int o = 0; o < 8; o++) {
     const uint32_t q = static_cast<uint32_t>(child3_order(o) * n8 + M);
-    acc += f[q] - row_apply3(Q, q, u);
+    acc += f[q] - apply(q, u);
   }
   gc[q_of_m3(static_cast<uint32_t>(M), Q.k - 1)] = acc;
 }
@@ -1212,11 +1213,12 @@ __global__ void __launch_bounds__(kOctSweepThreads) k_bhat3_small(QView<T> Q, co
   __shared__ double sg[1024];
   const int64_t n = Q.n, n8 = n >> 3;
   const int tid = static_cast<int>(threadIdx.x);
+  auto ap = [&Q](uint32_t q, const T *x) { return row_apply3(Q, q, x); };
   if (PART != 2) {
     for (int64_t q = tid; q < n; q += kOctSweepThreads) u[q] = T(0);
     __syncthreads();
-    for (int sw = 0; sw < sweeps; sw++) oct_sweep<T, true>(Q, f, u, dl);
-    for (int64_t M = tid; M < n8; M += kOctSweepThreads) oct_restrict<T>(Q, f, u, gc, M);
+    for (int sw = 0; sw < sweeps; sw++) oct_sweep<T, true>(Q, f, u, dl, ap);
+    for (int64_t M = tid; M < n8; M += kOctSweepThreads) oct_restrict<T>(Q, f, u, gc, M, ap);
     if (PART == 1) return;
     __syncthreads();
     for (int i = tid; i < nc; i += kOctSweepThreads) sg[i] = static_cast<double>(gc[i]);
@@ -1230,7 +1232,7 @@ __global__ void __launch_bounds__(kOctSweepThreads) k_bhat3_small(QView<T> Q, co
   }
   for (int64_t q = tid; q < n; q += kOctSweepThreads) u[q] += ec[q_of_m3(static_cast<uint32_t>(q & (n8 - 1)), Q.k - 1)];
   __syncthreads();
-  for (int sw = 0; sw < sweeps; sw++) oct_sweep<T, false>(Q, f, u, dl);
+  for (int sw = 0; sw < sweeps; sw++) oct_sweep<T, false>(Q, f, u, dl, ap);
 }
 
 // residual of the eight children of coarse cell M, summed in child3_order (Section 4.3's restriction order on each
@@ -1247,6 +1249,92 @@ __global__ void __launch_bounds__(kBlock) k_cres_restrict3(QView<T> Q, const T *
     acc += f[q] - row_apply3(Q, q, u);
   }
   gc[q_of_m3(static_cast<uint32_t>(M), Q.k - 1)] = acc;
+}
+
+// The whole B^ of k_bhat3_small (PART 0) with the level's operator, u, f, the coarse vectors and a table of each row's
+// 27 neighbours in LDS, made once: every step's gathers and operator values then come from LDS instead of L2, and
+// no step recomputes the 3D neighbour rule (the overflow lists stay in global memory). The same steps, arithmetic and
+// order as k_bhat3_small, so the same results bit for bit; u goes back to global memory at the end.
+template <class T>
+__global__ void __launch_bounds__(kOctSweepThreads) k_bhat3_lds(QView<T> Q, const T *__restrict__ f, T *u,
+                                                                 const double *__restrict__ ainv, int nc, int sweeps,
+                                                                 int use_delta) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t n = Q.n, n8 = n >> 3;
+  const int tid = static_cast<int>(threadIdx.x);
+  double *s_g = reinterpret_cast<double *>(smem);  // nc
+  T *s_ax = reinterpret_cast<T *>(s_g + nc);       // 27 n
+  T *s_u = s_ax + 27 * n, *s_f = s_u + n, *s_dl = s_f + n, *s_gt = s_dl + n, *s_e = s_gt + nc;
+  uint16_t *s_nb = reinterpret_cast<uint16_t *>(s_e + nc);  // 27 n: row q's neighbour in slot s (q itself outside)
+  for (int64_t i = tid; i < 27 * n; i += kOctSweepThreads) s_ax[i] = Q.ax[i];
+  for (int64_t i = tid; i < n; i += kOctSweepThreads) {
+    s_f[i] = f[i];
+    s_u[i] = T(0);
+    // the neighbour rule of row_apply3_f, once per row instead of once per row and step
+    const uint32_t q = static_cast<uint32_t>(i), m = m_of_q3(q, Q.k);
+    const int t1 = static_cast<int>(compact3(m)), t2 = static_cast<int>(compact3(m >> 1)),
+              t3 = static_cast<int>(compact3(m >> 2));
+    const int side = 1 << Q.k;
+    for (int s = 0; s < 27; s++) {
+      const int u1 = t1 + slot3_dx(s), u2 = t2 + slot3_dy(s), u3 = t3 + slot3_dz(s);
+      const bool in = u1 >= 0 && u2 >= 0 && u3 >= 0 && u1 < side && u2 < side && u3 < side;
+      s_nb[s * n + i] = static_cast<uint16_t>(
+          in ? q_of_m3(morton3(static_cast<uint32_t>(u1), static_cast<uint32_t>(u2), static_cast<uint32_t>(u3)), Q.k)
+             : q);
+    }
+  }
+  __syncthreads();
+  QView<T> QL = Q;
+  QL.ax = s_ax;
+  // row_apply3's sum (slots 0..26, then the overflow entries) with the neighbours from the table
+  auto ap = [&](uint32_t q, const T *x) {
+    T acc = 0;
+    for (int s = 0; s < 27; s++) acc += s_ax[s * n + q] * x[s_nb[s * n + q]];
+    if (Q.optr)
+      for (int32_t e = Q.optr[q]; e < Q.optr[q + 1]; e++) acc += Q.oval[e] * x[static_cast<uint32_t>(Q.ocol[e])];
+    return acc;
+  };
+  for (int sw = 0; sw < sweeps; sw++) oct_sweep<T, true>(QL, s_f, s_u, use_delta ? s_dl : nullptr, ap);
+  for (int64_t M = tid; M < n8; M += kOctSweepThreads) oct_restrict<T>(QL, s_f, s_u, s_gt, M, ap);
+  __syncthreads();
+  for (int i = tid; i < nc; i += kOctSweepThreads) s_g[i] = static_cast<double>(s_gt[i]);
+  __syncthreads();
+  for (int i = tid; i < nc; i += kOctSweepThreads) {
+    double acc = 0.0;
+    for (int j = 0; j < nc; j++) acc += ainv[static_cast<size_t>(i) * nc + j] * s_g[j];
+    s_e[i] = static_cast<T>(acc);
+  }
+  __syncthreads();
+  for (int64_t q = tid; q < n; q += kOctSweepThreads)
+    s_u[q] += s_e[q_of_m3(static_cast<uint32_t>(q & (n8 - 1)), Q.k - 1)];
+  __syncthreads();
+  for (int sw = 0; sw < sweeps; sw++) oct_sweep<T, false>(QL, s_f, s_u, use_delta ? s_dl : nullptr, ap);
+  for (int64_t q = tid; q < n; q += kOctSweepThreads) u[q] = s_u[q];
+}
+
+template <class T>
+static size_t bhat3_lds_bytes(int64_t n, int nc) {
+  if (n > 65536) return SIZE_MAX;  // the neighbour table holds 16-bit rows
+  return sizeof(double) * static_cast<size_t>(nc) + sizeof(T) * static_cast<size_t>(30 * n + 2 * nc) +
+         sizeof(uint16_t) * static_cast<size_t>(27 * n);
+}
+
+// the LDS a launch of k_bhat3_lds may take on this device (set once per device: above 64 KB it must be asked for)
+static int bhat3_lds_limit(int device) {
+  static std::once_flag once[64];
+  static int limit[64] = {};
+  if (device < 0 || device >= 64) return 0;
+  std::call_once(once[device], [&]() {
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) return;
+    if (hipFuncSetAttribute(reinterpret_cast<const void *>(k_bhat3_lds<float>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess ||
+        hipFuncSetAttribute(reinterpret_cast<const void *>(k_bhat3_lds<double>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, lds) != hipSuccess)
+      return;
+    limit[device] = lds;
+  });
+  return limit[device];
 }
 
 // u += P e_c: row q = c 8^(k-1) + M takes its parent's value
@@ -2985,7 +3073,10 @@ static void bhat_oct(amg_hierarchy *h, int l, const T *f, T *u) {
   if (small) {  // B^ in one workgroup: whole when the next level is the coarsest, else around its B~
     const bool whole = l + 1 == h->nlev - 1;
     const int nc = whole ? static_cast<int>(h->nc) : 0, sw = h->opt.sweeps;
-    if (whole) {
+    const size_t lds = bhat3_lds_bytes<T>(Q.n, nc);
+    if (whole && lds <= static_cast<size_t>(bhat3_lds_limit(h->device))) {
+      k_bhat3_lds<T><<<1, kOctSweepThreads, lds, s>>>(qview<T>(Q), f, u, h->ainv, nc, sw, dl ? 1 : 0);
+    } else if (whole) {
       k_bhat3_small<T, 0><<<1, kOctSweepThreads, 0, s>>>(qview<T>(Q), f, u, dl, wc.g, wc.e, h->ainv, nc, sw);
     } else {
       k_bhat3_small<T, 1><<<1, kOctSweepThreads, 0, s>>>(qview<T>(Q), f, u, dl, wc.g, wc.e, nullptr, 0, sw);
