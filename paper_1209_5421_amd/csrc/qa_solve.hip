@@ -1046,6 +1046,146 @@ __global__ void __launch_bounds__(kBlock) k_cgs_post(QView<T> Q, const T *__rest
   if constexpr (BETA) reduce_finish<1>(v, R);
 }
 
+// The whole first post-smoothing sweep (color phases 3, 2, 1, 0, each with the prolongation folded in as in
+// k_cgs_post) of a level without same-color couplings or overflow entries, in one launch. Workgroup b owns the
+// 16 x 16 super-cells j in [256 b, 256 b + 256), a Morton-aligned square, and stages u + P e_c over the square and
+// four rings of super-cells around it in LDS. Phase C relaxes the color-C rows of the square and of its C innermost
+// rings: a stencil reaches one super-cell further, so every row a later phase of the square reads is relaxed here
+// (the ring rows again in the neighbouring workgroups, from the same values). Each row takes the values, slot
+// order and arithmetic of k_cgs_post, so the square's rows are the four launches' bit for bit; with BETA the
+// square's thread j forms (p1, q0) over rows j + c n/4 as k_cgs_post<T, 0, true> does, with the same partials.
+constexpr int kPostTile = 16;                         // super-cells per side of a workgroup's square
+constexpr int kPostRing = 4;                          // rings staged around it
+constexpr int kPostSide = kPostTile + 2 * kPostRing;  // 24
+static_assert(kPostTile * kPostTile == kBlock, "one super-cell of the square per thread");
+
+template <int C>
+struct PostRows {  // row slots per thread of phase C: (16 + 2C)^2 rows over kBlock threads
+  static constexpr int side = kPostTile + 2 * C;
+  static constexpr int count = side * side;
+  static constexpr int slots = (count + kBlock - 1) / kBlock;
+};
+
+template <class T, int C>
+struct PostRowData {
+  T a[PostRows<C>::slots][9];
+  T f[PostRows<C>::slots];
+  int l[PostRows<C>::slots];  // staged index of the row's super-cell, -1 when the slot has no row
+};
+
+// local super-cell (lx, ly) of the staged square of phase C's slot i (row-major over the phase's region; for C = 0
+// the Morton order of the square, so thread t holds super-cell 256 b + t)
+template <int C>
+__device__ inline void post_slot_xy(int i, int &lx, int &ly) {
+  const int r = static_cast<int>(threadIdx.x) + i * kBlock;
+  if constexpr (C == 0) {
+    lx = static_cast<int>(compact_bits(static_cast<uint32_t>(r))) + kPostRing;
+    ly = static_cast<int>(compact_bits(static_cast<uint32_t>(r) >> 1)) + kPostRing;
+  } else {
+    lx = r % PostRows<C>::side + (kPostRing - C);
+    ly = r / PostRows<C>::side + (kPostRing - C);
+  }
+}
+
+template <class T, int C>
+__device__ inline void post_load(const QView<T> &Q, const T *__restrict__ f, int px0, int py0, int np, uint32_t n4,
+                                 PostRowData<T, C> &D) {
+#pragma unroll
+  for (int i = 0; i < PostRows<C>::slots; i++) {
+    int lx, ly;
+    post_slot_xy<C>(i, lx, ly);
+    const int r = static_cast<int>(threadIdx.x) + i * kBlock;
+    const int px = px0 + lx, py = py0 + ly;
+    const bool ok = r < PostRows<C>::count && px >= 0 && px < np && py >= 0 && py < np;
+    D.l[i] = ok ? ly * kPostSide + lx : -1;
+    if (ok) {
+      const uint32_t q = static_cast<uint32_t>(C) * n4 + morton(static_cast<uint32_t>(px), static_cast<uint32_t>(py));
+#pragma unroll
+      for (int s = 0; s < 9; s++) D.a[i][s] = Q.ax[s * Q.n + q];
+      D.f[i] = f[q];
+    }
+  }
+}
+
+template <class T, int C>
+__device__ inline void post_phase(const PostRowData<T, C> &D, int px0, int py0, int np, T (*sv)[kPostSide * kPostSide],
+                                  T *xr0) {
+  constexpr int cx = C & 1, cy = C >> 1;
+#pragma unroll
+  for (int i = 0; i < PostRows<C>::slots; i++) {
+    const int l = D.l[i];
+    if (l < 0) continue;
+    const int lx = l % kPostSide, ly = l / kPostSide;
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < 9; s++) {
+      const int ux = cx + slot_dx(s), uy = cy + slot_dy(s);
+      const int cn = (ux & 1) | ((uy & 1) << 1);
+      const int nx = lx + (ux >> 1), ny = ly + (uy >> 1);
+      const int gx = px0 + nx, gy = py0 + ny;
+      const bool in = gx >= 0 && gx < np && gy >= 0 && gy < np;
+      // outside the grid the slot holds 0: its product is taken with the row's own value, as k_cgs_post does
+      acc += D.a[i][s] * (in ? sv[cn][ny * kPostSide + nx] : sv[C][l]);
+    }
+    const T xq = sv[C][l];
+    const T xr = xq + (D.f[i] - acc) / D.a[i][0];
+    sv[C][l] = xr;
+    if constexpr (C == 0) xr0[i] = xr;
+  }
+}
+
+template <class T, bool BETA>
+__global__ void __launch_bounds__(kBlock) k_cgs_post4(QView<T> Q, const T *__restrict__ f, T *__restrict__ x,
+                                                      const T *__restrict__ ec, Pending<T> pend,
+                                                      const T *__restrict__ q0, Red R) {
+  __shared__ T sv[4][kPostSide * kPostSide];
+  const int kc = Q.k - 1;
+  const int np = 1 << kc;
+  const uint32_t n4 = static_cast<uint32_t>(Q.n >> 2);
+  const uint32_t j0 = blockIdx.x * static_cast<uint32_t>(kBlock);
+  const int px0 = static_cast<int>(compact_bits(j0)) - kPostRing;
+  const int py0 = static_cast<int>(compact_bits(j0 >> 1)) - kPostRing;
+  // stage u + P e_c (each value as k_cgs_post forms it) over the square and its rings
+  for (int l = static_cast<int>(threadIdx.x); l < kPostSide * kPostSide; l += kBlock) {
+    const int px = px0 + l % kPostSide, py = py0 + l / kPostSide;
+    if (px < 0 || px >= np || py < 0 || py >= np) continue;
+    const uint32_t jm = morton(static_cast<uint32_t>(px), static_cast<uint32_t>(py));
+    const T em = pend.apply(ec, q_of_m(jm, kc));
+#pragma unroll
+    for (int c = 0; c < 4; c++) sv[c][l] = x[c * n4 + jm] + em;
+  }
+  PostRowData<T, 3> D3;
+  PostRowData<T, 2> D2;
+  PostRowData<T, 1> D1;
+  PostRowData<T, 0> D0;
+  post_load<T, 3>(Q, f, px0, py0, np, n4, D3);
+  post_load<T, 2>(Q, f, px0, py0, np, n4, D2);
+  post_load<T, 1>(Q, f, px0, py0, np, n4, D1);
+  post_load<T, 0>(Q, f, px0, py0, np, n4, D0);
+  T xr0[1];
+  __syncthreads();
+  post_phase<T, 3>(D3, px0, py0, np, sv, xr0);
+  __syncthreads();
+  post_phase<T, 2>(D2, px0, py0, np, sv, xr0);
+  __syncthreads();
+  post_phase<T, 1>(D1, px0, py0, np, sv, xr0);
+  __syncthreads();
+  post_phase<T, 0>(D0, px0, py0, np, sv, xr0);
+  __syncthreads();
+  // the square's rows of the four colors; thread t holds super-cell j0 + t
+  const uint32_t j = j0 + threadIdx.x;
+  const int lj = D0.l[0];
+  double v[1] = {0.0};
+#pragma unroll
+  for (int c = 0; c < 4; c++) x[c * n4 + j] = sv[c][lj];
+  if constexpr (BETA) {
+    v[0] = static_cast<double>(xr0[0]) * static_cast<double>(q0[j]);
+#pragma unroll
+    for (int c = 1; c < 4; c++) v[0] += static_cast<double>(sv[c][lj]) * static_cast<double>(q0[c * n4 + j]);
+    reduce_finish<1>(v, R);
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_add_range(int64_t begin, int64_t count, const T *__restrict__ delta,
                                                        T *__restrict__ x) {
@@ -2877,7 +3017,20 @@ static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u, const Upd1<T>
   if (!fold_prolong) k_cprolong<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, wc.e, pend, u);
   const int64_t n4 = Q.n >> 2;
   const Red rb = red(h, l, EPI_BETA);
-  for (int sw = 0; sw < sweeps; sw++)
+  // the first post-smoothing sweep in one launch (tiles of 16 x 16 super-cells; the per-step path keeps one launch
+  // per color)
+  const bool tiled = fold_prolong && h->use_engine != 0 && Q.ovf_nnz == 0 && n4 >= kBlock;
+  if (tiled) {
+    const QView<T> V = qview<T>(Q);
+    const unsigned grid = static_cast<unsigned>(n4 / kBlock);
+    if (beta_q0 && sweeps == 1) {
+      k_cgs_post4<T, true><<<grid, kBlock, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb);
+      finish<1>(h, nblk(n4), rb);
+    } else {
+      k_cgs_post4<T, false><<<grid, kBlock, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb);
+    }
+  }
+  for (int sw = tiled ? 1 : 0; sw < sweeps; sw++)
     for (int c = 3; c >= 0; c--) {
       const bool beta_here = beta_q0 && sw == sweeps - 1 && c == 0;
       if (fold_prolong && sw == 0) {
