@@ -1046,143 +1046,227 @@ __global__ void __launch_bounds__(kBlock) k_cgs_post(QView<T> Q, const T *__rest
   if constexpr (BETA) reduce_finish<1>(v, R);
 }
 
-// The whole first post-smoothing sweep (color phases 3, 2, 1, 0, each with the prolongation folded in as in
-// k_cgs_post) of a level without same-color couplings or overflow entries, in one launch. Workgroup b owns the
-// 16 x 16 super-cells j in [256 b, 256 b + 256), a Morton-aligned square, and stages u + P e_c over the square and
-// four rings of super-cells around it in LDS. Phase C relaxes the color-C rows of the square and of its C innermost
-// rings: a stencil reaches one super-cell further, so every row a later phase of the square reads is relaxed here
-// (the ring rows again in the neighbouring workgroups, from the same values). Each row takes the values, slot
-// order and arithmetic of k_cgs_post, so the square's rows are the four launches' bit for bit; with BETA the
-// square's thread j forms (p1, q0) over rows j + c n/4 as k_cgs_post<T, 0, true> does, with the same partials.
-constexpr int kPostTile = 16;                         // super-cells per side of a workgroup's square
-constexpr int kPostRing = 4;                          // rings staged around it
-constexpr int kPostSide = kPostTile + 2 * kPostRing;  // 24
-static_assert(kPostTile * kPostTile == kBlock, "one super-cell of the square per thread");
+// Tiles of the per-step path. Workgroup b owns the 16 x 16 super-cells j in [256 b, 256 b + 256), a Morton-aligned
+// square, and stages the values of the square and four rings of super-cells around it in LDS. A stencil reaches one
+// super-cell further, so a chain of color phases runs on shrinking rings: each phase relaxes the rows that the later
+// phases of the square's rows read (ring rows again in the neighbouring workgroups, from the same values). Each row
+// takes the values, slot order and arithmetic of the one-launch-per-phase kernels, so the square's rows equal
+// theirs bit for bit.
+constexpr int kTileSide = 16;                          // super-cells per side of a workgroup's square
+constexpr int kTileRings = 4;                          // rings staged around it
+constexpr int kTileStage = kTileSide + 2 * kTileRings;  // 24
+static_assert(kTileSide * kTileSide == kBlock, "one super-cell of the square per thread");
 
-template <int C>
-struct PostRows {  // row slots per thread of phase C: (16 + 2C)^2 rows over kBlock threads
-  static constexpr int side = kPostTile + 2 * C;
+template <int RG>
+struct RingRows {  // row slots per thread of a phase over the square and its RG innermost rings
+  static constexpr int side = kTileSide + 2 * RG;
   static constexpr int count = side * side;
   static constexpr int slots = (count + kBlock - 1) / kBlock;
 };
 
-template <class T, int C>
-struct PostRowData {
-  T a[PostRows<C>::slots][9];
-  T f[PostRows<C>::slots];
-  int l[PostRows<C>::slots];  // staged index of the row's super-cell, -1 when the slot has no row
+template <class T, int RG>
+struct RingData {
+  T a[RingRows<RG>::slots][9];
+  T f[RingRows<RG>::slots];
+  int l[RingRows<RG>::slots];  // staged index of the row's super-cell, -1 when the slot has no row
 };
 
-// local super-cell (lx, ly) of the staged square of phase C's slot i (row-major over the phase's region; for C = 0
-// the Morton order of the square, so thread t holds super-cell 256 b + t)
-template <int C>
-__device__ inline void post_slot_xy(int i, int &lx, int &ly) {
+// staged super-cell (lx, ly) of slot i: row-major over the phase's region, and for the square alone (RG = 0) its
+// Morton order, so that thread t holds super-cell 256 b + t
+template <int RG>
+__device__ inline void ring_slot_xy(int i, int &lx, int &ly) {
   const int r = static_cast<int>(threadIdx.x) + i * kBlock;
-  if constexpr (C == 0) {
-    lx = static_cast<int>(compact_bits(static_cast<uint32_t>(r))) + kPostRing;
-    ly = static_cast<int>(compact_bits(static_cast<uint32_t>(r) >> 1)) + kPostRing;
+  if constexpr (RG == 0) {
+    lx = static_cast<int>(compact_bits(static_cast<uint32_t>(r))) + kTileRings;
+    ly = static_cast<int>(compact_bits(static_cast<uint32_t>(r) >> 1)) + kTileRings;
   } else {
-    lx = r % PostRows<C>::side + (kPostRing - C);
-    ly = r / PostRows<C>::side + (kPostRing - C);
+    lx = r % RingRows<RG>::side + (kTileRings - RG);
+    ly = r / RingRows<RG>::side + (kTileRings - RG);
   }
 }
 
-template <class T, int C>
-__device__ inline void post_load(const QView<T> &Q, const T *__restrict__ f, int px0, int py0, int np, uint32_t n4,
-                                 PostRowData<T, C> &D) {
+// the operator rows and right-hand sides of the color-C rows of the region (fv: right-hand side of a row)
+template <class T, int RG, int C, class FV>
+__device__ inline void ring_load(const QView<T> &Q, FV fv, int px0, int py0, int np, uint32_t n4, RingData<T, RG> &D) {
 #pragma unroll
-  for (int i = 0; i < PostRows<C>::slots; i++) {
+  for (int i = 0; i < RingRows<RG>::slots; i++) {
     int lx, ly;
-    post_slot_xy<C>(i, lx, ly);
+    ring_slot_xy<RG>(i, lx, ly);
     const int r = static_cast<int>(threadIdx.x) + i * kBlock;
     const int px = px0 + lx, py = py0 + ly;
-    const bool ok = r < PostRows<C>::count && px >= 0 && px < np && py >= 0 && py < np;
-    D.l[i] = ok ? ly * kPostSide + lx : -1;
+    const bool ok = r < RingRows<RG>::count && px >= 0 && px < np && py >= 0 && py < np;
+    D.l[i] = ok ? ly * kTileStage + lx : -1;
     if (ok) {
       const uint32_t q = static_cast<uint32_t>(C) * n4 + morton(static_cast<uint32_t>(px), static_cast<uint32_t>(py));
 #pragma unroll
       for (int s = 0; s < 9; s++) D.a[i][s] = Q.ax[s * Q.n + q];
-      D.f[i] = f[q];
+      D.f[i] = fv(q);
     }
   }
 }
 
+// sum over the nine slots of a color-C row at staged index l (a slot outside the grid holds 0: its product is taken
+// with the row's own value, as the per-phase kernels do)
 template <class T, int C>
-__device__ inline void post_phase(const PostRowData<T, C> &D, int px0, int py0, int np, T (*sv)[kPostSide * kPostSide],
-                                  T *xr0) {
+__device__ inline T ring_row(const T (&a)[9], int l, int px0, int py0, int np, const T (*sv)[kTileStage * kTileStage]) {
   constexpr int cx = C & 1, cy = C >> 1;
+  const int lx = l % kTileStage, ly = l / kTileStage;
+  T acc = 0;
 #pragma unroll
-  for (int i = 0; i < PostRows<C>::slots; i++) {
+  for (int s = 0; s < 9; s++) {
+    const int ux = cx + slot_dx(s), uy = cy + slot_dy(s);
+    const int cn = (ux & 1) | ((uy & 1) << 1);
+    const int nx = lx + (ux >> 1), ny = ly + (uy >> 1);
+    const int gx = px0 + nx, gy = py0 + ny;
+    const bool in = gx >= 0 && gx < np && gy >= 0 && gy < np;
+    acc += a[s] * (in ? sv[cn][ny * kTileStage + nx] : sv[C][l]);
+  }
+  return acc;
+}
+
+// one color phase: x_q + (f_q - (A x)_q) / a_qq for the color-C rows of the region
+template <class T, int RG, int C>
+__device__ inline void ring_phase(const RingData<T, RG> &D, int px0, int py0, int np, T (*sv)[kTileStage * kTileStage]) {
+#pragma unroll
+  for (int i = 0; i < RingRows<RG>::slots; i++) {
     const int l = D.l[i];
     if (l < 0) continue;
-    const int lx = l % kPostSide, ly = l / kPostSide;
-    T acc = 0;
-#pragma unroll
-    for (int s = 0; s < 9; s++) {
-      const int ux = cx + slot_dx(s), uy = cy + slot_dy(s);
-      const int cn = (ux & 1) | ((uy & 1) << 1);
-      const int nx = lx + (ux >> 1), ny = ly + (uy >> 1);
-      const int gx = px0 + nx, gy = py0 + ny;
-      const bool in = gx >= 0 && gx < np && gy >= 0 && gy < np;
-      // outside the grid the slot holds 0: its product is taken with the row's own value, as k_cgs_post does
-      acc += D.a[i][s] * (in ? sv[cn][ny * kPostSide + nx] : sv[C][l]);
-    }
+    const T acc = ring_row<T, C>(D.a[i], l, px0, py0, np, sv);
     const T xq = sv[C][l];
-    const T xr = xq + (D.f[i] - acc) / D.a[i][0];
-    sv[C][l] = xr;
-    if constexpr (C == 0) xr0[i] = xr;
+    sv[C][l] = xq + (D.f[i] - acc) / D.a[i][0];
   }
 }
 
+// residuals f_q - (A x)_q of the square's color-C rows among the region's rows, by the square's Morton index
+template <class T, int RG, int C>
+__device__ inline void ring_resid(const RingData<T, RG> &D, int px0, int py0, int np,
+                                  const T (*sv)[kTileStage * kTileStage], T *res) {
+#pragma unroll
+  for (int i = 0; i < RingRows<RG>::slots; i++) {
+    const int l = D.l[i];
+    if (l < 0) continue;
+    const int tx = l % kTileStage - kTileRings, ty = l / kTileStage - kTileRings;
+    if (tx < 0 || tx >= kTileSide || ty < 0 || ty >= kTileSide) continue;
+    const T acc = ring_row<T, C>(D.a[i], l, px0, py0, np, sv);
+    res[morton(static_cast<uint32_t>(tx), static_cast<uint32_t>(ty))] = D.f[i] - acc;
+  }
+}
+
+// The whole first post-smoothing sweep (color phases 3, 2, 1, 0, the prolongation folded in as in k_cgs_post) of a
+// level without same-color couplings or overflow entries, in one launch: u + P e_c staged over the square and its
+// rings, phase C on the color-C rows of the square and its C innermost rings. With BETA thread t forms (p1, q0) over
+// rows j + c n/4 of super-cell j = 256 b + t, as k_cgs_post<T, 0, true> does, so the partials are the same.
 template <class T, bool BETA>
 __global__ void __launch_bounds__(kBlock) k_cgs_post4(QView<T> Q, const T *__restrict__ f, T *__restrict__ x,
                                                       const T *__restrict__ ec, Pending<T> pend,
                                                       const T *__restrict__ q0, Red R) {
-  __shared__ T sv[4][kPostSide * kPostSide];
+  __shared__ T sv[4][kTileStage * kTileStage];
   const int kc = Q.k - 1;
   const int np = 1 << kc;
   const uint32_t n4 = static_cast<uint32_t>(Q.n >> 2);
   const uint32_t j0 = blockIdx.x * static_cast<uint32_t>(kBlock);
-  const int px0 = static_cast<int>(compact_bits(j0)) - kPostRing;
-  const int py0 = static_cast<int>(compact_bits(j0 >> 1)) - kPostRing;
-  // stage u + P e_c (each value as k_cgs_post forms it) over the square and its rings
-  for (int l = static_cast<int>(threadIdx.x); l < kPostSide * kPostSide; l += kBlock) {
-    const int px = px0 + l % kPostSide, py = py0 + l / kPostSide;
+  const int px0 = static_cast<int>(compact_bits(j0)) - kTileRings;
+  const int py0 = static_cast<int>(compact_bits(j0 >> 1)) - kTileRings;
+  for (int l = static_cast<int>(threadIdx.x); l < kTileStage * kTileStage; l += kBlock) {
+    const int px = px0 + l % kTileStage, py = py0 + l / kTileStage;
     if (px < 0 || px >= np || py < 0 || py >= np) continue;
     const uint32_t jm = morton(static_cast<uint32_t>(px), static_cast<uint32_t>(py));
     const T em = pend.apply(ec, q_of_m(jm, kc));
 #pragma unroll
     for (int c = 0; c < 4; c++) sv[c][l] = x[c * n4 + jm] + em;
   }
-  PostRowData<T, 3> D3;
-  PostRowData<T, 2> D2;
-  PostRowData<T, 1> D1;
-  PostRowData<T, 0> D0;
-  post_load<T, 3>(Q, f, px0, py0, np, n4, D3);
-  post_load<T, 2>(Q, f, px0, py0, np, n4, D2);
-  post_load<T, 1>(Q, f, px0, py0, np, n4, D1);
-  post_load<T, 0>(Q, f, px0, py0, np, n4, D0);
-  T xr0[1];
+  auto fv = [f](uint32_t q) { return f[q]; };
+  RingData<T, 3> D3;
+  RingData<T, 2> D2;
+  RingData<T, 1> D1;
+  RingData<T, 0> D0;
+  ring_load<T, 3, 3>(Q, fv, px0, py0, np, n4, D3);
+  ring_load<T, 2, 2>(Q, fv, px0, py0, np, n4, D2);
+  ring_load<T, 1, 1>(Q, fv, px0, py0, np, n4, D1);
+  ring_load<T, 0, 0>(Q, fv, px0, py0, np, n4, D0);
   __syncthreads();
-  post_phase<T, 3>(D3, px0, py0, np, sv, xr0);
+  ring_phase<T, 3, 3>(D3, px0, py0, np, sv);
   __syncthreads();
-  post_phase<T, 2>(D2, px0, py0, np, sv, xr0);
+  ring_phase<T, 2, 2>(D2, px0, py0, np, sv);
   __syncthreads();
-  post_phase<T, 1>(D1, px0, py0, np, sv, xr0);
+  ring_phase<T, 1, 1>(D1, px0, py0, np, sv);
   __syncthreads();
-  post_phase<T, 0>(D0, px0, py0, np, sv, xr0);
-  __syncthreads();
-  // the square's rows of the four colors; thread t holds super-cell j0 + t
+  ring_phase<T, 0, 0>(D0, px0, py0, np, sv);  // thread t's own row: read back below by thread t alone
   const uint32_t j = j0 + threadIdx.x;
   const int lj = D0.l[0];
-  double v[1] = {0.0};
 #pragma unroll
   for (int c = 0; c < 4; c++) x[c * n4 + j] = sv[c][lj];
   if constexpr (BETA) {
-    v[0] = static_cast<double>(xr0[0]) * static_cast<double>(q0[j]);
+    double v[1];
+    v[0] = static_cast<double>(sv[0][lj]) * static_cast<double>(q0[j]);
 #pragma unroll
     for (int c = 1; c < 4; c++) v[0] += static_cast<double>(sv[c][lj]) * static_cast<double>(q0[c * n4 + j]);
     reduce_finish<1>(v, R);
+  }
+}
+
+// The whole presmoothing sweep from zero and the restriction (k_cgs_first2, the color phases 2 and 3, k_cres_restrict)
+// of a level without same-color couplings or overflow entries, in one launch: color 0 = f / diag staged over the
+// square and its rings (colors 1 to 3 zero), then color 1 on three rings, color 2 on two, color 3 on one, and the
+// square's residuals summed over the four children in the order 0, 1, 3, 2 into the parent's slot. UPD: the right-hand
+// side is the pending first inner update's r, formed on the fly, and the update's e and r are stored for the square.
+template <class T, bool UPD>
+__global__ void __launch_bounds__(kBlock) k_cgs_pre4(QView<T> Q, const T *__restrict__ f, T *__restrict__ x, Upd1<T> U,
+                                                     T *__restrict__ gc) {
+  __shared__ T sv[4][kTileStage * kTileStage];
+  __shared__ T res[4][kBlock];
+  const int kc = Q.k - 1;
+  const int np = 1 << kc;
+  const uint32_t n4 = static_cast<uint32_t>(Q.n >> 2);
+  const uint32_t j0 = blockIdx.x * static_cast<uint32_t>(kBlock);
+  const int px0 = static_cast<int>(compact_bits(j0)) - kTileRings;
+  const int py0 = static_cast<int>(compact_bits(j0 >> 1)) - kTileRings;
+  const T a0 = UPD ? U.a0() : T(0);
+  auto fv = [f, U, a0](uint32_t q) -> T {
+    if constexpr (UPD) return U.rv(a0, q);
+    else return f[q];
+  };
+  for (int l = static_cast<int>(threadIdx.x); l < kTileStage * kTileStage; l += kBlock) {
+    const int px = px0 + l % kTileStage, py = py0 + l / kTileStage;
+    if (px < 0 || px >= np || py < 0 || py >= np) continue;
+    const uint32_t jm = morton(static_cast<uint32_t>(px), static_cast<uint32_t>(py));
+    sv[0][l] = fv(jm) / Q.ax[jm];
+    sv[1][l] = T(0);
+    sv[2][l] = T(0);
+    sv[3][l] = T(0);
+  }
+  RingData<T, 3> D1;
+  RingData<T, 2> D2;
+  RingData<T, 1> D3;
+  RingData<T, 0> D0;
+  ring_load<T, 3, 1>(Q, fv, px0, py0, np, n4, D1);
+  ring_load<T, 2, 2>(Q, fv, px0, py0, np, n4, D2);
+  ring_load<T, 1, 3>(Q, fv, px0, py0, np, n4, D3);
+  ring_load<T, 0, 0>(Q, fv, px0, py0, np, n4, D0);
+  __syncthreads();
+  ring_phase<T, 3, 1>(D1, px0, py0, np, sv);
+  __syncthreads();
+  ring_phase<T, 2, 2>(D2, px0, py0, np, sv);
+  __syncthreads();
+  ring_phase<T, 1, 3>(D3, px0, py0, np, sv);
+  __syncthreads();
+  ring_resid<T, 0, 0>(D0, px0, py0, np, sv, res[0]);
+  ring_resid<T, 3, 1>(D1, px0, py0, np, sv, res[1]);
+  ring_resid<T, 2, 2>(D2, px0, py0, np, sv, res[2]);
+  ring_resid<T, 1, 3>(D3, px0, py0, np, sv, res[3]);
+  __syncthreads();
+  const int t = static_cast<int>(threadIdx.x);
+  const uint32_t j = j0 + static_cast<uint32_t>(t);
+  const int lj = D0.l[0];
+  const int order[4] = {0, 1, 3, 2};
+  T acc = 0;
+#pragma unroll
+  for (int oi = 0; oi < 4; oi++) acc += res[order[oi]][t];
+  gc[q_of_m(j, kc)] = acc;
+#pragma unroll
+  for (int c = 0; c < 4; c++) {
+    x[c * n4 + j] = sv[c][lj];
+    if constexpr (UPD) U.store(a0, static_cast<int64_t>(c * n4 + j));
   }
 }
 
@@ -2996,7 +3080,18 @@ static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u, const Upd1<T>
   hipStream_t s = h->stream;
   const int sweeps = h->opt.sweeps;
   const bool U = upd.sc != nullptr;
-  for (int sw = 0; sw < sweeps; sw++)
+  const int64_t n4 = Q.n >> 2;
+  LevelWork<T> &wc = P<T>::W(h)[l + 1];
+  // the per-step path keeps one launch per color phase; with tiles the presmoothing sweep and the restriction take
+  // one launch, and so does the first post-smoothing sweep
+  const bool tiles = h->use_engine != 0 && !Q.same_color_ovf && Q.ovf_nnz == 0 && n4 >= kBlock;
+  const bool tiled_pre = tiles && sweeps == 1;
+  if (tiled_pre) {
+    const unsigned grid = static_cast<unsigned>(n4 / kBlock);
+    if (U) k_cgs_pre4<T, true><<<grid, kBlock, 0, s>>>(qview<T>(Q), f, u, upd, wc.g);
+    else k_cgs_pre4<T, false><<<grid, kBlock, 0, s>>>(qview<T>(Q), f, u, upd, wc.g);
+  }
+  for (int sw = 0; sw < (tiled_pre ? 0 : sweeps); sw++)
     for (int c = 0; c < 4; c++) {
       if (sw == 0 && c == 0 && !Q.same_color_ovf) {
         if (U) k_cgs_first2<T, true><<<nblk(Q.n), kBlock, 0, s>>>(qview<T>(Q), f, u, upd);
@@ -3009,17 +3104,13 @@ static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u, const Upd1<T>
         gs_phase_coarse<T>(h, l, f, u, c);
       }
     }
-  LevelWork<T> &wc = P<T>::W(h)[l + 1];
-  k_cres_restrict<T><<<nblk(Q.n >> 2), kBlock, 0, s>>>(qview<T>(Q), f, u, wc.g);
+  if (!tiled_pre) k_cres_restrict<T><<<nblk(Q.n >> 2), kBlock, 0, s>>>(qview<T>(Q), f, u, wc.g);
   const Pending<T> pend = coarse_solve_or_cycle<T>(h, l + 1);
   // without same-color couplings the prolongation folds into the first post-smoothing sweep
   const bool fold_prolong = !Q.same_color_ovf && sweeps >= 1;
   if (!fold_prolong) k_cprolong<T><<<nblk(Q.n), kBlock, 0, s>>>(Q.k, Q.n, wc.e, pend, u);
-  const int64_t n4 = Q.n >> 2;
   const Red rb = red(h, l, EPI_BETA);
-  // the first post-smoothing sweep in one launch (tiles of 16 x 16 super-cells; the per-step path keeps one launch
-  // per color)
-  const bool tiled = fold_prolong && h->use_engine != 0 && Q.ovf_nnz == 0 && n4 >= kBlock;
+  const bool tiled = tiles && fold_prolong;
   if (tiled) {
     const QView<T> V = qview<T>(Q);
     const unsigned grid = static_cast<unsigned>(n4 / kBlock);
