@@ -153,10 +153,13 @@ template <class T>
 struct Pending {
   const double *sc;
   const T *p1, *p0;
+  __device__ T mix(T em, T p1m, T p0m) const {
+    const T a1 = static_cast<T>(sc[S_A1]), beta = static_cast<T>(sc[S_BETA]);
+    return em + a1 * (p1m + beta * p0m);
+  }
   __device__ T apply(const T *e, uint32_t m) const {
     if (!sc) return e[m];
-    const T a1 = static_cast<T>(sc[S_A1]), beta = static_cast<T>(sc[S_BETA]);
-    return e[m] + a1 * (p1[m] + beta * p0[m]);
+    return mix(e[m], p1[m], p0[m]);
   }
 };
 
@@ -1056,6 +1059,7 @@ constexpr int kTileSide = 16;                          // super-cells per side o
 constexpr int kTileRings = 4;                          // rings staged around it
 constexpr int kTileStage = kTileSide + 2 * kTileRings;  // 24
 static_assert(kTileSide * kTileSide == kBlock, "one super-cell of the square per thread");
+static_assert(kTileStage == 24 && kTileRings == 4, "the staged square is 6 x 6 blocks of 4 x 4 super-cells");
 
 template <int RG>
 struct RingRows {  // row slots per thread of a phase over the square and its RG innermost rings
@@ -1064,15 +1068,33 @@ struct RingRows {  // row slots per thread of a phase over the square and its RG
   static constexpr int slots = (count + kBlock - 1) / kBlock;
 };
 
+constexpr int kStageSlots = (kTileStage * kTileStage + kBlock - 1) / kBlock;  // 3
+
+// staging slot i of this thread (the 6 x 6 blocks of 4 x 4 super-cells in turn, Morton order inside a block, so a
+// wavefront reads four contiguous runs): its staged index, -1 outside the grid, and its super-cell's Morton index
+__device__ inline int stage_slot(int i, int px0, int py0, int np, uint32_t &jm) {
+  const int e = static_cast<int>(threadIdx.x) + i * kBlock;
+  const int blk = e >> 4, w = e & 15;
+  const int lx = 4 * (blk % 6) + static_cast<int>(compact_bits(static_cast<uint32_t>(w)));
+  const int ly = 4 * (blk / 6) + static_cast<int>(compact_bits(static_cast<uint32_t>(w) >> 1));
+  const int px = px0 + lx, py = py0 + ly;
+  const bool ok = e < kTileStage * kTileStage && px >= 0 && px < np && py >= 0 && py < np;
+  jm = ok ? morton(static_cast<uint32_t>(px), static_cast<uint32_t>(py)) : 0u;
+  return ok ? ly * kTileStage + lx : -1;
+}
+
 template <class T, int RG>
 struct RingData {
   T a[RingRows<RG>::slots][9];
   T f[RingRows<RG>::slots];
+  T f2[RingRows<RG>::slots];  // with a pending first inner update: q0 of the row (f holds g until rhs_upd)
   int l[RingRows<RG>::slots];  // staged index of the row's super-cell, -1 when the slot has no row
 };
 
-// staged super-cell (lx, ly) of slot i: row-major over the phase's region, and for the square alone (RG = 0) its
-// Morton order, so that thread t holds super-cell 256 b + t
+// staged super-cell (lx, ly) of slot i. The staged square is 6 x 6 Morton-contiguous blocks of 4 x 4 super-cells;
+// the rows of a region are taken block by block (bands of block rows, blocks across a band, row-major inside the
+// part of a block in the region), so that a wavefront's loads touch a few blocks. For the square alone (RG = 0):
+// its Morton order, so that thread t holds super-cell 256 b + t.
 template <int RG>
 __device__ inline void ring_slot_xy(int i, int &lx, int &ly) {
   const int r = static_cast<int>(threadIdx.x) + i * kBlock;
@@ -1080,14 +1102,36 @@ __device__ inline void ring_slot_xy(int i, int &lx, int &ly) {
     lx = static_cast<int>(compact_bits(static_cast<uint32_t>(r))) + kTileRings;
     ly = static_cast<int>(compact_bits(static_cast<uint32_t>(r) >> 1)) + kTileRings;
   } else {
-    lx = r % RingRows<RG>::side + (kTileRings - RG);
-    ly = r / RingRows<RG>::side + (kTileRings - RG);
+    constexpr int W = RingRows<RG>::side;
+    constexpr int band0 = W * RG, bandm = W * 4;  // rows of the outer and of an inner band of blocks
+    int by, rb, h;
+    if (r < band0) {
+      by = 0, rb = r, h = RG;
+    } else if (r < band0 + 4 * bandm) {
+      const int t = r - band0;
+      by = 1 + t / bandm, rb = t % bandm, h = 4;
+    } else {
+      by = 5, rb = r - band0 - 4 * bandm, h = RG;
+    }
+    int bx, rs, w;
+    if (rb < RG * h) {
+      bx = 0, rs = rb, w = RG;
+    } else if (rb < RG * h + 16 * h) {
+      const int t = rb - RG * h;
+      bx = 1 + t / (4 * h), rs = t % (4 * h), w = 4;
+    } else {
+      bx = 5, rs = rb - RG * h - 16 * h, w = RG;
+    }
+    lx = (bx == 0 ? kTileRings - RG : 4 * bx) + rs % w;
+    ly = (by == 0 ? kTileRings - RG : 4 * by) + rs / w;
   }
 }
 
-// the operator rows and right-hand sides of the color-C rows of the region (fv: right-hand side of a row)
-template <class T, int RG, int C, class FV>
-__device__ inline void ring_load(const QView<T> &Q, FV fv, int px0, int py0, int np, uint32_t n4, RingData<T, RG> &D) {
+// the operator rows and right-hand sides of the color-C rows of the region. UPD: f and f2 take g and q0 of the
+// pending first inner update, combined by rhs_upd once every load has been issued.
+template <class T, int RG, int C, bool UPD>
+__device__ inline void ring_load(const QView<T> &Q, const T *__restrict__ f, const Upd1<T> &U, int px0, int py0,
+                                 int np, uint32_t n4, RingData<T, RG> &D) {
 #pragma unroll
   for (int i = 0; i < RingRows<RG>::slots; i++) {
     int lx, ly;
@@ -1096,13 +1140,26 @@ __device__ inline void ring_load(const QView<T> &Q, FV fv, int px0, int py0, int
     const int px = px0 + lx, py = py0 + ly;
     const bool ok = r < RingRows<RG>::count && px >= 0 && px < np && py >= 0 && py < np;
     D.l[i] = ok ? ly * kTileStage + lx : -1;
-    if (ok) {
-      const uint32_t q = static_cast<uint32_t>(C) * n4 + morton(static_cast<uint32_t>(px), static_cast<uint32_t>(py));
+    // loads without branches (a slot without a row reads row C n/4 and ignores it), so that none waits for another
+    const uint32_t jm = ok ? morton(static_cast<uint32_t>(px), static_cast<uint32_t>(py)) : 0u;
+    const uint32_t q = static_cast<uint32_t>(C) * n4 + jm;
 #pragma unroll
-      for (int s = 0; s < 9; s++) D.a[i][s] = Q.ax[s * Q.n + q];
-      D.f[i] = fv(q);
+    for (int s = 0; s < 9; s++) D.a[i][s] = Q.ax[s * Q.n + q];
+    if constexpr (UPD) {
+      D.f[i] = U.g[q];
+      D.f2[i] = U.q0[q];
+    } else {
+      D.f[i] = f[q];
     }
   }
+}
+
+// r = g - a0 q0 of the pending first inner update as the right-hand side of the region's rows
+template <class T, int RG>
+__device__ inline void rhs_upd(RingData<T, RG> &D, T a0) {
+#pragma unroll
+  for (int i = 0; i < RingRows<RG>::slots; i++)
+    if (D.l[i] >= 0) D.f[i] = upd1_r(D.f[i], a0, D.f2[i]);
 }
 
 // sum over the nine slots of a color-C row at staged index l (a slot outside the grid holds 0: its product is taken
@@ -1167,23 +1224,45 @@ __global__ void __launch_bounds__(kBlock) k_cgs_post4(QView<T> Q, const T *__res
   const uint32_t j0 = blockIdx.x * static_cast<uint32_t>(kBlock);
   const int px0 = static_cast<int>(compact_bits(j0)) - kTileRings;
   const int py0 = static_cast<int>(compact_bits(j0 >> 1)) - kTileRings;
-  for (int l = static_cast<int>(threadIdx.x); l < kTileStage * kTileStage; l += kBlock) {
-    const int px = px0 + l % kTileStage, py = py0 + l / kTileStage;
-    if (px < 0 || px >= np || py < 0 || py >= np) continue;
-    const uint32_t jm = morton(static_cast<uint32_t>(px), static_cast<uint32_t>(py));
-    const T em = pend.apply(ec, q_of_m(jm, kc));
+  // every load of the prologue is issued before the first value is formed
+  // (branch-free: a slot outside the grid reads super-cell 0 and ignores it)
+  int sl[kStageSlots];
+  T sx[kStageSlots][4], se[kStageSlots], s1[kStageSlots], s0[kStageSlots];
+  const T *p1p = pend.sc ? pend.p1 : ec, *p0p = pend.sc ? pend.p0 : ec;
 #pragma unroll
-    for (int c = 0; c < 4; c++) sv[c][l] = x[c * n4 + jm] + em;
+  for (int i = 0; i < kStageSlots; i++) {
+    uint32_t jm;
+    sl[i] = stage_slot(i, px0, py0, np, jm);
+#pragma unroll
+    for (int c = 0; c < 4; c++) sx[i][c] = x[c * n4 + jm];
+    const uint32_t m = q_of_m(jm, kc);
+    se[i] = ec[m];
+    s1[i] = p1p[m];
+    s0[i] = p0p[m];
   }
-  auto fv = [f](uint32_t q) { return f[q]; };
+  T q0v[4];
+  if constexpr (BETA) {
+    const uint32_t jt = j0 + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 4; c++) q0v[c] = q0[c * n4 + jt];
+  }
+  const Upd1<T> none{};
   RingData<T, 3> D3;
   RingData<T, 2> D2;
   RingData<T, 1> D1;
   RingData<T, 0> D0;
-  ring_load<T, 3, 3>(Q, fv, px0, py0, np, n4, D3);
-  ring_load<T, 2, 2>(Q, fv, px0, py0, np, n4, D2);
-  ring_load<T, 1, 1>(Q, fv, px0, py0, np, n4, D1);
-  ring_load<T, 0, 0>(Q, fv, px0, py0, np, n4, D0);
+  ring_load<T, 3, 3, false>(Q, f, none, px0, py0, np, n4, D3);
+  ring_load<T, 2, 2, false>(Q, f, none, px0, py0, np, n4, D2);
+  ring_load<T, 1, 1, false>(Q, f, none, px0, py0, np, n4, D1);
+  ring_load<T, 0, 0, false>(Q, f, none, px0, py0, np, n4, D0);
+  // u + P e_c as k_cgs_post forms it
+#pragma unroll
+  for (int i = 0; i < kStageSlots; i++)
+    if (sl[i] >= 0) {
+      const T em = pend.sc ? pend.mix(se[i], s1[i], s0[i]) : se[i];
+#pragma unroll
+      for (int c = 0; c < 4; c++) sv[c][sl[i]] = sx[i][c] + em;
+    }
   __syncthreads();
   ring_phase<T, 3, 3>(D3, px0, py0, np, sv);
   __syncthreads();
@@ -1198,9 +1277,9 @@ __global__ void __launch_bounds__(kBlock) k_cgs_post4(QView<T> Q, const T *__res
   for (int c = 0; c < 4; c++) x[c * n4 + j] = sv[c][lj];
   if constexpr (BETA) {
     double v[1];
-    v[0] = static_cast<double>(sv[0][lj]) * static_cast<double>(q0[j]);
+    v[0] = static_cast<double>(sv[0][lj]) * static_cast<double>(q0v[0]);
 #pragma unroll
-    for (int c = 1; c < 4; c++) v[0] += static_cast<double>(sv[c][lj]) * static_cast<double>(q0[c * n4 + j]);
+    for (int c = 1; c < 4; c++) v[0] += static_cast<double>(sv[c][lj]) * static_cast<double>(q0v[c]);
     reduce_finish<1>(v, R);
   }
 }
@@ -1222,27 +1301,65 @@ __global__ void __launch_bounds__(kBlock) k_cgs_pre4(QView<T> Q, const T *__rest
   const int px0 = static_cast<int>(compact_bits(j0)) - kTileRings;
   const int py0 = static_cast<int>(compact_bits(j0 >> 1)) - kTileRings;
   const T a0 = UPD ? U.a0() : T(0);
-  auto fv = [f, U, a0](uint32_t q) -> T {
-    if constexpr (UPD) return U.rv(a0, q);
-    else return f[q];
-  };
-  for (int l = static_cast<int>(threadIdx.x); l < kTileStage * kTileStage; l += kBlock) {
-    const int px = px0 + l % kTileStage, py = py0 + l / kTileStage;
-    if (px < 0 || px >= np || py < 0 || py >= np) continue;
-    const uint32_t jm = morton(static_cast<uint32_t>(px), static_cast<uint32_t>(py));
-    sv[0][l] = fv(jm) / Q.ax[jm];
-    sv[1][l] = T(0);
-    sv[2][l] = T(0);
-    sv[3][l] = T(0);
+  // every load of the prologue is issued before the first value is formed
+  int sl[kStageSlots];
+  T sf[kStageSlots], sq[kStageSlots], sd[kStageSlots];
+#pragma unroll
+  for (int i = 0; i < kStageSlots; i++) {  // branch-free, as in k_cgs_post4
+    uint32_t jm;
+    sl[i] = stage_slot(i, px0, py0, np, jm);
+    if constexpr (UPD) {
+      sf[i] = U.g[jm];
+      sq[i] = U.q0[jm];
+    } else {
+      sf[i] = f[jm];
+    }
+    sd[i] = Q.ax[jm];
+  }
+  T up[4], ug[4], uq[4];  // p0, g, q0 of the square's rows for the update's e and r
+  if constexpr (UPD) {
+    const uint32_t jt = j0 + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      up[c] = U.p0[c * n4 + jt];
+      ug[c] = U.g[c * n4 + jt];
+      uq[c] = U.q0[c * n4 + jt];
+    }
   }
   RingData<T, 3> D1;
   RingData<T, 2> D2;
   RingData<T, 1> D3;
   RingData<T, 0> D0;
-  ring_load<T, 3, 1>(Q, fv, px0, py0, np, n4, D1);
-  ring_load<T, 2, 2>(Q, fv, px0, py0, np, n4, D2);
-  ring_load<T, 1, 3>(Q, fv, px0, py0, np, n4, D3);
-  ring_load<T, 0, 0>(Q, fv, px0, py0, np, n4, D0);
+  ring_load<T, 3, 1, UPD>(Q, f, U, px0, py0, np, n4, D1);
+  ring_load<T, 2, 2, UPD>(Q, f, U, px0, py0, np, n4, D2);
+  ring_load<T, 1, 3, UPD>(Q, f, U, px0, py0, np, n4, D3);
+  ring_load<T, 0, 0, UPD>(Q, f, U, px0, py0, np, n4, D0);
+  if constexpr (UPD) {
+    rhs_upd<T, 3>(D1, a0);
+    rhs_upd<T, 2>(D2, a0);
+    rhs_upd<T, 1>(D3, a0);
+    rhs_upd<T, 0>(D0, a0);
+  }
+  // color 0 = f / diag as k_cgs_first2 forms it, colors 1 to 3 zero
+#pragma unroll
+  for (int i = 0; i < kStageSlots; i++)
+    if (sl[i] >= 0) {
+      T fi;
+      if constexpr (UPD) fi = upd1_r(sf[i], a0, sq[i]);
+      else fi = sf[i];
+      sv[0][sl[i]] = fi / sd[i];
+      sv[1][sl[i]] = T(0);
+      sv[2][sl[i]] = T(0);
+      sv[3][sl[i]] = T(0);
+    }
+  if constexpr (UPD) {  // the update's e and r of the square's rows as Upd1::store forms them (independent of the sweep)
+    const uint32_t jt = j0 + threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      U.e[c * n4 + jt] = a0 * up[c];
+      U.r[c * n4 + jt] = upd1_r(ug[c], a0, uq[c]);
+    }
+  }
   __syncthreads();
   ring_phase<T, 3, 1>(D1, px0, py0, np, sv);
   __syncthreads();
@@ -1264,10 +1381,7 @@ __global__ void __launch_bounds__(kBlock) k_cgs_pre4(QView<T> Q, const T *__rest
   for (int oi = 0; oi < 4; oi++) acc += res[order[oi]][t];
   gc[q_of_m(j, kc)] = acc;
 #pragma unroll
-  for (int c = 0; c < 4; c++) {
-    x[c * n4 + j] = sv[c][lj];
-    if constexpr (UPD) U.store(a0, static_cast<int64_t>(c * n4 + j));
-  }
+  for (int c = 0; c < 4; c++) x[c * n4 + j] = sv[c][lj];
 }
 
 template <class T>
