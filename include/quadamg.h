@@ -55,7 +55,10 @@ typedef struct {
     int32_t max_iters;   /* outer iteration cap (default 1000) */
     int32_t engine;      /* 1 (default): the small coarse levels of the cycle run inside one persistent workgroup
                             with LDS-resident operators, specialised at compile time to the level shape where the
-                            levels allow it; 2: the same workgroup always through its generic step interpreter;
+                            levels allow it, and each larger quadtree level without same-color or overflow couplings
+                            runs its presmoothing sweep with the restriction, and its first post-smoothing sweep, as
+                            one launch each (16 x 16 super-cell tiles; the same values as one launch per color
+                            phase); 2: the same, with the workgroup always through its generic step interpreter;
                             0: one kernel launch per step on every level */
     int32_t batch;       /* 1 (default): amg_solve_batch runs this system, when it has at most 65,536 unknowns, as
                             one workgroup of a whole-solve launch shared with the batch's other small systems;

@@ -204,6 +204,45 @@ def test_engine_matches_per_step_launches(name, precision):
     gb.close()
 
 
+def _tile_problem():
+    # 88,804 unknowns, L = 8: levels of 4,096 to 65,536 cells above the engine in both precisions, each with squares
+    # of 16 x 16 super-cells inside the grid and along its edges
+    if "jittered300" not in _cache:
+        _cache["jittered300"] = mg.jittered_problem(300)
+    return _cache["jittered300"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_tiled_tree_levels(precision):
+    """The tree levels' tiled launches (engine on: presmoothing with the restriction, and the first post-smoothing
+    sweep, on 16 x 16 super-cell squares with staged rings) against one launch per color phase (engine off) and, in
+    FP64, the oracle: the same preconditioner to rounding (the engine's levels below use other reduction trees)."""
+    prob = _tile_problem()
+    ga = gpu_hier(prob, engine=1)
+    gb = gpu_hier(prob, engine=0)
+    info = ga.engine_info(precision)
+    print(f"[gpu] tiles p{precision}: engine {info}", flush=True)
+    assert info["top_level"] >= 2, "no tree level above the engine"
+    r = T(np.random.default_rng(5).standard_normal(prob.n))
+    za = ga.apply_precond(r, precision=precision).cpu().numpy()
+    zb = gb.apply_precond(r, precision=precision).cpu().numpy()
+    tol = 1e-11 if precision == 0 else 1e-4
+    assert np.linalg.norm(za - zb) <= tol * np.linalg.norm(zb)
+    if precision == 0:
+        o = oracle.setup_problem(prob)
+        z_o = o.apply_precond(r.cpu().numpy())
+        assert np.linalg.norm(za - z_o) <= 1e-10 * np.linalg.norm(z_o)
+        o.close()
+    ga.set_precision(precision)
+    gb.set_precision(precision)
+    xa, ia = ga.solve(T(prob.b))
+    xb, ib = gb.solve(T(prob.b))
+    assert ia["status"] == 0 and abs(ia["iters"] - ib["iters"]) <= 1
+    assert torch.linalg.norm(xa - xb) <= 1e-6 * torch.linalg.norm(xb)
+    ga.close()
+    gb.close()
+
+
 @pytest.mark.parametrize("name", ["uniform65", "jittered130", "jittered177_kappa", "graded20k", "disk130"])
 @pytest.mark.parametrize("precision", [0, 1])
 def test_specialised_engine_matches_interpreter(name, precision):
