@@ -1058,22 +1058,25 @@ __global__ void __launch_bounds__(kBlock) k_cgs_post(QView<T> Q, const T *__rest
 constexpr int kTileSide = 16;                          // super-cells per side of a workgroup's square
 constexpr int kTileRings = 4;                          // rings staged around it
 constexpr int kTileStage = kTileSide + 2 * kTileRings;  // 24
-static_assert(kTileSide * kTileSide == kBlock, "one super-cell of the square per thread");
+constexpr int kTileCells = kTileSide * kTileSide;       // 256: thread t < 256 holds super-cell 256 b + t
+constexpr int kTileThreads = 512;                      // threads of a tile workgroup: one row slot per thread and
+                                                       // phase, so a wavefront's prologue loads stay in flight together
+static_assert(kTileCells == kBlock, "the square's partial sums are those of a kBlock-thread per-phase launch");
 static_assert(kTileStage == 24 && kTileRings == 4, "the staged square is 6 x 6 blocks of 4 x 4 super-cells");
 
 template <int RG>
 struct RingRows {  // row slots per thread of a phase over the square and its RG innermost rings
   static constexpr int side = kTileSide + 2 * RG;
   static constexpr int count = side * side;
-  static constexpr int slots = (count + kBlock - 1) / kBlock;
+  static constexpr int slots = (count + kTileThreads - 1) / kTileThreads;
 };
 
-constexpr int kStageSlots = (kTileStage * kTileStage + kBlock - 1) / kBlock;  // 3
+constexpr int kStageSlots = (kTileStage * kTileStage + kTileThreads - 1) / kTileThreads;  // 2
 
 // staging slot i of this thread (the 6 x 6 blocks of 4 x 4 super-cells in turn, Morton order inside a block, so a
 // wavefront reads four contiguous runs): its staged index, -1 outside the grid, and its super-cell's Morton index
 __device__ inline int stage_slot(int i, int px0, int py0, int np, uint32_t &jm) {
-  const int e = static_cast<int>(threadIdx.x) + i * kBlock;
+  const int e = static_cast<int>(threadIdx.x) + i * kTileThreads;
   const int blk = e >> 4, w = e & 15;
   const int lx = 4 * (blk % 6) + static_cast<int>(compact_bits(static_cast<uint32_t>(w)));
   const int ly = 4 * (blk / 6) + static_cast<int>(compact_bits(static_cast<uint32_t>(w) >> 1));
@@ -1094,10 +1097,10 @@ struct RingData {
 // staged super-cell (lx, ly) of slot i. The staged square is 6 x 6 Morton-contiguous blocks of 4 x 4 super-cells;
 // the rows of a region are taken block by block (bands of block rows, blocks across a band, row-major inside the
 // part of a block in the region), so that a wavefront's loads touch a few blocks. For the square alone (RG = 0):
-// its Morton order, so that thread t holds super-cell 256 b + t.
+// its Morton order, so that thread t holds super-cell 256 b + t (threads from 256 on hold no row).
 template <int RG>
 __device__ inline void ring_slot_xy(int i, int &lx, int &ly) {
-  const int r = static_cast<int>(threadIdx.x) + i * kBlock;
+  const int r = static_cast<int>(threadIdx.x) + i * kTileThreads;
   if constexpr (RG == 0) {
     lx = static_cast<int>(compact_bits(static_cast<uint32_t>(r))) + kTileRings;
     ly = static_cast<int>(compact_bits(static_cast<uint32_t>(r) >> 1)) + kTileRings;
@@ -1136,7 +1139,7 @@ __device__ inline void ring_load(const QView<T> &Q, const T *__restrict__ f, con
   for (int i = 0; i < RingRows<RG>::slots; i++) {
     int lx, ly;
     ring_slot_xy<RG>(i, lx, ly);
-    const int r = static_cast<int>(threadIdx.x) + i * kBlock;
+    const int r = static_cast<int>(threadIdx.x) + i * kTileThreads;
     const int px = px0 + lx, py = py0 + ly;
     const bool ok = r < RingRows<RG>::count && px >= 0 && px < np && py >= 0 && py < np;
     D.l[i] = ok ? ly * kTileStage + lx : -1;
@@ -1209,19 +1212,34 @@ __device__ inline void ring_resid(const RingData<T, RG> &D, int px0, int py0, in
   }
 }
 
+// (p1, q0) partial of the square: the sum over threads 0..255 in block_sum's order, stored as reduce_finish stores
+// it (every thread of the workgroup calls this)
+__device__ inline void tile_reduce_finish(double v, const Red &R) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  __shared__ double s[kTileThreads / 64];
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double acc[1] = {(s[0] + s[1]) + (s[2] + s[3])};
+    if (gridDim.x == 1) epilogue(acc, R);
+    else R.partials[blockIdx.x] = acc[0];
+  }
+}
+
 // The whole first post-smoothing sweep (color phases 3, 2, 1, 0, the prolongation folded in as in k_cgs_post) of a
 // level without same-color couplings or overflow entries, in one launch: u + P e_c staged over the square and its
 // rings, phase C on the color-C rows of the square and its C innermost rings. With BETA thread t forms (p1, q0) over
 // rows j + c n/4 of super-cell j = 256 b + t, as k_cgs_post<T, 0, true> does, so the partials are the same.
 template <class T, bool BETA>
-__global__ void __launch_bounds__(kBlock) k_cgs_post4(QView<T> Q, const T *__restrict__ f, T *__restrict__ x,
+__global__ void __launch_bounds__(kTileThreads) k_cgs_post4(QView<T> Q, const T *__restrict__ f, T *__restrict__ x,
                                                       const T *__restrict__ ec, Pending<T> pend,
                                                       const T *__restrict__ q0, Red R) {
   __shared__ T sv[4][kTileStage * kTileStage];
   const int kc = Q.k - 1;
   const int np = 1 << kc;
   const uint32_t n4 = static_cast<uint32_t>(Q.n >> 2);
-  const uint32_t j0 = blockIdx.x * static_cast<uint32_t>(kBlock);
+  const uint32_t j0 = blockIdx.x * static_cast<uint32_t>(kTileCells);
   const int px0 = static_cast<int>(compact_bits(j0)) - kTileRings;
   const int py0 = static_cast<int>(compact_bits(j0 >> 1)) - kTileRings;
   // every load of the prologue is issued before the first value is formed
@@ -1241,8 +1259,9 @@ __global__ void __launch_bounds__(kBlock) k_cgs_post4(QView<T> Q, const T *__res
     s0[i] = p0p[m];
   }
   T q0v[4];
+  const int t = static_cast<int>(threadIdx.x);
+  const uint32_t jt = j0 + static_cast<uint32_t>(t & (kTileCells - 1));  // clamped for threads without a super-cell
   if constexpr (BETA) {
-    const uint32_t jt = j0 + threadIdx.x;
 #pragma unroll
     for (int c = 0; c < 4; c++) q0v[c] = q0[c * n4 + jt];
   }
@@ -1271,17 +1290,18 @@ __global__ void __launch_bounds__(kBlock) k_cgs_post4(QView<T> Q, const T *__res
   ring_phase<T, 1, 1>(D1, px0, py0, np, sv);
   __syncthreads();
   ring_phase<T, 0, 0>(D0, px0, py0, np, sv);  // thread t's own row: read back below by thread t alone
-  const uint32_t j = j0 + threadIdx.x;
   const int lj = D0.l[0];
+  double v = 0.0;
+  if (t < kTileCells) {
 #pragma unroll
-  for (int c = 0; c < 4; c++) x[c * n4 + j] = sv[c][lj];
-  if constexpr (BETA) {
-    double v[1];
-    v[0] = static_cast<double>(sv[0][lj]) * static_cast<double>(q0v[0]);
+    for (int c = 0; c < 4; c++) x[c * n4 + jt] = sv[c][lj];
+    if constexpr (BETA) {
+      v = static_cast<double>(sv[0][lj]) * static_cast<double>(q0v[0]);
 #pragma unroll
-    for (int c = 1; c < 4; c++) v[0] += static_cast<double>(sv[c][lj]) * static_cast<double>(q0v[c]);
-    reduce_finish<1>(v, R);
+      for (int c = 1; c < 4; c++) v += static_cast<double>(sv[c][lj]) * static_cast<double>(q0v[c]);
+    }
   }
+  if constexpr (BETA) tile_reduce_finish(v, R);
 }
 
 // The whole presmoothing sweep from zero and the restriction (k_cgs_first2, the color phases 2 and 3, k_cres_restrict)
@@ -1290,14 +1310,14 @@ __global__ void __launch_bounds__(kBlock) k_cgs_post4(QView<T> Q, const T *__res
 // square's residuals summed over the four children in the order 0, 1, 3, 2 into the parent's slot. UPD: the right-hand
 // side is the pending first inner update's r, formed on the fly, and the update's e and r are stored for the square.
 template <class T, bool UPD>
-__global__ void __launch_bounds__(kBlock) k_cgs_pre4(QView<T> Q, const T *__restrict__ f, T *__restrict__ x, Upd1<T> U,
+__global__ void __launch_bounds__(kTileThreads) k_cgs_pre4(QView<T> Q, const T *__restrict__ f, T *__restrict__ x, Upd1<T> U,
                                                      T *__restrict__ gc) {
   __shared__ T sv[4][kTileStage * kTileStage];
-  __shared__ T res[4][kBlock];
+  __shared__ T res[4][kTileCells];
   const int kc = Q.k - 1;
   const int np = 1 << kc;
   const uint32_t n4 = static_cast<uint32_t>(Q.n >> 2);
-  const uint32_t j0 = blockIdx.x * static_cast<uint32_t>(kBlock);
+  const uint32_t j0 = blockIdx.x * static_cast<uint32_t>(kTileCells);
   const int px0 = static_cast<int>(compact_bits(j0)) - kTileRings;
   const int py0 = static_cast<int>(compact_bits(j0 >> 1)) - kTileRings;
   const T a0 = UPD ? U.a0() : T(0);
@@ -1317,8 +1337,9 @@ __global__ void __launch_bounds__(kBlock) k_cgs_pre4(QView<T> Q, const T *__rest
     sd[i] = Q.ax[jm];
   }
   T up[4], ug[4], uq[4];  // p0, g, q0 of the square's rows for the update's e and r
+  const int t = static_cast<int>(threadIdx.x);
+  const uint32_t jt = j0 + static_cast<uint32_t>(t & (kTileCells - 1));  // clamped for threads without a super-cell
   if constexpr (UPD) {
-    const uint32_t jt = j0 + threadIdx.x;
 #pragma unroll
     for (int c = 0; c < 4; c++) {
       up[c] = U.p0[c * n4 + jt];
@@ -1352,8 +1373,8 @@ __global__ void __launch_bounds__(kBlock) k_cgs_pre4(QView<T> Q, const T *__rest
       sv[2][sl[i]] = T(0);
       sv[3][sl[i]] = T(0);
     }
-  if constexpr (UPD) {  // the update's e and r of the square's rows as Upd1::store forms them (independent of the sweep)
-    const uint32_t jt = j0 + threadIdx.x;
+  if (UPD && t < kTileCells) {  // the update's e and r of the square's rows as Upd1::store forms them (independent
+                                // of the sweep)
 #pragma unroll
     for (int c = 0; c < 4; c++) {
       U.e[c * n4 + jt] = a0 * up[c];
@@ -1372,16 +1393,15 @@ __global__ void __launch_bounds__(kBlock) k_cgs_pre4(QView<T> Q, const T *__rest
   ring_resid<T, 2, 2>(D2, px0, py0, np, sv, res[2]);
   ring_resid<T, 1, 3>(D3, px0, py0, np, sv, res[3]);
   __syncthreads();
-  const int t = static_cast<int>(threadIdx.x);
-  const uint32_t j = j0 + static_cast<uint32_t>(t);
+  if (t >= kTileCells) return;
   const int lj = D0.l[0];
   const int order[4] = {0, 1, 3, 2};
   T acc = 0;
 #pragma unroll
   for (int oi = 0; oi < 4; oi++) acc += res[order[oi]][t];
-  gc[q_of_m(j, kc)] = acc;
+  gc[q_of_m(jt, kc)] = acc;
 #pragma unroll
-  for (int c = 0; c < 4; c++) x[c * n4 + j] = sv[c][lj];
+  for (int c = 0; c < 4; c++) x[c * n4 + jt] = sv[c][lj];
 }
 
 template <class T>
@@ -3198,12 +3218,12 @@ static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u, const Upd1<T>
   LevelWork<T> &wc = P<T>::W(h)[l + 1];
   // the per-step path keeps one launch per color phase; with tiles the presmoothing sweep and the restriction take
   // one launch, and so does the first post-smoothing sweep
-  const bool tiles = h->use_engine != 0 && !Q.same_color_ovf && Q.ovf_nnz == 0 && n4 >= kBlock;
+  const bool tiles = h->use_engine != 0 && !Q.same_color_ovf && Q.ovf_nnz == 0 && n4 >= kTileCells;
   const bool tiled_pre = tiles && sweeps == 1;
   if (tiled_pre) {
-    const unsigned grid = static_cast<unsigned>(n4 / kBlock);
-    if (U) k_cgs_pre4<T, true><<<grid, kBlock, 0, s>>>(qview<T>(Q), f, u, upd, wc.g);
-    else k_cgs_pre4<T, false><<<grid, kBlock, 0, s>>>(qview<T>(Q), f, u, upd, wc.g);
+    const unsigned grid = static_cast<unsigned>(n4 / kTileCells);
+    if (U) k_cgs_pre4<T, true><<<grid, kTileThreads, 0, s>>>(qview<T>(Q), f, u, upd, wc.g);
+    else k_cgs_pre4<T, false><<<grid, kTileThreads, 0, s>>>(qview<T>(Q), f, u, upd, wc.g);
   }
   for (int sw = 0; sw < (tiled_pre ? 0 : sweeps); sw++)
     for (int c = 0; c < 4; c++) {
@@ -3227,12 +3247,12 @@ static void bhat_coarse(amg_hierarchy *h, int l, const T *f, T *u, const Upd1<T>
   const bool tiled = tiles && fold_prolong;
   if (tiled) {
     const QView<T> V = qview<T>(Q);
-    const unsigned grid = static_cast<unsigned>(n4 / kBlock);
+    const unsigned grid = static_cast<unsigned>(n4 / kTileCells);
     if (beta_q0 && sweeps == 1) {
-      k_cgs_post4<T, true><<<grid, kBlock, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb);
+      k_cgs_post4<T, true><<<grid, kTileThreads, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb);
       finish<1>(h, nblk(n4), rb);
     } else {
-      k_cgs_post4<T, false><<<grid, kBlock, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb);
+      k_cgs_post4<T, false><<<grid, kTileThreads, 0, s>>>(V, f, u, wc.e, pend, beta_q0, rb);
     }
   }
   for (int sw = tiled ? 1 : 0; sw < sweeps; sw++)
