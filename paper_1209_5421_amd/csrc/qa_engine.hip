@@ -695,6 +695,27 @@ struct FeEngine {
   }
 };
 
+// dst[i] = src[i] for i < N: a thread's loads issued in rounds of eight before any of them is stored (a plain copy
+// loop waits for each load before the next)
+template <class V, int N, int NT>
+__device__ __forceinline__ void fe_stage(V *dst, const V *__restrict__ src, int tid) {
+  constexpr int per = (N + NT - 1) / NT, R = 8;
+#pragma unroll
+  for (int k0 = 0; k0 < per; k0 += R) {
+    V tmp[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+      const int i = tid + (k0 + k) * NT;
+      if (k0 + k < per) tmp[k] = src[i < N ? i : N - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+      const int i = tid + (k0 + k) * NT;
+      if (k0 + k < per && i < N) dst[i] = tmp[k];
+    }
+  }
+}
+
 template <class T, int KT, int KL>
 __global__ void __launch_bounds__((FeLayout<T, KT, KL>::threads)) k_engine_fast(FeArgs<T> A) {
   using Lay = FeLayout<T, KT, KL>;
@@ -722,20 +743,17 @@ __global__ void __launch_bounds__((FeLayout<T, KT, KL>::threads)) k_engine_fast(
       });
   }
   for (int i = tid; i < A.nops; i += NT) ops[i] = A.ops[i];
-  for (int i = tid; i < kFeCoarse * kFeCoarse; i += NT) ainv[i] = A.ainv[i];
+  fe_stage<double, kFeCoarse * kFeCoarse, NT>(ainv, A.ainv, tid);
   // operators of the LDS levels
-#pragma unroll
-  for (int l = 0; l < 3; l++)
-    if (l >= Lay::first_lds && l <= Lay::lw) {
-      const int n9 = 9 * Lay::n(l);
-      T *dst = S + Lay::ax_off(l);
-      const T *src = A.ax[l];
-      for (int i = tid; i < n9; i += NT) dst[i] = src[i];
-    }
-  if constexpr (Lay::lds(0)) {
-    T *g = S + Lay::vec_off(0) + V_G * Lay::n(0);
-    for (int i = tid; i < Lay::n(0); i += NT) g[i] = A.gv[V_G][i];
-  }
+  auto stage_level = [&](auto ll) {
+    constexpr int l = decltype(ll)::value;
+    if constexpr (l >= Lay::first_lds && l <= Lay::lw)
+      fe_stage<T, 9 * Lay::n(l), NT>(S + Lay::ax_off(l), A.ax[l], tid);
+  };
+  stage_level(IC<0>{});
+  stage_level(IC<1>{});
+  stage_level(IC<2>{});
+  if constexpr (Lay::lds(0)) fe_stage<T, Lay::n(0), NT>(S + Lay::vec_off(0) + V_G * Lay::n(0), A.gv[V_G], tid);
   __syncthreads();
   const FeEngine<T, KT, KL> E{S, ainv, A, sc, red, R};
   for (int oi = 0; oi < A.nops; oi++) {
